@@ -1,0 +1,145 @@
+"""Canonical ordering of the primal vector z and the dual vector eta.
+
+Follows section 5.2 ("Operator splitting"):
+  z   = (s^0, z_1, z_2), z_1 = ((x^i) over all nodes, (u^i) over nonleaf nodes),
+        z_2 = (y^i, tau^{[i]}, s^{[i]}) per nonleaf node i, where tau^{[i]} and
+        s^{[i]} collect the slack of every child of i;
+  eta = ((y^i, s^i - b^i'y^i, (x^i, u^i)) per nonleaf i,
+         (Q^{1/2}x^{anc(i)}, R^{1/2}u^{anc(i)}, tau^i/2, tau^i/2) per non-root i,
+         (x^j, (Q_N^{1/2}x^j, s^j/2, s^j/2)) per leaf j),
+with nodes in breadth-first order (Fig. 1). The constraint maps Gamma are the
+identity (box constraints), so the "(x^i, u^i)" and "x^j" parts are copies.
+For AV@R (section 4.3) y^i has 2 n_i + 1 entries, n_i = |ch(i)|.
+
+All offsets are built by walking the nodes in order and accumulating sizes.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+class Layout:
+    def __init__(self, inst):
+        anc = np.asarray(inst.anc, dtype=np.int64)
+        nn = anc.shape[0]
+        nx, nu = int(inst.nx), int(inst.nu)
+        self.nx, self.nu, self.num_nodes = nx, nu, nn
+        self.anc = anc
+        self.children = [[] for _ in range(nn)]
+        for i in range(1, nn):
+            if not (0 <= anc[i] < i):
+                raise ValueError("ancestor must precede its child")
+            self.children[anc[i]].append(i)
+        self.stage = np.zeros(nn, dtype=np.int64)
+        for i in range(1, nn):
+            self.stage[i] = self.stage[anc[i]] + 1
+        self.N = int(self.stage.max())
+        self.nonleaf = [i for i in range(nn) if self.children[i]]
+        self.leaves = [i for i in range(nn) if not self.children[i]]
+        for j in self.leaves:
+            if self.stage[j] != self.N:
+                raise ValueError("every leaf must sit at the last stage")
+        self.stage_nodes = [[i for i in range(nn) if self.stage[i] == t]
+                            for t in range(self.N + 1)]
+        prob = np.asarray(inst.prob, dtype=float)
+        # conditional probability of a child given its ancestor (the pi used
+        # by the risk measure of the ancestor's node, section 4.4)
+        self.p = np.ones(nn)
+        for i in range(1, nn):
+            self.p[i] = prob[i] / prob[anc[i]]
+
+        # ---- z ----
+        off = 0
+        self.s_off = np.full(nn, -1, dtype=np.int64)
+        self.s_off[0] = off
+        off += 1
+        self.x_off = np.zeros(nn, dtype=np.int64)
+        for i in range(nn):
+            self.x_off[i] = off
+            off += nx
+        self.u_off = np.full(nn, -1, dtype=np.int64)
+        for i in self.nonleaf:
+            self.u_off[i] = off
+            off += nu
+        self.y_off = np.full(nn, -1, dtype=np.int64)
+        self.tau_off = np.full(nn, -1, dtype=np.int64)
+        for i in self.nonleaf:
+            n = len(self.children[i])
+            self.y_off[i] = off
+            off += 2 * n + 1
+            for c in self.children[i]:
+                self.tau_off[c] = off
+                off += 1
+            for c in self.children[i]:
+                self.s_off[c] = off
+                off += 1
+        self.n_z = off
+
+        # ---- eta ----
+        off = 0
+        self.e1y = np.full(nn, -1, dtype=np.int64)
+        self.e1s = np.full(nn, -1, dtype=np.int64)
+        self.e1x = np.full(nn, -1, dtype=np.int64)
+        self.e1u = np.full(nn, -1, dtype=np.int64)
+        for i in self.nonleaf:
+            n = len(self.children[i])
+            self.e1y[i] = off
+            off += 2 * n + 1
+            self.e1s[i] = off
+            off += 1
+            self.e1x[i] = off
+            off += nx
+            self.e1u[i] = off
+            off += nu
+        self.e2x = np.full(nn, -1, dtype=np.int64)
+        self.e2u = np.full(nn, -1, dtype=np.int64)
+        self.e2a = np.full(nn, -1, dtype=np.int64)
+        self.e2b = np.full(nn, -1, dtype=np.int64)
+        for c in range(1, nn):
+            self.e2x[c] = off
+            off += nx
+            self.e2u[c] = off
+            off += nu
+            self.e2a[c] = off
+            off += 1
+            self.e2b[c] = off
+            off += 1
+        self.e3x = np.full(nn, -1, dtype=np.int64)
+        self.e3q = np.full(nn, -1, dtype=np.int64)
+        self.e3a = np.full(nn, -1, dtype=np.int64)
+        self.e3b = np.full(nn, -1, dtype=np.int64)
+        for j in self.leaves:
+            self.e3x[j] = off
+            off += nx
+            self.e3q[j] = off
+            off += nx
+            self.e3a[j] = off
+            off += 1
+            self.e3b[j] = off
+            off += 1
+        self.n_eta = off
+        self.n_v = self.n_z + self.n_eta
+
+    # ---- small helpers ----
+    def b_vector(self, i):
+        """b^i = (pi, 0_n, 1) of the AV@R conic form (section 4.3), with pi the
+        conditional probabilities of the children of i."""
+        ch = self.children[i]
+        n = len(ch)
+        return np.concatenate([self.p[ch], np.zeros(n), [1.0]])
+
+    def split(self, v):
+        return v[: self.n_z], v[self.n_z:]
+
+    def x_of(self, z, i):
+        return z[self.x_off[i]: self.x_off[i] + self.nx]
+
+    def u_of(self, z, i):
+        return z[self.u_off[i]: self.u_off[i] + self.nu]
+
+    def unpack_xu(self, z):
+        x = np.stack([self.x_of(z, i) for i in range(self.num_nodes)])
+        u = np.zeros((self.num_nodes, self.nu))
+        for i in self.nonleaf:
+            u[i] = self.u_of(z, i)
+        return x, u

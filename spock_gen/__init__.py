@@ -1,0 +1,312 @@
+"""Seeded synthetic instances of the multistage risk-averse optimal control problem.
+
+This module only draws inputs: tree shapes, node probabilities, dynamics, cost
+weights, boxes, risk parameters and initial states. It contains none of the
+solver's arithmetic and is the only code shared by the CPU oracle and the GPU
+path.
+
+Problem statement followed (paper section 4, "Multistage nested risk-averse
+OCPs"): a scenario tree whose nodes are numbered breadth-first with contiguous
+children (Fig. 1), node probabilities pi^i summing to one per stage, per-child
+dynamics x^{i+} = A^{i+} x^i + B^{i+} u^i, quadratic stage costs
+x'Q^{i+}x + u'R^{i+}u and terminal costs x'Q_N x, box constraints on states
+and inputs, and an AV@R_a risk measure per nonleaf node (section 4.2).
+Q, R and Q_N are diagonal in every workload here; they are stored as vectors.
+
+Arrays (all float64 unless stated, row 0 of per-child data unused):
+  anc   int32 [nn]        ancestor, anc[0] = -1
+  prob        [nn]        node probability pi^i
+  A           [nn,nx,nx]  dynamics of the edge anc(i) -> i (row-major)
+  B           [nn,nx,nu]
+  q           [nn,nx]     diag(Q^i), stage cost charged at child i
+  r           [nn,nu]     diag(R^i)
+  qN          [nn,nx]     diag(Q_N^j), read at leaves only
+  xmin, xmax  [nn,nx]     state box at every node
+  umin, umax  [nn,nu]     input box, read at nonleaf nodes only
+  a_risk      [nn]        AV@R parameter a in [0,1], read at nonleaf nodes
+  x0          [nx]        initial state
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Sequence
+
+import numpy as np
+
+__all__ = [
+    "Instance",
+    "branching_anc",
+    "rotation_scaled",
+    "spectral_scaled",
+    "make_config",
+    "make_batch",
+    "make_datacentre",
+    "make_random_small",
+    "CONFIG_NAMES",
+]
+
+
+@dataclass
+class Instance:
+    anc: np.ndarray
+    prob: np.ndarray
+    nx: int
+    nu: int
+    A: np.ndarray
+    B: np.ndarray
+    q: np.ndarray
+    r: np.ndarray
+    qN: np.ndarray
+    xmin: np.ndarray
+    xmax: np.ndarray
+    umin: np.ndarray
+    umax: np.ndarray
+    a_risk: np.ndarray
+    x0: np.ndarray
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def num_nodes(self) -> int:
+        return int(self.anc.shape[0])
+
+    def copy(self) -> "Instance":
+        return Instance(**{k: (v.copy() if isinstance(v, np.ndarray) else v)
+                           for k, v in self.__dict__.items()})
+
+
+def branching_anc(branching: Sequence[int]) -> np.ndarray:
+    """Breadth-first ancestor array of a tree in which every node of stage t
+    has branching[t] children (len(branching) = horizon N)."""
+    anc = [-1]
+    stage_nodes = [0]
+    for b in branching:
+        nxt = []
+        for i in stage_nodes:
+            for _ in range(int(b)):
+                anc.append(i)
+                nxt.append(len(anc) - 1)
+        stage_nodes = nxt
+    return np.asarray(anc, dtype=np.int32)
+
+
+def _children_counts(anc: np.ndarray) -> np.ndarray:
+    cnt = np.zeros(anc.shape[0], dtype=np.int64)
+    for i in range(1, anc.shape[0]):
+        cnt[anc[i]] += 1
+    return cnt
+
+
+def node_probabilities(anc: np.ndarray, cond: np.ndarray) -> np.ndarray:
+    """pi^i from conditional probabilities cond[i] = pi^i / pi^{anc(i)}."""
+    prob = np.zeros(anc.shape[0])
+    prob[0] = 1.0
+    for i in range(1, anc.shape[0]):
+        prob[i] = prob[anc[i]] * cond[i]
+    return prob
+
+
+def rotation_scaled(rng: np.random.Generator, n: int, radius: float) -> np.ndarray:
+    """radius * (Haar-orthogonal matrix); a planar rotation when n == 2."""
+    if n == 1:
+        return np.array([[radius * (1.0 if rng.random() < 0.5 else -1.0)]])
+    if n == 2:
+        th = rng.uniform(0.0, 2.0 * np.pi)
+        c, s = np.cos(th), np.sin(th)
+        return radius * np.array([[c, -s], [s, c]])
+    g = rng.standard_normal((n, n))
+    qm, rm = np.linalg.qr(g)
+    qm = qm * np.sign(np.diag(rm))[None, :]
+    return radius * qm
+
+
+def spectral_scaled(rng: np.random.Generator, n: int, radius: float) -> np.ndarray:
+    """radius * G / rho(G), G with i.i.d. N(0,1) entries."""
+    g = rng.standard_normal((n, n))
+    rho = np.max(np.abs(np.linalg.eigvals(g)))
+    return radius * g / rho
+
+
+def _cond_probs(rng, anc, kind, fixed=None):
+    nn = anc.shape[0]
+    cnt = _children_counts(anc)
+    cond = np.ones(nn)
+    first = {}
+    for i in range(1, nn):
+        first.setdefault(int(anc[i]), i)
+    for par, fc in sorted(first.items()):
+        n = int(cnt[par])
+        if n == 1:
+            cond[fc] = 1.0
+            continue
+        if kind == "uniform":
+            w = np.full(n, 1.0 / n)
+        elif kind == "dirichlet":
+            w = rng.dirichlet(np.ones(n))
+            w = np.maximum(w, 1e-3)
+            w = w / w.sum()
+        elif kind == "fixed":
+            w = np.asarray(fixed, float)
+            assert w.shape[0] == n
+        else:
+            raise ValueError(kind)
+        cond[fc:fc + n] = w
+    return cond
+
+
+def _assemble(rng, anc, nx, nu, *, A_kind, A_radius, B_std, q_kind, r_val,
+              qN_val, xbox, ubox, a_kind, prob_kind, x0_kind, name,
+              prob_fixed=None):
+    nn = anc.shape[0]
+    cond = _cond_probs(rng, anc, prob_kind, prob_fixed)
+    prob = node_probabilities(anc, cond)
+    A = np.zeros((nn, nx, nx))
+    B = np.zeros((nn, nx, nu))
+    q = np.ones((nn, nx))
+    r = np.full((nn, nu), r_val)
+    for i in range(1, nn):
+        rad = rng.uniform(*A_radius)
+        A[i] = (rotation_scaled if A_kind == "rotation" else spectral_scaled)(rng, nx, rad)
+        B[i] = B_std * rng.standard_normal((nx, nu))
+        if q_kind == "diagU":
+            q[i] = rng.uniform(0.5, 2.0, size=nx)
+    qN = np.full((nn, nx), qN_val)
+    xmin = np.full((nn, nx), -xbox)
+    xmax = np.full((nn, nx), xbox)
+    umin = np.full((nn, nu), -ubox)
+    umax = np.full((nn, nu), ubox)
+    cnt = _children_counts(anc)
+    a_risk = np.zeros(nn)
+    for i in range(nn):
+        if cnt[i] > 0:
+            a_risk[i] = a_kind(rng) if callable(a_kind) else float(a_kind)
+    if x0_kind == "U2":
+        x0 = rng.uniform(-2.0, 2.0, size=nx)
+    else:
+        x0 = rng.standard_normal(nx)
+    return Instance(anc=anc, prob=prob, nx=nx, nu=nu, A=A, B=B, q=q, r=r, qN=qN,
+                    xmin=xmin, xmax=xmax, umin=umin, umax=umax, a_risk=a_risk,
+                    x0=x0, name=name)
+
+
+CONFIG_NAMES = {
+    1: "plain-fp64 nx2 nu1 N3 binary (15 nodes)",
+    2: "single nx20 nu10 N10 b2x5 (223 nodes)",
+    3: "large nx50 nu20 N15 b3x7 (20776 nodes)",
+    4: "batched 512 uneven nx10 nu5",
+    5: "diff 64 shared-tree nx20 nu10 N8 b2x4 (95 nodes)",
+}
+
+
+def make_config(k: int, seed: int = 0) -> Instance:
+    """Single-instance workloads 1, 2, 3 (and the shared tree of 5)."""
+    rng = np.random.default_rng(seed)
+    if k == 1:
+        anc = branching_anc([2, 2, 2])
+        return _assemble(rng, anc, 2, 1, A_kind="rotation", A_radius=(0.9, 1.1),
+                         B_std=1.0, q_kind="I", r_val=0.1, qN_val=1.0, xbox=5.0,
+                         ubox=1.0, a_kind=0.5, prob_kind="uniform", x0_kind="U2",
+                         name="config1")
+    if k == 2:
+        anc = branching_anc([2] * 5 + [1] * 5)
+        return _assemble(rng, anc, 20, 10, A_kind="spectral", A_radius=(0.95, 1.05),
+                         B_std=1.0 / np.sqrt(10.0), q_kind="diagU", r_val=0.1,
+                         qN_val=1.0, xbox=10.0, ubox=2.0,
+                         a_kind=lambda g: g.uniform(0.1, 0.9), prob_kind="dirichlet",
+                         x0_kind="N", name="config2")
+    if k == 3:
+        anc = branching_anc([3] * 7 + [1] * 8)
+        return _assemble(rng, anc, 50, 20, A_kind="rotation", A_radius=(0.9, 1.1),
+                         B_std=1.0, q_kind="I", r_val=0.1, qN_val=1.0, xbox=5.0,
+                         ubox=1.0, a_kind=0.2, prob_kind="dirichlet", x0_kind="U2",
+                         name="config3")
+    if k == 5:
+        anc = branching_anc([2] * 4 + [1] * 4)
+        return _assemble(rng, anc, 20, 10, A_kind="rotation", A_radius=(0.9, 1.1),
+                         B_std=1.0, q_kind="I", r_val=0.1, qN_val=1.0, xbox=5.0,
+                         ubox=1.0, a_kind=0.3, prob_kind="uniform", x0_kind="N",
+                         name="config5")
+    raise ValueError(f"no single-instance config {k}")
+
+
+def make_batch(k: int, seed: int = 0, count: int | None = None) -> List[Instance]:
+    """Batched workloads: 4 (512 uneven trees) and 5 (64 instances sharing one
+    tree and its data, differing in x0)."""
+    if k == 4:
+        count = 512 if count is None else count
+        out = []
+        for b in range(count):
+            rng = np.random.default_rng([seed, b])
+            N = int(rng.integers(5, 13))
+            kb = min(int(rng.integers(2, 7)), N)
+            anc = branching_anc([2] * kb + [1] * (N - kb))
+            inst = _assemble(rng, anc, 10, 5, A_kind="rotation", A_radius=(0.9, 1.1),
+                             B_std=1.0, q_kind="I", r_val=0.1, qN_val=1.0, xbox=5.0,
+                             ubox=1.0, a_kind=lambda g: g.uniform(0.1, 0.9),
+                             prob_kind="uniform", x0_kind="N", name=f"config4[{b}]")
+            inst.meta.update(N=N, k=kb)
+            out.append(inst)
+        return out
+    if k == 5:
+        count = 64 if count is None else count
+        base = make_config(5, seed)
+        out = []
+        for b in range(count):
+            rng = np.random.default_rng([seed, 1000 + b])
+            inst = base.copy()
+            inst.x0 = rng.standard_normal(base.nx)
+            inst.name = f"config5[{b}]"
+            out.append(inst)
+        return out
+    raise ValueError(f"no batched config {k}")
+
+
+def make_datacentre(N: int, nx: int, d: int = 2, probs=(0.3, 0.7), a: float = 0.95,
+                    x0_scale: float = 0.1) -> Instance:
+    """The paper's data-centre thermal example (section 6, eq. dynamics-example):
+    tridiagonal A(w) with diagonal 1 + (w-1)/d * (1 + (j-1)/nx) and off-diagonals
+    0.01, B = I, Q = Q_N = I, R = 10 I, |x| <= 1, |u| <= 1.5, AV@R_a at every
+    nonleaf node, binary tree with conditional probabilities (0.3, 0.7)."""
+    anc = branching_anc([d] * N)
+    nn = anc.shape[0]
+    nu = nx
+    cnt = _children_counts(anc)
+    cond = np.ones(nn)
+    first = {}
+    for i in range(1, nn):
+        first.setdefault(int(anc[i]), i)
+    for par, fc in first.items():
+        cond[fc:fc + d] = probs
+    prob = node_probabilities(anc, cond)
+    A = np.zeros((nn, nx, nx))
+    B = np.zeros((nn, nx, nu))
+    for i in range(1, nn):
+        w = (i - first[int(anc[i])]) + 1  # disturbance value 1..d
+        for j in range(1, nx + 1):
+            A[i, j - 1, j - 1] = 1.0 + (w - 1) / d * (1.0 + (j - 1) / nx)
+            if j >= 2:
+                A[i, j - 1, j - 2] = 0.01
+                A[i, j - 2, j - 1] = 0.01
+        B[i] = np.eye(nx)
+    a_risk = np.where(cnt > 0, a, 0.0)
+    return Instance(anc=anc, prob=prob, nx=nx, nu=nu, A=A, B=B,
+                    q=np.ones((nn, nx)), r=np.full((nn, nu), 10.0),
+                    qN=np.ones((nn, nx)), xmin=-np.ones((nn, nx)),
+                    xmax=np.ones((nn, nx)), umin=np.full((nn, nu), -1.5),
+                    umax=np.full((nn, nu), 1.5), a_risk=a_risk,
+                    x0=np.full(nx, x0_scale), name=f"datacentre N{N} nx{nx}")
+
+
+def make_random_small(seed: int, branching: Sequence[int], nx: int, nu: int,
+                      a: float | None = None, box: float = 5.0, ubox: float = 1.0,
+                      q_kind: str = "diagU", prob_kind: str = "dirichlet") -> Instance:
+    """Small random instance for tests (any branching pattern)."""
+    rng = np.random.default_rng(seed)
+    anc = branching_anc(branching)
+    inst = _assemble(rng, anc, nx, nu, A_kind="rotation", A_radius=(0.9, 1.1),
+                     B_std=1.0, q_kind=q_kind, r_val=0.1, qN_val=1.0, xbox=box,
+                     ubox=ubox, a_kind=(lambda g: g.uniform(0.1, 0.9)) if a is None else a,
+                     prob_kind=prob_kind, x0_kind="N", name=f"random{seed}")
+    inst.r = rng.uniform(0.1, 1.0, size=inst.r.shape)
+    inst.qN = rng.uniform(0.5, 2.0, size=inst.qN.shape)
+    return inst
