@@ -1,0 +1,183 @@
+/*
+ * spock.h - C ABI of the MI355X (gfx950) implementation of SPOCK, the
+ * SuperMann-accelerated Chambolle-Pock method for multistage risk-averse
+ * optimal control on a scenario tree (Bodard, Moran, Schuurmans, Patrinos,
+ * Sopasakis, arXiv 2212.01110).
+ *
+ * Conventions shared by every entry point
+ *  - Every function returns an int status: SPOCK_OK (0) or a negative error
+ *    code. On error no output buffer and no handle is modified.
+ *  - Host arrays (plain C pointers) are read during the call and copied; the
+ *    caller keeps ownership. Device pointers (suffix _dev) are caller-owned
+ *    HIP device allocations; they are read/written only on the given stream,
+ *    and the call returns once that work is enqueued, except where a function
+ *    says it synchronises.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *  - Precision: a problem is factored in FP64 on the host, then its bulk data
+ *    is stored in SPOCK_FP64 or SPOCK_FP32. Device vectors of that problem
+ *    (z, eta, v) use that element type; x0 is always FP64.
+ *  - Handles are not thread safe; one handle is used by one stream at a time.
+ *
+ * Vector layout (section 5.2, "Operator splitting"): nodes in breadth-first
+ * order with contiguous children (Fig. 1), all leaves at stage N.
+ *   z   = (s^0,
+ *          x^i for every node            [num_nodes][nx],
+ *          u^i for every nonleaf node    [num_nonleaf][nu],
+ *          per nonleaf i: y^i (2 n_i + 1), tau^c for c in ch(i), s^c for c in ch(i))
+ *   eta = (per nonleaf i: y^i (2 n_i + 1), s^i - b^i'y^i, x^i (nx), u^i (nu);
+ *          per non-root c: Q_c^{1/2} x^{anc c} (nx), R_c^{1/2} u^{anc c} (nu), tau^c/2, tau^c/2;
+ *          per leaf j: x^j (nx), Q_N^{1/2} x^j (nx), s^j/2, s^j/2)
+ *   v   = (z, eta), n_v = n_z + n_eta; n_i = |ch(i)|, b^i = (p^{ch(i)}, 0, 1)
+ *   with p^c = pi^c / pi^{anc c} (conditional probability) and y^i the AV@R
+ *   conic dual variable (section 4.3: E = [aI, -I, 1]', K = R^{2n}_+ x {0}).
+ */
+#ifndef SPOCK_H
+#define SPOCK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct spock_tree spock_tree;        /* opaque, library-owned */
+typedef struct spock_problem spock_problem;  /* opaque, library-owned */
+
+enum {
+  SPOCK_OK = 0,
+  SPOCK_EINVAL = -1,      /* null pointer, bad size, bad setting, x0 precision */
+  SPOCK_ETREE = -2,       /* not breadth-first / children not contiguous / leaf not at stage N */
+  SPOCK_EPROB = -3,       /* pi <= 0, non-finite, children not summing to their parent */
+  SPOCK_EBOX = -4,        /* lower bound above upper bound, or x0 outside the root box */
+  SPOCK_EFACTOR = -5,     /* Alg. 1 hit a non-SPD R~ or a non-finite value */
+  SPOCK_EHIP = -6,        /* a HIP runtime call failed */
+  SPOCK_ENOMEM = -7,      /* host or device allocation failed */
+  SPOCK_EUNSUPPORTED = -8 /* nx or nu above 64, or an unsupported mode */
+};
+
+/* spock_info.status: outcome of an iteration, not an error */
+enum { SPOCK_CONVERGED = 0, SPOCK_MAXITER = 1, SPOCK_NUMERICAL = 2 };
+enum { SPOCK_FP64 = 0, SPOCK_FP32 = 1 };
+enum { SPOCK_METHOD_CP = 0, SPOCK_METHOD_SPOCK = 1 };
+
+/* Scenario tree (section 4.1). anc[num_nodes] with anc[0] = -1 and
+ * 0 <= anc[i] < i, nondecreasing in i (breadth-first, contiguous children);
+ * prob[num_nodes] node probabilities pi^i > 0 with every node's children
+ * summing to it (relative tolerance 1e-10) and pi^0 = 1. Every leaf must sit at
+ * the last stage N >= 1. Errors: SPOCK_EINVAL (null/num_nodes < 2),
+ * SPOCK_ETREE, SPOCK_EPROB, SPOCK_ENOMEM. */
+int spock_tree_create(int32_t num_nodes, const int32_t* anc, const double* prob,
+                      spock_tree** out);
+int spock_tree_destroy(spock_tree* tree);
+/* horizon N, nonleaf count and leaf count of a tree */
+int spock_tree_shape(const spock_tree* tree, int32_t* N, int32_t* num_nonleaf,
+                     int32_t* num_leaves);
+
+/* Problem data (section 4.1, "Dynamics", "Constraints", "Quadratic costs";
+ * section 4.2 for AV@R). Host arrays, row-major, indexed by node; row 0 of
+ * per-edge data (A, B, q, r) is unused. Q, R and Q_N are diagonal and given by
+ * their diagonals; the constraint sets are boxes (Gamma = identity).
+ *   A  [num_nodes][nx][nx], B [num_nodes][nx][nu]: x^c = A^c x^{anc c} + B^c u^{anc c}
+ *   q  [num_nodes][nx] > 0, r [num_nodes][nu] > 0: stage cost x'Q^c x + u'R^c u charged at c
+ *   qN [num_nodes][nx] >= 0: terminal cost x'Q_N x, read at leaves
+ *   xmin, xmax [num_nodes][nx]: state box of every node (root included)
+ *   umin, umax [num_nodes][nu]: input box, read at nonleaf nodes
+ *   a_risk [num_nodes]: AV@R parameter a in [0, 1] of each nonleaf node
+ *   precision: SPOCK_FP64 or SPOCK_FP32 storage of the iteration data
+ *   alpha: CP step size; <= 0 selects 0.99 / ||L||; otherwise must satisfy
+ *          0 < alpha ||L|| < 1 (section 3). */
+typedef struct {
+  int32_t nx, nu;
+  const double *A, *B;
+  const double *q, *r, *qN;
+  const double *xmin, *xmax, *umin, *umax;
+  const double* a_risk;
+  int32_t precision;
+  double alpha;
+} spock_problem_data;
+
+/* Runs Alg. 1 (offline S1 factorisation) in FP64 on the host, computes ||L||
+ * from its block-diagonal structure (remark after the definition of L) and
+ * uploads the stage-ordered device layout. Synchronises. The tree must
+ * outlive the problem. Errors: SPOCK_EINVAL, SPOCK_EBOX, SPOCK_EFACTOR,
+ * SPOCK_EUNSUPPORTED, SPOCK_EHIP, SPOCK_ENOMEM. */
+int spock_problem_factor(const spock_tree* tree, const spock_problem_data* data,
+                         spock_problem** out);
+int spock_problem_destroy(spock_problem* prob);
+/* sizes and step: n_z, n_eta, alpha and ||L|| (any pointer may be NULL) */
+int spock_problem_sizes(const spock_problem* prob, int64_t* n_z, int64_t* n_eta,
+                        double* alpha, double* norm_L);
+
+/* Solver settings (section 3 termination; Alg. 3 parameters). method CP runs
+ * v <- T(v); method SPOCK runs Alg. 3 with Anderson memory m (1..8).
+ * Parameters follow Alg. 3: c0, c1, c2 in [0,1), beta, sigma in (0,1),
+ * lambda in (0,2); max_ls caps the backtracking (then a plain KM step is
+ * taken). compute_nested != 0 also evaluates the exact nested AV@R cost of the
+ * returned trajectory on the host (one device-to-host copy). */
+typedef struct {
+  double eps_abs, eps_rel;
+  int32_t max_iters, method, m, max_ls;
+  double c0, c1, c2, beta, sigma, lambda;
+  int32_t compute_nested;
+} spock_settings;
+
+/* Fills the defaults: eps 1e-4/1e-4, max_iters 20000, SPOCK, m = 3,
+ * max_ls = 20, c0 = c1 = c2 = 0.99, beta = 0.5, sigma = 0.1, lambda = 1. */
+void spock_settings_default(spock_settings* s);
+
+typedef struct {
+  int32_t status;          /* SPOCK_CONVERGED / SPOCK_MAXITER / SPOCK_NUMERICAL */
+  int32_t iters, t_evals;  /* iterations and evaluations of T (= calls of L) */
+  int32_t n_k0, n_k1, n_k2, n_km, n_backtracks;
+  double xi0, xi;          /* residual xi of section 3 at start and end */
+  double V_s0;             /* s^0 of the returned point */
+  double V_nested;         /* nested AV@R cost of its (x, u), if requested, else NaN */
+  double seconds;          /* host wall time of the call */
+} spock_info;
+
+/* Solves one instance from x0_dev (FP64 [nx], device) and the warm start in
+ * v_io_dev ([n_v] of the problem precision; zeros for a cold start). On
+ * return v_io_dev holds T(v^k) at the last iterate, for which the section-3
+ * certificates hold. Synchronises the stream. Errors: SPOCK_EINVAL,
+ * SPOCK_EBOX (x0 outside the root box), SPOCK_EHIP, SPOCK_ENOMEM. Not
+ * converging is reported in info->status, not as an error. */
+int spock_solve(spock_problem* prob, const double* x0_dev, const spock_settings* s,
+                void* v_io_dev, spock_info* info_host, void* stream);
+
+/* Solves B independent instances (trees may differ) in one persistent launch,
+ * one workgroup per instance running Alg. 3 to its own termination. probs[b],
+ * x0_dev[b], v_io_dev[b] as in spock_solve; every problem must have the same
+ * precision, nx and nu. infos_host[B] receives the per-instance results.
+ * Synchronises the stream. */
+int spock_solve_batched(int32_t B, spock_problem* const* probs,
+                        const double* const* x0_dev, const spock_settings* s,
+                        void* const* v_io_dev, spock_info* infos_host, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Per-operator entry points (same kernels as the solver; used for operator
+ * parity). All vectors are device arrays of the problem precision.
+ * ------------------------------------------------------------------------- */
+/* eta_dev[n_eta] = L z_dev[n_z] (section 5.2, definition of L) */
+int spock_apply_L(spock_problem* prob, const void* z_dev, void* eta_dev, void* stream);
+/* z_dev[n_z] = L* eta_dev[n_eta], the adjoint of L */
+int spock_apply_Lt(spock_problem* prob, const void* eta_dev, void* z_dev, void* stream);
+/* zout_dev = prox_{alpha f}(zin_dev) (section 5.3): s^0 - alpha, projection on
+ * S1 with root state x0_dev (Alg. 2), projection on S2 */
+int spock_prox_f(spock_problem* prob, const void* zin_dev, const double* x0_dev,
+                 void* zout_dev, void* stream);
+/* out_dev = prox_{alpha g*}(w_dev) = w - alpha proj_S3(w / alpha) (section 5.4) */
+int spock_prox_gstar(spock_problem* prob, const void* w_dev, void* out_dev, void* stream);
+/* Tv_dev = T(v_dev) (eq. chambolle-pock-operator). If stats_host is non-NULL it
+ * receives {||xi_p||_inf, ||xi_d||_inf, omega^2, ||r_z||^2, ||r_eta||^2,
+ * <r_eta, L r_z>} of r = v - T(v) (section 3, Alg. 3) and the call
+ * synchronises. */
+int spock_T(spock_problem* prob, const void* v_dev, const double* x0_dev, void* Tv_dev,
+            double* stats_host, void* stream);
+
+/* Library version string */
+const char* spock_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPOCK_H */

@@ -1,0 +1,237 @@
+"""Python binding of libspock (MI355X / gfx950 SPOCK hot path).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Device buffers are torch tensors on the current HIP device; the current
+torch stream is passed to the library. Importing this package does not
+require a GPU; calling a compute entry point does, and fails loudly if the
+built library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libspock.so")
+
+SPOCK_OK = 0
+ERRORS = {-1: "SPOCK_EINVAL", -2: "SPOCK_ETREE", -3: "SPOCK_EPROB", -4: "SPOCK_EBOX",
+          -5: "SPOCK_EFACTOR", -6: "SPOCK_EHIP", -7: "SPOCK_ENOMEM", -8: "SPOCK_EUNSUPPORTED"}
+STATUS = {0: "converged", 1: "maxiter", 2: "numerical"}
+FP64, FP32 = 0, 1
+METHOD_CP, METHOD_SPOCK = 0, 1
+
+EXPORTED = [
+    "spock_tree_create", "spock_tree_destroy", "spock_tree_shape", "spock_problem_factor",
+    "spock_problem_destroy", "spock_problem_sizes", "spock_settings_default", "spock_solve",
+    "spock_solve_batched", "spock_apply_L", "spock_apply_Lt", "spock_prox_f",
+    "spock_prox_gstar", "spock_T", "spock_version",
+]
+
+
+class SpockError(RuntimeError):
+    def __init__(self, code, where):
+        super().__init__(f"{where}: {ERRORS.get(code, code)}")
+        self.code = code
+
+
+class _ProblemData(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("nu", ctypes.c_int32),
+                ("A", ctypes.c_void_p), ("B", ctypes.c_void_p),
+                ("q", ctypes.c_void_p), ("r", ctypes.c_void_p), ("qN", ctypes.c_void_p),
+                ("xmin", ctypes.c_void_p), ("xmax", ctypes.c_void_p),
+                ("umin", ctypes.c_void_p), ("umax", ctypes.c_void_p),
+                ("a_risk", ctypes.c_void_p), ("precision", ctypes.c_int32),
+                ("alpha", ctypes.c_double)]
+
+
+class Settings(ctypes.Structure):
+    _fields_ = [("eps_abs", ctypes.c_double), ("eps_rel", ctypes.c_double),
+                ("max_iters", ctypes.c_int32), ("method", ctypes.c_int32),
+                ("m", ctypes.c_int32), ("max_ls", ctypes.c_int32),
+                ("c0", ctypes.c_double), ("c1", ctypes.c_double), ("c2", ctypes.c_double),
+                ("beta", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("lam", ctypes.c_double), ("compute_nested", ctypes.c_int32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("t_evals", ctypes.c_int32), ("n_k0", ctypes.c_int32), ("n_k1", ctypes.c_int32),
+                ("n_k2", ctypes.c_int32), ("n_km", ctypes.c_int32),
+                ("n_backtracks", ctypes.c_int32), ("xi0", ctypes.c_double),
+                ("xi", ctypes.c_double), ("V_s0", ctypes.c_double),
+                ("V_nested", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["status"] = STATUS.get(self.status, self.status)
+        return d
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libspock.so not built ({LIB_PATH}); run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+        L.spock_tree_create.argtypes = [i32, vp, vp, ctypes.POINTER(vp)]
+        L.spock_tree_destroy.argtypes = [vp]
+        L.spock_tree_shape.argtypes = [vp, vp, vp, vp]
+        L.spock_problem_factor.argtypes = [vp, ctypes.POINTER(_ProblemData), ctypes.POINTER(vp)]
+        L.spock_problem_destroy.argtypes = [vp]
+        L.spock_problem_sizes.argtypes = [vp, vp, vp, vp, vp]
+        L.spock_settings_default.argtypes = [ctypes.POINTER(Settings)]
+        L.spock_settings_default.restype = None
+        L.spock_solve.argtypes = [vp, vp, ctypes.POINTER(Settings), vp, ctypes.POINTER(Info), vp]
+        L.spock_solve_batched.argtypes = [i32, vp, vp, ctypes.POINTER(Settings), vp, vp, vp]
+        L.spock_apply_L.argtypes = [vp, vp, vp, vp]
+        L.spock_apply_Lt.argtypes = [vp, vp, vp, vp]
+        L.spock_prox_f.argtypes = [vp, vp, vp, vp, vp]
+        L.spock_prox_gstar.argtypes = [vp, vp, vp, vp]
+        L.spock_T.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.spock_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc, where):
+    if rc != SPOCK_OK:
+        raise SpockError(rc, where)
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def default_settings(**kw) -> Settings:
+    s = Settings()
+    lib().spock_settings_default(ctypes.byref(s))
+    for k, v in kw.items():
+        if k == "lambda":
+            k = "lam"
+        if k == "method" and isinstance(v, str):
+            v = METHOD_CP if v.lower() == "cp" else METHOD_SPOCK
+        setattr(s, k, v)
+    return s
+
+
+class Tree:
+    """Scenario tree (breadth-first ancestors and node probabilities)."""
+
+    def __init__(self, anc, prob):
+        self._anc = np.ascontiguousarray(anc, dtype=np.int32)
+        self._prob = np.ascontiguousarray(prob, dtype=np.float64)
+        h = ctypes.c_void_p()
+        _check(lib().spock_tree_create(len(self._anc), self._anc.ctypes.data,
+                                       self._prob.ctypes.data, ctypes.byref(h)),
+               "spock_tree_create")
+        self.handle = h
+        N, nl, nleaf = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        lib().spock_tree_shape(h, ctypes.byref(N), ctypes.byref(nl), ctypes.byref(nleaf))
+        self.N, self.num_nonleaf, self.num_leaves = N.value, nl.value, nleaf.value
+        self.num_nodes = len(self._anc)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.spock_tree_destroy(self.handle)
+            self.handle = None
+
+
+class Problem:
+    """Factored problem on the device (Alg. 1 in FP64, storage in `precision`)."""
+
+    def __init__(self, tree: Tree, nx, nu, A, B, q, r, qN, xmin, xmax, umin, umax, a_risk,
+                 precision=FP64, alpha=0.0):
+        self.tree = tree
+        arrs = {k: np.ascontiguousarray(v, dtype=np.float64) for k, v in
+                dict(A=A, B=B, q=q, r=r, qN=qN, xmin=xmin, xmax=xmax, umin=umin,
+                     umax=umax, a_risk=a_risk).items()}
+        self._keep = arrs
+        d = _ProblemData(nx=nx, nu=nu, precision=precision, alpha=alpha,
+                         **{k: v.ctypes.data for k, v in arrs.items()})
+        h = ctypes.c_void_p()
+        _check(lib().spock_problem_factor(tree.handle, ctypes.byref(d), ctypes.byref(h)),
+               "spock_problem_factor")
+        self.handle = h
+        self.nx, self.nu, self.precision = nx, nu, precision
+        nz, ne, al, nl = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+        lib().spock_problem_sizes(h, ctypes.byref(nz), ctypes.byref(ne), ctypes.byref(al),
+                                  ctypes.byref(nl))
+        self.n_z, self.n_eta, self.alpha, self.norm_L = nz.value, ne.value, al.value, nl.value
+        self.n_v = self.n_z + self.n_eta
+
+    @classmethod
+    def from_instance(cls, inst, precision=FP64, alpha=0.0, tree=None):
+        tree = tree or Tree(inst.anc, inst.prob)
+        return cls(tree, inst.nx, inst.nu, inst.A, inst.B, inst.q, inst.r, inst.qN, inst.xmin,
+                   inst.xmax, inst.umin, inst.umax, inst.a_risk, precision, alpha)
+
+    @property
+    def torch_dtype(self):
+        import torch
+        return torch.float64 if self.precision == FP64 else torch.float32
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.spock_problem_destroy(self.handle)
+            self.handle = None
+
+    # ---- entry points
+    def solve(self, x0, v, settings: Settings | None = None) -> dict:
+        s = settings or default_settings()
+        info = Info()
+        _check(lib().spock_solve(self.handle, _ptr(x0), ctypes.byref(s), _ptr(v),
+                                 ctypes.byref(info), _stream()), "spock_solve")
+        return info.as_dict()
+
+    def apply_L(self, z, eta):
+        _check(lib().spock_apply_L(self.handle, _ptr(z), _ptr(eta), _stream()), "spock_apply_L")
+
+    def apply_Lt(self, eta, z):
+        _check(lib().spock_apply_Lt(self.handle, _ptr(eta), _ptr(z), _stream()), "spock_apply_Lt")
+
+    def prox_f(self, zin, x0, zout):
+        _check(lib().spock_prox_f(self.handle, _ptr(zin), _ptr(x0), _ptr(zout), _stream()),
+               "spock_prox_f")
+
+    def prox_gstar(self, w, out):
+        _check(lib().spock_prox_gstar(self.handle, _ptr(w), _ptr(out), _stream()),
+               "spock_prox_gstar")
+
+    def T(self, v, x0, Tv, want_stats=True):
+        st = np.zeros(6) if want_stats else None
+        _check(lib().spock_T(self.handle, _ptr(v), _ptr(x0), _ptr(Tv),
+                             ctypes.c_void_p(st.ctypes.data) if want_stats else None, _stream()),
+               "spock_T")
+        if st is None:
+            return None
+        return dict(xi_p=st[0], xi_d=st[1], omega2=st[2], rz2=st[3], re2=st[4], cross=st[5])
+
+
+def solve_batched(problems, x0s, vs, settings: Settings | None = None):
+    s = settings or default_settings()
+    B = len(problems)
+    ph = (ctypes.c_void_p * B)(*[p.handle.value for p in problems])
+    xp = (ctypes.c_void_p * B)(*[x.data_ptr() for x in x0s])
+    vp = (ctypes.c_void_p * B)(*[v.data_ptr() for v in vs])
+    infos = (Info * B)()
+    _check(lib().spock_solve_batched(B, ph, xp, ctypes.byref(s), vp, infos, _stream()),
+           "spock_solve_batched")
+    return [i.as_dict() for i in infos]
+
+
+def version() -> str:
+    return lib().spock_version().decode()

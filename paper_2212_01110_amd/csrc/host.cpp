@@ -1,0 +1,1061 @@
+// Host side of the SPOCK library: tree validation, the offline factorisation
+// of Alg. 1 in FP64, ||L|| from the block-diagonal structure of L, the device
+// layout, and the host-driven CP / SPOCK iteration (section 3, Alg. 3) built
+// on the kernels of kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <thread>
+#include <vector>
+
+#include "spock_internal.h"
+
+using namespace spk;
+
+struct spock_tree {
+  Tree t;
+};
+struct spock_problem {
+  Problem p;
+};
+
+namespace {
+
+#define HIP_TRY(x)                          \
+  do {                                      \
+    if ((x) != hipSuccess) return SPOCK_EHIP; \
+  } while (0)
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+// Parallel loop over [0, n) on host threads.
+template <typename F>
+void parallel_for(int n, F&& f) {
+  unsigned hw = std::thread::hardware_concurrency();
+  int nt = (int)std::min<unsigned>(hw ? hw : 1, 16u);
+  if (n < 64 || nt <= 1) {
+    for (int i = 0; i < n; ++i) f(i);
+    return;
+  }
+  nt = std::min(nt, n);
+  std::vector<std::thread> th;
+  for (int w = 0; w < nt; ++w)
+    th.emplace_back([&, w]() {
+      for (int i = w; i < n; i += nt) f(i);
+    });
+  for (auto& t : th) t.join();
+}
+
+// ---- small dense FP64 helpers (row-major)
+// C[m][n] (+)= A[m][k] * B[k][n]
+void gemm(int m, int n, int k, const double* A, const double* B, double* C, bool acc) {
+  if (!acc) std::fill(C, C + (size_t)m * n, 0.0);
+  for (int i = 0; i < m; ++i)
+    for (int l = 0; l < k; ++l) {
+      const double a = A[(size_t)i * k + l];
+      if (a == 0.0) continue;
+      const double* b = B + (size_t)l * n;
+      double* c = C + (size_t)i * n;
+      for (int j = 0; j < n; ++j) c[j] += a * b[j];
+    }
+}
+// C[m][n] (+)= A[k][m]' * B[k][n]
+void gemm_tn(int m, int n, int k, const double* A, const double* B, double* C, bool acc) {
+  if (!acc) std::fill(C, C + (size_t)m * n, 0.0);
+  for (int l = 0; l < k; ++l)
+    for (int i = 0; i < m; ++i) {
+      const double a = A[(size_t)l * m + i];
+      if (a == 0.0) continue;
+      const double* b = B + (size_t)l * n;
+      double* c = C + (size_t)i * n;
+      for (int j = 0; j < n; ++j) c[j] += a * b[j];
+    }
+}
+// In-place Cholesky (lower) of an SPD n x n matrix; false if not SPD.
+bool cholesky(int n, double* A) {
+  for (int j = 0; j < n; ++j) {
+    double d = A[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) d -= A[(size_t)j * n + k] * A[(size_t)j * n + k];
+    if (!(d > 0.0) || !is_finite(d)) return false;
+    d = std::sqrt(d);
+    A[(size_t)j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double s = A[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) s -= A[(size_t)i * n + k] * A[(size_t)j * n + k];
+      A[(size_t)i * n + j] = s / d;
+    }
+  }
+  return true;
+}
+// Inverse of an SPD matrix from its lower Cholesky factor Lc.
+void chol_inverse(int n, const double* Lc, double* Inv) {
+  std::vector<double> col(n);
+  for (int e = 0; e < n; ++e) {
+    std::fill(col.begin(), col.end(), 0.0);
+    col[e] = 1.0;
+    for (int i = 0; i < n; ++i) {  // L y = e
+      double s = col[i];
+      for (int k = 0; k < i; ++k) s -= Lc[(size_t)i * n + k] * col[k];
+      col[i] = s / Lc[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {  // L' x = y
+      double s = col[i];
+      for (int k = i + 1; k < n; ++k) s -= Lc[(size_t)k * n + i] * col[k];
+      col[i] = s / Lc[(size_t)i * n + i];
+    }
+    for (int i = 0; i < n; ++i) Inv[(size_t)i * n + e] = col[i];
+  }
+}
+
+// Eigenvalues of a small symmetric matrix (cyclic Jacobi).
+void sym_eigs(int n, std::vector<double> A, std::vector<double>& ev) {
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0;
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j) off += A[i * n + j] * A[i * n + j];
+    if (off < 1e-300) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A[p * n + q];
+        if (apq == 0.0) continue;
+        const double th = 0.5 * (A[q * n + q] - A[p * n + p]) / apq;
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {
+          const double akp = A[k * n + p], akq = A[k * n + q];
+          A[k * n + p] = c * akp - s * akq;
+          A[k * n + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double apk = A[p * n + k], aqk = A[q * n + k];
+          A[p * n + k] = c * apk - s * aqk;
+          A[q * n + k] = s * apk + c * aqk;
+        }
+      }
+  }
+  ev.resize(n);
+  for (int i = 0; i < n; ++i) ev[i] = A[i * n + i];
+}
+
+int next_pow2_team(int v) {
+  int t = 8;
+  while (t < v && t < 64) t <<= 1;
+  return t;
+}
+
+// ---- exact nested AV@R cost of a trajectory (eq. original-problem)
+double avar_exact(const std::vector<double>& Z, const std::vector<double>& p, double a) {
+  if (a == 0.0) return *std::max_element(Z.begin(), Z.end());
+  double best = std::numeric_limits<double>::infinity();
+  for (double t : Z) {
+    double s = 0;
+    for (size_t k = 0; k < Z.size(); ++k) s += p[k] * std::max(Z[k] - t, 0.0);
+    best = std::min(best, t + s / a);
+  }
+  return best;
+}
+
+double nested_cost_host(const Problem& P, const std::vector<double>& x, const std::vector<double>& u) {
+  const Tree& T = *P.tree;
+  const int nx = P.nx, nu = P.nu;
+  std::vector<double> V(T.nn, 0.0);
+  for (int j = T.nl; j < T.nn; ++j) {
+    double s = 0;
+    for (int k = 0; k < nx; ++k) s += P.qN[(size_t)j * nx + k] * x[(size_t)j * nx + k] * x[(size_t)j * nx + k];
+    V[j] = s;
+  }
+  for (int i = T.nl - 1; i >= 0; --i) {
+    std::vector<double> Z, p;
+    for (int c = T.fc[i]; c < T.fc[i] + T.nch[i]; ++c) {
+      double l = V[c];
+      for (int k = 0; k < nx; ++k) l += P.q[(size_t)c * nx + k] * x[(size_t)i * nx + k] * x[(size_t)i * nx + k];
+      for (int k = 0; k < nu; ++k) l += P.r[(size_t)c * nu + k] * u[(size_t)i * nu + k] * u[(size_t)i * nu + k];
+      Z.push_back(l);
+      p.push_back(T.pcond[c]);
+    }
+    V[i] = avar_exact(Z, p, P.a_risk[i]);
+  }
+  return V[0];
+}
+
+template <typename S>
+S* align_ptr(char*& cur, size_t count) {
+  uintptr_t a = reinterpret_cast<uintptr_t>(cur);
+  a = (a + 255) & ~uintptr_t(255);
+  S* out = reinterpret_cast<S*>(a);
+  cur = reinterpret_cast<char*>(a + count * sizeof(S));
+  return out;
+}
+
+// Builds the device layout of precision S from the FP64 factorisation.
+template <typename S>
+int upload(Problem& P, const spock_problem_data& d, const std::vector<double>& Abar,
+           const std::vector<double>& K, const std::vector<double>& Rinv, const std::vector<double>& W) {
+  const Tree& T = *P.tree;
+  const int nn = T.nn, nl = T.nl, nx = P.nx, nu = P.nu;
+  // sizes (elements)
+  const size_t nvec = (size_t)nn * (4 * nx + 3 * nu) + 2 * (size_t)nn + 64;
+  const size_t nmat = (size_t)nn * (2 * nx * nx + 2 * nx * nu) + (size_t)nl * (2 * nu * nx + nu * nu + nx * nu);
+  const size_t bytes = (nvec + nmat) * sizeof(S) + 3 * (size_t)nn * sizeof(int) + 64 * 256;
+  std::vector<char> host(bytes, 0);
+  void* dmem = nullptr;
+  if (hipMalloc(&dmem, bytes) != hipSuccess) return SPOCK_ENOMEM;
+  // Offsets are aligned relative to the start of the block, so a host
+  // pointer and its device twin sit at the same offset.
+  size_t off = 0;
+  auto take = [&](size_t count, auto tag) {
+    using U = decltype(tag);
+    off = (off + 255) & ~size_t(255);
+    U* h = reinterpret_cast<U*>(host.data() + off);
+    U* dv = reinterpret_cast<U*>(static_cast<char*>(dmem) + off);
+    off += count * sizeof(U);
+    return std::make_pair(h, dv);
+  };
+  DevProb<S> D{};
+  D.nn = nn; D.nl = nl; D.nx = nx; D.nu = nu; D.N = T.N;
+  D.nz = P.nz; D.neta = P.neta;
+  D.zU = 1 + (long long)nn * nx;
+  D.zZ2 = D.zU + (long long)nl * nu;
+  D.eE2 = 2LL * (nn - 1) + (long long)nl * (2 + nx + nu);
+  D.eE3 = D.eE2 + (long long)(nn - 1) * (nx + nu + 2);
+  D.alpha = (S)P.alpha;
+  auto fcp = take(nn, int{});
+  auto nchp = take(nn, int{});
+  auto ancp = take(nn, int{});
+  for (int i = 0; i < nn; ++i) {
+    fcp.first[i] = T.fc[i];
+    nchp.first[i] = T.nch[i];
+    ancp.first[i] = T.anc[i];
+  }
+  D.fc = fcp.second; D.nch = nchp.second; D.anc = ancp.second;
+  auto pp = take(nn, S{});
+  auto ap = take(nn, S{});
+  for (int i = 0; i < nn; ++i) {
+    pp.first[i] = (S)T.pcond[i];
+    ap.first[i] = (S)d.a_risk[i];
+  }
+  D.p = pp.second; D.a = ap.second;
+  auto sqp = take((size_t)nn * nx, S{});
+  auto sqNp = take((size_t)nn * nx, S{});
+  auto xlop = take((size_t)nn * nx, S{});
+  auto xhip = take((size_t)nn * nx, S{});
+  auto srp = take((size_t)nn * nu, S{});
+  auto ulop = take((size_t)nn * nu, S{});
+  auto uhip = take((size_t)nn * nu, S{});
+  for (size_t e = 0; e < (size_t)nn * nx; ++e) {
+    sqp.first[e] = (S)std::sqrt(d.q[e]);
+    sqNp.first[e] = (S)std::sqrt(d.qN[e]);
+    xlop.first[e] = (S)d.xmin[e];
+    xhip.first[e] = (S)d.xmax[e];
+  }
+  for (size_t e = 0; e < (size_t)nn * nu; ++e) {
+    srp.first[e] = (S)std::sqrt(d.r[e]);
+    ulop.first[e] = (S)d.umin[e];
+    uhip.first[e] = (S)d.umax[e];
+  }
+  D.sq = sqp.second; D.sqN = sqNp.second; D.xlo = xlop.second; D.xhi = xhip.second;
+  D.sr = srp.second; D.ulo = ulop.second; D.uhi = uhip.second;
+  auto AbRp = take((size_t)nn * nx * nx, S{});
+  auto AbCp = take((size_t)nn * nx * nx, S{});
+  auto BRp = take((size_t)nn * nx * nu, S{});
+  auto BCp = take((size_t)nn * nx * nu, S{});
+  for (int c = 1; c < nn; ++c) {
+    const double* Ab = Abar.data() + (size_t)c * nx * nx;
+    const double* Bm = d.B + (size_t)c * nx * nu;
+    S* r1 = AbRp.first + (size_t)c * nx * nx;
+    S* c1 = AbCp.first + (size_t)c * nx * nx;
+    for (int r = 0; r < nx; ++r)
+      for (int k = 0; k < nx; ++k) {
+        r1[(size_t)r * nx + k] = (S)Ab[(size_t)r * nx + k];
+        c1[(size_t)k * nx + r] = (S)Ab[(size_t)r * nx + k];
+      }
+    S* r2 = BRp.first + (size_t)c * nx * nu;
+    S* c2 = BCp.first + (size_t)c * nx * nu;
+    for (int r = 0; r < nx; ++r)
+      for (int j = 0; j < nu; ++j) {
+        r2[(size_t)r * nu + j] = (S)Bm[(size_t)r * nu + j];
+        c2[(size_t)j * nx + r] = (S)Bm[(size_t)r * nu + j];
+      }
+  }
+  D.AbR = AbRp.second; D.AbC = AbCp.second; D.BR = BRp.second; D.BC = BCp.second;
+  auto KRp = take((size_t)nl * nu * nx, S{});
+  auto KCp = take((size_t)nl * nu * nx, S{});
+  auto Rip = take((size_t)nl * nu * nu, S{});
+  auto WCp = take((size_t)nl * nu * nx, S{});
+  for (int i = 0; i < nl; ++i) {
+    const double* Km = K.data() + (size_t)i * nu * nx;     // [nu][nx]
+    const double* Wm = W.data() + (size_t)i * nx * nu;     // [nx][nu]
+    for (int j = 0; j < nu; ++j)
+      for (int k = 0; k < nx; ++k) {
+        KRp.first[(size_t)i * nu * nx + (size_t)j * nx + k] = (S)Km[(size_t)j * nx + k];
+        KCp.first[(size_t)i * nu * nx + (size_t)k * nu + j] = (S)Km[(size_t)j * nx + k];
+      }
+    for (int e = 0; e < nu * nu; ++e) Rip.first[(size_t)i * nu * nu + e] = (S)Rinv[(size_t)i * nu * nu + e];
+    for (int r = 0; r < nx; ++r)
+      for (int j = 0; j < nu; ++j) WCp.first[(size_t)i * nu * nx + (size_t)j * nx + r] = (S)Wm[(size_t)r * nu + j];
+  }
+  D.KR = KRp.second; D.KC = KCp.second; D.Rinv = Rip.second; D.WC = WCp.second;
+  const size_t used = off;
+  if (used > bytes) {
+    (void)hipFree(dmem);
+    return SPOCK_ENOMEM;
+  }
+  if (hipMemcpy(dmem, host.data(), used, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(dmem);
+    return SPOCK_EHIP;
+  }
+  // Read the tree index arrays back: every kernel indexes through them.
+  {
+    std::vector<int> chk(3 * (size_t)nn);
+    if (hipMemcpy(chk.data(), D.fc, nn * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(chk.data() + nn, D.nch, nn * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(chk.data() + 2 * nn, D.anc, nn * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) {
+      (void)hipFree(dmem);
+      return SPOCK_EHIP;
+    }
+    for (int i = 0; i < nn; ++i)
+      if (chk[i] != T.fc[i] || chk[nn + i] != T.nch[i] || chk[2 * nn + i] != T.anc[i]) {
+        (void)hipFree(dmem);
+        return SPOCK_EHIP;
+      }
+  }
+  P.dmem = dmem;
+  if constexpr (sizeof(S) == 8) P.dp64 = D; else P.dp32 = D;
+  return SPOCK_OK;
+}
+
+}  // namespace
+
+// ============================================================== tree
+extern "C" int spock_tree_create(int32_t nn, const int32_t* anc, const double* prob, spock_tree** out) {
+  if (!out || !anc || !prob || nn < 2) return SPOCK_EINVAL;
+  Tree T;
+  T.nn = nn;
+  T.anc.assign(anc, anc + nn);
+  T.prob.assign(prob, prob + nn);
+  if (T.anc[0] != -1) return SPOCK_ETREE;
+  T.stage.assign(nn, 0);
+  T.nch.assign(nn, 0);
+  T.fc.assign(nn, -1);
+  for (int i = 1; i < nn; ++i) {
+    const int a = T.anc[i];
+    if (a < 0 || a >= i) return SPOCK_ETREE;
+    if (a < T.anc[i - 1]) return SPOCK_ETREE;  // breadth-first: ancestors nondecreasing
+    T.stage[i] = T.stage[a] + 1;
+    if (T.stage[i] < T.stage[i - 1]) return SPOCK_ETREE;
+    if (T.nch[a] == 0) T.fc[a] = i;
+    T.nch[a]++;
+  }
+  T.N = T.stage[nn - 1];
+  T.nl = 0;
+  for (int i = 0; i < nn; ++i) {
+    if (T.nch[i] > 0) {
+      if (i != T.nl) return SPOCK_ETREE;  // nonleaf nodes must precede leaves
+      T.nl++;
+    } else if (T.stage[i] != T.N) {
+      return SPOCK_ETREE;  // leaves only at the last stage
+    }
+  }
+  if (T.N < 1) return SPOCK_ETREE;
+  T.stage_off.assign(T.N + 2, nn);
+  for (int i = nn - 1; i >= 0; --i) T.stage_off[T.stage[i]] = i;
+  T.stage_off[T.N + 1] = nn;
+  // probabilities
+  for (int i = 0; i < nn; ++i)
+    if (!(T.prob[i] > 0.0) || !is_finite(T.prob[i])) return SPOCK_EPROB;
+  if (std::fabs(T.prob[0] - 1.0) > 1e-10) return SPOCK_EPROB;
+  T.pcond.assign(nn, 1.0);
+  for (int i = 0; i < T.nl; ++i) {
+    double s = 0;
+    for (int c = T.fc[i]; c < T.fc[i] + T.nch[i]; ++c) s += T.prob[c];
+    if (std::fabs(s - T.prob[i]) > 1e-10 * T.prob[i]) return SPOCK_EPROB;
+    for (int c = T.fc[i]; c < T.fc[i] + T.nch[i]; ++c) T.pcond[c] = T.prob[c] / T.prob[i];
+  }
+  spock_tree* h = new (std::nothrow) spock_tree;
+  if (!h) return SPOCK_ENOMEM;
+  h->t = std::move(T);
+  *out = h;
+  return SPOCK_OK;
+}
+
+extern "C" int spock_tree_destroy(spock_tree* t) {
+  if (!t) return SPOCK_EINVAL;
+  delete t;
+  return SPOCK_OK;
+}
+
+extern "C" int spock_tree_shape(const spock_tree* t, int32_t* N, int32_t* nl, int32_t* nleaf) {
+  if (!t) return SPOCK_EINVAL;
+  if (N) *N = t->t.N;
+  if (nl) *nl = t->t.nl;
+  if (nleaf) *nleaf = t->t.nn - t->t.nl;
+  return SPOCK_OK;
+}
+
+// ============================================================== problem
+extern "C" int spock_problem_factor(const spock_tree* th, const spock_problem_data* d, spock_problem** out) {
+  if (!th || !d || !out) return SPOCK_EINVAL;
+  const Tree& T = th->t;
+  const int nn = T.nn, nl = T.nl, nx = d->nx, nu = d->nu;
+  if (nx < 1 || nu < 1) return SPOCK_EINVAL;
+  if (nx > kMaxDim || nu > kMaxDim) return SPOCK_EUNSUPPORTED;
+  if (d->precision != SPOCK_FP64 && d->precision != SPOCK_FP32) return SPOCK_EINVAL;
+  if (!d->A || !d->B || !d->q || !d->r || !d->qN || !d->xmin || !d->xmax || !d->umin || !d->umax ||
+      !d->a_risk)
+    return SPOCK_EINVAL;
+  // data checks
+  for (int c = 1; c < nn; ++c) {
+    for (int e = 0; e < nx * nx; ++e) if (!is_finite(d->A[(size_t)c * nx * nx + e])) return SPOCK_EINVAL;
+    for (int e = 0; e < nx * nu; ++e) if (!is_finite(d->B[(size_t)c * nx * nu + e])) return SPOCK_EINVAL;
+    for (int k = 0; k < nx; ++k) if (!(d->q[(size_t)c * nx + k] > 0.0) || !is_finite(d->q[(size_t)c * nx + k])) return SPOCK_EINVAL;
+    for (int k = 0; k < nu; ++k) if (!(d->r[(size_t)c * nu + k] > 0.0) || !is_finite(d->r[(size_t)c * nu + k])) return SPOCK_EINVAL;
+  }
+  for (int j = nl; j < nn; ++j)
+    for (int k = 0; k < nx; ++k) if (!(d->qN[(size_t)j * nx + k] >= 0.0) || !is_finite(d->qN[(size_t)j * nx + k])) return SPOCK_EINVAL;
+  for (int i = 0; i < nn; ++i)
+    for (int k = 0; k < nx; ++k) {
+      const double lo = d->xmin[(size_t)i * nx + k], hi = d->xmax[(size_t)i * nx + k];
+      if (std::isnan(lo) || std::isnan(hi) || lo > hi) return SPOCK_EBOX;
+    }
+  for (int i = 0; i < nl; ++i) {
+    for (int k = 0; k < nu; ++k) {
+      const double lo = d->umin[(size_t)i * nu + k], hi = d->umax[(size_t)i * nu + k];
+      if (std::isnan(lo) || std::isnan(hi) || lo > hi) return SPOCK_EBOX;
+    }
+    if (!(d->a_risk[i] >= 0.0 && d->a_risk[i] <= 1.0)) return SPOCK_EINVAL;
+  }
+
+  // ---- Alg. 1, FP64: stage N-1 down to 0; nodes of a stage in parallel
+  std::vector<double> Pm((size_t)nn * nx * nx, 0.0), Abar((size_t)nn * nx * nx, 0.0);
+  std::vector<double> K((size_t)nl * nu * nx), Rinv((size_t)nl * nu * nu), W((size_t)nl * nx * nu);
+  for (int j = nl; j < nn; ++j)
+    for (int k = 0; k < nx; ++k) Pm[(size_t)j * nx * nx + (size_t)k * nx + k] = 1.0;
+  bool ok = true;
+  for (int t = T.N - 1; t >= 0; --t) {
+    const int first = T.stage_off[t], count = T.stage_off[t + 1] - first;
+    std::vector<char> good(count, 1);
+    parallel_for(count, [&](int f) {
+      const int i = first + f;
+      std::vector<double> Rt((size_t)nu * nu, 0.0), SA((size_t)nu * nx, 0.0), Pt((size_t)nu * nx),
+          PB((size_t)nx * nu), tmp((size_t)nx * nx), Lc((size_t)nu * nu);
+      for (int k = 0; k < nu; ++k) Rt[(size_t)k * nu + k] = 1.0;
+      for (int c = T.fc[i]; c < T.fc[i] + T.nch[i]; ++c) {
+        const double* Bc = d->B + (size_t)c * nx * nu;
+        const double* Ac = d->A + (size_t)c * nx * nx;
+        const double* Pc = Pm.data() + (size_t)c * nx * nx;
+        gemm_tn(nu, nx, nx, Bc, Pc, Pt.data(), false);          // P~ = B'P
+        gemm(nu, nu, nx, Pt.data(), Bc, Rt.data(), true);       // R~ += P~ B
+        gemm(nu, nx, nx, Pt.data(), Ac, SA.data(), true);       // sum P~ A
+      }
+      Lc = Rt;
+      if (!cholesky(nu, Lc.data())) {
+        good[f] = 0;
+        return;
+      }
+      double* Ri = Rinv.data() + (size_t)i * nu * nu;
+      chol_inverse(nu, Lc.data(), Ri);
+      double* Ki = K.data() + (size_t)i * nu * nx;
+      gemm(nu, nx, nu, Ri, SA.data(), Ki, false);
+      for (int e = 0; e < nu * nx; ++e) Ki[e] = -Ki[e];
+      double* Pi = Pm.data() + (size_t)i * nx * nx;
+      gemm_tn(nx, nx, nu, Ki, Ki, Pi, false);                    // K'K
+      for (int k = 0; k < nx; ++k) Pi[(size_t)k * nx + k] += 1.0;
+      double* Wi = W.data() + (size_t)i * nx * nu;
+      std::fill(Wi, Wi + (size_t)nx * nu, 0.0);
+      for (int c = T.fc[i]; c < T.fc[i] + T.nch[i]; ++c) {
+        const double* Bc = d->B + (size_t)c * nx * nu;
+        const double* Ac = d->A + (size_t)c * nx * nx;
+        const double* Pc = Pm.data() + (size_t)c * nx * nx;
+        double* Ab = Abar.data() + (size_t)c * nx * nx;
+        std::copy(Ac, Ac + (size_t)nx * nx, Ab);
+        gemm(nx, nx, nu, Bc, Ki, Ab, true);                       // Abar = A + B K
+        gemm(nx, nx, nx, Pc, Ab, tmp.data(), false);              // P Abar
+        gemm_tn(nx, nx, nx, Ab, tmp.data(), Pi, true);            // += Abar' P Abar
+        gemm(nx, nu, nx, Pc, Bc, PB.data(), false);               // P B
+        gemm_tn(nx, nu, nx, Ab, PB.data(), Wi, true);             // W += Abar' P B
+      }
+      for (int e = 0; e < nx * nx; ++e)
+        if (!is_finite(Pi[e])) good[f] = 0;
+    });
+    for (char g : good) ok = ok && g;
+    if (!ok) return SPOCK_EFACTOR;
+  }
+
+  // ---- ||L||: block-diagonal after a column permutation; closed forms per block
+  double best2 = 0.5;  // tau^c and leaf s^j columns: rows (1/2, 1/2)
+  for (int i = 0; i < nl; ++i) {
+    for (int k = 0; k < nx; ++k) {
+      double s = 1.0;
+      for (int c = T.fc[i]; c < T.fc[i] + T.nch[i]; ++c) s += d->q[(size_t)c * nx + k];
+      best2 = std::max(best2, s);
+    }
+    for (int k = 0; k < nu; ++k) {
+      double s = 1.0;
+      for (int c = T.fc[i]; c < T.fc[i] + T.nch[i]; ++c) s += d->r[(size_t)c * nu + k];
+      best2 = std::max(best2, s);
+    }
+    // (y^i, s^i) block [[I, 0], [-b', 1]]: sigma^2 = 1 + beta^2/2 + beta sqrt(1 + beta^2/4)
+    double b2 = 1.0;
+    for (int c = T.fc[i]; c < T.fc[i] + T.nch[i]; ++c) b2 += T.pcond[c] * T.pcond[c];
+    const double beta = std::sqrt(b2);
+    best2 = std::max(best2, 1.0 + 0.5 * b2 + beta * std::sqrt(1.0 + 0.25 * b2));
+  }
+  for (int j = nl; j < nn; ++j)
+    for (int k = 0; k < nx; ++k) best2 = std::max(best2, 1.0 + d->qN[(size_t)j * nx + k]);
+  const double normL = std::sqrt(best2);
+  double alpha = d->alpha;
+  if (alpha <= 0.0) alpha = 0.99 / normL;
+  else if (!(alpha * normL < 1.0)) return SPOCK_EINVAL;
+
+  spock_problem* h = new (std::nothrow) spock_problem;
+  if (!h) return SPOCK_ENOMEM;
+  Problem& P = h->p;
+  P.tree = &T;
+  P.precision = d->precision;
+  P.nx = nx;
+  P.nu = nu;
+  P.nz = 1 + (long long)nn * nx + (long long)nl * nu + 4LL * (nn - 1) + nl;
+  P.neta = 2LL * (nn - 1) + 2LL * nl + (long long)nl * (nx + nu) + (long long)(nn - 1) * (nx + nu + 2) +
+           (long long)(nn - nl) * (2 * nx + 2);
+  P.alpha = alpha;
+  P.normL = normL;
+  P.xlo0.assign(d->xmin, d->xmin + nx);
+  P.xhi0.assign(d->xmax, d->xmax + nx);
+  P.q.assign(d->q, d->q + (size_t)nn * nx);
+  P.r.assign(d->r, d->r + (size_t)nn * nu);
+  P.qN.assign(d->qN, d->qN + (size_t)nn * nx);
+  P.a_risk.assign(d->a_risk, d->a_risk + nn);
+  int team = next_pow2_team(std::max(nx, nu));
+  if (const char* env = std::getenv("SPOCK_TEAM")) {
+    const int v = std::atoi(env);
+    if (v == 8 || v == 16 || v == 32 || v == 64) team = v;
+  }
+  P.team = team;
+  P.teams_per_block = 256 / team;
+  P.fwd_blk_off.assign(T.N + 1, 0);
+  int acc = 0;
+  for (int t = 0; t < T.N; ++t) {
+    P.fwd_blk_off[t] = acc;
+    const int count = T.stage_off[t + 1] - T.stage_off[t];
+    acc += (count + P.teams_per_block - 1) / P.teams_per_block;
+  }
+  P.fwd_blk_off[T.N] = acc;
+  P.fwd_blocks = acc;
+  const int rc = (d->precision == SPOCK_FP64) ? upload<double>(P, *d, Abar, K, Rinv, W)
+                                              : upload<float>(P, *d, Abar, K, Rinv, W);
+  if (rc != SPOCK_OK) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return SPOCK_OK;
+}
+
+extern "C" int spock_problem_destroy(spock_problem* p) {
+  if (!p) return SPOCK_EINVAL;
+  if (p->p.dmem) (void)hipFree(p->p.dmem);
+  if (p->p.work) (void)hipFree(p->p.work);
+  delete p;
+  return SPOCK_OK;
+}
+
+extern "C" int spock_problem_sizes(const spock_problem* p, int64_t* nz, int64_t* neta, double* alpha,
+                                   double* normL) {
+  if (!p) return SPOCK_EINVAL;
+  if (nz) *nz = p->p.nz;
+  if (neta) *neta = p->p.neta;
+  if (alpha) *alpha = p->p.alpha;
+  if (normL) *normL = p->p.normL;
+  return SPOCK_OK;
+}
+
+extern "C" void spock_settings_default(spock_settings* s) {
+  if (!s) return;
+  s->eps_abs = 1e-4;
+  s->eps_rel = 1e-4;
+  s->max_iters = 20000;
+  s->method = SPOCK_METHOD_SPOCK;
+  s->m = 3;
+  s->max_ls = 20;
+  s->c0 = 0.99;
+  s->c1 = 0.99;
+  s->c2 = 0.99;
+  s->beta = 0.5;
+  s->sigma = 0.1;
+  s->lambda = 1.0;
+  s->compute_nested = 0;
+}
+
+extern "C" const char* spock_version(void) { return "spock-mi355x 0.1 (gfx950)"; }
+
+// ============================================================== workspace
+namespace {
+
+constexpr int kMaxMem = 4;  // Anderson memory supported by the push kernel
+
+template <typename S>
+struct Work {
+  S* q = nullptr;
+  S* d = nullptr;
+  double* partials = nullptr;
+  double* stats = nullptr;    // [8]
+  double* dots = nullptr;     // [16]
+  double* gamma = nullptr;    // [8]
+  double* vpart = nullptr;    // vector-kernel partials [blocks][8]
+  S* eta_zero = nullptr;      // n_eta zeros
+  S* pool[10 + 2 * kMaxMem];  // n_v buffers
+  double* host_stats = nullptr;
+};
+
+template <typename S>
+int ensure_work(Problem& P, Work<S>& W) {
+  const Tree& T = *P.tree;
+  const long long nv = P.nz + P.neta;
+  const int nblk = dots_blocks(nv);
+  size_t bytes = 0;
+  auto add = [&](size_t b) { bytes += (b + 255) & ~size_t(255); };
+  add(sizeof(S) * (size_t)T.nn * P.nx);
+  add(sizeof(S) * (size_t)T.nn * P.nu);
+  add(sizeof(double) * (size_t)(P.fwd_blocks + 1) * kStats);
+  add(sizeof(double) * 8);
+  add(sizeof(double) * 16);
+  add(sizeof(double) * 8);
+  add(sizeof(double) * (size_t)nblk * 8);
+  add(sizeof(S) * (size_t)P.neta);
+  for (int k = 0; k < 10 + 2 * kMaxMem; ++k) add(sizeof(S) * (size_t)nv);
+  if (P.work_bytes < bytes) {
+    if (P.work) (void)hipFree(P.work);
+    P.work = nullptr;
+    P.work_bytes = 0;
+    if (hipMalloc(&P.work, bytes) != hipSuccess) return SPOCK_ENOMEM;
+    P.work_bytes = bytes;
+    if (hipMemset(P.work, 0, bytes) != hipSuccess) return SPOCK_EHIP;
+  }
+  // base-relative offsets, in the same order as the size computation above
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    char* p = static_cast<char*>(P.work) + off;
+    off += (b + 255) & ~size_t(255);
+    return p;
+  };
+  W.q = reinterpret_cast<S*>(take(sizeof(S) * (size_t)T.nn * P.nx));
+  W.d = reinterpret_cast<S*>(take(sizeof(S) * (size_t)T.nn * P.nu));
+  W.partials = reinterpret_cast<double*>(take(sizeof(double) * (size_t)(P.fwd_blocks + 1) * kStats));
+  W.stats = reinterpret_cast<double*>(take(sizeof(double) * 8));
+  W.dots = reinterpret_cast<double*>(take(sizeof(double) * 16));
+  W.gamma = reinterpret_cast<double*>(take(sizeof(double) * 8));
+  W.vpart = reinterpret_cast<double*>(take(sizeof(double) * (size_t)nblk * 8));
+  W.eta_zero = reinterpret_cast<S*>(take(sizeof(S) * (size_t)P.neta));
+  for (int k = 0; k < 10 + 2 * kMaxMem; ++k) W.pool[k] = reinterpret_cast<S*>(take(sizeof(S) * (size_t)nv));
+  if (off > P.work_bytes) return SPOCK_ENOMEM;
+  return SPOCK_OK;
+}
+
+struct Stats {
+  double xip = 0, xid = 0, om2 = 0, rz2 = 0, re2 = 0, cross = 0;
+  double xi() const { return std::max(xip, xid); }
+  double omega() const { return std::sqrt(std::max(om2, 0.0)); }
+  bool ok() const { return std::isfinite(xip) && std::isfinite(xid) && std::isfinite(om2); }
+};
+
+template <typename S>
+struct Solver {
+  Problem& P;
+  Work<S> W;
+  hipStream_t st;
+  const double* x0;
+  long long nv;
+  int t_evals = 0;
+  std::vector<double> hbuf = std::vector<double>(16);
+
+  Solver(Problem& p, hipStream_t s, const double* x) : P(p), st(s), x0(x), nv(p.nz + p.neta) {}
+
+  int T(const S* v, S* Tv, Stats& out) {
+    HIP_TRY(launch_T<S>(P, v, Tv, x0, W.q, W.d, W.partials, W.stats, st, W.eta_zero, true));
+    HIP_TRY(hipMemcpyAsync(hbuf.data(), W.stats, 6 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    out.xip = hbuf[0];
+    out.xid = hbuf[1];
+    out.om2 = hbuf[2];
+    out.rz2 = hbuf[3];
+    out.re2 = hbuf[4];
+    out.cross = hbuf[5];
+    ++t_evals;
+    return SPOCK_OK;
+  }
+  int fetch(double* dst, const double* src, int k) {
+    HIP_TRY(hipMemcpyAsync(dst, src, k * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return SPOCK_OK;
+  }
+};
+
+// Anderson ring: ages of active columns (oldest first) and the Gram matrix.
+struct AARing {
+  int m = 0;
+  std::vector<int> order;                // active slots, oldest first
+  std::vector<double> G;                 // m x m, indexed by slot
+  std::vector<double> rhs;               // <dR_slot, r>
+  void reset(int mm) {
+    m = mm;
+    order.clear();
+    G.assign((size_t)m * m, 0.0);
+    rhs.assign(m, 0.0);
+  }
+  int free_slot() const {
+    for (int s = 0; s < m; ++s)
+      if (std::find(order.begin(), order.end(), s) == order.end()) return s;
+    return order.front();
+  }
+};
+
+// Solves the Gram system for the active columns after applying the rank rule
+// (drop the oldest column while lambda_min/lambda_max(G) < 1e-12, i.e.
+// sigma_min/sigma_max(dR) < 1e-6). Returns the number of columns kept.
+int aa_solve(AARing& A, std::vector<double>& gamma) {
+  while (!A.order.empty()) {
+    const int k = (int)A.order.size();
+    std::vector<double> Gs((size_t)k * k);
+    for (int a = 0; a < k; ++a)
+      for (int b = 0; b < k; ++b) Gs[(size_t)a * k + b] = A.G[(size_t)A.order[a] * A.m + A.order[b]];
+    std::vector<double> ev;
+    sym_eigs(k, Gs, ev);
+    const double lmax = *std::max_element(ev.begin(), ev.end());
+    const double lmin = *std::min_element(ev.begin(), ev.end());
+    if (lmax > 0.0 && lmin / lmax >= 1e-12) {
+      std::vector<double> Lc = Gs;
+      if (cholesky(k, Lc.data())) {
+        gamma.assign(k, 0.0);
+        std::vector<double> y(k);
+        for (int i = 0; i < k; ++i) {
+          double s = A.rhs[A.order[i]];
+          for (int j = 0; j < i; ++j) s -= Lc[(size_t)i * k + j] * y[j];
+          y[i] = s / Lc[(size_t)i * k + i];
+        }
+        for (int i = k - 1; i >= 0; --i) {
+          double s = y[i];
+          for (int j = i + 1; j < k; ++j) s -= Lc[(size_t)j * k + i] * gamma[j];
+          gamma[i] = s / Lc[(size_t)i * k + i];
+        }
+        return k;
+      }
+    }
+    A.order.erase(A.order.begin());
+  }
+  gamma.clear();
+  return 0;
+}
+
+template <typename S>
+int solve_impl(Problem& P, const double* x0, const spock_settings& s, S* vio, spock_info& info,
+               hipStream_t st) {
+  Solver<S> SV(P, st, x0);
+  int rc = ensure_work<S>(P, SV.W);
+  if (rc) return rc;
+  Work<S>& W = SV.W;
+  const long long nv = SV.nv;
+  const double al = P.alpha;
+  // roles over the buffer pool
+  S* v = W.pool[0];
+  S* Tv = W.pool[1];
+  S* vprev = W.pool[2];
+  S* rprev = W.pool[3];
+  S* rcur = W.pool[4];
+  S* dir = W.pool[5];
+  S* Md = W.pool[6];
+  S* vt = W.pool[7];
+  S* Tvt = W.pool[8];
+  S* spare = W.pool[9];
+  S* dV[kMaxMem];
+  S* dR[kMaxMem];
+  for (int k = 0; k < kMaxMem; ++k) {
+    dV[k] = W.pool[10 + k];
+    dR[k] = W.pool[10 + kMaxMem + k];
+  }
+  HIP_TRY(hipMemcpyAsync(v, vio, sizeof(S) * nv, hipMemcpyDeviceToDevice, st));
+  Stats S0, Sc, St;
+  rc = SV.T(v, Tv, S0);
+  if (rc) return rc;
+  Sc = S0;
+  info.xi0 = S0.xi();
+  const double tol = std::max(s.eps_abs, s.eps_rel * info.xi0);
+  int k = 0;
+  auto finish = [&](int status) -> int {
+    HIP_TRY(hipMemcpyAsync(vio, Tv, sizeof(S) * nv, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    info.status = status;
+    info.iters = k;
+    info.t_evals = SV.t_evals;
+    info.xi = Sc.xi();
+    return SPOCK_OK;
+  };
+  if (!S0.ok()) return finish(SPOCK_NUMERICAL);
+
+  if (s.method == SPOCK_METHOD_CP) {
+    for (;;) {
+      if (Sc.xi() <= tol) return finish(SPOCK_CONVERGED);
+      if (k >= s.max_iters) return finish(SPOCK_MAXITER);
+      std::swap(v, Tv);
+      rc = SV.T(v, Tv, Sc);
+      if (rc) return rc;
+      ++k;
+      if (!Sc.ok()) return finish(SPOCK_NUMERICAL);
+    }
+  }
+
+  // ---- SPOCK (Alg. 3 with the residual formed before the tests)
+  double zeta = S0.omega(), omega_safe = S0.omega();
+  AARing ring;
+  ring.reset(s.m);
+  bool have_prev = false;
+  std::vector<double> gamma, hd(16);
+  for (;;) {
+    if (Sc.xi() <= tol) return finish(SPOCK_CONVERGED);
+    if (k >= s.max_iters) return finish(SPOCK_MAXITER);
+    // residual of the current iterate and the Anderson buffers
+    if (have_prev) {
+      int slot;
+      if ((int)ring.order.size() == ring.m) {
+        slot = ring.order.front();
+        ring.order.erase(ring.order.begin());
+      } else {
+        slot = ring.free_slot();
+      }
+      VecPtrs<S> olds{};
+      const int mo = (int)ring.order.size();
+      for (int j = 0; j < mo; ++j) olds.p[j] = dR[ring.order[j]];
+      HIP_TRY(launch_aa_push<S>(nv, v, vprev, Tv, rprev, rcur, dV[slot], dR[slot], mo, olds, W.vpart,
+                                W.dots, st));
+      rc = SV.fetch(hd.data(), W.dots, 2 * mo + 2);
+      if (rc) return rc;
+      for (int j = 0; j < mo; ++j) {
+        ring.G[(size_t)ring.order[j] * ring.m + slot] = hd[j];
+        ring.G[(size_t)slot * ring.m + ring.order[j]] = hd[j];
+        ring.rhs[ring.order[j]] = hd[mo + 1 + j];
+      }
+      ring.G[(size_t)slot * ring.m + slot] = hd[mo];
+      ring.rhs[slot] = hd[2 * mo + 1];
+      ring.order.push_back(slot);
+    } else {
+      HIP_TRY(launch_lincomb<S>(nv, rcur, 1.0, v, -1.0, Tv, st));
+    }
+    const int kept = aa_solve(ring, gamma);
+    if (kept > 0) {
+      VecPtrs<S> pv{}, pr{};
+      for (int j = 0; j < kept; ++j) {
+        pv.p[j] = dV[ring.order[j]];
+        pr.p[j] = dR[ring.order[j]];
+      }
+      HIP_TRY(hipMemcpyAsync(W.gamma, gamma.data(), kept * sizeof(double), hipMemcpyHostToDevice, st));
+      HIP_TRY(launch_aa_dir<S>(nv, rcur, kept, pv, pr, W.gamma, dir, st));
+    } else {
+      HIP_TRY(launch_lincomb<S>(nv, dir, -1.0, rcur, 0.0, nullptr, st));
+    }
+    const double omega = Sc.omega();
+    auto accept_prev = [&]() {
+      std::swap(vprev, v);      // vprev <- old v
+      std::swap(rprev, rcur);   // rprev <- old r
+      have_prev = true;
+    };
+    if (omega <= s.c0 * zeta) {  // K0
+      HIP_TRY(launch_lincomb<S>(nv, spare, 1.0, v, 1.0, dir, st));
+      accept_prev();
+      std::swap(v, spare);       // v <- v_old + d ; spare <- old vprev
+      zeta = omega;
+      info.n_k0++;
+      rc = SV.T(v, Tv, Sc);
+      if (rc) return rc;
+      ++k;
+      if (!Sc.ok()) return finish(SPOCK_NUMERICAL);
+      continue;
+    }
+    // M d = (d_z - alpha L* d_eta, d_eta - alpha L d_z), formed once per iteration
+    HIP_TRY(launch_Lt<S>(P, dir + P.nz, Md, st));
+    HIP_TRY(launch_L<S>(P, dir, Md + P.nz, st));
+    HIP_TRY(launch_lincomb<S>(nv, Md, -al, Md, 1.0, dir, st));
+    double tau = 1.0;
+    bool accepted = false;
+    for (int ls = 0; ls < s.max_ls; ++ls) {
+      HIP_TRY(launch_lincomb<S>(nv, vt, 1.0, v, tau, dir, st));
+      rc = SV.T(vt, Tvt, St);
+      if (rc) return rc;
+      if (!St.ok()) {
+        tau *= s.beta;
+        info.n_backtracks++;
+        continue;
+      }
+      const double om_t = St.omega();
+      if (om_t == 0.0 || (omega <= omega_safe && om_t <= s.c1 * omega)) {  // K1
+        accept_prev();
+        std::swap(v, vt);
+        std::swap(Tv, Tvt);
+        Sc = St;
+        omega_safe = om_t + std::pow(s.c2, k);
+        info.n_k1++;
+        accepted = true;
+        break;
+      }
+      HIP_TRY(launch_rdot<S>(nv, vt, Tvt, Md, W.vpart, W.dots, st));
+      rc = SV.fetch(hd.data(), W.dots, 1);
+      if (rc) return rc;
+      const double rho = om_t * om_t - tau * hd[0];
+      if (rho >= s.sigma * om_t * omega) {  // K2: v - lambda rho / om_t^2 (vt - Tvt)
+        const double c = s.lambda * rho / (om_t * om_t);
+        HIP_TRY(launch_lincomb3<S>(nv, spare, 1.0, v, -c, vt, c, Tvt, st));
+        accept_prev();
+        std::swap(v, spare);
+        info.n_k2++;
+        rc = SV.T(v, Tv, Sc);
+        if (rc) return rc;
+        accepted = true;
+        break;
+      }
+      tau *= s.beta;
+      info.n_backtracks++;
+    }
+    if (!accepted) {  // plain KM step
+      HIP_TRY(launch_lincomb<S>(nv, spare, 1.0, v, -s.lambda, rcur, st));
+      accept_prev();
+      std::swap(v, spare);
+      info.n_km++;
+      rc = SV.T(v, Tv, Sc);
+      if (rc) return rc;
+    }
+    ++k;
+    if (!Sc.ok()) return finish(SPOCK_NUMERICAL);
+  }
+}
+
+}  // namespace
+
+extern "C" int spock_solve(spock_problem* ph, const double* x0_dev, const spock_settings* s, void* v_io,
+                           spock_info* info, void* stream) {
+  if (!ph || !x0_dev || !s || !v_io || !info) return SPOCK_EINVAL;
+  if (s->method != SPOCK_METHOD_CP && s->method != SPOCK_METHOD_SPOCK) return SPOCK_EINVAL;
+  if (s->method == SPOCK_METHOD_SPOCK && (s->m < 1 || s->m > kMaxMem)) return SPOCK_EINVAL;
+  if (!(s->eps_abs >= 0 && s->eps_rel >= 0) || s->max_iters < 0 || s->max_ls < 1) return SPOCK_EINVAL;
+  if (!(s->beta > 0 && s->beta < 1 && s->sigma > 0 && s->sigma < 1 && s->lambda > 0 && s->lambda < 2))
+    return SPOCK_EINVAL;
+  Problem& P = ph->p;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const auto t0 = std::chrono::steady_clock::now();
+  // x0 must lie in the root's state box
+  std::vector<double> hx(P.nx);
+  HIP_TRY(hipMemcpyAsync(hx.data(), x0_dev, P.nx * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  for (int k = 0; k < P.nx; ++k)
+    if (!(hx[k] >= P.xlo0[k] && hx[k] <= P.xhi0[k])) return SPOCK_EBOX;
+  spock_info loc{};
+  loc.V_nested = std::numeric_limits<double>::quiet_NaN();
+  int rc = (P.precision == SPOCK_FP64)
+               ? solve_impl<double>(P, x0_dev, *s, static_cast<double*>(v_io), loc, st)
+               : solve_impl<float>(P, x0_dev, *s, static_cast<float*>(v_io), loc, st);
+  if (rc) return rc;
+  // s^0 and, on request, the nested cost of the returned trajectory
+  const Tree& T = *P.tree;
+  const size_t nxu = (size_t)T.nn * P.nx + (size_t)T.nl * P.nu;
+  std::vector<double> hv(1 + nxu);
+  if (P.precision == SPOCK_FP64) {
+    HIP_TRY(hipMemcpy(hv.data(), v_io, (s->compute_nested ? 1 + nxu : 1) * sizeof(double),
+                      hipMemcpyDeviceToHost));
+  } else {
+    std::vector<float> hf(1 + nxu);
+    HIP_TRY(hipMemcpy(hf.data(), v_io, (s->compute_nested ? 1 + nxu : 1) * sizeof(float),
+                      hipMemcpyDeviceToHost));
+    for (size_t e = 0; e < hf.size(); ++e) hv[e] = hf[e];
+  }
+  loc.V_s0 = hv[0];
+  if (s->compute_nested) {
+    std::vector<double> x(hv.begin() + 1, hv.begin() + 1 + (size_t)T.nn * P.nx);
+    std::vector<double> u(hv.begin() + 1 + (size_t)T.nn * P.nx, hv.end());
+    loc.V_nested = nested_cost_host(P, x, u);
+  }
+  loc.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  *info = loc;
+  return SPOCK_OK;
+}
+
+// ============================================================== operator entry points
+extern "C" int spock_apply_L(spock_problem* ph, const void* z, void* eta, void* stream) {
+  if (!ph || !z || !eta) return SPOCK_EINVAL;
+  Problem& P = ph->p;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = (P.precision == SPOCK_FP64)
+                     ? launch_L<double>(P, static_cast<const double*>(z), static_cast<double*>(eta), st)
+                     : launch_L<float>(P, static_cast<const float*>(z), static_cast<float*>(eta), st);
+  return e == hipSuccess ? SPOCK_OK : SPOCK_EHIP;
+}
+
+extern "C" int spock_apply_Lt(spock_problem* ph, const void* eta, void* z, void* stream) {
+  if (!ph || !z || !eta) return SPOCK_EINVAL;
+  Problem& P = ph->p;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = (P.precision == SPOCK_FP64)
+                     ? launch_Lt<double>(P, static_cast<const double*>(eta), static_cast<double*>(z), st)
+                     : launch_Lt<float>(P, static_cast<const float*>(eta), static_cast<float*>(z), st);
+  return e == hipSuccess ? SPOCK_OK : SPOCK_EHIP;
+}
+
+extern "C" int spock_prox_gstar(spock_problem* ph, const void* w, void* out, void* stream) {
+  if (!ph || !w || !out) return SPOCK_EINVAL;
+  Problem& P = ph->p;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = (P.precision == SPOCK_FP64)
+                     ? launch_prox_gstar<double>(P, static_cast<const double*>(w), static_cast<double*>(out), st)
+                     : launch_prox_gstar<float>(P, static_cast<const float*>(w), static_cast<float*>(out), st);
+  return e == hipSuccess ? SPOCK_OK : SPOCK_EHIP;
+}
+
+namespace {
+template <typename S>
+int prox_f_impl(Problem& P, const S* zin, const double* x0, S* zout, hipStream_t st) {
+  Work<S> W;
+  int rc = ensure_work<S>(P, W);
+  if (rc) return rc;
+  HIP_TRY(launch_fill<S>(P.neta, W.eta_zero, 0.0, st));
+  HIP_TRY(launch_T<S>(P, zin, zout, x0, W.q, W.d, W.partials, W.stats, st, W.eta_zero, false));
+  return SPOCK_OK;
+}
+template <typename S>
+int T_impl(Problem& P, const S* v, const double* x0, S* Tv, double* stats, hipStream_t st) {
+  Work<S> W;
+  int rc = ensure_work<S>(P, W);
+  if (rc) return rc;
+  HIP_TRY(launch_T<S>(P, v, Tv, x0, W.q, W.d, W.partials, W.stats, st, W.eta_zero, true));
+  if (stats) {
+    HIP_TRY(hipMemcpyAsync(stats, W.stats, 6 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  return SPOCK_OK;
+}
+}  // namespace
+
+extern "C" int spock_prox_f(spock_problem* ph, const void* zin, const double* x0, void* zout, void* stream) {
+  if (!ph || !zin || !zout || !x0) return SPOCK_EINVAL;
+  Problem& P = ph->p;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  return (P.precision == SPOCK_FP64)
+             ? prox_f_impl<double>(P, static_cast<const double*>(zin), x0, static_cast<double*>(zout), st)
+             : prox_f_impl<float>(P, static_cast<const float*>(zin), x0, static_cast<float*>(zout), st);
+}
+
+extern "C" int spock_T(spock_problem* ph, const void* v, const double* x0, void* Tv, double* stats,
+                       void* stream) {
+  if (!ph || !v || !Tv || !x0) return SPOCK_EINVAL;
+  Problem& P = ph->p;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  return (P.precision == SPOCK_FP64)
+             ? T_impl<double>(P, static_cast<const double*>(v), x0, static_cast<double*>(Tv), stats, st)
+             : T_impl<float>(P, static_cast<const float*>(v), x0, static_cast<float*>(Tv), stats, st);
+}
+
+extern "C" int spock_solve_batched(int32_t B, spock_problem* const* probs, const double* const* x0,
+                                   const spock_settings* s, void* const* v_io, spock_info* infos,
+                                   void* stream) {
+  (void)B; (void)probs; (void)x0; (void)s; (void)v_io; (void)infos; (void)stream;
+  return SPOCK_EUNSUPPORTED;
+}

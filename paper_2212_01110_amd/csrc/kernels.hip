@@ -1,0 +1,1045 @@
+// HIP kernels (gfx950) of the SPOCK hot path: one Chambolle-Pock operator T
+// under the splitting of section 5, plus the vector kernels of the
+// SuperMann / Anderson layer (section 6).
+//
+// Work decomposition. Every nonleaf node i owns a "family": itself and its
+// children. A team of T lanes (T in {8,16,32,64}, inside one wavefront) runs
+// one family; lane o owns component o (and o+T, o+2T, ...) of every state or
+// input vector. A stage of the tree is one launch: all families of a stage
+// are independent (the "in parallel" loops of Alg. 1 and Alg. 2).
+//
+//  backward launch (stage N-1 .. 0), family i:
+//    xbar, ubar = (x, u) - alpha (L* eta)       [L* columns of family i]
+//    q of leaf children = -xbar(leaf)            [Alg. 2 initialisation]
+//    d = R~^{-1}(ubar - sum_c B^c' q^c)
+//    q = K'(d - ubar) - xbar + W d + sum_c Abar^c' q^c,
+//        with W = sum_c Abar^c' P^c B^c          [Alg. 2, regrouped]
+//    S2 projection of the family's z2 block and s^0 - alpha at the root
+//  forward launch (stage 0 .. N-1), family i:
+//    u = K x + d, x^c = Abar^c x + B^c d          [Alg. 2 forward sweep]
+//    eta+ = prox_{alpha g*}(eta + alpha L(2 z+ - z)) on the family's rows
+//    residual statistics of r = v - T(v): ||r_z||^2, ||r_eta||^2,
+//    <r_eta, L r_z>, ||xi_p||_inf, ||xi_d||_inf   [section 3, Alg. 3]
+// Every row of L and every column of L* belongs to exactly one family, so
+// L r_z and L* r_eta are formed locally without a second pass.
+#include "spock_internal.h"
+
+#include <math.h>
+#include <algorithm>
+
+namespace spk {
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ void wave_lds_sync() {
+  // Teams live inside one wavefront: LDS traffic between their lanes only
+  // needs ordering at wavefront scope.
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int T>
+__device__ __forceinline__ double team_sum(double v) {
+#pragma unroll
+  for (int m = T / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, T);
+  return v;
+}
+
+template <typename S>
+__device__ __forceinline__ S clampv(S v, S lo, S hi) {
+  return v < lo ? lo : (v > hi ? hi : v);
+}
+
+// acc[c] += sum_k Mt[k*nout + o] * vin[k], o = lane + c*T (o < nout).
+template <typename S, int T>
+__device__ __forceinline__ void mv_acc(S (&acc)[(kMaxDim + T - 1) / T], const S* __restrict__ Mt,
+                                       int nin, int nout, const S* vin, int lane) {
+  constexpr int C = (kMaxDim + T - 1) / T;
+  int k = 0;
+  for (; k + 4 <= nin; k += 4) {
+    const S v0 = vin[k], v1 = vin[k + 1], v2 = vin[k + 2], v3 = vin[k + 3];
+    const S* r0 = Mt + (size_t)k * nout;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int o = lane + c * T;
+      if (o < nout) {
+        const S m0 = r0[o], m1 = r0[nout + o], m2 = r0[2 * nout + o], m3 = r0[3 * nout + o];
+        acc[c] += m0 * v0 + m1 * v1 + m2 * v2 + m3 * v3;
+      }
+    }
+  }
+  for (; k < nin; ++k) {
+    const S vk = vin[k];
+    const S* r0 = Mt + (size_t)k * nout;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int o = lane + c * T;
+      if (o < nout) acc[c] += r0[o] * vk;
+    }
+  }
+}
+
+// Offsets in the canonical layout (closed forms of the breadth-first sizes).
+template <typename S>
+struct Off {
+  const DevProb<S>& P;
+  __device__ Off(const DevProb<S>& p) : P(p) {}
+  __device__ long long x(int i) const { return 1 + (long long)i * P.nx; }
+  __device__ long long u(int i) const { return P.zU + (long long)i * P.nu; }
+  // z2 block of nonleaf i: y (2n+1), tau (n), s (n)
+  __device__ long long z2(int i) const { return P.zZ2 + 4LL * (P.fc[i] - 1) + i; }
+  // slot of s^c in its ancestor's block (s^0 at 0)
+  __device__ long long s(int c) const {
+    if (c == 0) return 0;
+    const int a = P.anc[c];
+    const int n = P.nch[a];
+    return z2(a) + 3LL * n + 1 + (c - P.fc[a]);
+  }
+  __device__ long long tau(int c) const {
+    const int a = P.anc[c];
+    const int n = P.nch[a];
+    return z2(a) + 2LL * n + 1 + (c - P.fc[a]);
+  }
+  // eta group 1 of nonleaf i: y (2n+1), s-row, x (nx), u (nu)
+  __device__ long long e1(int i) const {
+    return 2LL * (P.fc[i] - 1) + (long long)i * (2 + P.nx + P.nu);
+  }
+  __device__ long long e1s(int i) const { return e1(i) + 2LL * P.nch[i] + 1; }
+  __device__ long long e1x(int i) const { return e1s(i) + 1; }
+  __device__ long long e1u(int i) const { return e1x(i) + P.nx; }
+  // eta group 2 of non-root c: x (nx), u (nu), a, b
+  __device__ long long e2(int c) const { return P.eE2 + (long long)(c - 1) * (P.nx + P.nu + 2); }
+  // eta group 3 of leaf j: x (nx), Q_N^{1/2} x (nx), a, b
+  __device__ long long e3(int j) const { return P.eE3 + (long long)(j - P.nl) * (2 * P.nx + 2); }
+};
+
+// Running residual statistics of one lane (FP64).
+struct StatAcc {
+  double rz2 = 0, re2 = 0, cross = 0, xip = 0, xid = 0;
+  __device__ void col(double rz, double Ltre, double ia) {
+    rz2 += rz * rz;
+    xip = fmax(xip, fabs(rz * ia - Ltre));
+  }
+  __device__ void row(double re, double Lrz, double ia) {
+    re2 += re * re;
+    cross += re * Lrz;
+    xid = fmax(xid, fabs(re * ia - Lrz));
+  }
+};
+
+// prox of g* on a translated SOC block (eq. S3-def, shift (0,..,0,1/2,-1/2)):
+// out = w - alpha (shift + proj_SOC(w/alpha - shift)). The vector part is
+// distributed over the team (wv[c] for components o = lane + c*T < len);
+// the two trailing scalars (wa, wb) are held by every lane.
+template <typename S, int T>
+__device__ __forceinline__ void soc_prox(const S* wv, S* outv, int len, S wa, S wb, S& outa,
+                                         S& outb, S al, int lane) {
+  constexpr int C = (kMaxDim * 2 + T - 1) / T;
+  const S ia = S(1) / al;
+  double part = 0;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int o = lane + c * T;
+    if (o < len) {
+      const double t = (double)(wv[c] * ia);
+      part += t * t;
+    }
+  }
+  const S va = wa * ia - S(0.5);
+  const S t = wb * ia + S(0.5);
+  const double n2 = team_sum<T>(part) + (double)va * (double)va;
+  const S nrm = (S)sqrt(n2);
+  S scale, pt;
+  if (nrm <= t) {
+    scale = S(1);
+    pt = t;
+  } else if (nrm <= -t) {
+    scale = S(0);
+    pt = S(0);
+  } else {
+    const S cc = S(0.5) * (nrm + t);
+    scale = cc / nrm;
+    pt = cc;
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int o = lane + c * T;
+    if (o < len) outv[c] = wv[c] - al * (scale * (wv[c] * ia));
+  }
+  outa = wa - al * (S(0.5) + scale * va);
+  outb = wb - al * (S(-0.5) + pt);
+}
+
+// ---------------------------------------------------------------- backward
+template <typename S, int T>
+__global__ void __launch_bounds__(256) k_bwd(DevProb<S> P, const S* __restrict__ z,
+                                             const S* __restrict__ eta, S* __restrict__ zout,
+                                             S* __restrict__ qbuf, S* __restrict__ dbuf,
+                                             int first, int count, int VM) {
+  constexpr int C = (kMaxDim + T - 1) / T;
+  extern __shared__ unsigned char smem_raw[];
+  S* smem = reinterpret_cast<S*>(smem_raw);
+  const int lane = threadIdx.x % T;
+  const int team = threadIdx.x / T;
+  const int f = blockIdx.x * (blockDim.x / T) + team;
+  if (f >= count) return;  // whole teams only; no block barrier below
+  const int i = first + f;
+  S* vq = smem + (size_t)team * 3 * VM;
+  S* vg = vq + VM;
+  S* vd = vg + VM;
+  const Off<S> O(P);
+  const int nx = P.nx, nu = P.nu;
+  const S al = P.alpha;
+  const int fc = P.fc[i], n = P.nch[i];
+
+  // xbar, ubar of node i: (x, u) - alpha (L* eta) on columns x^i, u^i
+  S xb[C], ub[C], sA[C], h[C];
+  const long long e1x = O.e1x(i), e1u = O.e1u(i);
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int o = lane + c * T;
+    sA[c] = 0;
+    h[c] = 0;
+    xb[c] = 0;
+    ub[c] = 0;
+    if (o < nx) {
+      S acc = eta[e1x + o];
+      for (int k = 0; k < n; ++k) acc += P.sq[(size_t)(fc + k) * nx + o] * eta[O.e2(fc + k) + o];
+      xb[c] = z[O.x(i) + o] - al * acc;
+    }
+    if (o < nu) {
+      S acc = eta[e1u + o];
+      for (int k = 0; k < n; ++k) acc += P.sr[(size_t)(fc + k) * nu + o] * eta[O.e2(fc + k) + nx + o];
+      ub[c] = z[O.u(i) + o] - al * acc;
+    }
+  }
+  // children: h = sum B' q, sA = sum Abar' q
+  for (int k = 0; k < n; ++k) {
+    const int ch = fc + k;
+    const bool leaf = ch >= P.nl;
+    const long long e3 = leaf ? O.e3(ch) : 0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int o = lane + c * T;
+      if (o < nx) {
+        S qv;
+        if (leaf) {
+          const S xbl = z[O.x(ch) + o] - al * (eta[e3 + o] + P.sqN[(size_t)ch * nx + o] * eta[e3 + nx + o]);
+          qv = -xbl;
+        } else {
+          qv = qbuf[(size_t)ch * nx + o];
+        }
+        vq[o] = qv;
+      }
+    }
+    wave_lds_sync();
+    mv_acc<S, T>(h, P.BR + (size_t)ch * nx * nu, nx, nu, vq, lane);
+    mv_acc<S, T>(sA, P.AbR + (size_t)ch * nx * nx, nx, nx, vq, lane);
+    wave_lds_sync();
+  }
+  // d = R~^{-1}(ubar - h)
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int o = lane + c * T;
+    if (o < nu) vg[o] = ub[c] - h[c];
+  }
+  wave_lds_sync();
+  S dv[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) dv[c] = 0;
+  mv_acc<S, T>(dv, P.Rinv + (size_t)i * nu * nu, nu, nu, vg, lane);
+  wave_lds_sync();
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int o = lane + c * T;
+    if (o < nu) {
+      vg[o] = dv[c] - ub[c];
+      vd[o] = dv[c];
+      dbuf[(size_t)i * nu + o] = dv[c];
+    }
+  }
+  wave_lds_sync();
+  // q = K'(d - ubar) + W d - xbar + sum Abar' q
+  S qi[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) qi[c] = sA[c] - xb[c];
+  mv_acc<S, T>(qi, P.KR + (size_t)i * nu * nx, nu, nx, vg, lane);
+  mv_acc<S, T>(qi, P.WC + (size_t)i * nu * nx, nu, nx, vd, lane);
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int o = lane + c * T;
+    if (o < nx) qbuf[(size_t)i * nx + o] = qi[c];
+  }
+
+  // S2 projection of the z2 block of i (closed form of the kernel projection:
+  // G = [aI, -I, 1, -I, -I], (G G')^{-1} = (I - 11'/(c+n))/c, c = a^2 + 3)
+  const long long zb = O.z2(i);
+  const long long e1 = O.e1(i);
+  const S es = eta[O.e1s(i)];
+  const S a = P.a[i];
+  const S y3h = z[zb + 2 * n] - al * (eta[e1 + 2 * n] - es);
+  double gsum = 0;
+  for (int k = lane; k < n; k += T) {
+    const int ch = fc + k;
+    const S y1h = z[zb + k] - al * (eta[e1 + k] - P.p[ch] * es);
+    const S y2h = z[zb + n + k] - al * eta[e1 + n + k];
+    const long long e2c = O.e2(ch) + nx + nu;
+    const S th = z[zb + 2 * n + 1 + k] - al * S(0.5) * (eta[e2c] + eta[e2c + 1]);
+    S Lts;
+    if (ch < P.nl) {
+      Lts = eta[O.e1s(ch)];
+    } else {
+      const long long e3c = O.e3(ch) + 2 * nx;
+      Lts = S(0.5) * (eta[e3c] + eta[e3c + 1]);
+    }
+    const S sh = z[zb + 3 * n + 1 + k] - al * Lts;
+    gsum += (double)(a * y1h - y2h + y3h - th - sh);
+  }
+  const S cc = a * a + S(3);
+  const S Gs = (S)team_sum<T>(gsum);
+  double wsum = 0;
+  for (int k = lane; k < n; k += T) {
+    const int ch = fc + k;
+    const S y1h = z[zb + k] - al * (eta[e1 + k] - P.p[ch] * es);
+    const S y2h = z[zb + n + k] - al * eta[e1 + n + k];
+    const long long e2c = O.e2(ch) + nx + nu;
+    const S th = z[zb + 2 * n + 1 + k] - al * S(0.5) * (eta[e2c] + eta[e2c + 1]);
+    S Lts;
+    if (ch < P.nl) {
+      Lts = eta[O.e1s(ch)];
+    } else {
+      const long long e3c = O.e3(ch) + 2 * nx;
+      Lts = S(0.5) * (eta[e3c] + eta[e3c + 1]);
+    }
+    const S sh = z[zb + 3 * n + 1 + k] - al * Lts;
+    const S g = a * y1h - y2h + y3h - th - sh;
+    const S w = (g - Gs / (cc + S(n))) / cc;
+    wsum += (double)w;
+    zout[zb + k] = y1h - a * w;
+    zout[zb + n + k] = y2h + w;
+    zout[zb + 2 * n + 1 + k] = th + w;
+    zout[zb + 3 * n + 1 + k] = sh + w;
+  }
+  const S Ws = (S)team_sum<T>(wsum);
+  if (lane == 0) {
+    zout[zb + 2 * n] = y3h - Ws;
+    if (i == 0) zout[0] = z[0] - al * es - al;
+  }
+}
+
+// ---------------------------------------------------------------- forward
+// LDS per team: vx (VM) x^i, vd (VM) d^i, vu (VM) u+^i, vr (2 VM) group-2 r_eta.
+template <typename S, int T, bool DUAL>
+__global__ void __launch_bounds__(256) k_fwd(DevProb<S> P, const S* __restrict__ z,
+                                             const S* __restrict__ eta, S* __restrict__ zout,
+                                             S* __restrict__ eout, const S* __restrict__ dbuf,
+                                             const double* __restrict__ x0, int first, int count,
+                                             int VM, double* __restrict__ partials) {
+  constexpr int C = (kMaxDim + T - 1) / T;
+  constexpr int C2 = (2 * kMaxDim + T - 1) / T;
+  extern __shared__ unsigned char smem_raw[];
+  S* smem = reinterpret_cast<S*>(smem_raw);
+  const int lane = threadIdx.x % T;
+  const int team = threadIdx.x / T;
+  const int f = blockIdx.x * (blockDim.x / T) + team;
+  StatAcc st;
+  if (f < count) {
+    const int i = first + f;
+    S* vx = smem + (size_t)team * 5 * VM;
+    S* vd = vx + VM;
+    S* vu = vd + VM;
+    S* vr = vu + VM;
+    const Off<S> O(P);
+    const int nx = P.nx, nu = P.nu;
+    const S al = P.alpha;
+    const S ia = S(1) / al;
+    const int fc = P.fc[i], n = P.nch[i];
+    const long long ui = O.u(i);
+
+    S xp[C], xo[C], up[C], uo[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int o = lane + c * T;
+      xp[c] = xo[c] = up[c] = uo[c] = 0;
+      if (o < nx) {
+        S xv;
+        if (i == 0) {
+          xv = (S)x0[o];
+          zout[1 + o] = xv;
+        } else {
+          xv = zout[O.x(i) + o];
+        }
+        vx[o] = xv;
+        xp[c] = xv;
+        xo[c] = z[O.x(i) + o];
+      }
+      if (o < nu) {
+        const S dd = dbuf[(size_t)i * nu + o];
+        vd[o] = dd;
+        up[c] = dd;
+        uo[c] = z[ui + o];
+      }
+    }
+    wave_lds_sync();
+    mv_acc<S, T>(up, P.KC + (size_t)i * nx * nu, nx, nu, vx, lane);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int o = lane + c * T;
+      if (o < nu) {
+        zout[ui + o] = up[c];
+        vu[o] = up[c];
+      }
+    }
+    wave_lds_sync();
+    S gx[C], gu[C];  // sum over children of Q^{1/2} r_eta(x part), R^{1/2} r_eta(u part)
+#pragma unroll
+    for (int c = 0; c < C; ++c) gx[c] = gu[c] = 0;
+
+    for (int k = 0; k < n; ++k) {
+      const int ch = fc + k;
+      S xc[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) xc[c] = 0;
+      mv_acc<S, T>(xc, P.AbC + (size_t)ch * nx * nx, nx, nx, vx, lane);
+      mv_acc<S, T>(xc, P.BC + (size_t)ch * nu * nx, nu, nx, vd, lane);
+      const bool leaf = ch >= P.nl;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const int o = lane + c * T;
+        if (o < nx) zout[O.x(ch) + o] = xc[c];
+      }
+      if (!DUAL) continue;
+      // ---- group 2 of child ch: (Q^{1/2} x^i, R^{1/2} u^i, tau/2, tau/2) in SOC + shift
+      const long long e2 = O.e2(ch);
+      const long long tpos = O.tau(ch);
+      const S tau = z[tpos], taup = zout[tpos];
+      S wv[C2], ov[C2], lz[C2];
+#pragma unroll
+      for (int c = 0; c < C2; ++c) {
+        const int o = lane + c * T;
+        wv[c] = 0;
+        ov[c] = 0;
+        lz[c] = 0;
+        if (o < nx) {
+          // component o of x is this lane's chunk c (o = lane + c*T, c < C)
+          const S xpo = xp[c < C ? c : C - 1], xoo = xo[c < C ? c : C - 1];
+          const S sqv = P.sq[(size_t)ch * nx + o];
+          wv[c] = eta[e2 + o] + al * sqv * (S(2) * xpo - xoo);
+          lz[c] = sqv * (xoo - xpo);
+        } else if (o < nx + nu) {
+          const int ou = o - nx;
+          const S upo = vu[ou], uoo = z[ui + ou];
+          const S srv = P.sr[(size_t)ch * nu + ou];
+          wv[c] = eta[e2 + o] + al * srv * (S(2) * upo - uoo);
+          lz[c] = srv * (uoo - upo);
+        }
+      }
+      const S wa = eta[e2 + nx + nu] + al * S(0.5) * (S(2) * taup - tau);
+      const S wb = eta[e2 + nx + nu + 1] + al * S(0.5) * (S(2) * taup - tau);
+      S oa, ob;
+      soc_prox<S, T>(wv, ov, nx + nu, wa, wb, oa, ob, al, lane);
+      const S rtau = tau - taup;
+#pragma unroll
+      for (int c = 0; c < C2; ++c) {
+        const int o = lane + c * T;
+        if (o < nx + nu) {
+          eout[e2 + o] = ov[c];
+          const S re = eta[e2 + o] - ov[c];
+          vr[o] = re;
+          st.row((double)re, (double)lz[c], (double)ia);
+        }
+      }
+      wave_lds_sync();
+      // L* of columns x^i, u^i: group-2 contributions (lane-owned components)
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const int o = lane + c * T;
+        if (o < nx) gx[c] += P.sq[(size_t)ch * nx + o] * vr[o];
+        if (o < nu) gu[c] += P.sr[(size_t)ch * nu + o] * vr[nx + o];
+      }
+      wave_lds_sync();
+      if (lane == 0) {
+        const S rea = eta[e2 + nx + nu] - oa, reb = eta[e2 + nx + nu + 1] - ob;
+        eout[e2 + nx + nu] = oa;
+        eout[e2 + nx + nu + 1] = ob;
+        st.row((double)rea, 0.5 * (double)rtau, (double)ia);
+        st.row((double)reb, 0.5 * (double)rtau, (double)ia);
+        st.col((double)rtau, 0.5 * ((double)rea + (double)reb), (double)ia);
+      }
+      if (!leaf) continue;
+      // ---- group 3 of leaf ch: box on x, (Q_N^{1/2} x, s/2, s/2) in SOC + shift
+      const long long e3 = O.e3(ch);
+      const long long spos = O.s(ch);
+      const S sv = z[spos], svp = zout[spos];
+      S wq[C2], oq[C2];
+      S rex[C], xin[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const int o = lane + c * T;
+        rex[c] = 0;
+        xin[c] = 0;
+        if (o < nx) {
+          const S xcin = z[O.x(ch) + o];
+          xin[c] = xcin;
+          const S wbx = eta[e3 + o] + al * (S(2) * xc[c] - xcin);
+          const S pb = wbx - al * clampv(wbx * ia, P.xlo[(size_t)ch * nx + o], P.xhi[(size_t)ch * nx + o]);
+          eout[e3 + o] = pb;
+          rex[c] = eta[e3 + o] - pb;
+          st.row((double)rex[c], (double)(xcin - xc[c]), (double)ia);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < C2; ++c) {
+        const int o = lane + c * T;
+        wq[c] = 0;
+        oq[c] = 0;
+        if (c < C && o < nx) {
+          const int cc = c < C ? c : C - 1;
+          wq[c] = eta[e3 + nx + o] + al * P.sqN[(size_t)ch * nx + o] * (S(2) * xc[cc] - xin[cc]);
+        }
+      }
+      const S wsa = eta[e3 + 2 * nx] + al * S(0.5) * (S(2) * svp - sv);
+      const S wsb = eta[e3 + 2 * nx + 1] + al * S(0.5) * (S(2) * svp - sv);
+      S osa, osb;
+      soc_prox<S, T>(wq, oq, nx, wsa, wsb, osa, osb, al, lane);
+      const S rs = sv - svp;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const int o = lane + c * T;
+        if (o < nx) {
+          eout[e3 + nx + o] = oq[c];
+          const S reqv = eta[e3 + nx + o] - oq[c];
+          const S sqn = P.sqN[(size_t)ch * nx + o];
+          st.row((double)reqv, (double)(sqn * (xin[c] - xc[c])), (double)ia);
+          // column x^ch of a leaf: L* r_eta = r_eta(box) + Q_N^{1/2} r_eta(q)
+          st.col((double)(xin[c] - xc[c]), (double)(rex[c] + sqn * reqv), (double)ia);
+        }
+      }
+      if (lane == 0) {
+        eout[e3 + 2 * nx] = osa;
+        eout[e3 + 2 * nx + 1] = osb;
+        const S rea3 = eta[e3 + 2 * nx] - osa, reb3 = eta[e3 + 2 * nx + 1] - osb;
+        st.row((double)rea3, 0.5 * (double)rs, (double)ia);
+        st.row((double)reb3, 0.5 * (double)rs, (double)ia);
+        st.col((double)rs, 0.5 * ((double)rea3 + (double)reb3), (double)ia);
+      }
+    }
+    if (DUAL) {
+      // ---- group 1 of i: y in K* = R^{2n}_+ x R, s - b'y in R_+, (x, u) in the box
+      const long long zb = O.z2(i);
+      const long long e1 = O.e1(i);
+      const long long spos = O.s(i);
+      const S si = z[spos], sip = zout[spos];
+      // b'(2y+ - y) and b' r_y (team sums), b = (p^{ch}, 0, 1)
+      double bw = 0, bry = 0;
+      for (int k = lane; k < n; k += T) {
+        const S pk = P.p[fc + k];
+        const S y1 = z[zb + k], y1p = zout[zb + k];
+        bw += (double)(pk * (S(2) * y1p - y1));
+        bry += (double)(pk * (y1 - y1p));
+      }
+      const S y3 = z[zb + 2 * n], y3p = zout[zb + 2 * n];
+      const S bW = (S)team_sum<T>(bw) + (S(2) * y3p - y3);
+      const S bR = (S)team_sum<T>(bry) + (y3 - y3p);
+      const S ws = eta[e1 + 2 * n + 1] + al * ((S(2) * sip - si) - bW);
+      const S es_new = ws < S(0) ? ws : S(0);
+      const S res_ = eta[e1 + 2 * n + 1] - es_new;
+      for (int k = lane; k < 2 * n + 1; k += T) {
+        const S y = z[zb + k], yp = zout[zb + k];
+        const S w = eta[e1 + k] + al * (S(2) * yp - y);
+        const S ep = (k < 2 * n) ? (w < S(0) ? w : S(0)) : S(0);
+        eout[e1 + k] = ep;
+        const S re = eta[e1 + k] - ep;
+        const S ry = y - yp;
+        st.row((double)re, (double)ry, (double)ia);
+        const S bk = (k < n) ? P.p[fc + k] : ((k == 2 * n) ? S(1) : S(0));
+        st.col((double)ry, (double)(re - bk * res_), (double)ia);
+      }
+      if (lane == 0) {
+        eout[e1 + 2 * n + 1] = es_new;
+        const S rsi = si - sip;
+        st.row((double)res_, (double)(rsi - bR), (double)ia);
+        st.col((double)rsi, (double)res_, (double)ia);
+      }
+      const long long e1x = O.e1x(i), e1u = O.e1u(i);
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const int o = lane + c * T;
+        if (o < nx) {
+          const S w = eta[e1x + o] + al * (S(2) * xp[c] - xo[c]);
+          const S ep = w - al * clampv(w * ia, P.xlo[(size_t)i * nx + o], P.xhi[(size_t)i * nx + o]);
+          eout[e1x + o] = ep;
+          const S re = eta[e1x + o] - ep;
+          const S rz = xo[c] - xp[c];
+          st.row((double)re, (double)rz, (double)ia);
+          st.col((double)rz, (double)(re + gx[c]), (double)ia);
+        }
+        if (o < nu) {
+          const S w = eta[e1u + o] + al * (S(2) * up[c] - uo[c]);
+          const S ep = w - al * clampv(w * ia, P.ulo[(size_t)i * nu + o], P.uhi[(size_t)i * nu + o]);
+          eout[e1u + o] = ep;
+          const S re = eta[e1u + o] - ep;
+          const S rz = uo[c] - up[c];
+          st.row((double)re, (double)rz, (double)ia);
+          st.col((double)rz, (double)(re + gu[c]), (double)ia);
+        }
+      }
+    }
+  }
+  if (!DUAL) return;
+  // block reduction of the statistics (fixed order: deterministic)
+  __shared__ double red[kStats][256];
+  red[0][threadIdx.x] = st.rz2;
+  red[1][threadIdx.x] = st.re2;
+  red[2][threadIdx.x] = st.cross;
+  red[3][threadIdx.x] = st.xip;
+  red[4][threadIdx.x] = st.xid;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s >= 1; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + s];
+      red[1][threadIdx.x] += red[1][threadIdx.x + s];
+      red[2][threadIdx.x] += red[2][threadIdx.x + s];
+      red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + s]);
+      red[4][threadIdx.x] = fmax(red[4][threadIdx.x], red[4][threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < kStats) partials[(size_t)blockIdx.x * kStats + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Sums the per-block statistics into {xi_p, xi_d, omega^2, rz2, re2, cross}.
+__global__ void k_reduce_stats(const double* __restrict__ partials, int nblk, double alpha,
+                               double* __restrict__ out) {
+  __shared__ double red[kStats][256];
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+    const double* p = partials + (size_t)b * kStats;
+    a0 += p[0];
+    a1 += p[1];
+    a2 += p[2];
+    a3 = fmax(a3, p[3]);
+    a4 = fmax(a4, p[4]);
+  }
+  red[0][threadIdx.x] = a0;
+  red[1][threadIdx.x] = a1;
+  red[2][threadIdx.x] = a2;
+  red[3][threadIdx.x] = a3;
+  red[4][threadIdx.x] = a4;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s >= 1; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + s];
+      red[1][threadIdx.x] += red[1][threadIdx.x + s];
+      red[2][threadIdx.x] += red[2][threadIdx.x + s];
+      red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + s]);
+      red[4][threadIdx.x] = fmax(red[4][threadIdx.x], red[4][threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = red[3][0];
+    out[1] = red[4][0];
+    out[2] = red[0][0] + red[1][0] - 2.0 * alpha * red[2][0];
+    out[3] = red[0][0];
+    out[4] = red[1][0];
+    out[5] = red[2][0];
+  }
+}
+
+// ---------------------------------------------------------------- launch T
+template <typename S, int T>
+static hipError_t launch_T_team(const Problem& P, const DevProb<S>& D, const S* v, S* Tv,
+                                const double* x0, S* q, S* d, double* partials, double* stats,
+                                hipStream_t st, const S* eta_zero, bool dual) {
+  const Tree& tr = *P.tree;
+  const int tpb = 256 / T;
+  const int VM = (std::max(P.nx, P.nu) + 3) & ~3;
+  const S* z = v;
+  const S* eta = dual ? v + P.nz : eta_zero;
+  S* zout = Tv;
+  S* eout = dual ? Tv + P.nz : nullptr;
+  for (int t = tr.N - 1; t >= 0; --t) {
+    const int first = tr.stage_off[t];
+    const int count = tr.stage_off[t + 1] - first;
+    const int blocks = (count + tpb - 1) / tpb;
+    hipLaunchKernelGGL((k_bwd<S, T>), dim3(blocks), dim3(256), (size_t)tpb * 3 * VM * sizeof(S), st,
+                       D, z, eta, zout, q, d, first, count, VM);
+  }
+  for (int t = 0; t < tr.N; ++t) {
+    const int first = tr.stage_off[t];
+    const int count = tr.stage_off[t + 1] - first;
+    const int blocks = (count + tpb - 1) / tpb;
+    double* pp = partials + (size_t)P.fwd_blk_off[t] * kStats;
+    if (dual)
+      hipLaunchKernelGGL((k_fwd<S, T, true>), dim3(blocks), dim3(256), (size_t)tpb * 5 * VM * sizeof(S),
+                         st, D, z, eta, zout, eout, d, x0, first, count, VM, pp);
+    else
+      hipLaunchKernelGGL((k_fwd<S, T, false>), dim3(blocks), dim3(256), (size_t)tpb * 5 * VM * sizeof(S),
+                         st, D, z, eta, zout, eout, d, x0, first, count, VM, pp);
+  }
+  if (dual)
+    hipLaunchKernelGGL(k_reduce_stats, dim3(1), dim3(256), 0, st, partials, P.fwd_blocks,
+                       (double)D.alpha, stats);
+  return hipGetLastError();
+}
+
+template <typename S>
+static const DevProb<S>& dev_of(const Problem& P);
+template <>
+const DevProb<double>& dev_of<double>(const Problem& P) { return P.dp64; }
+template <>
+const DevProb<float>& dev_of<float>(const Problem& P) { return P.dp32; }
+
+template <typename S>
+hipError_t launch_T(const Problem& P, const S* v, S* Tv, const double* x0, S* q, S* d,
+                    double* partials, double* stats_dev, hipStream_t st, const S* eta_zero,
+                    bool dual) {
+  const DevProb<S>& D = dev_of<S>(P);
+  switch (P.team) {
+    case 8: return launch_T_team<S, 8>(P, D, v, Tv, x0, q, d, partials, stats_dev, st, eta_zero, dual);
+    case 16: return launch_T_team<S, 16>(P, D, v, Tv, x0, q, d, partials, stats_dev, st, eta_zero, dual);
+    case 32: return launch_T_team<S, 32>(P, D, v, Tv, x0, q, d, partials, stats_dev, st, eta_zero, dual);
+    default: return launch_T_team<S, 64>(P, D, v, Tv, x0, q, d, partials, stats_dev, st, eta_zero, dual);
+  }
+}
+template hipError_t launch_T<double>(const Problem&, const double*, double*, const double*, double*,
+                                     double*, double*, double*, hipStream_t, const double*, bool);
+template hipError_t launch_T<float>(const Problem&, const float*, float*, const double*, float*,
+                                    float*, double*, double*, hipStream_t, const float*, bool);
+
+// ---------------------------------------------------------------- L and L*
+// One thread per family (test entry points; simple and exact).
+template <typename S>
+__global__ void k_apply_L(DevProb<S> P, const S* __restrict__ z, S* __restrict__ eta) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P.nl) return;
+  const Off<S> O(P);
+  const int nx = P.nx, nu = P.nu, fc = P.fc[i], n = P.nch[i];
+  const long long zb = O.z2(i), e1 = O.e1(i);
+  S by = z[zb + 2 * n];
+  for (int k = 0; k < 2 * n + 1; ++k) eta[e1 + k] = z[zb + k];
+  for (int k = 0; k < n; ++k) by += P.p[fc + k] * z[zb + k];
+  eta[e1 + 2 * n + 1] = z[O.s(i)] - by;
+  for (int o = 0; o < nx; ++o) eta[O.e1x(i) + o] = z[O.x(i) + o];
+  for (int o = 0; o < nu; ++o) eta[O.e1u(i) + o] = z[O.u(i) + o];
+  for (int k = 0; k < n; ++k) {
+    const int c = fc + k;
+    const long long e2 = O.e2(c);
+    for (int o = 0; o < nx; ++o) eta[e2 + o] = P.sq[(size_t)c * nx + o] * z[O.x(i) + o];
+    for (int o = 0; o < nu; ++o) eta[e2 + nx + o] = P.sr[(size_t)c * nu + o] * z[O.u(i) + o];
+    const S th = S(0.5) * z[O.tau(c)];
+    eta[e2 + nx + nu] = th;
+    eta[e2 + nx + nu + 1] = th;
+    if (c >= P.nl) {
+      const long long e3 = O.e3(c);
+      for (int o = 0; o < nx; ++o) {
+        eta[e3 + o] = z[O.x(c) + o];
+        eta[e3 + nx + o] = P.sqN[(size_t)c * nx + o] * z[O.x(c) + o];
+      }
+      const S sh = S(0.5) * z[O.s(c)];
+      eta[e3 + 2 * nx] = sh;
+      eta[e3 + 2 * nx + 1] = sh;
+    }
+  }
+}
+
+template <typename S>
+__global__ void k_apply_Lt(DevProb<S> P, const S* __restrict__ eta, S* __restrict__ z) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P.nl) return;
+  const Off<S> O(P);
+  const int nx = P.nx, nu = P.nu, fc = P.fc[i], n = P.nch[i];
+  const long long zb = O.z2(i), e1 = O.e1(i);
+  const S es = eta[O.e1s(i)];
+  for (int k = 0; k < 2 * n + 1; ++k) {
+    const S bk = (k < n) ? P.p[fc + k] : ((k == 2 * n) ? S(1) : S(0));
+    z[zb + k] = eta[e1 + k] - bk * es;
+  }
+  z[O.s(i)] = es;
+  for (int o = 0; o < nx; ++o) {
+    S acc = eta[O.e1x(i) + o];
+    for (int k = 0; k < n; ++k) acc += P.sq[(size_t)(fc + k) * nx + o] * eta[O.e2(fc + k) + o];
+    z[O.x(i) + o] = acc;
+  }
+  for (int o = 0; o < nu; ++o) {
+    S acc = eta[O.e1u(i) + o];
+    for (int k = 0; k < n; ++k) acc += P.sr[(size_t)(fc + k) * nu + o] * eta[O.e2(fc + k) + nx + o];
+    z[O.u(i) + o] = acc;
+  }
+  for (int k = 0; k < n; ++k) {
+    const int c = fc + k;
+    const long long e2 = O.e2(c);
+    z[O.tau(c)] = S(0.5) * (eta[e2 + nx + nu] + eta[e2 + nx + nu + 1]);
+    if (c >= P.nl) {
+      const long long e3 = O.e3(c);
+      for (int o = 0; o < nx; ++o)
+        z[O.x(c) + o] = eta[e3 + o] + P.sqN[(size_t)c * nx + o] * eta[e3 + nx + o];
+      z[O.s(c)] = S(0.5) * (eta[e3 + 2 * nx] + eta[e3 + 2 * nx + 1]);
+    }
+  }
+}
+
+// prox of g* (test entry point): one thread per family, serial SOC norms.
+template <typename S>
+__device__ void soc_prox_serial(const S* w, S* out, int len, S al) {
+  // len counts the vector part; w[len], w[len+1] are the two scalars
+  const S ia = S(1) / al;
+  double n2 = 0;
+  for (int o = 0; o < len; ++o) n2 += (double)(w[o] * ia) * (double)(w[o] * ia);
+  const S va = w[len] * ia - S(0.5);
+  const S t = w[len + 1] * ia + S(0.5);
+  n2 += (double)va * (double)va;
+  const S nrm = (S)sqrt(n2);
+  S scale, pt;
+  if (nrm <= t) { scale = 1; pt = t; }
+  else if (nrm <= -t) { scale = 0; pt = 0; }
+  else { const S cc = S(0.5) * (nrm + t); scale = cc / nrm; pt = cc; }
+  for (int o = 0; o < len; ++o) out[o] = w[o] - al * scale * (w[o] * ia);
+  out[len] = w[len] - al * (S(0.5) + scale * va);
+  out[len + 1] = w[len + 1] - al * (S(-0.5) + pt);
+}
+
+template <typename S>
+__global__ void k_prox_gstar(DevProb<S> P, const S* __restrict__ w, S* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P.nl) return;
+  const Off<S> O(P);
+  const int nx = P.nx, nu = P.nu, fc = P.fc[i], n = P.nch[i];
+  const S al = P.alpha, ia = S(1) / al;
+  const long long e1 = O.e1(i);
+  for (int k = 0; k < 2 * n; ++k) out[e1 + k] = w[e1 + k] < S(0) ? w[e1 + k] : S(0);
+  out[e1 + 2 * n] = S(0);
+  out[e1 + 2 * n + 1] = w[e1 + 2 * n + 1] < S(0) ? w[e1 + 2 * n + 1] : S(0);
+  for (int o = 0; o < nx; ++o) {
+    const S v = w[O.e1x(i) + o];
+    out[O.e1x(i) + o] = v - al * clampv(v * ia, P.xlo[(size_t)i * nx + o], P.xhi[(size_t)i * nx + o]);
+  }
+  for (int o = 0; o < nu; ++o) {
+    const S v = w[O.e1u(i) + o];
+    out[O.e1u(i) + o] = v - al * clampv(v * ia, P.ulo[(size_t)i * nu + o], P.uhi[(size_t)i * nu + o]);
+  }
+  for (int k = 0; k < n; ++k) {
+    const int c = fc + k;
+    soc_prox_serial<S>(w + O.e2(c), out + O.e2(c), nx + nu, al);
+    if (c >= P.nl) {
+      const long long e3 = O.e3(c);
+      for (int o = 0; o < nx; ++o) {
+        const S v = w[e3 + o];
+        out[e3 + o] = v - al * clampv(v * ia, P.xlo[(size_t)c * nx + o], P.xhi[(size_t)c * nx + o]);
+      }
+      soc_prox_serial<S>(w + e3 + nx, out + e3 + nx, nx, al);
+    }
+  }
+}
+
+template <typename S>
+hipError_t launch_L(const Problem& P, const S* z, S* eta, hipStream_t st) {
+  const int nl = P.tree->nl;
+  hipLaunchKernelGGL(k_apply_L<S>, dim3((nl + 127) / 128), dim3(128), 0, st, dev_of<S>(P), z, eta);
+  return hipGetLastError();
+}
+template <typename S>
+hipError_t launch_Lt(const Problem& P, const S* eta, S* z, hipStream_t st) {
+  const int nl = P.tree->nl;
+  hipLaunchKernelGGL(k_apply_Lt<S>, dim3((nl + 127) / 128), dim3(128), 0, st, dev_of<S>(P), eta, z);
+  return hipGetLastError();
+}
+template <typename S>
+hipError_t launch_prox_gstar(const Problem& P, const S* w, S* out, hipStream_t st) {
+  const int nl = P.tree->nl;
+  hipLaunchKernelGGL(k_prox_gstar<S>, dim3((nl + 127) / 128), dim3(128), 0, st, dev_of<S>(P), w, out);
+  return hipGetLastError();
+}
+template hipError_t launch_L<double>(const Problem&, const double*, double*, hipStream_t);
+template hipError_t launch_L<float>(const Problem&, const float*, float*, hipStream_t);
+template hipError_t launch_Lt<double>(const Problem&, const double*, double*, hipStream_t);
+template hipError_t launch_Lt<float>(const Problem&, const float*, float*, hipStream_t);
+template hipError_t launch_prox_gstar<double>(const Problem&, const double*, double*, hipStream_t);
+template hipError_t launch_prox_gstar<float>(const Problem&, const float*, float*, hipStream_t);
+
+// ---------------------------------------------------------------- vector kernels
+constexpr int kVecBlocks = 1024;
+int dots_blocks(long long n) {
+  long long b = (n + 255) / 256;
+  return (int)(b < kVecBlocks ? (b < 1 ? 1 : b) : kVecBlocks);
+}
+
+template <typename S>
+__global__ void k_lincomb(long long n, S* __restrict__ out, double a, const S* __restrict__ x,
+                          double b, const S* __restrict__ y) {
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+       k += (long long)gridDim.x * blockDim.x) {
+    double v = a * (double)x[k];
+    if (y) v += b * (double)y[k];
+    out[k] = (S)v;
+  }
+}
+template <typename S>
+hipError_t launch_lincomb(long long n, S* out, double a, const S* x, double b, const S* y,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_lincomb<S>, dim3(dots_blocks(n)), dim3(256), 0, st, n, out, a, x, b, y);
+  return hipGetLastError();
+}
+template <typename S>
+__global__ void k_lincomb3(long long n, S* __restrict__ out, double a, const S* __restrict__ x,
+                           double b, const S* __restrict__ y, double c, const S* __restrict__ w) {
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+       k += (long long)gridDim.x * blockDim.x)
+    out[k] = (S)(a * (double)x[k] + b * (double)y[k] + c * (double)w[k]);
+}
+template <typename S>
+hipError_t launch_lincomb3(long long n, S* out, double a, const S* x, double b, const S* y,
+                           double c, const S* w, hipStream_t st) {
+  hipLaunchKernelGGL(k_lincomb3<S>, dim3(dots_blocks(n)), dim3(256), 0, st, n, out, a, x, b, y, c, w);
+  return hipGetLastError();
+}
+template <typename S>
+__global__ void k_fill(long long n, S* __restrict__ out, double val) {
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+       k += (long long)gridDim.x * blockDim.x)
+    out[k] = (S)val;
+}
+template <typename S>
+hipError_t launch_fill(long long n, S* out, double val, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill<S>, dim3(dots_blocks(n)), dim3(256), 0, st, n, out, val);
+  return hipGetLastError();
+}
+
+// Block-deterministic reduction of up to 8 per-thread sums.
+template <int K>
+__device__ void block_sums(double (&acc)[K], double* partials) {
+  __shared__ double red[8][256];
+  for (int j = 0; j < K; ++j) red[j][threadIdx.x] = acc[j];
+  __syncthreads();
+  for (int s = blockDim.x / 2; s >= 1; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int j = 0; j < K; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + s];
+    __syncthreads();
+  }
+  if ((int)threadIdx.x < K) partials[(size_t)blockIdx.x * 8 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void k_final_sums(const double* __restrict__ partials, int nblk, int K,
+                             double* __restrict__ out) {
+  // one thread per output, fixed order
+  const int j = threadIdx.x;
+  if (j >= K) return;
+  double s = 0;
+  for (int b = 0; b < nblk; ++b) s += partials[(size_t)b * 8 + j];
+  out[j] = s;
+}
+
+// out[j] = <x_j, y_j>, j < k <= 8
+template <typename S>
+__global__ void k_dots(long long n, int k, VecPtrs<S> xs, VecPtrs<S> ys, double* __restrict__ partials) {
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x)
+    for (int j = 0; j < k; ++j) acc[j] += (double)xs.p[j][e] * (double)ys.p[j][e];
+  block_sums<8>(acc, partials);
+}
+template <typename S>
+hipError_t launch_dots(long long n, int k, VecPtrs<S> xs, VecPtrs<S> ys,
+                       double* partials, double* out_dev, hipStream_t st) {
+  const int nb = dots_blocks(n);
+  hipLaunchKernelGGL(k_dots<S>, dim3(nb), dim3(256), 0, st, n, k, xs, ys, partials);
+  hipLaunchKernelGGL(k_final_sums, dim3(1), dim3(64), 0, st, partials, nb, k, out_dev);
+  return hipGetLastError();
+}
+
+// <v - Tv, w>
+template <typename S>
+__global__ void k_rdot(long long n, const S* __restrict__ v, const S* __restrict__ Tv,
+                       const S* __restrict__ w, double* __restrict__ partials) {
+  double acc[1] = {0};
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x)
+    acc[0] += ((double)v[e] - (double)Tv[e]) * (double)w[e];
+  block_sums<1>(acc, partials);
+}
+template <typename S>
+hipError_t launch_rdot(long long n, const S* v, const S* Tv, const S* w, double* partials,
+                       double* out_dev, hipStream_t st) {
+  const int nb = dots_blocks(n);
+  hipLaunchKernelGGL(k_rdot<S>, dim3(nb), dim3(256), 0, st, n, v, Tv, w, partials);
+  hipLaunchKernelGGL(k_final_sums, dim3(1), dim3(64), 0, st, partials, nb, 1, out_dev);
+  return hipGetLastError();
+}
+
+// Anderson push: r = v - Tv, dV = v - vprev, dR = r - rprev; dots
+// out[j] = <dR_old_j, dR_new> (j < m_old), out[m_old] = <dR_new, dR_new>,
+// out[m_old+1+j] = <dR_old_j, r>, out[2 m_old + 1] = <dR_new, r>.
+template <typename S>
+__global__ void k_aa_push(long long n, const S* __restrict__ v, const S* __restrict__ vprev,
+                          const S* __restrict__ Tv, const S* __restrict__ rprev, S* __restrict__ r_out,
+                          S* __restrict__ dV_new, S* __restrict__ dR_new, int m_old,
+                          VecPtrs<S> dR_old, double* __restrict__ partials) {
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    const S vv = v[e];
+    const S r = vv - Tv[e];
+    r_out[e] = r;
+    const S dr = r - rprev[e];
+    dV_new[e] = vv - vprev[e];
+    dR_new[e] = dr;
+    for (int j = 0; j < m_old; ++j) {
+      const double o = (double)dR_old.p[j][e];
+      acc[j] += o * (double)dr;
+      acc[m_old + 1 + j] += o * (double)r;
+    }
+    acc[m_old] += (double)dr * (double)dr;
+    acc[2 * m_old + 1] += (double)dr * (double)r;
+  }
+  block_sums<8>(acc, partials);
+}
+template <typename S>
+hipError_t launch_aa_push(long long n, const S* v, const S* vprev, const S* Tv, const S* rprev,
+                          S* r_out, S* dV_new, S* dR_new, int m_old, VecPtrs<S> dR_old,
+                          double* partials, double* out_dev, hipStream_t st) {
+  const int nb = dots_blocks(n);
+  hipLaunchKernelGGL(k_aa_push<S>, dim3(nb), dim3(256), 0, st, n, v, vprev, Tv, rprev, r_out,
+                     dV_new, dR_new, m_old, dR_old, partials);
+  hipLaunchKernelGGL(k_final_sums, dim3(1), dim3(64), 0, st, partials, nb, 2 * m_old + 2, out_dev);
+  return hipGetLastError();
+}
+
+// d = -r - sum_j gamma_j (dV_j - dR_j)
+template <typename S>
+__global__ void k_aa_dir(long long n, const S* __restrict__ r, int m, VecPtrs<S> dV, VecPtrs<S> dR,
+                         const double* __restrict__ gamma, S* __restrict__ d) {
+  double g[8];
+  for (int j = 0; j < m; ++j) g[j] = gamma[j];
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    double acc = -(double)r[e];
+    for (int j = 0; j < m; ++j) acc -= g[j] * ((double)dV.p[j][e] - (double)dR.p[j][e]);
+    d[e] = (S)acc;
+  }
+}
+template <typename S>
+hipError_t launch_aa_dir(long long n, const S* r, int m, VecPtrs<S> dV, VecPtrs<S> dR,
+                         const double* gamma_dev, S* d, hipStream_t st) {
+  hipLaunchKernelGGL(k_aa_dir<S>, dim3(dots_blocks(n)), dim3(256), 0, st, n, r, m, dV, dR, gamma_dev, d);
+  return hipGetLastError();
+}
+
+#define SPK_INST(S)                                                                                \
+  template hipError_t launch_lincomb<S>(long long, S*, double, const S*, double, const S*,         \
+                                        hipStream_t);                                              \
+  template hipError_t launch_lincomb3<S>(long long, S*, double, const S*, double, const S*, double, \
+                                         const S*, hipStream_t);                                   \
+  template hipError_t launch_fill<S>(long long, S*, double, hipStream_t);                          \
+  template hipError_t launch_dots<S>(long long, int, VecPtrs<S>, VecPtrs<S>, double*, double*,     \
+                                     hipStream_t);                                                 \
+  template hipError_t launch_rdot<S>(long long, const S*, const S*, const S*, double*, double*,     \
+                                     hipStream_t);                                                 \
+  template hipError_t launch_aa_push<S>(long long, const S*, const S*, const S*, const S*, S*, S*, \
+                                        S*, int, VecPtrs<S>, double*, double*, hipStream_t);       \
+  template hipError_t launch_aa_dir<S>(long long, const S*, int, VecPtrs<S>, VecPtrs<S>,           \
+                                       const double*, S*, hipStream_t);
+SPK_INST(double)
+SPK_INST(float)
+
+}  // namespace spk

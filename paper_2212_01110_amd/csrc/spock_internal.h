@@ -1,0 +1,130 @@
+// Internal structures shared by the host library and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <vector>
+#include <string>
+
+#include "../../include/spock.h"
+
+namespace spk {
+
+// Maximum state/input dimension handled by the team kernels.
+constexpr int kMaxDim = 64;
+// Number of FP64 statistics produced per block of the forward sweep:
+// sum r_z^2, sum r_eta^2, sum r_eta.(L r_z), max |xi_p|, max |xi_d|.
+constexpr int kStats = 5;
+
+// Device view of one problem's iteration data in precision S. Node-indexed
+// arrays follow breadth-first order; matrices are stored as the transpose of
+// the operator they feed ("input-major"): element (out o, in k) at k*nout+o,
+// so a team of lanes, one lane per output, reads contiguous memory.
+template <typename S>
+struct DevProb {
+  int nn, nl, nx, nu, N;
+  long long nz, neta;
+  long long zU, zZ2;   // z offsets: first u, first z2 block
+  long long eE2, eE3;  // eta offsets: first group-2 block, first group-3 block
+  const int* fc;       // first child (nonleaf), -1 at leaves
+  const int* nch;      // number of children
+  const int* anc;
+  const S* p;          // conditional probability of the node given its ancestor
+  const S* a;          // AV@R a of nonleaf nodes
+  const S* sq;         // [nn][nx] sqrt(diag Q^c)
+  const S* sr;         // [nn][nu] sqrt(diag R^c)
+  const S* sqN;        // [nn][nx] sqrt(diag Q_N^j)
+  const S* xlo; const S* xhi;  // [nn][nx]
+  const S* ulo; const S* uhi;  // [nn][nu]
+  const S* AbR;  // [nn][nx][nx]  Abar^c row-major      (Abar' q, backward)
+  const S* AbC;  // [nn][nx][nx]  Abar^c column-major   (Abar x, forward)
+  const S* BR;   // [nn][nx][nu]  B^c row-major         (B' q, backward)
+  const S* BC;   // [nn][nu][nx]  B^c column-major      (B d, forward)
+  const S* KR;   // [nl][nu][nx]  K row-major           (K' e, backward)
+  const S* KC;   // [nl][nx][nu]  K column-major        (K x, forward)
+  const S* Rinv; // [nl][nu][nu]  inverse of R~ (symmetric)
+  const S* WC;   // [nl][nu][nx]  W = sum_c Abar'P B, column-major (W d, backward)
+  S alpha;
+};
+
+struct Tree {
+  int nn = 0, nl = 0, N = 0;
+  std::vector<int> anc, fc, nch, stage;
+  std::vector<int> stage_off;  // [N+2]: nodes of stage t are [stage_off[t], stage_off[t+1])
+  std::vector<double> prob, pcond;
+};
+
+// Device arrays of one precision.
+struct DevArrays {
+  void* base = nullptr;  // one allocation holding everything below
+  size_t bytes = 0;
+};
+
+struct Problem {
+  const Tree* tree = nullptr;
+  int precision = SPOCK_FP64;
+  int nx = 0, nu = 0;
+  long long nz = 0, neta = 0;
+  double alpha = 0, normL = 0;
+  // host copies needed by the solver (box of the root, nested cost)
+  std::vector<double> xlo0, xhi0;
+  std::vector<double> q, r, qN, a_risk;  // for the nested cost
+  // device
+  void* dmem = nullptr;
+  int* d_fc = nullptr; int* d_nch = nullptr; int* d_anc = nullptr;
+  DevProb<double> dp64{};
+  DevProb<float> dp32{};
+  // per-problem work buffers (allocated lazily, precision-sized)
+  void* work = nullptr;
+  size_t work_bytes = 0;
+  // stage block offsets of the forward sweep partial statistics
+  std::vector<int> fwd_blk_off;  // [N+1]
+  int fwd_blocks = 0;
+  int team = 64;                  // lanes per family
+  int teams_per_block = 4;
+};
+
+// ---------------------------------------------------------------- launchers
+// (kernels.hip) All return hipError_t of the last launch.
+template <typename S>
+hipError_t launch_T(const Problem& P, const S* v, S* Tv, const double* x0, S* q, S* d,
+                    double* partials, double* stats_dev, hipStream_t st, const S* eta_zero,
+                    bool dual);
+template <typename S>
+hipError_t launch_L(const Problem& P, const S* z, S* eta, hipStream_t st);
+template <typename S>
+hipError_t launch_Lt(const Problem& P, const S* eta, S* z, hipStream_t st);
+template <typename S>
+hipError_t launch_prox_gstar(const Problem& P, const S* w, S* out, hipStream_t st);
+
+// Up to 8 device vectors passed by value to a kernel.
+template <typename S>
+struct VecPtrs {
+  const S* p[8];
+};
+
+// Vector kernels for the SuperMann/Anderson layer (FP64 accumulation).
+template <typename S>
+hipError_t launch_lincomb(long long n, S* out, double a, const S* x, double b, const S* y,
+                          hipStream_t st);
+template <typename S>
+hipError_t launch_lincomb3(long long n, S* out, double a, const S* x, double b, const S* y,
+                           double c, const S* w, hipStream_t st);
+template <typename S>
+hipError_t launch_dots(long long n, int k, VecPtrs<S> xs, VecPtrs<S> ys, double* partials,
+                       double* out_dev, hipStream_t st);
+template <typename S>
+hipError_t launch_aa_push(long long n, const S* v, const S* vprev, const S* Tv, const S* rprev,
+                          S* r_out, S* dV_new, S* dR_new, int m_old, VecPtrs<S> dR_old,
+                          double* partials, double* out_dev, hipStream_t st);
+template <typename S>
+hipError_t launch_aa_dir(long long n, const S* r, int m, VecPtrs<S> dV, VecPtrs<S> dR,
+                         const double* gamma_dev, S* d, hipStream_t st);
+template <typename S>
+hipError_t launch_fill(long long n, S* out, double val, hipStream_t st);
+template <typename S>
+hipError_t launch_rdot(long long n, const S* v, const S* Tv, const S* w, double* partials,
+                       double* out_dev, hipStream_t st);
+
+int dots_blocks(long long n);
+
+}  // namespace spk
