@@ -109,7 +109,7 @@ int spock_problem_sizes(const spock_problem* prob, int64_t* n_z, int64_t* n_eta,
                         double* alpha, double* norm_L);
 
 /* Solver settings (section 3 termination; Alg. 3 parameters). method CP runs
- * v <- T(v); method SPOCK runs Alg. 3 with Anderson memory m (1..8).
+ * v <- T(v); method SPOCK runs Alg. 3 with Anderson memory m (1..4).
  * Parameters follow Alg. 3: c0, c1, c2 in [0,1), beta, sigma in (0,1),
  * lambda in (0,2); max_ls caps the backtracking (then a plain KM step is
  * taken). compute_nested != 0 also evaluates the exact nested AV@R cost of the
@@ -133,10 +133,14 @@ typedef struct {
   double V_s0;             /* s^0 of the returned point */
   double V_nested;         /* nested AV@R cost of its (x, u), if requested, else NaN */
   double seconds;          /* host wall time of the call */
+  int32_t mapping;         /* lanes per tree family used (8..64), or 256 for one workgroup per family */
 } spock_info;
 
 /* Solves one instance from x0_dev (FP64 [nx], device) and the warm start in
- * v_io_dev ([n_v] of the problem precision; zeros for a cold start). On
+ * v_io_dev. The first solve of a problem times the candidate family-to-lane
+ * mappings on its own workspace and keeps the fastest (set the environment
+ * variable SPOCK_TEAM to 8, 16, 32, 64 or 256 before factoring to fix it).
+ * v_io_dev is [n_v] of the problem precision (zeros for a cold start). On
  * return v_io_dev holds T(v^k) at the last iterate, for which the section-3
  * certificates hold. Synchronises the stream. Errors: SPOCK_EINVAL,
  * SPOCK_EBOX (x0 outside the root box), SPOCK_EHIP, SPOCK_ENOMEM. Not

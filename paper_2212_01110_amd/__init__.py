@@ -63,7 +63,8 @@ class Info(ctypes.Structure):
                 ("n_k2", ctypes.c_int32), ("n_km", ctypes.c_int32),
                 ("n_backtracks", ctypes.c_int32), ("xi0", ctypes.c_double),
                 ("xi", ctypes.c_double), ("V_s0", ctypes.c_double),
-                ("V_nested", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("V_nested", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("mapping", ctypes.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}

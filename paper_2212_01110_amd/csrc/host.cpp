@@ -328,6 +328,32 @@ int upload(Problem& P, const spock_problem_data& d, const std::vector<double>& A
   return SPOCK_OK;
 }
 
+// Family-to-lane mapping: team size (or kTeamWG), the first stage walked by
+// subtree-owning workgroups (kTeamWG only; N = none), and the offsets of the
+// forward-sweep statistic records of every launch.
+void set_mapping(Problem& P, int team, int cut) {
+  const Tree& T = *P.tree;
+  P.team = team;
+  P.teams_per_block = (team == kTeamWG) ? 1 : 256 / team;
+  P.cut = (team == kTeamWG) ? std::max(cut, std::max(0, T.N - 64)) : T.N;
+  if (P.cut > T.N) P.cut = T.N;
+}
+
+// Default cut: the first stage with at least 256 nodes (enough subtrees to
+// fill the device), or none.
+int default_cut(const Tree& T) {
+  for (int t = 0; t < T.N; ++t)
+    if (T.stage_off[t + 1] - T.stage_off[t] >= 256) return t;
+  return T.N;
+}
+
+// LDS bytes per block of a mapping (team kernels size their LDS at launch).
+size_t mapping_lds(const Problem& P, int team, size_t elem) {
+  if (team == kTeamWG) return 0;
+  const int VM = (std::max(P.nx, P.nu) + 3) & ~3;
+  return (size_t)(256 / team) * 5 * VM * elem + kStats * 256 * sizeof(double);
+}
+
 }  // namespace
 
 // ============================================================== tree
@@ -529,22 +555,20 @@ extern "C" int spock_problem_factor(const spock_tree* th, const spock_problem_da
   P.r.assign(d->r, d->r + (size_t)nn * nu);
   P.qN.assign(d->qN, d->qN + (size_t)nn * nx);
   P.a_risk.assign(d->a_risk, d->a_risk + nn);
-  int team = next_pow2_team(std::max(nx, nu));
+  int team = std::max(nx, nu) >= 24 ? kTeamWG : next_pow2_team(std::max(nx, nu));
+  const size_t elem = d->precision == SPOCK_FP64 ? 8 : 4;
+  if (mapping_lds(P, team, elem) > 64 * 1024) team = kTeamWG;
   if (const char* env = std::getenv("SPOCK_TEAM")) {
     const int v = std::atoi(env);
-    if (v == 8 || v == 16 || v == 32 || v == 64) team = v;
+    if (v == 8 || v == 16 || v == 32 || v == 64 || v == kTeamWG) {
+      team = mapping_lds(P, v, elem) > 64 * 1024 ? kTeamWG : v;
+      P.tuned = true;  // fixed by the caller's environment
+    }
   }
-  P.team = team;
-  P.teams_per_block = 256 / team;
-  P.fwd_blk_off.assign(T.N + 1, 0);
-  int acc = 0;
-  for (int t = 0; t < T.N; ++t) {
-    P.fwd_blk_off[t] = acc;
-    const int count = T.stage_off[t + 1] - T.stage_off[t];
-    acc += (count + P.teams_per_block - 1) / P.teams_per_block;
-  }
-  P.fwd_blk_off[T.N] = acc;
-  P.fwd_blocks = acc;
+  int cut = default_cut(T);
+  if (const char* env = std::getenv("SPOCK_CUT")) cut = std::atoi(env);
+  set_mapping(P, team, cut);
+  P.team_pp = next_pow2_team(std::max(nx, nu));
   const int rc = (d->precision == SPOCK_FP64) ? upload<double>(P, *d, Abar, K, Rinv, W)
                                               : upload<float>(P, *d, Abar, K, Rinv, W);
   if (rc != SPOCK_OK) {
@@ -601,12 +625,15 @@ template <typename S>
 struct Work {
   S* q = nullptr;
   S* d = nullptr;
+  S* xbar = nullptr;
+  S* ubar = nullptr;
   double* partials = nullptr;
   double* stats = nullptr;    // [8]
   double* dots = nullptr;     // [16]
   double* gamma = nullptr;    // [8]
   double* vpart = nullptr;    // vector-kernel partials [blocks][8]
   S* eta_zero = nullptr;      // n_eta zeros
+  double* x0_zero = nullptr;  // kMaxDim zeros (autotuning input)
   S* pool[10 + 2 * kMaxMem];  // n_v buffers
   double* host_stats = nullptr;
 };
@@ -620,12 +647,15 @@ int ensure_work(Problem& P, Work<S>& W) {
   auto add = [&](size_t b) { bytes += (b + 255) & ~size_t(255); };
   add(sizeof(S) * (size_t)T.nn * P.nx);
   add(sizeof(S) * (size_t)T.nn * P.nu);
-  add(sizeof(double) * (size_t)(P.fwd_blocks + 1) * kStats);
+  add(sizeof(S) * (size_t)T.nn * P.nx);
+  add(sizeof(S) * (size_t)T.nn * P.nu);
+  add(sizeof(double) * (size_t)(T.nl + 1) * kStats);  // enough for every mapping
   add(sizeof(double) * 8);
   add(sizeof(double) * 16);
   add(sizeof(double) * 8);
   add(sizeof(double) * (size_t)nblk * 8);
   add(sizeof(S) * (size_t)P.neta);
+  add(sizeof(double) * kMaxDim);
   for (int k = 0; k < 10 + 2 * kMaxMem; ++k) add(sizeof(S) * (size_t)nv);
   if (P.work_bytes < bytes) {
     if (P.work) (void)hipFree(P.work);
@@ -644,14 +674,66 @@ int ensure_work(Problem& P, Work<S>& W) {
   };
   W.q = reinterpret_cast<S*>(take(sizeof(S) * (size_t)T.nn * P.nx));
   W.d = reinterpret_cast<S*>(take(sizeof(S) * (size_t)T.nn * P.nu));
-  W.partials = reinterpret_cast<double*>(take(sizeof(double) * (size_t)(P.fwd_blocks + 1) * kStats));
+  W.xbar = reinterpret_cast<S*>(take(sizeof(S) * (size_t)T.nn * P.nx));
+  W.ubar = reinterpret_cast<S*>(take(sizeof(S) * (size_t)T.nn * P.nu));
+  W.partials = reinterpret_cast<double*>(take(sizeof(double) * (size_t)(T.nl + 1) * kStats));
   W.stats = reinterpret_cast<double*>(take(sizeof(double) * 8));
   W.dots = reinterpret_cast<double*>(take(sizeof(double) * 16));
   W.gamma = reinterpret_cast<double*>(take(sizeof(double) * 8));
   W.vpart = reinterpret_cast<double*>(take(sizeof(double) * (size_t)nblk * 8));
   W.eta_zero = reinterpret_cast<S*>(take(sizeof(S) * (size_t)P.neta));
+  W.x0_zero = reinterpret_cast<double*>(take(sizeof(double) * kMaxDim));
   for (int k = 0; k < 10 + 2 * kMaxMem; ++k) W.pool[k] = reinterpret_cast<S*>(take(sizeof(S) * (size_t)nv));
   if (off > P.work_bytes) return SPOCK_ENOMEM;
+  return SPOCK_OK;
+}
+
+// Picks the fastest family-to-lane mapping for this problem by timing T on
+// a zero iterate (a few repetitions per candidate).
+template <typename S>
+int autotune(Problem& P, hipStream_t st) {
+  if (P.tuned) return SPOCK_OK;
+  Work<S> W;
+  int rc = ensure_work<S>(P, W);
+  if (rc) return rc;
+  const long long nv = P.nz + P.neta;
+  HIP_TRY(launch_fill<S>(nv, W.pool[0], 0.0, st));
+  HIP_TRY(hipMemsetAsync(W.x0_zero, 0, sizeof(double) * kMaxDim, st));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const Tree& T = *P.tree;
+  std::vector<std::pair<int, int>> cands = {{8, T.N}, {16, T.N}, {32, T.N}, {64, T.N}, {kTeamWG, T.N}};
+  int ncut = 0;
+  for (int t = std::max(0, T.N - 64); t < T.N && ncut < 3; ++t)
+    if (T.stage_off[t + 1] - T.stage_off[t] >= 128) {
+      cands.push_back({kTeamWG, t});
+      ++ncut;
+    }
+  float best = 1e30f;
+  std::pair<int, int> best_map = {P.team, P.cut};
+  for (auto c : cands) {
+    if (mapping_lds(P, c.first, sizeof(S)) > 64 * 1024) continue;
+    set_mapping(P, c.first, c.second);
+    HIP_TRY(launch_T<S>(P, W.pool[0], W.pool[1], W.x0_zero, W.q, W.d, W.xbar, W.ubar, W.partials, W.stats, st,
+                        W.eta_zero, true));
+    HIP_TRY(hipEventRecord(e0, st));
+    for (int r = 0; r < 3; ++r)
+      HIP_TRY(launch_T<S>(P, W.pool[0], W.pool[1], W.x0_zero, W.q, W.d, W.xbar, W.ubar, W.partials, W.stats, st,
+                          W.eta_zero, true));
+    HIP_TRY(hipEventRecord(e1, st));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      best_map = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  set_mapping(P, best_map.first, best_map.second);
+  P.tuned = true;
   return SPOCK_OK;
 }
 
@@ -675,7 +757,7 @@ struct Solver {
   Solver(Problem& p, hipStream_t s, const double* x) : P(p), st(s), x0(x), nv(p.nz + p.neta) {}
 
   int T(const S* v, S* Tv, Stats& out) {
-    HIP_TRY(launch_T<S>(P, v, Tv, x0, W.q, W.d, W.partials, W.stats, st, W.eta_zero, true));
+    HIP_TRY(launch_T<S>(P, v, Tv, x0, W.q, W.d, W.xbar, W.ubar, W.partials, W.stats, st, W.eta_zero, true));
     HIP_TRY(hipMemcpyAsync(hbuf.data(), W.stats, 6 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     out.xip = hbuf[0];
@@ -951,6 +1033,11 @@ extern "C" int spock_solve(spock_problem* ph, const double* x0_dev, const spock_
     if (!(hx[k] >= P.xlo0[k] && hx[k] <= P.xhi0[k])) return SPOCK_EBOX;
   spock_info loc{};
   loc.V_nested = std::numeric_limits<double>::quiet_NaN();
+  {
+    const int rt = (P.precision == SPOCK_FP64) ? autotune<double>(P, st) : autotune<float>(P, st);
+    if (rt) return rt;
+  }
+  loc.mapping = P.team;
   int rc = (P.precision == SPOCK_FP64)
                ? solve_impl<double>(P, x0_dev, *s, static_cast<double*>(v_io), loc, st)
                : solve_impl<float>(P, x0_dev, *s, static_cast<float*>(v_io), loc, st);
@@ -1017,7 +1104,7 @@ int prox_f_impl(Problem& P, const S* zin, const double* x0, S* zout, hipStream_t
   int rc = ensure_work<S>(P, W);
   if (rc) return rc;
   HIP_TRY(launch_fill<S>(P.neta, W.eta_zero, 0.0, st));
-  HIP_TRY(launch_T<S>(P, zin, zout, x0, W.q, W.d, W.partials, W.stats, st, W.eta_zero, false));
+  HIP_TRY(launch_T<S>(P, zin, zout, x0, W.q, W.d, W.xbar, W.ubar, W.partials, W.stats, st, W.eta_zero, false));
   return SPOCK_OK;
 }
 template <typename S>
@@ -1025,7 +1112,7 @@ int T_impl(Problem& P, const S* v, const double* x0, S* Tv, double* stats, hipSt
   Work<S> W;
   int rc = ensure_work<S>(P, W);
   if (rc) return rc;
-  HIP_TRY(launch_T<S>(P, v, Tv, x0, W.q, W.d, W.partials, W.stats, st, W.eta_zero, true));
+  HIP_TRY(launch_T<S>(P, v, Tv, x0, W.q, W.d, W.xbar, W.ubar, W.partials, W.stats, st, W.eta_zero, true));
   if (stats) {
     HIP_TRY(hipMemcpyAsync(stats, W.stats, 6 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));

@@ -170,36 +170,23 @@ __device__ __forceinline__ void soc_prox(const S* wv, S* outv, int len, S wa, S 
   outb = wb - al * (S(-0.5) + pt);
 }
 
-// ---------------------------------------------------------------- backward
-template <typename S, int T>
-__global__ void __launch_bounds__(256) k_bwd(DevProb<S> P, const S* __restrict__ z,
-                                             const S* __restrict__ eta, S* __restrict__ zout,
-                                             S* __restrict__ qbuf, S* __restrict__ dbuf,
-                                             int first, int count, int VM) {
-  constexpr int C = (kMaxDim + T - 1) / T;
-  extern __shared__ unsigned char smem_raw[];
-  S* smem = reinterpret_cast<S*>(smem_raw);
-  const int lane = threadIdx.x % T;
-  const int team = threadIdx.x / T;
-  const int f = blockIdx.x * (blockDim.x / T) + team;
-  if (f >= count) return;  // whole teams only; no block barrier below
-  const int i = first + f;
-  S* vq = smem + (size_t)team * 3 * VM;
-  S* vg = vq + VM;
-  S* vd = vg + VM;
-  const Off<S> O(P);
-  const int nx = P.nx, nu = P.nu;
-  const S al = P.alpha;
-  const int fc = P.fc[i], n = P.nch[i];
+// ---------------------------------------------------------------- family pieces
+// The functions below run on one team of T lanes (T <= 64, inside one
+// wavefront); lane o owns components o, o+T, ... of node vectors.
 
-  // xbar, ubar of node i: (x, u) - alpha (L* eta) on columns x^i, u^i
-  S xb[C], ub[C], sA[C], h[C];
+// xbar, ubar of nonleaf i: (x, u) - alpha (L* eta) on columns x^i, u^i.
+template <typename S, int T>
+__device__ __forceinline__ void fam_xbar_ubar(const DevProb<S>& P, const Off<S>& O,
+                                              const S* __restrict__ z, const S* __restrict__ eta,
+                                              int i, int lane, S (&xb)[(kMaxDim + T - 1) / T],
+                                              S (&ub)[(kMaxDim + T - 1) / T]) {
+  constexpr int C = (kMaxDim + T - 1) / T;
+  const int nx = P.nx, nu = P.nu, fc = P.fc[i], n = P.nch[i];
+  const S al = P.alpha;
   const long long e1x = O.e1x(i), e1u = O.e1u(i);
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     const int o = lane + c * T;
-    sA[c] = 0;
-    h[c] = 0;
     xb[c] = 0;
     ub[c] = 0;
     if (o < nx) {
@@ -213,31 +200,433 @@ __global__ void __launch_bounds__(256) k_bwd(DevProb<S> P, const S* __restrict__
       ub[c] = z[O.u(i) + o] - al * acc;
     }
   }
-  // children: h = sum B' q, sA = sum Abar' q
-  for (int k = 0; k < n; ++k) {
-    const int ch = fc + k;
-    const bool leaf = ch >= P.nl;
-    const long long e3 = leaf ? O.e3(ch) : 0;
+}
+
+// q of a child for the backward sweep: -xbar at a leaf (Alg. 2 start), the
+// stored q otherwise. Component o < nx.
+template <typename S>
+__device__ __forceinline__ S fam_child_q(const DevProb<S>& P, const Off<S>& O, const S* __restrict__ z,
+                                         const S* __restrict__ eta, const S* __restrict__ qbuf, int ch,
+                                         int o) {
+  const int nx = P.nx;
+  if (ch >= P.nl) {
+    const long long e3 = O.e3(ch);
+    return -(z[O.x(ch) + o] - P.alpha * (eta[e3 + o] + P.sqN[(size_t)ch * nx + o] * eta[e3 + nx + o]));
+  }
+  return qbuf[(size_t)ch * nx + o];
+}
+
+// S2 projection of the z2 block of nonleaf i after the step z - alpha L* eta,
+// and s^0 - alpha at the root. Closed form of the projection on the kernel of
+// G = [aI, -I, 1, -I, -I]: (G G')^{-1} = (I - 11'/(c+n))/c, c = a^2 + 3.
+template <typename S, int T>
+__device__ __forceinline__ void fam_s2(const DevProb<S>& P, const Off<S>& O, const S* __restrict__ z,
+                                       const S* __restrict__ eta, S* __restrict__ zout, int i,
+                                       int lane) {
+  const int nx = P.nx, nu = P.nu, fc = P.fc[i], n = P.nch[i];
+  const S al = P.alpha;
+  const long long zb = O.z2(i);
+  const long long e1 = O.e1(i);
+  const S es = eta[O.e1s(i)];
+  const S a = P.a[i];
+  const S y3h = z[zb + 2 * n] - al * (eta[e1 + 2 * n] - es);
+  double gsum = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    const S cc = a * a + S(3);
+    const S Gs = pass ? (S)team_sum<T>(gsum) : S(0);
+    double wsum = 0;
+    for (int k = lane; k < n; k += T) {
+      const int ch = fc + k;
+      const S y1h = z[zb + k] - al * (eta[e1 + k] - P.p[ch] * es);
+      const S y2h = z[zb + n + k] - al * eta[e1 + n + k];
+      const long long e2c = O.e2(ch) + nx + nu;
+      const S th = z[zb + 2 * n + 1 + k] - al * S(0.5) * (eta[e2c] + eta[e2c + 1]);
+      S Lts;
+      if (ch < P.nl) {
+        Lts = eta[O.e1s(ch)];
+      } else {
+        const long long e3c = O.e3(ch) + 2 * nx;
+        Lts = S(0.5) * (eta[e3c] + eta[e3c + 1]);
+      }
+      const S sh = z[zb + 3 * n + 1 + k] - al * Lts;
+      const S g = a * y1h - y2h + y3h - th - sh;
+      if (!pass) {
+        gsum += (double)g;
+      } else {
+        const S w = (g - Gs / (cc + S(n))) / cc;
+        wsum += (double)w;
+        zout[zb + k] = y1h - a * w;
+        zout[zb + n + k] = y2h + w;
+        zout[zb + 2 * n + 1 + k] = th + w;
+        zout[zb + 3 * n + 1 + k] = sh + w;
+      }
+    }
+    if (pass) {
+      const S Ws = (S)team_sum<T>(wsum);
+      if (lane == 0) {
+        zout[zb + 2 * n] = y3h - Ws;
+        if (i == 0) zout[0] = z[0] - al * es - al;
+      }
+    }
+  }
+}
+
+// Dual update and residual statistics of the rows of child ch (group 2, and
+// group 3 if ch is a leaf) and of the columns tau^ch (and x^ch, s^ch at a
+// leaf). xp/xo: x+^i and x^i (lane chunks); vu: u+^i in LDS; xc: x+^ch (lane
+// chunks); vr: LDS scratch of 2*VM; gx, gu accumulate the group-2 part of
+// L* r_eta on columns x^i, u^i.
+template <typename S, int T>
+__device__ __forceinline__ void fam_dual_child(const DevProb<S>& P, const Off<S>& O,
+                                               const S* __restrict__ z, const S* __restrict__ eta,
+                                               const S* __restrict__ zout, S* __restrict__ eout, int i,
+                                               int ch, int lane, const S (&xp)[(kMaxDim + T - 1) / T],
+                                               const S (&xo)[(kMaxDim + T - 1) / T], const S* vu,
+                                               const S (&xc)[(kMaxDim + T - 1) / T], S* vr,
+                                               S (&gx)[(kMaxDim + T - 1) / T],
+                                               S (&gu)[(kMaxDim + T - 1) / T], StatAcc& st) {
+  constexpr int C = (kMaxDim + T - 1) / T;
+  constexpr int C2 = (2 * kMaxDim + T - 1) / T;
+  const int nx = P.nx, nu = P.nu;
+  const S al = P.alpha;
+  const S ia = S(1) / al;
+  const long long ui = O.u(i);
+  // ---- group 2: (Q^{1/2} x^i, R^{1/2} u^i, tau/2, tau/2) in SOC + shift
+  const long long e2 = O.e2(ch);
+  const long long tpos = O.tau(ch);
+  const S tau = z[tpos], taup = zout[tpos];
+  S wv[C2], ov[C2], lz[C2];
+#pragma unroll
+  for (int c = 0; c < C2; ++c) {
+    const int o = lane + c * T;
+    wv[c] = 0;
+    ov[c] = 0;
+    lz[c] = 0;
+    if (o < nx) {
+      const S xpo = xp[c < C ? c : C - 1], xoo = xo[c < C ? c : C - 1];
+      const S sqv = P.sq[(size_t)ch * nx + o];
+      wv[c] = eta[e2 + o] + al * sqv * (S(2) * xpo - xoo);
+      lz[c] = sqv * (xoo - xpo);
+    } else if (o < nx + nu) {
+      const int ou = o - nx;
+      const S upo = vu[ou], uoo = z[ui + ou];
+      const S srv = P.sr[(size_t)ch * nu + ou];
+      wv[c] = eta[e2 + o] + al * srv * (S(2) * upo - uoo);
+      lz[c] = srv * (uoo - upo);
+    }
+  }
+  const S wa = eta[e2 + nx + nu] + al * S(0.5) * (S(2) * taup - tau);
+  const S wb = eta[e2 + nx + nu + 1] + al * S(0.5) * (S(2) * taup - tau);
+  S oa, ob;
+  soc_prox<S, T>(wv, ov, nx + nu, wa, wb, oa, ob, al, lane);
+  const S rtau = tau - taup;
+#pragma unroll
+  for (int c = 0; c < C2; ++c) {
+    const int o = lane + c * T;
+    if (o < nx + nu) {
+      eout[e2 + o] = ov[c];
+      const S re = eta[e2 + o] - ov[c];
+      vr[o] = re;
+      st.row((double)re, (double)lz[c], (double)ia);
+    }
+  }
+  wave_lds_sync();
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int o = lane + c * T;
+    if (o < nx) gx[c] += P.sq[(size_t)ch * nx + o] * vr[o];
+    if (o < nu) gu[c] += P.sr[(size_t)ch * nu + o] * vr[nx + o];
+  }
+  wave_lds_sync();
+  if (lane == 0) {
+    const S rea = eta[e2 + nx + nu] - oa, reb = eta[e2 + nx + nu + 1] - ob;
+    eout[e2 + nx + nu] = oa;
+    eout[e2 + nx + nu + 1] = ob;
+    st.row((double)rea, 0.5 * (double)rtau, (double)ia);
+    st.row((double)reb, 0.5 * (double)rtau, (double)ia);
+    st.col((double)rtau, 0.5 * ((double)rea + (double)reb), (double)ia);
+  }
+  if (ch < P.nl) return;
+  // ---- group 3 of a leaf: box on x, (Q_N^{1/2} x, s/2, s/2) in SOC + shift
+  const long long e3 = O.e3(ch);
+  const long long spos = O.s(ch);
+  const S sv = z[spos], svp = zout[spos];
+  S wq[C2], oq[C2];
+  S rex[C], xin[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int o = lane + c * T;
+    rex[c] = 0;
+    xin[c] = 0;
+    if (o < nx) {
+      const S xcin = z[O.x(ch) + o];
+      xin[c] = xcin;
+      const S wbx = eta[e3 + o] + al * (S(2) * xc[c] - xcin);
+      const S pb = wbx - al * clampv(wbx * ia, P.xlo[(size_t)ch * nx + o], P.xhi[(size_t)ch * nx + o]);
+      eout[e3 + o] = pb;
+      rex[c] = eta[e3 + o] - pb;
+      st.row((double)rex[c], (double)(xcin - xc[c]), (double)ia);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < C2; ++c) {
+    const int o = lane + c * T;
+    wq[c] = 0;
+    oq[c] = 0;
+    if (c < C && o < nx) {
+      const int cc = c < C ? c : C - 1;
+      wq[c] = eta[e3 + nx + o] + al * P.sqN[(size_t)ch * nx + o] * (S(2) * xc[cc] - xin[cc]);
+    }
+  }
+  const S wsa = eta[e3 + 2 * nx] + al * S(0.5) * (S(2) * svp - sv);
+  const S wsb = eta[e3 + 2 * nx + 1] + al * S(0.5) * (S(2) * svp - sv);
+  S osa, osb;
+  soc_prox<S, T>(wq, oq, nx, wsa, wsb, osa, osb, al, lane);
+  const S rs = sv - svp;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int o = lane + c * T;
+    if (o < nx) {
+      eout[e3 + nx + o] = oq[c];
+      const S reqv = eta[e3 + nx + o] - oq[c];
+      const S sqn = P.sqN[(size_t)ch * nx + o];
+      st.row((double)reqv, (double)(sqn * (xin[c] - xc[c])), (double)ia);
+      // column x^ch of a leaf: L* r_eta = r_eta(box) + Q_N^{1/2} r_eta(q)
+      st.col((double)(xin[c] - xc[c]), (double)(rex[c] + sqn * reqv), (double)ia);
+    }
+  }
+  if (lane == 0) {
+    eout[e3 + 2 * nx] = osa;
+    eout[e3 + 2 * nx + 1] = osb;
+    const S rea3 = eta[e3 + 2 * nx] - osa, reb3 = eta[e3 + 2 * nx + 1] - osb;
+    st.row((double)rea3, 0.5 * (double)rs, (double)ia);
+    st.row((double)reb3, 0.5 * (double)rs, (double)ia);
+    st.col((double)rs, 0.5 * ((double)rea3 + (double)reb3), (double)ia);
+  }
+}
+
+// Dual update of group 1 of nonleaf i: y in K* = R^{2n}_+ x R, s - b'y in
+// R_+, (x, u) in the box; columns y^i, s^i, x^i, u^i of L* r_eta.
+template <typename S, int T>
+__device__ __forceinline__ void fam_dual_node(const DevProb<S>& P, const Off<S>& O,
+                                              const S* __restrict__ z, const S* __restrict__ eta,
+                                              const S* __restrict__ zout, S* __restrict__ eout, int i,
+                                              int lane, const S (&xp)[(kMaxDim + T - 1) / T],
+                                              const S (&xo)[(kMaxDim + T - 1) / T],
+                                              const S (&up)[(kMaxDim + T - 1) / T],
+                                              const S (&uo)[(kMaxDim + T - 1) / T],
+                                              const S (&gx)[(kMaxDim + T - 1) / T],
+                                              const S (&gu)[(kMaxDim + T - 1) / T], StatAcc& st) {
+  constexpr int C = (kMaxDim + T - 1) / T;
+  const int nx = P.nx, nu = P.nu, fc = P.fc[i], n = P.nch[i];
+  const S al = P.alpha;
+  const S ia = S(1) / al;
+  const long long zb = O.z2(i);
+  const long long e1 = O.e1(i);
+  const long long spos = O.s(i);
+  const S si = z[spos], sip = zout[spos];
+  double bw = 0, bry = 0;
+  for (int k = lane; k < n; k += T) {
+    const S pk = P.p[fc + k];
+    const S y1 = z[zb + k], y1p = zout[zb + k];
+    bw += (double)(pk * (S(2) * y1p - y1));
+    bry += (double)(pk * (y1 - y1p));
+  }
+  const S y3 = z[zb + 2 * n], y3p = zout[zb + 2 * n];
+  const S bW = (S)team_sum<T>(bw) + (S(2) * y3p - y3);
+  const S bR = (S)team_sum<T>(bry) + (y3 - y3p);
+  const S ws = eta[e1 + 2 * n + 1] + al * ((S(2) * sip - si) - bW);
+  const S es_new = ws < S(0) ? ws : S(0);
+  const S res_ = eta[e1 + 2 * n + 1] - es_new;
+  for (int k = lane; k < 2 * n + 1; k += T) {
+    const S y = z[zb + k], yp = zout[zb + k];
+    const S w = eta[e1 + k] + al * (S(2) * yp - y);
+    const S ep = (k < 2 * n) ? (w < S(0) ? w : S(0)) : S(0);
+    eout[e1 + k] = ep;
+    const S re = eta[e1 + k] - ep;
+    const S ry = y - yp;
+    st.row((double)re, (double)ry, (double)ia);
+    const S bk = (k < n) ? P.p[fc + k] : ((k == 2 * n) ? S(1) : S(0));
+    st.col((double)ry, (double)(re - bk * res_), (double)ia);
+  }
+  if (lane == 0) {
+    eout[e1 + 2 * n + 1] = es_new;
+    const S rsi = si - sip;
+    st.row((double)res_, (double)(rsi - bR), (double)ia);
+    st.col((double)rsi, (double)res_, (double)ia);
+  }
+  const long long e1x = O.e1x(i), e1u = O.e1u(i);
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int o = lane + c * T;
+    if (o < nx) {
+      const S w = eta[e1x + o] + al * (S(2) * xp[c] - xo[c]);
+      const S ep = w - al * clampv(w * ia, P.xlo[(size_t)i * nx + o], P.xhi[(size_t)i * nx + o]);
+      eout[e1x + o] = ep;
+      const S re = eta[e1x + o] - ep;
+      const S rz = xo[c] - xp[c];
+      st.row((double)re, (double)rz, (double)ia);
+      st.col((double)rz, (double)(re + gx[c]), (double)ia);
+    }
+    if (o < nu) {
+      const S w = eta[e1u + o] + al * (S(2) * up[c] - uo[c]);
+      const S ep = w - al * clampv(w * ia, P.ulo[(size_t)i * nu + o], P.uhi[(size_t)i * nu + o]);
+      eout[e1u + o] = ep;
+      const S re = eta[e1u + o] - ep;
+      const S rz = uo[c] - up[c];
+      st.row((double)re, (double)rz, (double)ia);
+      st.col((double)rz, (double)(re + gu[c]), (double)ia);
+    }
+  }
+}
+
+// Fixed-order block reduction of the statistics into one partial record.
+__device__ __forceinline__ void block_stats(const StatAcc& st, double* __restrict__ partials) {
+  __shared__ double red[kStats][256];
+  red[0][threadIdx.x] = st.rz2;
+  red[1][threadIdx.x] = st.re2;
+  red[2][threadIdx.x] = st.cross;
+  red[3][threadIdx.x] = st.xip;
+  red[4][threadIdx.x] = st.xid;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s >= 1; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + s];
+      red[1][threadIdx.x] += red[1][threadIdx.x + s];
+      red[2][threadIdx.x] += red[2][threadIdx.x + s];
+      red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + s]);
+      red[4][threadIdx.x] = fmax(red[4][threadIdx.x], red[4][threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < kStats) partials[(size_t)blockIdx.x * kStats + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// ---------------------------------------------------------------- pre / post passes
+// Both passes are fully parallel over families (no recursion): team of T
+// lanes per family, 256 / T families per block, one launch for the tree.
+
+// pre-pass: xbar, ubar = (x, u) - alpha L* eta on columns x^i, u^i; leaf
+// children seed the backward sweep with q = -xbar (Alg. 2 start); the z2
+// block is projected on S2; s^0 - alpha at the root.
+template <typename S, int T>
+__global__ void __launch_bounds__(256) k_pre(DevProb<S> P, const S* __restrict__ z,
+                                             const S* __restrict__ eta, S* __restrict__ zout,
+                                             S* __restrict__ xbar, S* __restrict__ ubar,
+                                             S* __restrict__ qbuf) {
+  constexpr int C = (kMaxDim + T - 1) / T;
+  const int lane = threadIdx.x % T;
+  const int f = blockIdx.x * (blockDim.x / T) + threadIdx.x / T;
+  if (f >= P.nl) return;  // whole teams only; no block barrier below
+  const int i = f;
+  const Off<S> O(P);
+  const int nx = P.nx, nu = P.nu, fc = P.fc[i], n = P.nch[i];
+  S xb[C], ub[C];
+  fam_xbar_ubar<S, T>(P, O, z, eta, i, lane, xb, ub);
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int o = lane + c * T;
+    if (o < nx) xbar[(size_t)i * nx + o] = xb[c];
+    if (o < nu) ubar[(size_t)i * nu + o] = ub[c];
+  }
+  if (fc >= P.nl) {  // children are leaves
+    for (int k = 0; k < n; ++k)
+      for (int o = lane; o < nx; o += T) qbuf[(size_t)(fc + k) * nx + o] = fam_child_q<S>(P, O, z, eta, qbuf, fc + k, o);
+  }
+  fam_s2<S, T>(P, O, z, eta, zout, i, lane);
+}
+
+// post-pass: eta+ = prox_{alpha g*}(eta + alpha L(2 z+ - z)) on the family's
+// rows and the residual statistics of r = v - T(v) on its rows and columns.
+template <typename S, int T>
+__global__ void __launch_bounds__(256) k_post(DevProb<S> P, const S* __restrict__ z,
+                                              const S* __restrict__ eta, const S* __restrict__ zout,
+                                              S* __restrict__ eout, int VM,
+                                              double* __restrict__ partials) {
+  constexpr int C = (kMaxDim + T - 1) / T;
+  extern __shared__ unsigned char smem_raw[];
+  S* smem = reinterpret_cast<S*>(smem_raw);
+  const int lane = threadIdx.x % T;
+  const int team = threadIdx.x / T;
+  const int f = blockIdx.x * (blockDim.x / T) + team;
+  StatAcc st;
+  if (f < P.nl) {
+    const int i = f;
+    S* vu = smem + (size_t)team * 3 * VM;
+    S* vr = vu + VM;
+    const Off<S> O(P);
+    const int nx = P.nx, nu = P.nu, fc = P.fc[i], n = P.nch[i];
+    const long long ui = O.u(i);
+    S xp[C], xo[C], up[C], uo[C], gx[C], gu[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const int o = lane + c * T;
+      xp[c] = xo[c] = up[c] = uo[c] = gx[c] = gu[c] = 0;
       if (o < nx) {
-        S qv;
-        if (leaf) {
-          const S xbl = z[O.x(ch) + o] - al * (eta[e3 + o] + P.sqN[(size_t)ch * nx + o] * eta[e3 + nx + o]);
-          qv = -xbl;
-        } else {
-          qv = qbuf[(size_t)ch * nx + o];
-        }
-        vq[o] = qv;
+        xp[c] = zout[O.x(i) + o];
+        xo[c] = z[O.x(i) + o];
       }
+      if (o < nu) {
+        up[c] = zout[ui + o];
+        uo[c] = z[ui + o];
+        vu[o] = up[c];
+      }
+    }
+    wave_lds_sync();
+    for (int k = 0; k < n; ++k) {
+      const int ch = fc + k;
+      S xc[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const int o = lane + c * T;
+        xc[c] = (o < nx) ? zout[O.x(ch) + o] : S(0);
+      }
+      fam_dual_child<S, T>(P, O, z, eta, zout, eout, i, ch, lane, xp, xo, vu, xc, vr, gx, gu, st);
+    }
+    fam_dual_node<S, T>(P, O, z, eta, zout, eout, i, lane, xp, xo, up, uo, gx, gu, st);
+  }
+  block_stats(st, partials);
+}
+
+// ---------------------------------------------------------------- team sweeps
+// One team of T lanes per family; one launch per stage.
+template <typename S, int T>
+__global__ void __launch_bounds__(256) k_bwd(DevProb<S> P, const S* __restrict__ xbar,
+                                             const S* __restrict__ ubar, S* __restrict__ qbuf,
+                                             S* __restrict__ dbuf, int first, int count, int VM) {
+  constexpr int C = (kMaxDim + T - 1) / T;
+  extern __shared__ unsigned char smem_raw[];
+  S* smem = reinterpret_cast<S*>(smem_raw);
+  const int lane = threadIdx.x % T;
+  const int team = threadIdx.x / T;
+  const int f = blockIdx.x * (blockDim.x / T) + team;
+  if (f >= count) return;  // whole teams only; no block barrier below
+  const int i = first + f;
+  S* vq = smem + (size_t)team * 3 * VM;
+  S* vg = vq + VM;
+  S* vd = vg + VM;
+  const int nx = P.nx, nu = P.nu;
+  const int fc = P.fc[i], n = P.nch[i];
+  S xb[C], ub[C], sA[C], h[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int o = lane + c * T;
+    xb[c] = (o < nx) ? xbar[(size_t)i * nx + o] : S(0);
+    ub[c] = (o < nu) ? ubar[(size_t)i * nu + o] : S(0);
+    sA[c] = h[c] = 0;
+  }
+  for (int k = 0; k < n; ++k) {
+    const int ch = fc + k;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int o = lane + c * T;
+      if (o < nx) vq[o] = qbuf[(size_t)ch * nx + o];
     }
     wave_lds_sync();
     mv_acc<S, T>(h, P.BR + (size_t)ch * nx * nu, nx, nu, vq, lane);
     mv_acc<S, T>(sA, P.AbR + (size_t)ch * nx * nx, nx, nx, vq, lane);
     wave_lds_sync();
   }
-  // d = R~^{-1}(ubar - h)
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     const int o = lane + c * T;
@@ -259,7 +648,6 @@ __global__ void __launch_bounds__(256) k_bwd(DevProb<S> P, const S* __restrict__
     }
   }
   wave_lds_sync();
-  // q = K'(d - ubar) + W d - xbar + sum Abar' q
   S qi[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) qi[c] = sA[c] - xb[c];
@@ -270,342 +658,384 @@ __global__ void __launch_bounds__(256) k_bwd(DevProb<S> P, const S* __restrict__
     const int o = lane + c * T;
     if (o < nx) qbuf[(size_t)i * nx + o] = qi[c];
   }
-
-  // S2 projection of the z2 block of i (closed form of the kernel projection:
-  // G = [aI, -I, 1, -I, -I], (G G')^{-1} = (I - 11'/(c+n))/c, c = a^2 + 3)
-  const long long zb = O.z2(i);
-  const long long e1 = O.e1(i);
-  const S es = eta[O.e1s(i)];
-  const S a = P.a[i];
-  const S y3h = z[zb + 2 * n] - al * (eta[e1 + 2 * n] - es);
-  double gsum = 0;
-  for (int k = lane; k < n; k += T) {
-    const int ch = fc + k;
-    const S y1h = z[zb + k] - al * (eta[e1 + k] - P.p[ch] * es);
-    const S y2h = z[zb + n + k] - al * eta[e1 + n + k];
-    const long long e2c = O.e2(ch) + nx + nu;
-    const S th = z[zb + 2 * n + 1 + k] - al * S(0.5) * (eta[e2c] + eta[e2c + 1]);
-    S Lts;
-    if (ch < P.nl) {
-      Lts = eta[O.e1s(ch)];
-    } else {
-      const long long e3c = O.e3(ch) + 2 * nx;
-      Lts = S(0.5) * (eta[e3c] + eta[e3c + 1]);
-    }
-    const S sh = z[zb + 3 * n + 1 + k] - al * Lts;
-    gsum += (double)(a * y1h - y2h + y3h - th - sh);
-  }
-  const S cc = a * a + S(3);
-  const S Gs = (S)team_sum<T>(gsum);
-  double wsum = 0;
-  for (int k = lane; k < n; k += T) {
-    const int ch = fc + k;
-    const S y1h = z[zb + k] - al * (eta[e1 + k] - P.p[ch] * es);
-    const S y2h = z[zb + n + k] - al * eta[e1 + n + k];
-    const long long e2c = O.e2(ch) + nx + nu;
-    const S th = z[zb + 2 * n + 1 + k] - al * S(0.5) * (eta[e2c] + eta[e2c + 1]);
-    S Lts;
-    if (ch < P.nl) {
-      Lts = eta[O.e1s(ch)];
-    } else {
-      const long long e3c = O.e3(ch) + 2 * nx;
-      Lts = S(0.5) * (eta[e3c] + eta[e3c + 1]);
-    }
-    const S sh = z[zb + 3 * n + 1 + k] - al * Lts;
-    const S g = a * y1h - y2h + y3h - th - sh;
-    const S w = (g - Gs / (cc + S(n))) / cc;
-    wsum += (double)w;
-    zout[zb + k] = y1h - a * w;
-    zout[zb + n + k] = y2h + w;
-    zout[zb + 2 * n + 1 + k] = th + w;
-    zout[zb + 3 * n + 1 + k] = sh + w;
-  }
-  const S Ws = (S)team_sum<T>(wsum);
-  if (lane == 0) {
-    zout[zb + 2 * n] = y3h - Ws;
-    if (i == 0) zout[0] = z[0] - al * es - al;
-  }
 }
 
-// ---------------------------------------------------------------- forward
-// LDS per team: vx (VM) x^i, vd (VM) d^i, vu (VM) u+^i, vr (2 VM) group-2 r_eta.
-template <typename S, int T, bool DUAL>
-__global__ void __launch_bounds__(256) k_fwd(DevProb<S> P, const S* __restrict__ z,
-                                             const S* __restrict__ eta, S* __restrict__ zout,
-                                             S* __restrict__ eout, const S* __restrict__ dbuf,
+template <typename S, int T>
+__global__ void __launch_bounds__(256) k_fwd(DevProb<S> P, S* __restrict__ zout,
+                                             const S* __restrict__ dbuf,
                                              const double* __restrict__ x0, int first, int count,
-                                             int VM, double* __restrict__ partials) {
+                                             int VM) {
   constexpr int C = (kMaxDim + T - 1) / T;
-  constexpr int C2 = (2 * kMaxDim + T - 1) / T;
   extern __shared__ unsigned char smem_raw[];
   S* smem = reinterpret_cast<S*>(smem_raw);
   const int lane = threadIdx.x % T;
   const int team = threadIdx.x / T;
   const int f = blockIdx.x * (blockDim.x / T) + team;
-  StatAcc st;
-  if (f < count) {
-    const int i = first + f;
-    S* vx = smem + (size_t)team * 5 * VM;
-    S* vd = vx + VM;
-    S* vu = vd + VM;
-    S* vr = vu + VM;
-    const Off<S> O(P);
-    const int nx = P.nx, nu = P.nu;
-    const S al = P.alpha;
-    const S ia = S(1) / al;
-    const int fc = P.fc[i], n = P.nch[i];
-    const long long ui = O.u(i);
-
-    S xp[C], xo[C], up[C], uo[C];
+  if (f >= count) return;
+  const int i = first + f;
+  S* vx = smem + (size_t)team * 2 * VM;
+  S* vd = vx + VM;
+  const Off<S> O(P);
+  const int nx = P.nx, nu = P.nu;
+  const int fc = P.fc[i], n = P.nch[i];
+  const long long ui = O.u(i);
+  S up[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int o = lane + c * T;
+    up[c] = 0;
+    if (o < nx) {
+      S xv;
+      if (i == 0) {
+        xv = (S)x0[o];
+        zout[1 + o] = xv;
+      } else {
+        xv = zout[O.x(i) + o];
+      }
+      vx[o] = xv;
+    }
+    if (o < nu) {
+      const S dd = dbuf[(size_t)i * nu + o];
+      vd[o] = dd;
+      up[c] = dd;
+    }
+  }
+  wave_lds_sync();
+  mv_acc<S, T>(up, P.KC + (size_t)i * nx * nu, nx, nu, vx, lane);
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int o = lane + c * T;
+    if (o < nu) zout[ui + o] = up[c];
+  }
+  for (int k = 0; k < n; ++k) {
+    const int ch = fc + k;
+    S xc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) xc[c] = 0;
+    mv_acc<S, T>(xc, P.AbC + (size_t)ch * nx * nx, nx, nx, vx, lane);
+    mv_acc<S, T>(xc, P.BC + (size_t)ch * nu * nx, nu, nx, vd, lane);
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const int o = lane + c * T;
-      xp[c] = xo[c] = up[c] = uo[c] = 0;
-      if (o < nx) {
-        S xv;
-        if (i == 0) {
-          xv = (S)x0[o];
-          zout[1 + o] = xv;
-        } else {
-          xv = zout[O.x(i) + o];
-        }
-        vx[o] = xv;
-        xp[c] = xv;
-        xo[c] = z[O.x(i) + o];
-      }
-      if (o < nu) {
-        const S dd = dbuf[(size_t)i * nu + o];
-        vd[o] = dd;
-        up[c] = dd;
-        uo[c] = z[ui + o];
-      }
+      if (o < nx) zout[O.x(ch) + o] = xc[c];
     }
-    wave_lds_sync();
-    mv_acc<S, T>(up, P.KC + (size_t)i * nx * nu, nx, nu, vx, lane);
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-      const int o = lane + c * T;
-      if (o < nu) {
-        zout[ui + o] = up[c];
-        vu[o] = up[c];
-      }
-    }
-    wave_lds_sync();
-    S gx[C], gu[C];  // sum over children of Q^{1/2} r_eta(x part), R^{1/2} r_eta(u part)
-#pragma unroll
-    for (int c = 0; c < C; ++c) gx[c] = gu[c] = 0;
+  }
+}
 
-    for (int k = 0; k < n; ++k) {
-      const int ch = fc + k;
-      S xc[C];
+// ---------------------------------------------------------------- workgroup sweeps
+// One 256-thread workgroup (4 wavefronts) per family. Every mat-vec is split
+// over the input index across the 4 wavefronts; inside a wavefront the lanes
+// form G = floor(64 / nout) groups (G = 1 when nout > 32), each group reading
+// one input row, so one load instruction covers G consecutive rows of the
+// input-major matrix. All matrix loads of a family are issued into registers
+// before the first barrier; partial sums are combined in LDS in a fixed order.
+constexpr int kWG = 256;
+constexpr int kKJ = 16;         // max loads per lane per mat-vec: ceil(64 / 4)
+constexpr int kMaxLevels = 64;  // stages a subtree-owning workgroup walks
+
+template <typename S>
+struct MvRegs {
+  S m[kKJ];
+};
+
+struct MvGeom {
+  int G, o, kg, stride;
+  bool act;
+  __device__ __forceinline__ MvGeom(int nout) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    G = nout > 32 ? 1 : 64 / nout;
+    const int g = lane / nout;
+    o = lane - g * nout;
+    act = g < G;
+    kg = w * G + g;
+    stride = 4 * G;
+  }
+};
+
+template <typename S>
+__device__ __forceinline__ void mv_load(MvRegs<S>& r, const S* __restrict__ M, int nin, int nout) {
+  const MvGeom g(nout);
 #pragma unroll
-      for (int c = 0; c < C; ++c) xc[c] = 0;
-      mv_acc<S, T>(xc, P.AbC + (size_t)ch * nx * nx, nx, nx, vx, lane);
-      mv_acc<S, T>(xc, P.BC + (size_t)ch * nu * nx, nu, nx, vd, lane);
-      const bool leaf = ch >= P.nl;
+  for (int j = 0; j < kKJ; ++j) {
+    const int k = g.kg + g.stride * j;
+    r.m[j] = (g.act && k < nin) ? M[(size_t)k * nout + g.o] : S(0);
+  }
+}
+
+// partial sum of this thread, written to red[kg * nout + o]
+template <typename S>
+__device__ __forceinline__ void mv_partial(const MvRegs<S>& r, const S* v, int nin, int nout, S* red) {
+  const MvGeom g(nout);
+  if (!g.act) return;
+  S acc = 0;
 #pragma unroll
-      for (int c = 0; c < C; ++c) {
-        const int o = lane + c * T;
-        if (o < nx) zout[O.x(ch) + o] = xc[c];
-      }
-      if (!DUAL) continue;
-      // ---- group 2 of child ch: (Q^{1/2} x^i, R^{1/2} u^i, tau/2, tau/2) in SOC + shift
-      const long long e2 = O.e2(ch);
-      const long long tpos = O.tau(ch);
-      const S tau = z[tpos], taup = zout[tpos];
-      S wv[C2], ov[C2], lz[C2];
+  for (int j = 0; j < kKJ; ++j) {
+    const int k = g.kg + g.stride * j;
+    if (k < nin) acc += r.m[j] * v[k];
+  }
+  red[g.kg * nout + g.o] = acc;
+}
+
+// y[o] = sum over the 4 G partials of output o (call with o = threadIdx.x < nout)
+template <typename S>
+__device__ __forceinline__ S mv_sum(const S* red, int nout, int o) {
+  const int G = nout > 32 ? 1 : 64 / nout;
+  S s = 0;
+  for (int q = 0; q < 4 * G; ++q) s += red[q * nout + o];
+  return s;
+}
+
+// Prefetch of up to 8 byte ranges into L2: thread t reads one 32-bit word of
+// lines t, t + 256, ... of the concatenated ranges (128-byte lines), so a later
+// family's loads hit L2. The words are folded into acc, which the caller
+// keeps alive.
+struct Ranges {
+  const char* p[8] = {};
+  int lines[8] = {};
+  int n = 0;
+  __device__ __forceinline__ void add(const void* ptr, size_t bytes) {
+    p[n] = static_cast<const char*>(ptr);
+    lines[n] = (int)((bytes + 127) / 128);
+    ++n;
+  }
+};
+
+__device__ __forceinline__ void touch(const Ranges& R, unsigned& acc) {
+  int total = 0;
 #pragma unroll
-      for (int c = 0; c < C2; ++c) {
-        const int o = lane + c * T;
-        wv[c] = 0;
-        ov[c] = 0;
-        lz[c] = 0;
-        if (o < nx) {
-          // component o of x is this lane's chunk c (o = lane + c*T, c < C)
-          const S xpo = xp[c < C ? c : C - 1], xoo = xo[c < C ? c : C - 1];
-          const S sqv = P.sq[(size_t)ch * nx + o];
-          wv[c] = eta[e2 + o] + al * sqv * (S(2) * xpo - xoo);
-          lz[c] = sqv * (xoo - xpo);
-        } else if (o < nx + nu) {
-          const int ou = o - nx;
-          const S upo = vu[ou], uoo = z[ui + ou];
-          const S srv = P.sr[(size_t)ch * nu + ou];
-          wv[c] = eta[e2 + o] + al * srv * (S(2) * upo - uoo);
-          lz[c] = srv * (uoo - upo);
-        }
-      }
-      const S wa = eta[e2 + nx + nu] + al * S(0.5) * (S(2) * taup - tau);
-      const S wb = eta[e2 + nx + nu + 1] + al * S(0.5) * (S(2) * taup - tau);
-      S oa, ob;
-      soc_prox<S, T>(wv, ov, nx + nu, wa, wb, oa, ob, al, lane);
-      const S rtau = tau - taup;
+  for (int r = 0; r < 8; ++r)
+    if (r < R.n) total += R.lines[r];
+  for (int l = threadIdx.x; l < total; l += kWG) {
+    int off = l;
 #pragma unroll
-      for (int c = 0; c < C2; ++c) {
-        const int o = lane + c * T;
-        if (o < nx + nu) {
-          eout[e2 + o] = ov[c];
-          const S re = eta[e2 + o] - ov[c];
-          vr[o] = re;
-          st.row((double)re, (double)lz[c], (double)ia);
-        }
-      }
-      wave_lds_sync();
-      // L* of columns x^i, u^i: group-2 contributions (lane-owned components)
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        const int o = lane + c * T;
-        if (o < nx) gx[c] += P.sq[(size_t)ch * nx + o] * vr[o];
-        if (o < nu) gu[c] += P.sr[(size_t)ch * nu + o] * vr[nx + o];
-      }
-      wave_lds_sync();
-      if (lane == 0) {
-        const S rea = eta[e2 + nx + nu] - oa, reb = eta[e2 + nx + nu + 1] - ob;
-        eout[e2 + nx + nu] = oa;
-        eout[e2 + nx + nu + 1] = ob;
-        st.row((double)rea, 0.5 * (double)rtau, (double)ia);
-        st.row((double)reb, 0.5 * (double)rtau, (double)ia);
-        st.col((double)rtau, 0.5 * ((double)rea + (double)reb), (double)ia);
-      }
-      if (!leaf) continue;
-      // ---- group 3 of leaf ch: box on x, (Q_N^{1/2} x, s/2, s/2) in SOC + shift
-      const long long e3 = O.e3(ch);
-      const long long spos = O.s(ch);
-      const S sv = z[spos], svp = zout[spos];
-      S wq[C2], oq[C2];
-      S rex[C], xin[C];
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        const int o = lane + c * T;
-        rex[c] = 0;
-        xin[c] = 0;
-        if (o < nx) {
-          const S xcin = z[O.x(ch) + o];
-          xin[c] = xcin;
-          const S wbx = eta[e3 + o] + al * (S(2) * xc[c] - xcin);
-          const S pb = wbx - al * clampv(wbx * ia, P.xlo[(size_t)ch * nx + o], P.xhi[(size_t)ch * nx + o]);
-          eout[e3 + o] = pb;
-          rex[c] = eta[e3 + o] - pb;
-          st.row((double)rex[c], (double)(xcin - xc[c]), (double)ia);
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < C2; ++c) {
-        const int o = lane + c * T;
-        wq[c] = 0;
-        oq[c] = 0;
-        if (c < C && o < nx) {
-          const int cc = c < C ? c : C - 1;
-          wq[c] = eta[e3 + nx + o] + al * P.sqN[(size_t)ch * nx + o] * (S(2) * xc[cc] - xin[cc]);
-        }
-      }
-      const S wsa = eta[e3 + 2 * nx] + al * S(0.5) * (S(2) * svp - sv);
-      const S wsb = eta[e3 + 2 * nx + 1] + al * S(0.5) * (S(2) * svp - sv);
-      S osa, osb;
-      soc_prox<S, T>(wq, oq, nx, wsa, wsb, osa, osb, al, lane);
-      const S rs = sv - svp;
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        const int o = lane + c * T;
-        if (o < nx) {
-          eout[e3 + nx + o] = oq[c];
-          const S reqv = eta[e3 + nx + o] - oq[c];
-          const S sqn = P.sqN[(size_t)ch * nx + o];
-          st.row((double)reqv, (double)(sqn * (xin[c] - xc[c])), (double)ia);
-          // column x^ch of a leaf: L* r_eta = r_eta(box) + Q_N^{1/2} r_eta(q)
-          st.col((double)(xin[c] - xc[c]), (double)(rex[c] + sqn * reqv), (double)ia);
-        }
-      }
-      if (lane == 0) {
-        eout[e3 + 2 * nx] = osa;
-        eout[e3 + 2 * nx + 1] = osb;
-        const S rea3 = eta[e3 + 2 * nx] - osa, reb3 = eta[e3 + 2 * nx + 1] - osb;
-        st.row((double)rea3, 0.5 * (double)rs, (double)ia);
-        st.row((double)reb3, 0.5 * (double)rs, (double)ia);
-        st.col((double)rs, 0.5 * ((double)rea3 + (double)reb3), (double)ia);
-      }
-    }
-    if (DUAL) {
-      // ---- group 1 of i: y in K* = R^{2n}_+ x R, s - b'y in R_+, (x, u) in the box
-      const long long zb = O.z2(i);
-      const long long e1 = O.e1(i);
-      const long long spos = O.s(i);
-      const S si = z[spos], sip = zout[spos];
-      // b'(2y+ - y) and b' r_y (team sums), b = (p^{ch}, 0, 1)
-      double bw = 0, bry = 0;
-      for (int k = lane; k < n; k += T) {
-        const S pk = P.p[fc + k];
-        const S y1 = z[zb + k], y1p = zout[zb + k];
-        bw += (double)(pk * (S(2) * y1p - y1));
-        bry += (double)(pk * (y1 - y1p));
-      }
-      const S y3 = z[zb + 2 * n], y3p = zout[zb + 2 * n];
-      const S bW = (S)team_sum<T>(bw) + (S(2) * y3p - y3);
-      const S bR = (S)team_sum<T>(bry) + (y3 - y3p);
-      const S ws = eta[e1 + 2 * n + 1] + al * ((S(2) * sip - si) - bW);
-      const S es_new = ws < S(0) ? ws : S(0);
-      const S res_ = eta[e1 + 2 * n + 1] - es_new;
-      for (int k = lane; k < 2 * n + 1; k += T) {
-        const S y = z[zb + k], yp = zout[zb + k];
-        const S w = eta[e1 + k] + al * (S(2) * yp - y);
-        const S ep = (k < 2 * n) ? (w < S(0) ? w : S(0)) : S(0);
-        eout[e1 + k] = ep;
-        const S re = eta[e1 + k] - ep;
-        const S ry = y - yp;
-        st.row((double)re, (double)ry, (double)ia);
-        const S bk = (k < n) ? P.p[fc + k] : ((k == 2 * n) ? S(1) : S(0));
-        st.col((double)ry, (double)(re - bk * res_), (double)ia);
-      }
-      if (lane == 0) {
-        eout[e1 + 2 * n + 1] = es_new;
-        const S rsi = si - sip;
-        st.row((double)res_, (double)(rsi - bR), (double)ia);
-        st.col((double)rsi, (double)res_, (double)ia);
-      }
-      const long long e1x = O.e1x(i), e1u = O.e1u(i);
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        const int o = lane + c * T;
-        if (o < nx) {
-          const S w = eta[e1x + o] + al * (S(2) * xp[c] - xo[c]);
-          const S ep = w - al * clampv(w * ia, P.xlo[(size_t)i * nx + o], P.xhi[(size_t)i * nx + o]);
-          eout[e1x + o] = ep;
-          const S re = eta[e1x + o] - ep;
-          const S rz = xo[c] - xp[c];
-          st.row((double)re, (double)rz, (double)ia);
-          st.col((double)rz, (double)(re + gx[c]), (double)ia);
-        }
-        if (o < nu) {
-          const S w = eta[e1u + o] + al * (S(2) * up[c] - uo[c]);
-          const S ep = w - al * clampv(w * ia, P.ulo[(size_t)i * nu + o], P.uhi[(size_t)i * nu + o]);
-          eout[e1u + o] = ep;
-          const S re = eta[e1u + o] - ep;
-          const S rz = uo[c] - up[c];
-          st.row((double)re, (double)rz, (double)ia);
-          st.col((double)rz, (double)(re + gu[c]), (double)ia);
-        }
+    for (int r = 0; r < 8; ++r) {  // fixed trip count keeps R in registers
+      if (r < R.n) {
+        if (off >= 0 && off < R.lines[r]) acc ^= *reinterpret_cast<const unsigned*>(R.p[r] + (size_t)off * 128);
+        off -= R.lines[r];
       }
     }
   }
-  if (!DUAL) return;
-  // block reduction of the statistics (fixed order: deterministic)
-  __shared__ double red[kStats][256];
-  red[0][threadIdx.x] = st.rz2;
-  red[1][threadIdx.x] = st.re2;
-  red[2][threadIdx.x] = st.cross;
-  red[3][threadIdx.x] = st.xip;
-  red[4][threadIdx.x] = st.xid;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s >= 1; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      red[0][threadIdx.x] += red[0][threadIdx.x + s];
-      red[1][threadIdx.x] += red[1][threadIdx.x + s];
-      red[2][threadIdx.x] += red[2][threadIdx.x + s];
-      red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + s]);
-      red[4][threadIdx.x] = fmax(red[4][threadIdx.x], red[4][threadIdx.x + s]);
+}
+
+// Backward data of family j (matrices, xbar, ubar) pulled into L2.
+template <typename S>
+__device__ __forceinline__ void prefetch_bwd(const DevProb<S>& P, const S* xbar, const S* ubar,
+                                             const S* qbuf, int j, unsigned& acc) {
+  const int nx = P.nx, nu = P.nu, fc = P.fc[j], n = P.nch[j];
+  Ranges R;
+  R.add(P.AbR + (size_t)fc * nx * nx, sizeof(S) * n * nx * nx);
+  R.add(P.BR + (size_t)fc * nx * nu, sizeof(S) * n * nx * nu);
+  R.add(P.Rinv + (size_t)j * nu * nu, sizeof(S) * nu * nu);
+  R.add(P.KR + (size_t)j * nu * nx, sizeof(S) * nu * nx);
+  R.add(P.WC + (size_t)j * nu * nx, sizeof(S) * nu * nx);
+  R.add(xbar + (size_t)j * nx, sizeof(S) * nx);
+  R.add(ubar + (size_t)j * nu, sizeof(S) * nu);
+  touch(R, acc);
+  (void)qbuf;
+}
+
+// Forward data of family j (matrices and d) pulled into L2.
+template <typename S>
+__device__ __forceinline__ void prefetch_fwd(const DevProb<S>& P, const S* dbuf, int j, unsigned& acc) {
+  const int nx = P.nx, nu = P.nu, fc = P.fc[j], n = P.nch[j];
+  Ranges R;
+  R.add(P.AbC + (size_t)fc * nx * nx, sizeof(S) * n * nx * nx);
+  R.add(P.BC + (size_t)fc * nu * nx, sizeof(S) * n * nu * nx);
+  R.add(P.KC + (size_t)j * nx * nu, sizeof(S) * nx * nu);
+  R.add(dbuf + (size_t)j * nu, sizeof(S) * nu);
+  touch(R, acc);
+}
+
+// Backward step of family i by the whole workgroup (called uniformly).
+// `next` (or -1) is the family this workgroup handles afterwards; its data is
+// prefetched into L2 once this family's own loads are in flight.
+template <typename S>
+__device__ void bwd_family_wg(const DevProb<S>& P, const S* __restrict__ xbar,
+                              const S* __restrict__ ubar, S* __restrict__ qbuf,
+                              S* __restrict__ dbuf, int i, int next, unsigned& pf) {
+  __shared__ S vq[kMaxDim], vg[kMaxDim], vd[kMaxDim], sA[kMaxDim], hh[kMaxDim], xbs[kMaxDim],
+      ubs[kMaxDim];
+  __shared__ S red1[kWG], red2[kWG];
+  const int t = threadIdx.x;
+  const int nx = P.nx, nu = P.nu;
+  const int fc = P.fc[i], n = P.nch[i];
+  MvRegs<S> mR, mK, mW, mA, mB;
+  mv_load(mA, P.AbR + (size_t)fc * nx * nx, nx, nx);  // first child, prefetched
+  mv_load(mB, P.BR + (size_t)fc * nx * nu, nx, nu);
+  mv_load(mR, P.Rinv + (size_t)i * nu * nu, nu, nu);
+  mv_load(mK, P.KR + (size_t)i * nu * nx, nu, nx);
+  mv_load(mW, P.WC + (size_t)i * nu * nx, nu, nx);
+  if (t < nx) xbs[t] = xbar[(size_t)i * nx + t];
+  if (t < nu) ubs[t] = ubar[(size_t)i * nu + t];
+  if (t < 64) {
+    sA[t] = 0;
+    hh[t] = 0;
+  }
+  S qnext = (t < nx) ? qbuf[(size_t)fc * nx + t] : S(0);
+  for (int k = 0; k < n; ++k) {
+    const int ch = fc + k;
+    if (t < nx) vq[t] = qnext;
+    __syncthreads();
+    // this family's own loads have all been consumed: the next family's data
+    // now streams into L2 while this one computes
+    if (k == 0 && next >= 0) prefetch_bwd(P, xbar, ubar, qbuf, next, pf);
+    mv_partial(mA, vq, nx, nx, red1);
+    mv_partial(mB, vq, nx, nu, red2);
+    if (k + 1 < n) {  // prefetch the next child's matrices and q
+      mv_load(mA, P.AbR + (size_t)(ch + 1) * nx * nx, nx, nx);
+      mv_load(mB, P.BR + (size_t)(ch + 1) * nx * nu, nx, nu);
+      if (t < nx) qnext = qbuf[(size_t)(ch + 1) * nx + t];
     }
     __syncthreads();
+    if (t < nx) sA[t] += mv_sum(red1, nx, t);
+    if (t < nu) hh[t] += mv_sum(red2, nu, t);
+    __syncthreads();
   }
-  if (threadIdx.x < kStats) partials[(size_t)blockIdx.x * kStats + threadIdx.x] = red[threadIdx.x][0];
+  // d = R~^{-1}(ubar - h)
+  if (t < nu) vg[t] = ubs[t] - hh[t];
+  __syncthreads();
+  mv_partial(mR, vg, nu, nu, red1);
+  __syncthreads();
+  if (t < nu) {
+    const S dv = mv_sum(red1, nu, t);
+    vd[t] = dv;
+    dbuf[(size_t)i * nu + t] = dv;
+    vg[t] = dv - ubs[t];
+  }
+  __syncthreads();
+  // q = K'(d - ubar) + W d - xbar + sum Abar' q
+  mv_partial(mK, vg, nu, nx, red1);
+  mv_partial(mW, vd, nu, nx, red2);
+  __syncthreads();
+  if (t < nx) qbuf[(size_t)i * nx + t] = mv_sum(red1, nx, t) + mv_sum(red2, nx, t) - xbs[t] + sA[t];
+  __syncthreads();  // LDS reuse by the next family of this workgroup
+}
+
+template <typename S>
+__global__ void __launch_bounds__(kWG) k_bwd_wg(DevProb<S> P, const S* __restrict__ xbar,
+                                                const S* __restrict__ ubar, S* __restrict__ qbuf,
+                                                S* __restrict__ dbuf, int first) {
+  unsigned pf = 0;
+  bwd_family_wg<S>(P, xbar, ubar, qbuf, dbuf, first + blockIdx.x, -1, pf);
+}
+
+// Descendant ranges of subtree root r (stage tc) down to the last nonleaf
+// stage: nodes of a subtree at one stage are contiguous (breadth-first order
+// with contiguous children). lo[l], hi[l] (LDS) belong to stage tc + l;
+// thread 0 fills them, the caller's barrier publishes them.
+template <typename S>
+__device__ __forceinline__ int subtree_levels(const DevProb<S>& P, int r, int tc, int* lo, int* hi) {
+  const int levels = P.N - tc;  // nonleaf stages tc .. N-1
+  if (threadIdx.x == 0) {
+    lo[0] = r;
+    hi[0] = r + 1;
+    for (int l = 1; l < levels; ++l) {
+      lo[l] = P.fc[lo[l - 1]];
+      hi[l] = P.fc[hi[l - 1] - 1] + P.nch[hi[l - 1] - 1];
+    }
+  }
+  __syncthreads();
+  return levels;
+}
+
+// Backward sweep over whole subtrees rooted at stage tc: one workgroup per
+// subtree walks its stages bottom-up, so the stages below tc need no launch
+// of their own.
+template <typename S>
+__global__ void __launch_bounds__(kWG) k_bwd_tail_wg(DevProb<S> P, const S* __restrict__ xbar,
+                                                     const S* __restrict__ ubar, S* __restrict__ qbuf,
+                                                     S* __restrict__ dbuf, int tc, int root_first,
+                                                     int nroots) {
+  __shared__ int lo[kMaxLevels], hi[kMaxLevels];
+  unsigned pf = 0;
+  for (int r = blockIdx.x; r < nroots; r += gridDim.x) {
+    const int levels = subtree_levels(P, root_first + r, tc, lo, hi);
+    for (int l = levels - 1; l >= 0; --l) {
+      const int a = lo[l], b = hi[l];
+      for (int i = a; i < b; ++i) {
+        const int next = (i + 1 < b) ? i + 1 : (l > 0 ? lo[l - 1] : -1);
+        bwd_family_wg<S>(P, xbar, ubar, qbuf, dbuf, i, next, pf);
+      }
+    }
+    __syncthreads();  // before the ranges are overwritten
+  }
+  if (P.nn < 0) qbuf[0] = S(pf);  // never true: keeps the prefetch loads alive
+}
+
+// Forward step of family i by the whole workgroup.
+template <typename S>
+__device__ void fwd_family_wg(const DevProb<S>& P, S* __restrict__ zout, const S* __restrict__ dbuf,
+                              const double* __restrict__ x0, int i, int next, unsigned& pf) {
+  __shared__ S vx[kMaxDim], vd[kMaxDim];
+  __shared__ S red1[kWG], red2[kWG];
+  const int t = threadIdx.x;
+  const Off<S> O(P);
+  const int nx = P.nx, nu = P.nu;
+  const int fc = P.fc[i], n = P.nch[i];
+  const long long ui = O.u(i);
+  MvRegs<S> mK, mA, mB;
+  mv_load(mA, P.AbC + (size_t)fc * nx * nx, nx, nx);  // first child, prefetched
+  mv_load(mB, P.BC + (size_t)fc * nu * nx, nu, nx);
+  mv_load(mK, P.KC + (size_t)i * nx * nu, nx, nu);
+  if (t < nx) {
+    S xv;
+    if (i == 0) {
+      xv = (S)x0[t];
+      zout[1 + t] = xv;
+    } else {
+      xv = zout[O.x(i) + t];
+    }
+    vx[t] = xv;
+  }
+  if (t < nu) vd[t] = dbuf[(size_t)i * nu + t];
+  __syncthreads();
+  mv_partial(mK, vx, nx, nu, red1);
+  if (next >= 0) prefetch_fwd(P, dbuf, next, pf);  // after this family's loads were consumed
+  __syncthreads();
+  if (t < nu) zout[ui + t] = mv_sum(red1, nu, t) + vd[t];
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    const int ch = fc + k;
+    mv_partial(mA, vx, nx, nx, red1);
+    mv_partial(mB, vd, nu, nx, red2);
+    if (k + 1 < n) {  // prefetch the next child's matrices
+      mv_load(mA, P.AbC + (size_t)(ch + 1) * nx * nx, nx, nx);
+      mv_load(mB, P.BC + (size_t)(ch + 1) * nu * nx, nu, nx);
+    }
+    __syncthreads();
+    if (t < nx) zout[O.x(ch) + t] = mv_sum(red1, nx, t) + mv_sum(red2, nx, t);
+    __syncthreads();
+  }
+}
+
+template <typename S>
+__global__ void __launch_bounds__(kWG) k_fwd_wg(DevProb<S> P, S* __restrict__ zout,
+                                                const S* __restrict__ dbuf,
+                                                const double* __restrict__ x0, int first) {
+  unsigned pf = 0;
+  fwd_family_wg<S>(P, zout, dbuf, x0, first + blockIdx.x, -1, pf);
+}
+
+// Forward sweep over whole subtrees rooted at stage tc (top-down per subtree).
+template <typename S>
+__global__ void __launch_bounds__(kWG) k_fwd_tail_wg(DevProb<S> P, S* __restrict__ zout,
+                                                     const S* __restrict__ dbuf,
+                                                     const double* __restrict__ x0, int tc,
+                                                     int root_first, int nroots) {
+  __shared__ int lo[kMaxLevels], hi[kMaxLevels];
+  unsigned pf = 0;
+  for (int r = blockIdx.x; r < nroots; r += gridDim.x) {
+    const int levels = subtree_levels(P, root_first + r, tc, lo, hi);
+    for (int l = 0; l < levels; ++l) {
+      const int a = lo[l], b = hi[l];
+      for (int i = a; i < b; ++i) {
+        const int next = (i + 1 < b) ? i + 1 : (l + 1 < levels ? lo[l + 1] : -1);
+        fwd_family_wg<S>(P, zout, dbuf, x0, i, next, pf);
+      }
+    }
+    __syncthreads();  // before the ranges are overwritten
+  }
+  if (P.nn < 0) zout[0] = S(pf);  // never true: keeps the prefetch loads alive
 }
 
 // Sums the per-block statistics into {xi_p, xi_d, omega^2, rz2, re2, cross}.
@@ -648,42 +1078,6 @@ __global__ void k_reduce_stats(const double* __restrict__ partials, int nblk, do
 }
 
 // ---------------------------------------------------------------- launch T
-template <typename S, int T>
-static hipError_t launch_T_team(const Problem& P, const DevProb<S>& D, const S* v, S* Tv,
-                                const double* x0, S* q, S* d, double* partials, double* stats,
-                                hipStream_t st, const S* eta_zero, bool dual) {
-  const Tree& tr = *P.tree;
-  const int tpb = 256 / T;
-  const int VM = (std::max(P.nx, P.nu) + 3) & ~3;
-  const S* z = v;
-  const S* eta = dual ? v + P.nz : eta_zero;
-  S* zout = Tv;
-  S* eout = dual ? Tv + P.nz : nullptr;
-  for (int t = tr.N - 1; t >= 0; --t) {
-    const int first = tr.stage_off[t];
-    const int count = tr.stage_off[t + 1] - first;
-    const int blocks = (count + tpb - 1) / tpb;
-    hipLaunchKernelGGL((k_bwd<S, T>), dim3(blocks), dim3(256), (size_t)tpb * 3 * VM * sizeof(S), st,
-                       D, z, eta, zout, q, d, first, count, VM);
-  }
-  for (int t = 0; t < tr.N; ++t) {
-    const int first = tr.stage_off[t];
-    const int count = tr.stage_off[t + 1] - first;
-    const int blocks = (count + tpb - 1) / tpb;
-    double* pp = partials + (size_t)P.fwd_blk_off[t] * kStats;
-    if (dual)
-      hipLaunchKernelGGL((k_fwd<S, T, true>), dim3(blocks), dim3(256), (size_t)tpb * 5 * VM * sizeof(S),
-                         st, D, z, eta, zout, eout, d, x0, first, count, VM, pp);
-    else
-      hipLaunchKernelGGL((k_fwd<S, T, false>), dim3(blocks), dim3(256), (size_t)tpb * 5 * VM * sizeof(S),
-                         st, D, z, eta, zout, eout, d, x0, first, count, VM, pp);
-  }
-  if (dual)
-    hipLaunchKernelGGL(k_reduce_stats, dim3(1), dim3(256), 0, st, partials, P.fwd_blocks,
-                       (double)D.alpha, stats);
-  return hipGetLastError();
-}
-
 template <typename S>
 static const DevProb<S>& dev_of(const Problem& P);
 template <>
@@ -691,22 +1085,116 @@ const DevProb<double>& dev_of<double>(const Problem& P) { return P.dp64; }
 template <>
 const DevProb<float>& dev_of<float>(const Problem& P) { return P.dp32; }
 
-template <typename S>
-hipError_t launch_T(const Problem& P, const S* v, S* Tv, const double* x0, S* q, S* d,
-                    double* partials, double* stats_dev, hipStream_t st, const S* eta_zero,
-                    bool dual) {
-  const DevProb<S>& D = dev_of<S>(P);
-  switch (P.team) {
-    case 8: return launch_T_team<S, 8>(P, D, v, Tv, x0, q, d, partials, stats_dev, st, eta_zero, dual);
-    case 16: return launch_T_team<S, 16>(P, D, v, Tv, x0, q, d, partials, stats_dev, st, eta_zero, dual);
-    case 32: return launch_T_team<S, 32>(P, D, v, Tv, x0, q, d, partials, stats_dev, st, eta_zero, dual);
-    default: return launch_T_team<S, 64>(P, D, v, Tv, x0, q, d, partials, stats_dev, st, eta_zero, dual);
+template <typename S, int T>
+static void launch_sweeps_team(const Problem& P, const DevProb<S>& D, S* zout, const double* x0,
+                               const S* xbar, const S* ubar, S* q, S* d, hipStream_t st) {
+  const Tree& tr = *P.tree;
+  const int tpb = 256 / T;
+  const int VM = (std::max(P.nx, P.nu) + 3) & ~3;
+  for (int t = tr.N - 1; t >= 0; --t) {
+    const int first = tr.stage_off[t];
+    const int count = tr.stage_off[t + 1] - first;
+    hipLaunchKernelGGL((k_bwd<S, T>), dim3((count + tpb - 1) / tpb), dim3(256),
+                       (size_t)tpb * 3 * VM * sizeof(S), st, D, xbar, ubar, q, d, first, count, VM);
+  }
+  for (int t = 0; t < tr.N; ++t) {
+    const int first = tr.stage_off[t];
+    const int count = tr.stage_off[t + 1] - first;
+    hipLaunchKernelGGL((k_fwd<S, T>), dim3((count + tpb - 1) / tpb), dim3(256),
+                       (size_t)tpb * 2 * VM * sizeof(S), st, D, zout, d, x0, first, count, VM);
   }
 }
+
+template <typename S>
+static void launch_sweeps_wg(const Problem& P, const DevProb<S>& D, S* zout, const double* x0,
+                             const S* xbar, const S* ubar, S* q, S* d, hipStream_t st) {
+  const Tree& tr = *P.tree;
+  const int tc = P.cut;  // stages >= tc are walked by subtree-owning workgroups
+  if (tc < tr.N) {
+    const int roots = tr.stage_off[tc + 1] - tr.stage_off[tc];
+    hipLaunchKernelGGL(k_bwd_tail_wg<S>, dim3(roots), dim3(kWG), 0, st, D, xbar, ubar, q, d, tc,
+                       tr.stage_off[tc], roots);
+  }
+  for (int t = std::min(tc, tr.N) - 1; t >= 0; --t) {
+    const int first = tr.stage_off[t];
+    const int count = tr.stage_off[t + 1] - first;
+    hipLaunchKernelGGL(k_bwd_wg<S>, dim3(count), dim3(kWG), 0, st, D, xbar, ubar, q, d, first);
+  }
+  for (int t = 0; t < std::min(tc, tr.N); ++t) {
+    const int first = tr.stage_off[t];
+    const int count = tr.stage_off[t + 1] - first;
+    hipLaunchKernelGGL(k_fwd_wg<S>, dim3(count), dim3(kWG), 0, st, D, zout, d, x0, first);
+  }
+  if (tc < tr.N) {
+    const int roots = tr.stage_off[tc + 1] - tr.stage_off[tc];
+    hipLaunchKernelGGL(k_fwd_tail_wg<S>, dim3(roots), dim3(kWG), 0, st, D, zout, d, x0, tc,
+                       tr.stage_off[tc], roots);
+  }
+}
+
+template <typename S, int T>
+static void launch_pre(const Problem& P, const DevProb<S>& D, const S* z, const S* eta, S* zout,
+                       S* xbar, S* ubar, S* q, hipStream_t st) {
+  const int tpb = 256 / T;
+  hipLaunchKernelGGL((k_pre<S, T>), dim3((P.tree->nl + tpb - 1) / tpb), dim3(256), 0, st, D, z, eta,
+                     zout, xbar, ubar, q);
+}
+
+template <typename S, int T>
+static void launch_post(const Problem& P, const DevProb<S>& D, const S* z, const S* eta,
+                        const S* zout, S* eout, double* partials, hipStream_t st) {
+  const int tpb = 256 / T;
+  const int VM = (std::max(P.nx, P.nu) + 3) & ~3;
+  hipLaunchKernelGGL((k_post<S, T>), dim3((P.tree->nl + tpb - 1) / tpb), dim3(256),
+                     (size_t)tpb * 3 * VM * sizeof(S), st, D, z, eta, zout, eout, VM, partials);
+}
+
+// Number of statistic records written by the post-pass.
+int post_blocks(const Problem& P) {
+  const int tpb = 256 / P.team_pp;
+  return (P.tree->nl + tpb - 1) / tpb;
+}
+
+template <typename S>
+hipError_t launch_T(const Problem& P, const S* v, S* Tv, const double* x0, S* q, S* d, S* xbar,
+                    S* ubar, double* partials, double* stats_dev, hipStream_t st,
+                    const S* eta_zero, bool dual) {
+  const DevProb<S>& D = dev_of<S>(P);
+  const S* z = v;
+  const S* eta = dual ? v + P.nz : eta_zero;
+  S* zout = Tv;
+  S* eout = dual ? Tv + P.nz : nullptr;
+  switch (P.team_pp) {
+    case 8: launch_pre<S, 8>(P, D, z, eta, zout, xbar, ubar, q, st); break;
+    case 16: launch_pre<S, 16>(P, D, z, eta, zout, xbar, ubar, q, st); break;
+    case 32: launch_pre<S, 32>(P, D, z, eta, zout, xbar, ubar, q, st); break;
+    default: launch_pre<S, 64>(P, D, z, eta, zout, xbar, ubar, q, st); break;
+  }
+  switch (P.team) {
+    case 8: launch_sweeps_team<S, 8>(P, D, zout, x0, xbar, ubar, q, d, st); break;
+    case 16: launch_sweeps_team<S, 16>(P, D, zout, x0, xbar, ubar, q, d, st); break;
+    case 32: launch_sweeps_team<S, 32>(P, D, zout, x0, xbar, ubar, q, d, st); break;
+    case 64: launch_sweeps_team<S, 64>(P, D, zout, x0, xbar, ubar, q, d, st); break;
+    default: launch_sweeps_wg<S>(P, D, zout, x0, xbar, ubar, q, d, st); break;
+  }
+  if (dual) {
+    switch (P.team_pp) {
+      case 8: launch_post<S, 8>(P, D, z, eta, zout, eout, partials, st); break;
+      case 16: launch_post<S, 16>(P, D, z, eta, zout, eout, partials, st); break;
+      case 32: launch_post<S, 32>(P, D, z, eta, zout, eout, partials, st); break;
+      default: launch_post<S, 64>(P, D, z, eta, zout, eout, partials, st); break;
+    }
+    hipLaunchKernelGGL(k_reduce_stats, dim3(1), dim3(256), 0, st, partials, post_blocks(P),
+                       (double)D.alpha, stats_dev);
+  }
+  return hipGetLastError();
+}
 template hipError_t launch_T<double>(const Problem&, const double*, double*, const double*, double*,
-                                     double*, double*, double*, hipStream_t, const double*, bool);
+                                     double*, double*, double*, double*, double*, hipStream_t,
+                                     const double*, bool);
 template hipError_t launch_T<float>(const Problem&, const float*, float*, const double*, float*,
-                                    float*, double*, double*, hipStream_t, const float*, bool);
+                                    float*, float*, float*, double*, double*, hipStream_t, const float*,
+                                    bool);
 
 // ---------------------------------------------------------------- L and L*
 // One thread per family (test entry points; simple and exact).

@@ -14,6 +14,8 @@ constexpr int kMaxDim = 64;
 // Number of FP64 statistics produced per block of the forward sweep:
 // sum r_z^2, sum r_eta^2, sum r_eta.(L r_z), max |xi_p|, max |xi_d|.
 constexpr int kStats = 5;
+// Mapping code of the workgroup-per-family kernels.
+constexpr int kTeamWG = 256;
 
 // Device view of one problem's iteration data in precision S. Node-indexed
 // arrays follow breadth-first order; matrices are stored as the transpose of
@@ -76,19 +78,26 @@ struct Problem {
   // per-problem work buffers (allocated lazily, precision-sized)
   void* work = nullptr;
   size_t work_bytes = 0;
-  // stage block offsets of the forward sweep partial statistics
-  std::vector<int> fwd_blk_off;  // [N+1]
-  int fwd_blocks = 0;
-  int team = 64;                  // lanes per family
+  // lanes per family: 8, 16, 32 or 64 (team kernels), or kTeamWG for one
+  // 256-thread workgroup per family
+  int team = 64;
   int teams_per_block = 4;
+  // first stage walked by subtree-owning workgroups (workgroup mapping only);
+  // N means every stage has its own launch
+  int cut = 0;
+  int team_pp = 64;  // lanes per family of the parallel pre/post passes
+  bool tuned = false;
 };
 
 // ---------------------------------------------------------------- launchers
 // (kernels.hip) All return hipError_t of the last launch.
+// T(v) (or prox_f of z when dual is false): parallel pre-pass, backward and
+// forward sweeps, parallel post-pass with the residual statistics.
 template <typename S>
-hipError_t launch_T(const Problem& P, const S* v, S* Tv, const double* x0, S* q, S* d,
-                    double* partials, double* stats_dev, hipStream_t st, const S* eta_zero,
-                    bool dual);
+hipError_t launch_T(const Problem& P, const S* v, S* Tv, const double* x0, S* q, S* d, S* xbar,
+                    S* ubar, double* partials, double* stats_dev, hipStream_t st,
+                    const S* eta_zero, bool dual);
+int post_blocks(const Problem& P);
 template <typename S>
 hipError_t launch_L(const Problem& P, const S* z, S* eta, hipStream_t st);
 template <typename S>

@@ -1,0 +1,59 @@
+"""Writes tests/golden/oracle_refs.json: reference solutions of the seeded
+workloads computed by the CPU oracle only (nothing here touches the GPU
+path). Run: OMP_NUM_THREADS=1 python tests/golden/make_golden.py [names...]
+
+Entries: V* as s^0 of the returned point and as the exact nested AV@R cost
+of its trajectory (eq. original-problem), the first input u^0 (unique since
+R > 0), the iteration counts, and the settings used.
+"""
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import oracle as O  # noqa: E402
+import spock_gen as G  # noqa: E402
+
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_refs.json")
+
+
+def run(name, inst, method, eps, max_iters=200000):
+    op = O.Problem(inst)
+    s = O.Settings(eps_abs=eps, eps_rel=eps, max_iters=max_iters)
+    t = time.time()
+    res = (O.cp_solve if method == "cp" else O.spock_solve)(op, inst.x0, s)
+    dt = time.time() - t
+    print(f"{name}: {method} eps={eps} {res.status} iters={res.iters} t_evals={res.t_evals} "
+          f"V={res.V_nested:.12g} {dt:.1f}s", flush=True)
+    return {"method": method, "eps": eps, "status": res.status, "iters": res.iters,
+            "t_evals": res.t_evals, "V_s0": res.V_s0, "V_nested": res.V_nested,
+            "u0": res.u0.tolist(), "alpha": op.alpha, "norm_L": op.normL,
+            "xi0": res.xi0, "xi": res.xi, "seconds": dt, "counts": res.counts}
+
+
+JOBS = {
+    "config1_spock_1e-10": lambda: run("config1", G.make_config(1), "spock", 1e-10),
+    "config1_cp_1e-6": lambda: run("config1", G.make_config(1), "cp", 1e-6),
+    "config5_spock_1e-5": lambda: run("config5", G.make_config(5), "spock", 1e-5),
+    "config2_spock_1e-4": lambda: run("config2", G.make_config(2), "spock", 1e-4),
+    "config2_spock_1e-5": lambda: run("config2", G.make_config(2), "spock", 1e-5),
+    "datacentre_N7_nx5_cp_1e-5": lambda: run("datacentre", G.make_datacentre(7, 5), "cp", 1e-5),
+    "datacentre_N7_nx5_spock_1e-5": lambda: run("datacentre", G.make_datacentre(7, 5), "spock", 1e-5),
+}
+
+
+def main(names):
+    refs = json.load(open(OUT)) if os.path.exists(OUT) else {}
+    for n in names or JOBS:
+        refs[n] = JOBS[n]()
+        with open(OUT, "w") as f:
+            json.dump(refs, f, indent=1, sort_keys=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])
