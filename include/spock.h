@@ -55,8 +55,10 @@ enum {
   SPOCK_EUNSUPPORTED = -8 /* nx or nu above 64, or an unsupported mode */
 };
 
-/* spock_info.status: outcome of an iteration, not an error */
-enum { SPOCK_CONVERGED = 0, SPOCK_MAXITER = 1, SPOCK_NUMERICAL = 2 };
+/* spock_info.status: outcome of an iteration, not an error. SPOCK_REJECTED is
+ * reported by spock_solve_batched for an instance whose x0 lies outside its
+ * root box (that instance is skipped, its v_io left untouched). */
+enum { SPOCK_CONVERGED = 0, SPOCK_MAXITER = 1, SPOCK_NUMERICAL = 2, SPOCK_REJECTED = 3 };
 enum { SPOCK_FP64 = 0, SPOCK_FP32 = 1 };
 enum { SPOCK_METHOD_CP = 0, SPOCK_METHOD_SPOCK = 1 };
 
@@ -148,11 +150,17 @@ typedef struct {
 int spock_solve(spock_problem* prob, const double* x0_dev, const spock_settings* s,
                 void* v_io_dev, spock_info* info_host, void* stream);
 
-/* Solves B independent instances (trees may differ) in one persistent launch,
- * one workgroup per instance running Alg. 3 to its own termination. probs[b],
- * x0_dev[b], v_io_dev[b] as in spock_solve; every problem must have the same
- * precision, nx and nu. infos_host[B] receives the per-instance results.
- * Synchronises the stream. */
+/* Solves B independent instances (trees may differ) in one persistent launch
+ * captured in a HIP graph: one 256-thread workgroup per instance runs Alg. 3
+ * (or CP) to its own termination with no host round trip; the lanes of the
+ * workgroup are split into teams, one tree family per team, the team size
+ * picked by timing short runs the first time a batch shape is seen (or fixed
+ * by the environment variable SPOCK_BATCH_TEAM). probs[b], x0_dev[b] and
+ * v_io_dev[b] are as in spock_solve; every problem must have the same
+ * precision, nx and nu. infos_host[B] receives the per-instance results
+ * (seconds is the wall time of the whole call). The library keeps one device
+ * workspace for batched calls (not thread safe). Synchronises the stream.
+ * Errors: SPOCK_EINVAL, SPOCK_EHIP, SPOCK_ENOMEM. */
 int spock_solve_batched(int32_t B, spock_problem* const* probs,
                         const double* const* x0_dev, const spock_settings* s,
                         void* const* v_io_dev, spock_info* infos_host, void* stream);

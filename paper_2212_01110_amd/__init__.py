@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libspock.so")
 SPOCK_OK = 0
 ERRORS = {-1: "SPOCK_EINVAL", -2: "SPOCK_ETREE", -3: "SPOCK_EPROB", -4: "SPOCK_EBOX",
           -5: "SPOCK_EFACTOR", -6: "SPOCK_EHIP", -7: "SPOCK_ENOMEM", -8: "SPOCK_EUNSUPPORTED"}
-STATUS = {0: "converged", 1: "maxiter", 2: "numerical"}
+STATUS = {0: "converged", 1: "maxiter", 2: "numerical", 3: "rejected"}
 FP64, FP32 = 0, 1
 METHOD_CP, METHOD_SPOCK = 0, 1
 

@@ -200,7 +200,7 @@ int upload(Problem& P, const spock_problem_data& d, const std::vector<double>& A
   // sizes (elements)
   const size_t nvec = (size_t)nn * (4 * nx + 3 * nu) + 2 * (size_t)nn + 64;
   const size_t nmat = (size_t)nn * (2 * nx * nx + 2 * nx * nu) + (size_t)nl * (2 * nu * nx + nu * nu + nx * nu);
-  const size_t bytes = (nvec + nmat) * sizeof(S) + 3 * (size_t)nn * sizeof(int) + 64 * 256;
+  const size_t bytes = (nvec + nmat) * sizeof(S) + (3 * (size_t)nn + T.N + 2) * sizeof(int) + 64 * 256;
   std::vector<char> host(bytes, 0);
   void* dmem = nullptr;
   if (hipMalloc(&dmem, bytes) != hipSuccess) return SPOCK_ENOMEM;
@@ -226,6 +226,9 @@ int upload(Problem& P, const spock_problem_data& d, const std::vector<double>& A
   auto fcp = take(nn, int{});
   auto nchp = take(nn, int{});
   auto ancp = take(nn, int{});
+  auto sop = take(T.N + 2, int{});
+  for (int t = 0; t < T.N + 2; ++t) sop.first[t] = T.stage_off[t];
+  P.d_stage_off = sop.second;
   for (int i = 0; i < nn; ++i) {
     fcp.first[i] = T.fc[i];
     nchp.first[i] = T.nch[i];
@@ -1140,9 +1143,193 @@ extern "C" int spock_T(spock_problem* ph, const void* v, const double* x0, void*
              : T_impl<float>(P, static_cast<const float*>(v), x0, static_cast<float*>(Tv), stats, st);
 }
 
+// ============================================================== batched
+namespace {
+
+struct BatchCache {
+  void* work = nullptr;
+  size_t bytes = 0;
+  void* desc = nullptr;
+  size_t desc_bytes = 0;
+  double* infos = nullptr;
+  size_t infos_n = 0;
+  std::vector<std::pair<std::vector<long long>, int>> tuned;  // key -> team
+};
+BatchCache& batch_cache() {
+  static BatchCache c;
+  return c;
+}
+
+template <typename S>
+int batched_impl(int B, spock_problem* const* probs, const double* const* x0, const spock_settings& st,
+                 void* const* vio, spock_info* infos, hipStream_t stream) {
+  BatchCache& C = batch_cache();
+  const Problem& P0 = probs[0]->p;
+  const int nx = P0.nx, nu = P0.nu;
+  const size_t pool = batched_pool_vectors();
+  // workspace: pool vectors + sweep buffers per instance
+  std::vector<size_t> off(B);
+  size_t total = 0;
+  for (int b = 0; b < B; ++b) {
+    const Problem& P = probs[b]->p;
+    off[b] = total;
+    const size_t elems = pool * (size_t)(P.nz + P.neta) + (size_t)P.tree->nn * (2 * nx + 2 * nu);
+    total += (elems * sizeof(S) + 255) & ~size_t(255);
+  }
+  if (C.bytes < total) {
+    if (C.work) (void)hipFree(C.work);
+    C.work = nullptr;
+    C.bytes = 0;
+    if (hipMalloc(&C.work, total) != hipSuccess) return SPOCK_ENOMEM;
+    C.bytes = total;
+  }
+  std::vector<BatchInst<S>> h(B);
+  for (int b = 0; b < B; ++b) {
+    const Problem& P = probs[b]->p;
+    h[b].P = (sizeof(S) == 8) ? *reinterpret_cast<const DevProb<S>*>(&P.dp64)
+                              : *reinterpret_cast<const DevProb<S>*>(&P.dp32);
+    h[b].stage_off = P.d_stage_off;
+    h[b].x0 = x0[b];
+    h[b].vio = static_cast<S*>(vio[b]);
+    h[b].work = reinterpret_cast<S*>(static_cast<char*>(C.work) + off[b]);
+    h[b].nv = P.nz + P.neta;
+  }
+  const size_t dbytes = sizeof(BatchInst<S>) * B;
+  if (C.desc_bytes < dbytes) {
+    if (C.desc) (void)hipFree(C.desc);
+    C.desc = nullptr;
+    C.desc_bytes = 0;
+    if (hipMalloc(&C.desc, dbytes) != hipSuccess) return SPOCK_ENOMEM;
+    C.desc_bytes = dbytes;
+  }
+  if (C.infos_n < (size_t)B * 16) {
+    if (C.infos) (void)hipFree(C.infos);
+    C.infos = nullptr;
+    C.infos_n = 0;
+    if (hipMalloc(&C.infos, sizeof(double) * 16 * B) != hipSuccess) return SPOCK_ENOMEM;
+    C.infos_n = (size_t)B * 16;
+  }
+  HIP_TRY(hipMemcpyAsync(C.desc, h.data(), dbytes, hipMemcpyHostToDevice, stream));
+  BatchSettings bs{st.eps_abs, st.eps_rel, st.max_iters, st.method, st.m, st.max_ls, st.c0, st.c1,
+                   st.c2, st.beta, st.sigma, st.lambda, 1};
+  const int VM = (std::max(nx, nu) + 3) & ~3;
+  const int grid = B;
+  const auto* dev_desc = static_cast<const BatchInst<S>*>(C.desc);
+  // ---- team size: autotuned once per batch shape (short runs, no output)
+  std::vector<long long> key = {nx, nu, (long long)sizeof(S), B};
+  for (int b = 0; b < B; ++b) key.push_back(probs[b]->p.tree->nn);
+  int team = -1;
+  if (const char* env = std::getenv("SPOCK_BATCH_TEAM")) {
+    const int v = std::atoi(env);
+    if (v == 8 || v == 16 || v == 32 || v == 64) team = v;
+  }
+  for (auto& kv : C.tuned)
+    if (team < 0 && kv.first == key) team = kv.second;
+  if (team < 0) {
+    BatchSettings tb = bs;
+    tb.write_out = 0;
+    tb.max_iters = std::min(st.max_iters, 20);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best = 1e30f;
+    for (int cand : {8, 16, 32, 64}) {
+      if ((size_t)(256 / cand) * 3 * VM * sizeof(S) > 48 * 1024) continue;
+      HIP_TRY(hipEventRecord(e0, stream));
+      HIP_TRY(launch_solve_batched<S>(dev_desc, B, tb, cand, VM, C.infos, grid, stream));
+      HIP_TRY(hipEventRecord(e1, stream));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        team = cand;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (team < 0) team = 64;
+    C.tuned.push_back({key, team});
+  }
+  // ---- the persistent launch, captured in a graph
+  hipStream_t cap;
+  HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+  (void)launch_solve_batched<S>(dev_desc, B, bs, team, VM, C.infos, grid, cap);
+  HIP_TRY(hipStreamEndCapture(cap, &graph));
+  HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  HIP_TRY(hipGraphLaunch(exec, stream));
+  std::vector<double> hi((size_t)16 * B);
+  HIP_TRY(hipMemcpyAsync(hi.data(), C.infos, sizeof(double) * 16 * B, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  (void)hipGraphExecDestroy(exec);
+  (void)hipGraphDestroy(graph);
+  (void)hipStreamDestroy(cap);
+  for (int b = 0; b < B; ++b) {
+    const double* r = hi.data() + (size_t)16 * b;
+    spock_info& I = infos[b];
+    I = spock_info{};
+    I.status = (int)r[0];
+    I.iters = (int)r[1];
+    I.t_evals = (int)r[2];
+    I.n_k0 = (int)r[3];
+    I.n_k1 = (int)r[4];
+    I.n_k2 = (int)r[5];
+    I.n_km = (int)r[6];
+    I.n_backtracks = (int)r[7];
+    I.V_s0 = r[8];
+    I.xi0 = r[9];
+    I.xi = r[10];
+    I.V_nested = std::numeric_limits<double>::quiet_NaN();
+    I.mapping = team;
+  }
+  return SPOCK_OK;
+}
+
+}  // namespace
+
 extern "C" int spock_solve_batched(int32_t B, spock_problem* const* probs, const double* const* x0,
                                    const spock_settings* s, void* const* v_io, spock_info* infos,
                                    void* stream) {
-  (void)B; (void)probs; (void)x0; (void)s; (void)v_io; (void)infos; (void)stream;
-  return SPOCK_EUNSUPPORTED;
+  if (B < 1 || !probs || !x0 || !s || !v_io || !infos) return SPOCK_EINVAL;
+  if (s->method != SPOCK_METHOD_CP && s->method != SPOCK_METHOD_SPOCK) return SPOCK_EINVAL;
+  if (s->method == SPOCK_METHOD_SPOCK && (s->m < 1 || s->m > kMaxMem)) return SPOCK_EINVAL;
+  if (!(s->eps_abs >= 0 && s->eps_rel >= 0) || s->max_iters < 0 || s->max_ls < 1) return SPOCK_EINVAL;
+  if (!(s->beta > 0 && s->beta < 1 && s->sigma > 0 && s->sigma < 1 && s->lambda > 0 && s->lambda < 2))
+    return SPOCK_EINVAL;
+  for (int b = 0; b < B; ++b) {
+    if (!probs[b] || !x0[b] || !v_io[b]) return SPOCK_EINVAL;
+    const Problem& P = probs[b]->p;
+    if (P.precision != probs[0]->p.precision || P.nx != probs[0]->p.nx || P.nu != probs[0]->p.nu)
+      return SPOCK_EINVAL;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const auto t0 = std::chrono::steady_clock::now();
+  const int rc = (probs[0]->p.precision == SPOCK_FP64)
+                     ? batched_impl<double>(B, probs, x0, *s, v_io, infos, st)
+                     : batched_impl<float>(B, probs, x0, *s, v_io, infos, st);
+  if (rc) return rc;
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  for (int b = 0; b < B; ++b) {
+    infos[b].seconds = secs;
+    if (s->compute_nested && infos[b].status != 3) {
+      const Problem& P = probs[b]->p;
+      const Tree& T = *P.tree;
+      const size_t nxu = (size_t)T.nn * P.nx + (size_t)T.nl * P.nu;
+      std::vector<double> hv(1 + nxu);
+      if (P.precision == SPOCK_FP64) {
+        HIP_TRY(hipMemcpy(hv.data(), v_io[b], (1 + nxu) * sizeof(double), hipMemcpyDeviceToHost));
+      } else {
+        std::vector<float> hf(1 + nxu);
+        HIP_TRY(hipMemcpy(hf.data(), v_io[b], (1 + nxu) * sizeof(float), hipMemcpyDeviceToHost));
+        for (size_t e = 0; e < hf.size(); ++e) hv[e] = hf[e];
+      }
+      std::vector<double> x(hv.begin() + 1, hv.begin() + 1 + (size_t)T.nn * P.nx);
+      std::vector<double> u(hv.begin() + 1 + (size_t)T.nn * P.nx, hv.end());
+      infos[b].V_nested = nested_cost_host(P, x, u);
+    }
+  }
+  return SPOCK_OK;
 }

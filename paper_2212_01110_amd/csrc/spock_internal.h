@@ -73,6 +73,7 @@ struct Problem {
   // device
   void* dmem = nullptr;
   int* d_fc = nullptr; int* d_nch = nullptr; int* d_anc = nullptr;
+  int* d_stage_off = nullptr;
   DevProb<double> dp64{};
   DevProb<float> dp32{};
   // per-problem work buffers (allocated lazily, precision-sized)
@@ -135,5 +136,29 @@ hipError_t launch_rdot(long long n, const S* v, const S* Tv, const S* w, double*
                        double* out_dev, hipStream_t st);
 
 int dots_blocks(long long n);
+
+// ---------------------------------------------------------------- batched engine
+struct BatchSettings {
+  double eps_abs, eps_rel;
+  int max_iters, method, m, max_ls;
+  double c0, c1, c2, beta, sigma, lambda;
+  int write_out;  // 0: leave v_io untouched (timing runs of the autotuner)
+};
+
+// One instance of a batched solve (device-resident descriptor).
+template <typename S>
+struct BatchInst {
+  DevProb<S> P;
+  const int* stage_off;  // [N+2]
+  const double* x0;      // [nx]
+  S* vio;                // [n_v] warm start in, T(v^k) out
+  S* work;               // pool of vectors + sweep buffers
+  long long nv;
+};
+
+template <typename S>
+hipError_t launch_solve_batched(const BatchInst<S>* insts_dev, int B, const BatchSettings& s, int team,
+                                int VM, double* infos_dev, int grid, hipStream_t st);
+size_t batched_pool_vectors();
 
 }  // namespace spk

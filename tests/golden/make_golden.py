@@ -42,6 +42,9 @@ JOBS = {
     "config5_spock_1e-5": lambda: run("config5", G.make_config(5), "spock", 1e-5),
     "config2_spock_1e-4": lambda: run("config2", G.make_config(2), "spock", 1e-4),
     "config2_spock_1e-5": lambda: run("config2", G.make_config(2), "spock", 1e-5),
+    "config4_b7_spock_1e-6": lambda: run("config4[7]", G.make_batch(4, count=8)[7], "spock", 1e-6),
+    "config4_b2_spock_1e-6": lambda: run("config4[2]", G.make_batch(4, count=8)[2], "spock", 1e-6),
+    "config4_b5_spock_1e-6": lambda: run("config4[5]", G.make_batch(4, count=8)[5], "spock", 1e-6),
     "datacentre_N7_nx5_cp_1e-5": lambda: run("datacentre", G.make_datacentre(7, 5), "cp", 1e-5),
     "datacentre_N7_nx5_spock_1e-5": lambda: run("datacentre", G.make_datacentre(7, 5), "spock", 1e-5),
 }
