@@ -165,6 +165,29 @@ int spock_solve_batched(int32_t B, spock_problem* const* probs,
                         const double* const* x0_dev, const spock_settings* s,
                         void* const* v_io_dev, spock_info* infos_host, void* stream);
 
+/* Gradients of the optimal risk-averse cost V* = s^0 and of the first input
+ * u^0 with respect to x0 and the diagonal cost weights, by implicit
+ * differentiation at the fixed point v* = T(v*) (section 3): the adjoint
+ * w = J_T(v*)' w + g is iterated with the transposed CP operator (projection
+ * Jacobians at the stored pre-prox point, Alg. 2 sweeps with zero root state
+ * for the S1 projection), then the parameter Jacobian of T is applied.
+ *   v_star_dev: [n_v] of the problem precision, the output of spock_solve
+ *   x0_dev: FP64 [nx]; gV: cotangent of V*; gu0_dev: FP64 [nu] cotangent of u^0 or NULL
+ *   grad_x0_dev: FP64 [nx] out; grad_q_dev: FP64 [num_nodes][nx] out or NULL
+ *     (row c = d/d diag(Q^c), row 0 zero); grad_qN_dev: FP64 [num_nodes][nx]
+ *     out or NULL (leaf rows = d/d diag(Q_N^j), other rows zero)
+ *   s->eps_abs: tolerance on ||w_{k+1} - w_k||_inf relative to max(1, ||w||_inf);
+ *   s->max_iters: adjoint iteration cap. info->iters, info->xi report the
+ *   adjoint iterations and last increment; info->status is SPOCK_CONVERGED or
+ *   SPOCK_MAXITER. Synchronises the stream. The gradient is that of the
+ *   fixed point reached; where the solution is not unique (degenerate active
+ *   sets) the adjoint may not converge and info->status says so.
+ * Errors: SPOCK_EINVAL, SPOCK_EHIP, SPOCK_ENOMEM. */
+int spock_backward(spock_problem* prob, const void* v_star_dev, const double* x0_dev, double gV,
+                   const double* gu0_dev, double* grad_x0_dev, double* grad_q_dev,
+                   double* grad_qN_dev, const spock_settings* s, spock_info* info_host,
+                   void* stream);
+
 /* ---------------------------------------------------------------------------
  * Per-operator entry points (same kernels as the solver; used for operator
  * parity). All vectors are device arrays of the problem precision.

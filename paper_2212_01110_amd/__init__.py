@@ -28,7 +28,7 @@ EXPORTED = [
     "spock_tree_create", "spock_tree_destroy", "spock_tree_shape", "spock_problem_factor",
     "spock_problem_destroy", "spock_problem_sizes", "spock_settings_default", "spock_solve",
     "spock_solve_batched", "spock_apply_L", "spock_apply_Lt", "spock_prox_f",
-    "spock_prox_gstar", "spock_T", "spock_version",
+    "spock_prox_gstar", "spock_T", "spock_version", "spock_backward",
 ]
 
 
@@ -98,6 +98,8 @@ def lib():
         L.spock_prox_f.argtypes = [vp, vp, vp, vp, vp]
         L.spock_prox_gstar.argtypes = [vp, vp, vp, vp]
         L.spock_T.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.spock_backward.argtypes = [vp, vp, vp, dbl, vp, vp, vp, vp, ctypes.POINTER(Settings),
+                                     ctypes.POINTER(Info), vp]
         L.spock_version.restype = ctypes.c_char_p
         _lib = L
     return _lib
@@ -211,6 +213,23 @@ class Problem:
     def prox_gstar(self, w, out):
         _check(lib().spock_prox_gstar(self.handle, _ptr(w), _ptr(out), _stream()),
                "spock_prox_gstar")
+
+    def backward(self, v_star, x0, gV=1.0, gu0=None, want_q=True, settings: Settings | None = None):
+        """Gradients of gV * V* + gu0 . u0 with respect to x0, diag(Q) and
+        diag(Q_N) at the solution v_star; returns (grad_x0, grad_q, grad_qN,
+        info) as FP64 device tensors."""
+        import torch
+        s = settings or default_settings(eps_abs=1e-12, max_iters=200000)
+        gx = torch.zeros(self.nx, dtype=torch.float64, device=x0.device)
+        gq = torch.zeros((self.tree.num_nodes, self.nx), dtype=torch.float64, device=x0.device) if want_q else None
+        gqN = torch.zeros_like(gq) if want_q else None
+        info = Info()
+        _check(lib().spock_backward(self.handle, _ptr(v_star), _ptr(x0), float(gV),
+                                    _ptr(gu0) if gu0 is not None else None, _ptr(gx),
+                                    _ptr(gq) if want_q else None, _ptr(gqN) if want_q else None,
+                                    ctypes.byref(s), ctypes.byref(info), _stream()),
+               "spock_backward")
+        return gx, gq, gqN, info.as_dict()
 
     def T(self, v, x0, Tv, want_stats=True):
         st = np.zeros(6) if want_stats else None

@@ -1333,3 +1333,137 @@ extern "C" int spock_solve_batched(int32_t B, spock_problem* const* probs, const
   }
   return SPOCK_OK;
 }
+
+// ============================================================== backward
+namespace {
+
+template <typename S>
+int backward_impl(Problem& P, const S* vstar, const double* x0, double gV, const double* gu0,
+                  double* gx0, double* gq, double* gqN, const spock_settings& s, spock_info& info,
+                  hipStream_t st) {
+  Work<S> W;
+  int rc = ensure_work<S>(P, W);
+  if (rc) return rc;
+  const Tree& T = *P.tree;
+  const long long nz = P.nz, ne = P.neta, nv = nz + ne;
+  const double al = P.alpha;
+  S* Tv = W.pool[0];
+  S* dz = W.pool[1];
+  S* Ldz = W.pool[2];
+  S* b = W.pool[3];
+  S* g = W.pool[4];
+  S* w = W.pool[5];
+  S* wn = W.pool[6];
+  S* lb = W.pool[7];
+  S* cz = W.pool[8];
+  S* la = W.pool[9];
+  S* tz = W.pool[10];
+  S* te = W.pool[11];
+  // pre-prox point of the dual update at v*: b* = eta* + alpha L (2 z+ - z*)
+  HIP_TRY(launch_T<S>(P, vstar, Tv, x0, W.q, W.d, W.xbar, W.ubar, W.partials, W.stats, st, W.eta_zero, true));
+  HIP_TRY(launch_lincomb<S>(nz, dz, 2.0, Tv, -1.0, vstar, st));
+  HIP_TRY(launch_L<S>(P, dz, Ldz, st));
+  HIP_TRY(launch_lincomb<S>(ne, b, 1.0, vstar + nz, al, Ldz, st));
+  // cotangent of v*: gV on s^0, gu0 on u^0
+  HIP_TRY(launch_fill<S>(nv, g, 0.0, st));
+  {
+    std::vector<S> head(1 + (size_t)T.nn * P.nx + P.nu, S(0));
+    HIP_TRY(hipMemcpyAsync(head.data(), g, head.size() * sizeof(S), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    head[0] = (S)gV;
+    if (gu0) {
+      std::vector<double> hu(P.nu);
+      HIP_TRY(hipMemcpy(hu.data(), gu0, P.nu * sizeof(double), hipMemcpyDeviceToHost));
+      const size_t u0 = 1 + (size_t)T.nn * P.nx;  // u^0 follows every x^i
+      for (int k = 0; k < P.nu; ++k) head[u0 + k] = (S)hu[k];
+    }
+    HIP_TRY(hipMemcpyAsync(g, head.data(), head.size() * sizeof(S), hipMemcpyHostToDevice, st));
+  }
+  HIP_TRY(launch_lincomb<S>(nv, w, 1.0, g, 0.0, nullptr, st));
+  S* zeros = W.pool[12];
+  HIP_TRY(launch_fill<S>(nv, zeros, 0.0, st));
+  HIP_TRY(hipMemsetAsync(W.x0_zero, 0, sizeof(double) * kMaxDim, st));
+  HIP_TRY(launch_fill<S>(ne, W.eta_zero, 0.0, st));
+  // one application of the transposed operator: writes lb, tz, cz, la
+  auto partial = [&](const S* wv) -> int {
+    HIP_TRY(launch_jg<S>(P, b, wv + nz, lb, st));                  // lambda_b = J_G w_eta
+    HIP_TRY(launch_Lt<S>(P, lb, tz, st));                          // L* lambda_b
+    HIP_TRY(launch_lincomb<S>(nz, cz, 1.0, wv, 2.0 * al, tz, st)); // c = w_z + 2 alpha L* lambda_b
+    HIP_TRY(launch_T<S>(P, cz, la, W.x0_zero, W.q, W.d, W.xbar, W.ubar, W.partials, W.stats, st,
+                        W.eta_zero, false));                         // J_f c (S1 with x0 = 0, S2)
+    HIP_TRY(launch_copy_elem<S>(la, cz, st));                        // identity on s^0
+    return SPOCK_OK;
+  };
+  const double tol = std::max(s.eps_abs, 1e-15);
+  int k = 0;
+  double diff = 0;
+  info.status = SPOCK_MAXITER;
+  std::vector<double> hd(2);
+  for (; k < s.max_iters; ++k) {
+    rc = partial(w);
+    if (rc) return rc;
+    HIP_TRY(launch_L<S>(P, la, te, st));
+    HIP_TRY(launch_lincomb3<S>(nz, wn, 1.0, la, -al, tz, 1.0, g, st));
+    HIP_TRY(launch_lincomb3<S>(ne, wn + nz, 1.0, lb, -al, te, 1.0, g + nz, st));
+    std::swap(w, wn);
+    if ((k + 1) % 10 == 0) {
+      HIP_TRY(launch_maxdiff<S>(nv, w, wn, W.vpart, W.dots, st));
+      HIP_TRY(launch_maxdiff<S>(nv, w, zeros, W.vpart, W.dots + 1, st));
+      HIP_TRY(hipMemcpyAsync(hd.data(), W.dots, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      diff = hd[0];
+      if (!std::isfinite(diff)) {
+        info.status = SPOCK_NUMERICAL;
+        break;
+      }
+      if (diff <= tol * std::max(1.0, hd[1])) {
+        info.status = SPOCK_CONVERGED;
+        ++k;
+        break;
+      }
+    }
+  }
+  info.iters = k;
+  info.xi = diff;
+  // gradients from the converged adjoint
+  rc = partial(w);
+  if (rc) return rc;
+  S* mu = W.q;
+  HIP_TRY(launch_phiT<S>(P, cz, mu, st));
+  {
+    std::vector<S> hm(P.nx);
+    HIP_TRY(hipMemcpyAsync(hm.data(), mu, P.nx * sizeof(S), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    std::vector<double> out(P.nx);
+    for (int j = 0; j < P.nx; ++j) out[j] = hm[j];
+    HIP_TRY(hipMemcpy(gx0, out.data(), P.nx * sizeof(double), hipMemcpyHostToDevice));
+  }
+  if (gq) HIP_TRY(hipMemsetAsync(gq, 0, sizeof(double) * (size_t)T.nn * P.nx, st));
+  if (gqN) HIP_TRY(hipMemsetAsync(gqN, 0, sizeof(double) * (size_t)T.nn * P.nx, st));
+  if (gq || gqN) HIP_TRY(launch_grad_q<S>(P, vstar, la, lb, gq, gqN, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return SPOCK_OK;
+}
+
+}  // namespace
+
+extern "C" int spock_backward(spock_problem* ph, const void* v_star, const double* x0, double gV,
+                              const double* gu0, double* grad_x0, double* grad_q, double* grad_qN,
+                              const spock_settings* s, spock_info* info, void* stream) {
+  if (!ph || !v_star || !x0 || !grad_x0 || !s || !info || s->max_iters < 1) return SPOCK_EINVAL;
+  Problem& P = ph->p;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const auto t0 = std::chrono::steady_clock::now();
+  spock_info loc{};
+  loc.V_nested = std::numeric_limits<double>::quiet_NaN();
+  loc.mapping = P.team;
+  const int rc = (P.precision == SPOCK_FP64)
+                     ? backward_impl<double>(P, static_cast<const double*>(v_star), x0, gV, gu0, grad_x0,
+                                             grad_q, grad_qN, *s, loc, st)
+                     : backward_impl<float>(P, static_cast<const float*>(v_star), x0, gV, gu0, grad_x0,
+                                            grad_q, grad_qN, *s, loc, st);
+  if (rc) return rc;
+  loc.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  *info = loc;
+  return SPOCK_OK;
+}

@@ -161,4 +161,18 @@ hipError_t launch_solve_batched(const BatchInst<S>* insts_dev, int B, const Batc
                                 int VM, double* infos_dev, int grid, hipStream_t st);
 size_t batched_pool_vectors();
 
+// ---------------------------------------------------------------- adjoint (backward.hip)
+template <typename S>
+hipError_t launch_jg(const Problem& P, const S* b, const S* w, S* out, hipStream_t st);
+template <typename S>
+hipError_t launch_phiT(const Problem& P, const S* cz, S* mu, hipStream_t st);
+template <typename S>
+hipError_t launch_grad_q(const Problem& P, const S* vstar, const S* la, const S* lb, double* gq,
+                         double* gqN, hipStream_t st);
+template <typename S>
+hipError_t launch_maxdiff(long long n, const S* a, const S* b, double* partials, double* out,
+                          hipStream_t st);
+template <typename S>
+hipError_t launch_copy_elem(S* dst, const S* src, hipStream_t st);
+
 }  // namespace spk
