@@ -109,6 +109,8 @@ __device__ void dev_eig_extremes(int n, const double* G, double& lmin, double& l
 }
 
 // ---- the per-instance solver -------------------------------------------------
+// T lanes per family with T >= max(nx, nu): every lane owns one component,
+// so the per-lane vectors of the family steps have a single entry (D = T).
 template <typename S, int T>
 struct BlockSolver {
   const BatchInst<S>& I;
@@ -137,27 +139,28 @@ struct BlockSolver {
   }
   __device__ S* pool(int k) const { return I.work + (size_t)k * I.nv; }
 
-  // Tv = T(v) and the residual statistics of v - T(v)
-  __device__ BStats Teval(const S* v, S* Tv) {
+  // Tv = T(v) and the residual statistics of v - T(v) (one out-of-line copy:
+  // Alg. 3 calls it from several places)
+  __device__ __noinline__ BStats Teval(const S* v, S* Tv) {
     const S* z = v;
     const S* eta = v + P.nz;
     S* zout = Tv;
     S* eout = Tv + P.nz;
     S* mylds = lds_team + (size_t)team * 3 * VM;
-    for (int f = team; f < P.nl; f += nteams) fam_pre_team<S, T>(P, z, eta, zout, xbar, ubar, q, f, lane);
+    for (int f = team; f < P.nl; f += nteams) fam_pre_team<S, T, T>(P, z, eta, zout, xbar, ubar, q, f, lane);
     __syncthreads();
     for (int t = P.N - 1; t >= 0; --t) {
       const int a = I.stage_off[t], b = I.stage_off[t + 1];
-      for (int i = a + team; i < b; i += nteams) fam_bwd_team<S, T>(P, xbar, ubar, q, d, i, lane, mylds, VM);
+      for (int i = a + team; i < b; i += nteams) fam_bwd_team<S, T, T>(P, xbar, ubar, q, d, i, lane, mylds, VM);
       __syncthreads();
     }
     for (int t = 0; t < P.N; ++t) {
       const int a = I.stage_off[t], b = I.stage_off[t + 1];
-      for (int i = a + team; i < b; i += nteams) fam_fwd_team<S, T>(P, zout, d, I.x0, i, lane, mylds, VM);
+      for (int i = a + team; i < b; i += nteams) fam_fwd_team<S, T, T>(P, zout, d, I.x0, i, lane, mylds, VM);
       __syncthreads();
     }
     StatAcc st;
-    for (int f = team; f < P.nl; f += nteams) fam_post_team<S, T>(P, z, eta, zout, eout, f, lane, mylds, VM, st);
+    for (int f = team; f < P.nl; f += nteams) fam_post_team<S, T, T>(P, z, eta, zout, eout, f, lane, mylds, VM, st);
     __syncthreads();
     double o[5];
     blk_stats(st, red, o);
@@ -169,7 +172,7 @@ struct BlockSolver {
     return r;
   }
 
-  __device__ void lincomb(S* out, double a, const S* x, double b, const S* y) {
+  __device__ __noinline__ void lincomb(S* out, double a, const S* x, double b, const S* y) {
     for (long long e = threadIdx.x; e < I.nv; e += kBT) {
       double v = a * (double)x[e];
       if (y) v += b * (double)y[e];
@@ -177,12 +180,13 @@ struct BlockSolver {
     }
     __syncthreads();
   }
-  __device__ void lincomb3(S* out, double a, const S* x, double b, const S* y, double c, const S* w) {
+  __device__ __noinline__ void lincomb3(S* out, double a, const S* x, double b, const S* y, double c,
+                                        const S* w) {
     for (long long e = threadIdx.x; e < I.nv; e += kBT)
       out[e] = (S)(a * (double)x[e] + b * (double)y[e] + c * (double)w[e]);
     __syncthreads();
   }
-  __device__ double rdot(const S* v, const S* Tv, const S* w) {
+  __device__ __noinline__ double rdot(const S* v, const S* Tv, const S* w) {
     double acc[8] = {0};
     for (long long e = threadIdx.x; e < I.nv; e += kBT)
       acc[0] += ((double)v[e] - (double)Tv[e]) * (double)w[e];
@@ -190,7 +194,7 @@ struct BlockSolver {
     return acc[0];
   }
   // M d = (d_z - alpha L* d_eta, d_eta - alpha L d_z), node-local per family
-  __device__ void apply_M(const S* dv, S* Md) {
+  __device__ __noinline__ void apply_M(const S* dv, S* Md) {
     const Off<S> O(P);
     const S al = P.alpha;
     const S* dz = dv;
@@ -268,12 +272,7 @@ struct BlockSolver {
     S* vt = pool(7);
     S* Tvt = pool(8);
     S* spare = pool(9);
-    S* dV[kBMem];
-    S* dR[kBMem];
-    for (int k = 0; k < kBMem; ++k) {
-      dV[k] = pool(10 + k);
-      dR[k] = pool(10 + kBMem + k);
-    }
+    // Anderson columns j: dV(j) = pool(10 + j), dR(j) = pool(10 + kBMem + j)
     // x0 must lie in the root's state box
     bool box_ok = true;
     for (int o = 0; o < P.nx; ++o) box_ok = box_ok && I.x0[o] >= (double)P.xlo[o] && I.x0[o] <= (double)P.xhi[o];
@@ -316,22 +315,37 @@ struct BlockSolver {
               if (!used) slot = c;
             }
           }
-          double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+          // <dR_j, dR_new> (j < nord), <dR_new, dR_new>, <dR_j, r>, <dR_new, r>;
+          // fixed-trip loops keep the accumulators in registers
+          double aG[kBMem] = {0, 0, 0, 0}, aR[kBMem] = {0, 0, 0, 0}, aNN = 0, aNR = 0;
+          const S* oldc[kBMem];
+#pragma unroll
+          for (int j = 0; j < kBMem; ++j) oldc[j] = pool(10 + kBMem + order[j < nord ? j : 0]);
           for (long long e = threadIdx.x; e < nv; e += kBT) {
             const S vv = v[e];
             const S r = vv - Tv[e];
             rcur[e] = r;
             const S dr = r - rprev[e];
-            dV[slot][e] = vv - vprev[e];
-            dR[slot][e] = dr;
-            for (int j = 0; j < nord; ++j) {
-              const double ob = (double)dR[order[j]][e];
-              acc[j] += ob * (double)dr;
-              acc[nord + 1 + j] += ob * (double)r;
+            pool(10 + slot)[e] = vv - vprev[e];
+            pool(10 + kBMem + slot)[e] = dr;
+#pragma unroll
+            for (int j = 0; j < kBMem; ++j) {
+              if (j < nord) {
+                const double ob = (double)oldc[j][e];
+                aG[j] += ob * (double)dr;
+                aR[j] += ob * (double)r;
+              }
             }
-            acc[nord] += (double)dr * (double)dr;
-            acc[2 * nord + 1] += (double)dr * (double)r;
+            aNN += (double)dr * (double)dr;
+            aNR += (double)dr * (double)r;
           }
+          double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+          for (int j = 0; j < nord; ++j) {
+            acc[j] = aG[j];
+            acc[nord + 1 + j] = aR[j];
+          }
+          acc[nord] = aNN;
+          acc[2 * nord + 1] = aNR;
           blk_sum(acc, 2 * nord + 2, red);
           if (threadIdx.x == 0) {
             for (int j = 0; j < nord; ++j) {
@@ -385,7 +399,8 @@ struct BlockSolver {
         }
         for (long long e = threadIdx.x; e < nv; e += kBT) {
           double acc = -(double)rcur[e];
-          for (int j = 0; j < nord; ++j) acc -= gam[j] * ((double)dV[order[j]][e] - (double)dR[order[j]][e]);
+          for (int j = 0; j < nord; ++j)
+            acc -= gam[j] * ((double)pool(10 + order[j])[e] - (double)pool(10 + kBMem + order[j])[e]);
           dir[e] = (S)acc;
         }
         __syncthreads();

@@ -29,11 +29,12 @@ __device__ __forceinline__ S clampv(S v, S lo, S hi) {
   return v < lo ? lo : (v > hi ? hi : v);
 }
 
-// acc[c] += sum_k Mt[k*nout + o] * vin[k], o = lane + c*T (o < nout).
-template <typename S, int T>
-__device__ __forceinline__ void mv_acc(S (&acc)[(kMaxDim + T - 1) / T], const S* __restrict__ Mt,
+// acc[c] += sum_k Mt[k*nout + o] * vin[k], o = lane + c*T (o < nout);
+// D bounds the output dimension (compile-time chunk count C = ceil(D / T)).
+template <typename S, int T, int D = kMaxDim>
+__device__ __forceinline__ void mv_acc(S (&acc)[(D + T - 1) / T], const S* __restrict__ Mt,
                                        int nin, int nout, const S* vin, int lane) {
-  constexpr int C = (kMaxDim + T - 1) / T;
+  constexpr int C = (D + T - 1) / T;
   int k = 0;
   for (; k + 4 <= nin; k += 4) {
     const S v0 = vin[k], v1 = vin[k + 1], v2 = vin[k + 2], v3 = vin[k + 3];
@@ -110,10 +111,10 @@ struct StatAcc {
 // out = w - alpha (shift + proj_SOC(w/alpha - shift)). The vector part is
 // distributed over the team (wv[c] for components o = lane + c*T < len);
 // the two trailing scalars (wa, wb) are held by every lane.
-template <typename S, int T>
+template <typename S, int T, int D = kMaxDim>
 __device__ __forceinline__ void soc_prox(const S* wv, S* outv, int len, S wa, S wb, S& outa,
                                          S& outb, S al, int lane) {
-  constexpr int C = (kMaxDim * 2 + T - 1) / T;
+  constexpr int C = (D * 2 + T - 1) / T;
   const S ia = S(1) / al;
   double part = 0;
 #pragma unroll
@@ -154,12 +155,12 @@ __device__ __forceinline__ void soc_prox(const S* wv, S* outv, int len, S wa, S 
 // wavefront); lane o owns components o, o+T, ... of node vectors.
 
 // xbar, ubar of nonleaf i: (x, u) - alpha (L* eta) on columns x^i, u^i.
-template <typename S, int T>
+template <typename S, int T, int D = kMaxDim>
 __device__ __forceinline__ void fam_xbar_ubar(const DevProb<S>& P, const Off<S>& O,
                                               const S* __restrict__ z, const S* __restrict__ eta,
-                                              int i, int lane, S (&xb)[(kMaxDim + T - 1) / T],
-                                              S (&ub)[(kMaxDim + T - 1) / T]) {
-  constexpr int C = (kMaxDim + T - 1) / T;
+                                              int i, int lane, S (&xb)[(D + T - 1) / T],
+                                              S (&ub)[(D + T - 1) / T]) {
+  constexpr int C = (D + T - 1) / T;
   const int nx = P.nx, nu = P.nu, fc = P.fc[i], n = P.nch[i];
   const S al = P.alpha;
   const long long e1x = O.e1x(i), e1u = O.e1u(i);
@@ -198,7 +199,7 @@ __device__ __forceinline__ S fam_child_q(const DevProb<S>& P, const Off<S>& O, c
 // S2 projection of the z2 block of nonleaf i after the step z - alpha L* eta,
 // and s^0 - alpha at the root. Closed form of the projection on the kernel of
 // G = [aI, -I, 1, -I, -I]: (G G')^{-1} = (I - 11'/(c+n))/c, c = a^2 + 3.
-template <typename S, int T>
+template <typename S, int T, int D = kMaxDim>
 __device__ __forceinline__ void fam_s2(const DevProb<S>& P, const Off<S>& O, const S* __restrict__ z,
                                        const S* __restrict__ eta, S* __restrict__ zout, int i,
                                        int lane) {
@@ -255,17 +256,17 @@ __device__ __forceinline__ void fam_s2(const DevProb<S>& P, const Off<S>& O, con
 // leaf). xp/xo: x+^i and x^i (lane chunks); vu: u+^i in LDS; xc: x+^ch (lane
 // chunks); vr: LDS scratch of 2*VM; gx, gu accumulate the group-2 part of
 // L* r_eta on columns x^i, u^i.
-template <typename S, int T>
+template <typename S, int T, int D = kMaxDim>
 __device__ __forceinline__ void fam_dual_child(const DevProb<S>& P, const Off<S>& O,
                                                const S* __restrict__ z, const S* __restrict__ eta,
                                                const S* __restrict__ zout, S* __restrict__ eout, int i,
-                                               int ch, int lane, const S (&xp)[(kMaxDim + T - 1) / T],
-                                               const S (&xo)[(kMaxDim + T - 1) / T], const S* vu,
-                                               const S (&xc)[(kMaxDim + T - 1) / T], S* vr,
-                                               S (&gx)[(kMaxDim + T - 1) / T],
-                                               S (&gu)[(kMaxDim + T - 1) / T], StatAcc& st) {
-  constexpr int C = (kMaxDim + T - 1) / T;
-  constexpr int C2 = (2 * kMaxDim + T - 1) / T;
+                                               int ch, int lane, const S (&xp)[(D + T - 1) / T],
+                                               const S (&xo)[(D + T - 1) / T], const S* vu,
+                                               const S (&xc)[(D + T - 1) / T], S* vr,
+                                               S (&gx)[(D + T - 1) / T],
+                                               S (&gu)[(D + T - 1) / T], StatAcc& st) {
+  constexpr int C = (D + T - 1) / T;
+  constexpr int C2 = (2 * D + T - 1) / T;
   const int nx = P.nx, nu = P.nu;
   const S al = P.alpha;
   const S ia = S(1) / al;
@@ -297,7 +298,7 @@ __device__ __forceinline__ void fam_dual_child(const DevProb<S>& P, const Off<S>
   const S wa = eta[e2 + nx + nu] + al * S(0.5) * (S(2) * taup - tau);
   const S wb = eta[e2 + nx + nu + 1] + al * S(0.5) * (S(2) * taup - tau);
   S oa, ob;
-  soc_prox<S, T>(wv, ov, nx + nu, wa, wb, oa, ob, al, lane);
+  soc_prox<S, T, D>(wv, ov, nx + nu, wa, wb, oa, ob, al, lane);
   const S rtau = tau - taup;
 #pragma unroll
   for (int c = 0; c < C2; ++c) {
@@ -360,7 +361,7 @@ __device__ __forceinline__ void fam_dual_child(const DevProb<S>& P, const Off<S>
   const S wsa = eta[e3 + 2 * nx] + al * S(0.5) * (S(2) * svp - sv);
   const S wsb = eta[e3 + 2 * nx + 1] + al * S(0.5) * (S(2) * svp - sv);
   S osa, osb;
-  soc_prox<S, T>(wq, oq, nx, wsa, wsb, osa, osb, al, lane);
+  soc_prox<S, T, D>(wq, oq, nx, wsa, wsb, osa, osb, al, lane);
   const S rs = sv - svp;
 #pragma unroll
   for (int c = 0; c < C; ++c) {
@@ -386,17 +387,17 @@ __device__ __forceinline__ void fam_dual_child(const DevProb<S>& P, const Off<S>
 
 // Dual update of group 1 of nonleaf i: y in K* = R^{2n}_+ x R, s - b'y in
 // R_+, (x, u) in the box; columns y^i, s^i, x^i, u^i of L* r_eta.
-template <typename S, int T>
+template <typename S, int T, int D = kMaxDim>
 __device__ __forceinline__ void fam_dual_node(const DevProb<S>& P, const Off<S>& O,
                                               const S* __restrict__ z, const S* __restrict__ eta,
                                               const S* __restrict__ zout, S* __restrict__ eout, int i,
-                                              int lane, const S (&xp)[(kMaxDim + T - 1) / T],
-                                              const S (&xo)[(kMaxDim + T - 1) / T],
-                                              const S (&up)[(kMaxDim + T - 1) / T],
-                                              const S (&uo)[(kMaxDim + T - 1) / T],
-                                              const S (&gx)[(kMaxDim + T - 1) / T],
-                                              const S (&gu)[(kMaxDim + T - 1) / T], StatAcc& st) {
-  constexpr int C = (kMaxDim + T - 1) / T;
+                                              int lane, const S (&xp)[(D + T - 1) / T],
+                                              const S (&xo)[(D + T - 1) / T],
+                                              const S (&up)[(D + T - 1) / T],
+                                              const S (&uo)[(D + T - 1) / T],
+                                              const S (&gx)[(D + T - 1) / T],
+                                              const S (&gu)[(D + T - 1) / T], StatAcc& st) {
+  constexpr int C = (D + T - 1) / T;
   const int nx = P.nx, nu = P.nu, fc = P.fc[i], n = P.nch[i];
   const S al = P.alpha;
   const S ia = S(1) / al;
@@ -484,11 +485,11 @@ __device__ __forceinline__ void block_stats(const StatAcc& st, double* __restric
 // Backward step of nonleaf i by one team (Alg. 2 backward sweep with
 // W = sum_c Abar^c' P^c B^c): d = R~^{-1}(ubar - sum_c B^c' q^c),
 // q = K'(d - ubar) + W d - xbar + sum_c Abar^c' q^c. LDS: 3 VM per team.
-template <typename S, int T>
+template <typename S, int T, int D = kMaxDim>
 __device__ __forceinline__ void fam_bwd_team(const DevProb<S>& P, const S* __restrict__ xbar,
                                              const S* __restrict__ ubar, S* __restrict__ qbuf,
                                              S* __restrict__ dbuf, int i, int lane, S* lds, int VM) {
-  constexpr int C = (kMaxDim + T - 1) / T;
+  constexpr int C = (D + T - 1) / T;
   S* vq = lds;
   S* vg = vq + VM;
   S* vd = vg + VM;
@@ -510,8 +511,8 @@ __device__ __forceinline__ void fam_bwd_team(const DevProb<S>& P, const S* __res
       if (o < nx) vq[o] = qbuf[(size_t)ch * nx + o];
     }
     wave_lds_sync();
-    mv_acc<S, T>(h, P.BR + (size_t)ch * nx * nu, nx, nu, vq, lane);
-    mv_acc<S, T>(sA, P.AbR + (size_t)ch * nx * nx, nx, nx, vq, lane);
+    mv_acc<S, T, D>(h, P.BR + (size_t)ch * nx * nu, nx, nu, vq, lane);
+    mv_acc<S, T, D>(sA, P.AbR + (size_t)ch * nx * nx, nx, nx, vq, lane);
     wave_lds_sync();
   }
 #pragma unroll
@@ -523,7 +524,7 @@ __device__ __forceinline__ void fam_bwd_team(const DevProb<S>& P, const S* __res
   S dv[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) dv[c] = 0;
-  mv_acc<S, T>(dv, P.Rinv + (size_t)i * nu * nu, nu, nu, vg, lane);
+  mv_acc<S, T, D>(dv, P.Rinv + (size_t)i * nu * nu, nu, nu, vg, lane);
   wave_lds_sync();
 #pragma unroll
   for (int c = 0; c < C; ++c) {
@@ -538,8 +539,8 @@ __device__ __forceinline__ void fam_bwd_team(const DevProb<S>& P, const S* __res
   S qi[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) qi[c] = sA[c] - xb[c];
-  mv_acc<S, T>(qi, P.KR + (size_t)i * nu * nx, nu, nx, vg, lane);
-  mv_acc<S, T>(qi, P.WC + (size_t)i * nu * nx, nu, nx, vd, lane);
+  mv_acc<S, T, D>(qi, P.KR + (size_t)i * nu * nx, nu, nx, vg, lane);
+  mv_acc<S, T, D>(qi, P.WC + (size_t)i * nu * nx, nu, nx, vd, lane);
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     const int o = lane + c * T;
@@ -550,11 +551,11 @@ __device__ __forceinline__ void fam_bwd_team(const DevProb<S>& P, const S* __res
 
 // Forward step of nonleaf i by one team (Alg. 2 forward sweep):
 // u = K x + d, x^c = Abar^c x + B^c d; x^0 = x0 at the root. LDS: 2 VM.
-template <typename S, int T>
+template <typename S, int T, int D = kMaxDim>
 __device__ __forceinline__ void fam_fwd_team(const DevProb<S>& P, S* __restrict__ zout,
                                              const S* __restrict__ dbuf, const double* __restrict__ x0,
                                              int i, int lane, S* lds, int VM) {
-  constexpr int C = (kMaxDim + T - 1) / T;
+  constexpr int C = (D + T - 1) / T;
   S* vx = lds;
   S* vd = vx + VM;
   const Off<S> O(P);
@@ -583,7 +584,7 @@ __device__ __forceinline__ void fam_fwd_team(const DevProb<S>& P, S* __restrict_
     }
   }
   wave_lds_sync();
-  mv_acc<S, T>(up, P.KC + (size_t)i * nx * nu, nx, nu, vx, lane);
+  mv_acc<S, T, D>(up, P.KC + (size_t)i * nx * nu, nx, nu, vx, lane);
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     const int o = lane + c * T;
@@ -594,8 +595,8 @@ __device__ __forceinline__ void fam_fwd_team(const DevProb<S>& P, S* __restrict_
     S xc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) xc[c] = 0;
-    mv_acc<S, T>(xc, P.AbC + (size_t)ch * nx * nx, nx, nx, vx, lane);
-    mv_acc<S, T>(xc, P.BC + (size_t)ch * nu * nx, nu, nx, vd, lane);
+    mv_acc<S, T, D>(xc, P.AbC + (size_t)ch * nx * nx, nx, nx, vx, lane);
+    mv_acc<S, T, D>(xc, P.BC + (size_t)ch * nu * nx, nu, nx, vd, lane);
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const int o = lane + c * T;
@@ -607,16 +608,16 @@ __device__ __forceinline__ void fam_fwd_team(const DevProb<S>& P, S* __restrict_
 
 // pre-pass of family i by one team: xbar, ubar; leaf children's q = -xbar;
 // S2 projection of the z2 block; s^0 - alpha at the root.
-template <typename S, int T>
+template <typename S, int T, int D = kMaxDim>
 __device__ __forceinline__ void fam_pre_team(const DevProb<S>& P, const S* __restrict__ z,
                                              const S* __restrict__ eta, S* __restrict__ zout,
                                              S* __restrict__ xbar, S* __restrict__ ubar,
                                              S* __restrict__ qbuf, int i, int lane) {
-  constexpr int C = (kMaxDim + T - 1) / T;
+  constexpr int C = (D + T - 1) / T;
   const Off<S> O(P);
   const int nx = P.nx, nu = P.nu, fc = P.fc[i], n = P.nch[i];
   S xb[C], ub[C];
-  fam_xbar_ubar<S, T>(P, O, z, eta, i, lane, xb, ub);
+  fam_xbar_ubar<S, T, D>(P, O, z, eta, i, lane, xb, ub);
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     const int o = lane + c * T;
@@ -628,17 +629,17 @@ __device__ __forceinline__ void fam_pre_team(const DevProb<S>& P, const S* __res
       for (int o = lane; o < nx; o += T)
         qbuf[(size_t)(fc + k) * nx + o] = fam_child_q<S>(P, O, z, eta, qbuf, fc + k, o);
   }
-  fam_s2<S, T>(P, O, z, eta, zout, i, lane);
+  fam_s2<S, T, D>(P, O, z, eta, zout, i, lane);
 }
 
 // post-pass of family i by one team: dual update and residual statistics.
 // LDS: 3 VM per team.
-template <typename S, int T>
+template <typename S, int T, int D = kMaxDim>
 __device__ __forceinline__ void fam_post_team(const DevProb<S>& P, const S* __restrict__ z,
                                               const S* __restrict__ eta, const S* __restrict__ zout,
                                               S* __restrict__ eout, int i, int lane, S* lds, int VM,
                                               StatAcc& st) {
-  constexpr int C = (kMaxDim + T - 1) / T;
+  constexpr int C = (D + T - 1) / T;
   S* vu = lds;
   S* vr = vu + VM;
   const Off<S> O(P);
@@ -668,9 +669,9 @@ __device__ __forceinline__ void fam_post_team(const DevProb<S>& P, const S* __re
       const int o = lane + c * T;
       xc[c] = (o < nx) ? zout[O.x(ch) + o] : S(0);
     }
-    fam_dual_child<S, T>(P, O, z, eta, zout, eout, i, ch, lane, xp, xo, vu, xc, vr, gx, gu, st);
+    fam_dual_child<S, T, D>(P, O, z, eta, zout, eout, i, ch, lane, xp, xo, vu, xc, vr, gx, gu, st);
   }
-  fam_dual_node<S, T>(P, O, z, eta, zout, eout, i, lane, xp, xo, up, uo, gx, gu, st);
+  fam_dual_node<S, T, D>(P, O, z, eta, zout, eout, i, lane, xp, xo, up, uo, gx, gu, st);
   wave_lds_sync();
 }
 

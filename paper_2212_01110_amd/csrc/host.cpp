@@ -1218,10 +1218,12 @@ int batched_impl(int B, spock_problem* const* probs, const double* const* x0, co
   // ---- team size: autotuned once per batch shape (short runs, no output)
   std::vector<long long> key = {nx, nu, (long long)sizeof(S), B};
   for (int b = 0; b < B; ++b) key.push_back(probs[b]->p.tree->nn);
+  // the block engine needs T >= max(nx, nu) lanes per family
+  const int tmin = next_pow2_team(std::max(nx, nu));
   int team = -1;
   if (const char* env = std::getenv("SPOCK_BATCH_TEAM")) {
     const int v = std::atoi(env);
-    if (v == 8 || v == 16 || v == 32 || v == 64) team = v;
+    if (v == 8 || v == 16 || v == 32 || v == 64) team = std::max(v, tmin);
   }
   for (auto& kv : C.tuned)
     if (team < 0 && kv.first == key) team = kv.second;
@@ -1234,6 +1236,7 @@ int batched_impl(int B, spock_problem* const* probs, const double* const* x0, co
     HIP_TRY(hipEventCreate(&e1));
     float best = 1e30f;
     for (int cand : {8, 16, 32, 64}) {
+      if (cand < tmin) continue;
       if ((size_t)(256 / cand) * 3 * VM * sizeof(S) > 48 * 1024) continue;
       HIP_TRY(hipEventRecord(e0, stream));
       HIP_TRY(launch_solve_batched<S>(dev_desc, B, tb, cand, VM, C.infos, grid, stream));

@@ -69,10 +69,17 @@ def test_batched_cp_iteration_count_matches_oracle():
     assert np.max(np.abs(host(vs[0]) - ref.v)) <= 1e-8 * max(1, np.max(np.abs(ref.v)))
 
 
-@pytest.mark.parametrize("team", ["8", "16", "32", "64"])
-def test_batched_every_team_size(team, monkeypatch):
+# the block engine needs a team of at least max(nx, nu) lanes: 8 serves the
+# nx=2 trees, 16 the nx=10 batch, 32 and 64 the nx=20 batch
+TEAM_CASES = [("8", lambda: SMALL[:3], 8), ("16", lambda: G.make_batch(4, count=3), 16),
+              ("32", lambda: G.make_batch(5, count=3), 32), ("64", lambda: G.make_batch(5, count=3), 64),
+              ("8", lambda: G.make_batch(5, count=2), 32)]
+
+
+@pytest.mark.parametrize("team,mk,expect", TEAM_CASES)
+def test_batched_every_team_size(team, mk, expect, monkeypatch):
     monkeypatch.setenv("SPOCK_BATCH_TEAM", team)
-    insts = G.make_batch(5, count=3)
+    insts = mk()
     probs, x0s, vs = _batch(insts, SP.FP64)
     infos = SP.solve_batched(probs, x0s, vs, SP.default_settings(eps_abs=1e-6, eps_rel=1e-6))
     # single-instance path on the same problems (parity with the oracle is
@@ -81,8 +88,9 @@ def test_batched_every_team_size(team, monkeypatch):
         v = torch.zeros(p.n_v, dtype=torch.float64, device="cuda")
         one = p.solve(x0, v, SP.default_settings(eps_abs=1e-6, eps_rel=1e-6))
         assert info["status"] == "converged" and one["status"] == "converged"
-        assert abs(info["V_s0"] - one["V_s0"]) <= 1e-4 * abs(one["V_s0"])
-        assert info["mapping"] == int(team)
+        assert abs(info["V_s0"] - one["V_s0"]) <= 1e-4 * max(1.0, abs(one["V_s0"]))
+        # a request below max(nx, nu) lanes is raised to the smallest team that fits
+        assert info["mapping"] == expect
 
 
 def test_batched_rejects_x0_outside_box():
