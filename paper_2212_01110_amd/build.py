@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libspock.so")
-SOURCES = ["host.cpp", "kernels.hip", "batched.hip", "backward.hip"]
+SOURCES = ["host.cpp", "kernels.hip", "flow.hip", "batched.hip", "backward.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed FP32 arithmetic disabled for every HIP translation unit

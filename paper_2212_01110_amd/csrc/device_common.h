@@ -29,6 +29,21 @@ __device__ __forceinline__ S clampv(S v, S lo, S hi) {
   return v < lo ? lo : (v > hi ? hi : v);
 }
 
+// Loads and stores of values that other workgroups produce or consume
+// within one launch (C = true): agent-coherent accesses (they bypass the
+// non-coherent caches), so a workgroup publishes them with a plain wait for
+// its stores instead of writing back the whole L2. C = false: plain access.
+template <bool C, typename S>
+__device__ __forceinline__ S ld_c(const S* p) {
+  if constexpr (C) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else return *p;
+}
+template <bool C, typename S>
+__device__ __forceinline__ void st_c(S* p, S v) {
+  if constexpr (C) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else *p = v;
+}
+
 // acc[c] += sum_k Mt[k*nout + o] * vin[k], o = lane + c*T (o < nout);
 // D bounds the output dimension (compile-time chunk count C = ceil(D / T)).
 template <typename S, int T, int D = kMaxDim>
@@ -199,7 +214,7 @@ __device__ __forceinline__ S fam_child_q(const DevProb<S>& P, const Off<S>& O, c
 // S2 projection of the z2 block of nonleaf i after the step z - alpha L* eta,
 // and s^0 - alpha at the root. Closed form of the projection on the kernel of
 // G = [aI, -I, 1, -I, -I]: (G G')^{-1} = (I - 11'/(c+n))/c, c = a^2 + 3.
-template <typename S, int T, int D = kMaxDim>
+template <typename S, int T, int D = kMaxDim, bool CZ = false>
 __device__ __forceinline__ void fam_s2(const DevProb<S>& P, const Off<S>& O, const S* __restrict__ z,
                                        const S* __restrict__ eta, S* __restrict__ zout, int i,
                                        int lane) {
@@ -235,17 +250,17 @@ __device__ __forceinline__ void fam_s2(const DevProb<S>& P, const Off<S>& O, con
       } else {
         const S w = (g - Gs / (cc + S(n))) / cc;
         wsum += (double)w;
-        zout[zb + k] = y1h - a * w;
-        zout[zb + n + k] = y2h + w;
-        zout[zb + 2 * n + 1 + k] = th + w;
-        zout[zb + 3 * n + 1 + k] = sh + w;
+        st_c<CZ>(zout + zb + k, y1h - a * w);
+        st_c<CZ>(zout + zb + n + k, y2h + w);
+        st_c<CZ>(zout + zb + 2 * n + 1 + k, th + w);
+        st_c<CZ>(zout + zb + 3 * n + 1 + k, sh + w);
       }
     }
     if (pass) {
       const S Ws = (S)team_sum<T>(wsum);
       if (lane == 0) {
-        zout[zb + 2 * n] = y3h - Ws;
-        if (i == 0) zout[0] = z[0] - al * es - al;
+        st_c<CZ>(zout + zb + 2 * n, y3h - Ws);
+        if (i == 0) st_c<CZ>(zout, z[0] - al * es - al);
       }
     }
   }
@@ -256,7 +271,7 @@ __device__ __forceinline__ void fam_s2(const DevProb<S>& P, const Off<S>& O, con
 // leaf). xp/xo: x+^i and x^i (lane chunks); vu: u+^i in LDS; xc: x+^ch (lane
 // chunks); vr: LDS scratch of 2*VM; gx, gu accumulate the group-2 part of
 // L* r_eta on columns x^i, u^i.
-template <typename S, int T, int D = kMaxDim>
+template <typename S, int T, int D = kMaxDim, bool CZ = false>
 __device__ __forceinline__ void fam_dual_child(const DevProb<S>& P, const Off<S>& O,
                                                const S* __restrict__ z, const S* __restrict__ eta,
                                                const S* __restrict__ zout, S* __restrict__ eout, int i,
@@ -274,7 +289,7 @@ __device__ __forceinline__ void fam_dual_child(const DevProb<S>& P, const Off<S>
   // ---- group 2: (Q^{1/2} x^i, R^{1/2} u^i, tau/2, tau/2) in SOC + shift
   const long long e2 = O.e2(ch);
   const long long tpos = O.tau(ch);
-  const S tau = z[tpos], taup = zout[tpos];
+  const S tau = z[tpos], taup = ld_c<CZ>(zout + tpos);
   S wv[C2], ov[C2], lz[C2];
 #pragma unroll
   for (int c = 0; c < C2; ++c) {
@@ -330,7 +345,7 @@ __device__ __forceinline__ void fam_dual_child(const DevProb<S>& P, const Off<S>
   // ---- group 3 of a leaf: box on x, (Q_N^{1/2} x, s/2, s/2) in SOC + shift
   const long long e3 = O.e3(ch);
   const long long spos = O.s(ch);
-  const S sv = z[spos], svp = zout[spos];
+  const S sv = z[spos], svp = ld_c<CZ>(zout + spos);
   S wq[C2], oq[C2];
   S rex[C], xin[C];
 #pragma unroll
@@ -387,7 +402,7 @@ __device__ __forceinline__ void fam_dual_child(const DevProb<S>& P, const Off<S>
 
 // Dual update of group 1 of nonleaf i: y in K* = R^{2n}_+ x R, s - b'y in
 // R_+, (x, u) in the box; columns y^i, s^i, x^i, u^i of L* r_eta.
-template <typename S, int T, int D = kMaxDim>
+template <typename S, int T, int D = kMaxDim, bool CZ = false>
 __device__ __forceinline__ void fam_dual_node(const DevProb<S>& P, const Off<S>& O,
                                               const S* __restrict__ z, const S* __restrict__ eta,
                                               const S* __restrict__ zout, S* __restrict__ eout, int i,
@@ -404,22 +419,22 @@ __device__ __forceinline__ void fam_dual_node(const DevProb<S>& P, const Off<S>&
   const long long zb = O.z2(i);
   const long long e1 = O.e1(i);
   const long long spos = O.s(i);
-  const S si = z[spos], sip = zout[spos];
+  const S si = z[spos], sip = ld_c<CZ>(zout + spos);
   double bw = 0, bry = 0;
   for (int k = lane; k < n; k += T) {
     const S pk = P.p[fc + k];
-    const S y1 = z[zb + k], y1p = zout[zb + k];
+    const S y1 = z[zb + k], y1p = ld_c<CZ>(zout + zb + k);
     bw += (double)(pk * (S(2) * y1p - y1));
     bry += (double)(pk * (y1 - y1p));
   }
-  const S y3 = z[zb + 2 * n], y3p = zout[zb + 2 * n];
+  const S y3 = z[zb + 2 * n], y3p = ld_c<CZ>(zout + zb + 2 * n);
   const S bW = (S)team_sum<T>(bw) + (S(2) * y3p - y3);
   const S bR = (S)team_sum<T>(bry) + (y3 - y3p);
   const S ws = eta[e1 + 2 * n + 1] + al * ((S(2) * sip - si) - bW);
   const S es_new = ws < S(0) ? ws : S(0);
   const S res_ = eta[e1 + 2 * n + 1] - es_new;
   for (int k = lane; k < 2 * n + 1; k += T) {
-    const S y = z[zb + k], yp = zout[zb + k];
+    const S y = z[zb + k], yp = ld_c<CZ>(zout + zb + k);
     const S w = eta[e1 + k] + al * (S(2) * yp - y);
     const S ep = (k < 2 * n) ? (w < S(0) ? w : S(0)) : S(0);
     eout[e1 + k] = ep;
@@ -634,7 +649,7 @@ __device__ __forceinline__ void fam_pre_team(const DevProb<S>& P, const S* __res
 
 // post-pass of family i by one team: dual update and residual statistics.
 // LDS: 3 VM per team.
-template <typename S, int T, int D = kMaxDim>
+template <typename S, int T, int D = kMaxDim, bool CZ = false>
 __device__ __forceinline__ void fam_post_team(const DevProb<S>& P, const S* __restrict__ z,
                                               const S* __restrict__ eta, const S* __restrict__ zout,
                                               S* __restrict__ eout, int i, int lane, S* lds, int VM,
@@ -651,11 +666,11 @@ __device__ __forceinline__ void fam_post_team(const DevProb<S>& P, const S* __re
     const int o = lane + c * T;
     xp[c] = xo[c] = up[c] = uo[c] = gx[c] = gu[c] = 0;
     if (o < nx) {
-      xp[c] = zout[O.x(i) + o];
+      xp[c] = ld_c<CZ>(zout + O.x(i) + o);
       xo[c] = z[O.x(i) + o];
     }
     if (o < nu) {
-      up[c] = zout[ui + o];
+      up[c] = ld_c<CZ>(zout + ui + o);
       uo[c] = z[ui + o];
       vu[o] = up[c];
     }
@@ -667,11 +682,11 @@ __device__ __forceinline__ void fam_post_team(const DevProb<S>& P, const S* __re
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const int o = lane + c * T;
-      xc[c] = (o < nx) ? zout[O.x(ch) + o] : S(0);
+      xc[c] = (o < nx) ? ld_c<CZ>(zout + O.x(ch) + o) : S(0);
     }
-    fam_dual_child<S, T, D>(P, O, z, eta, zout, eout, i, ch, lane, xp, xo, vu, xc, vr, gx, gu, st);
+    fam_dual_child<S, T, D, CZ>(P, O, z, eta, zout, eout, i, ch, lane, xp, xo, vu, xc, vr, gx, gu, st);
   }
-  fam_dual_node<S, T, D>(P, O, z, eta, zout, eout, i, lane, xp, xo, up, uo, gx, gu, st);
+  fam_dual_node<S, T, D, CZ>(P, O, z, eta, zout, eout, i, lane, xp, xo, up, uo, gx, gu, st);
   wave_lds_sync();
 }
 

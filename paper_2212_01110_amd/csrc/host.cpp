@@ -337,7 +337,7 @@ int upload(Problem& P, const spock_problem_data& d, const std::vector<double>& A
 void set_mapping(Problem& P, int team, int cut) {
   const Tree& T = *P.tree;
   P.team = team;
-  P.teams_per_block = (team == kTeamWG) ? 1 : 256 / team;
+  P.teams_per_block = (team == kTeamWG || team == kTeamFlow) ? 1 : 256 / team;
   P.cut = (team == kTeamWG) ? std::max(cut, std::max(0, T.N - 64)) : T.N;
   if (P.cut > T.N) P.cut = T.N;
 }
@@ -352,7 +352,7 @@ int default_cut(const Tree& T) {
 
 // LDS bytes per block of a mapping (team kernels size their LDS at launch).
 size_t mapping_lds(const Problem& P, int team, size_t elem) {
-  if (team == kTeamWG) return 0;
+  if (team == kTeamWG || team == kTeamFlow) return 0;
   const int VM = (std::max(P.nx, P.nu) + 3) & ~3;
   return (size_t)(256 / team) * 5 * VM * elem + kStats * 256 * sizeof(double);
 }
@@ -563,7 +563,7 @@ extern "C" int spock_problem_factor(const spock_tree* th, const spock_problem_da
   if (mapping_lds(P, team, elem) > 64 * 1024) team = kTeamWG;
   if (const char* env = std::getenv("SPOCK_TEAM")) {
     const int v = std::atoi(env);
-    if (v == 8 || v == 16 || v == 32 || v == 64 || v == kTeamWG) {
+    if (v == 8 || v == 16 || v == 32 || v == 64 || v == kTeamWG || v == kTeamFlow) {
       team = mapping_lds(P, v, elem) > 64 * 1024 ? kTeamWG : v;
       P.tuned = true;  // fixed by the caller's environment
     }
@@ -586,6 +586,7 @@ extern "C" int spock_problem_destroy(spock_problem* p) {
   if (!p) return SPOCK_EINVAL;
   if (p->p.dmem) (void)hipFree(p->p.dmem);
   if (p->p.work) (void)hipFree(p->p.work);
+  if (p->p.flow.mem) (void)hipFree(p->p.flow.mem);
   delete p;
   return SPOCK_OK;
 }
@@ -641,6 +642,54 @@ struct Work {
   double* host_stats = nullptr;
 };
 
+// Sizes and allocates the state of the dataflow form of T for precision S:
+// children per LDS chunk (largest count whose LDS stays within the budget,
+// at least one), resident workgroups from the occupancy of the kernel, and
+// the flag / chunk arrays (zeroed once; flags are epoch-tagged). The error
+// word is cleared on every call (each API call starts clean).
+template <typename S>
+int ensure_flow(Problem& P, int occ = 0) {
+  FlowState& F = P.flow;
+  const Tree& T = *P.tree;
+  if (occ == 0) occ = F.mem ? F.occ : 2;
+  if (const char* env = std::getenv("SPOCK_FLOW_OCC")) occ = std::atoi(env) >= 4 ? 4 : 2;
+  if (F.mem && F.elem == (int)sizeof(S) && F.occ == occ) {
+    if (hipMemset(F.err, 0, sizeof(unsigned)) != hipSuccess) return SPOCK_EHIP;
+    return SPOCK_OK;
+  }
+  if (F.mem) (void)hipFree(F.mem);
+  F = FlowState{};
+  int maxch = 1;
+  for (int i = 0; i < T.nl; ++i) maxch = std::max(maxch, T.nch[i]);
+  int budget = 40 * 1024;
+  if (const char* env = std::getenv("SPOCK_FLOW_LDS")) budget = std::max(4096, std::atoi(env));
+  int nc = std::min(maxch, 8);
+  while (nc > 1 && flow_lds_bytes(P.nx, P.nu, nc, (int)sizeof(S)) > budget) --nc;
+  const int lds = flow_lds_bytes(P.nx, P.nu, nc, (int)sizeof(S));
+  int dev = 0, ncu = 0, coop = 0, nb = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return SPOCK_EHIP;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return SPOCK_EHIP;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess) return SPOCK_EHIP;
+  if (lds <= 64 * 1024 &&
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, flow_kernel<S>(occ), 256, (size_t)lds) != hipSuccess)
+    return SPOCK_EHIP;
+  const int nr = (T.nl + 255) / 256;
+  const size_t bytes = 256 + sizeof(unsigned) * (size_t)(T.nl + nr + 64) + sizeof(double) * (size_t)nr * kStats;
+  if (hipMalloc(&F.mem, bytes) != hipSuccess) return SPOCK_ENOMEM;
+  if (hipMemset(F.mem, 0, bytes) != hipSuccess) return SPOCK_EHIP;
+  char* b = static_cast<char*>(F.mem);
+  F.part2 = reinterpret_cast<double*>(b);
+  b += (sizeof(double) * (size_t)nr * kStats + 255) & ~size_t(255);
+  F.err = reinterpret_cast<unsigned*>(b);
+  F.flag2 = F.err + 64;
+  F.flag = F.flag2 + nr;
+  F.nc = nc;
+  F.occ = occ;
+  F.elem = (int)sizeof(S);
+  F.grid = (coop && lds <= 64 * 1024) ? nb * ncu : 0;
+  return SPOCK_OK;
+}
+
 template <typename S>
 int ensure_work(Problem& P, Work<S>& W) {
   const Tree& T = *P.tree;
@@ -688,6 +737,13 @@ int ensure_work(Problem& P, Work<S>& W) {
   W.x0_zero = reinterpret_cast<double*>(take(sizeof(double) * kMaxDim));
   for (int k = 0; k < 10 + 2 * kMaxMem; ++k) W.pool[k] = reinterpret_cast<S*>(take(sizeof(S) * (size_t)nv));
   if (off > P.work_bytes) return SPOCK_ENOMEM;
+  if (P.team == kTeamFlow) {
+    const int rc = ensure_flow<S>(P);
+    if (rc) return rc;
+    // the dataflow form does not fit (LDS) or cannot be launched resident:
+    // per-stage workgroup launches instead
+    if (P.flow.grid <= 0) set_mapping(P, kTeamWG, default_cut(*P.tree));
+  }
   return SPOCK_OK;
 }
 
@@ -707,6 +763,10 @@ int autotune(Problem& P, hipStream_t st) {
   HIP_TRY(hipEventCreate(&e1));
   const Tree& T = *P.tree;
   std::vector<std::pair<int, int>> cands = {{8, T.N}, {16, T.N}, {32, T.N}, {64, T.N}, {kTeamWG, T.N}};
+  // dataflow form at both register budgets (the cut field carries the
+  // budget: 2 or 4 wavefronts per SIMD)
+  if (ensure_flow<S>(P, 2) == SPOCK_OK && P.flow.grid > 0) cands.push_back({kTeamFlow, 2});
+  if (ensure_flow<S>(P, 4) == SPOCK_OK && P.flow.grid > 0) cands.push_back({kTeamFlow, 4});
   int ncut = 0;
   for (int t = std::max(0, T.N - 64); t < T.N && ncut < 3; ++t)
     if (T.stage_off[t + 1] - T.stage_off[t] >= 128) {
@@ -717,6 +777,7 @@ int autotune(Problem& P, hipStream_t st) {
   std::pair<int, int> best_map = {P.team, P.cut};
   for (auto c : cands) {
     if (mapping_lds(P, c.first, sizeof(S)) > 64 * 1024) continue;
+    if (c.first == kTeamFlow && (ensure_flow<S>(P, c.second) != SPOCK_OK || P.flow.grid <= 0)) continue;
     set_mapping(P, c.first, c.second);
     HIP_TRY(launch_T<S>(P, W.pool[0], W.pool[1], W.x0_zero, W.q, W.d, W.xbar, W.ubar, W.partials, W.stats, st,
                         W.eta_zero, true));
@@ -735,6 +796,7 @@ int autotune(Problem& P, hipStream_t st) {
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  if (best_map.first == kTeamFlow && ensure_flow<S>(P, best_map.second) != SPOCK_OK) return SPOCK_EHIP;
   set_mapping(P, best_map.first, best_map.second);
   P.tuned = true;
   return SPOCK_OK;

@@ -535,6 +535,7 @@ hipError_t launch_T(const Problem& P, const S* v, S* Tv, const double* x0, S* q,
   const S* eta = dual ? v + P.nz : eta_zero;
   S* zout = Tv;
   S* eout = dual ? Tv + P.nz : nullptr;
+  if (P.team == kTeamFlow) return launch_T_flow<S>(P, D, z, eta, zout, eout, x0, q, d, partials, stats_dev, dual, st);
   switch (P.team_pp) {
     case 8: launch_pre<S, 8>(P, D, z, eta, zout, xbar, ubar, q, st); break;
     case 16: launch_pre<S, 16>(P, D, z, eta, zout, xbar, ubar, q, st); break;

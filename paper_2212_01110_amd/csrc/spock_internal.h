@@ -16,6 +16,8 @@ constexpr int kMaxDim = 64;
 constexpr int kStats = 5;
 // Mapping code of the workgroup-per-family kernels.
 constexpr int kTeamWG = 256;
+// Mapping code of the one-launch dataflow form of T (flow.hip).
+constexpr int kTeamFlow = 512;
 
 // Device view of one problem's iteration data in precision S. Node-indexed
 // arrays follow breadth-first order; matrices are stored as the transpose of
@@ -61,6 +63,21 @@ struct DevArrays {
   size_t bytes = 0;
 };
 
+// Device state of the dataflow form of T: completion flags per family and
+// per statistics chunk, an error word raised by a bounded wait that gave up,
+// and the chunk sums. Flags are never cleared (epoch-tagged values).
+struct FlowState {
+  void* mem = nullptr;
+  unsigned* flag = nullptr;   // [nl]
+  unsigned* flag2 = nullptr;  // [nr]
+  unsigned* err = nullptr;    // [1]
+  double* part2 = nullptr;    // [nr][kStats]
+  int nc = 1;                 // children per LDS chunk
+  int grid = 0;               // resident workgroups (0: form unavailable)
+  int occ = 2;                // register budget: 2 or 4 wavefronts per SIMD
+  int elem = 0;               // element size the state was sized for
+};
+
 struct Problem {
   const Tree* tree = nullptr;
   int precision = SPOCK_FP64;
@@ -88,6 +105,8 @@ struct Problem {
   int cut = 0;
   int team_pp = 64;  // lanes per family of the parallel pre/post passes
   bool tuned = false;
+  FlowState flow;
+  mutable unsigned flow_epoch = 1;  // launches of the dataflow form so far
 };
 
 // ---------------------------------------------------------------- launchers
@@ -99,6 +118,14 @@ hipError_t launch_T(const Problem& P, const S* v, S* Tv, const double* x0, S* q,
                     S* ubar, double* partials, double* stats_dev, hipStream_t st,
                     const S* eta_zero, bool dual);
 int post_blocks(const Problem& P);
+// Dataflow form (flow.hip): one persistent launch per T.
+template <typename S>
+hipError_t launch_T_flow(const Problem& P, const DevProb<S>& D, const S* z, const S* eta, S* zout, S* eout,
+                         const double* x0, S* q, S* d, double* partials, double* stats, bool dual,
+                         hipStream_t st);
+int flow_lds_bytes(int nx, int nu, int nc, int elem);
+template <typename S>
+const void* flow_kernel(int occ);
 template <typename S>
 hipError_t launch_L(const Problem& P, const S* z, S* eta, hipStream_t st);
 template <typename S>

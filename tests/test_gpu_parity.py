@@ -233,12 +233,17 @@ MAP_CASES = ["config2", "b3-1-2", "b2x3-nx64", "b5-wide", "config1"]
 
 
 @pytest.mark.parametrize("prec", list(FP))
-@pytest.mark.parametrize("mapping", ["8", "16", "32", "64", "256", "256c0", "256c1", "256c2"])
+@pytest.mark.parametrize("mapping", ["8", "16", "32", "64", "256", "256c0", "256c1", "256c2", "512", "512n1"])
 @pytest.mark.parametrize("name", MAP_CASES)
 def test_T_every_mapping(name, mapping, prec, monkeypatch):
-    # team sizes 8..64, one workgroup per family with per-stage launches, and
-    # subtree-owning workgroups below cut stage 0, 1 or 2
+    # team sizes 8..64, one workgroup per family with per-stage launches,
+    # subtree-owning workgroups below cut stage 0, 1 or 2, and the one-launch
+    # dataflow form (512; 512n1 with an LDS budget of one child per chunk, so
+    # families with several children take several chunks)
     team, _, cut = mapping.partition("c")
+    if team.startswith("512"):
+        team, _, _ = team.partition("n")
+        monkeypatch.setenv("SPOCK_FLOW_LDS", "4096" if mapping.endswith("n1") else "40960")
     monkeypatch.setenv("SPOCK_TEAM", team)
     monkeypatch.setenv("SPOCK_CUT", cut if cut else "1000")
     inst = CASES[name]
@@ -262,3 +267,42 @@ def test_T_every_mapping(name, mapping, prec, monkeypatch):
     gp.prox_f(vt[: op.lay.n_z].contiguous(), x0, zo)
     reff = O.prox_f(op.lay, op.inst, op.fac, vin[: op.lay.n_z], op.alpha, op.inst.x0)
     assert relerr(host(zo), reff) <= 50 * tol
+
+
+@pytest.mark.parametrize("prec", list(FP))
+def test_flow_form_repeated_launches(prec, monkeypatch):
+    # the dataflow form tags its completion flags with a launch epoch: back to
+    # back launches on the same problem (T, prox_f, T) must each be exact
+    monkeypatch.setenv("SPOCK_TEAM", "512")
+    inst = CASES["b3-1-2"]
+    gp, op = build(inst, FP[prec][0])
+    tol = FP[prec][1]
+    dt = gp.torch_dtype
+    x0 = dev(op.inst.x0, torch.float64)
+    rng = np.random.default_rng(77)
+    for rep in range(4):
+        v = rng.standard_normal(op.lay.n_v)
+        vt = dev(v, dt)
+        Tv = torch.zeros_like(vt)
+        st = gp.T(vt, x0, Tv)
+        ref = O.T_apply(op, host(vt), op.inst.x0)
+        assert relerr(host(Tv), ref) <= 50 * tol, rep
+        assert np.isfinite(st["omega2"])
+        zo = torch.zeros(op.lay.n_z, dtype=dt, device="cuda")
+        gp.prox_f(vt[: op.lay.n_z].contiguous(), x0, zo)
+        reff = O.prox_f(op.lay, op.inst, op.fac, host(vt)[: op.lay.n_z], op.alpha, op.inst.x0)
+        assert relerr(host(zo), reff) <= 50 * tol, rep
+
+
+@pytest.mark.parametrize("method", ["cp", "spock"])
+def test_flow_form_solve_config1(method, monkeypatch):
+    monkeypatch.setenv("SPOCK_TEAM", "512")
+    inst = G.make_config(1)
+    op = O.Problem(inst)
+    ref = O.spock_solve(op, inst.x0, O.Settings(eps_abs=1e-10, eps_rel=1e-10))
+    gp = SP.Problem.from_instance(inst, precision=SP.FP64, alpha=op.alpha)
+    x0 = dev(inst.x0, torch.float64)
+    v = torch.zeros(gp.n_v, dtype=torch.float64, device="cuda")
+    info = gp.solve(x0, v, SP.default_settings(eps_abs=1e-9, eps_rel=1e-9, method=method))
+    assert info["status"] == "converged" and info["mapping"] == 512
+    assert abs(info["V_s0"] - ref.V_s0) <= 1e-6 * max(1, abs(ref.V_s0))
