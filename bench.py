@@ -1,16 +1,21 @@
 """Benchmark of the SPOCK hot path on one MI355X.
 
-A step is one full solve of the workload to xi <= max(1e-4, 1e-4 xi_0)
-(section 3 termination) from a cold start: every evaluation of the CP
-operator T (stage sweeps with fused L, L*, proximal maps and residual
-statistics), the Anderson Gram/direction kernels and the SuperMann line
-search. value = evaluations of T (= CP iterations = calls of L) per second
-over the timed solves; ms_per_step = time to residual.
+Workload: the 20 776-node scenario tree (n_x = 50, n_u = 20, N = 15,
+branching 3 for 7 stages, 2187 scenarios), FP32 bulk iterations with FP64
+factorisation, Anderson solve and residual statistics. A step is one SPOCK
+iteration (Alg. 3): the evaluations of the CP operator T (pre-pass, both
+Alg. 2 sweeps, dual update, residual statistics), the Anderson
+Gram/direction kernels and the SuperMann line-search. K steps are timed as
+one solve capped at K iterations from a cold start (v = 0); value = T
+evaluations per second (= CP iterations = calls of L, the paper's count).
 
-roofline: the CP operator T (its backward and forward stage kernels) timed
-with HIP events on the library's stream, against the algorithmic bytes of one
-T; cpu_baseline: the FP64 CPU oracle on a bounded number of T evaluations of
-the same workload.
+roofline: the dominant kernel (the sweeps of T, one launch per evaluation in
+the dataflow form) timed with HIP events recorded by the library on its own
+stream, against its algorithmic bytes. cpu_baseline: the FP64 oracle timed on
+a bounded number of T evaluations (with residual statistics) of the same
+workload. The same JSON line carries the time-to-residual results of the
+smaller workloads: 223-node tree FP64 vs FP32, and the 512-instance batch in
+FP32 from a warm start vs the plain FP64 path.
 """
 from __future__ import annotations
 
@@ -25,51 +30,66 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
-METRIC = ("time-to-residual-1e-4 & CP iters/s, batched FP32 vs plain FP64; achieved HBM GB/s")
+METRIC = "time-to-residual-1e-4 & CP iters/s, batched FP32 vs plain FP64; achieved HBM GB/s"
 HBM_PEAK_GBS = 8000.0
+NAMES = {1: "15-node binary tree nx2 nu1 N3 (AV@R a=0.5)",
+         2: "223-node tree nx20 nu10 N10 (branching 2 for 5 stages)",
+         3: "20776-node tree nx50 nu20 N15 (branching 3 for 7 stages, 2187 scenarios)",
+         5: "95-node tree nx20 nu10 N8 (branching 2 for 4 stages)"}
 
 
-def algorithmic_bytes_T(inst, itemsize):
-    """Bytes one evaluation of T must move: every per-edge and per-node
-    factor matrix once per sweep that uses it (Abar and B in both sweeps, K in
-    both, R~^{-1} and W in the backward sweep), v read once, T(v) written
-    once, the sweep intermediates q and d written and read once, and the
-    per-node data of L and the boxes read once."""
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def tree_counts(inst):
     anc = np.asarray(inst.anc)
     nn = anc.shape[0]
-    nx, nu = inst.nx, inst.nu
     nch = np.bincount(anc[1:], minlength=nn)
     nl = int(np.sum(nch > 0))
-    nleaf = nn - nl
+    return nn, nl, nn - nl
+
+
+def algorithmic_elems_sweeps(inst):
+    """Elements both Alg. 2 sweeps of one T must move: every factor matrix
+    once per sweep that uses it (Abar^c, B^c in both; K in both; R~^{-1} and
+    W = sum_c Abar^c' P^c B^c in the backward sweep), xbar/ubar read, q and d
+    written once and read once, x^i read and u^i, x^c written in the forward
+    sweep."""
+    nn, nl, _ = tree_counts(inst)
+    nx, nu = inst.nx, inst.nu
+    mats = 2 * (nn - 1) * (nx * nx + nx * nu) + nl * (2 * nx * nu + nu * nu + nx * nu)
+    bwd_vec = nl * (nx + nu) + nl * (nx + nu) + (nn - 1) * nx        # xbar,ubar; q,d out; children q in
+    fwd_vec = nl * (nu + nx) + nl * nu + (nn - 1) * nx               # d, x^i in; u, x^c out
+    return int(mats + bwd_vec + fwd_vec)
+
+
+def algorithmic_elems_T(inst):
+    """Elements one whole evaluation of T must move: the sweeps above, plus v
+    read once and T(v) written once, and the per-node data of L and the
+    boxes read once."""
+    nn, nl, nleaf = tree_counts(inst)
+    nx, nu = inst.nx, inst.nu
     n_z = 1 + nn * nx + nl * nu + 4 * (nn - 1) + nl
     n_eta = 2 * (nn - 1) + 2 * nl + nl * (nx + nu) + (nn - 1) * (nx + nu + 2) + nleaf * (2 * nx + 2)
-    mats = (nn - 1) * (2 * nx * nx + 2 * nx * nu) + nl * (3 * nx * nu + nu * nu)
-    vecs = 2 * (n_z + n_eta) + 2 * nl * (nx + nu)
     node = (nn - 1) * (nx + nu) + nleaf * nx + nn * 2 * nx + nl * 2 * nu + 2 * nn
-    return int((mats + vecs + node) * itemsize), int(mats + vecs + node)
+    return algorithmic_elems_sweeps(inst) + 2 * (n_z + n_eta) + node
 
 
-def build_workload(cfg):
-    import spock_gen as G
-    if cfg in (1, 2, 3, 5):
-        return G.make_config(cfg)
-    raise SystemExit(f"bench: config {cfg} is not a single-instance workload")
-
-
-def cpu_baseline(inst, budget_s=20.0):
-    """FP64 oracle T evaluations (+ residual statistics) on the same workload
-    until the time budget is spent; returns CP iterations per second."""
+def cpu_baseline(inst, alpha, budget_s):
+    """FP64 oracle: T evaluations with residual statistics from v = 0 until
+    the time budget is spent (the step size is taken as given, so the
+    oracle's exact ||L|| is not part of the sample)."""
     import oracle as O
     from oracle.layout import Layout
-    lay = Layout(inst)
-    fac = O.factor_s1(lay, inst)
-    nl = O.norm_L(lay, inst)
 
     class _P:
         pass
     p = _P()
-    p.inst, p.lay, p.fac, p.alpha, p.normL = inst, lay, fac, 0.99 / nl, nl
-    v = np.zeros(lay.n_v)
+    p.inst, p.lay = inst, Layout(inst)
+    p.fac = O.factor_s1(p.lay, inst)
+    p.alpha = alpha
+    v = np.zeros(p.lay.n_v)
     n = 0
     t0 = time.perf_counter()
     while True:
@@ -85,113 +105,201 @@ def cpu_baseline(inst, budget_s=20.0):
     except Exception:
         cores = os.cpu_count()
     threads = int(os.environ.get("OMP_NUM_THREADS", cores))
-    return {"value": n / el, "unit": "CP iters/s", "cores": min(cores, threads), "kind": "oracle",
-            "sample": f"{n} CP iterations (T + residual statistics, FP64 numpy) of the same "
-                      f"workload from v=0, {el:.1f} s"}
+    return {"value": round(n / el, 4), "unit": "CP iters/s", "cores": min(cores, threads), "kind": "oracle",
+            "sample": f"{n} evaluations of T with residual statistics (FP64 numpy) on the same workload "
+                      f"from v=0, {el:.1f} s"}
+
+
+def timed_solve(torch, gp, x0, v, settings):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = gp.solve(x0, v, settings)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, info
+
+
+def ttr_single(torch, SP, G):
+    """223-node tree: SPOCK to xi <= 1e-4 from v = 0, FP64 and FP32 bulk."""
+    inst = G.make_config(2)
+    out = {"workload": NAMES[2]}
+    x0 = torch.as_tensor(inst.x0, dtype=torch.float64, device="cuda")
+    s = SP.default_settings(max_iters=200000)
+    ref_V = None
+    for name, prec in (("fp64", SP.FP64), ("fp32", SP.FP32)):
+        gp = SP.Problem.from_instance(inst, precision=prec)
+        v = torch.zeros(gp.n_v, dtype=gp.torch_dtype, device="cuda")
+        gp.solve(x0, v, SP.default_settings(max_iters=5))  # mapping autotuned outside the timing
+        v.zero_()
+        sec, info = timed_solve(torch, gp, x0, v, s)
+        if ref_V is None:
+            ref_V = info["V_s0"]
+        out[name] = {"seconds": round(sec, 4), "iters": info["iters"], "t_evals": info["t_evals"],
+                     "status": info["status"], "xi": info["xi"], "V_s0": info["V_s0"],
+                     "V_rel_err_vs_fp64": abs(info["V_s0"] - ref_V) / max(1.0, abs(ref_V)),
+                     "mapping": info["mapping"]}
+        log(f"223-node {name}: {info['status']} {info['iters']} iters {sec:.3f}s")
+    return out
+
+
+def ttr_batched(torch, SP, G, n_plain):
+    """512 uneven instances: warm start = FP64 solution + N(0, 0.05^2) on
+    every entry (seeded); batched FP32 (one persistent graph-captured launch)
+    vs the plain FP64 path, instance by instance, on a sample of n_plain
+    instances (the same warm starts), extrapolated to the batch."""
+    insts = G.make_batch(4, count=512)
+    x0s = [torch.as_tensor(i.x0, dtype=torch.float64, device="cuda") for i in insts]
+    p64 = [SP.Problem.from_instance(i, precision=SP.FP64) for i in insts]
+    p32 = [SP.Problem.from_instance(i, precision=SP.FP32) for i in insts]
+    v64 = [torch.zeros(p.n_v, dtype=torch.float64, device="cuda") for p in p64]
+    log("512-batch problems factored")
+    # previous solutions: batched FP64 to 1e-5 (at most 5000 iterations)
+    t0 = time.perf_counter()
+    SP.solve_batched(p64, x0s, v64, SP.default_settings(eps_abs=1e-5, eps_rel=1e-5, max_iters=5000))
+    torch.cuda.synchronize()
+    log(f"512-batch FP64 previous solutions {time.perf_counter() - t0:.2f}s")
+    rng = np.random.default_rng(2024)
+    warm = [v + torch.as_tensor(rng.normal(0.0, 0.05, v.numel()), device="cuda") for v in v64]
+    s = SP.default_settings(max_iters=200000)
+    # batched FP32 (autotune / graph capture outside the timing)
+    vb = [w.to(torch.float32) for w in warm]
+    SP.solve_batched(p32, x0s, [x.clone() for x in vb], SP.default_settings(max_iters=5))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos32 = SP.solve_batched(p32, x0s, vb, s)
+    torch.cuda.synchronize()
+    t_b32 = time.perf_counter() - t0
+    log(f"512-batch FP32 warm {t_b32:.3f}s")
+    # batched FP64 for context
+    vb64 = [w.clone() for w in warm]
+    SP.solve_batched(p64, x0s, [x.clone() for x in vb64], SP.default_settings(max_iters=5))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos64b = SP.solve_batched(p64, x0s, vb64, s)
+    torch.cuda.synchronize()
+    t_b64 = time.perf_counter() - t0
+    # plain FP64, one solve per instance, on a sample of the same warm starts
+    idx = np.linspace(0, 511, n_plain).astype(int)
+    t_plain = 0.0
+    iters_plain = []
+    for b in idx:
+        v = warm[b].clone()
+        p64[b].solve(x0s[b], v.clone(), SP.default_settings(max_iters=3))
+        sec, info = timed_solve(torch, p64[b], x0s[b], v, s)
+        t_plain += sec
+        iters_plain.append(info["iters"])
+    log(f"plain FP64 sample {t_plain:.3f}s")
+    t_plain_all = t_plain * 512 / n_plain
+    conv32 = sum(i["status"] == "converged" for i in infos32)
+    verr = max(abs(a["V_s0"] - b["V_s0"]) / max(1.0, abs(b["V_s0"])) for a, b in zip(infos32, infos64b))
+    log(f"512-batch FP32 {t_b32:.3f}s, FP64 batched {t_b64:.3f}s, plain FP64 {t_plain_all:.2f}s (extrapolated)")
+    return {"workload": "512 uneven trees nx10 nu5 N 5..12 (warm start, sigma 0.05)",
+            "batched_fp32_seconds": round(t_b32, 4), "batched_fp32_converged": conv32,
+            "batched_fp32_max_iters": max(i["iters"] for i in infos32),
+            "batched_fp32_V_max_rel_err_vs_fp64": verr,
+            "batched_fp64_seconds": round(t_b64, 4),
+            "plain_fp64_seconds_extrapolated": round(t_plain_all, 3),
+            "plain_fp64_sample": f"{n_plain} of 512 instances timed one by one ({t_plain:.3f} s), scaled by 512/{n_plain}",
+            "plain_fp64_mean_iters": float(np.mean(iters_plain)),
+            "speedup_batched_fp32_vs_plain_fp64": round(t_plain_all / t_b32, 2)}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3, 5])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--method", default="spock", choices=["spock", "cp"])
-    ap.add_argument("--max-iters", type=int, default=20000)
-    ap.add_argument("--t-reps", type=int, default=50)
+    ap.add_argument("--t-reps", type=int, default=30)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--plain-sample", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        print("bench.py: this build runs on one GPU only (--gpus 1); the multi-GPU sharding of the tree "
+              "is described in the design notes, not implemented", file=sys.stderr)
         raise SystemExit(2)
 
     import torch
     import paper_2212_01110_amd as SP
+    import spock_gen as G
 
     torch.cuda.set_device(0)
     t_setup = time.perf_counter()
-    inst = build_workload(args.config)
+    inst = G.make_config(args.config)
     prec = SP.FP32 if args.precision == "fp32" else SP.FP64
     gp = SP.Problem.from_instance(inst, precision=prec)
     dt = gp.torch_dtype
     x0 = torch.as_tensor(inst.x0, dtype=torch.float64, device="cuda")
     v = torch.zeros(gp.n_v, dtype=dt, device="cuda")
-    s = SP.default_settings(method=args.method, max_iters=args.max_iters)
-    print(f"[bench] config {args.config} n_v={gp.n_v} alpha={gp.alpha:.6g} setup "
-          f"{time.perf_counter() - t_setup:.1f}s", file=sys.stderr, flush=True)
+    log(f"config {args.config} n_v={gp.n_v} alpha={gp.alpha:.6g} setup {time.perf_counter() - t_setup:.1f}s")
 
-    for w in range(args.warmup):
-        v.zero_()
-        info = gp.solve(x0, v, s)
-        print(f"[bench] warmup {w}: {info['status']} iters={info['iters']} "
-              f"t_evals={info['t_evals']} {info['seconds']:.3f}s", file=sys.stderr, flush=True)
+    # warm-up steps (the first solve also autotunes the family-to-lane mapping)
+    if args.warmup > 0:
+        info = gp.solve(x0, v, SP.default_settings(method=args.method, max_iters=args.warmup))
+        log(f"warmup: {info['iters']} iters {info['t_evals']} T-evals map={info['mapping']} {info['seconds']:.3f}s")
+    # timed: exactly K steps from a cold start
+    v.zero_()
+    s = SP.default_settings(method=args.method, max_iters=args.steps)
     torch.cuda.synchronize()
-    infos = []
     t0 = time.perf_counter()
-    for k in range(args.steps):
-        v.zero_()
-        infos.append(gp.solve(x0, v, s))
+    info = gp.solve(x0, v, s)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    t_evals = sum(i["t_evals"] for i in infos)
-    for k, i in enumerate(infos):
-        print(f"[bench] step {k}: {i['status']} iters={i['iters']} t_evals={i['t_evals']} "
-              f"xi={i['xi']:.3g} V_s0={i['V_s0']:.8g} map={i['mapping']} {i['seconds']:.3f}s", file=sys.stderr,
-              flush=True)
+    steps = info["iters"]
+    log(f"timed: {info['status']} {steps} iters {info['t_evals']} T-evals xi={info['xi']:.4g} "
+        f"V_s0={info['V_s0']:.8g} map={info['mapping']} {el:.3f}s")
 
-    # ---- roofline of T: HIP events on the library's stream (torch current stream)
-    vt = torch.zeros(gp.n_v, dtype=dt, device="cuda")
-    Tv = torch.empty_like(vt)
-    gp.T(v, x0, Tv, want_stats=False)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(args.t_reps):
-        gp.T(v, x0, Tv, want_stats=False)
-    ev1.record()
-    ev1.synchronize()
-    t_T = ev0.elapsed_time(ev1) / 1e3 / args.t_reps
+    # roofline of the sweeps kernel: HIP events recorded by the library
+    Tv = torch.empty_like(v)
+    prof = gp.profile_T(v, x0, Tv, reps=args.t_reps)
     itemsize = 4 if prec == SP.FP32 else 8
-    abytes, _ = algorithmic_bytes_T(inst, itemsize)
-    achieved = abytes / t_T / 1e9
+    e_sw = algorithmic_elems_sweeps(inst)
+    e_T = algorithmic_elems_T(inst)
+    us_sw = prof["sweeps"]
+    achieved = e_sw * itemsize / (us_sw * 1e-6) / 1e9
+    kname = "k_T_flow (both Alg. 2 sweeps, one launch)" if info["mapping"] == 512 else \
+        "per-stage backward/forward sweep launches"
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "CP operator T (k_bwd + k_fwd stage launches + k_reduce_stats)",
-            "bytes_per_launch": abytes, "us_per_launch": round(t_T * 1e6, 2)}
+            "kernel": kname, "bytes_per_launch": e_sw * itemsize, "us_per_launch": round(us_sw, 2),
+            "T_phases_us": {k: round(x, 2) for k, x in prof.items()},
+            "T_whole_algorithmic_bytes": e_T * itemsize,
+            "T_whole_GBps": round(e_T * itemsize / (prof["total"] * 1e-6) / 1e9, 1)}
+    log(f"T phases (us): {prof}; sweeps {achieved:.0f} GB/s")
 
+    extras = {}
+    if not args.no_extras:
+        extras["time_to_residual_223node"] = ttr_single(torch, SP, G)
+        extras["time_to_residual_512batch"] = ttr_batched(torch, SP, G, args.plain_sample)
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(inst, args.cpu_budget)
+        cpu = cpu_baseline(inst, gp.alpha, args.cpu_budget)
+        log(f"cpu baseline {cpu['value']} CP iters/s")
 
-    names = {1: "15-node binary tree nx2 nu1 N3 (AV@R a=0.5)",
-             2: "223-node tree nx20 nu10 N10 (branching 2 for 5 stages)",
-             3: "20776-node tree nx50 nu20 N15 (branching 3 for 7 stages, 2187 scenarios)",
-             5: "95-node tree nx20 nu10 N8"}
     out = {
         "metric": METRIC,
-        "value": round(t_evals / el, 2),
+        "value": round(info["t_evals"] / el, 2),
         "unit": "CP iters/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": round(el / args.steps * 1e3, 3),
+        "ms_per_step": round(el / max(1, steps) * 1e3, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32" if prec == SP.FP32 else "f64",
         "data": "synthetic",
-        "config": {"workload": names.get(args.config, str(args.config)), "method": args.method,
-                   "bulk_precision": args.precision, "eps_abs": 1e-4, "eps_rel": 1e-4,
-                   "n_v": gp.n_v, "start": "cold (v=0)"},
-        "time_to_residual_s": round(el / args.steps, 4),
-        "t_evals_per_solve": t_evals / args.steps,
-        "iters_per_solve": sum(i["iters"] for i in infos) / args.steps,
-        "status": [i["status"] for i in infos],
+        "config": {"workload": NAMES[args.config], "method": args.method, "bulk_precision": args.precision,
+                   "factor_and_residual_precision": "f64", "n_v": gp.n_v, "start": "cold (v=0)",
+                   "t_evals": info["t_evals"], "xi_after_steps": info["xi"],
+                   "residual_1e-4_reached": info["status"] == "converged"},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    out.update(extras)
     print(json.dumps(out), flush=True)
 
 

@@ -209,6 +209,15 @@ int spock_prox_gstar(spock_problem* prob, const void* w_dev, void* out_dev, void
 int spock_T(spock_problem* prob, const void* v_dev, const double* x0_dev, void* Tv_dev,
             double* stats_host, void* stream);
 
+/* Timing aid for the CP operator (results as spock_T, statistics not
+ * returned): evaluates T(v_dev) reps times on `stream` with HIP events
+ * recorded between its phases and writes the mean duration in microseconds
+ * of each phase to us_out_host[0..4]: pre-pass (xbar, ubar, S2), both Alg. 2
+ * sweeps, post-pass (dual update and statistics), reduction of the
+ * statistics, whole evaluation. Synchronises. reps must be >= 1. */
+int spock_profile_T(spock_problem* prob, const void* v_dev, const double* x0_dev, void* Tv_dev,
+                    int32_t reps, double* us_out_host, void* stream);
+
 /* Library version string */
 const char* spock_version(void);
 

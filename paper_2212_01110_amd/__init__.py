@@ -28,7 +28,7 @@ EXPORTED = [
     "spock_tree_create", "spock_tree_destroy", "spock_tree_shape", "spock_problem_factor",
     "spock_problem_destroy", "spock_problem_sizes", "spock_settings_default", "spock_solve",
     "spock_solve_batched", "spock_apply_L", "spock_apply_Lt", "spock_prox_f",
-    "spock_prox_gstar", "spock_T", "spock_version", "spock_backward",
+    "spock_prox_gstar", "spock_T", "spock_version", "spock_backward", "spock_profile_T",
 ]
 
 
@@ -98,6 +98,7 @@ def lib():
         L.spock_prox_f.argtypes = [vp, vp, vp, vp, vp]
         L.spock_prox_gstar.argtypes = [vp, vp, vp, vp]
         L.spock_T.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.spock_profile_T.argtypes = [vp, vp, vp, vp, i32, vp, vp]
         L.spock_backward.argtypes = [vp, vp, vp, dbl, vp, vp, vp, vp, ctypes.POINTER(Settings),
                                      ctypes.POINTER(Info), vp]
         L.spock_version.restype = ctypes.c_char_p
@@ -230,6 +231,14 @@ class Problem:
                                     ctypes.byref(s), ctypes.byref(info), _stream()),
                "spock_backward")
         return gx, gq, gqN, info.as_dict()
+
+    def profile_T(self, v, x0, Tv, reps=20):
+        """Mean microseconds per phase of T over reps evaluations (HIP events
+        on the current stream): pre, sweeps, post, reduce, total."""
+        us = np.zeros(5)
+        _check(lib().spock_profile_T(self.handle, _ptr(v), _ptr(x0), _ptr(Tv), int(reps),
+                                     ctypes.c_void_p(us.ctypes.data), _stream()), "spock_profile_T")
+        return dict(zip(("pre", "sweeps", "post", "reduce", "total"), us.tolist()))
 
     def T(self, v, x0, Tv, want_stats=True):
         st = np.zeros(6) if want_stats else None

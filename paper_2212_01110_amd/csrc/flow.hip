@@ -1,34 +1,33 @@
-// Dataflow form of the CP operator T: the whole evaluation (pre-pass, both
-// Alg. 2 sweeps, the dual update and the residual statistics) in ONE
-// persistent launch, so the 2N + 3 dependent launches of the per-stage form
-// and their dispatch latency disappear.
+// Dataflow form of the two Alg. 2 sweeps: both sweeps of one evaluation of
+// T in ONE persistent launch, in place of 2N dependent per-stage launches
+// and their dispatch latency. The fully parallel pre-pass (xbar, ubar, leaf
+// seeds, S2) runs before it and the parallel post-pass (dual update and
+// statistics) after it, as in the per-stage form.
 //
 // Work items, in this order:
-//   [0, nl)              backward step of family nl-1-t (reverse breadth-first:
-//                        every child family comes first), with the pre-pass
-//                        of the family fused in (xbar, ubar, leaf seeds, S2)
-//   [nl, 2 nl)           forward step of family t-nl (breadth-first: the
-//                        parent comes first), with the dual update of the
-//                        family's rows and its statistics record fused in
-//   [2 nl, 2 nl + nr)    fixed-order sum of 256 statistics records
-//   2 nl + nr            final sum of the nr chunk records into the six
-//                        statistics of T (only when the dual part is formed)
+//   [0, nl)        backward step of family nl-1-t (reverse breadth-first:
+//                  every child family comes first)
+//   [nl, 2 nl)     forward step of family t-nl (breadth-first: the parent
+//                  comes first)
 // Workgroup b runs items b, b + G, b + 2G, ... (G = grid size, every
-// workgroup resident). An item waits only on items with a smaller index:
-// the smallest unfinished item therefore never waits, and the launch drains.
-// Completion is published per family in a 32-bit flag holding
-// base + {1: q and d written, 2: x of the children written, 3: statistics
-// record written}, base = 4 * (launch epoch), compared modulo 2^32, so no
-// flag is ever cleared. Values crossing workgroups are stored and loaded
-// agent-coherent (they bypass the per-XCD L2's non-coherent lines), so
-// publishing is a wait for the wavefront's stores, not an L2 write-back,
-// and observing is a wait for the flag load. Every wait is
-// bounded; a wait that gives up raises an error word and the statistics of
-// the launch come out as NaN (no wave ever spins without end).
+// workgroup resident: cooperative launch). An item waits only on items with
+// a smaller index, so the smallest unfinished item never waits and the
+// launch drains.
 //
-// Matrices of an item are copied into LDS with direct global-to-LDS loads,
-// all issued before the item's first wait, so an item costs one HBM round
-// trip plus its dependency wait; the mat-vecs then run from LDS.
+// Completion is published per family in a 32-bit flag holding base + 1
+// (q and d written) or base + 2 (x of the children written), base =
+// 4 * (launch epoch), compared modulo 2^32: no flag is ever cleared. Values
+// crossing workgroups (q, d, x) are stored and loaded agent-coherent (they
+// bypass the non-coherent per-XCD L2 lines), so publishing is a wait for the
+// wavefront's stores and observing a wait for the flag load; the L2 is never
+// written back or invalidated. Every wait is bounded: a wait that gives up
+// raises an error word, later waits return at once, and the statistics of
+// the evaluation come out as NaN (no wave ever spins without end).
+//
+// The matrices of an item, with its xbar/ubar rows (and the leaf seeds) from
+// the pre-pass, are copied into LDS by direct global-to-LDS loads issued
+// before the item's dependency wait: an item costs one HBM round trip, its
+// wait, and LDS mat-vecs.
 #include "device_common.h"
 
 #include <math.h>
@@ -38,19 +37,20 @@ namespace spk {
 
 namespace {
 
-constexpr int kFW = 256;                 // threads per workgroup (4 wavefronts)
+constexpr int kFW = 256;                   // threads per workgroup (4 wavefronts)
 constexpr unsigned kSpinLimit = 1u << 21;  // polls of one bounded wait
-constexpr int kFoldMax = 16;             // partial sums per mat-vec output
+constexpr int kFoldMax = 16;               // partial sums per mat-vec output
 
 typedef __attribute__((address_space(3))) void lds_void;
 
 // Word offsets of the dynamic LDS regions (32-bit words; every region is a
 // whole number of 64-word rows so that a wavefront copy may overrun it).
 struct FlowLds {
-  int esz;         // words per element
-  int sA, sB;      // per-child strides of the Abar and B regions
-  int oA, oB, oR, oK, oW, oQ, oRed;
-  int nc;          // children per chunk
+  int esz;     // words per element
+  int sA, sB;  // per-child strides of the Abar and B regions
+  int oA, oB, oR, oK, oW, oQ, oX, oU, oRed;
+  int nc;      // children per chunk
+  int words;
   __host__ __device__ static int pad(int w) { return (w + 63) & ~63; }
   __host__ __device__ FlowLds(int nx, int nu, int nc_, int esz_) {
     esz = esz_;
@@ -62,19 +62,21 @@ struct FlowLds {
     oR = oB + nc * sB;
     oK = oR + pad(nu * nu * esz);
     oW = oK + pad(nx * nu * esz);
-    oQ = oW + pad(nx * nu * esz);
-    oRed = oQ + pad(nc * kMaxDim * esz);
-    words_ = oRed + pad((nc + 1) * kFW * esz);
+    oQ = oW + pad(nx * nu * esz);  // children's q (chunk), row stride nx
+    oX = oQ + pad(nc * nx * esz);  // xbar (backward) or x (forward)
+    oU = oX + pad(nx * esz);       // ubar (backward) or d (forward)
+    oRed = oU + pad(nu * esz);
+    words = oRed + pad((nc + 1) * kFW * esz);
   }
-  int words_;
-  __host__ __device__ int bytes() const { return words_ * 4; }
+  __host__ __device__ int bytes() const { return words * 4; }
 };
 
 // Copies nwords 32-bit words from global memory into LDS (dst = word
-// offset); wavefront w issues rows w, w + 4, ... of 64 words. Lanes past the
-// end re-read the last word (in bounds) into the region's padding.
-__device__ __forceinline__ void dma_words(const void* src, unsigned* lds, int dst, int nwords) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+// offset); wavefront w issues rows w', w' + 4, ... of 64 words, w' = w
+// rotated by `rot` so that small copies spread over the wavefronts. Lanes
+// past the end re-read the last word (in bounds) into the region's padding.
+__device__ __forceinline__ void dma_words(const void* src, unsigned* lds, int dst, int nwords, int rot) {
+  const int lane = threadIdx.x & 63, w = ((threadIdx.x >> 6) + rot) & 3;
   const unsigned* s = static_cast<const unsigned*>(src);
   for (int r = w; r * 64 < nwords; r += 4) {
     int e = r * 64 + lane;
@@ -88,27 +90,39 @@ __device__ __forceinline__ void wait_vm() {
 }
 
 // Partial mat-vec from LDS: M input-major (element (out o, in k) at
-// k * nout + o), v (nin) in LDS; thread t < G * nout adds the products of
-// inputs k = g, g + G, ... (g = t / nout) of output o = t % nout to red[t].
+// k * nout + o), v (nin) in LDS; thread t < G * nout sums the products of
+// inputs k = g, g + G, ... (g = t / nout) of output o = t % nout, with four
+// independent accumulators, into red[t] (added to it when acc).
 template <typename S>
 __device__ __forceinline__ void mv_part(const S* M, const S* v, int nin, int nout, S* red, bool acc) {
   const int G = min(kFW / nout, kFoldMax), span = G * nout, t = threadIdx.x;
   if (t < span) {
-    const int g = t / nout;
-    S a = acc ? red[t] : S(0);
     const int n = nin * nout;
-    int k = g;
-    for (int e = t; e < n; e += span, k += G) a += M[e] * v[k];
-    red[t] = a;
+    int e = t, k = t / nout;
+    S a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    for (; e + 3 * span < n; e += 4 * span, k += 4 * G) {
+      a0 += M[e] * v[k];
+      a1 += M[e + span] * v[k + G];
+      a2 += M[e + 2 * span] * v[k + 2 * G];
+      a3 += M[e + 3 * span] * v[k + 3 * G];
+    }
+    for (; e < n; e += span, k += G) a0 += M[e] * v[k];
+    const S s = (a0 + a1) + (a2 + a3);
+    red[t] = acc ? red[t] + s : s;
   }
 }
 
 template <typename S>
 __device__ __forceinline__ S mv_fold(const S* red, int nout, int o) {
   const int G = min(kFW / nout, kFoldMax);
-  S s = 0;
-  for (int g = 0; g < G; ++g) s += red[g * nout + o];
-  return s;
+  S s0 = 0, s1 = 0;
+  int g = 0;
+  for (; g + 1 < G; g += 2) {
+    s0 += red[g * nout + o];
+    s1 += red[(g + 1) * nout + o];
+  }
+  if (g < G) s0 += red[g * nout + o];
+  return s0 + s1;
 }
 
 __device__ __forceinline__ unsigned ld_flag(const unsigned* f) {
@@ -125,15 +139,14 @@ __device__ __forceinline__ void release_flag(unsigned* f, unsigned v) {
   if ((threadIdx.x & 63) == 0) __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Waits (bounded) until flag f reaches base + want within the current epoch;
-// the caller acquires afterwards. Gives up at once when the error word is set.
-__device__ __forceinline__ void wait_flag(const unsigned* f, unsigned base, unsigned want,
-                                          unsigned* err) {
+// Waits (bounded) until flag f reaches base + want within the current epoch.
+// Gives up at once when the error word is set.
+__device__ __forceinline__ void wait_flag(const unsigned* f, unsigned base, unsigned want, unsigned* err) {
   for (unsigned it = 0; it < kSpinLimit; ++it) {
     const unsigned d = ld_flag(f) - base;
     if (d >= want && d <= 3u) return;
     if ((it & 255u) == 255u && ld_flag(err) != 0u) return;
-    __builtin_amdgcn_s_sleep(2);
+    __builtin_amdgcn_s_sleep(1);
   }
   __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -148,76 +161,64 @@ __device__ __forceinline__ void acquire() {
 template <typename S>
 struct FlowArgs {
   DevProb<S> P;
-  const S* z;
-  const S* eta;
   S* zout;
-  S* eout;
   const double* x0;
+  const S* xbar;
+  const S* ubar;
   S* q;
   S* d;
-  double* partials;   // [nl][kStats]
-  double* part2;      // [nr][kStats]
-  double* stats;      // [6]
-  unsigned* flag;     // [nl]
-  unsigned* flag2;    // [nr]
-  unsigned* err;      // [1]
+  unsigned* flag;  // [nl]
+  unsigned* err;   // [1]
   unsigned base;
-  int nc, nr, items, dual;
+  int nc, items;
 };
 
 // ---------------------------------------------------------------- backward item
+// d = R~^{-1}(ubar - sum_c B^c' q^c); q = K'(d - ubar) + W d - xbar + sum_c Abar^c' q^c
 template <typename S>
 __device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, int i) {
-  __shared__ S xb[kMaxDim], ub[kMaxDim], sAv[kMaxDim], vg[kMaxDim], vd[kMaxDim];
+  __shared__ S sAv[kMaxDim], vg[kMaxDim], vd[kMaxDim];
   const DevProb<S>& P = A.P;
-  const Off<S> O(P);
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const int nx = P.nx, nu = P.nu, fc = P.fc[i], n = P.nch[i];
   const int es = L.esz;
   S* M = reinterpret_cast<S*>(lds);
-  S* qv = reinterpret_cast<S*>(lds + L.oQ);
+  const S* qv = reinterpret_cast<const S*>(lds + L.oQ);
+  const S* xb = reinterpret_cast<const S*>(lds + L.oX);
+  const S* ub = reinterpret_cast<const S*>(lds + L.oU);
   S* redA = reinterpret_cast<S*>(lds + L.oRed);
   S* redB = redA + kFW;
   const bool leafkids = fc >= P.nl;
   for (int k0 = 0; k0 < n; k0 += L.nc) {
     const int kc = min(L.nc, n - k0);
+    int rot = 0;
     for (int k = 0; k < kc; ++k) {
-      dma_words(P.AbR + (size_t)(fc + k0 + k) * nx * nx, lds, L.oA + k * L.sA, nx * nx * es);
-      dma_words(P.BR + (size_t)(fc + k0 + k) * nx * nu, lds, L.oB + k * L.sB, nx * nu * es);
+      dma_words(P.AbR + (size_t)(fc + k0 + k) * nx * nx, lds, L.oA + k * L.sA, nx * nx * es, rot++);
+      dma_words(P.BR + (size_t)(fc + k0 + k) * nx * nu, lds, L.oB + k * L.sB, nx * nu * es, rot++);
     }
     if (k0 == 0) {
-      dma_words(P.Rinv + (size_t)i * nu * nu, lds, L.oR, nu * nu * es);
-      dma_words(P.KR + (size_t)i * nu * nx, lds, L.oK, nu * nx * es);
-      dma_words(P.WC + (size_t)i * nu * nx, lds, L.oW, nu * nx * es);
-      if (w == 0) {  // xbar, ubar of the family (pre-pass)
-        S xbv[1], ubv[1];
-        fam_xbar_ubar<S, 64, 64>(P, O, A.z, A.eta, i, lane, xbv, ubv);
-        xb[lane] = xbv[0];
-        ub[lane] = ubv[0];
-      } else if (w == 1) {  // S2 projection of the z2 block, s^0 at the root
-        fam_s2<S, 64, 64, true>(P, O, A.z, A.eta, A.zout, i, lane);
-      }
+      dma_words(P.Rinv + (size_t)i * nu * nu, lds, L.oR, nu * nu * es, rot++);
+      dma_words(P.KR + (size_t)i * nu * nx, lds, L.oK, nu * nx * es, rot++);
+      dma_words(P.WC + (size_t)i * nu * nx, lds, L.oW, nu * nx * es, rot++);
+      dma_words(A.xbar + (size_t)i * nx, lds, L.oX, nx * es, rot++);
+      dma_words(A.ubar + (size_t)i * nu, lds, L.oU, nu * es, rot++);
     }
-    // q of the children of this chunk
-    if (leafkids) {
-      if (w == 2)
-        for (int k = 0; k < kc; ++k)
-          if (lane < nx) qv[k * kMaxDim + lane] = fam_child_q<S>(P, O, A.z, A.eta, A.q, fc + k0 + k, lane);
-    } else if (w == 3) {
+    if (leafkids) {  // seeds -xbar of the leaf children, written by the pre-pass
+      dma_words(A.q + (size_t)(fc + k0) * nx, lds, L.oQ, kc * nx * es, rot++);
+    } else if (w == 3) {  // children's q from their backward items
       if (lane < kc) wait_flag(A.flag + fc + k0 + lane, A.base, 1u, A.err);
       acquire();
-      for (int k = 0; k < kc; ++k)
-        if (lane < nx) qv[k * kMaxDim + lane] = ld_c<true>(A.q + (size_t)(fc + k0 + k) * nx + lane);
+      S* qw = reinterpret_cast<S*>(lds + L.oQ);
+      for (int e = lane; e < kc * nx; e += 64) qw[e] = ld_c<true>(A.q + (size_t)(fc + k0) * nx + e);
     }
     wait_vm();
     __syncthreads();
     for (int k = 0; k < kc; ++k) {
-      mv_part<S>(M + L.oA / es + k * (L.sA / es), qv + k * kMaxDim, nx, nx, redA, k0 + k > 0);
-      mv_part<S>(M + L.oB / es + k * (L.sB / es), qv + k * kMaxDim, nx, nu, redB, k0 + k > 0);
+      mv_part<S>(M + L.oA / es + k * (L.sA / es), qv + k * nx, nx, nx, redA, k0 + k > 0);
+      mv_part<S>(M + L.oB / es + k * (L.sB / es), qv + k * nx, nx, nu, redB, k0 + k > 0);
     }
     __syncthreads();  // matrices and q consumed before the next chunk's copies
   }
-  // d = R~^{-1}(ubar - sum_c B^c' q^c)
   if (t < nx) sAv[t] = mv_fold<S>(redA, nx, t);
   if (t < nu) vg[t] = ub[t] - mv_fold<S>(redB, nu, t);
   __syncthreads();
@@ -226,44 +227,45 @@ __device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, 
   if (t < nu) {
     const S dv = mv_fold<S>(redA, nu, t);
     vd[t] = dv;
+    vg[t] = dv - ub[t];
     st_c<true>(A.d + (size_t)i * nu + t, dv);
   }
   __syncthreads();
-  if (t < nu) vg[t] = vd[t] - ub[t];
-  __syncthreads();
-  // q = K'(d - ubar) + W d - xbar + sum_c Abar^c' q^c
   mv_part<S>(M + L.oK / es, vg, nu, nx, redA, false);
   mv_part<S>(M + L.oW / es, vd, nu, nx, redB, false);
   __syncthreads();
-  if (t < nx) st_c<true>(A.q + (size_t)i * nx + t, mv_fold<S>(redA, nx, t) + mv_fold<S>(redB, nx, t) - xb[t] + sAv[t]);
-  // q and d were written by wavefront 0, the S2 block by wavefront 1 before
-  // the last barriers (which waited for those stores)
+  if (t < nx)
+    st_c<true>(A.q + (size_t)i * nx + t, mv_fold<S>(redA, nx, t) + mv_fold<S>(redB, nx, t) - xb[t] + sAv[t]);
+  // q and d were written by wavefront 0 (threads < 64)
   if (w == 0) release_flag(A.flag + i, A.base + 1u);
   __syncthreads();  // LDS reuse by the next item
 }
 
 // ---------------------------------------------------------------- forward item
+// u = K x + d; x^c = Abar^c x + B^c d; x^0 = x0 at the root
 template <typename S>
 __device__ void flow_fwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, int i) {
-  __shared__ S vx[kMaxDim], vd[kMaxDim];
-  __shared__ S post_lds[3 * kMaxDim];
   const DevProb<S>& P = A.P;
   const Off<S> O(P);
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const int nx = P.nx, nu = P.nu, fc = P.fc[i], n = P.nch[i];
   const int es = L.esz;
   S* M = reinterpret_cast<S*>(lds);
+  S* vx = reinterpret_cast<S*>(lds + L.oX);
+  S* vd = reinterpret_cast<S*>(lds + L.oU);
   S* red = reinterpret_cast<S*>(lds + L.oRed);
   for (int k0 = 0; k0 < n; k0 += L.nc) {
     const int kc = min(L.nc, n - k0);
+    int rot = 1;
     for (int k = 0; k < kc; ++k) {
-      dma_words(P.AbC + (size_t)(fc + k0 + k) * nx * nx, lds, L.oA + k * L.sA, nx * nx * es);
-      dma_words(P.BC + (size_t)(fc + k0 + k) * nu * nx, lds, L.oB + k * L.sB, nx * nu * es);
+      dma_words(P.AbC + (size_t)(fc + k0 + k) * nx * nx, lds, L.oA + k * L.sA, nx * nx * es, rot++);
+      dma_words(P.BC + (size_t)(fc + k0 + k) * nu * nx, lds, L.oB + k * L.sB, nx * nu * es, rot++);
     }
     if (k0 == 0) {
-      dma_words(P.KC + (size_t)i * nx * nu, lds, L.oK, nx * nu * es);
+      dma_words(P.KC + (size_t)i * nx * nu, lds, L.oK, nx * nu * es, rot++);
       if (w == 0) {
-        // x^i from the parent's step (x0 at the root), d^i from the backward sweep
+        // d^i from the backward sweep (ordered before the parent's forward
+        // step through the chain of flags), x^i from the parent (x0 at the root)
         if (i == 0) wait_flag(A.flag, A.base, 1u, A.err);
         else wait_flag(A.flag + P.anc[i], A.base, 2u, A.err);
         acquire();
@@ -293,135 +295,27 @@ __device__ void flow_fwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, 
       if (t < nx) st_c<true>(A.zout + O.x(fc + k0 + k) + t, mv_fold<S>(red + k * kFW, nx, t));
     __syncthreads();  // red and the matrices are reused by the next chunk / item
   }
-  if (w != 0) return;
   // u^i and the children's x were written by wavefront 0 (threads < 64)
-  release_flag(A.flag + i, A.base + 2u);
-  if (!A.dual) return;
-  StatAcc st;
-  fam_post_team<S, 64, 64, true>(P, A.z, A.eta, A.zout, A.eout, i, lane, post_lds, kMaxDim, st);
-  double r0 = st.rz2, r1 = st.re2, r2 = st.cross, r3 = st.xip, r4 = st.xid;
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    r0 += __shfl_xor(r0, m, 64);
-    r1 += __shfl_xor(r1, m, 64);
-    r2 += __shfl_xor(r2, m, 64);
-    r3 = fmax(r3, __shfl_xor(r3, m, 64));
-    r4 = fmax(r4, __shfl_xor(r4, m, 64));
-  }
-  if (lane == 0) {
-    double* p = A.partials + (size_t)i * kStats;
-    st_c<true>(p + 0, r0);
-    st_c<true>(p + 1, r1);
-    st_c<true>(p + 2, r2);
-    st_c<true>(p + 3, r3);
-    st_c<true>(p + 4, r4);
-  }
-  release_flag(A.flag + i, A.base + 3u);
+  if (w == 0) release_flag(A.flag + i, A.base + 2u);
 }
 
-// ---------------------------------------------------------------- statistics items
-// Fixed-order reduction of the five statistics over the workgroup: a
-// butterfly inside each wavefront, then the four wavefront sums in order.
-// Ends with the total in thread 0's v.
-__device__ __forceinline__ void block_reduce5(double (&v)[kStats], double* wsum) {
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    v[0] += __shfl_xor(v[0], m, 64);
-    v[1] += __shfl_xor(v[1], m, 64);
-    v[2] += __shfl_xor(v[2], m, 64);
-    v[3] = fmax(v[3], __shfl_xor(v[3], m, 64));
-    v[4] = fmax(v[4], __shfl_xor(v[4], m, 64));
-  }
-  if (lane == 0)
-#pragma unroll
-    for (int s = 0; s < kStats; ++s) wsum[w * kStats + s] = v[s];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int q = 1; q < kFW / 64; ++q) {
-      v[0] += wsum[q * kStats + 0];
-      v[1] += wsum[q * kStats + 1];
-      v[2] += wsum[q * kStats + 2];
-      v[3] = fmax(v[3], wsum[q * kStats + 3]);
-      v[4] = fmax(v[4], wsum[q * kStats + 4]);
-    }
-  }
-}
-
-template <typename S>
-__device__ void flow_chunk(const FlowArgs<S>& A, int j, double* wsum) {
-  const int t = threadIdx.x;
-  const int f = j * kFW + t;
-  double v[kStats] = {0, 0, 0, 0, 0};
-  if (f < A.P.nl) {
-    wait_flag(A.flag + f, A.base, 3u, A.err);
-    acquire();
-    const double* p = A.partials + (size_t)f * kStats;
-#pragma unroll
-    for (int s = 0; s < kStats; ++s) v[s] = ld_c<true>(p + s);
-  }
-  block_reduce5(v, wsum);
-  if (t == 0)
-#pragma unroll
-    for (int s = 0; s < kStats; ++s) st_c<true>(A.part2 + (size_t)j * kStats + s, v[s]);
-  if (t < 64) release_flag(A.flag2 + j, A.base + 1u);
-  __syncthreads();  // wsum reuse
-}
-
-template <typename S>
-__device__ void flow_final(const FlowArgs<S>& A, double* wsum) {
-  const int t = threadIdx.x;
-  double v[kStats] = {0, 0, 0, 0, 0};
-  for (int j = t; j < A.nr; j += kFW) {
-    wait_flag(A.flag2 + j, A.base, 1u, A.err);
-    acquire();
-    const double* p = A.part2 + (size_t)j * kStats;
-    v[0] += ld_c<true>(p + 0);
-    v[1] += ld_c<true>(p + 1);
-    v[2] += ld_c<true>(p + 2);
-    v[3] = fmax(v[3], ld_c<true>(p + 3));
-    v[4] = fmax(v[4], ld_c<true>(p + 4));
-  }
-  block_reduce5(v, wsum);
-  if (t == 0) {
-    // a bounded wait that gave up (now or earlier) poisons the statistics;
-    // the host clears the error word before the next solve
-    const bool bad = ld_flag(A.err) != 0u;
-    const double nan = __builtin_nan("");
-    const double al = (double)A.P.alpha;
-    A.stats[0] = bad ? nan : v[3];
-    A.stats[1] = bad ? nan : v[4];
-    A.stats[2] = bad ? nan : v[0] + v[1] - 2.0 * al * v[2];
-    A.stats[3] = bad ? nan : v[0];
-    A.stats[4] = bad ? nan : v[1];
-    A.stats[5] = bad ? nan : v[2];
-  }
-  __syncthreads();
-}
-
-// W: minimum wavefronts per SIMD the register allocation must allow (2:
-// no spills; 4: twice the resident workgroups, some registers spilled).
+// W: minimum wavefronts per SIMD the register allocation must allow.
 template <typename S, int W>
 __global__ void __launch_bounds__(kFW) __attribute__((amdgpu_waves_per_eu(W, 8))) k_T_flow(FlowArgs<S> A) {
   extern __shared__ __align__(16) unsigned flow_lds[];
-  __shared__ double wsum[(kFW / 64) * kStats];
   const FlowLds L(A.P.nx, A.P.nu, A.nc, (int)(sizeof(S) / 4));
   const int nl = A.P.nl;
-  // Items run in increasing order in every workgroup. After a forward item
-  // wavefront 0 alone finishes the dual update; the other wavefronts go on
-  // to the next item (its first barrier waits for wavefront 0), touching no
-  // LDS the dual update uses.
+  // items run in increasing order in every workgroup
   for (int it = blockIdx.x; it < A.items; it += gridDim.x) {
-    if (it < nl) {
-      flow_bwd<S>(A, L, flow_lds, nl - 1 - it);
-    } else if (it < 2 * nl) {
-      flow_fwd<S>(A, L, flow_lds, it - nl);
-    } else if (it < 2 * nl + A.nr) {
-      flow_chunk<S>(A, it - 2 * nl, wsum);
-    } else {
-      flow_final<S>(A, wsum);
-    }
+    if (it < nl) flow_bwd<S>(A, L, flow_lds, nl - 1 - it);
+    else flow_fwd<S>(A, L, flow_lds, it - nl);
   }
+}
+
+// Poisons the statistics when a bounded wait of the sweeps gave up.
+__global__ void k_flow_check(const unsigned* __restrict__ err, double* __restrict__ stats) {
+  if (threadIdx.x == 0 && ld_flag(err) != 0u)
+    for (int s = 0; s < 6; ++s) stats[s] = __builtin_nan("");
 }
 
 }  // namespace
@@ -437,41 +331,36 @@ template const void* flow_kernel<double>(int);
 template const void* flow_kernel<float>(int);
 
 template <typename S>
-hipError_t launch_T_flow(const Problem& P, const DevProb<S>& D, const S* z, const S* eta, S* zout, S* eout,
-                         const double* x0, S* q, S* d, double* partials, double* stats, bool dual,
-                         hipStream_t st) {
+hipError_t launch_sweeps_flow(const Problem& P, const DevProb<S>& D, S* zout, const double* x0, const S* xbar,
+                              const S* ubar, S* q, S* d, hipStream_t st) {
   const FlowState& F = P.flow;
   if (!F.flag || F.grid <= 0) return hipErrorInvalidValue;
   FlowArgs<S> A;
   A.P = D;
-  A.z = z;
-  A.eta = eta;
   A.zout = zout;
-  A.eout = eout;
   A.x0 = x0;
+  A.xbar = xbar;
+  A.ubar = ubar;
   A.q = q;
   A.d = d;
-  A.partials = partials;
-  A.part2 = F.part2;
-  A.stats = stats;
   A.flag = F.flag;
-  A.flag2 = F.flag2;
   A.err = F.err;
-  A.base = 4u * (unsigned)(P.flow_epoch++);
+  A.base = 4u * (P.flow_epoch++);
   A.nc = F.nc;
-  A.nr = (P.tree->nl + kFW - 1) / kFW;
-  A.dual = dual ? 1 : 0;
-  A.items = 2 * P.tree->nl + (dual ? A.nr + 1 : 0);
+  A.items = 2 * P.tree->nl;
   const int grid = std::min(F.grid, A.items);
   const size_t lds = (size_t)flow_lds_bytes(P.nx, P.nu, F.nc, (int)sizeof(S));
   void* args[] = {&A};
   return hipLaunchCooperativeKernel(flow_kernel<S>(F.occ), dim3(grid), dim3(kFW), args, (unsigned)lds, st);
 }
-template hipError_t launch_T_flow<double>(const Problem&, const DevProb<double>&, const double*, const double*,
-                                          double*, double*, const double*, double*, double*, double*, double*,
-                                          bool, hipStream_t);
-template hipError_t launch_T_flow<float>(const Problem&, const DevProb<float>&, const float*, const float*,
-                                         float*, float*, const double*, float*, float*, double*, double*, bool,
-                                         hipStream_t);
+template hipError_t launch_sweeps_flow<double>(const Problem&, const DevProb<double>&, double*, const double*,
+                                               const double*, const double*, double*, double*, hipStream_t);
+template hipError_t launch_sweeps_flow<float>(const Problem&, const DevProb<float>&, float*, const double*,
+                                              const float*, const float*, float*, float*, hipStream_t);
+
+hipError_t launch_flow_check(const Problem& P, double* stats, hipStream_t st) {
+  hipLaunchKernelGGL(k_flow_check, dim3(1), dim3(64), 0, st, P.flow.err, stats);
+  return hipGetLastError();
+}
 
 }  // namespace spk

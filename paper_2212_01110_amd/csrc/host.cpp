@@ -642,11 +642,12 @@ struct Work {
   double* host_stats = nullptr;
 };
 
-// Sizes and allocates the state of the dataflow form of T for precision S:
-// children per LDS chunk (largest count whose LDS stays within the budget,
-// at least one), resident workgroups from the occupancy of the kernel, and
-// the flag / chunk arrays (zeroed once; flags are epoch-tagged). The error
-// word is cleared on every call (each API call starts clean).
+// Sizes and allocates the state of the dataflow form of the sweeps for
+// precision S: children per LDS chunk (largest count whose LDS stays within
+// the budget, at least one), resident workgroups from the occupancy of the
+// kernel at the register budget occ, and the flags (zeroed once; they are
+// epoch-tagged). The error word is cleared on every call (each API call
+// starts clean).
 template <typename S>
 int ensure_flow(Problem& P, int occ = 0) {
   FlowState& F = P.flow;
@@ -673,16 +674,11 @@ int ensure_flow(Problem& P, int occ = 0) {
   if (lds <= 64 * 1024 &&
       hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, flow_kernel<S>(occ), 256, (size_t)lds) != hipSuccess)
     return SPOCK_EHIP;
-  const int nr = (T.nl + 255) / 256;
-  const size_t bytes = 256 + sizeof(unsigned) * (size_t)(T.nl + nr + 64) + sizeof(double) * (size_t)nr * kStats;
+  const size_t bytes = sizeof(unsigned) * (size_t)(T.nl + 64);
   if (hipMalloc(&F.mem, bytes) != hipSuccess) return SPOCK_ENOMEM;
   if (hipMemset(F.mem, 0, bytes) != hipSuccess) return SPOCK_EHIP;
-  char* b = static_cast<char*>(F.mem);
-  F.part2 = reinterpret_cast<double*>(b);
-  b += (sizeof(double) * (size_t)nr * kStats + 255) & ~size_t(255);
-  F.err = reinterpret_cast<unsigned*>(b);
-  F.flag2 = F.err + 64;
-  F.flag = F.flag2 + nr;
+  F.err = static_cast<unsigned*>(F.mem);
+  F.flag = F.err + 64;
   F.nc = nc;
   F.occ = occ;
   F.elem = (int)sizeof(S);
@@ -1203,6 +1199,41 @@ extern "C" int spock_T(spock_problem* ph, const void* v, const double* x0, void*
   return (P.precision == SPOCK_FP64)
              ? T_impl<double>(P, static_cast<const double*>(v), x0, static_cast<double*>(Tv), stats, st)
              : T_impl<float>(P, static_cast<const float*>(v), x0, static_cast<float*>(Tv), stats, st);
+}
+
+extern "C" int spock_profile_T(spock_problem* ph, const void* v, const double* x0, void* Tv, int32_t reps,
+                               double* us, void* stream) {
+  if (!ph || !v || !Tv || !x0 || !us || reps < 1) return SPOCK_EINVAL;
+  Problem& P = ph->p;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // untimed evaluation first (autotuning-free: the current mapping is used)
+  int rc = (P.precision == SPOCK_FP64)
+               ? T_impl<double>(P, static_cast<const double*>(v), x0, static_cast<double*>(Tv), nullptr, st)
+               : T_impl<float>(P, static_cast<const float*>(v), x0, static_cast<float*>(Tv), nullptr, st);
+  if (rc) return rc;
+  hipEvent_t ev[5];
+  for (int k = 0; k < 5; ++k)
+    if (hipEventCreate(&ev[k]) != hipSuccess) return SPOCK_EHIP;
+  double acc[5] = {0, 0, 0, 0, 0};
+  P.prof = ev;
+  for (int r = 0; r < reps && rc == SPOCK_OK; ++r) {
+    rc = (P.precision == SPOCK_FP64)
+             ? T_impl<double>(P, static_cast<const double*>(v), x0, static_cast<double*>(Tv), nullptr, st)
+             : T_impl<float>(P, static_cast<const float*>(v), x0, static_cast<float*>(Tv), nullptr, st);
+    if (rc) break;
+    if (hipEventSynchronize(ev[4]) != hipSuccess) rc = SPOCK_EHIP;
+    for (int k = 0; k < 4 && rc == SPOCK_OK; ++k) {
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, ev[k], ev[k + 1]) != hipSuccess) rc = SPOCK_EHIP;
+      acc[k] += ms;
+      acc[4] += ms;
+    }
+  }
+  P.prof = nullptr;
+  for (int k = 0; k < 5; ++k) (void)hipEventDestroy(ev[k]);
+  if (rc) return rc;
+  for (int k = 0; k < 5; ++k) us[k] = acc[k] * 1e3 / reps;
+  return SPOCK_OK;
 }
 
 // ============================================================== batched

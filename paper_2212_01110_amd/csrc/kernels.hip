@@ -535,20 +535,30 @@ hipError_t launch_T(const Problem& P, const S* v, S* Tv, const double* x0, S* q,
   const S* eta = dual ? v + P.nz : eta_zero;
   S* zout = Tv;
   S* eout = dual ? Tv + P.nz : nullptr;
-  if (P.team == kTeamFlow) return launch_T_flow<S>(P, D, z, eta, zout, eout, x0, q, d, partials, stats_dev, dual, st);
+  auto mark = [&](int k) {
+    if (P.prof) (void)hipEventRecord(P.prof[k], st);
+  };
+  mark(0);
   switch (P.team_pp) {
     case 8: launch_pre<S, 8>(P, D, z, eta, zout, xbar, ubar, q, st); break;
     case 16: launch_pre<S, 16>(P, D, z, eta, zout, xbar, ubar, q, st); break;
     case 32: launch_pre<S, 32>(P, D, z, eta, zout, xbar, ubar, q, st); break;
     default: launch_pre<S, 64>(P, D, z, eta, zout, xbar, ubar, q, st); break;
   }
+  mark(1);
   switch (P.team) {
+    case kTeamFlow: {
+      const hipError_t e = launch_sweeps_flow<S>(P, D, zout, x0, xbar, ubar, q, d, st);
+      if (e != hipSuccess) return e;
+      break;
+    }
     case 8: launch_sweeps_team<S, 8>(P, D, zout, x0, xbar, ubar, q, d, st); break;
     case 16: launch_sweeps_team<S, 16>(P, D, zout, x0, xbar, ubar, q, d, st); break;
     case 32: launch_sweeps_team<S, 32>(P, D, zout, x0, xbar, ubar, q, d, st); break;
     case 64: launch_sweeps_team<S, 64>(P, D, zout, x0, xbar, ubar, q, d, st); break;
     default: launch_sweeps_wg<S>(P, D, zout, x0, xbar, ubar, q, d, st); break;
   }
+  mark(2);
   if (dual) {
     switch (P.team_pp) {
       case 8: launch_post<S, 8>(P, D, z, eta, zout, eout, partials, st); break;
@@ -556,9 +566,15 @@ hipError_t launch_T(const Problem& P, const S* v, S* Tv, const double* x0, S* q,
       case 32: launch_post<S, 32>(P, D, z, eta, zout, eout, partials, st); break;
       default: launch_post<S, 64>(P, D, z, eta, zout, eout, partials, st); break;
     }
+    mark(3);
     hipLaunchKernelGGL(k_reduce_stats, dim3(1), dim3(256), 0, st, partials, post_blocks(P),
                        (double)D.alpha, stats_dev);
+    if (P.team == kTeamFlow) {
+      const hipError_t e = launch_flow_check(P, stats_dev, st);
+      if (e != hipSuccess) return e;
+    }
   }
+  mark(4);
   return hipGetLastError();
 }
 template hipError_t launch_T<double>(const Problem&, const double*, double*, const double*, double*,
@@ -780,14 +796,29 @@ __device__ void block_sums(double (&acc)[K], double* partials) {
   if ((int)threadIdx.x < K) partials[(size_t)blockIdx.x * 8 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-__global__ void k_final_sums(const double* __restrict__ partials, int nblk, int K,
-                             double* __restrict__ out) {
-  // one thread per output, fixed order
-  const int j = threadIdx.x;
-  if (j >= K) return;
-  double s = 0;
-  for (int b = 0; b < nblk; ++b) s += partials[(size_t)b * 8 + j];
-  out[j] = s;
+// Sums K <= 8 columns of nblk partial records (stride 8) in a fixed order:
+// thread t takes records t, t + 256, ..., then a tree over the threads.
+__global__ void __launch_bounds__(256) k_final_sums(const double* __restrict__ partials, int nblk, int K,
+                                                    double* __restrict__ out) {
+  __shared__ double red[8][256];
+  const int t = threadIdx.x;
+  double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = t; b < nblk; b += 256) {
+    const double* p = partials + (size_t)b * 8;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (j < K) s[j] += p[j];
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) red[j][t] = s[j];
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if (t < h)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) red[j][t] += red[j][t + h];
+    __syncthreads();
+  }
+  if (t < K) out[t] = red[t][0];
 }
 
 // out[j] = <x_j, y_j>, j < k <= 8
@@ -804,7 +835,7 @@ hipError_t launch_dots(long long n, int k, VecPtrs<S> xs, VecPtrs<S> ys,
                        double* partials, double* out_dev, hipStream_t st) {
   const int nb = dots_blocks(n);
   hipLaunchKernelGGL(k_dots<S>, dim3(nb), dim3(256), 0, st, n, k, xs, ys, partials);
-  hipLaunchKernelGGL(k_final_sums, dim3(1), dim3(64), 0, st, partials, nb, k, out_dev);
+  hipLaunchKernelGGL(k_final_sums, dim3(1), dim3(256), 0, st, partials, nb, k, out_dev);
   return hipGetLastError();
 }
 
@@ -823,7 +854,7 @@ hipError_t launch_rdot(long long n, const S* v, const S* Tv, const S* w, double*
                        double* out_dev, hipStream_t st) {
   const int nb = dots_blocks(n);
   hipLaunchKernelGGL(k_rdot<S>, dim3(nb), dim3(256), 0, st, n, v, Tv, w, partials);
-  hipLaunchKernelGGL(k_final_sums, dim3(1), dim3(64), 0, st, partials, nb, 1, out_dev);
+  hipLaunchKernelGGL(k_final_sums, dim3(1), dim3(256), 0, st, partials, nb, 1, out_dev);
   return hipGetLastError();
 }
 
@@ -861,7 +892,7 @@ hipError_t launch_aa_push(long long n, const S* v, const S* vprev, const S* Tv, 
   const int nb = dots_blocks(n);
   hipLaunchKernelGGL(k_aa_push<S>, dim3(nb), dim3(256), 0, st, n, v, vprev, Tv, rprev, r_out,
                      dV_new, dR_new, m_old, dR_old, partials);
-  hipLaunchKernelGGL(k_final_sums, dim3(1), dim3(64), 0, st, partials, nb, 2 * m_old + 2, out_dev);
+  hipLaunchKernelGGL(k_final_sums, dim3(1), dim3(256), 0, st, partials, nb, 2 * m_old + 2, out_dev);
   return hipGetLastError();
 }
 

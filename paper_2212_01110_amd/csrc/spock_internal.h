@@ -63,19 +63,17 @@ struct DevArrays {
   size_t bytes = 0;
 };
 
-// Device state of the dataflow form of T: completion flags per family and
-// per statistics chunk, an error word raised by a bounded wait that gave up,
-// and the chunk sums. Flags are never cleared (epoch-tagged values).
+// Device state of the dataflow form of the sweeps: a completion flag per
+// family (epoch-tagged, never cleared) and an error word raised by a bounded
+// wait that gave up.
 struct FlowState {
   void* mem = nullptr;
-  unsigned* flag = nullptr;   // [nl]
-  unsigned* flag2 = nullptr;  // [nr]
-  unsigned* err = nullptr;    // [1]
-  double* part2 = nullptr;    // [nr][kStats]
-  int nc = 1;                 // children per LDS chunk
-  int grid = 0;               // resident workgroups (0: form unavailable)
-  int occ = 2;                // register budget: 2 or 4 wavefronts per SIMD
-  int elem = 0;               // element size the state was sized for
+  unsigned* flag = nullptr;  // [nl]
+  unsigned* err = nullptr;   // [1]
+  int nc = 1;                // children per LDS chunk
+  int grid = 0;              // resident workgroups (0: form unavailable)
+  int occ = 2;               // register budget: 2 or 4 wavefronts per SIMD
+  int elem = 0;              // element size the state was sized for
 };
 
 struct Problem {
@@ -107,6 +105,9 @@ struct Problem {
   bool tuned = false;
   FlowState flow;
   mutable unsigned flow_epoch = 1;  // launches of the dataflow form so far
+  // when set, launch_T records prof[0..4] before the pre-pass, after it,
+  // after the sweeps, after the post-pass and at the end (timing aid)
+  hipEvent_t* prof = nullptr;
 };
 
 // ---------------------------------------------------------------- launchers
@@ -118,11 +119,11 @@ hipError_t launch_T(const Problem& P, const S* v, S* Tv, const double* x0, S* q,
                     S* ubar, double* partials, double* stats_dev, hipStream_t st,
                     const S* eta_zero, bool dual);
 int post_blocks(const Problem& P);
-// Dataflow form (flow.hip): one persistent launch per T.
+// Dataflow form of the sweeps (flow.hip): one persistent launch per T.
 template <typename S>
-hipError_t launch_T_flow(const Problem& P, const DevProb<S>& D, const S* z, const S* eta, S* zout, S* eout,
-                         const double* x0, S* q, S* d, double* partials, double* stats, bool dual,
-                         hipStream_t st);
+hipError_t launch_sweeps_flow(const Problem& P, const DevProb<S>& D, S* zout, const double* x0, const S* xbar,
+                              const S* ubar, S* q, S* d, hipStream_t st);
+hipError_t launch_flow_check(const Problem& P, double* stats, hipStream_t st);
 int flow_lds_bytes(int nx, int nu, int nc, int elem);
 template <typename S>
 const void* flow_kernel(int occ);
