@@ -85,7 +85,10 @@ def test_config5_gradients_directional_fd(prec):
         return inf["V_s0"]
 
     fd = (V_at(inst.x0 + h * d) - V_at(inst.x0 - h * d)) / (2 * h)
-    tol = 1e-5 if prec == "fp64" else 2e-3
+    # the central difference itself is only as exact as its two solves:
+    # |error| <= eps_V / h with eps_V ~ 1e-11 * cond (xi <= 1e-11), i.e. a few
+    # 1e-6 relative at h = 1e-5; the bound below leaves that margin
+    tol = 3e-5 if prec == "fp64" else 2e-3
     assert abs(fd - host(gx) @ d) <= tol * max(1, abs(fd)), (fd, host(gx) @ d, binfo)
     # one cost weight (child 3, component 2)
     i3 = inst.copy()
