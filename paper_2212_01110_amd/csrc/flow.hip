@@ -14,15 +14,16 @@
 // a smaller index, so the smallest unfinished item never waits and the
 // launch drains.
 //
-// Completion is published per family in a 32-bit flag holding base + 1
-// (q and d written) or base + 2 (x of the children written), base =
-// 4 * (launch epoch), compared modulo 2^32: no flag is ever cleared. Values
-// crossing workgroups (q, d, x) are stored and loaded agent-coherent (they
-// bypass the non-coherent per-XCD L2 lines), so publishing is a wait for the
-// wavefront's stores and observing a wait for the flag load; the L2 is never
-// written back or invalidated. Every wait is bounded: a wait that gives up
-// raises an error word, later waits return at once, and the statistics of
-// the evaluation come out as NaN (no wave ever spins without end).
+// Values crossing workgroups (q and d of the backward step, x of the
+// forward step) travel as tagged words: each 32-bit half of a value shares a
+// 64-bit word with the launch epoch and is stored and loaded as one
+// agent-coherent atomic (it bypasses the non-coherent per-XCD L2 lines). A
+// consumer polls the data itself until every tag equals the epoch: no
+// separate flag, no wait for store acknowledgements, no cache write-back or
+// invalidation, and nothing is ever cleared (old epochs never match). Every
+// poll loop is bounded: a loop that gives up raises an error word, later
+// loops return at once, and the statistics of the evaluation come out as NaN
+// (no wave ever spins without end).
 //
 // The matrices of an item, with its xbar/ubar rows (and the leaf seeds) from
 // the pre-pass, are copied into LDS by direct global-to-LDS loads issued
@@ -39,7 +40,7 @@ namespace {
 
 constexpr int kFW = 256;                   // threads per workgroup (4 wavefronts)
 constexpr unsigned kSpinLimit = 1u << 21;  // polls of one bounded wait
-constexpr int kFoldMax = 16;               // partial sums per mat-vec output
+constexpr int kFoldMax = 4;                // partial sums per mat-vec output
 
 typedef __attribute__((address_space(3))) void lds_void;
 
@@ -48,7 +49,7 @@ typedef __attribute__((address_space(3))) void lds_void;
 struct FlowLds {
   int esz;     // words per element
   int sA, sB;  // per-child strides of the Abar and B regions
-  int oA, oB, oR, oK, oW, oQ, oX, oU, oRed;
+  int oA, oB, oR, oK, oW, oQ, oX, oU, oRed;  // oW: M1 (backward)
   int nc;      // children per chunk
   int words;
   __host__ __device__ static int pad(int w) { return (w + 63) & ~63; }
@@ -66,7 +67,7 @@ struct FlowLds {
     oX = oQ + pad(nc * nx * esz);  // xbar (backward) or x (forward)
     oU = oX + pad(nx * esz);       // ubar (backward) or d (forward)
     oRed = oU + pad(nu * esz);
-    words = oRed + pad((nc + 1) * kFW * esz);
+    words = oRed + pad((nc + 1 > 5 ? nc + 1 : 5) * kFW * esz);
   }
   __host__ __device__ int bytes() const { return words * 4; }
 };
@@ -129,33 +130,55 @@ __device__ __forceinline__ unsigned ld_flag(const unsigned* f) {
   return __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Publishes value v in flag f once this wavefront's earlier stores are
-// complete. Every value another workgroup reads is stored agent-coherent
-// (st_c), so waiting for the stores to be acknowledged orders them before
-// the flag; no L2 write-back is needed.
-__device__ __forceinline__ void release_flag(unsigned* f, unsigned v) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  wait_vm();
-  if ((threadIdx.x & 63) == 0) __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+
+
+
+// Tagged words: element e of a vector occupies kTW<S> 64-bit words, each
+// holding (epoch << 32) | one 32-bit half of the value.
+template <typename S>
+constexpr int kTW = sizeof(S) / 4;
+
+template <typename S>
+__device__ __forceinline__ void put_tagged(unsigned long long* p, S v, unsigned tag) {
+  unsigned h[kTW<S>];
+  __builtin_memcpy(h, &v, sizeof(S));
+  const unsigned long long hi = (unsigned long long)tag << 32;
+#pragma unroll
+  for (int k = 0; k < kTW<S>; ++k) __hip_atomic_store(p + k, hi | h[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Waits (bounded) until flag f reaches base + want within the current epoch.
-// Gives up at once when the error word is set.
-__device__ __forceinline__ void wait_flag(const unsigned* f, unsigned base, unsigned want, unsigned* err) {
+template <typename S>
+__device__ __forceinline__ bool get_tagged(const unsigned long long* p, unsigned tag, S& v) {
+  unsigned h[kTW<S>];
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < kTW<S>; ++k) {
+    const unsigned long long w = __hip_atomic_load(p + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    ok = ok && (unsigned)(w >> 32) == tag;
+    h[k] = (unsigned)w;
+  }
+  __builtin_memcpy(&v, h, sizeof(S));
+  return ok;
+}
+
+// One wavefront polls the n tagged elements at src until all carry `tag`
+// (bounded), copying the values to dst (LDS).
+template <typename S>
+__device__ __forceinline__ void wait_tagged(const unsigned long long* src, int n, unsigned tag, S* dst,
+                                            unsigned* err) {
+  const int lane = threadIdx.x & 63;
   for (unsigned it = 0; it < kSpinLimit; ++it) {
-    const unsigned d = ld_flag(f) - base;
-    if (d >= want && d <= 3u) return;
+    bool ok = true;
+    for (int e = lane; e < n; e += 64) {
+      S v;
+      ok = get_tagged<S>(src + (size_t)e * kTW<S>, tag, v) && ok;
+      dst[e] = v;
+    }
+    if (__all(ok)) return;
     if ((it & 255u) == 255u && ld_flag(err) != 0u) return;
     __builtin_amdgcn_s_sleep(1);
   }
   __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// After a wait: the flag loads are complete before any later load issues;
-// the values behind the flag are then read agent-coherent (ld_c).
-__device__ __forceinline__ void acquire() {
-  wait_vm();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <typename S>
@@ -165,19 +188,24 @@ struct FlowArgs {
   const double* x0;
   const S* xbar;
   const S* ubar;
-  S* q;
-  S* d;
-  unsigned* flag;  // [nl]
-  unsigned* err;   // [1]
-  unsigned base;
+  const S* seeds;            // q of the leaf children (pre-pass), plain
+  unsigned long long* qt;    // [nl][nx] tagged q
+  unsigned long long* dt;    // [nl][nu] tagged d
+  unsigned long long* xt;    // [nn][nx] tagged x (forward step of the parent)
+  unsigned* err;             // [1]
+  unsigned tag;
   int nc, items;
 };
 
 // ---------------------------------------------------------------- backward item
-// d = R~^{-1}(ubar - sum_c B^c' q^c); q = K'(d - ubar) + W d - xbar + sum_c Abar^c' q^c
+// Alg. 2 backward step regrouped: with g = ubar - sum_c B^c' q^c,
+//   d = R~^{-1} g,   q = M1 g + c0 + sum_c Abar^c' q^c,
+//   M1 = (K' + W) R~^{-1} (offline, FP64),  c0 = -K' ubar - xbar.
+// c0 is formed before the children are waited for, so two mat-vec phases
+// remain on the dependency chain.
 template <typename S>
 __device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, int i) {
-  __shared__ S sAv[kMaxDim], vg[kMaxDim], vd[kMaxDim];
+  __shared__ S c0[kMaxDim], vg[kMaxDim];
   const DevProb<S>& P = A.P;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const int nx = P.nx, nu = P.nu, fc = P.fc[i], n = P.nch[i];
@@ -186,8 +214,11 @@ __device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, 
   const S* qv = reinterpret_cast<const S*>(lds + L.oQ);
   const S* xb = reinterpret_cast<const S*>(lds + L.oX);
   const S* ub = reinterpret_cast<const S*>(lds + L.oU);
-  S* redA = reinterpret_cast<S*>(lds + L.oRed);
-  S* redB = redA + kFW;
+  S* redA = reinterpret_cast<S*>(lds + L.oRed);  // sum_c Abar' q partials
+  S* redB = redA + kFW;                           // sum_c B' q
+  S* redR = redB + kFW;                           // R~^{-1} g
+  S* redM = redR + kFW;                           // M1 g
+  S* redC = redM + kFW;                           // K' ubar
   const bool leafkids = fc >= P.nl;
   for (int k0 = 0; k0 < n; k0 += L.nc) {
     const int kc = min(L.nc, n - k0);
@@ -199,18 +230,21 @@ __device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, 
     if (k0 == 0) {
       dma_words(P.Rinv + (size_t)i * nu * nu, lds, L.oR, nu * nu * es, rot++);
       dma_words(P.KR + (size_t)i * nu * nx, lds, L.oK, nu * nx * es, rot++);
-      dma_words(P.WC + (size_t)i * nu * nx, lds, L.oW, nu * nx * es, rot++);
+      dma_words(P.M1C + (size_t)i * nu * nx, lds, L.oW, nu * nx * es, rot++);
       dma_words(A.xbar + (size_t)i * nx, lds, L.oX, nx * es, rot++);
       dma_words(A.ubar + (size_t)i * nu, lds, L.oU, nu * es, rot++);
     }
-    if (leafkids) {  // seeds -xbar of the leaf children, written by the pre-pass
-      dma_words(A.q + (size_t)(fc + k0) * nx, lds, L.oQ, kc * nx * es, rot++);
-    } else if (w == 3) {  // children's q from their backward items
-      if (lane < kc) wait_flag(A.flag + fc + k0 + lane, A.base, 1u, A.err);
-      acquire();
-      S* qw = reinterpret_cast<S*>(lds + L.oQ);
-      for (int e = lane; e < kc * nx; e += 64) qw[e] = ld_c<true>(A.q + (size_t)(fc + k0) * nx + e);
+    if (leafkids)  // seeds -xbar of the leaf children, written by the pre-pass
+      dma_words(A.seeds + (size_t)(fc + k0) * nx, lds, L.oQ, kc * nx * es, rot++);
+    if (k0 == 0) {  // c0 = -K' ubar - xbar while the children may still run
+      wait_vm();
+      __syncthreads();
+      mv_part<S>(M + L.oK / es, ub, nu, nx, redC, false);
+      __syncthreads();
+      if (t < nx) c0[t] = -mv_fold<S>(redC, nx, t) - xb[t];
     }
+    if (!leafkids && w == 3)  // children's q from their backward items
+      wait_tagged<S>(A.qt + (size_t)(fc + k0) * nx * kTW<S>, kc * nx, A.tag, reinterpret_cast<S*>(lds + L.oQ), A.err);
     wait_vm();
     __syncthreads();
     for (int k = 0; k < kc; ++k) {
@@ -219,30 +253,22 @@ __device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, 
     }
     __syncthreads();  // matrices and q consumed before the next chunk's copies
   }
-  if (t < nx) sAv[t] = mv_fold<S>(redA, nx, t);
   if (t < nu) vg[t] = ub[t] - mv_fold<S>(redB, nu, t);
   __syncthreads();
-  mv_part<S>(M + L.oR / es, vg, nu, nu, redA, false);
+  mv_part<S>(M + L.oR / es, vg, nu, nu, redR, false);
+  mv_part<S>(M + L.oW / es, vg, nu, nx, redM, false);
   __syncthreads();
-  if (t < nu) {
-    const S dv = mv_fold<S>(redA, nu, t);
-    vd[t] = dv;
-    vg[t] = dv - ub[t];
-    st_c<true>(A.d + (size_t)i * nu + t, dv);
-  }
-  __syncthreads();
-  mv_part<S>(M + L.oK / es, vg, nu, nx, redA, false);
-  mv_part<S>(M + L.oW / es, vd, nu, nx, redB, false);
-  __syncthreads();
+  if (t < nu) put_tagged<S>(A.dt + ((size_t)i * nu + t) * kTW<S>, mv_fold<S>(redR, nu, t), A.tag);
   if (t < nx)
-    st_c<true>(A.q + (size_t)i * nx + t, mv_fold<S>(redA, nx, t) + mv_fold<S>(redB, nx, t) - xb[t] + sAv[t]);
-  // q and d were written by wavefront 0 (threads < 64)
-  if (w == 0) release_flag(A.flag + i, A.base + 1u);
+    put_tagged<S>(A.qt + ((size_t)i * nx + t) * kTW<S>, mv_fold<S>(redM, nx, t) + mv_fold<S>(redA, nx, t) + c0[t],
+                  A.tag);
   __syncthreads();  // LDS reuse by the next item
 }
 
 // ---------------------------------------------------------------- forward item
-// u = K x + d; x^c = Abar^c x + B^c d; x^0 = x0 at the root
+// u = K x + d; x^c = Abar^c x + B^c d; x^0 = x0 at the root. B^c d is formed
+// once d (backward step of the family) is there, before x (the parent's
+// forward step) is waited for.
 template <typename S>
 __device__ void flow_fwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, int i) {
   const DevProb<S>& P = A.P;
@@ -253,7 +279,7 @@ __device__ void flow_fwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, 
   S* M = reinterpret_cast<S*>(lds);
   S* vx = reinterpret_cast<S*>(lds + L.oX);
   S* vd = reinterpret_cast<S*>(lds + L.oU);
-  S* red = reinterpret_cast<S*>(lds + L.oRed);
+  S* red = reinterpret_cast<S*>(lds + L.oRed);  // [child k] partials; [nc] K x
   for (int k0 = 0; k0 < n; k0 += L.nc) {
     const int kc = min(L.nc, n - k0);
     int rot = 1;
@@ -263,40 +289,34 @@ __device__ void flow_fwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, 
     }
     if (k0 == 0) {
       dma_words(P.KC + (size_t)i * nx * nu, lds, L.oK, nx * nu * es, rot++);
-      if (w == 0) {
-        // d^i from the backward sweep (ordered before the parent's forward
-        // step through the chain of flags), x^i from the parent (x0 at the root)
-        if (i == 0) wait_flag(A.flag, A.base, 1u, A.err);
-        else wait_flag(A.flag + P.anc[i], A.base, 2u, A.err);
-        acquire();
-        if (lane < nx) {
-          S xv;
-          if (i == 0) {
-            xv = (S)A.x0[lane];
-            st_c<true>(A.zout + 1 + lane, xv);
-          } else {
-            xv = ld_c<true>(A.zout + O.x(i) + lane);
-          }
-          vx[lane] = xv;
-        }
-        if (lane < nu) vd[lane] = ld_c<true>(A.d + (size_t)i * nu + lane);
-      }
+      if (w == 0)  // d^i of the family's backward step
+        wait_tagged<S>(A.dt + (size_t)i * nu * kTW<S>, nu, A.tag, vd, A.err);
     }
     wait_vm();
     __syncthreads();
-    if (k0 == 0) mv_part<S>(M + L.oK / es, vx, nx, nu, red + L.nc * kFW, false);
-    for (int k = 0; k < kc; ++k) {
-      mv_part<S>(M + L.oA / es + k * (L.sA / es), vx, nx, nx, red + k * kFW, false);
-      mv_part<S>(M + L.oB / es + k * (L.sB / es), vd, nu, nx, red + k * kFW, true);
+    for (int k = 0; k < kc; ++k) mv_part<S>(M + L.oB / es + k * (L.sB / es), vd, nu, nx, red + k * kFW, false);
+    if (k0 == 0 && w == 0) {  // x^i from the parent's forward step (x0 at the root)
+      if (i != 0) {
+        wait_tagged<S>(A.xt + (size_t)i * nx * kTW<S>, nx, A.tag, vx, A.err);
+      } else if (lane < nx) {
+        const S xv = (S)A.x0[lane];
+        A.zout[1 + lane] = xv;
+        vx[lane] = xv;
+      }
     }
     __syncthreads();
-    if (k0 == 0 && t < nu) st_c<true>(A.zout + O.u(i) + t, mv_fold<S>(red + L.nc * kFW, nu, t) + vd[t]);
+    if (k0 == 0) mv_part<S>(M + L.oK / es, vx, nx, nu, red + L.nc * kFW, false);
+    for (int k = 0; k < kc; ++k) mv_part<S>(M + L.oA / es + k * (L.sA / es), vx, nx, nx, red + k * kFW, true);
+    __syncthreads();
+    if (k0 == 0 && t < nu) A.zout[O.u(i) + t] = mv_fold<S>(red + L.nc * kFW, nu, t) + vd[t];
     for (int k = 0; k < kc; ++k)
-      if (t < nx) st_c<true>(A.zout + O.x(fc + k0 + k) + t, mv_fold<S>(red + k * kFW, nx, t));
+      if (t < nx) {
+        const S xc = mv_fold<S>(red + k * kFW, nx, t);
+        A.zout[O.x(fc + k0 + k) + t] = xc;
+        if (fc + k0 + k < P.nl) put_tagged<S>(A.xt + ((size_t)(fc + k0 + k) * nx + t) * kTW<S>, xc, A.tag);
+      }
     __syncthreads();  // red and the matrices are reused by the next chunk / item
   }
-  // u^i and the children's x were written by wavefront 0 (threads < 64)
-  if (w == 0) release_flag(A.flag + i, A.base + 2u);
 }
 
 // W: minimum wavefronts per SIMD the register allocation must allow.
@@ -334,18 +354,21 @@ template <typename S>
 hipError_t launch_sweeps_flow(const Problem& P, const DevProb<S>& D, S* zout, const double* x0, const S* xbar,
                               const S* ubar, S* q, S* d, hipStream_t st) {
   const FlowState& F = P.flow;
-  if (!F.flag || F.grid <= 0) return hipErrorInvalidValue;
+  if (!F.qt || F.grid <= 0) return hipErrorInvalidValue;
   FlowArgs<S> A;
   A.P = D;
   A.zout = zout;
   A.x0 = x0;
   A.xbar = xbar;
   A.ubar = ubar;
-  A.q = q;
-  A.d = d;
-  A.flag = F.flag;
+  A.seeds = q;
+  (void)d;
+  A.qt = F.qt;
+  A.dt = F.dt;
+  A.xt = F.xt;
   A.err = F.err;
-  A.base = 4u * (P.flow_epoch++);
+  if (++P.flow_epoch == 0u) P.flow_epoch = 1u;  // tag 0 is the cleared state
+  A.tag = P.flow_epoch;
   A.nc = F.nc;
   A.items = 2 * P.tree->nl;
   const int grid = std::min(F.grid, A.items);

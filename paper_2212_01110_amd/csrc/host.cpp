@@ -199,7 +199,7 @@ int upload(Problem& P, const spock_problem_data& d, const std::vector<double>& A
   const int nn = T.nn, nl = T.nl, nx = P.nx, nu = P.nu;
   // sizes (elements)
   const size_t nvec = (size_t)nn * (4 * nx + 3 * nu) + 2 * (size_t)nn + 64;
-  const size_t nmat = (size_t)nn * (2 * nx * nx + 2 * nx * nu) + (size_t)nl * (2 * nu * nx + nu * nu + nx * nu);
+  const size_t nmat = (size_t)nn * (2 * nx * nx + 2 * nx * nu) + (size_t)nl * (2 * nu * nx + nu * nu + 2 * nx * nu);
   const size_t bytes = (nvec + nmat) * sizeof(S) + (3 * (size_t)nn + T.N + 2) * sizeof(int) + 64 * 256;
   std::vector<char> host(bytes, 0);
   void* dmem = nullptr;
@@ -302,6 +302,22 @@ int upload(Problem& P, const spock_problem_data& d, const std::vector<double>& A
       for (int j = 0; j < nu; ++j) WCp.first[(size_t)i * nu * nx + (size_t)j * nx + r] = (S)Wm[(size_t)r * nu + j];
   }
   D.KR = KRp.second; D.KC = KCp.second; D.Rinv = Rip.second; D.WC = WCp.second;
+  // M1 = (K' + W) R~^{-1} (n_x x n_u, FP64): with g = ubar - sum_c B^c' q^c,
+  // the backward step is d = R~^{-1} g, q = M1 g - K' ubar - xbar + sum_c Abar^c' q^c
+  // (the same recursion regrouped); stored like W
+  auto M1p = take((size_t)nl * nu * nx, S{});
+  parallel_for(nl, [&](int i) {
+    const double* Km = K.data() + (size_t)i * nu * nx;  // [nu][nx]
+    const double* Wm = W.data() + (size_t)i * nx * nu;  // [nx][nu]
+    const double* Ri = Rinv.data() + (size_t)i * nu * nu;
+    for (int r = 0; r < nx; ++r)
+      for (int j = 0; j < nu; ++j) {
+        double acc = 0;
+        for (int l = 0; l < nu; ++l) acc += (Km[(size_t)l * nx + r] + Wm[(size_t)r * nu + l]) * Ri[(size_t)l * nu + j];
+        M1p.first[(size_t)i * nu * nx + (size_t)j * nx + r] = (S)acc;
+      }
+  });
+  D.M1C = M1p.second;
   const size_t used = off;
   if (used > bytes) {
     (void)hipFree(dmem);
@@ -667,22 +683,30 @@ int ensure_flow(Problem& P, int occ = 0) {
   int nc = std::min(maxch, 8);
   while (nc > 1 && flow_lds_bytes(P.nx, P.nu, nc, (int)sizeof(S)) > budget) --nc;
   const int lds = flow_lds_bytes(P.nx, P.nu, nc, (int)sizeof(S));
-  int dev = 0, ncu = 0, coop = 0, nb = 0;
+  int dev = 0, ncu = 0, coop = 0, nb = 0, smax = 0;
   if (hipGetDevice(&dev) != hipSuccess) return SPOCK_EHIP;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return SPOCK_EHIP;
   if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess) return SPOCK_EHIP;
-  if (lds <= 64 * 1024 &&
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, flow_kernel<S>(occ), 256, (size_t)lds) != hipSuccess)
+  if (hipDeviceGetAttribute(&smax, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return SPOCK_EHIP;
+  const bool fits = lds <= smax;
+  if (fits && lds > 64 * 1024 &&
+      hipFuncSetAttribute(flow_kernel<S>(occ), hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
     return SPOCK_EHIP;
-  const size_t bytes = sizeof(unsigned) * (size_t)(T.nl + 64);
+  if (fits && hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, flow_kernel<S>(occ), 256, (size_t)lds) != hipSuccess)
+    return SPOCK_EHIP;
+  const size_t tw = sizeof(S) / 4;  // tagged words per element
+  const size_t nq = (size_t)T.nl * P.nx * tw, nd = (size_t)T.nl * P.nu * tw, nxw = (size_t)T.nn * P.nx * tw;
+  const size_t bytes = 256 + sizeof(unsigned long long) * (nq + nd + nxw);
   if (hipMalloc(&F.mem, bytes) != hipSuccess) return SPOCK_ENOMEM;
   if (hipMemset(F.mem, 0, bytes) != hipSuccess) return SPOCK_EHIP;
   F.err = static_cast<unsigned*>(F.mem);
-  F.flag = F.err + 64;
+  F.qt = reinterpret_cast<unsigned long long*>(static_cast<char*>(F.mem) + 256);
+  F.dt = F.qt + nq;
+  F.xt = F.dt + nd;
   F.nc = nc;
   F.occ = occ;
   F.elem = (int)sizeof(S);
-  F.grid = (coop && lds <= 64 * 1024) ? nb * ncu : 0;
+  F.grid = (coop && fits) ? nb * ncu : 0;
   return SPOCK_OK;
 }
 

@@ -47,6 +47,7 @@ struct DevProb {
   const S* KC;   // [nl][nx][nu]  K column-major        (K x, forward)
   const S* Rinv; // [nl][nu][nu]  inverse of R~ (symmetric)
   const S* WC;   // [nl][nu][nx]  W = sum_c Abar'P B, column-major (W d, backward)
+  const S* M1C;  // [nl][nu][nx]  M1 = (K' + W) R~^{-1}, column-major (dataflow backward step)
   S alpha;
 };
 
@@ -63,17 +64,20 @@ struct DevArrays {
   size_t bytes = 0;
 };
 
-// Device state of the dataflow form of the sweeps: a completion flag per
-// family (epoch-tagged, never cleared) and an error word raised by a bounded
-// wait that gave up.
+// Device state of the dataflow form of the sweeps: the tagged exchange
+// buffers (q, d of the backward step, x of the forward step; 64-bit words
+// holding the launch epoch and half of a value, zeroed once and never
+// cleared) and an error word raised by a bounded poll that gave up.
 struct FlowState {
   void* mem = nullptr;
-  unsigned* flag = nullptr;  // [nl]
-  unsigned* err = nullptr;   // [1]
-  int nc = 1;                // children per LDS chunk
-  int grid = 0;              // resident workgroups (0: form unavailable)
-  int occ = 2;               // register budget: 2 or 4 wavefronts per SIMD
-  int elem = 0;              // element size the state was sized for
+  unsigned* err = nullptr;          // [1]
+  unsigned long long* qt = nullptr;  // [nl][nx][words per element]
+  unsigned long long* dt = nullptr;  // [nl][nu][...]
+  unsigned long long* xt = nullptr;  // [nn][nx][...]
+  int nc = 1;                        // children per LDS chunk
+  int grid = 0;                      // resident workgroups (0: form unavailable)
+  int occ = 2;                       // register budget: 2 or 4 wavefronts per SIMD
+  int elem = 0;                      // element size the state was sized for
 };
 
 struct Problem {
@@ -104,7 +108,7 @@ struct Problem {
   int team_pp = 64;  // lanes per family of the parallel pre/post passes
   bool tuned = false;
   FlowState flow;
-  mutable unsigned flow_epoch = 1;  // launches of the dataflow form so far
+  mutable unsigned flow_epoch = 0;  // tag of the last dataflow launch (never 0 once launched)
   // when set, launch_T records prof[0..4] before the pre-pass, after it,
   // after the sweeps, after the post-pass and at the end (timing aid)
   hipEvent_t* prof = nullptr;
