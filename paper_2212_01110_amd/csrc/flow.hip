@@ -91,24 +91,29 @@ __device__ __forceinline__ void wait_vm() {
 }
 
 // Partial mat-vec from LDS: M input-major (element (out o, in k) at
-// k * nout + o), v (nin) in LDS; thread t < G * nout sums the products of
-// inputs k = g, g + G, ... (g = t / nout) of output o = t % nout, with four
-// independent accumulators, into red[t] (added to it when acc).
+// k * nout + o), v (nin) in LDS. Thread t < G * nout (g = t / nout,
+// o = t % nout) sums the
+// products of the inputs k in [g * kb, (g + 1) * kb), kb a multiple of 4:
+// the vector is read four entries at a time, the matrix down one column
+// with a single running address, into red[t] (added to it when acc).
 template <typename S>
 __device__ __forceinline__ void mv_part(const S* M, const S* v, int nin, int nout, S* red, bool acc) {
-  const int G = min(kFW / nout, kFoldMax), span = G * nout, t = threadIdx.x;
-  if (t < span) {
-    const int n = nin * nout;
-    int e = t, k = t / nout;
-    S a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-    for (; e + 3 * span < n; e += 4 * span, k += 4 * G) {
-      a0 += M[e] * v[k];
-      a1 += M[e + span] * v[k + G];
-      a2 += M[e + 2 * span] * v[k + 2 * G];
-      a3 += M[e + 3 * span] * v[k + 3 * G];
+  const int G = min(kFW / nout, kFoldMax), t = threadIdx.x;
+  if (t < G * nout) {
+    const int g = t / nout, o = t - g * nout;
+    const int kb = (((nin + G - 1) / G) + 3) & ~3;
+    const int k0 = g * kb, k1 = min(nin, k0 + kb);
+    const S* mp = M + (size_t)k0 * nout + o;
+    S a0 = 0, a1 = 0;
+    int k = k0;
+    for (; k + 4 <= k1; k += 4, mp += 4 * nout) {
+      const S v0 = v[k], v1 = v[k + 1], v2 = v[k + 2], v3 = v[k + 3];
+      const S m0 = mp[0], m1 = mp[nout], m2 = mp[2 * nout], m3 = mp[3 * nout];
+      a0 += m0 * v0 + m2 * v2;
+      a1 += m1 * v1 + m3 * v3;
     }
-    for (; e < n; e += span, k += G) a0 += M[e] * v[k];
-    const S s = (a0 + a1) + (a2 + a3);
+    for (; k < k1; ++k, mp += nout) a0 += mp[0] * v[k];
+    const S s = a0 + a1;
     red[t] = acc ? red[t] + s : s;
   }
 }
@@ -345,7 +350,7 @@ int flow_lds_bytes(int nx, int nu, int nc, int elem) { return FlowLds(nx, nu, nc
 
 template <typename S>
 const void* flow_kernel(int occ) {
-  return occ >= 4 ? reinterpret_cast<const void*>(&k_T_flow<S, 4>) : reinterpret_cast<const void*>(&k_T_flow<S, 2>);
+  return occ >= 5 ? reinterpret_cast<const void*>(&k_T_flow<S, 5>) : reinterpret_cast<const void*>(&k_T_flow<S, 4>);
 }
 template const void* flow_kernel<double>(int);
 template const void* flow_kernel<float>(int);

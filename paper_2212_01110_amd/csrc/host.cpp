@@ -668,8 +668,8 @@ template <typename S>
 int ensure_flow(Problem& P, int occ = 0) {
   FlowState& F = P.flow;
   const Tree& T = *P.tree;
-  if (occ == 0) occ = F.mem ? F.occ : 2;
-  if (const char* env = std::getenv("SPOCK_FLOW_OCC")) occ = std::atoi(env) >= 4 ? 4 : 2;
+  if (occ == 0) occ = F.mem ? F.occ : 5;
+  if (const char* env = std::getenv("SPOCK_FLOW_OCC")) occ = std::atoi(env) >= 5 ? 5 : 4;
   if (F.mem && F.elem == (int)sizeof(S) && F.occ == occ) {
     if (hipMemset(F.err, 0, sizeof(unsigned)) != hipSuccess) return SPOCK_EHIP;
     return SPOCK_OK;
@@ -784,9 +784,9 @@ int autotune(Problem& P, hipStream_t st) {
   const Tree& T = *P.tree;
   std::vector<std::pair<int, int>> cands = {{8, T.N}, {16, T.N}, {32, T.N}, {64, T.N}, {kTeamWG, T.N}};
   // dataflow form at both register budgets (the cut field carries the
-  // budget: 2 or 4 wavefronts per SIMD)
-  if (ensure_flow<S>(P, 2) == SPOCK_OK && P.flow.grid > 0) cands.push_back({kTeamFlow, 2});
+  // budget: 4 or 5 wavefronts per SIMD)
   if (ensure_flow<S>(P, 4) == SPOCK_OK && P.flow.grid > 0) cands.push_back({kTeamFlow, 4});
+  if (ensure_flow<S>(P, 5) == SPOCK_OK && P.flow.grid > 0) cands.push_back({kTeamFlow, 5});
   int ncut = 0;
   for (int t = std::max(0, T.N - 64); t < T.N && ncut < 3; ++t)
     if (T.stage_off[t + 1] - T.stage_off[t] >= 128) {

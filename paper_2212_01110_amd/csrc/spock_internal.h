@@ -76,7 +76,7 @@ struct FlowState {
   unsigned long long* xt = nullptr;  // [nn][nx][...]
   int nc = 1;                        // children per LDS chunk
   int grid = 0;                      // resident workgroups (0: form unavailable)
-  int occ = 2;                       // register budget: 2 or 4 wavefronts per SIMD
+  int occ = 5;                       // register budget: 4 or 5 wavefronts per SIMD
   int elem = 0;                      // element size the state was sized for
 };
 
