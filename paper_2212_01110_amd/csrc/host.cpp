@@ -588,6 +588,10 @@ extern "C" int spock_problem_factor(const spock_tree* th, const spock_problem_da
   if (const char* env = std::getenv("SPOCK_CUT")) cut = std::atoi(env);
   set_mapping(P, team, cut);
   P.team_pp = next_pow2_team(std::max(nx, nu));
+  if (const char* env = std::getenv("SPOCK_TEAM_PP")) {
+    const int v = std::atoi(env);
+    if ((v == 8 || v == 16 || v == 32 || v == 64) && v * 4 >= P.team_pp) P.team_pp = v;
+  }
   const int rc = (d->precision == SPOCK_FP64) ? upload<double>(P, *d, Abar, K, Rinv, W)
                                               : upload<float>(P, *d, Abar, K, Rinv, W);
   if (rc != SPOCK_OK) {
@@ -814,10 +818,36 @@ int autotune(Problem& P, hipStream_t st) {
       best_map = c;
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   if (best_map.first == kTeamFlow && ensure_flow<S>(P, best_map.second) != SPOCK_OK) return SPOCK_EHIP;
   set_mapping(P, best_map.first, best_map.second);
+  // lanes per family of the parallel pre/post passes (fewer lanes: more
+  // families in flight per workgroup, longer per-lane loops)
+  {
+    const int tmin = next_pow2_team(std::max(P.nx, P.nu));
+    float best_pp = 1e30f;
+    int pick = P.team_pp;
+    for (int tpp : {16, 32, 64}) {
+      if (tpp * 4 < tmin) continue;  // at most 4 components per lane
+      P.team_pp = tpp;
+      HIP_TRY(launch_T<S>(P, W.pool[0], W.pool[1], W.x0_zero, W.q, W.d, W.xbar, W.ubar, W.partials, W.stats, st,
+                          W.eta_zero, true));
+      HIP_TRY(hipEventRecord(e0, st));
+      for (int r = 0; r < 3; ++r)
+        HIP_TRY(launch_T<S>(P, W.pool[0], W.pool[1], W.x0_zero, W.q, W.d, W.xbar, W.ubar, W.partials, W.stats,
+                            st, W.eta_zero, true));
+      HIP_TRY(hipEventRecord(e1, st));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_pp) {
+        best_pp = ms;
+        pick = tpp;
+      }
+    }
+    P.team_pp = pick;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   P.tuned = true;
   return SPOCK_OK;
 }

@@ -233,7 +233,8 @@ MAP_CASES = ["config2", "b3-1-2", "b2x3-nx64", "b5-wide", "config1"]
 
 
 @pytest.mark.parametrize("prec", list(FP))
-@pytest.mark.parametrize("mapping", ["8", "16", "32", "64", "256", "256c0", "256c1", "256c2", "512", "512n1"])
+@pytest.mark.parametrize("mapping", ["8", "16", "32", "64", "256", "256c0", "256c1", "256c2", "512", "512n1",
+                                     "512p16", "512p32"])
 @pytest.mark.parametrize("name", MAP_CASES)
 def test_T_every_mapping(name, mapping, prec, monkeypatch):
     # team sizes 8..64, one workgroup per family with per-stage launches,
@@ -242,6 +243,10 @@ def test_T_every_mapping(name, mapping, prec, monkeypatch):
     # families with several children take several chunks)
     team, _, cut = mapping.partition("c")
     if team.startswith("512"):
+        # p16 / p32: 16 or 32 lanes per family in the pre/post passes
+        team, _, pp = team.partition("p")
+        if pp:
+            monkeypatch.setenv("SPOCK_TEAM_PP", pp)
         team, _, _ = team.partition("n")
         monkeypatch.setenv("SPOCK_FLOW_LDS", "4096" if mapping.endswith("n1") else "40960")
     monkeypatch.setenv("SPOCK_TEAM", team)
