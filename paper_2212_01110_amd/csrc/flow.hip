@@ -9,10 +9,11 @@
 //                  every child family comes first)
 //   [nl, 2 nl)     forward step of family t-nl (breadth-first: the parent
 //                  comes first)
-// Workgroup b runs items b, b + G, b + 2G, ... (G = grid size, every
-// workgroup resident: cooperative launch). An item waits only on items with
-// a smaller index, so the smallest unfinished item never waits and the
-// launch drains.
+// Workgroup b runs items b, b + G, b + 2G, ... (G = grid size = the
+// resident capacity from the occupancy of the kernel; a cooperative launch
+// guarantees residency, a plain one, the default, has it whenever the device
+// runs nothing else). An item waits only on items with a smaller index, so
+// the smallest unfinished item never waits and the launch drains.
 //
 // Values crossing workgroups (q and d of the backward step, x of the
 // forward step) travel as tagged words: each 32-bit half of a value shares a
@@ -379,7 +380,11 @@ hipError_t launch_sweeps_flow(const Problem& P, const DevProb<S>& D, S* zout, co
   const int grid = std::min(F.grid, A.items);
   const size_t lds = (size_t)flow_lds_bytes(P.nx, P.nu, F.nc, (int)sizeof(S));
   void* args[] = {&A};
-  return hipLaunchCooperativeKernel(flow_kernel<S>(F.occ), dim3(grid), dim3(kFW), args, (unsigned)lds, st);
+  if (F.coop) return hipLaunchCooperativeKernel(flow_kernel<S>(F.occ), dim3(grid), dim3(kFW), args, (unsigned)lds, st);
+  // plain launch of a grid sized to the resident capacity (every wait is
+  // bounded, so a grid that were not all resident ends with the error word
+  // set, never hangs)
+  return hipLaunchKernel(flow_kernel<S>(F.occ), dim3(grid), dim3(kFW), args, lds, st);
 }
 template hipError_t launch_sweeps_flow<double>(const Problem&, const DevProb<double>&, double*, const double*,
                                                const double*, const double*, double*, double*, hipStream_t);

@@ -709,6 +709,7 @@ int ensure_flow(Problem& P, int occ = 0) {
   F.xt = F.dt + nd;
   F.nc = nc;
   F.occ = occ;
+  if (const char* env = std::getenv("SPOCK_FLOW_COOP")) F.coop = std::atoi(env) != 0;
   F.elem = (int)sizeof(S);
   F.grid = (coop && fits) ? nb * ncu : 0;
   return SPOCK_OK;

@@ -274,11 +274,14 @@ def test_T_every_mapping(name, mapping, prec, monkeypatch):
     assert relerr(host(zo), reff) <= 50 * tol
 
 
+@pytest.mark.parametrize("coop", ["0", "1"])
 @pytest.mark.parametrize("prec", list(FP))
-def test_flow_form_repeated_launches(prec, monkeypatch):
-    # the dataflow form tags its completion flags with a launch epoch: back to
-    # back launches on the same problem (T, prox_f, T) must each be exact
+def test_flow_form_repeated_launches(prec, coop, monkeypatch):
+    # the dataflow form tags its exchanged words with a launch epoch: back to
+    # back launches on the same problem (T, prox_f, T) must each be exact,
+    # with a plain and with a cooperative launch
     monkeypatch.setenv("SPOCK_TEAM", "512")
+    monkeypatch.setenv("SPOCK_FLOW_COOP", coop)
     inst = CASES["b3-1-2"]
     gp, op = build(inst, FP[prec][0])
     tol = FP[prec][1]
