@@ -111,35 +111,6 @@ void chol_inverse(int n, const double* Lc, double* Inv) {
   }
 }
 
-// Eigenvalues of a small symmetric matrix (cyclic Jacobi).
-void sym_eigs(int n, std::vector<double> A, std::vector<double>& ev) {
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    double off = 0;
-    for (int i = 0; i < n; ++i)
-      for (int j = i + 1; j < n; ++j) off += A[i * n + j] * A[i * n + j];
-    if (off < 1e-300) break;
-    for (int p = 0; p < n; ++p)
-      for (int q = p + 1; q < n; ++q) {
-        const double apq = A[p * n + q];
-        if (apq == 0.0) continue;
-        const double th = 0.5 * (A[q * n + q] - A[p * n + p]) / apq;
-        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
-        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
-        for (int k = 0; k < n; ++k) {
-          const double akp = A[k * n + p], akq = A[k * n + q];
-          A[k * n + p] = c * akp - s * akq;
-          A[k * n + q] = s * akp + c * akq;
-        }
-        for (int k = 0; k < n; ++k) {
-          const double apk = A[p * n + k], aqk = A[q * n + k];
-          A[p * n + k] = c * apk - s * aqk;
-          A[q * n + k] = s * apk + c * aqk;
-        }
-      }
-  }
-  ev.resize(n);
-  for (int i = 0; i < n; ++i) ev[i] = A[i * n + i];
-}
 
 int next_pow2_team(int v) {
   int t = 8;
@@ -655,6 +626,7 @@ struct Work {
   double* stats = nullptr;    // [8]
   double* dots = nullptr;     // [16]
   double* gamma = nullptr;    // [8]
+  double* aaG = nullptr;      // Anderson Gram matrix [16] (by slot) and right-hand side [16..20)
   double* vpart = nullptr;    // vector-kernel partials [blocks][8]
   S* eta_zero = nullptr;      // n_eta zeros
   double* x0_zero = nullptr;  // kMaxDim zeros (autotuning input)
@@ -730,6 +702,7 @@ int ensure_work(Problem& P, Work<S>& W) {
   add(sizeof(double) * 8);
   add(sizeof(double) * 16);
   add(sizeof(double) * 8);
+  add(sizeof(double) * 32);
   add(sizeof(double) * (size_t)nblk * 8);
   add(sizeof(S) * (size_t)P.neta);
   add(sizeof(double) * kMaxDim);
@@ -757,6 +730,7 @@ int ensure_work(Problem& P, Work<S>& W) {
   W.stats = reinterpret_cast<double*>(take(sizeof(double) * 8));
   W.dots = reinterpret_cast<double*>(take(sizeof(double) * 16));
   W.gamma = reinterpret_cast<double*>(take(sizeof(double) * 8));
+  W.aaG = reinterpret_cast<double*>(take(sizeof(double) * 32));
   W.vpart = reinterpret_cast<double*>(take(sizeof(double) * (size_t)nblk * 8));
   W.eta_zero = reinterpret_cast<S*>(take(sizeof(S) * (size_t)P.neta));
   W.x0_zero = reinterpret_cast<double*>(take(sizeof(double) * kMaxDim));
@@ -868,14 +842,20 @@ struct Solver {
   const double* x0;
   long long nv;
   int t_evals = 0;
+  double last_kept = 0;  // kept columns of the last device Anderson solve
   std::vector<double> hbuf = std::vector<double>(16);
 
   Solver(Problem& p, hipStream_t s, const double* x) : P(p), st(s), x0(x), nv(p.nz + p.neta) {}
 
-  int T(const S* v, S* Tv, Stats& out) {
+  // T(v) and its statistics; with md, also <v - T(v), md> (line search),
+  // fetched in the same transfer (statistics slot 6)
+  int T(const S* v, S* Tv, Stats& out, const S* md = nullptr, double* rdot = nullptr) {
     HIP_TRY(launch_T<S>(P, v, Tv, x0, W.q, W.d, W.xbar, W.ubar, W.partials, W.stats, st, W.eta_zero, true));
-    HIP_TRY(hipMemcpyAsync(hbuf.data(), W.stats, 6 * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (md) HIP_TRY(launch_rdot<S>(nv, v, Tv, md, W.vpart, W.stats + 6, st));
+    HIP_TRY(hipMemcpyAsync(hbuf.data(), W.stats, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    last_kept = hbuf[7];
+    if (rdot) *rdot = hbuf[6];
     out.xip = hbuf[0];
     out.xid = hbuf[1];
     out.om2 = hbuf[2];
@@ -892,17 +872,14 @@ struct Solver {
   }
 };
 
-// Anderson ring: ages of active columns (oldest first) and the Gram matrix.
+// Anderson ring: slots of the active columns, oldest first (the Gram matrix
+// and the right-hand side, indexed by slot, live on the device).
 struct AARing {
   int m = 0;
-  std::vector<int> order;                // active slots, oldest first
-  std::vector<double> G;                 // m x m, indexed by slot
-  std::vector<double> rhs;               // <dR_slot, r>
+  std::vector<int> order;
   void reset(int mm) {
     m = mm;
     order.clear();
-    G.assign((size_t)m * m, 0.0);
-    rhs.assign(m, 0.0);
   }
   int free_slot() const {
     for (int s = 0; s < m; ++s)
@@ -914,39 +891,6 @@ struct AARing {
 // Solves the Gram system for the active columns after applying the rank rule
 // (drop the oldest column while lambda_min/lambda_max(G) < 1e-12, i.e.
 // sigma_min/sigma_max(dR) < 1e-6). Returns the number of columns kept.
-int aa_solve(AARing& A, std::vector<double>& gamma) {
-  while (!A.order.empty()) {
-    const int k = (int)A.order.size();
-    std::vector<double> Gs((size_t)k * k);
-    for (int a = 0; a < k; ++a)
-      for (int b = 0; b < k; ++b) Gs[(size_t)a * k + b] = A.G[(size_t)A.order[a] * A.m + A.order[b]];
-    std::vector<double> ev;
-    sym_eigs(k, Gs, ev);
-    const double lmax = *std::max_element(ev.begin(), ev.end());
-    const double lmin = *std::min_element(ev.begin(), ev.end());
-    if (lmax > 0.0 && lmin / lmax >= 1e-12) {
-      std::vector<double> Lc = Gs;
-      if (cholesky(k, Lc.data())) {
-        gamma.assign(k, 0.0);
-        std::vector<double> y(k);
-        for (int i = 0; i < k; ++i) {
-          double s = A.rhs[A.order[i]];
-          for (int j = 0; j < i; ++j) s -= Lc[(size_t)i * k + j] * y[j];
-          y[i] = s / Lc[(size_t)i * k + i];
-        }
-        for (int i = k - 1; i >= 0; --i) {
-          double s = y[i];
-          for (int j = i + 1; j < k; ++j) s -= Lc[(size_t)j * k + i] * gamma[j];
-          gamma[i] = s / Lc[(size_t)i * k + i];
-        }
-        return k;
-      }
-    }
-    A.order.erase(A.order.begin());
-  }
-  gamma.clear();
-  return 0;
-}
 
 template <typename S>
 int solve_impl(Problem& P, const double* x0, const spock_settings& s, S* vio, spock_info& info,
@@ -1010,7 +954,18 @@ int solve_impl(Problem& P, const double* x0, const spock_settings& s, S* vio, sp
   AARing ring;
   ring.reset(s.m);
   bool have_prev = false;
-  std::vector<double> gamma, hd(16);
+  // The Anderson Gram matrix lives on the device; the solve (with its rank
+  // rule) runs there right after the push, and the number of columns it kept
+  // comes back with the statistics of the next evaluation of T, which drops
+  // the oldest columns from the host's order before the next push.
+  int pending_k = -1;
+  auto apply_kept = [&]() {
+    if (pending_k < 0) return;
+    const int kept = (int)SV.last_kept;
+    const int drop = std::max(0, std::min(pending_k, pending_k - kept));
+    ring.order.erase(ring.order.begin(), ring.order.begin() + std::min(drop, (int)ring.order.size()));
+    pending_k = -1;
+  };
   for (;;) {
     if (Sc.xi() <= tol) return finish(SPOCK_CONVERGED);
     if (k >= s.max_iters) return finish(SPOCK_MAXITER);
@@ -1024,33 +979,28 @@ int solve_impl(Problem& P, const double* x0, const spock_settings& s, S* vio, sp
         slot = ring.free_slot();
       }
       VecPtrs<S> olds{};
+      AAPush a{};
       const int mo = (int)ring.order.size();
-      for (int j = 0; j < mo; ++j) olds.p[j] = dR[ring.order[j]];
+      a.m = ring.m;
+      a.mo = mo;
+      a.slot = slot;
+      for (int j = 0; j < mo; ++j) {
+        olds.p[j] = dR[ring.order[j]];
+        a.order_old[j] = ring.order[j];
+      }
       HIP_TRY(launch_aa_push<S>(nv, v, vprev, Tv, rprev, rcur, dV[slot], dR[slot], mo, olds, W.vpart,
                                 W.dots, st));
-      rc = SV.fetch(hd.data(), W.dots, 2 * mo + 2);
-      if (rc) return rc;
-      for (int j = 0; j < mo; ++j) {
-        ring.G[(size_t)ring.order[j] * ring.m + slot] = hd[j];
-        ring.G[(size_t)slot * ring.m + ring.order[j]] = hd[j];
-        ring.rhs[ring.order[j]] = hd[mo + 1 + j];
-      }
-      ring.G[(size_t)slot * ring.m + slot] = hd[mo];
-      ring.rhs[slot] = hd[2 * mo + 1];
+      HIP_TRY(launch_aa_solve(W.aaG, W.aaG + 16, W.dots, a, W.gamma, W.stats + 7, st));
       ring.order.push_back(slot);
-    } else {
-      HIP_TRY(launch_lincomb<S>(nv, rcur, 1.0, v, -1.0, Tv, st));
-    }
-    const int kept = aa_solve(ring, gamma);
-    if (kept > 0) {
+      pending_k = mo + 1;
       VecPtrs<S> pv{}, pr{};
-      for (int j = 0; j < kept; ++j) {
+      for (int j = 0; j < mo + 1; ++j) {
         pv.p[j] = dV[ring.order[j]];
         pr.p[j] = dR[ring.order[j]];
       }
-      HIP_TRY(hipMemcpyAsync(W.gamma, gamma.data(), kept * sizeof(double), hipMemcpyHostToDevice, st));
-      HIP_TRY(launch_aa_dir<S>(nv, rcur, kept, pv, pr, W.gamma, dir, st));
+      HIP_TRY(launch_aa_dir<S>(nv, rcur, mo + 1, pv, pr, W.gamma, dir, st));
     } else {
+      HIP_TRY(launch_lincomb<S>(nv, rcur, 1.0, v, -1.0, Tv, st));
       HIP_TRY(launch_lincomb<S>(nv, dir, -1.0, rcur, 0.0, nullptr, st));
     }
     const double omega = Sc.omega();
@@ -1067,6 +1017,7 @@ int solve_impl(Problem& P, const double* x0, const spock_settings& s, S* vio, sp
       info.n_k0++;
       rc = SV.T(v, Tv, Sc);
       if (rc) return rc;
+      apply_kept();
       ++k;
       if (!Sc.ok()) return finish(SPOCK_NUMERICAL);
       continue;
@@ -1079,8 +1030,10 @@ int solve_impl(Problem& P, const double* x0, const spock_settings& s, S* vio, sp
     bool accepted = false;
     for (int ls = 0; ls < s.max_ls; ++ls) {
       HIP_TRY(launch_lincomb<S>(nv, vt, 1.0, v, tau, dir, st));
-      rc = SV.T(vt, Tvt, St);
+      double rdot = 0;
+      rc = SV.T(vt, Tvt, St, Md, &rdot);
       if (rc) return rc;
+      apply_kept();
       if (!St.ok()) {
         tau *= s.beta;
         info.n_backtracks++;
@@ -1097,10 +1050,7 @@ int solve_impl(Problem& P, const double* x0, const spock_settings& s, S* vio, sp
         accepted = true;
         break;
       }
-      HIP_TRY(launch_rdot<S>(nv, vt, Tvt, Md, W.vpart, W.dots, st));
-      rc = SV.fetch(hd.data(), W.dots, 1);
-      if (rc) return rc;
-      const double rho = om_t * om_t - tau * hd[0];
+      const double rho = om_t * om_t - tau * rdot;
       if (rho >= s.sigma * om_t * omega) {  // K2: v - lambda rho / om_t^2 (vt - Tvt)
         const double c = s.lambda * rho / (om_t * om_t);
         HIP_TRY(launch_lincomb3<S>(nv, spare, 1.0, v, -c, vt, c, Tvt, st));
@@ -1109,6 +1059,7 @@ int solve_impl(Problem& P, const double* x0, const spock_settings& s, S* vio, sp
         info.n_k2++;
         rc = SV.T(v, Tv, Sc);
         if (rc) return rc;
+        apply_kept();
         accepted = true;
         break;
       }
@@ -1122,6 +1073,7 @@ int solve_impl(Problem& P, const double* x0, const spock_settings& s, S* vio, sp
       info.n_km++;
       rc = SV.T(v, Tv, Sc);
       if (rc) return rc;
+      apply_kept();
     }
     ++k;
     if (!Sc.ok()) return finish(SPOCK_NUMERICAL);

@@ -909,6 +909,156 @@ __global__ void k_aa_dir(long long n, const S* __restrict__ r, int m, VecPtrs<S>
     d[e] = (S)acc;
   }
 }
+// Anderson step on the device (section 6.2, type-II; one thread, k <= 4):
+// the Gram row of the newest difference and the right-hand side <dR_j, r>
+// come from the push dot products; the oldest columns are dropped until the
+// Gram matrix of the kept ones has lambda_min / lambda_max >= 1e-12
+// (cyclic Jacobi) and a Cholesky factor; gamma solves G gamma = rhs. gamma
+// is written for every column of the order (0 for dropped ones) and the
+// kept count to kept_out (as a double).
+// Fixed-size (N <= 4) helpers, fully unrolled so that the matrices stay in
+// registers.
+template <int N>
+__device__ __forceinline__ bool dev_chol(double (&A)[16]) {
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    double d = A[j * 4 + j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) d -= A[j * 4 + k] * A[j * 4 + k];
+    if (!(d > 0.0) || !isfinite(d)) return false;
+    d = sqrt(d);
+    A[j * 4 + j] = d;
+#pragma unroll
+    for (int i = j + 1; i < N; ++i) {
+      double s = A[i * 4 + j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) s -= A[i * 4 + k] * A[j * 4 + k];
+      A[i * 4 + j] = s / d;
+    }
+  }
+  return true;
+}
+
+// Extreme eigenvalues of a symmetric N x N matrix (cyclic Jacobi).
+template <int N>
+__device__ __forceinline__ void dev_eig_range(double (&A)[16], double& lmin, double& lmax) {
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = i + 1; j < N; ++j) off += A[i * 4 + j] * A[i * 4 + j];
+    if (off < 1e-300) break;
+#pragma unroll
+    for (int p = 0; p < N; ++p)
+#pragma unroll
+      for (int q = p + 1; q < N; ++q) {
+        const double apq = A[p * 4 + q];
+        if (apq != 0.0) {
+          const double th = 0.5 * (A[q * 4 + q] - A[p * 4 + p]) / apq;
+          const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+          const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+#pragma unroll
+          for (int k = 0; k < N; ++k) {
+            const double akp = A[k * 4 + p], akq = A[k * 4 + q];
+            A[k * 4 + p] = c * akp - s * akq;
+            A[k * 4 + q] = s * akp + c * akq;
+          }
+#pragma unroll
+          for (int k = 0; k < N; ++k) {
+            const double apk = A[p * 4 + k], aqk = A[q * 4 + k];
+            A[p * 4 + k] = c * apk - s * aqk;
+            A[q * 4 + k] = s * apk + c * aqk;
+          }
+        }
+      }
+  }
+  lmin = lmax = A[0];
+#pragma unroll
+  for (int i = 1; i < N; ++i) {
+    lmin = fmin(lmin, A[i * 4 + i]);
+    lmax = fmax(lmax, A[i * 4 + i]);
+  }
+}
+
+// Rank test and solve for the last N of the k active columns (rows/cols
+// `off..off+N` of Gk, right-hand side rk); true when kept.
+template <int N>
+__device__ __forceinline__ bool dev_aa_try(const double (&Gk)[16], const double (&rk)[4], int off, double (&g)[4]) {
+  double E[16], L[16];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) E[i * 4 + j] = L[i * 4 + j] = Gk[(off + i) * 4 + off + j];
+  double lmin, lmax;
+  dev_eig_range<N>(E, lmin, lmax);
+  if (!(lmax > 0.0 && lmin / lmax >= 1e-12) || !dev_chol<N>(L)) return false;
+  double y[4];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double s = rk[off + i];
+#pragma unroll
+    for (int j = 0; j < i; ++j) s -= L[i * 4 + j] * y[j];
+    y[i] = s / L[i * 4 + i];
+  }
+#pragma unroll
+  for (int i = N - 1; i >= 0; --i) {
+    double s = y[i];
+#pragma unroll
+    for (int j = i + 1; j < N; ++j) s -= L[j * 4 + i] * g[off + j];
+    g[off + i] = s / L[i * 4 + i];
+  }
+  return true;
+}
+
+__global__ void k_aa_solve(double* __restrict__ G, double* __restrict__ rhs, const double* __restrict__ dots,
+                           AAPush a, double* __restrict__ gamma, double* __restrict__ kept_out) {
+  if (threadIdx.x != 0) return;
+  const int m = a.m, mo = a.mo, slot = a.slot;
+  for (int j = 0; j < mo; ++j) {
+    G[a.order_old[j] * m + slot] = dots[j];
+    G[slot * m + a.order_old[j]] = dots[j];
+    rhs[a.order_old[j]] = dots[mo + 1 + j];
+  }
+  G[slot * m + slot] = dots[mo];
+  rhs[slot] = dots[2 * mo + 1];
+  const int k = mo + 1;  // order_new = order_old + [slot]
+  int ord[4] = {0, 0, 0, 0};
+  for (int j = 0; j < mo; ++j) ord[j] = a.order_old[j];
+  ord[mo] = slot;
+  // Gram matrix and right-hand side of the active columns, in registers
+  double Gk[16], rk[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    rk[i] = i < k ? rhs[ord[i]] : 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) Gk[i * 4 + j] = (i < k && j < k) ? G[ord[i] * m + ord[j]] : 0.0;
+  }
+  double g[4] = {0, 0, 0, 0};
+  int kept = 0;
+  // drop the oldest columns until the rest pass the rank test
+  for (int drop = 0; drop < k && kept == 0; ++drop) {
+    const int kk = k - drop;
+    bool ok = false;
+    switch (kk) {
+      case 4: ok = dev_aa_try<4>(Gk, rk, drop, g); break;
+      case 3: ok = dev_aa_try<3>(Gk, rk, drop, g); break;
+      case 2: ok = dev_aa_try<2>(Gk, rk, drop, g); break;
+      default: ok = dev_aa_try<1>(Gk, rk, drop, g); break;
+    }
+    if (ok) kept = kk;
+  }
+  if (kept == 0) g[0] = g[1] = g[2] = g[3] = 0.0;
+  for (int j = 0; j < k; ++j) gamma[j] = g[j];
+  *kept_out = (double)kept;
+}
+
+hipError_t launch_aa_solve(double* G, double* rhs, const double* dots, const AAPush& a, double* gamma,
+                           double* kept_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_aa_solve, dim3(1), dim3(64), 0, st, G, rhs, dots, a, gamma, kept_out);
+  return hipGetLastError();
+}
+
 template <typename S>
 hipError_t launch_aa_dir(long long n, const S* r, int m, VecPtrs<S> dV, VecPtrs<S> dR,
                          const double* gamma_dev, S* d, hipStream_t st) {

@@ -173,6 +173,15 @@ hipError_t launch_rdot(long long n, const S* v, const S* Tv, const S* w, double*
 
 int dots_blocks(long long n);
 
+// Anderson step on the device: the push that just ran (slots of the columns
+// before it, oldest first, and the slot of the new column).
+struct AAPush {
+  int m, mo, slot;
+  int order_old[4];
+};
+hipError_t launch_aa_solve(double* G, double* rhs, const double* dots, const AAPush& a, double* gamma,
+                           double* kept_out, hipStream_t st);
+
 // ---------------------------------------------------------------- batched engine
 struct BatchSettings {
   double eps_abs, eps_rel;
