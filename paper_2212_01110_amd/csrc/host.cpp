@@ -1023,9 +1023,7 @@ int solve_impl(Problem& P, const double* x0, const spock_settings& s, S* vio, sp
       continue;
     }
     // M d = (d_z - alpha L* d_eta, d_eta - alpha L d_z), formed once per iteration
-    HIP_TRY(launch_Lt<S>(P, dir + P.nz, Md, st));
-    HIP_TRY(launch_L<S>(P, dir, Md + P.nz, st));
-    HIP_TRY(launch_lincomb<S>(nv, Md, -al, Md, 1.0, dir, st));
+    HIP_TRY(launch_M<S>(P, dir, Md, st));
     double tau = 1.0;
     bool accepted = false;
     for (int ls = 0; ls < s.max_ls; ++ls) {

@@ -141,6 +141,9 @@ template <typename S>
 hipError_t launch_Lt(const Problem& P, const S* eta, S* z, hipStream_t st);
 template <typename S>
 hipError_t launch_prox_gstar(const Problem& P, const S* w, S* out, hipStream_t st);
+// M d = (d_z - alpha L* d_eta, d_eta - alpha L d_z), team of team_pp lanes per family
+template <typename S>
+hipError_t launch_M(const Problem& P, const S* d, S* Md, hipStream_t st);
 
 // Up to 8 device vectors passed by value to a kernel.
 template <typename S>

@@ -175,6 +175,29 @@ def test_solve_config1_fp64(method):
         assert np.max(np.abs(x[c] - inst.A[c] @ x[i] - inst.B[c] @ u[i])) <= 1e-10
 
 
+@pytest.mark.parametrize("name", ["config1", "b3-1-2", "b5-wide"])
+def test_spock_matches_oracle_step_by_step(name):
+    # Alg. 3 step by step: over the first 60 iterations the FP64 path takes
+    # the same K0/K1/K2/KM decisions and backtracks as the oracle and reaches
+    # the same iterate, which checks the Anderson step, the metric M d of the
+    # line search and the K2 step, not only the point finally reached. (The
+    # two FP64 trajectories separate like any chaotic iteration: their
+    # difference grows from 1e-14 to about 1e-8 over 80 iterations on the
+    # five-child tree, after which a decision can flip.)
+    inst = CASES[name]
+    gp, op = build(inst)
+    ref = O.spock_solve(op, inst.x0, O.Settings(eps_abs=1e-12, eps_rel=1e-12, max_iters=60))
+    x0 = dev(inst.x0, torch.float64)
+    v = torch.zeros(gp.n_v, dtype=torch.float64, device="cuda")
+    info = gp.solve(x0, v, SP.default_settings(eps_abs=1e-12, eps_rel=1e-12, max_iters=60))
+    c = ref.counts
+    got = (info["iters"], info["n_k0"], info["n_k1"], info["n_k2"], info["n_km"], info["n_backtracks"])
+    want = (ref.iters, c["K0"], c["K1"], c["K2"], c["KM"], c["backtracks"])
+    assert got == want
+    assert abs(info["xi"] - ref.xi) <= 1e-8 * ref.xi
+    assert np.max(np.abs(host(v) - ref.v)) <= 1e-9 * max(1.0, np.max(np.abs(ref.v)))
+
+
 def test_cp_matches_oracle_iteration_count():
     # vanilla CP is deterministic up to rounding: same number of iterations
     inst = G.make_config(1)
