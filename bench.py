@@ -76,6 +76,27 @@ def algorithmic_elems_T(inst):
     return algorithmic_elems_sweeps(inst) + 2 * (n_z + n_eta) + node
 
 
+def measured_traffic():
+    """HBM bytes per launch of the sweeps kernel from the committed counter
+    summary (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a plain copy), or
+    None when the kernel sources differ from those the counters were taken
+    on."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "k_T_flow_20776node_fp32_traffic.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    b = re.search(r"traffic_bytes_per_launch: (\d+)", txt)
+    h = re.search(r"kernel_sources_sha256_16: ([0-9a-f]+)", txt)
+    if not b or not h:
+        return None
+    sha = hashlib.sha256()
+    for f in ("flow.hip", "device_common.h", "spock_internal.h"):
+        sha.update(open(os.path.join(ROOT, "paper_2212_01110_amd", "csrc", f), "rb").read())
+    return int(b.group(1)) if sha.hexdigest()[:16] == h.group(1) else None
+
+
 def cpu_baseline(inst, alpha, budget_s):
     """FP64 oracle: T evaluations with residual statistics from v = 0 until
     the time budget is spent (the step size is taken as given, so the
@@ -216,6 +237,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--plain-sample", type=int, default=16)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain device copy of 512 MiB (reference for the memory-traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (--gpus 1); the multi-GPU sharding of the tree "
@@ -252,6 +275,14 @@ def main():
     log(f"timed: {info['status']} {steps} iters {info['t_evals']} T-evals xi={info['xi']:.4g} "
         f"V_s0={info['V_s0']:.8g} map={info['mapping']} {el:.3f}s")
 
+    if args.calibrate_copy:
+        a = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("calibration copy: 536870912 bytes read, 536870912 bytes written")
+        del a, b
     # roofline of the sweeps kernel: HIP events recorded by the library
     Tv = torch.empty_like(v)
     prof = gp.profile_T(v, x0, Tv, reps=args.t_reps)
@@ -262,8 +293,9 @@ def main():
     achieved = e_sw * itemsize / (us_sw * 1e-6) / 1e9
     kname = "k_T_flow (both Alg. 2 sweeps, one launch)" if info["mapping"] == 512 else \
         "per-stage backward/forward sweep launches"
+    traffic = measured_traffic() if (args.config == 3 and prec == SP.FP32 and info["mapping"] == 512) else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": kname, "bytes_per_launch": e_sw * itemsize, "us_per_launch": round(us_sw, 2),
             "T_phases_us": {k: round(x, 2) for k, x in prof.items()},
             "T_whole_algorithmic_bytes": e_T * itemsize,
