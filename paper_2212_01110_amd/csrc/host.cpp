@@ -993,15 +993,15 @@ int solve_impl(Problem& P, const double* x0, const spock_settings& s, S* vio, sp
       HIP_TRY(launch_aa_solve(W.aaG, W.aaG + 16, W.dots, a, W.gamma, W.stats + 7, st));
       ring.order.push_back(slot);
       pending_k = mo + 1;
-      VecPtrs<S> pv{}, pr{};
-      for (int j = 0; j < mo + 1; ++j) {
-        pv.p[j] = dV[ring.order[j]];
-        pr.p[j] = dR[ring.order[j]];
-      }
-      HIP_TRY(launch_aa_dir<S>(nv, rcur, mo + 1, pv, pr, W.gamma, dir, st));
+      VecPtrs<S> pe{};
+      for (int j = 0; j < mo + 1; ++j) pe.p[j] = dV[ring.order[j]];  // dV - dR, as stored by the push
+      // when the K0 test will pass, the step v + d is formed in the same pass
+      const bool k0 = Sc.omega() <= s.c0 * zeta;
+      HIP_TRY(launch_aa_dir<S>(nv, rcur, mo + 1, pe, W.gamma, dir, k0 ? v : nullptr, k0 ? spare : nullptr, st));
     } else {
       HIP_TRY(launch_lincomb<S>(nv, rcur, 1.0, v, -1.0, Tv, st));
       HIP_TRY(launch_lincomb<S>(nv, dir, -1.0, rcur, 0.0, nullptr, st));
+      if (Sc.omega() <= s.c0 * zeta) HIP_TRY(launch_lincomb<S>(nv, spare, 1.0, v, 1.0, dir, st));
     }
     const double omega = Sc.omega();
     auto accept_prev = [&]() {
@@ -1009,8 +1009,7 @@ int solve_impl(Problem& P, const double* x0, const spock_settings& s, S* vio, sp
       std::swap(rprev, rcur);   // rprev <- old r
       have_prev = true;
     };
-    if (omega <= s.c0 * zeta) {  // K0
-      HIP_TRY(launch_lincomb<S>(nv, spare, 1.0, v, 1.0, dir, st));
+    if (omega <= s.c0 * zeta) {  // K0 (spare = v + d was formed with the direction)
       accept_prev();
       std::swap(v, spare);       // v <- v_old + d ; spare <- old vprev
       zeta = omega;

@@ -979,7 +979,8 @@ __global__ void k_aa_push(long long n, const S* __restrict__ v, const S* __restr
     const S r = vv - Tv[e];
     r_out[e] = r;
     const S dr = r - rprev[e];
-    dV_new[e] = vv - vprev[e];
+    // the direction only needs dV - dR: that difference is stored
+    dV_new[e] = (S)(((double)vv - (double)vprev[e]) - (double)dr);
     dR_new[e] = dr;
     for (int j = 0; j < m_old; ++j) {
       const double o = (double)dR_old.p[j][e];
@@ -1004,15 +1005,21 @@ hipError_t launch_aa_push(long long n, const S* v, const S* vprev, const S* Tv, 
 
 // d = -r - sum_j gamma_j (dV_j - dR_j)
 template <typename S>
-__global__ void k_aa_dir(long long n, const S* __restrict__ r, int m, VecPtrs<S> dV, VecPtrs<S> dR,
-                         const double* __restrict__ gamma, S* __restrict__ d) {
-  double g[8];
-  for (int j = 0; j < m; ++j) g[j] = gamma[j];
+__global__ void k_aa_dir(long long n, const S* __restrict__ r, int m, VecPtrs<S> dE,
+                         const double* __restrict__ gamma, S* __restrict__ d, const S* __restrict__ base,
+                         S* __restrict__ step) {
+  double g[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    if (j < m) g[j] = gamma[j];
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
        e += (long long)gridDim.x * blockDim.x) {
     double acc = -(double)r[e];
-    for (int j = 0; j < m; ++j) acc -= g[j] * ((double)dV.p[j][e] - (double)dR.p[j][e]);
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (j < m) acc -= g[j] * (double)dE.p[j][e];
     d[e] = (S)acc;
+    if (step) step[e] = (S)((double)base[e] + acc);
   }
 }
 // Anderson step on the device (section 6.2, type-II; one thread, k <= 4):
@@ -1166,9 +1173,9 @@ hipError_t launch_aa_solve(double* G, double* rhs, const double* dots, const AAP
 }
 
 template <typename S>
-hipError_t launch_aa_dir(long long n, const S* r, int m, VecPtrs<S> dV, VecPtrs<S> dR,
-                         const double* gamma_dev, S* d, hipStream_t st) {
-  hipLaunchKernelGGL(k_aa_dir<S>, dim3(dots_blocks(n)), dim3(256), 0, st, n, r, m, dV, dR, gamma_dev, d);
+hipError_t launch_aa_dir(long long n, const S* r, int m, VecPtrs<S> dE, const double* gamma_dev, S* d,
+                         const S* base, S* step, hipStream_t st) {
+  hipLaunchKernelGGL(k_aa_dir<S>, dim3(dots_blocks(n)), dim3(256), 0, st, n, r, m, dE, gamma_dev, d, base, step);
   return hipGetLastError();
 }
 
@@ -1184,8 +1191,8 @@ hipError_t launch_aa_dir(long long n, const S* r, int m, VecPtrs<S> dV, VecPtrs<
                                      hipStream_t);                                                 \
   template hipError_t launch_aa_push<S>(long long, const S*, const S*, const S*, const S*, S*, S*, \
                                         S*, int, VecPtrs<S>, double*, double*, hipStream_t);       \
-  template hipError_t launch_aa_dir<S>(long long, const S*, int, VecPtrs<S>, VecPtrs<S>,           \
-                                       const double*, S*, hipStream_t);
+  template hipError_t launch_aa_dir<S>(long long, const S*, int, VecPtrs<S>, const double*, S*,    \
+                                       const S*, S*, hipStream_t);
 SPK_INST(double)
 SPK_INST(float)
 

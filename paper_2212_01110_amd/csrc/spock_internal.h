@@ -166,8 +166,10 @@ hipError_t launch_aa_push(long long n, const S* v, const S* vprev, const S* Tv, 
                           S* r_out, S* dV_new, S* dR_new, int m_old, VecPtrs<S> dR_old,
                           double* partials, double* out_dev, hipStream_t st);
 template <typename S>
-hipError_t launch_aa_dir(long long n, const S* r, int m, VecPtrs<S> dV, VecPtrs<S> dR,
-                         const double* gamma_dev, S* d, hipStream_t st);
+// d = -r - sum_j gamma_j E_j with E_j = dV_j - dR_j (as stored by the push);
+// when step is non-null also step = base + d
+hipError_t launch_aa_dir(long long n, const S* r, int m, VecPtrs<S> dE, const double* gamma_dev, S* d,
+                         const S* base, S* step, hipStream_t st);
 template <typename S>
 hipError_t launch_fill(long long n, S* out, double val, hipStream_t st);
 template <typename S>
