@@ -68,7 +68,7 @@ struct FlowLds {
     oX = oQ + pad(nc * nx * esz);  // xbar (backward) or x (forward)
     oU = oX + pad(nx * esz);       // ubar (backward) or d (forward)
     oRed = oU + pad(nu * esz);
-    words = oRed + pad((nc + 1 > 5 ? nc + 1 : 5) * kFW * esz);
+    words = oRed + pad((nc + 1 > 3 ? nc + 1 : 3) * kFW * esz);
   }
   __host__ __device__ int bytes() const { return words * 4; }
 };
@@ -207,13 +207,14 @@ struct FlowArgs {
 // Alg. 2 backward step regrouped: with g = ubar - sum_c B^c' q^c,
 //   d = R~^{-1} g,   q = M1 g + c0 + sum_c Abar^c' q^c,
 //   M1 = (K' + W) R~^{-1} (offline, FP64),  c0 = -K' ubar - xbar.
-// c0 is formed before the children are waited for, so two mat-vec phases
-// remain on the dependency chain.
+// Wavefront 3 polls the children's q while the copies are in flight; K' ubar
+// and the children's products then form one mat-vec phase, R~^{-1} g and
+// M1 g a second.
 template <typename S>
 __device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, int i) {
-  __shared__ S c0[kMaxDim], vg[kMaxDim];
+  __shared__ S vg[kMaxDim];
   const DevProb<S>& P = A.P;
-  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int t = threadIdx.x, w = t >> 6;
   const int nx = P.nx, nu = P.nu, fc = P.fc[i], n = P.nch[i];
   const int es = L.esz;
   S* M = reinterpret_cast<S*>(lds);
@@ -221,10 +222,8 @@ __device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, 
   const S* xb = reinterpret_cast<const S*>(lds + L.oX);
   const S* ub = reinterpret_cast<const S*>(lds + L.oU);
   S* redA = reinterpret_cast<S*>(lds + L.oRed);  // sum_c Abar' q partials
-  S* redB = redA + kFW;                           // sum_c B' q
-  S* redR = redB + kFW;                           // R~^{-1} g
-  S* redM = redR + kFW;                           // M1 g
-  S* redC = redM + kFW;                           // K' ubar
+  S* redB = redA + kFW;                           // sum_c B' q; then R~^{-1} g
+  S* redC = redB + kFW;                           // K' ubar; then M1 g
   const bool leafkids = fc >= P.nl;
   for (int k0 = 0; k0 < n; k0 += L.nc) {
     const int kc = min(L.nc, n - k0);
@@ -242,39 +241,36 @@ __device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, 
     }
     if (leafkids)  // seeds -xbar of the leaf children, written by the pre-pass
       dma_words(A.seeds + (size_t)(fc + k0) * nx, lds, L.oQ, kc * nx * es, rot++);
-    if (k0 == 0) {  // c0 = -K' ubar - xbar while the children may still run
-      wait_vm();
-      __syncthreads();
-      mv_part<S>(M + L.oK / es, ub, nu, nx, redC, false);
-      __syncthreads();
-      if (t < nx) c0[t] = -mv_fold<S>(redC, nx, t) - xb[t];
-    }
-    if (!leafkids && w == 3)  // children's q from their backward items
+    else if (w == 3)  // children's q from their backward items
       wait_tagged<S>(A.qt + (size_t)(fc + k0) * nx * kTW<S>, kc * nx, A.tag, reinterpret_cast<S*>(lds + L.oQ), A.err);
     wait_vm();
     __syncthreads();
+    if (k0 == 0) mv_part<S>(M + L.oK / es, ub, nu, nx, redC, false);
     for (int k = 0; k < kc; ++k) {
       mv_part<S>(M + L.oA / es + k * (L.sA / es), qv + k * nx, nx, nx, redA, k0 + k > 0);
       mv_part<S>(M + L.oB / es + k * (L.sB / es), qv + k * nx, nx, nu, redB, k0 + k > 0);
     }
     __syncthreads();  // matrices and q consumed before the next chunk's copies
   }
+  // g = ubar - sum_c B' q; c0 = -K' ubar - xbar (kept by thread t < nx)
+  S c0 = 0;
+  if (t < nx) c0 = -mv_fold<S>(redC, nx, t) - xb[t];
   if (t < nu) vg[t] = ub[t] - mv_fold<S>(redB, nu, t);
   __syncthreads();
-  mv_part<S>(M + L.oR / es, vg, nu, nu, redR, false);
-  mv_part<S>(M + L.oW / es, vg, nu, nx, redM, false);
+  mv_part<S>(M + L.oR / es, vg, nu, nu, redB, false);
+  mv_part<S>(M + L.oW / es, vg, nu, nx, redC, false);
   __syncthreads();
-  if (t < nu) put_tagged<S>(A.dt + ((size_t)i * nu + t) * kTW<S>, mv_fold<S>(redR, nu, t), A.tag);
+  if (t < nu) put_tagged<S>(A.dt + ((size_t)i * nu + t) * kTW<S>, mv_fold<S>(redB, nu, t), A.tag);
   if (t < nx)
-    put_tagged<S>(A.qt + ((size_t)i * nx + t) * kTW<S>, mv_fold<S>(redM, nx, t) + mv_fold<S>(redA, nx, t) + c0[t],
+    put_tagged<S>(A.qt + ((size_t)i * nx + t) * kTW<S>, mv_fold<S>(redC, nx, t) + mv_fold<S>(redA, nx, t) + c0,
                   A.tag);
   __syncthreads();  // LDS reuse by the next item
 }
 
 // ---------------------------------------------------------------- forward item
-// u = K x + d; x^c = Abar^c x + B^c d; x^0 = x0 at the root. B^c d is formed
-// once d (backward step of the family) is there, before x (the parent's
-// forward step) is waited for.
+// u = K x + d; x^c = Abar^c x + B^c d; x^0 = x0 at the root. Wavefront 0
+// polls d (the family's backward step) and x (the parent's forward step)
+// while the copies are in flight.
 template <typename S>
 __device__ void flow_fwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, int i) {
   const DevProb<S>& P = A.P;
@@ -295,24 +291,24 @@ __device__ void flow_fwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, 
     }
     if (k0 == 0) {
       dma_words(P.KC + (size_t)i * nx * nu, lds, L.oK, nx * nu * es, rot++);
-      if (w == 0)  // d^i of the family's backward step
+      if (w == 0) {
         wait_tagged<S>(A.dt + (size_t)i * nu * kTW<S>, nu, A.tag, vd, A.err);
+        if (i != 0) {
+          wait_tagged<S>(A.xt + (size_t)i * nx * kTW<S>, nx, A.tag, vx, A.err);
+        } else if (lane < nx) {
+          const S xv = (S)A.x0[lane];
+          A.zout[1 + lane] = xv;
+          vx[lane] = xv;
+        }
+      }
     }
     wait_vm();
     __syncthreads();
-    for (int k = 0; k < kc; ++k) mv_part<S>(M + L.oB / es + k * (L.sB / es), vd, nu, nx, red + k * kFW, false);
-    if (k0 == 0 && w == 0) {  // x^i from the parent's forward step (x0 at the root)
-      if (i != 0) {
-        wait_tagged<S>(A.xt + (size_t)i * nx * kTW<S>, nx, A.tag, vx, A.err);
-      } else if (lane < nx) {
-        const S xv = (S)A.x0[lane];
-        A.zout[1 + lane] = xv;
-        vx[lane] = xv;
-      }
-    }
-    __syncthreads();
     if (k0 == 0) mv_part<S>(M + L.oK / es, vx, nx, nu, red + L.nc * kFW, false);
-    for (int k = 0; k < kc; ++k) mv_part<S>(M + L.oA / es + k * (L.sA / es), vx, nx, nx, red + k * kFW, true);
+    for (int k = 0; k < kc; ++k) {
+      mv_part<S>(M + L.oB / es + k * (L.sB / es), vd, nu, nx, red + k * kFW, false);
+      mv_part<S>(M + L.oA / es + k * (L.sA / es), vx, nx, nx, red + k * kFW, true);
+    }
     __syncthreads();
     if (k0 == 0 && t < nu) A.zout[O.u(i) + t] = mv_fold<S>(red + L.nc * kFW, nu, t) + vd[t];
     for (int k = 0; k < kc; ++k)

@@ -641,12 +641,14 @@ struct Work {
 // epoch-tagged). The error word is cleared on every call (each API call
 // starts clean).
 template <typename S>
-int ensure_flow(Problem& P, int occ = 0) {
+int ensure_flow(Problem& P, int occ = 0, int budget = 0) {
   FlowState& F = P.flow;
   const Tree& T = *P.tree;
   if (occ == 0) occ = F.mem ? F.occ : 5;
+  if (budget == 0) budget = F.mem ? F.budget : 40 * 1024;
   if (const char* env = std::getenv("SPOCK_FLOW_OCC")) occ = std::atoi(env) >= 5 ? 5 : 4;
-  if (F.mem && F.elem == (int)sizeof(S) && F.occ == occ) {
+  if (const char* env = std::getenv("SPOCK_FLOW_LDS")) budget = std::max(4096, std::atoi(env));
+  if (F.mem && F.elem == (int)sizeof(S) && F.occ == occ && F.budget == budget) {
     if (hipMemset(F.err, 0, sizeof(unsigned)) != hipSuccess) return SPOCK_EHIP;
     return SPOCK_OK;
   }
@@ -654,8 +656,6 @@ int ensure_flow(Problem& P, int occ = 0) {
   F = FlowState{};
   int maxch = 1;
   for (int i = 0; i < T.nl; ++i) maxch = std::max(maxch, T.nch[i]);
-  int budget = 40 * 1024;
-  if (const char* env = std::getenv("SPOCK_FLOW_LDS")) budget = std::max(4096, std::atoi(env));
   int nc = std::min(maxch, 8);
   while (nc > 1 && flow_lds_bytes(P.nx, P.nu, nc, (int)sizeof(S)) > budget) --nc;
   const int lds = flow_lds_bytes(P.nx, P.nu, nc, (int)sizeof(S));
@@ -681,6 +681,7 @@ int ensure_flow(Problem& P, int occ = 0) {
   F.xt = F.dt + nd;
   F.nc = nc;
   F.occ = occ;
+  F.budget = budget;
   if (const char* env = std::getenv("SPOCK_FLOW_COOP")) F.coop = std::atoi(env) != 0;
   F.elem = (int)sizeof(S);
   F.grid = (coop && fits) ? nb * ncu : 0;
@@ -762,10 +763,12 @@ int autotune(Problem& P, hipStream_t st) {
   HIP_TRY(hipEventCreate(&e1));
   const Tree& T = *P.tree;
   std::vector<std::pair<int, int>> cands = {{8, T.N}, {16, T.N}, {32, T.N}, {64, T.N}, {kTeamWG, T.N}};
-  // dataflow form at both register budgets (the cut field carries the
-  // budget: 4 or 5 wavefronts per SIMD)
-  if (ensure_flow<S>(P, 4) == SPOCK_OK && P.flow.grid > 0) cands.push_back({kTeamFlow, 4});
-  if (ensure_flow<S>(P, 5) == SPOCK_OK && P.flow.grid > 0) cands.push_back({kTeamFlow, 5});
+  // dataflow form: register budget (4 or 5 wavefronts per SIMD) and LDS
+  // budget (children per chunk against workgroups per CU); the cut field
+  // carries occ * 1000 + LDS budget in KiB
+  for (int code : {4040, 5040, 5046, 5060})
+    if (ensure_flow<S>(P, code / 1000, (code % 1000) * 1024) == SPOCK_OK && P.flow.grid > 0)
+      cands.push_back({kTeamFlow, code});
   int ncut = 0;
   for (int t = std::max(0, T.N - 64); t < T.N && ncut < 3; ++t)
     if (T.stage_off[t + 1] - T.stage_off[t] >= 128) {
@@ -776,7 +779,9 @@ int autotune(Problem& P, hipStream_t st) {
   std::pair<int, int> best_map = {P.team, P.cut};
   for (auto c : cands) {
     if (mapping_lds(P, c.first, sizeof(S)) > 64 * 1024) continue;
-    if (c.first == kTeamFlow && (ensure_flow<S>(P, c.second) != SPOCK_OK || P.flow.grid <= 0)) continue;
+    if (c.first == kTeamFlow &&
+        (ensure_flow<S>(P, c.second / 1000, (c.second % 1000) * 1024) != SPOCK_OK || P.flow.grid <= 0))
+      continue;
     set_mapping(P, c.first, c.second);
     HIP_TRY(launch_T<S>(P, W.pool[0], W.pool[1], W.x0_zero, W.q, W.d, W.xbar, W.ubar, W.partials, W.stats, st,
                         W.eta_zero, true));
@@ -793,7 +798,9 @@ int autotune(Problem& P, hipStream_t st) {
       best_map = c;
     }
   }
-  if (best_map.first == kTeamFlow && ensure_flow<S>(P, best_map.second) != SPOCK_OK) return SPOCK_EHIP;
+  if (best_map.first == kTeamFlow &&
+      ensure_flow<S>(P, best_map.second / 1000, (best_map.second % 1000) * 1024) != SPOCK_OK)
+    return SPOCK_EHIP;
   set_mapping(P, best_map.first, best_map.second);
   // lanes per family of the parallel pre/post passes (fewer lanes: more
   // families in flight per workgroup, longer per-lane loops)

@@ -78,6 +78,7 @@ struct FlowState {
   int grid = 0;                      // resident workgroups (0: form unavailable)
   int occ = 5;                       // register budget: 4 or 5 wavefronts per SIMD
   int elem = 0;                      // element size the state was sized for
+  int budget = 40 * 1024;            // LDS budget the chunk size was chosen for
   // cooperative launch (residency guaranteed by the runtime) or a plain
   // launch of the resident-sized grid (about 20 us less dispatch per T; a
   // grid that were not all resident ends with the error word set)
