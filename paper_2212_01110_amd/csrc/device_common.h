@@ -690,4 +690,32 @@ __device__ __forceinline__ void fam_post_team(const DevProb<S>& P, const S* __re
   wave_lds_sync();
 }
 
+// Tagged words: element e of a vector occupies kTW<S> 64-bit words, each
+// holding (epoch << 32) | one 32-bit half of the value.
+template <typename S>
+constexpr int kTW = sizeof(S) / 4;
+
+template <typename S>
+__device__ __forceinline__ void put_tagged(unsigned long long* p, S v, unsigned tag) {
+  unsigned h[kTW<S>];
+  __builtin_memcpy(h, &v, sizeof(S));
+  const unsigned long long hi = (unsigned long long)tag << 32;
+#pragma unroll
+  for (int k = 0; k < kTW<S>; ++k) __hip_atomic_store(p + k, hi | h[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename S>
+__device__ __forceinline__ bool get_tagged(const unsigned long long* p, unsigned tag, S& v) {
+  unsigned h[kTW<S>];
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < kTW<S>; ++k) {
+    const unsigned long long w = __hip_atomic_load(p + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    ok = ok && (unsigned)(w >> 32) == tag;
+    h[k] = (unsigned)w;
+  }
+  __builtin_memcpy(&v, h, sizeof(S));
+  return ok;
+}
+
 }  // namespace spk

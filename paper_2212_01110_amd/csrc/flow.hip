@@ -139,34 +139,6 @@ __device__ __forceinline__ unsigned ld_flag(const unsigned* f) {
 
 
 
-// Tagged words: element e of a vector occupies kTW<S> 64-bit words, each
-// holding (epoch << 32) | one 32-bit half of the value.
-template <typename S>
-constexpr int kTW = sizeof(S) / 4;
-
-template <typename S>
-__device__ __forceinline__ void put_tagged(unsigned long long* p, S v, unsigned tag) {
-  unsigned h[kTW<S>];
-  __builtin_memcpy(h, &v, sizeof(S));
-  const unsigned long long hi = (unsigned long long)tag << 32;
-#pragma unroll
-  for (int k = 0; k < kTW<S>; ++k) __hip_atomic_store(p + k, hi | h[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-template <typename S>
-__device__ __forceinline__ bool get_tagged(const unsigned long long* p, unsigned tag, S& v) {
-  unsigned h[kTW<S>];
-  bool ok = true;
-#pragma unroll
-  for (int k = 0; k < kTW<S>; ++k) {
-    const unsigned long long w = __hip_atomic_load(p + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    ok = ok && (unsigned)(w >> 32) == tag;
-    h[k] = (unsigned)w;
-  }
-  __builtin_memcpy(&v, h, sizeof(S));
-  return ok;
-}
-
 // One wavefront polls the n tagged elements at src until all carry `tag`
 // (bounded), copying the values to dst (LDS).
 template <typename S>
@@ -334,12 +306,6 @@ __global__ void __launch_bounds__(kFW) __attribute__((amdgpu_waves_per_eu(W, 8))
   }
 }
 
-// Poisons the statistics when a bounded wait of the sweeps gave up.
-__global__ void k_flow_check(const unsigned* __restrict__ err, double* __restrict__ stats) {
-  if (threadIdx.x == 0 && ld_flag(err) != 0u)
-    for (int s = 0; s < 6; ++s) stats[s] = __builtin_nan("");
-}
-
 }  // namespace
 
 // LDS bytes of the dataflow launch with nc children per chunk.
@@ -386,10 +352,5 @@ template hipError_t launch_sweeps_flow<double>(const Problem&, const DevProb<dou
                                                const double*, const double*, double*, double*, hipStream_t);
 template hipError_t launch_sweeps_flow<float>(const Problem&, const DevProb<float>&, float*, const double*,
                                               const float*, const float*, float*, float*, hipStream_t);
-
-hipError_t launch_flow_check(const Problem& P, double* stats, hipStream_t st) {
-  hipLaunchKernelGGL(k_flow_check, dim3(1), dim3(64), 0, st, P.flow.err, stats);
-  return hipGetLastError();
-}
 
 }  // namespace spk

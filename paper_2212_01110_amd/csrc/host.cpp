@@ -578,6 +578,7 @@ extern "C" int spock_problem_destroy(spock_problem* p) {
   if (p->p.dmem) (void)hipFree(p->p.dmem);
   if (p->p.work) (void)hipFree(p->p.work);
   if (p->p.flow.mem) (void)hipFree(p->p.flow.mem);
+  if (p->p.mbox) (void)hipHostFree(p->p.mbox);
   delete p;
   return SPOCK_OK;
 }
@@ -631,7 +632,10 @@ struct Work {
   S* eta_zero = nullptr;      // n_eta zeros
   double* x0_zero = nullptr;  // kMaxDim zeros (autotuning input)
   S* pool[10 + 2 * kMaxMem];  // n_v buffers
-  double* host_stats = nullptr;
+  unsigned* counters = nullptr;       // arrival counts of the push and the rdot [2][kRedCounters]
+  unsigned long long* rec = nullptr;  // tagged records of their grid sums [kRedRecWords]
+  unsigned tag = 0;                   // tag of their last launch (never 0 once launched)
+  unsigned next_tag() { return ++tag == 0u ? ++tag : tag; }
 };
 
 // Sizes and allocates the state of the dataflow form of the sweeps for
@@ -705,6 +709,8 @@ int ensure_work(Problem& P, Work<S>& W) {
   add(sizeof(double) * 8);
   add(sizeof(double) * 32);
   add(sizeof(double) * (size_t)nblk * 8);
+  add(sizeof(unsigned) * 2 * kRedCounters);
+  add(sizeof(unsigned long long) * kRedRecWords);
   add(sizeof(S) * (size_t)P.neta);
   add(sizeof(double) * kMaxDim);
   for (int k = 0; k < 10 + 2 * kMaxMem; ++k) add(sizeof(S) * (size_t)nv);
@@ -733,10 +739,31 @@ int ensure_work(Problem& P, Work<S>& W) {
   W.gamma = reinterpret_cast<double*>(take(sizeof(double) * 8));
   W.aaG = reinterpret_cast<double*>(take(sizeof(double) * 32));
   W.vpart = reinterpret_cast<double*>(take(sizeof(double) * (size_t)nblk * 8));
+  W.counters = reinterpret_cast<unsigned*>(take(sizeof(unsigned) * 2 * kRedCounters));
+  W.rec = reinterpret_cast<unsigned long long*>(take(sizeof(unsigned long long) * kRedRecWords));
   W.eta_zero = reinterpret_cast<S*>(take(sizeof(S) * (size_t)P.neta));
   W.x0_zero = reinterpret_cast<double*>(take(sizeof(double) * kMaxDim));
   for (int k = 0; k < 10 + 2 * kMaxMem; ++k) W.pool[k] = reinterpret_cast<S*>(take(sizeof(S) * (size_t)nv));
   if (off > P.work_bytes) return SPOCK_ENOMEM;
+  // the layout depends on the precision: the counts and the tagged records
+  // (tag 0: never written) start cleared here
+  if (hipMemset(W.counters, 0, sizeof(unsigned) * 2 * kRedCounters) != hipSuccess) return SPOCK_EHIP;
+  if (hipMemset(W.rec, 0, sizeof(unsigned long long) * kRedRecWords) != hipSuccess) return SPOCK_EHIP;
+  W.tag = 0;
+  if (!P.mbox) {
+    void* hp = nullptr;
+    if (hipHostMalloc(&hp, sizeof(Mailbox), hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess)
+      return SPOCK_ENOMEM;
+    std::memset(hp, 0, sizeof(Mailbox));
+    void* dp = nullptr;
+    if (hipHostGetDevicePointer(&dp, hp, 0) != hipSuccess) {
+      (void)hipHostFree(hp);
+      return SPOCK_EHIP;
+    }
+    P.mbox = static_cast<Mailbox*>(hp);
+    P.mbox_dev = static_cast<Mailbox*>(dp);
+    P.mbox_epoch = 0;
+  }
   if (P.team == kTeamFlow) {
     const int rc = ensure_flow<S>(P);
     if (rc) return rc;
@@ -857,10 +884,14 @@ struct Solver {
   // T(v) and its statistics; with md, also <v - T(v), md> (line search),
   // fetched in the same transfer (statistics slot 6)
   int T(const S* v, S* Tv, Stats& out, const S* md = nullptr, double* rdot = nullptr) {
-    HIP_TRY(launch_T<S>(P, v, Tv, x0, W.q, W.d, W.xbar, W.ubar, W.partials, W.stats, st, W.eta_zero, true));
-    if (md) HIP_TRY(launch_rdot<S>(nv, v, Tv, md, W.vpart, W.stats + 6, st));
-    HIP_TRY(hipMemcpyAsync(hbuf.data(), W.stats, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    const Publish pub{P.mbox_dev, ++P.mbox_epoch};
+    HIP_TRY(launch_T<S>(P, v, Tv, x0, W.q, W.d, W.xbar, W.ubar, W.partials, W.stats, st, W.eta_zero, true,
+                        md ? Publish{} : pub));
+    if (md)
+      HIP_TRY(launch_rdot<S>(nv, v, Tv, md, W.rec, W.counters + kRedCounters, W.next_tag(), W.stats + 6, W.stats, pub, st));
+    const int rc = wait_mailbox(pub.epoch);
+    if (rc) return rc;
+    for (int k = 0; k < 8; ++k) hbuf[k] = P.mbox->v[k];
     last_kept = hbuf[7];
     if (rdot) *rdot = hbuf[6];
     out.xip = hbuf[0];
@@ -871,6 +902,19 @@ struct Solver {
     out.cross = hbuf[5];
     ++t_evals;
     return SPOCK_OK;
+  }
+  // Polls the mailbox for the epoch; every 4096 polls the stream is asked
+  // whether it drained (then the epoch must be there) or failed.
+  int wait_mailbox(unsigned long long epoch) {
+    for (unsigned n = 1;; ++n) {
+      if (__atomic_load_n(&P.mbox->flag, __ATOMIC_ACQUIRE) == epoch) return SPOCK_OK;
+      if ((n & 4095u) == 0u) {
+        const hipError_t e = hipStreamQuery(st);
+        if (e == hipSuccess)
+          return __atomic_load_n(&P.mbox->flag, __ATOMIC_ACQUIRE) == epoch ? SPOCK_OK : SPOCK_EHIP;
+        if (e != hipErrorNotReady) return SPOCK_EHIP;
+      }
+    }
   }
   int fetch(double* dst, const double* src, int k) {
     HIP_TRY(hipMemcpyAsync(dst, src, k * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -995,9 +1039,8 @@ int solve_impl(Problem& P, const double* x0, const spock_settings& s, S* vio, sp
         olds.p[j] = dR[ring.order[j]];
         a.order_old[j] = ring.order[j];
       }
-      HIP_TRY(launch_aa_push<S>(nv, v, vprev, Tv, rprev, rcur, dV[slot], dR[slot], mo, olds, W.vpart,
-                                W.dots, st));
-      HIP_TRY(launch_aa_solve(W.aaG, W.aaG + 16, W.dots, a, W.gamma, W.stats + 7, st));
+      HIP_TRY(launch_aa_push<S>(nv, v, vprev, Tv, rprev, rcur, dV[slot], dR[slot], olds, W.rec, W.counters,
+                                W.next_tag(), W.aaG, W.aaG + 16, a, W.gamma, W.stats + 7, st));
       ring.order.push_back(slot);
       pending_k = mo + 1;
       VecPtrs<S> pe{};

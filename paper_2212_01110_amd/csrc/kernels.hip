@@ -26,6 +26,8 @@
 
 #include <math.h>
 #include <algorithm>
+#include <cstdint>
+#include <initializer_list>
 
 namespace spk {
 
@@ -409,9 +411,18 @@ __global__ void __launch_bounds__(kWG) k_fwd_tail_wg(DevProb<S> P, S* __restrict
   if (P.nn < 0) zout[0] = S(pf);  // never true: keeps the prefetch loads alive
 }
 
-// Sums the per-block statistics into {xi_p, xi_d, omega^2, rz2, re2, cross}.
+// Hands stats[0..8) to the host mailbox: the values, then the epoch with
+// system-scope release (one thread).
+__device__ void publish_stats(const double* vals, Publish pub) {
+  for (int s = 0; s < 8; ++s) pub.mb->v[s] = vals[s];
+  __hip_atomic_store(&pub.mb->flag, pub.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Sums the per-block statistics into {xi_p, xi_d, omega^2, rz2, re2, cross};
+// NaN when the error word of the dataflow sweeps is set (a bounded wait gave
+// up); then, when pub.mb is set, publishes out[0..8) to the host.
 __global__ void k_reduce_stats(const double* __restrict__ partials, int nblk, double alpha,
-                               double* __restrict__ out) {
+                               double* __restrict__ out, const unsigned* __restrict__ err, Publish pub) {
   __shared__ double red[kStats][256];
   double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0;
   for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
@@ -439,12 +450,21 @@ __global__ void k_reduce_stats(const double* __restrict__ partials, int nblk, do
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    out[0] = red[3][0];
-    out[1] = red[4][0];
-    out[2] = red[0][0] + red[1][0] - 2.0 * alpha * red[2][0];
-    out[3] = red[0][0];
-    out[4] = red[1][0];
-    out[5] = red[2][0];
+    double r[8];
+    r[0] = red[3][0];
+    r[1] = red[4][0];
+    r[2] = red[0][0] + red[1][0] - 2.0 * alpha * red[2][0];
+    r[3] = red[0][0];
+    r[4] = red[1][0];
+    r[5] = red[2][0];
+    if (err && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
+      for (int k = 0; k < 6; ++k) r[k] = __builtin_nan("");
+    for (int k = 0; k < 6; ++k) out[k] = r[k];
+    if (pub.mb) {
+      r[6] = out[6];
+      r[7] = out[7];
+      publish_stats(r, pub);
+    }
   }
 }
 
@@ -529,7 +549,7 @@ int post_blocks(const Problem& P) {
 template <typename S>
 hipError_t launch_T(const Problem& P, const S* v, S* Tv, const double* x0, S* q, S* d, S* xbar,
                     S* ubar, double* partials, double* stats_dev, hipStream_t st,
-                    const S* eta_zero, bool dual) {
+                    const S* eta_zero, bool dual, Publish pub) {
   const DevProb<S>& D = dev_of<S>(P);
   const S* z = v;
   const S* eta = dual ? v + P.nz : eta_zero;
@@ -568,21 +588,18 @@ hipError_t launch_T(const Problem& P, const S* v, S* Tv, const double* x0, S* q,
     }
     mark(3);
     hipLaunchKernelGGL(k_reduce_stats, dim3(1), dim3(256), 0, st, partials, post_blocks(P),
-                       (double)D.alpha, stats_dev);
-    if (P.team == kTeamFlow) {
-      const hipError_t e = launch_flow_check(P, stats_dev, st);
-      if (e != hipSuccess) return e;
-    }
+                       (double)D.alpha, stats_dev, P.team == kTeamFlow ? (const unsigned*)P.flow.err : nullptr,
+                       pub);
   }
   mark(4);
   return hipGetLastError();
 }
 template hipError_t launch_T<double>(const Problem&, const double*, double*, const double*, double*,
                                      double*, double*, double*, double*, double*, hipStream_t,
-                                     const double*, bool);
+                                     const double*, bool, Publish);
 template hipError_t launch_T<float>(const Problem&, const float*, float*, const double*, float*,
                                     float*, float*, float*, double*, double*, hipStream_t, const float*,
-                                    bool);
+                                    bool, Publish);
 
 // ---------------------------------------------------------------- L and L*
 // One thread per family (test entry points; simple and exact).
@@ -847,40 +864,98 @@ int dots_blocks(long long n) {
   return (int)(b < kVecBlocks ? (b < 1 ? 1 : b) : kVecBlocks);
 }
 
+// Streaming vector kernels read and write 16 bytes per lane (float4 /
+// double2, kVW elements): enough bytes in flight per wavefront to cover the
+// HBM latency. Elements past the last whole vector, and every element when a
+// pointer is not 16-byte aligned, take the scalar path of the same kernel.
 template <typename S>
-__global__ void k_lincomb(long long n, S* __restrict__ out, double a, const S* __restrict__ x,
-                          double b, const S* __restrict__ y) {
-  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
-       k += (long long)gridDim.x * blockDim.x) {
-    double v = a * (double)x[k];
-    if (y) v += b * (double)y[k];
-    out[k] = (S)v;
+constexpr int kVW = 16 / (int)sizeof(S);
+template <typename S>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  using T = float4;
+};
+template <>
+struct Vec16<double> {
+  using T = double2;
+};
+template <typename S>
+__device__ __forceinline__ void ld16(const S* __restrict__ p, long long k, S (&a)[kVW<S>]) {
+  const typename Vec16<S>::T x = reinterpret_cast<const typename Vec16<S>::T*>(p)[k];
+  __builtin_memcpy(a, &x, 16);
+}
+template <typename S>
+__device__ __forceinline__ void st16(S* __restrict__ p, long long k, const S (&a)[kVW<S>]) {
+  typename Vec16<S>::T x;
+  __builtin_memcpy(&x, a, 16);
+  reinterpret_cast<typename Vec16<S>::T*>(p)[k] = x;
+}
+static bool al16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+// whole vectors of the vector path (0 when some pointer is unaligned)
+template <typename S>
+static long long nvec16(long long n, std::initializer_list<const void*> ptrs) {
+  for (const void* q : ptrs)
+    if (q && !al16(q)) return 0;
+  return n / kVW<S>;
+}
+#define SPK_GRID_LOOP(k, lo, hi)                                                             \
+  for (long long k = (lo) + blockIdx.x * (long long)blockDim.x + threadIdx.x; k < (hi); \
+       k += (long long)gridDim.x * blockDim.x)
+
+// out = a x + b y (y may be null)
+template <typename S>
+__global__ void __launch_bounds__(256) k_lincomb(long long n, long long nv, S* __restrict__ out, double a,
+                                                 const S* __restrict__ x, double b, const S* __restrict__ y) {
+  constexpr int W = kVW<S>;
+  SPK_GRID_LOOP(k, 0, nv) {
+    S xv[W], yv[W], o[W];
+    ld16(x, k, xv);
+    if (y) ld16(y, k, yv);
+#pragma unroll
+    for (int c = 0; c < W; ++c) o[c] = (S)(a * (double)xv[c] + (y ? b * (double)yv[c] : 0.0));
+    st16(out, k, o);
+  }
+  SPK_GRID_LOOP(e, nv * W, n) {
+    double v = a * (double)x[e];
+    if (y) v += b * (double)y[e];
+    out[e] = (S)v;
   }
 }
 template <typename S>
 hipError_t launch_lincomb(long long n, S* out, double a, const S* x, double b, const S* y,
                           hipStream_t st) {
-  hipLaunchKernelGGL(k_lincomb<S>, dim3(dots_blocks(n)), dim3(256), 0, st, n, out, a, x, b, y);
+  hipLaunchKernelGGL(k_lincomb<S>, dim3(dots_blocks(n)), dim3(256), 0, st, n, nvec16<S>(n, {out, x, y}), out, a,
+                     x, b, y);
   return hipGetLastError();
 }
+// out = a x + b y + c w
 template <typename S>
-__global__ void k_lincomb3(long long n, S* __restrict__ out, double a, const S* __restrict__ x,
-                           double b, const S* __restrict__ y, double c, const S* __restrict__ w) {
-  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
-       k += (long long)gridDim.x * blockDim.x)
-    out[k] = (S)(a * (double)x[k] + b * (double)y[k] + c * (double)w[k]);
+__global__ void __launch_bounds__(256) k_lincomb3(long long n, long long nv, S* __restrict__ out, double a,
+                                                  const S* __restrict__ x, double b, const S* __restrict__ y,
+                                                  double c, const S* __restrict__ w) {
+  constexpr int W = kVW<S>;
+  SPK_GRID_LOOP(k, 0, nv) {
+    S xv[W], yv[W], wv[W], o[W];
+    ld16(x, k, xv);
+    ld16(y, k, yv);
+    ld16(w, k, wv);
+#pragma unroll
+    for (int q = 0; q < W; ++q) o[q] = (S)(a * (double)xv[q] + b * (double)yv[q] + c * (double)wv[q]);
+    st16(out, k, o);
+  }
+  SPK_GRID_LOOP(e, nv * W, n) out[e] = (S)(a * (double)x[e] + b * (double)y[e] + c * (double)w[e]);
 }
 template <typename S>
 hipError_t launch_lincomb3(long long n, S* out, double a, const S* x, double b, const S* y,
                            double c, const S* w, hipStream_t st) {
-  hipLaunchKernelGGL(k_lincomb3<S>, dim3(dots_blocks(n)), dim3(256), 0, st, n, out, a, x, b, y, c, w);
+  hipLaunchKernelGGL(k_lincomb3<S>, dim3(dots_blocks(n)), dim3(256), 0, st, n, nvec16<S>(n, {out, x, y, w}), out,
+                     a, x, b, y, c, w);
   return hipGetLastError();
 }
 template <typename S>
 __global__ void k_fill(long long n, S* __restrict__ out, double val) {
-  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
-       k += (long long)gridDim.x * blockDim.x)
-    out[k] = (S)val;
+  SPK_GRID_LOOP(e, 0, n) out[e] = (S)val;
 }
 template <typename S>
 hipError_t launch_fill(long long n, S* out, double val, hipStream_t st) {
@@ -903,10 +978,9 @@ __device__ void block_sums(double (&acc)[K], double* partials) {
 }
 
 // Sums K <= 8 columns of nblk partial records (stride 8) in a fixed order:
-// thread t takes records t, t + 256, ..., then a tree over the threads.
-__global__ void __launch_bounds__(256) k_final_sums(const double* __restrict__ partials, int nblk, int K,
-                                                    double* __restrict__ out) {
-  __shared__ double red[8][256];
+// thread t takes records t, t + 256, ..., then a tree over the threads (a
+// 256-thread block; the sums end in red[j][0]).
+__device__ void final_sums_in(const double* __restrict__ partials, int nblk, int K, double (*red)[256]) {
   const int t = threadIdx.x;
   double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int b = t; b < nblk; b += 256) {
@@ -924,7 +998,83 @@ __global__ void __launch_bounds__(256) k_final_sums(const double* __restrict__ p
       for (int j = 0; j < 8; ++j) red[j][t] += red[j][t + h];
     __syncthreads();
   }
-  if (t < K) out[t] = red[t][0];
+}
+__global__ void __launch_bounds__(256) k_final_sums(const double* __restrict__ partials, int nblk, int K,
+                                                    double* __restrict__ out) {
+  __shared__ double red[8][256];
+  final_sums_in(partials, nblk, K, red);
+  if ((int)threadIdx.x < K) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Reduction finished inside the launch, in two levels of tagged records.
+// Each block's sums (fixed-order tree) go to its record as tagged words
+// (epoch << 32 | half; record r holds 8 doubles, rec[(r * 8 + j) * 2 + {0,1}]).
+// Blocks arrive in groups of kGroup on device-scope counters; the last block
+// of a group sums the group's records in block order into a group record
+// (after the kMaxRecBlocks block records), and the last group to finish sums
+// the group records in order. The records carry the launch's tag, so readers
+// poll until they arrive and no fence orders them against the counts; each
+// last arriver resets its counter for the next launch.
+constexpr int kGroup = kRedGroup;
+constexpr int kMaxRecBlocks = kRedMaxBlocks;
+static_assert(kVecBlocks <= kMaxRecBlocks, "one record per block of a vector kernel");
+constexpr unsigned kRecSpin = 1u << 20;  // polls of one record word before giving up (NaN)
+
+__device__ double poll_tagged(const unsigned long long* w, unsigned tag) {
+  double v = 0;
+  unsigned it = 0;
+  while (!get_tagged<double>(w, tag, v) && ++it < kRecSpin) __builtin_amdgcn_s_sleep(1);
+  return it < kRecSpin ? v : __builtin_nan("");
+}
+
+// Sums the first n records at base in order (256 threads; thread r * 8 + j
+// reads column j of record r, n <= 32); column sums end in red[j][0].
+__device__ void sum_records(const unsigned long long* base, int n, int K, unsigned tag, double (*red)[256]) {
+  const int t = threadIdx.x, r = t >> 3, j = t & 7;
+  red[j][r] = (r < n && j < K) ? poll_tagged(base + ((size_t)r * 8 + j) * 2, tag) : 0.0;
+  __syncthreads();
+  if (t < 8) {
+    double s = 0;
+    for (int q = 0; q < n; ++q) s += red[t][q];
+    red[t][0] = s;  // row 0 of column t: only this thread touches column t here
+  }
+  __syncthreads();
+}
+
+__device__ bool arrive(unsigned* c, unsigned expected) {
+  __shared__ int last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    last = atomicAdd(c, 1u) == expected - 1;
+    if (last) atomicExch(c, 0u);
+  }
+  __syncthreads();
+  return last != 0;
+}
+
+// Block sums of acc, then the grid sums: true in the one block that holds
+// them (red[j][0], j < K) at the end.
+template <int K>
+__device__ bool grid_sums_tagged(const double* acc, unsigned long long* rec, unsigned* counters, unsigned tag,
+                                 double (*red)[256]) {
+  for (int j = 0; j < K; ++j) red[j][threadIdx.x] = acc[j];
+  __syncthreads();
+  for (int s = blockDim.x / 2; s >= 1; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int j = 0; j < K; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + s];
+    __syncthreads();
+  }
+  const int b = blockIdx.x, nb = gridDim.x;
+  if ((int)threadIdx.x < K) put_tagged<double>(rec + ((size_t)b * 8 + threadIdx.x) * 2, red[threadIdx.x][0], tag);
+  const int g = b / kGroup, ng = (nb + kGroup - 1) / kGroup;
+  const int gsize = min(kGroup, nb - g * kGroup);
+  if (!arrive(counters + g, gsize)) return false;
+  sum_records(rec + (size_t)g * kGroup * 16, gsize, K, tag, red);
+  unsigned long long* grec = rec + (size_t)kMaxRecBlocks * 16;
+  if ((int)threadIdx.x < K) put_tagged<double>(grec + ((size_t)g * 8 + threadIdx.x) * 2, red[threadIdx.x][0], tag);
+  if (!arrive(counters + kMaxRecBlocks / kGroup, ng)) return false;
+  sum_records(grec, ng, K, tag, red);
+  return true;
 }
 
 // out[j] = <x_j, y_j>, j < k <= 8
@@ -945,79 +1095,81 @@ hipError_t launch_dots(long long n, int k, VecPtrs<S> xs, VecPtrs<S> ys,
   return hipGetLastError();
 }
 
-// <v - Tv, w>
+// <v - Tv, w> into *out; the last block to finish sums the records and
+// publishes stats[0..8) (with out among them) when pub.mb is set
 template <typename S>
-__global__ void k_rdot(long long n, const S* __restrict__ v, const S* __restrict__ Tv,
-                       const S* __restrict__ w, double* __restrict__ partials) {
+__global__ void __launch_bounds__(256) k_rdot(long long n, long long nv, const S* __restrict__ v,
+                                              const S* __restrict__ Tv, const S* __restrict__ w,
+                                              unsigned long long* __restrict__ rec,
+                                              unsigned* __restrict__ counter, unsigned tag, double* out,
+                                              const double* stats, Publish pub) {
+  __shared__ double red[8][256];
+  constexpr int W = kVW<S>;
   double acc[1] = {0};
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
-       e += (long long)gridDim.x * blockDim.x)
-    acc[0] += ((double)v[e] - (double)Tv[e]) * (double)w[e];
-  block_sums<1>(acc, partials);
-}
-template <typename S>
-hipError_t launch_rdot(long long n, const S* v, const S* Tv, const S* w, double* partials,
-                       double* out_dev, hipStream_t st) {
-  const int nb = dots_blocks(n);
-  hipLaunchKernelGGL(k_rdot<S>, dim3(nb), dim3(256), 0, st, n, v, Tv, w, partials);
-  hipLaunchKernelGGL(k_final_sums, dim3(1), dim3(256), 0, st, partials, nb, 1, out_dev);
-  return hipGetLastError();
-}
-
-// Anderson push: r = v - Tv, dV = v - vprev, dR = r - rprev; dots
-// out[j] = <dR_old_j, dR_new> (j < m_old), out[m_old] = <dR_new, dR_new>,
-// out[m_old+1+j] = <dR_old_j, r>, out[2 m_old + 1] = <dR_new, r>.
-template <typename S>
-__global__ void k_aa_push(long long n, const S* __restrict__ v, const S* __restrict__ vprev,
-                          const S* __restrict__ Tv, const S* __restrict__ rprev, S* __restrict__ r_out,
-                          S* __restrict__ dV_new, S* __restrict__ dR_new, int m_old,
-                          VecPtrs<S> dR_old, double* __restrict__ partials) {
-  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
-       e += (long long)gridDim.x * blockDim.x) {
-    const S vv = v[e];
-    const S r = vv - Tv[e];
-    r_out[e] = r;
-    const S dr = r - rprev[e];
-    // the direction only needs dV - dR: that difference is stored
-    dV_new[e] = (S)(((double)vv - (double)vprev[e]) - (double)dr);
-    dR_new[e] = dr;
-    for (int j = 0; j < m_old; ++j) {
-      const double o = (double)dR_old.p[j][e];
-      acc[j] += o * (double)dr;
-      acc[m_old + 1 + j] += o * (double)r;
-    }
-    acc[m_old] += (double)dr * (double)dr;
-    acc[2 * m_old + 1] += (double)dr * (double)r;
-  }
-  block_sums<8>(acc, partials);
-}
-template <typename S>
-hipError_t launch_aa_push(long long n, const S* v, const S* vprev, const S* Tv, const S* rprev,
-                          S* r_out, S* dV_new, S* dR_new, int m_old, VecPtrs<S> dR_old,
-                          double* partials, double* out_dev, hipStream_t st) {
-  const int nb = dots_blocks(n);
-  hipLaunchKernelGGL(k_aa_push<S>, dim3(nb), dim3(256), 0, st, n, v, vprev, Tv, rprev, r_out,
-                     dV_new, dR_new, m_old, dR_old, partials);
-  hipLaunchKernelGGL(k_final_sums, dim3(1), dim3(256), 0, st, partials, nb, 2 * m_old + 2, out_dev);
-  return hipGetLastError();
-}
-
-// d = -r - sum_j gamma_j (dV_j - dR_j)
-template <typename S>
-__global__ void k_aa_dir(long long n, const S* __restrict__ r, int m, VecPtrs<S> dE,
-                         const double* __restrict__ gamma, S* __restrict__ d, const S* __restrict__ base,
-                         S* __restrict__ step) {
-  double g[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  SPK_GRID_LOOP(k, 0, nv) {
+    S a[W], b[W], c[W];
+    ld16(v, k, a);
+    ld16(Tv, k, b);
+    ld16(w, k, c);
 #pragma unroll
-  for (int j = 0; j < 8; ++j)
-    if (j < m) g[j] = gamma[j];
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
-       e += (long long)gridDim.x * blockDim.x) {
+    for (int q = 0; q < W; ++q) acc[0] += ((double)a[q] - (double)b[q]) * (double)c[q];
+  }
+  SPK_GRID_LOOP(e, nv * W, n) acc[0] += ((double)v[e] - (double)Tv[e]) * (double)w[e];
+  if (!grid_sums_tagged<1>(acc, rec, counter, tag, red)) return;
+  if (threadIdx.x == 0) {
+    *out = red[0][0];
+    if (pub.mb) {
+      double r[8];
+      for (int k = 0; k < 8; ++k) r[k] = stats[k];
+      publish_stats(r, pub);
+    }
+  }
+}
+template <typename S>
+hipError_t launch_rdot(long long n, const S* v, const S* Tv, const S* w, unsigned long long* rec, unsigned* counter,
+                       unsigned tag, double* out_dev, const double* stats, Publish pub, hipStream_t st) {
+  const int nb = dots_blocks(n);
+  hipLaunchKernelGGL(k_rdot<S>, dim3(nb), dim3(256), 0, st, n, nvec16<S>(n, {v, Tv, w}), v, Tv, w, rec, counter,
+                     tag, out_dev, stats, pub);
+  return hipGetLastError();
+}
+
+// d = -r - sum_j gamma_j (dV_j - dR_j), M columns; step = base + d when
+// step is set
+template <typename S, int M>
+__global__ void __launch_bounds__(256) k_aa_dir(long long n, long long nv, const S* __restrict__ r, VecPtrs<S> dE,
+                                                const double* __restrict__ gamma, S* __restrict__ d,
+                                                const S* __restrict__ base, S* __restrict__ step) {
+  constexpr int W = kVW<S>;
+  double g[M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) g[j] = gamma[j];
+  SPK_GRID_LOOP(k, 0, nv) {
+    S rv[W], ev[M][W], o[W];
+    ld16(r, k, rv);
+#pragma unroll
+    for (int j = 0; j < M; ++j) ld16(dE.p[j], k, ev[j]);
+    double acc[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+      acc[q] = -(double)rv[q];
+#pragma unroll
+      for (int j = 0; j < M; ++j) acc[q] -= g[j] * (double)ev[j][q];
+      o[q] = (S)acc[q];
+    }
+    st16(d, k, o);
+    if (step) {
+      S bv[W];
+      ld16(base, k, bv);
+#pragma unroll
+      for (int q = 0; q < W; ++q) o[q] = (S)((double)bv[q] + acc[q]);
+      st16(step, k, o);
+    }
+  }
+  SPK_GRID_LOOP(e, nv * W, n) {
     double acc = -(double)r[e];
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
-      if (j < m) acc -= g[j] * (double)dE.p[j][e];
+    for (int j = 0; j < M; ++j) acc -= g[j] * (double)dE.p[j][e];
     d[e] = (S)acc;
     if (step) step[e] = (S)((double)base[e] + acc);
   }
@@ -1096,8 +1248,8 @@ __device__ __forceinline__ void dev_eig_range(double (&A)[16], double& lmin, dou
 
 // Rank test and solve for the last N of the k active columns (rows/cols
 // `off..off+N` of Gk, right-hand side rk); true when kept.
-template <int N>
-__device__ __forceinline__ bool dev_aa_try(const double (&Gk)[16], const double (&rk)[4], int off, double (&g)[4]) {
+template <int N, int off>
+__device__ __forceinline__ bool dev_aa_try(const double (&Gk)[16], const double (&rk)[4], double (&g)[4]) {
   double E[16], L[16];
 #pragma unroll
   for (int i = 0; i < N; ++i)
@@ -1124,21 +1276,36 @@ __device__ __forceinline__ bool dev_aa_try(const double (&Gk)[16], const double 
   return true;
 }
 
-__global__ void k_aa_solve(double* __restrict__ G, double* __restrict__ rhs, const double* __restrict__ dots,
-                           AAPush a, double* __restrict__ gamma, double* __restrict__ kept_out) {
-  if (threadIdx.x != 0) return;
-  const int m = a.m, mo = a.mo, slot = a.slot;
-  for (int j = 0; j < mo; ++j) {
+// Tries the last K - DROP columns, then fewer; the number kept (0: none).
+template <int K, int DROP>
+__device__ __forceinline__ int aa_try_from(const double (&Gk)[16], const double (&rk)[4], double (&g)[4]) {
+  if constexpr (DROP >= K) {
+    return 0;
+  } else {
+    if (dev_aa_try<K - DROP, DROP>(Gk, rk, g)) return K - DROP;
+    return aa_try_from<K, DROP + 1>(Gk, rk, g);
+  }
+}
+
+// MO columns before the push (all indices fixed at compile time).
+template <int MO>
+__device__ __forceinline__ void aa_solve_dev(double* __restrict__ G, double* __restrict__ rhs,
+                                             const double (&dots)[8], const AAPush& a,
+                                             double* __restrict__ gamma, double* __restrict__ kept_out) {
+  const int m = a.m, slot = a.slot;
+#pragma unroll
+  for (int j = 0; j < MO; ++j) {
     G[a.order_old[j] * m + slot] = dots[j];
     G[slot * m + a.order_old[j]] = dots[j];
-    rhs[a.order_old[j]] = dots[mo + 1 + j];
+    rhs[a.order_old[j]] = dots[MO + 1 + j];
   }
-  G[slot * m + slot] = dots[mo];
-  rhs[slot] = dots[2 * mo + 1];
-  const int k = mo + 1;  // order_new = order_old + [slot]
+  G[slot * m + slot] = dots[MO];
+  rhs[slot] = dots[2 * MO + 1];
+  constexpr int k = MO + 1;  // order_new = order_old + [slot]
   int ord[4] = {0, 0, 0, 0};
-  for (int j = 0; j < mo; ++j) ord[j] = a.order_old[j];
-  ord[mo] = slot;
+#pragma unroll
+  for (int j = 0; j < MO; ++j) ord[j] = a.order_old[j];
+  ord[MO] = slot;
   // Gram matrix and right-hand side of the active columns, in registers
   double Gk[16], rk[4];
 #pragma unroll
@@ -1148,34 +1315,105 @@ __global__ void k_aa_solve(double* __restrict__ G, double* __restrict__ rhs, con
     for (int j = 0; j < 4; ++j) Gk[i * 4 + j] = (i < k && j < k) ? G[ord[i] * m + ord[j]] : 0.0;
   }
   double g[4] = {0, 0, 0, 0};
-  int kept = 0;
   // drop the oldest columns until the rest pass the rank test
-  for (int drop = 0; drop < k && kept == 0; ++drop) {
-    const int kk = k - drop;
-    bool ok = false;
-    switch (kk) {
-      case 4: ok = dev_aa_try<4>(Gk, rk, drop, g); break;
-      case 3: ok = dev_aa_try<3>(Gk, rk, drop, g); break;
-      case 2: ok = dev_aa_try<2>(Gk, rk, drop, g); break;
-      default: ok = dev_aa_try<1>(Gk, rk, drop, g); break;
-    }
-    if (ok) kept = kk;
-  }
+  const int kept = aa_try_from<k, 0>(Gk, rk, g);
   if (kept == 0) g[0] = g[1] = g[2] = g[3] = 0.0;
+#pragma unroll
   for (int j = 0; j < k; ++j) gamma[j] = g[j];
   *kept_out = (double)kept;
 }
 
-hipError_t launch_aa_solve(double* G, double* rhs, const double* dots, const AAPush& a, double* gamma,
-                           double* kept_out, hipStream_t st) {
-  hipLaunchKernelGGL(k_aa_solve, dim3(1), dim3(64), 0, st, G, rhs, dots, a, gamma, kept_out);
+// Anderson push: r = v - Tv, dV = v - vprev, dR = r - rprev, with the
+// difference E = dV - dR stored in place of dV (the direction needs only E);
+// dots[j] = <dR_old_j, dR_new> (j < m_old), dots[m_old] = <dR_new, dR_new>,
+// dots[m_old+1+j] = <dR_old_j, r>, dots[2 m_old + 1] = <dR_new, r>, summed
+// in a fixed order by the last block to finish, which then solves for gamma.
+template <typename S, int MO>
+__global__ void __launch_bounds__(256) k_aa_push(long long n, long long nv, const S* __restrict__ v,
+                                                 const S* __restrict__ vprev,
+                                                 const S* __restrict__ Tv, const S* __restrict__ rprev,
+                                                 S* __restrict__ r_out, S* __restrict__ dV_new,
+                                                 S* __restrict__ dR_new, VecPtrs<S> dR_old,
+                                                 unsigned long long* __restrict__ rec,
+                                                 unsigned* __restrict__ counter, unsigned tag, double* __restrict__ G, double* __restrict__ rhs, AAPush a,
+                                                 double* __restrict__ gamma, double* __restrict__ kept_out) {
+  __shared__ double red[8][256];
+  constexpr int m_old = MO;
+  constexpr int W = kVW<S>;
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // one element: r, dR and E = dV - dR, and the dot-product terms
+  auto elem = [&](S vv, S tv, S rp, S vp, const S (&o)[MO > 0 ? MO : 1], S& r, S& dr, S& ev) {
+    r = vv - tv;
+    dr = r - rp;
+    ev = (S)(((double)vv - (double)vp) - (double)dr);
+#pragma unroll
+    for (int j = 0; j < m_old; ++j) {
+      acc[j] += (double)o[j] * (double)dr;
+      acc[m_old + 1 + j] += (double)o[j] * (double)r;
+    }
+    acc[m_old] += (double)dr * (double)dr;
+    acc[2 * m_old + 1] += (double)dr * (double)r;
+  };
+  SPK_GRID_LOOP(k, 0, nv) {
+    S vv[W], tv[W], rp[W], vp[W], ov[MO > 0 ? MO : 1][W], r[W], dr[W], ev[W];
+    ld16(v, k, vv);
+    ld16(Tv, k, tv);
+    ld16(rprev, k, rp);
+    ld16(vprev, k, vp);
+#pragma unroll
+    for (int j = 0; j < MO; ++j) ld16(dR_old.p[j], k, ov[j]);
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+      S o[MO > 0 ? MO : 1];
+#pragma unroll
+      for (int j = 0; j < MO; ++j) o[j] = ov[j][q];
+      elem(vv[q], tv[q], rp[q], vp[q], o, r[q], dr[q], ev[q]);
+    }
+    st16(r_out, k, r);
+    st16(dR_new, k, dr);
+    st16(dV_new, k, ev);
+  }
+  SPK_GRID_LOOP(e, nv * W, n) {
+    S o[MO > 0 ? MO : 1];
+#pragma unroll
+    for (int j = 0; j < MO; ++j) o[j] = dR_old.p[j][e];
+    S r, dr, ev;
+    elem(v[e], Tv[e], rprev[e], vprev[e], o, r, dr, ev);
+    r_out[e] = r;
+    dR_new[e] = dr;
+    dV_new[e] = ev;
+  }
+  if (!grid_sums_tagged<2 * m_old + 2>(acc, rec, counter, tag, red)) return;
+  if (threadIdx.x == 0) {
+    double dots[8];
+    for (int k = 0; k < 8; ++k) dots[k] = red[k][0];
+    aa_solve_dev<MO>(G, rhs, dots, a, gamma, kept_out);
+  }
+}
+template <typename S>
+hipError_t launch_aa_push(long long n, const S* v, const S* vprev, const S* Tv, const S* rprev,
+                          S* r_out, S* dV_new, S* dR_new, VecPtrs<S> dR_old, unsigned long long* rec,
+                          unsigned* counter, unsigned tag, double* G, double* rhs, const AAPush& a, double* gamma,
+                          double* kept_out, hipStream_t st) {
+  if (a.mo < 0 || a.mo > 3 || a.m < 1 || a.m > 4) return hipErrorInvalidValue;
+  auto kern = a.mo == 0 ? k_aa_push<S, 0> : a.mo == 1 ? k_aa_push<S, 1> : a.mo == 2 ? k_aa_push<S, 2> : k_aa_push<S, 3>;
+  long long nv = nvec16<S>(n, {v, vprev, Tv, rprev, r_out, dV_new, dR_new});
+  for (int j = 0; j < a.mo; ++j)
+    if (!al16(dR_old.p[j])) nv = 0;
+  hipLaunchKernelGGL(kern, dim3(dots_blocks(n)), dim3(256), 0, st, n, nv, v, vprev, Tv, rprev, r_out, dV_new,
+                     dR_new, dR_old, rec, counter, tag, G, rhs, a, gamma, kept_out);
   return hipGetLastError();
 }
 
 template <typename S>
 hipError_t launch_aa_dir(long long n, const S* r, int m, VecPtrs<S> dE, const double* gamma_dev, S* d,
                          const S* base, S* step, hipStream_t st) {
-  hipLaunchKernelGGL(k_aa_dir<S>, dim3(dots_blocks(n)), dim3(256), 0, st, n, r, m, dE, gamma_dev, d, base, step);
+  if (m < 1 || m > 4) return hipErrorInvalidValue;
+  long long nv = nvec16<S>(n, {r, d, base, step});
+  for (int j = 0; j < m; ++j)
+    if (!al16(dE.p[j])) nv = 0;
+  auto kern = m == 1 ? k_aa_dir<S, 1> : m == 2 ? k_aa_dir<S, 2> : m == 3 ? k_aa_dir<S, 3> : k_aa_dir<S, 4>;
+  hipLaunchKernelGGL(kern, dim3(dots_blocks(n)), dim3(256), 0, st, n, nv, r, dE, gamma_dev, d, base, step);
   return hipGetLastError();
 }
 
@@ -1187,10 +1425,13 @@ hipError_t launch_aa_dir(long long n, const S* r, int m, VecPtrs<S> dE, const do
   template hipError_t launch_fill<S>(long long, S*, double, hipStream_t);                          \
   template hipError_t launch_dots<S>(long long, int, VecPtrs<S>, VecPtrs<S>, double*, double*,     \
                                      hipStream_t);                                                 \
-  template hipError_t launch_rdot<S>(long long, const S*, const S*, const S*, double*, double*,     \
-                                     hipStream_t);                                                 \
-  template hipError_t launch_aa_push<S>(long long, const S*, const S*, const S*, const S*, S*, S*, \
-                                        S*, int, VecPtrs<S>, double*, double*, hipStream_t);       \
+  template hipError_t launch_rdot<S>(long long, const S*, const S*, const S*, unsigned long long*,  \
+                                     unsigned*, unsigned, double*, const double*, Publish,          \
+                                     hipStream_t);                                                  \
+  template hipError_t launch_aa_push<S>(long long, const S*, const S*, const S*, const S*, S*, S*,  \
+                                        S*, VecPtrs<S>, unsigned long long*, unsigned*, unsigned,   \
+                                        double*, double*, const AAPush&, double*, double*,          \
+                                        hipStream_t);                                               \
   template hipError_t launch_aa_dir<S>(long long, const S*, int, VecPtrs<S>, const double*, S*,    \
                                        const S*, S*, hipStream_t);
 SPK_INST(double)

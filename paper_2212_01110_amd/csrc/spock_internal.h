@@ -85,6 +85,20 @@ struct FlowState {
   bool coop = false;
 };
 
+// Statistics of one evaluation of T handed to the host without a copy: the
+// last kernel writes them into pinned, coherent host memory and then the
+// epoch of the evaluation into flag (system-scope release); the host polls
+// the flag.
+struct Mailbox {
+  double v[8];
+  unsigned long long flag;
+  unsigned long long pad[7];
+};
+struct Publish {
+  Mailbox* mb = nullptr;  // device view of the mailbox (nullptr: no publish)
+  unsigned long long epoch = 0;
+};
+
 struct Problem {
   const Tree* tree = nullptr;
   int precision = SPOCK_FP64;
@@ -117,6 +131,9 @@ struct Problem {
   // when set, launch_T records prof[0..4] before the pre-pass, after it,
   // after the sweeps, after the post-pass and at the end (timing aid)
   hipEvent_t* prof = nullptr;
+  Mailbox* mbox = nullptr;      // host view (hipHostMalloc, coherent)
+  Mailbox* mbox_dev = nullptr;  // device view of the same memory
+  unsigned long long mbox_epoch = 0;
 };
 
 // ---------------------------------------------------------------- launchers
@@ -126,13 +143,12 @@ struct Problem {
 template <typename S>
 hipError_t launch_T(const Problem& P, const S* v, S* Tv, const double* x0, S* q, S* d, S* xbar,
                     S* ubar, double* partials, double* stats_dev, hipStream_t st,
-                    const S* eta_zero, bool dual);
+                    const S* eta_zero, bool dual, Publish pub = Publish{});
 int post_blocks(const Problem& P);
 // Dataflow form of the sweeps (flow.hip): one persistent launch per T.
 template <typename S>
 hipError_t launch_sweeps_flow(const Problem& P, const DevProb<S>& D, S* zout, const double* x0, const S* xbar,
                               const S* ubar, S* q, S* d, hipStream_t st);
-hipError_t launch_flow_check(const Problem& P, double* stats, hipStream_t st);
 int flow_lds_bytes(int nx, int nu, int nc, int elem);
 template <typename S>
 const void* flow_kernel(int occ);
@@ -162,10 +178,29 @@ hipError_t launch_lincomb3(long long n, S* out, double a, const S* x, double b, 
 template <typename S>
 hipError_t launch_dots(long long n, int k, VecPtrs<S> xs, VecPtrs<S> ys, double* partials,
                        double* out_dev, hipStream_t st);
+// Anderson step on the device: the push about to run (slots of the columns
+// before it, oldest first, and the slot of the new column).
+struct AAPush {
+  int m, mo, slot;
+  int order_old[4];
+};
+// Push of the newest difference pair, its Gram row and right-hand side
+// (fixed-order sums in the last workgroup to finish, counted on *counter,
+// which is left at zero), then the Gram solve in that workgroup: gamma for
+// every column of the order and the kept count to kept_out.
+// Grid sums finished inside a vector kernel: tagged records of the blocks
+// and of groups of kRedGroup blocks (kRedRecWords 64-bit words, zeroed once;
+// every launch's tag differs from the earlier ones' and is not 0) and
+// kRedCounters arrival counters (zero between launches).
+constexpr int kRedGroup = 32;
+constexpr int kRedMaxBlocks = 1024;
+constexpr int kRedRecWords = (kRedMaxBlocks + kRedMaxBlocks / kRedGroup) * 16;
+constexpr int kRedCounters = kRedMaxBlocks / kRedGroup + 1;
 template <typename S>
 hipError_t launch_aa_push(long long n, const S* v, const S* vprev, const S* Tv, const S* rprev,
-                          S* r_out, S* dV_new, S* dR_new, int m_old, VecPtrs<S> dR_old,
-                          double* partials, double* out_dev, hipStream_t st);
+                          S* r_out, S* dV_new, S* dR_new, VecPtrs<S> dR_old, unsigned long long* rec,
+                          unsigned* counter, unsigned tag, double* G, double* rhs, const AAPush& a, double* gamma,
+                          double* kept_out, hipStream_t st);
 template <typename S>
 // d = -r - sum_j gamma_j E_j with E_j = dV_j - dR_j (as stored by the push);
 // when step is non-null also step = base + d
@@ -173,20 +208,15 @@ hipError_t launch_aa_dir(long long n, const S* r, int m, VecPtrs<S> dE, const do
                          const S* base, S* step, hipStream_t st);
 template <typename S>
 hipError_t launch_fill(long long n, S* out, double val, hipStream_t st);
+// <v - Tv, w> to *out_dev (fixed-order sum in the last workgroup to finish,
+// counted on *counter, over tagged records as for the push), then the
+// statistics stats[0..8) published to pub.
 template <typename S>
-hipError_t launch_rdot(long long n, const S* v, const S* Tv, const S* w, double* partials,
-                       double* out_dev, hipStream_t st);
+hipError_t launch_rdot(long long n, const S* v, const S* Tv, const S* w, unsigned long long* rec, unsigned* counter,
+                       unsigned tag, double* out_dev, const double* stats, Publish pub, hipStream_t st);
 
 int dots_blocks(long long n);
 
-// Anderson step on the device: the push that just ran (slots of the columns
-// before it, oldest first, and the slot of the new column).
-struct AAPush {
-  int m, mo, slot;
-  int order_old[4];
-};
-hipError_t launch_aa_solve(double* G, double* rhs, const double* dots, const AAPush& a, double* gamma,
-                           double* kept_out, hipStream_t st);
 
 // ---------------------------------------------------------------- batched engine
 struct BatchSettings {
