@@ -4,11 +4,15 @@
 // seeds, S2) runs before it and the parallel post-pass (dual update and
 // statistics) after it, as in the per-stage form.
 //
-// Work items, in this order:
-//   [0, nl)        backward step of family nl-1-t (reverse breadth-first:
-//                  every child family comes first)
-//   [nl, 2 nl)     forward step of family t-nl (breadth-first: the parent
-//                  comes first)
+// Work items: one per chunk of (at most nc) children of a family; the
+// backward items come first, families in reverse breadth-first order (every
+// child family comes first), then the forward items in breadth-first order
+// (the parent comes first), the chunks of a family in increasing order.
+// A family with several chunks has them on different workgroups at the same
+// time: in the forward sweep each writes its own children's states; in the
+// backward sweep each but the last publishes its partial sums
+// sum_c Abar^c' q^c and sum_c B^c' q^c, which the last one adds, in chunk
+// order, to its own before the family's step.
 // Workgroup b runs items b, b + G, b + 2G, ... (G = grid size = the
 // resident capacity from the occupancy of the kernel; a cooperative launch
 // guarantees residency, a plain one, the default, has it whenever the device
@@ -170,20 +174,38 @@ struct FlowArgs {
   unsigned long long* qt;    // [nl][nx] tagged q
   unsigned long long* dt;    // [nl][nu] tagged d
   unsigned long long* xt;    // [nn][nx] tagged x (forward step of the parent)
+  unsigned long long* pt;    // [slots][nx + nu] tagged partial sums of backward chunks
+  const int* items;          // family * kChunkCodes + chunk: backward items, then forward
+  const int* pbase;          // [nl] first partial slot of a family with several chunks
   unsigned* err;             // [1]
   unsigned tag;
-  int nc, items;
+  int nc, nbwd, nitems;
 };
+
+// One tagged element polled by the calling thread (bounded).
+template <typename S>
+__device__ __forceinline__ S wait_one(const unsigned long long* p, unsigned tag, unsigned* err) {
+  S v = 0;
+  for (unsigned it = 0; it < kSpinLimit; ++it) {
+    if (get_tagged<S>(p, tag, v)) return v;
+    if ((it & 255u) == 255u && ld_flag(err) != 0u) return v;
+    __builtin_amdgcn_s_sleep(1);
+  }
+  __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return v;
+}
 
 // ---------------------------------------------------------------- backward item
 // Alg. 2 backward step regrouped: with g = ubar - sum_c B^c' q^c,
 //   d = R~^{-1} g,   q = M1 g + c0 + sum_c Abar^c' q^c,
 //   M1 = (K' + W) R~^{-1} (offline, FP64),  c0 = -K' ubar - xbar.
-// Wavefront 3 polls the children's q while the copies are in flight; K' ubar
-// and the children's products then form one mat-vec phase, R~^{-1} g and
-// M1 g a second.
+// Chunk j of family i (children j nc, ...). Wavefront 3 polls the chunk's
+// children's q while the copies are in flight. A chunk that is not the
+// family's last publishes its two partial sums; the last chunk forms K' ubar
+// with its children's products in one mat-vec phase, adds the earlier
+// chunks' partial sums (chunk order), then R~^{-1} g and M1 g.
 template <typename S>
-__device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, int i) {
+__device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, int i, int j) {
   __shared__ S vg[kMaxDim];
   const DevProb<S>& P = A.P;
   const int t = threadIdx.x, w = t >> 6;
@@ -197,54 +219,70 @@ __device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, 
   S* redB = redA + kFW;                           // sum_c B' q; then R~^{-1} g
   S* redC = redB + kFW;                           // K' ubar; then M1 g
   const bool leafkids = fc >= P.nl;
-  for (int k0 = 0; k0 < n; k0 += L.nc) {
-    const int kc = min(L.nc, n - k0);
-    int rot = 0;
-    for (int k = 0; k < kc; ++k) {
-      dma_words(P.AbR + (size_t)(fc + k0 + k) * nx * nx, lds, L.oA + k * L.sA, nx * nx * es, rot++);
-      dma_words(P.BR + (size_t)(fc + k0 + k) * nx * nu, lds, L.oB + k * L.sB, nx * nu * es, rot++);
-    }
-    if (k0 == 0) {
-      dma_words(P.Rinv + (size_t)i * nu * nu, lds, L.oR, nu * nu * es, rot++);
-      dma_words(P.KR + (size_t)i * nu * nx, lds, L.oK, nu * nx * es, rot++);
-      dma_words(P.M1C + (size_t)i * nu * nx, lds, L.oW, nu * nx * es, rot++);
-      dma_words(A.xbar + (size_t)i * nx, lds, L.oX, nx * es, rot++);
-      dma_words(A.ubar + (size_t)i * nu, lds, L.oU, nu * es, rot++);
-    }
-    if (leafkids)  // seeds -xbar of the leaf children, written by the pre-pass
-      dma_words(A.seeds + (size_t)(fc + k0) * nx, lds, L.oQ, kc * nx * es, rot++);
-    else if (w == 3)  // children's q from their backward items
-      wait_tagged<S>(A.qt + (size_t)(fc + k0) * nx * kTW<S>, kc * nx, A.tag, reinterpret_cast<S*>(lds + L.oQ), A.err);
-    wait_vm();
-    __syncthreads();
-    if (k0 == 0) mv_part<S>(M + L.oK / es, ub, nu, nx, redC, false);
-    for (int k = 0; k < kc; ++k) {
-      mv_part<S>(M + L.oA / es + k * (L.sA / es), qv + k * nx, nx, nx, redA, k0 + k > 0);
-      mv_part<S>(M + L.oB / es + k * (L.sB / es), qv + k * nx, nx, nu, redB, k0 + k > 0);
-    }
-    __syncthreads();  // matrices and q consumed before the next chunk's copies
+  const int k0 = j * L.nc, kc = min(L.nc, n - k0);
+  const bool last = k0 + kc == n;
+  int rot = 0;
+  for (int k = 0; k < kc; ++k) {
+    dma_words(P.AbR + (size_t)(fc + k0 + k) * nx * nx, lds, L.oA + k * L.sA, nx * nx * es, rot++);
+    dma_words(P.BR + (size_t)(fc + k0 + k) * nx * nu, lds, L.oB + k * L.sB, nx * nu * es, rot++);
+  }
+  if (last) {
+    dma_words(P.Rinv + (size_t)i * nu * nu, lds, L.oR, nu * nu * es, rot++);
+    dma_words(P.KR + (size_t)i * nu * nx, lds, L.oK, nu * nx * es, rot++);
+    dma_words(P.M1C + (size_t)i * nu * nx, lds, L.oW, nu * nx * es, rot++);
+    dma_words(A.xbar + (size_t)i * nx, lds, L.oX, nx * es, rot++);
+    dma_words(A.ubar + (size_t)i * nu, lds, L.oU, nu * es, rot++);
+  }
+  if (leafkids)  // seeds -xbar of the leaf children, written by the pre-pass
+    dma_words(A.seeds + (size_t)(fc + k0) * nx, lds, L.oQ, kc * nx * es, rot++);
+  else if (w == 3)  // children's q from their backward items
+    wait_tagged<S>(A.qt + (size_t)(fc + k0) * nx * kTW<S>, kc * nx, A.tag, reinterpret_cast<S*>(lds + L.oQ), A.err);
+  wait_vm();
+  __syncthreads();
+  if (last) mv_part<S>(M + L.oK / es, ub, nu, nx, redC, false);
+  for (int k = 0; k < kc; ++k) {
+    mv_part<S>(M + L.oA / es + k * (L.sA / es), qv + k * nx, nx, nx, redA, k > 0);
+    mv_part<S>(M + L.oB / es + k * (L.sB / es), qv + k * nx, nx, nu, redB, k > 0);
+  }
+  __syncthreads();
+  const int nprev = k0 / L.nc;  // chunks before this one
+  if (!last) {
+    unsigned long long* pp = A.pt + (size_t)(A.pbase[i] + j) * (nx + nu) * kTW<S>;
+    if (t < nx) put_tagged<S>(pp + (size_t)t * kTW<S>, mv_fold<S>(redA, nx, t), A.tag);
+    if (t < nu) put_tagged<S>(pp + (size_t)(nx + t) * kTW<S>, mv_fold<S>(redB, nu, t), A.tag);
+    __syncthreads();  // LDS reuse by the next item
+    return;
+  }
+  // this chunk's sums after the earlier chunks' (chunk order)
+  const unsigned long long* pp = nprev > 0 ? A.pt + (size_t)A.pbase[i] * (nx + nu) * kTW<S> : nullptr;
+  S sa = 0;
+  if (t < nx) {
+    for (int q = 0; q < nprev; ++q) sa += wait_one<S>(pp + ((size_t)q * (nx + nu) + t) * kTW<S>, A.tag, A.err);
+    sa += mv_fold<S>(redA, nx, t);
   }
   // g = ubar - sum_c B' q; c0 = -K' ubar - xbar (kept by thread t < nx)
   S c0 = 0;
   if (t < nx) c0 = -mv_fold<S>(redC, nx, t) - xb[t];
-  if (t < nu) vg[t] = ub[t] - mv_fold<S>(redB, nu, t);
+  if (t < nu) {
+    S sb = 0;
+    for (int q = 0; q < nprev; ++q) sb += wait_one<S>(pp + ((size_t)q * (nx + nu) + nx + t) * kTW<S>, A.tag, A.err);
+    vg[t] = ub[t] - (sb + mv_fold<S>(redB, nu, t));
+  }
   __syncthreads();
   mv_part<S>(M + L.oR / es, vg, nu, nu, redB, false);
   mv_part<S>(M + L.oW / es, vg, nu, nx, redC, false);
   __syncthreads();
   if (t < nu) put_tagged<S>(A.dt + ((size_t)i * nu + t) * kTW<S>, mv_fold<S>(redB, nu, t), A.tag);
-  if (t < nx)
-    put_tagged<S>(A.qt + ((size_t)i * nx + t) * kTW<S>, mv_fold<S>(redC, nx, t) + mv_fold<S>(redA, nx, t) + c0,
-                  A.tag);
+  if (t < nx) put_tagged<S>(A.qt + ((size_t)i * nx + t) * kTW<S>, mv_fold<S>(redC, nx, t) + sa + c0, A.tag);
   __syncthreads();  // LDS reuse by the next item
 }
 
 // ---------------------------------------------------------------- forward item
-// u = K x + d; x^c = Abar^c x + B^c d; x^0 = x0 at the root. Wavefront 0
-// polls d (the family's backward step) and x (the parent's forward step)
-// while the copies are in flight.
+// u = K x + d (chunk 0); x^c = Abar^c x + B^c d for the chunk's children;
+// x^0 = x0 at the root. Wavefront 0 polls d (the family's backward step) and
+// x (the parent's forward step) while the copies are in flight.
 template <typename S>
-__device__ void flow_fwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, int i) {
+__device__ void flow_fwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, int i, int j) {
   const DevProb<S>& P = A.P;
   const Off<S> O(P);
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
@@ -254,43 +292,39 @@ __device__ void flow_fwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, 
   S* vx = reinterpret_cast<S*>(lds + L.oX);
   S* vd = reinterpret_cast<S*>(lds + L.oU);
   S* red = reinterpret_cast<S*>(lds + L.oRed);  // [child k] partials; [nc] K x
-  for (int k0 = 0; k0 < n; k0 += L.nc) {
-    const int kc = min(L.nc, n - k0);
-    int rot = 1;
-    for (int k = 0; k < kc; ++k) {
-      dma_words(P.AbC + (size_t)(fc + k0 + k) * nx * nx, lds, L.oA + k * L.sA, nx * nx * es, rot++);
-      dma_words(P.BC + (size_t)(fc + k0 + k) * nu * nx, lds, L.oB + k * L.sB, nx * nu * es, rot++);
-    }
-    if (k0 == 0) {
-      dma_words(P.KC + (size_t)i * nx * nu, lds, L.oK, nx * nu * es, rot++);
-      if (w == 0) {
-        wait_tagged<S>(A.dt + (size_t)i * nu * kTW<S>, nu, A.tag, vd, A.err);
-        if (i != 0) {
-          wait_tagged<S>(A.xt + (size_t)i * nx * kTW<S>, nx, A.tag, vx, A.err);
-        } else if (lane < nx) {
-          const S xv = (S)A.x0[lane];
-          A.zout[1 + lane] = xv;
-          vx[lane] = xv;
-        }
-      }
-    }
-    wait_vm();
-    __syncthreads();
-    if (k0 == 0) mv_part<S>(M + L.oK / es, vx, nx, nu, red + L.nc * kFW, false);
-    for (int k = 0; k < kc; ++k) {
-      mv_part<S>(M + L.oB / es + k * (L.sB / es), vd, nu, nx, red + k * kFW, false);
-      mv_part<S>(M + L.oA / es + k * (L.sA / es), vx, nx, nx, red + k * kFW, true);
-    }
-    __syncthreads();
-    if (k0 == 0 && t < nu) A.zout[O.u(i) + t] = mv_fold<S>(red + L.nc * kFW, nu, t) + vd[t];
-    for (int k = 0; k < kc; ++k)
-      if (t < nx) {
-        const S xc = mv_fold<S>(red + k * kFW, nx, t);
-        A.zout[O.x(fc + k0 + k) + t] = xc;
-        if (fc + k0 + k < P.nl) put_tagged<S>(A.xt + ((size_t)(fc + k0 + k) * nx + t) * kTW<S>, xc, A.tag);
-      }
-    __syncthreads();  // red and the matrices are reused by the next chunk / item
+  const int k0 = j * L.nc, kc = min(L.nc, n - k0);
+  int rot = 1;
+  for (int k = 0; k < kc; ++k) {
+    dma_words(P.AbC + (size_t)(fc + k0 + k) * nx * nx, lds, L.oA + k * L.sA, nx * nx * es, rot++);
+    dma_words(P.BC + (size_t)(fc + k0 + k) * nu * nx, lds, L.oB + k * L.sB, nx * nu * es, rot++);
   }
+  if (j == 0) dma_words(P.KC + (size_t)i * nx * nu, lds, L.oK, nx * nu * es, rot++);
+  if (w == 0) {
+    wait_tagged<S>(A.dt + (size_t)i * nu * kTW<S>, nu, A.tag, vd, A.err);
+    if (i != 0) {
+      wait_tagged<S>(A.xt + (size_t)i * nx * kTW<S>, nx, A.tag, vx, A.err);
+    } else if (lane < nx) {
+      const S xv = (S)A.x0[lane];
+      if (j == 0) A.zout[1 + lane] = xv;
+      vx[lane] = xv;
+    }
+  }
+  wait_vm();
+  __syncthreads();
+  if (j == 0) mv_part<S>(M + L.oK / es, vx, nx, nu, red + L.nc * kFW, false);
+  for (int k = 0; k < kc; ++k) {
+    mv_part<S>(M + L.oB / es + k * (L.sB / es), vd, nu, nx, red + k * kFW, false);
+    mv_part<S>(M + L.oA / es + k * (L.sA / es), vx, nx, nx, red + k * kFW, true);
+  }
+  __syncthreads();
+  if (j == 0 && t < nu) A.zout[O.u(i) + t] = mv_fold<S>(red + L.nc * kFW, nu, t) + vd[t];
+  for (int k = 0; k < kc; ++k)
+    if (t < nx) {
+      const S xc = mv_fold<S>(red + k * kFW, nx, t);
+      A.zout[O.x(fc + k0 + k) + t] = xc;
+      if (fc + k0 + k < P.nl) put_tagged<S>(A.xt + ((size_t)(fc + k0 + k) * nx + t) * kTW<S>, xc, A.tag);
+    }
+  __syncthreads();  // red and the matrices are reused by the next item
 }
 
 // W: minimum wavefronts per SIMD the register allocation must allow.
@@ -298,11 +332,11 @@ template <typename S, int W>
 __global__ void __launch_bounds__(kFW) __attribute__((amdgpu_waves_per_eu(W, 8))) k_T_flow(FlowArgs<S> A) {
   extern __shared__ __align__(16) unsigned flow_lds[];
   const FlowLds L(A.P.nx, A.P.nu, A.nc, (int)(sizeof(S) / 4));
-  const int nl = A.P.nl;
   // items run in increasing order in every workgroup
-  for (int it = blockIdx.x; it < A.items; it += gridDim.x) {
-    if (it < nl) flow_bwd<S>(A, L, flow_lds, nl - 1 - it);
-    else flow_fwd<S>(A, L, flow_lds, it - nl);
+  for (int it = blockIdx.x; it < A.nitems; it += gridDim.x) {
+    const int code = A.items[it];
+    if (it < A.nbwd) flow_bwd<S>(A, L, flow_lds, code / kChunkCodes, code % kChunkCodes);
+    else flow_fwd<S>(A, L, flow_lds, code / kChunkCodes, code % kChunkCodes);
   }
 }
 
@@ -334,12 +368,16 @@ hipError_t launch_sweeps_flow(const Problem& P, const DevProb<S>& D, S* zout, co
   A.qt = F.qt;
   A.dt = F.dt;
   A.xt = F.xt;
+  A.pt = F.pt;
+  A.items = F.items;
+  A.pbase = F.pbase;
   A.err = F.err;
   if (++P.flow_epoch == 0u) P.flow_epoch = 1u;  // tag 0 is the cleared state
   A.tag = P.flow_epoch;
   A.nc = F.nc;
-  A.items = 2 * P.tree->nl;
-  const int grid = std::min(F.grid, A.items);
+  A.nbwd = F.nbwd;
+  A.nitems = 2 * F.nbwd;
+  const int grid = std::min(F.grid, A.nitems);
   const size_t lds = (size_t)flow_lds_bytes(P.nx, P.nu, F.nc, (int)sizeof(S));
   void* args[] = {&A};
   if (F.coop) return hipLaunchCooperativeKernel(flow_kernel<S>(F.occ), dim3(grid), dim3(kFW), args, (unsigned)lds, st);

@@ -674,15 +674,40 @@ int ensure_flow(Problem& P, int occ = 0, int budget = 0) {
     return SPOCK_EHIP;
   if (fits && hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, flow_kernel<S>(occ), 256, (size_t)lds) != hipSuccess)
     return SPOCK_EHIP;
+  // items: one per chunk of nc children; backward (reverse breadth-first),
+  // then forward (breadth-first); partial slots for families of several chunks
+  std::vector<int> items, pbase(T.nl, 0);
+  int nslots = 0;
+  for (int i = T.nl - 1; i >= 0; --i) {
+    const int J = (T.nch[i] + nc - 1) / nc;
+    if (J >= kChunkCodes) return SPOCK_EINVAL;
+    for (int j = 0; j < J; ++j) items.push_back(i * kChunkCodes + j);
+    if (J > 1) {
+      pbase[i] = nslots;
+      nslots += J - 1;
+    }
+  }
+  const int nbwd = (int)items.size();
+  for (int i = 0; i < T.nl; ++i)
+    for (int j = 0, J = (T.nch[i] + nc - 1) / nc; j < J; ++j) items.push_back(i * kChunkCodes + j);
   const size_t tw = sizeof(S) / 4;  // tagged words per element
   const size_t nq = (size_t)T.nl * P.nx * tw, nd = (size_t)T.nl * P.nu * tw, nxw = (size_t)T.nn * P.nx * tw;
-  const size_t bytes = 256 + sizeof(unsigned long long) * (nq + nd + nxw);
+  const size_t npw = (size_t)nslots * (P.nx + P.nu) * tw;
+  const size_t tagged = sizeof(unsigned long long) * (nq + nd + nxw + npw);
+  const size_t bytes = 256 + tagged + sizeof(int) * (items.size() + pbase.size());
   if (hipMalloc(&F.mem, bytes) != hipSuccess) return SPOCK_ENOMEM;
   if (hipMemset(F.mem, 0, bytes) != hipSuccess) return SPOCK_EHIP;
   F.err = static_cast<unsigned*>(F.mem);
   F.qt = reinterpret_cast<unsigned long long*>(static_cast<char*>(F.mem) + 256);
   F.dt = F.qt + nq;
   F.xt = F.dt + nd;
+  F.pt = F.xt + nxw;
+  F.items = reinterpret_cast<int*>(static_cast<char*>(F.mem) + 256 + tagged);
+  F.pbase = F.items + items.size();
+  F.nbwd = nbwd;
+  if (hipMemcpy(F.items, items.data(), sizeof(int) * items.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(F.pbase, pbase.data(), sizeof(int) * pbase.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return SPOCK_EHIP;
   F.nc = nc;
   F.occ = occ;
   F.budget = budget;

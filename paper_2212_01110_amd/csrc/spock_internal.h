@@ -68,12 +68,17 @@ struct DevArrays {
 // buffers (q, d of the backward step, x of the forward step; 64-bit words
 // holding the launch epoch and half of a value, zeroed once and never
 // cleared) and an error word raised by a bounded poll that gave up.
+constexpr int kChunkCodes = 64;  // item code = family * kChunkCodes + chunk (chunks per family < 64)
 struct FlowState {
   void* mem = nullptr;
   unsigned* err = nullptr;          // [1]
   unsigned long long* qt = nullptr;  // [nl][nx][words per element]
   unsigned long long* dt = nullptr;  // [nl][nu][...]
   unsigned long long* xt = nullptr;  // [nn][nx][...]
+  unsigned long long* pt = nullptr;  // [slots][nx + nu][...] partial sums of backward chunks
+  int* items = nullptr;              // family * kChunkCodes + chunk; backward, then forward
+  int* pbase = nullptr;              // [nl] first partial slot of a family with several chunks
+  int nbwd = 0;                      // backward items (as many forward items follow)
   int nc = 1;                        // children per LDS chunk
   int grid = 0;                      // resident workgroups (0: form unavailable)
   int occ = 5;                       // register budget: 4 or 5 wavefronts per SIMD
