@@ -78,16 +78,30 @@ struct FlowLds {
 };
 
 // Copies nwords 32-bit words from global memory into LDS (dst = word
-// offset); wavefront w issues rows w', w' + 4, ... of 64 words, w' = w
-// rotated by `rot` so that small copies spread over the wavefronts. Lanes
-// past the end re-read the last word (in bounds) into the region's padding.
+// offset, a multiple of 64). From a 16-byte aligned source, whole rows of
+// 256 words go as 16 bytes per lane (lane l fills words 4l..4l+3 of the
+// row); the rest (all of it from an unaligned source) goes in rows of 64
+// words, 4 bytes per lane, lanes past the end re-reading the last word (in
+// bounds) into the region's padding. Wavefront w issues rows w', w' + 4, ...
+// (w' = w rotated by `rot`, so that small copies spread over the
+// wavefronts).
 __device__ __forceinline__ void dma_words(const void* src, unsigned* lds, int dst, int nwords, int rot) {
   const int lane = threadIdx.x & 63, w = ((threadIdx.x >> 6) + rot) & 3;
-  const unsigned* s = static_cast<const unsigned*>(src);
-  for (int r = w; r * 64 < nwords; r += 4) {
+  // uniform base + 32-bit lane byte offset (scalar-base addressing)
+  const char* s = static_cast<const char*>(src);
+  int done = 0;
+  if ((reinterpret_cast<uintptr_t>(src) & 15u) == 0) {
+    const int rows = nwords >> 8;
+    for (int r = w; r < rows; r += 4)
+      __builtin_amdgcn_global_load_lds(s + (unsigned)((r * 256 + lane * 4) * 4), (lds_void*)(lds + dst + r * 256), 16, 0,
+                                       0);
+    done = rows << 8;
+  }
+  const int rest = nwords - done;
+  for (int r = w; r * 64 < rest; r += 4) {
     int e = r * 64 + lane;
-    e = e < nwords ? e : nwords - 1;
-    __builtin_amdgcn_global_load_lds(s + e, (lds_void*)(lds + dst + r * 64), 4, 0, 0);
+    e = e < rest ? e : rest - 1;
+    __builtin_amdgcn_global_load_lds(s + (unsigned)((done + e) * 4), (lds_void*)(lds + dst + done + r * 64), 4, 0, 0);
   }
 }
 
