@@ -51,10 +51,15 @@ typedef __attribute__((address_space(3))) void lds_void;
 
 // Word offsets of the dynamic LDS regions (32-bit words; every region is a
 // whole number of 64-word rows so that a wavefront copy may overrun it).
+// The mat-vec partial sums of an output vector of n entries take
+// min(4, 256 / n) * n elements (at most kFoldMax partial sums per output):
+// rx for n_x outputs, ru for n_u outputs. Backward: A' q (rx), B' q then
+// R~^{-1} g (ru), K' ubar then M1 g (rx); forward: child k (rx each), K x (ru).
 struct FlowLds {
   int esz;     // words per element
   int sA, sB;  // per-child strides of the Abar and B regions
   int oA, oB, oR, oK, oW, oQ, oX, oU, oRed;  // oW: M1 (backward)
+  int rx, ru;  // elements of an n_x-output and an n_u-output partial-sum area
   int nc;      // children per chunk
   int words;
   __host__ __device__ static int pad(int w) { return (w + 63) & ~63; }
@@ -68,11 +73,13 @@ struct FlowLds {
     oR = oB + nc * sB;
     oK = oR + pad(nu * nu * esz);
     oW = oK + pad(nx * nu * esz);
-    oQ = oW + pad(nx * nu * esz);  // children's q (chunk), row stride nx
-    oX = oQ + pad(nc * nx * esz);  // xbar (backward) or x (forward)
+    oQ = oW + pad(nx * nu * esz);  // children's q (chunk), row stride nx; then g
+    oX = oQ + pad((nc * nx > nu ? nc * nx : nu) * esz);  // xbar (backward) or x (forward)
     oU = oX + pad(nx * esz);       // ubar (backward) or d (forward)
     oRed = oU + pad(nu * esz);
-    words = oRed + pad((nc + 1 > 3 ? nc + 1 : 3) * kFW * esz);
+    rx = (kFW / nx < kFoldMax ? kFW / nx : kFoldMax) * nx;
+    ru = (kFW / nu < kFoldMax ? kFW / nu : kFoldMax) * nu;
+    words = oRed + pad(((nc > 2 ? nc : 2) * rx + ru) * esz);
   }
   __host__ __device__ int bytes() const { return words * 4; }
 };
@@ -220,7 +227,6 @@ __device__ __forceinline__ S wait_one(const unsigned long long* p, unsigned tag,
 // chunks' partial sums (chunk order), then R~^{-1} g and M1 g.
 template <typename S>
 __device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, int i, int j) {
-  __shared__ S vg[kMaxDim];
   const DevProb<S>& P = A.P;
   const int t = threadIdx.x, w = t >> 6;
   const int nx = P.nx, nu = P.nu, fc = P.fc[i], n = P.nch[i];
@@ -230,8 +236,9 @@ __device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, 
   const S* xb = reinterpret_cast<const S*>(lds + L.oX);
   const S* ub = reinterpret_cast<const S*>(lds + L.oU);
   S* redA = reinterpret_cast<S*>(lds + L.oRed);  // sum_c Abar' q partials
-  S* redB = redA + kFW;                           // sum_c B' q; then R~^{-1} g
-  S* redC = redB + kFW;                           // K' ubar; then M1 g
+  S* redC = redA + L.rx;                          // K' ubar; then M1 g
+  S* redB = redC + L.rx;                          // sum_c B' q; then R~^{-1} g
+  S* vg = reinterpret_cast<S*>(lds + L.oQ);       // g, once the children's q are consumed
   const bool leafkids = fc >= P.nl;
   const int k0 = j * L.nc, kc = min(L.nc, n - k0);
   const bool last = k0 + kc == n;
@@ -305,7 +312,7 @@ __device__ void flow_fwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, 
   S* M = reinterpret_cast<S*>(lds);
   S* vx = reinterpret_cast<S*>(lds + L.oX);
   S* vd = reinterpret_cast<S*>(lds + L.oU);
-  S* red = reinterpret_cast<S*>(lds + L.oRed);  // [child k] partials; [nc] K x
+  S* red = reinterpret_cast<S*>(lds + L.oRed);  // [child k] partials (rx each); then K x (ru)
   const int k0 = j * L.nc, kc = min(L.nc, n - k0);
   int rot = 1;
   for (int k = 0; k < kc; ++k) {
@@ -325,16 +332,17 @@ __device__ void flow_fwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, 
   }
   wait_vm();
   __syncthreads();
-  if (j == 0) mv_part<S>(M + L.oK / es, vx, nx, nu, red + L.nc * kFW, false);
+  S* redK = red + (L.nc > 2 ? L.nc : 2) * L.rx;
+  if (j == 0) mv_part<S>(M + L.oK / es, vx, nx, nu, redK, false);
   for (int k = 0; k < kc; ++k) {
-    mv_part<S>(M + L.oB / es + k * (L.sB / es), vd, nu, nx, red + k * kFW, false);
-    mv_part<S>(M + L.oA / es + k * (L.sA / es), vx, nx, nx, red + k * kFW, true);
+    mv_part<S>(M + L.oB / es + k * (L.sB / es), vd, nu, nx, red + k * L.rx, false);
+    mv_part<S>(M + L.oA / es + k * (L.sA / es), vx, nx, nx, red + k * L.rx, true);
   }
   __syncthreads();
-  if (j == 0 && t < nu) A.zout[O.u(i) + t] = mv_fold<S>(red + L.nc * kFW, nu, t) + vd[t];
+  if (j == 0 && t < nu) A.zout[O.u(i) + t] = mv_fold<S>(redK, nu, t) + vd[t];
   for (int k = 0; k < kc; ++k)
     if (t < nx) {
-      const S xc = mv_fold<S>(red + k * kFW, nx, t);
+      const S xc = mv_fold<S>(red + k * L.rx, nx, t);
       A.zout[O.x(fc + k0 + k) + t] = xc;
       if (fc + k0 + k < P.nl) put_tagged<S>(A.xt + ((size_t)(fc + k0 + k) * nx + t) * kTW<S>, xc, A.tag);
     }

@@ -845,6 +845,16 @@ int autotune(Problem& P, hipStream_t st) {
     HIP_TRY(hipEventSynchronize(e1));
     float ms = 0;
     HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    if (c.first == kTeamFlow) {
+      // a bounded wait that gave up (a grid that was not all resident):
+      // the candidate is rejected, whatever its time
+      unsigned err = 0;
+      HIP_TRY(hipMemcpy(&err, P.flow.err, sizeof(unsigned), hipMemcpyDeviceToHost));
+      if (err != 0u) {
+        HIP_TRY(hipMemset(P.flow.err, 0, sizeof(unsigned)));
+        continue;
+      }
+    }
     if (ms < best) {
       best = ms;
       best_map = c;
