@@ -627,7 +627,7 @@ struct Work {
   double* stats = nullptr;    // [8]
   double* dots = nullptr;     // [16]
   double* gamma = nullptr;    // [8]
-  double* aaG = nullptr;      // Anderson Gram matrix [16] (by slot) and right-hand side [16..20)
+  double* aaG = nullptr;      // Anderson Gram matrix [16] (by slot)
   double* vpart = nullptr;    // vector-kernel partials [blocks][8]
   S* eta_zero = nullptr;      // n_eta zeros
   double* x0_zero = nullptr;  // kMaxDim zeros (autotuning input)
@@ -1075,7 +1075,7 @@ int solve_impl(Problem& P, const double* x0, const spock_settings& s, S* vio, sp
         a.order_old[j] = ring.order[j];
       }
       HIP_TRY(launch_aa_push<S>(nv, v, vprev, Tv, rprev, rcur, dV[slot], dR[slot], olds, W.rec, W.counters,
-                                W.next_tag(), W.aaG, W.aaG + 16, a, W.gamma, W.stats + 7, st));
+                                W.next_tag(), W.aaG, a, W.gamma, W.stats + 7, st));
       ring.order.push_back(slot);
       pending_k = mo + 1;
       VecPtrs<S> pe{};

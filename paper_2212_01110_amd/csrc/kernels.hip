@@ -1054,9 +1054,9 @@ __device__ bool arrive(unsigned* c, unsigned expected) {
 
 // Block sums of acc, then the grid sums: true in the one block that holds
 // them (red[j][0], j < K) at the end.
-template <int K>
+template <int K, typename F>
 __device__ bool grid_sums_tagged(const double* acc, unsigned long long* rec, unsigned* counters, unsigned tag,
-                                 double (*red)[256]) {
+                                 double (*red)[256], F&& on_group_last) {
   for (int j = 0; j < K; ++j) red[j][threadIdx.x] = acc[j];
   __syncthreads();
   for (int s = blockDim.x / 2; s >= 1; s >>= 1) {
@@ -1069,6 +1069,7 @@ __device__ bool grid_sums_tagged(const double* acc, unsigned long long* rec, uns
   const int g = b / kGroup, ng = (nb + kGroup - 1) / kGroup;
   const int gsize = min(kGroup, nb - g * kGroup);
   if (!arrive(counters + g, gsize)) return false;
+  on_group_last();  // loads the final block may need, issued before its polls
   sum_records(rec + (size_t)g * kGroup * 16, gsize, K, tag, red);
   unsigned long long* grec = rec + (size_t)kMaxRecBlocks * 16;
   if ((int)threadIdx.x < K) put_tagged<double>(grec + ((size_t)g * 8 + threadIdx.x) * 2, red[threadIdx.x][0], tag);
@@ -1115,7 +1116,7 @@ __global__ void __launch_bounds__(256) k_rdot(long long n, long long nv, const S
     for (int q = 0; q < W; ++q) acc[0] += ((double)a[q] - (double)b[q]) * (double)c[q];
   }
   SPK_GRID_LOOP(e, nv * W, n) acc[0] += ((double)v[e] - (double)Tv[e]) * (double)w[e];
-  if (!grid_sums_tagged<1>(acc, rec, counter, tag, red)) return;
+  if (!grid_sums_tagged<1>(acc, rec, counter, tag, red, [] {})) return;
   if (threadIdx.x == 0) {
     *out = red[0][0];
     if (pub.mb) {
@@ -1177,8 +1178,9 @@ __global__ void __launch_bounds__(256) k_aa_dir(long long n, long long nv, const
 // Anderson step on the device (section 6.2, type-II; one thread, k <= 4):
 // the Gram row of the newest difference and the right-hand side <dR_j, r>
 // come from the push dot products; the oldest columns are dropped until the
-// Gram matrix of the kept ones has lambda_min / lambda_max >= 1e-12
-// (cyclic Jacobi) and a Cholesky factor; gamma solves G gamma = rhs. gamma
+// Gram matrix of the kept ones has lambda_min / lambda_max >= 1e-12 (the
+// singular-value ratio 1e-6 of the residual differences; cyclic Jacobi until
+// the test is decided) and a Cholesky factor; gamma solves G gamma = rhs. gamma
 // is written for every column of the order (0 for dropped ones) and the
 // kept count to kept_out (as a double).
 // Fixed-size (N <= 4) helpers, fully unrolled so that the matrices stay in
@@ -1204,16 +1206,27 @@ __device__ __forceinline__ bool dev_chol(double (&A)[16]) {
   return true;
 }
 
-// Extreme eigenvalues of a symmetric N x N matrix (cyclic Jacobi).
+// Rank test of a symmetric N x N matrix: lambda_min / lambda_max >= 1e-12
+// with lambda_max > 0. Cyclic Jacobi sweeps until the test is decided: with
+// off the sum of squares of the upper off-diagonal entries, every eigenvalue
+// lies within e = sqrt(2 off) of a diagonal entry (Weyl), so the extreme
+// eigenvalues are within e of the smallest and largest diagonal entries.
 template <int N>
-__device__ __forceinline__ void dev_eig_range(double (&A)[16], double& lmin, double& lmax) {
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    double off = 0;
+__device__ __forceinline__ bool dev_rank_ok(double (&A)[16]) {
+  constexpr double kTol = 1e-12;
+  for (int sweep = 0;; ++sweep) {
+    double off = 0, dmin = A[0], dmax = A[0];
 #pragma unroll
-    for (int i = 0; i < N; ++i)
+    for (int i = 0; i < N; ++i) {
+      dmin = fmin(dmin, A[i * 4 + i]);
+      dmax = fmax(dmax, A[i * 4 + i]);
 #pragma unroll
       for (int j = i + 1; j < N; ++j) off += A[i * 4 + j] * A[i * 4 + j];
-    if (off < 1e-300) break;
+    }
+    const double e = sqrt(2.0 * off);
+    if (dmax - e > 0.0 && dmin - e >= kTol * (dmax + e)) return true;           // certainly passes
+    if (dmax + e <= 0.0 || (dmax - e > 0.0 && dmin + e < kTol * (dmax - e))) return false;  // certainly fails
+    if (sweep == 60 || off < 1e-300) return dmax > 0.0 && dmin >= kTol * dmax;  // the diagonal is the spectrum
 #pragma unroll
     for (int p = 0; p < N; ++p)
 #pragma unroll
@@ -1238,12 +1251,6 @@ __device__ __forceinline__ void dev_eig_range(double (&A)[16], double& lmin, dou
         }
       }
   }
-  lmin = lmax = A[0];
-#pragma unroll
-  for (int i = 1; i < N; ++i) {
-    lmin = fmin(lmin, A[i * 4 + i]);
-    lmax = fmax(lmax, A[i * 4 + i]);
-  }
 }
 
 // Rank test and solve for the last N of the k active columns (rows/cols
@@ -1255,9 +1262,7 @@ __device__ __forceinline__ bool dev_aa_try(const double (&Gk)[16], const double 
   for (int i = 0; i < N; ++i)
 #pragma unroll
     for (int j = 0; j < N; ++j) E[i * 4 + j] = L[i * 4 + j] = Gk[(off + i) * 4 + off + j];
-  double lmin, lmax;
-  dev_eig_range<N>(E, lmin, lmax);
-  if (!(lmax > 0.0 && lmin / lmax >= 1e-12) || !dev_chol<N>(L)) return false;
+  if (!dev_rank_ok<N>(E) || !dev_chol<N>(L)) return false;
   double y[4];
 #pragma unroll
   for (int i = 0; i < N; ++i) {
@@ -1287,32 +1292,33 @@ __device__ __forceinline__ int aa_try_from(const double (&Gk)[16], const double 
   }
 }
 
-// MO columns before the push (all indices fixed at compile time).
+// MO columns before the push (all indices fixed at compile time). Gold:
+// the Gram entries of the old columns (oldest first), read before the sums
+// were done; the new column's entries and the right-hand side <dR_j, r>
+// come from the dots. The new row is stored in G (by slot) for later pushes.
 template <int MO>
-__device__ __forceinline__ void aa_solve_dev(double* __restrict__ G, double* __restrict__ rhs,
-                                             const double (&dots)[8], const AAPush& a,
+__device__ __forceinline__ void aa_solve_dev(double* __restrict__ G, const double (&dots)[8],
+                                             const double (&Gold)[16], const AAPush& a,
                                              double* __restrict__ gamma, double* __restrict__ kept_out) {
   const int m = a.m, slot = a.slot;
 #pragma unroll
   for (int j = 0; j < MO; ++j) {
     G[a.order_old[j] * m + slot] = dots[j];
     G[slot * m + a.order_old[j]] = dots[j];
-    rhs[a.order_old[j]] = dots[MO + 1 + j];
   }
   G[slot * m + slot] = dots[MO];
-  rhs[slot] = dots[2 * MO + 1];
   constexpr int k = MO + 1;  // order_new = order_old + [slot]
-  int ord[4] = {0, 0, 0, 0};
-#pragma unroll
-  for (int j = 0; j < MO; ++j) ord[j] = a.order_old[j];
-  ord[MO] = slot;
   // Gram matrix and right-hand side of the active columns, in registers
   double Gk[16], rk[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    rk[i] = i < k ? rhs[ord[i]] : 0.0;
+    rk[i] = i < MO ? dots[MO + 1 + i] : (i == MO ? dots[2 * MO + 1] : 0.0);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) Gk[i * 4 + j] = (i < k && j < k) ? G[ord[i] * m + ord[j]] : 0.0;
+    for (int j = 0; j < 4; ++j)
+      Gk[i * 4 + j] = (i < MO && j < MO) ? Gold[i * 4 + j]
+                    : (i == MO && j < MO) ? dots[j]
+                    : (j == MO && i < MO) ? dots[i]
+                    : (i == MO && j == MO) ? dots[MO] : 0.0;
   }
   double g[4] = {0, 0, 0, 0};
   // drop the oldest columns until the rest pass the rank test
@@ -1335,7 +1341,7 @@ __global__ void __launch_bounds__(256) k_aa_push(long long n, long long nv, cons
                                                  S* __restrict__ r_out, S* __restrict__ dV_new,
                                                  S* __restrict__ dR_new, VecPtrs<S> dR_old,
                                                  unsigned long long* __restrict__ rec,
-                                                 unsigned* __restrict__ counter, unsigned tag, double* __restrict__ G, double* __restrict__ rhs, AAPush a,
+                                                 unsigned* __restrict__ counter, unsigned tag, double* __restrict__ G, AAPush a,
                                                  double* __restrict__ gamma, double* __restrict__ kept_out) {
   __shared__ double red[8][256];
   constexpr int m_old = MO;
@@ -1383,17 +1389,25 @@ __global__ void __launch_bounds__(256) k_aa_push(long long n, long long nv, cons
     dR_new[e] = dr;
     dV_new[e] = ev;
   }
-  if (!grid_sums_tagged<2 * m_old + 2>(acc, rec, counter, tag, red)) return;
+  double Gold[16];
+  auto load_gram = [&] {
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) Gold[i * 4 + j] = (i < MO && j < MO) ? G[a.order_old[i] * a.m + a.order_old[j]] : 0.0;
+  };
+  if (!grid_sums_tagged<2 * m_old + 2>(acc, rec, counter, tag, red, load_gram)) return;
   if (threadIdx.x == 0) {
     double dots[8];
     for (int k = 0; k < 8; ++k) dots[k] = red[k][0];
-    aa_solve_dev<MO>(G, rhs, dots, a, gamma, kept_out);
+    aa_solve_dev<MO>(G, dots, Gold, a, gamma, kept_out);
   }
 }
 template <typename S>
 hipError_t launch_aa_push(long long n, const S* v, const S* vprev, const S* Tv, const S* rprev,
                           S* r_out, S* dV_new, S* dR_new, VecPtrs<S> dR_old, unsigned long long* rec,
-                          unsigned* counter, unsigned tag, double* G, double* rhs, const AAPush& a, double* gamma,
+                          unsigned* counter, unsigned tag, double* G, const AAPush& a, double* gamma,
                           double* kept_out, hipStream_t st) {
   if (a.mo < 0 || a.mo > 3 || a.m < 1 || a.m > 4) return hipErrorInvalidValue;
   auto kern = a.mo == 0 ? k_aa_push<S, 0> : a.mo == 1 ? k_aa_push<S, 1> : a.mo == 2 ? k_aa_push<S, 2> : k_aa_push<S, 3>;
@@ -1401,7 +1415,7 @@ hipError_t launch_aa_push(long long n, const S* v, const S* vprev, const S* Tv, 
   for (int j = 0; j < a.mo; ++j)
     if (!al16(dR_old.p[j])) nv = 0;
   hipLaunchKernelGGL(kern, dim3(dots_blocks(n)), dim3(256), 0, st, n, nv, v, vprev, Tv, rprev, r_out, dV_new,
-                     dR_new, dR_old, rec, counter, tag, G, rhs, a, gamma, kept_out);
+                     dR_new, dR_old, rec, counter, tag, G, a, gamma, kept_out);
   return hipGetLastError();
 }
 
@@ -1430,7 +1444,7 @@ hipError_t launch_aa_dir(long long n, const S* r, int m, VecPtrs<S> dE, const do
                                      hipStream_t);                                                  \
   template hipError_t launch_aa_push<S>(long long, const S*, const S*, const S*, const S*, S*, S*,  \
                                         S*, VecPtrs<S>, unsigned long long*, unsigned*, unsigned,   \
-                                        double*, double*, const AAPush&, double*, double*,          \
+                                        double*, const AAPush&, double*, double*,                   \
                                         hipStream_t);                                               \
   template hipError_t launch_aa_dir<S>(long long, const S*, int, VecPtrs<S>, const double*, S*,    \
                                        const S*, S*, hipStream_t);

@@ -204,7 +204,7 @@ constexpr int kRedCounters = kRedMaxBlocks / kRedGroup + 1;
 template <typename S>
 hipError_t launch_aa_push(long long n, const S* v, const S* vprev, const S* Tv, const S* rprev,
                           S* r_out, S* dV_new, S* dR_new, VecPtrs<S> dR_old, unsigned long long* rec,
-                          unsigned* counter, unsigned tag, double* G, double* rhs, const AAPush& a, double* gamma,
+                          unsigned* counter, unsigned tag, double* G, const AAPush& a, double* gamma,
                           double* kept_out, hipStream_t st);
 template <typename S>
 // d = -r - sum_j gamma_j E_j with E_j = dV_j - dR_j (as stored by the push);
