@@ -51,14 +51,15 @@ def tree_counts(inst):
 
 
 def algorithmic_elems_sweeps(inst):
-    """Elements both Alg. 2 sweeps of one T must move: every factor matrix
-    once per sweep that uses it (Abar^c, B^c in both; K in both; R~^{-1} and
-    W = sum_c Abar^c' P^c B^c in the backward sweep), xbar/ubar read, q and d
-    written once and read once, x^i read and u^i, x^c written in the forward
-    sweep."""
+    """Elements both Alg. 2 sweeps of one T must move, in the form the
+    sweeps kernel computes: every factor matrix once per sweep that uses it
+    (backward: At^c = Abar^c' - M1 B^c', Bt^c = R~^{-1} B^c' per child and
+    R~^{-1}, P1 = M1 - K' per family; forward: Abar^c, B^c per child and K
+    per family), xbar/ubar read, q and d written once and read once, x^i read
+    and u^i, x^c written in the forward sweep."""
     nn, nl, _ = tree_counts(inst)
     nx, nu = inst.nx, inst.nu
-    mats = 2 * (nn - 1) * (nx * nx + nx * nu) + nl * (2 * nx * nu + nu * nu + nx * nu)
+    mats = 2 * (nn - 1) * (nx * nx + nx * nu) + nl * (2 * nx * nu + nu * nu)
     bwd_vec = nl * (nx + nu) + nl * (nx + nu) + (nn - 1) * nx        # xbar,ubar; q,d out; children q in
     fwd_vec = nl * (nu + nx) + nl * nu + (nn - 1) * nx               # d, x^i in; u, x^c out
     return int(mats + bwd_vec + fwd_vec)

@@ -53,12 +53,12 @@ typedef __attribute__((address_space(3))) void lds_void;
 // whole number of 64-word rows so that a wavefront copy may overrun it).
 // The mat-vec partial sums of an output vector of n entries take
 // min(4, 256 / n) * n elements (at most kFoldMax partial sums per output):
-// rx for n_x outputs, ru for n_u outputs. Backward: A' q (rx), B' q then
-// R~^{-1} g (ru), K' ubar then M1 g (rx); forward: child k (rx each), K x (ru).
+// rx for n_x outputs, ru for n_u outputs. Backward: At q (rx), P1 ubar (rx),
+// Bt q (ru), R~^{-1} ubar (ru); forward: child k (rx each), K x (ru).
 struct FlowLds {
   int esz;     // words per element
-  int sA, sB;  // per-child strides of the Abar and B regions
-  int oA, oB, oR, oK, oW, oQ, oX, oU, oRed;  // oW: M1 (backward)
+  int sA, sB;  // per-child strides of the At / Abar and Bt / B regions
+  int oA, oB, oR, oK, oQ, oX, oU, oRed;  // oK: P1 (backward) or K (forward)
   int rx, ru;  // elements of an n_x-output and an n_u-output partial-sum area
   int nc;      // children per chunk
   int words;
@@ -72,14 +72,14 @@ struct FlowLds {
     oB = oA + nc * sA;
     oR = oB + nc * sB;
     oK = oR + pad(nu * nu * esz);
-    oW = oK + pad(nx * nu * esz);
-    oQ = oW + pad(nx * nu * esz);  // children's q (chunk), row stride nx; then g
-    oX = oQ + pad((nc * nx > nu ? nc * nx : nu) * esz);  // xbar (backward) or x (forward)
+    oQ = oK + pad(nx * nu * esz);  // children's q (chunk), row stride nx
+    oX = oQ + pad(nc * nx * esz);  // xbar (backward) or x (forward)
     oU = oX + pad(nx * esz);       // ubar (backward) or d (forward)
     oRed = oU + pad(nu * esz);
     rx = (kFW / nx < kFoldMax ? kFW / nx : kFoldMax) * nx;
     ru = (kFW / nu < kFoldMax ? kFW / nu : kFoldMax) * nu;
-    words = oRed + pad(((nc > 2 ? nc : 2) * rx + ru) * esz);
+    const int bwd = 2 * rx + 2 * ru, fwd = (nc > 2 ? nc : 2) * rx + ru;
+    words = oRed + pad((bwd > fwd ? bwd : fwd) * esz);
   }
   __host__ __device__ int bytes() const { return words * 4; }
 };
@@ -217,14 +217,17 @@ __device__ __forceinline__ S wait_one(const unsigned long long* p, unsigned tag,
 }
 
 // ---------------------------------------------------------------- backward item
-// Alg. 2 backward step regrouped: with g = ubar - sum_c B^c' q^c,
-//   d = R~^{-1} g,   q = M1 g + c0 + sum_c Abar^c' q^c,
-//   M1 = (K' + W) R~^{-1} (offline, FP64),  c0 = -K' ubar - xbar.
+// Alg. 2 backward step in one mat-vec phase: substituting
+// g = ubar - sum_c B^c' q^c into d = R~^{-1} g and q = M1 g - K' ubar - xbar
+// + sum_c Abar^c' q^c (M1 = (K' + W) R~^{-1}) gives
+//   d = R~^{-1} ubar - sum_c Bt^c q^c,   q = P1 ubar - xbar + sum_c At^c q^c
+// with Bt^c = R~^{-1} B^c', At^c = Abar^c' - M1 B^c', P1 = M1 - K' formed
+// offline in FP64 (equal to Alg. 2's step in exact arithmetic).
 // Chunk j of family i (children j nc, ...). Wavefront 3 polls the chunk's
 // children's q while the copies are in flight. A chunk that is not the
-// family's last publishes its two partial sums; the last chunk forms K' ubar
-// with its children's products in one mat-vec phase, adds the earlier
-// chunks' partial sums (chunk order), then R~^{-1} g and M1 g.
+// family's last publishes its two partial sums; the last chunk forms its
+// children's products with P1 ubar and R~^{-1} ubar in the same phase, adds
+// the earlier chunks' partial sums (chunk order) and publishes d and q.
 template <typename S>
 __device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, int i, int j) {
   const DevProb<S>& P = A.P;
@@ -235,22 +238,21 @@ __device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, 
   const S* qv = reinterpret_cast<const S*>(lds + L.oQ);
   const S* xb = reinterpret_cast<const S*>(lds + L.oX);
   const S* ub = reinterpret_cast<const S*>(lds + L.oU);
-  S* redA = reinterpret_cast<S*>(lds + L.oRed);  // sum_c Abar' q partials
-  S* redC = redA + L.rx;                          // K' ubar; then M1 g
-  S* redB = redC + L.rx;                          // sum_c B' q; then R~^{-1} g
-  S* vg = reinterpret_cast<S*>(lds + L.oQ);       // g, once the children's q are consumed
+  S* redA = reinterpret_cast<S*>(lds + L.oRed);  // sum_c At q partials
+  S* redC = redA + L.rx;                          // P1 ubar
+  S* redB = redC + L.rx;                          // sum_c Bt q
+  S* redD = redB + L.ru;                          // R~^{-1} ubar
   const bool leafkids = fc >= P.nl;
   const int k0 = j * L.nc, kc = min(L.nc, n - k0);
   const bool last = k0 + kc == n;
   int rot = 0;
   for (int k = 0; k < kc; ++k) {
-    dma_words(P.AbR + (size_t)(fc + k0 + k) * nx * nx, lds, L.oA + k * L.sA, nx * nx * es, rot++);
-    dma_words(P.BR + (size_t)(fc + k0 + k) * nx * nu, lds, L.oB + k * L.sB, nx * nu * es, rot++);
+    dma_words(P.AtR + (size_t)(fc + k0 + k) * nx * nx, lds, L.oA + k * L.sA, nx * nx * es, rot++);
+    dma_words(P.BtR + (size_t)(fc + k0 + k) * nx * nu, lds, L.oB + k * L.sB, nx * nu * es, rot++);
   }
   if (last) {
     dma_words(P.Rinv + (size_t)i * nu * nu, lds, L.oR, nu * nu * es, rot++);
-    dma_words(P.KR + (size_t)i * nu * nx, lds, L.oK, nu * nx * es, rot++);
-    dma_words(P.M1C + (size_t)i * nu * nx, lds, L.oW, nu * nx * es, rot++);
+    dma_words(P.P1C + (size_t)i * nu * nx, lds, L.oK, nu * nx * es, rot++);
     dma_words(A.xbar + (size_t)i * nx, lds, L.oX, nx * es, rot++);
     dma_words(A.ubar + (size_t)i * nu, lds, L.oU, nu * es, rot++);
   }
@@ -260,13 +262,15 @@ __device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, 
     wait_tagged<S>(A.qt + (size_t)(fc + k0) * nx * kTW<S>, kc * nx, A.tag, reinterpret_cast<S*>(lds + L.oQ), A.err);
   wait_vm();
   __syncthreads();
-  if (last) mv_part<S>(M + L.oK / es, ub, nu, nx, redC, false);
+  if (last) {
+    mv_part<S>(M + L.oK / es, ub, nu, nx, redC, false);
+    mv_part<S>(M + L.oR / es, ub, nu, nu, redD, false);
+  }
   for (int k = 0; k < kc; ++k) {
     mv_part<S>(M + L.oA / es + k * (L.sA / es), qv + k * nx, nx, nx, redA, k > 0);
     mv_part<S>(M + L.oB / es + k * (L.sB / es), qv + k * nx, nx, nu, redB, k > 0);
   }
   __syncthreads();
-  const int nprev = k0 / L.nc;  // chunks before this one
   if (!last) {
     unsigned long long* pp = A.pt + (size_t)(A.pbase[i] + j) * (nx + nu) * kTW<S>;
     if (t < nx) put_tagged<S>(pp + (size_t)t * kTW<S>, mv_fold<S>(redA, nx, t), A.tag);
@@ -275,26 +279,20 @@ __device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, 
     return;
   }
   // this chunk's sums after the earlier chunks' (chunk order)
+  const int nprev = k0 / L.nc;
   const unsigned long long* pp = nprev > 0 ? A.pt + (size_t)A.pbase[i] * (nx + nu) * kTW<S> : nullptr;
-  S sa = 0;
   if (t < nx) {
+    S sa = 0;
     for (int q = 0; q < nprev; ++q) sa += wait_one<S>(pp + ((size_t)q * (nx + nu) + t) * kTW<S>, A.tag, A.err);
     sa += mv_fold<S>(redA, nx, t);
+    put_tagged<S>(A.qt + ((size_t)i * nx + t) * kTW<S>, mv_fold<S>(redC, nx, t) - xb[t] + sa, A.tag);
   }
-  // g = ubar - sum_c B' q; c0 = -K' ubar - xbar (kept by thread t < nx)
-  S c0 = 0;
-  if (t < nx) c0 = -mv_fold<S>(redC, nx, t) - xb[t];
   if (t < nu) {
     S sb = 0;
     for (int q = 0; q < nprev; ++q) sb += wait_one<S>(pp + ((size_t)q * (nx + nu) + nx + t) * kTW<S>, A.tag, A.err);
-    vg[t] = ub[t] - (sb + mv_fold<S>(redB, nu, t));
+    sb += mv_fold<S>(redB, nu, t);
+    put_tagged<S>(A.dt + ((size_t)i * nu + t) * kTW<S>, mv_fold<S>(redD, nu, t) - sb, A.tag);
   }
-  __syncthreads();
-  mv_part<S>(M + L.oR / es, vg, nu, nu, redB, false);
-  mv_part<S>(M + L.oW / es, vg, nu, nx, redC, false);
-  __syncthreads();
-  if (t < nu) put_tagged<S>(A.dt + ((size_t)i * nu + t) * kTW<S>, mv_fold<S>(redB, nu, t), A.tag);
-  if (t < nx) put_tagged<S>(A.qt + ((size_t)i * nx + t) * kTW<S>, mv_fold<S>(redC, nx, t) + sa + c0, A.tag);
   __syncthreads();  // LDS reuse by the next item
 }
 

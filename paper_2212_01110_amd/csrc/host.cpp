@@ -170,7 +170,7 @@ int upload(Problem& P, const spock_problem_data& d, const std::vector<double>& A
   const int nn = T.nn, nl = T.nl, nx = P.nx, nu = P.nu;
   // sizes (elements)
   const size_t nvec = (size_t)nn * (4 * nx + 3 * nu) + 2 * (size_t)nn + 64;
-  const size_t nmat = (size_t)nn * (2 * nx * nx + 2 * nx * nu) + (size_t)nl * (2 * nu * nx + nu * nu + 2 * nx * nu);
+  const size_t nmat = (size_t)nn * (3 * nx * nx + 3 * nx * nu) + (size_t)nl * (2 * nu * nx + nu * nu + 3 * nx * nu);
   const size_t bytes = (nvec + nmat) * sizeof(S) + (3 * (size_t)nn + T.N + 2) * sizeof(int) + 64 * 256;
   std::vector<char> host(bytes, 0);
   void* dmem = nullptr;
@@ -277,6 +277,8 @@ int upload(Problem& P, const spock_problem_data& d, const std::vector<double>& A
   // the backward step is d = R~^{-1} g, q = M1 g - K' ubar - xbar + sum_c Abar^c' q^c
   // (the same recursion regrouped); stored like W
   auto M1p = take((size_t)nl * nu * nx, S{});
+  auto P1p = take((size_t)nl * nu * nx, S{});
+  std::vector<double> M1d((size_t)nl * nx * nu);  // M1[r][j], FP64
   parallel_for(nl, [&](int i) {
     const double* Km = K.data() + (size_t)i * nu * nx;  // [nu][nx]
     const double* Wm = W.data() + (size_t)i * nx * nu;  // [nx][nu]
@@ -285,10 +287,38 @@ int upload(Problem& P, const spock_problem_data& d, const std::vector<double>& A
       for (int j = 0; j < nu; ++j) {
         double acc = 0;
         for (int l = 0; l < nu; ++l) acc += (Km[(size_t)l * nx + r] + Wm[(size_t)r * nu + l]) * Ri[(size_t)l * nu + j];
+        M1d[(size_t)i * nx * nu + (size_t)r * nu + j] = acc;
         M1p.first[(size_t)i * nu * nx + (size_t)j * nx + r] = (S)acc;
+        P1p.first[(size_t)i * nu * nx + (size_t)j * nx + r] = (S)(acc - Km[(size_t)j * nx + r]);
       }
   });
   D.M1C = M1p.second;
+  D.P1C = P1p.second;
+  // per child c of family i: At^c = Abar^c' - M1 B^c' (element (out o, in k)
+  // at k nx + o), Bt^c = R~^{-1} B^c' (element (out o, in k) at k nu + o)
+  auto AtRp = take((size_t)nn * nx * nx, S{});
+  auto BtRp = take((size_t)nn * nx * nu, S{});
+  parallel_for(nn - 1, [&](int c1) {
+    const int c = c1 + 1, i = T.anc[c];
+    const double* Ab = Abar.data() + (size_t)c * nx * nx;  // Abar[k][o]
+    const double* Bm = d.B + (size_t)c * nx * nu;          // B[k][j]
+    const double* M1 = M1d.data() + (size_t)i * nx * nu;   // M1[o][j]
+    const double* Ri = Rinv.data() + (size_t)i * nu * nu;  // R~^{-1}[o][j]
+    for (int k = 0; k < nx; ++k) {
+      for (int o = 0; o < nx; ++o) {
+        double acc = Ab[(size_t)k * nx + o];
+        for (int j = 0; j < nu; ++j) acc -= M1[(size_t)o * nu + j] * Bm[(size_t)k * nu + j];
+        AtRp.first[(size_t)c * nx * nx + (size_t)k * nx + o] = (S)acc;
+      }
+      for (int o = 0; o < nu; ++o) {
+        double acc = 0;
+        for (int j = 0; j < nu; ++j) acc += Ri[(size_t)o * nu + j] * Bm[(size_t)k * nu + j];
+        BtRp.first[(size_t)c * nx * nu + (size_t)k * nu + o] = (S)acc;
+      }
+    }
+  });
+  D.AtR = AtRp.second;
+  D.BtR = BtRp.second;
   const size_t used = off;
   if (used > bytes) {
     (void)hipFree(dmem);
@@ -649,7 +679,7 @@ int ensure_flow(Problem& P, int occ = 0, int budget = 0) {
   FlowState& F = P.flow;
   const Tree& T = *P.tree;
   if (occ == 0) occ = F.mem ? F.occ : 5;
-  if (budget == 0) budget = F.mem ? F.budget : 40 * 1024;
+  if (budget == 0) budget = F.mem ? F.budget : 32 * 1024;
   if (const char* env = std::getenv("SPOCK_FLOW_OCC")) occ = std::atoi(env) >= 5 ? 5 : 4;
   if (const char* env = std::getenv("SPOCK_FLOW_LDS")) budget = std::max(4096, std::atoi(env));
   if (F.mem && F.elem == (int)sizeof(S) && F.occ == occ && F.budget == budget) {
@@ -818,7 +848,7 @@ int autotune(Problem& P, hipStream_t st) {
   // dataflow form: register budget (4 or 5 wavefronts per SIMD) and LDS
   // budget (children per chunk against workgroups per CU); the cut field
   // carries occ * 1000 + LDS budget in KiB
-  for (int code : {4040, 5040, 5046, 5060})
+  for (int code : {4024, 5024, 4032, 5032, 4040, 5040, 5046})
     if (ensure_flow<S>(P, code / 1000, (code % 1000) * 1024) == SPOCK_OK && P.flow.grid > 0)
       cands.push_back({kTeamFlow, code});
   int ncut = 0;

@@ -47,7 +47,12 @@ struct DevProb {
   const S* KC;   // [nl][nx][nu]  K column-major        (K x, forward)
   const S* Rinv; // [nl][nu][nu]  inverse of R~ (symmetric)
   const S* WC;   // [nl][nu][nx]  W = sum_c Abar'P B, column-major (W d, backward)
-  const S* M1C;  // [nl][nu][nx]  M1 = (K' + W) R~^{-1}, column-major (dataflow backward step)
+  const S* M1C;  // [nl][nu][nx]  M1 = (K' + W) R~^{-1}, column-major (per-stage forms)
+  // backward step of the dataflow form in one mat-vec phase (FP64-formed):
+  //   d = R~^{-1} ubar - sum_c Bt^c q^c,  q = P1 ubar - xbar + sum_c At^c q^c
+  const S* AtR;  // [nn][nx][nx]  At^c = Abar^c' - M1 B^c' (parent's M1), stored like AbR's role
+  const S* BtR;  // [nn][nx][nu]  Bt^c = R~^{-1} B^c' (parent's R~^{-1}), stored like BR's role
+  const S* P1C;  // [nl][nu][nx]  P1 = M1 - K', stored like M1C
   S alpha;
 };
 
@@ -83,7 +88,7 @@ struct FlowState {
   int grid = 0;                      // resident workgroups (0: form unavailable)
   int occ = 5;                       // register budget: 4 or 5 wavefronts per SIMD
   int elem = 0;                      // element size the state was sized for
-  int budget = 40 * 1024;            // LDS budget the chunk size was chosen for
+  int budget = 32 * 1024;            // LDS budget the chunk size was chosen for
   // cooperative launch (residency guaranteed by the runtime) or a plain
   // launch of the resident-sized grid (about 20 us less dispatch per T; a
   // grid that were not all resident ends with the error word set)
