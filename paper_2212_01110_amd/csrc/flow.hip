@@ -184,6 +184,31 @@ __device__ __forceinline__ void wait_tagged(const unsigned long long* src, int n
   __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Same for two sources at once (one memory round trip per poll).
+template <typename S>
+__device__ __forceinline__ void wait_tagged2(const unsigned long long* srcA, int nA, S* dstA,
+                                             const unsigned long long* srcB, int nB, S* dstB, unsigned tag,
+                                             unsigned* err) {
+  const int lane = threadIdx.x & 63;
+  for (unsigned it = 0; it < kSpinLimit; ++it) {
+    bool ok = true;
+    for (int e = lane; e < nA; e += 64) {
+      S v;
+      ok = get_tagged<S>(srcA + (size_t)e * kTW<S>, tag, v) && ok;
+      dstA[e] = v;
+    }
+    for (int e = lane; e < nB; e += 64) {
+      S v;
+      ok = get_tagged<S>(srcB + (size_t)e * kTW<S>, tag, v) && ok;
+      dstB[e] = v;
+    }
+    if (__all(ok)) return;
+    if ((it & 255u) == 255u && ld_flag(err) != 0u) return;
+    __builtin_amdgcn_s_sleep(1);
+  }
+  __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <typename S>
 struct FlowArgs {
   DevProb<S> P;
@@ -203,17 +228,35 @@ struct FlowArgs {
   int nc, nbwd, nitems;
 };
 
-// One tagged element polled by the calling thread (bounded).
+// Sums, in slot order, entries ea and eb (-1: none) of the first n partial
+// records at pp (stride rs elements), polled together by the calling thread
+// until every word carries tag (bounded).
 template <typename S>
-__device__ __forceinline__ S wait_one(const unsigned long long* p, unsigned tag, unsigned* err) {
-  S v = 0;
+__device__ __forceinline__ void sum_partials(const unsigned long long* pp, int n, int rs, int ea, int eb,
+                                             unsigned tag, unsigned* err, S& sa, S& sb) {
   for (unsigned it = 0; it < kSpinLimit; ++it) {
-    if (get_tagged<S>(p, tag, v)) return v;
-    if ((it & 255u) == 255u && ld_flag(err) != 0u) return v;
+    bool ok = true;
+    S a = 0, b = 0;
+    for (int q = 0; q < n; ++q) {
+      S v;
+      if (ea >= 0) {
+        ok = get_tagged<S>(pp + ((size_t)q * rs + ea) * kTW<S>, tag, v) && ok;
+        a += v;
+      }
+      if (eb >= 0) {
+        ok = get_tagged<S>(pp + ((size_t)q * rs + eb) * kTW<S>, tag, v) && ok;
+        b += v;
+      }
+    }
+    if (ok) {
+      sa = a;
+      sb = b;
+      return;
+    }
+    if ((it & 255u) == 255u && ld_flag(err) != 0u) return;
     __builtin_amdgcn_s_sleep(1);
   }
   __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return v;
 }
 
 // ---------------------------------------------------------------- backward item
@@ -281,15 +324,14 @@ __device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, 
   // this chunk's sums after the earlier chunks' (chunk order)
   const int nprev = k0 / L.nc;
   const unsigned long long* pp = nprev > 0 ? A.pt + (size_t)A.pbase[i] * (nx + nu) * kTW<S> : nullptr;
+  S sa = 0, sb = 0;
+  if (nprev > 0 && (t < nx || t < nu))
+    sum_partials<S>(pp, nprev, nx + nu, t < nx ? t : -1, t < nu ? nx + t : -1, A.tag, A.err, sa, sb);
   if (t < nx) {
-    S sa = 0;
-    for (int q = 0; q < nprev; ++q) sa += wait_one<S>(pp + ((size_t)q * (nx + nu) + t) * kTW<S>, A.tag, A.err);
     sa += mv_fold<S>(redA, nx, t);
     put_tagged<S>(A.qt + ((size_t)i * nx + t) * kTW<S>, mv_fold<S>(redC, nx, t) - xb[t] + sa, A.tag);
   }
   if (t < nu) {
-    S sb = 0;
-    for (int q = 0; q < nprev; ++q) sb += wait_one<S>(pp + ((size_t)q * (nx + nu) + nx + t) * kTW<S>, A.tag, A.err);
     sb += mv_fold<S>(redB, nu, t);
     put_tagged<S>(A.dt + ((size_t)i * nu + t) * kTW<S>, mv_fold<S>(redD, nu, t) - sb, A.tag);
   }
@@ -319,13 +361,15 @@ __device__ void flow_fwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, 
   }
   if (j == 0) dma_words(P.KC + (size_t)i * nx * nu, lds, L.oK, nx * nu * es, rot++);
   if (w == 0) {
-    wait_tagged<S>(A.dt + (size_t)i * nu * kTW<S>, nu, A.tag, vd, A.err);
-    if (i != 0) {
-      wait_tagged<S>(A.xt + (size_t)i * nx * kTW<S>, nx, A.tag, vx, A.err);
-    } else if (lane < nx) {
-      const S xv = (S)A.x0[lane];
-      if (j == 0) A.zout[1 + lane] = xv;
-      vx[lane] = xv;
+    if (i != 0) {  // d and x polled together
+      wait_tagged2<S>(A.dt + (size_t)i * nu * kTW<S>, nu, vd, A.xt + (size_t)i * nx * kTW<S>, nx, vx, A.tag, A.err);
+    } else {
+      wait_tagged<S>(A.dt, nu, A.tag, vd, A.err);
+      if (lane < nx) {
+        const S xv = (S)A.x0[lane];
+        if (j == 0) A.zout[1 + lane] = xv;
+        vx[lane] = xv;
+      }
     }
   }
   wait_vm();
