@@ -645,7 +645,7 @@ extern "C" const char* spock_version(void) { return "spock-mi355x 0.1 (gfx950)";
 // ============================================================== workspace
 namespace {
 
-constexpr int kMaxMem = 4;  // Anderson memory supported by the push kernel
+constexpr int kMaxMem = kAAMax;  // Anderson memory supported by the push kernel
 
 template <typename S>
 struct Work {
@@ -664,6 +664,7 @@ struct Work {
   S* pool[10 + 2 * kMaxMem];  // n_v buffers
   unsigned* counters = nullptr;       // arrival counts of the push and the rdot [2][kRedCounters]
   unsigned long long* rec = nullptr;  // tagged records of their grid sums [kRedRecWords]
+  AARingDev* ring = nullptr;          // Anderson ring (device)
   unsigned tag = 0;                   // tag of their last launch (never 0 once launched)
   unsigned next_tag() { return ++tag == 0u ? ++tag : tag; }
 };
@@ -766,6 +767,7 @@ int ensure_work(Problem& P, Work<S>& W) {
   add(sizeof(double) * (size_t)nblk * 8);
   add(sizeof(unsigned) * 2 * kRedCounters);
   add(sizeof(unsigned long long) * kRedRecWords);
+  add(sizeof(AARingDev));
   add(sizeof(S) * (size_t)P.neta);
   add(sizeof(double) * kMaxDim);
   for (int k = 0; k < 10 + 2 * kMaxMem; ++k) add(sizeof(S) * (size_t)nv);
@@ -796,6 +798,7 @@ int ensure_work(Problem& P, Work<S>& W) {
   W.vpart = reinterpret_cast<double*>(take(sizeof(double) * (size_t)nblk * 8));
   W.counters = reinterpret_cast<unsigned*>(take(sizeof(unsigned) * 2 * kRedCounters));
   W.rec = reinterpret_cast<unsigned long long*>(take(sizeof(unsigned long long) * kRedRecWords));
+  W.ring = reinterpret_cast<AARingDev*>(take(sizeof(AARingDev)));
   W.eta_zero = reinterpret_cast<S*>(take(sizeof(S) * (size_t)P.neta));
   W.x0_zero = reinterpret_cast<double*>(take(sizeof(double) * kMaxDim));
   for (int k = 0; k < 10 + 2 * kMaxMem; ++k) W.pool[k] = reinterpret_cast<S*>(take(sizeof(S) * (size_t)nv));
@@ -941,7 +944,6 @@ struct Solver {
   const double* x0;
   long long nv;
   int t_evals = 0;
-  double last_kept = 0;  // kept columns of the last device Anderson solve
   std::vector<double> hbuf = std::vector<double>(16);
 
   Solver(Problem& p, hipStream_t s, const double* x) : P(p), st(s), x0(x), nv(p.nz + p.neta) {}
@@ -949,15 +951,25 @@ struct Solver {
   // T(v) and its statistics; with md, also <v - T(v), md> (line search),
   // fetched in the same transfer (statistics slot 6)
   int T(const S* v, S* Tv, Stats& out, const S* md = nullptr, double* rdot = nullptr) {
+    unsigned long long ep = 0;
+    const int rc = launch(v, Tv, ep, md);
+    return rc ? rc : wait(ep, out, rdot);
+  }
+  // queues T(v) (and <v - T(v), md>) with its statistics published to the
+  // mailbox under the returned epoch
+  int launch(const S* v, S* Tv, unsigned long long& epoch, const S* md = nullptr) {
     const Publish pub{P.mbox_dev, ++P.mbox_epoch};
     HIP_TRY(launch_T<S>(P, v, Tv, x0, W.q, W.d, W.xbar, W.ubar, W.partials, W.stats, st, W.eta_zero, true,
                         md ? Publish{} : pub));
     if (md)
       HIP_TRY(launch_rdot<S>(nv, v, Tv, md, W.rec, W.counters + kRedCounters, W.next_tag(), W.stats + 6, W.stats, pub, st));
-    const int rc = wait_mailbox(pub.epoch);
+    epoch = pub.epoch;
+    return SPOCK_OK;
+  }
+  int wait(unsigned long long epoch, Stats& out, double* rdot = nullptr) {
+    const int rc = wait_mailbox(epoch);
     if (rc) return rc;
     for (int k = 0; k < 8; ++k) hbuf[k] = P.mbox->v[k];
-    last_kept = hbuf[7];
     if (rdot) *rdot = hbuf[6];
     out.xip = hbuf[0];
     out.xid = hbuf[1];
@@ -990,19 +1002,6 @@ struct Solver {
 
 // Anderson ring: slots of the active columns, oldest first (the Gram matrix
 // and the right-hand side, indexed by slot, live on the device).
-struct AARing {
-  int m = 0;
-  std::vector<int> order;
-  void reset(int mm) {
-    m = mm;
-    order.clear();
-  }
-  int free_slot() const {
-    for (int s = 0; s < m; ++s)
-      if (std::find(order.begin(), order.end(), s) == order.end()) return s;
-    return order.front();
-  }
-};
 
 // Solves the Gram system for the active columns after applying the rank rule
 // (drop the oldest column while lambda_min/lambda_max(G) < 1e-12, i.e.
@@ -1067,71 +1066,62 @@ int solve_impl(Problem& P, const double* x0, const spock_settings& s, S* vio, sp
 
   // ---- SPOCK (Alg. 3 with the residual formed before the tests)
   double zeta = S0.omega(), omega_safe = S0.omega();
-  AARing ring;
-  ring.reset(s.m);
   bool have_prev = false;
-  // The Anderson Gram matrix lives on the device; the solve (with its rank
-  // rule) runs there right after the push, and the number of columns it kept
-  // comes back with the statistics of the next evaluation of T, which drops
-  // the oldest columns from the host's order before the next push.
-  int pending_k = -1;
-  auto apply_kept = [&]() {
-    if (pending_k < 0) return;
-    const int kept = (int)SV.last_kept;
-    const int drop = std::max(0, std::min(pending_k, pending_k - kept));
-    ring.order.erase(ring.order.begin(), ring.order.begin() + std::min(drop, (int)ring.order.size()));
-    pending_k = -1;
-  };
-  for (;;) {
-    if (Sc.xi() <= tol) return finish(SPOCK_CONVERGED);
-    if (k >= s.max_iters) return finish(SPOCK_MAXITER);
-    // residual of the current iterate and the Anderson buffers
+  // The Anderson ring (column order, Gram matrix, rank rule) lives on the
+  // device, so the residual, the push, the Gram solve, the direction d and
+  // the K0 candidate v + d of an iterate are queued right behind its
+  // evaluation of T, before the host reads the statistics that decide the
+  // step: the host's decision overlaps that work.
+  // the slots' vectors sit at one stride in the pool (E at dV[0] + s stride,
+  // dR at dR[0] + s stride)
+  const long long sstride = dV[1] - dV[0];
+  for (int j = 0; j < kAAMax; ++j)
+    if (dV[j] - dV[0] != j * sstride || dR[j] - dR[0] != j * sstride) return SPOCK_EINVAL;
+  {
+    AARingDev r0{};
+    r0.m = s.m;
+    HIP_TRY(hipMemcpyAsync(W.ring, &r0, sizeof(r0), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  // r = v - Tv, the Anderson push and Gram solve, d, and spare = v + d for
+  // the current iterate (stream-ordered after its T)
+  auto prepare = [&]() -> int {
     if (have_prev) {
-      int slot;
-      if ((int)ring.order.size() == ring.m) {
-        slot = ring.order.front();
-        ring.order.erase(ring.order.begin());
-      } else {
-        slot = ring.free_slot();
-      }
-      VecPtrs<S> olds{};
-      AAPush a{};
-      const int mo = (int)ring.order.size();
-      a.m = ring.m;
-      a.mo = mo;
-      a.slot = slot;
-      for (int j = 0; j < mo; ++j) {
-        olds.p[j] = dR[ring.order[j]];
-        a.order_old[j] = ring.order[j];
-      }
-      HIP_TRY(launch_aa_push<S>(nv, v, vprev, Tv, rprev, rcur, dV[slot], dR[slot], olds, W.rec, W.counters,
-                                W.next_tag(), W.aaG, a, W.gamma, W.stats + 7, st));
-      ring.order.push_back(slot);
-      pending_k = mo + 1;
-      VecPtrs<S> pe{};
-      for (int j = 0; j < mo + 1; ++j) pe.p[j] = dV[ring.order[j]];  // dV - dR, as stored by the push
-      // when the K0 test will pass, the step v + d is formed in the same pass
-      const bool k0 = Sc.omega() <= s.c0 * zeta;
-      HIP_TRY(launch_aa_dir<S>(nv, rcur, mo + 1, pe, W.gamma, dir, k0 ? v : nullptr, k0 ? spare : nullptr, st));
+      HIP_TRY(launch_aa_push<S>(nv, v, vprev, Tv, rprev, rcur, dV[0], dR[0], sstride, W.rec, W.counters,
+                                W.next_tag(), W.aaG, W.ring, W.gamma, st));
+      HIP_TRY(launch_aa_dir<S>(nv, rcur, dV[0], sstride, W.ring, W.gamma, dir, v, spare, st));
     } else {
       HIP_TRY(launch_lincomb<S>(nv, rcur, 1.0, v, -1.0, Tv, st));
       HIP_TRY(launch_lincomb<S>(nv, dir, -1.0, rcur, 0.0, nullptr, st));
-      if (Sc.omega() <= s.c0 * zeta) HIP_TRY(launch_lincomb<S>(nv, spare, 1.0, v, 1.0, dir, st));
+      HIP_TRY(launch_lincomb<S>(nv, spare, 1.0, v, 1.0, dir, st));
     }
+    return SPOCK_OK;
+  };
+  // T of the new iterate, its preparation queued behind it, then its statistics
+  auto eval_next = [&]() -> int {
+    unsigned long long ep = 0;
+    int r = SV.launch(v, Tv, ep);
+    if (!r) r = prepare();
+    return r ? r : SV.wait(ep, Sc);
+  };
+  auto accept_prev = [&]() {
+    std::swap(vprev, v);      // vprev <- old v
+    std::swap(rprev, rcur);   // rprev <- old r
+    have_prev = true;
+  };
+  rc = prepare();
+  if (rc) return rc;
+  for (;;) {
+    if (Sc.xi() <= tol) return finish(SPOCK_CONVERGED);
+    if (k >= s.max_iters) return finish(SPOCK_MAXITER);
     const double omega = Sc.omega();
-    auto accept_prev = [&]() {
-      std::swap(vprev, v);      // vprev <- old v
-      std::swap(rprev, rcur);   // rprev <- old r
-      have_prev = true;
-    };
-    if (omega <= s.c0 * zeta) {  // K0 (spare = v + d was formed with the direction)
+    if (omega <= s.c0 * zeta) {  // K0: spare = v + d, formed with the direction
       accept_prev();
       std::swap(v, spare);       // v <- v_old + d ; spare <- old vprev
       zeta = omega;
       info.n_k0++;
-      rc = SV.T(v, Tv, Sc);
+      rc = eval_next();
       if (rc) return rc;
-      apply_kept();
       ++k;
       if (!Sc.ok()) return finish(SPOCK_NUMERICAL);
       continue;
@@ -1145,7 +1135,6 @@ int solve_impl(Problem& P, const double* x0, const spock_settings& s, S* vio, sp
       double rdot = 0;
       rc = SV.T(vt, Tvt, St, Md, &rdot);
       if (rc) return rc;
-      apply_kept();
       if (!St.ok()) {
         tau *= s.beta;
         info.n_backtracks++;
@@ -1159,6 +1148,8 @@ int solve_impl(Problem& P, const double* x0, const spock_settings& s, S* vio, sp
         Sc = St;
         omega_safe = om_t + std::pow(s.c2, k);
         info.n_k1++;
+        rc = prepare();
+        if (rc) return rc;
         accepted = true;
         break;
       }
@@ -1169,9 +1160,8 @@ int solve_impl(Problem& P, const double* x0, const spock_settings& s, S* vio, sp
         accept_prev();
         std::swap(v, spare);
         info.n_k2++;
-        rc = SV.T(v, Tv, Sc);
+        rc = eval_next();
         if (rc) return rc;
-        apply_kept();
         accepted = true;
         break;
       }
@@ -1183,9 +1173,8 @@ int solve_impl(Problem& P, const double* x0, const spock_settings& s, S* vio, sp
       accept_prev();
       std::swap(v, spare);
       info.n_km++;
-      rc = SV.T(v, Tv, Sc);
+      rc = eval_next();
       if (rc) return rc;
-      apply_kept();
     }
     ++k;
     if (!Sc.ok()) return finish(SPOCK_NUMERICAL);

@@ -1138,9 +1138,9 @@ hipError_t launch_rdot(long long n, const S* v, const S* Tv, const S* w, unsigne
 // d = -r - sum_j gamma_j (dV_j - dR_j), M columns; step = base + d when
 // step is set
 template <typename S, int M>
-__global__ void __launch_bounds__(256) k_aa_dir(long long n, long long nv, const S* __restrict__ r, VecPtrs<S> dE,
-                                                const double* __restrict__ gamma, S* __restrict__ d,
-                                                const S* __restrict__ base, S* __restrict__ step) {
+__device__ __forceinline__ void aa_dir_body(long long n, long long nv, const S* __restrict__ r, const VecPtrs<S>& dE,
+                                            const double* __restrict__ gamma, S* __restrict__ d,
+                                            const S* __restrict__ base, S* __restrict__ step) {
   constexpr int W = kVW<S>;
   double g[M];
 #pragma unroll
@@ -1173,6 +1173,25 @@ __global__ void __launch_bounds__(256) k_aa_dir(long long n, long long nv, const
     for (int j = 0; j < M; ++j) acc -= g[j] * (double)dE.p[j][e];
     d[e] = (S)acc;
     if (step) step[e] = (S)((double)base[e] + acc);
+  }
+}
+// The direction of the columns the last push used (ring->dk of them, slots
+// ring->dslot; E of slot s at eb + s * stride).
+template <typename S>
+__global__ void __launch_bounds__(256) k_aa_dir(long long n, long long nv, const S* __restrict__ r,
+                                                const S* __restrict__ eb, long long stride,
+                                                const AARingDev* __restrict__ ring,
+                                                const double* __restrict__ gamma, S* __restrict__ d,
+                                                const S* __restrict__ base, S* __restrict__ step) {
+  const int m = ring->dk;
+  VecPtrs<S> dE{};
+#pragma unroll
+  for (int j = 0; j < kAAMax; ++j) dE.p[j] = j < m ? eb + ring->dslot[j] * stride : eb;
+  switch (m) {
+    case 1: aa_dir_body<S, 1>(n, nv, r, dE, gamma, d, base, step); break;
+    case 2: aa_dir_body<S, 2>(n, nv, r, dE, gamma, d, base, step); break;
+    case 3: aa_dir_body<S, 3>(n, nv, r, dE, gamma, d, base, step); break;
+    default: aa_dir_body<S, 4>(n, nv, r, dE, gamma, d, base, step); break;
   }
 }
 // Anderson step on the device (section 6.2, type-II; one thread, k <= 4):
@@ -1299,7 +1318,7 @@ __device__ __forceinline__ int aa_try_from(const double (&Gk)[16], const double 
 template <int MO>
 __device__ __forceinline__ void aa_solve_dev(double* __restrict__ G, const double (&dots)[8],
                                              const double (&Gold)[16], const AAPush& a,
-                                             double* __restrict__ gamma, double* __restrict__ kept_out) {
+                                             double* __restrict__ gamma, AARingDev* __restrict__ ring) {
   const int m = a.m, slot = a.slot;
 #pragma unroll
   for (int j = 0; j < MO; ++j) {
@@ -1326,7 +1345,23 @@ __device__ __forceinline__ void aa_solve_dev(double* __restrict__ G, const doubl
   if (kept == 0) g[0] = g[1] = g[2] = g[3] = 0.0;
 #pragma unroll
   for (int j = 0; j < k; ++j) gamma[j] = g[j];
-  *kept_out = (double)kept;
+  // the ring: the direction uses the k columns (dropped ones with gamma 0);
+  // the next push keeps the newest `kept`
+  int ord[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < MO; ++j) ord[j] = a.order_old[j];
+  ord[MO] = slot;
+  ring->dk = k;
+#pragma unroll
+  for (int j = 0; j < k; ++j) ring->dslot[j] = ord[j];
+  ring->cnt = kept;
+#pragma unroll
+  for (int j = 0; j < k; ++j) {
+    int sel = 0;
+#pragma unroll
+    for (int q = 0; q < k; ++q) sel = (q == k - kept + j) ? ord[q] : sel;
+    if (j < kept) ring->order[j] = sel;
+  }
 }
 
 // Anderson push: r = v - Tv, dV = v - vprev, dR = r - rprev, with the
@@ -1335,15 +1370,14 @@ __device__ __forceinline__ void aa_solve_dev(double* __restrict__ G, const doubl
 // dots[m_old+1+j] = <dR_old_j, r>, dots[2 m_old + 1] = <dR_new, r>, summed
 // in a fixed order by the last block to finish, which then solves for gamma.
 template <typename S, int MO>
-__global__ void __launch_bounds__(256) k_aa_push(long long n, long long nv, const S* __restrict__ v,
-                                                 const S* __restrict__ vprev,
-                                                 const S* __restrict__ Tv, const S* __restrict__ rprev,
-                                                 S* __restrict__ r_out, S* __restrict__ dV_new,
-                                                 S* __restrict__ dR_new, VecPtrs<S> dR_old,
-                                                 unsigned long long* __restrict__ rec,
-                                                 unsigned* __restrict__ counter, unsigned tag, double* __restrict__ G, AAPush a,
-                                                 double* __restrict__ gamma, double* __restrict__ kept_out) {
-  __shared__ double red[8][256];
+__device__ __forceinline__ void aa_push_body(long long n, long long nv, const S* __restrict__ v,
+                                             const S* __restrict__ vprev, const S* __restrict__ Tv,
+                                             const S* __restrict__ rprev, S* __restrict__ r_out,
+                                             S* __restrict__ dV_new, S* __restrict__ dR_new, const VecPtrs<S>& dR_old,
+                                             unsigned long long* __restrict__ rec, unsigned* __restrict__ counter,
+                                             unsigned tag, double* __restrict__ G, const AAPush& a,
+                                             double* __restrict__ gamma, AARingDev* __restrict__ ring,
+                                             double (*red)[256]) {
   constexpr int m_old = MO;
   constexpr int W = kVW<S>;
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -1401,33 +1435,74 @@ __global__ void __launch_bounds__(256) k_aa_push(long long n, long long nv, cons
   if (threadIdx.x == 0) {
     double dots[8];
     for (int k = 0; k < 8; ++k) dots[k] = red[k][0];
-    aa_solve_dev<MO>(G, dots, Gold, a, gamma, kept_out);
+    aa_solve_dev<MO>(G, dots, Gold, a, gamma, ring);
   }
 }
+// The push reads the ring as the last push's solve left it: the new column
+// takes the oldest slot when the ring is full, else the lowest free one; the
+// dots run against the other columns of the order.
 template <typename S>
-hipError_t launch_aa_push(long long n, const S* v, const S* vprev, const S* Tv, const S* rprev,
-                          S* r_out, S* dV_new, S* dR_new, VecPtrs<S> dR_old, unsigned long long* rec,
-                          unsigned* counter, unsigned tag, double* G, const AAPush& a, double* gamma,
-                          double* kept_out, hipStream_t st) {
-  if (a.mo < 0 || a.mo > 3 || a.m < 1 || a.m > 4) return hipErrorInvalidValue;
-  auto kern = a.mo == 0 ? k_aa_push<S, 0> : a.mo == 1 ? k_aa_push<S, 1> : a.mo == 2 ? k_aa_push<S, 2> : k_aa_push<S, 3>;
-  long long nv = nvec16<S>(n, {v, vprev, Tv, rprev, r_out, dV_new, dR_new});
-  for (int j = 0; j < a.mo; ++j)
-    if (!al16(dR_old.p[j])) nv = 0;
-  hipLaunchKernelGGL(kern, dim3(dots_blocks(n)), dim3(256), 0, st, n, nv, v, vprev, Tv, rprev, r_out, dV_new,
-                     dR_new, dR_old, rec, counter, tag, G, a, gamma, kept_out);
+__global__ void __launch_bounds__(256) k_aa_push(long long n, long long nv, const S* __restrict__ v,
+                                                 const S* __restrict__ vprev, const S* __restrict__ Tv,
+                                                 const S* __restrict__ rprev, S* __restrict__ r_out,
+                                                 S* __restrict__ eb, S* __restrict__ rb, long long stride,
+                                                 unsigned long long* __restrict__ rec,
+                                                 unsigned* __restrict__ counter, unsigned tag, double* __restrict__ G,
+                                                 AARingDev* __restrict__ ring, double* __restrict__ gamma) {
+  __shared__ double red[8][256];
+  // (fixed indices and selects only, so that nothing lands in scratch)
+  AAPush a{};
+  a.m = ring->m;
+  const int cnt = ring->cnt;
+  int o[kAAMax];
+#pragma unroll
+  for (int j = 0; j < kAAMax; ++j) o[j] = ring->order[j];
+  const bool full = cnt == a.m;
+  a.mo = full ? cnt - 1 : cnt;
+#pragma unroll
+  for (int j = 0; j < kAAMax; ++j) a.order_old[j] = full ? (j + 1 < kAAMax ? o[j + 1] : 0) : o[j];
+  int fr = kAAMax;  // lowest slot not in the order
+#pragma unroll
+  for (int s = kAAMax - 1; s >= 0; --s) {
+    bool used = false;
+#pragma unroll
+    for (int j = 0; j < kAAMax; ++j) used = used || (j < cnt && o[j] == s);
+    if (!used && s < a.m) fr = s;
+  }
+  a.slot = full ? o[0] : fr;
+  VecPtrs<S> dR_old{};
+#pragma unroll
+  for (int j = 0; j < kAAMax - 1; ++j) dR_old.p[j] = j < a.mo ? rb + a.order_old[j] * stride : nullptr;
+  S* dV_new = eb + a.slot * stride;
+  S* dR_new = rb + a.slot * stride;
+  switch (a.mo) {
+    case 0: aa_push_body<S, 0>(n, nv, v, vprev, Tv, rprev, r_out, dV_new, dR_new, dR_old, rec, counter, tag, G, a, gamma, ring, red); break;
+    case 1: aa_push_body<S, 1>(n, nv, v, vprev, Tv, rprev, r_out, dV_new, dR_new, dR_old, rec, counter, tag, G, a, gamma, ring, red); break;
+    case 2: aa_push_body<S, 2>(n, nv, v, vprev, Tv, rprev, r_out, dV_new, dR_new, dR_old, rec, counter, tag, G, a, gamma, ring, red); break;
+    default: aa_push_body<S, 3>(n, nv, v, vprev, Tv, rprev, r_out, dV_new, dR_new, dR_old, rec, counter, tag, G, a, gamma, ring, red); break;
+  }
+}
+// 16-byte vector path when the bases and the stride keep every slot aligned
+template <typename S>
+static bool slots_aligned(const S* eb, const S* rb, long long stride) {
+  return al16(eb) && (!rb || al16(rb)) && ((stride * (long long)sizeof(S)) & 15) == 0;
+}
+template <typename S>
+hipError_t launch_aa_push(long long n, const S* v, const S* vprev, const S* Tv, const S* rprev, S* r_out, S* eb,
+                          S* rb, long long stride, unsigned long long* rec, unsigned* counter, unsigned tag,
+                          double* G, AARingDev* ring, double* gamma, hipStream_t st) {
+  const long long nv = slots_aligned<S>(eb, rb, stride) ? nvec16<S>(n, {v, vprev, Tv, rprev, r_out}) : 0;
+  hipLaunchKernelGGL(k_aa_push<S>, dim3(dots_blocks(n)), dim3(256), 0, st, n, nv, v, vprev, Tv, rprev, r_out, eb,
+                     rb, stride, rec, counter, tag, G, ring, gamma);
   return hipGetLastError();
 }
 
 template <typename S>
-hipError_t launch_aa_dir(long long n, const S* r, int m, VecPtrs<S> dE, const double* gamma_dev, S* d,
-                         const S* base, S* step, hipStream_t st) {
-  if (m < 1 || m > 4) return hipErrorInvalidValue;
-  long long nv = nvec16<S>(n, {r, d, base, step});
-  for (int j = 0; j < m; ++j)
-    if (!al16(dE.p[j])) nv = 0;
-  auto kern = m == 1 ? k_aa_dir<S, 1> : m == 2 ? k_aa_dir<S, 2> : m == 3 ? k_aa_dir<S, 3> : k_aa_dir<S, 4>;
-  hipLaunchKernelGGL(kern, dim3(dots_blocks(n)), dim3(256), 0, st, n, nv, r, dE, gamma_dev, d, base, step);
+hipError_t launch_aa_dir(long long n, const S* r, const S* eb, long long stride, const AARingDev* ring,
+                         const double* gamma_dev, S* d, const S* base, S* step, hipStream_t st) {
+  const long long nv = slots_aligned<S>(eb, nullptr, stride) ? nvec16<S>(n, {r, d, base, step}) : 0;
+  hipLaunchKernelGGL(k_aa_dir<S>, dim3(dots_blocks(n)), dim3(256), 0, st, n, nv, r, eb, stride, ring, gamma_dev, d,
+                     base, step);
   return hipGetLastError();
 }
 
@@ -1443,11 +1518,10 @@ hipError_t launch_aa_dir(long long n, const S* r, int m, VecPtrs<S> dE, const do
                                      unsigned*, unsigned, double*, const double*, Publish,          \
                                      hipStream_t);                                                  \
   template hipError_t launch_aa_push<S>(long long, const S*, const S*, const S*, const S*, S*, S*,  \
-                                        S*, VecPtrs<S>, unsigned long long*, unsigned*, unsigned,   \
-                                        double*, const AAPush&, double*, double*,                   \
-                                        hipStream_t);                                               \
-  template hipError_t launch_aa_dir<S>(long long, const S*, int, VecPtrs<S>, const double*, S*,    \
-                                       const S*, S*, hipStream_t);
+                                        S*, long long, unsigned long long*, unsigned*, unsigned,    \
+                                        double*, AARingDev*, double*, hipStream_t);                 \
+  template hipError_t launch_aa_dir<S>(long long, const S*, const S*, long long, const AARingDev*,  \
+                                       const double*, S*, const S*, S*, hipStream_t);
 SPK_INST(double)
 SPK_INST(float)
 

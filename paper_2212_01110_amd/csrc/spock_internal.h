@@ -194,10 +194,17 @@ struct AAPush {
   int m, mo, slot;
   int order_old[4];
 };
-// Push of the newest difference pair, its Gram row and right-hand side
-// (fixed-order sums in the last workgroup to finish, counted on *counter,
-// which is left at zero), then the Gram solve in that workgroup: gamma for
-// every column of the order and the kept count to kept_out.
+// The Anderson ring on the device (memory m <= kAAMax): the column slots in
+// use, oldest first, as the last Gram solve left them, and the columns (slots)
+// the last direction used. The host sets m and cnt = 0 once per solve.
+constexpr int kAAMax = 4;
+struct AARingDev {
+  int m;
+  int cnt;
+  int order[kAAMax];
+  int dk;
+  int dslot[kAAMax];
+};
 // Grid sums finished inside a vector kernel: tagged records of the blocks
 // and of groups of kRedGroup blocks (kRedRecWords 64-bit words, zeroed once;
 // every launch's tag differs from the earlier ones' and is not 0) and
@@ -206,16 +213,21 @@ constexpr int kRedGroup = 32;
 constexpr int kRedMaxBlocks = 1024;
 constexpr int kRedRecWords = (kRedMaxBlocks + kRedMaxBlocks / kRedGroup) * 16;
 constexpr int kRedCounters = kRedMaxBlocks / kRedGroup + 1;
+// Push of the newest difference pair into the slot the ring picks (E =
+// dV - dR of slot s at eb + s stride, dR at rb + s stride), its Gram row and
+// right-hand side (fixed-order sums finished in the launch over the tagged
+// records above), then the Gram solve in the last workgroup: gamma for the
+// columns of the new order, and the ring updated.
 template <typename S>
-hipError_t launch_aa_push(long long n, const S* v, const S* vprev, const S* Tv, const S* rprev,
-                          S* r_out, S* dV_new, S* dR_new, VecPtrs<S> dR_old, unsigned long long* rec,
-                          unsigned* counter, unsigned tag, double* G, const AAPush& a, double* gamma,
-                          double* kept_out, hipStream_t st);
-template <typename S>
-// d = -r - sum_j gamma_j E_j with E_j = dV_j - dR_j (as stored by the push);
+hipError_t launch_aa_push(long long n, const S* v, const S* vprev, const S* Tv, const S* rprev, S* r_out, S* eb,
+                          S* rb, long long stride, unsigned long long* rec, unsigned* counter, unsigned tag,
+                          double* G, AARingDev* ring, double* gamma, hipStream_t st);
+// d = -r - sum_j gamma_j E_j over the columns of the last push (the ring's
+// dk, dslot; E_j = dV_j - dR_j as stored by the push, at eb + slot stride);
 // when step is non-null also step = base + d
-hipError_t launch_aa_dir(long long n, const S* r, int m, VecPtrs<S> dE, const double* gamma_dev, S* d,
-                         const S* base, S* step, hipStream_t st);
+template <typename S>
+hipError_t launch_aa_dir(long long n, const S* r, const S* eb, long long stride, const AARingDev* ring,
+                         const double* gamma_dev, S* d, const S* base, S* step, hipStream_t st);
 template <typename S>
 hipError_t launch_fill(long long n, S* out, double val, hipStream_t st);
 // <v - Tv, w> to *out_dev (fixed-order sum in the last workgroup to finish,
