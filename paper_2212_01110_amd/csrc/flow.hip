@@ -391,16 +391,22 @@ __device__ void flow_fwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, 
   __syncthreads();  // red and the matrices are reused by the next item
 }
 
-// W: minimum wavefronts per SIMD the register allocation must allow.
+// W: wavefronts per SIMD the register allocation targets (4 to 7).
 template <typename S, int W>
-__global__ void __launch_bounds__(kFW) __attribute__((amdgpu_waves_per_eu(W, 8))) k_T_flow(FlowArgs<S> A) {
+__global__ void __launch_bounds__(kFW) __attribute__((amdgpu_waves_per_eu(W, W))) k_T_flow(FlowArgs<S> A) {
   extern __shared__ __align__(16) unsigned flow_lds[];
   const FlowLds L(A.P.nx, A.P.nu, A.nc, (int)(sizeof(S) / 4));
-  // items run in increasing order in every workgroup
-  for (int it = blockIdx.x; it < A.nitems; it += gridDim.x) {
+  // items run in increasing order in every workgroup: its backward items,
+  // then its forward items (two loops, so that the two kinds of item do not
+  // hold registers at the same time)
+  int it = blockIdx.x;
+  for (; it < A.nbwd; it += gridDim.x) {
     const int code = A.items[it];
-    if (it < A.nbwd) flow_bwd<S>(A, L, flow_lds, code / kChunkCodes, code % kChunkCodes);
-    else flow_fwd<S>(A, L, flow_lds, code / kChunkCodes, code % kChunkCodes);
+    flow_bwd<S>(A, L, flow_lds, code / kChunkCodes, code % kChunkCodes);
+  }
+  for (; it < A.nitems; it += gridDim.x) {
+    const int code = A.items[it];
+    flow_fwd<S>(A, L, flow_lds, code / kChunkCodes, code % kChunkCodes);
   }
 }
 
@@ -411,7 +417,12 @@ int flow_lds_bytes(int nx, int nu, int nc, int elem) { return FlowLds(nx, nu, nc
 
 template <typename S>
 const void* flow_kernel(int occ) {
-  return occ >= 5 ? reinterpret_cast<const void*>(&k_T_flow<S, 5>) : reinterpret_cast<const void*>(&k_T_flow<S, 4>);
+  switch (occ) {
+    case 7: return reinterpret_cast<const void*>(&k_T_flow<S, 7>);
+    case 6: return reinterpret_cast<const void*>(&k_T_flow<S, 6>);
+    case 5: return reinterpret_cast<const void*>(&k_T_flow<S, 5>);
+    default: return reinterpret_cast<const void*>(&k_T_flow<S, 4>);
+  }
 }
 template const void* flow_kernel<double>(int);
 template const void* flow_kernel<float>(int);

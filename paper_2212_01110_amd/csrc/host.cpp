@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <limits>
 #include <thread>
@@ -681,7 +682,7 @@ int ensure_flow(Problem& P, int occ = 0, int budget = 0) {
   const Tree& T = *P.tree;
   if (occ == 0) occ = F.mem ? F.occ : 5;
   if (budget == 0) budget = F.mem ? F.budget : 32 * 1024;
-  if (const char* env = std::getenv("SPOCK_FLOW_OCC")) occ = std::atoi(env) >= 5 ? 5 : 4;
+  if (const char* env = std::getenv("SPOCK_FLOW_OCC")) occ = std::max(4, std::min(7, std::atoi(env)));
   if (const char* env = std::getenv("SPOCK_FLOW_LDS")) budget = std::max(4096, std::atoi(env));
   if (F.mem && F.elem == (int)sizeof(S) && F.occ == occ && F.budget == budget) {
     if (hipMemset(F.err, 0, sizeof(unsigned)) != hipSuccess) return SPOCK_EHIP;
@@ -705,6 +706,22 @@ int ensure_flow(Problem& P, int occ = 0, int budget = 0) {
     return SPOCK_EHIP;
   if (fits && hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, flow_kernel<S>(occ), 256, (size_t)lds) != hipSuccess)
     return SPOCK_EHIP;
+  // Residency is what the waits rely on, so the count is also bounded by
+  // what the build guarantees: occ wavefronts per SIMD (the register budget
+  // the kernel is compiled for; one wavefront of each workgroup per SIMD)
+  // and the LDS in blocks of 512 bytes out of 160 KiB per CU. The occupancy
+  // query alone granted grids that were not all resident (it reported the
+  // same register count for every budget and left the LDS rounding out).
+  if (fits && nb > 0) {
+    hipFuncAttributes fa{};
+    if (hipFuncGetAttributes(&fa, flow_kernel<S>(occ)) != hipSuccess) return SPOCK_EHIP;
+    const int by_lds = (160 * 1024) / std::max(512, ((lds + (int)fa.sharedSizeBytes + 511) / 512) * 512);
+    const int bound = fa.localSizeBytes > 0 ? 0 : std::min(occ, by_lds);  // no scratch-using build
+    if (std::getenv("SPOCK_FLOW_DEBUG"))
+      std::fprintf(stderr, "[flow] occ %d nc %d lds %d: query %d per CU -> %d per CU\n", occ, nc, lds, nb,
+                   std::min(nb, bound));
+    nb = std::min(nb, bound);
+  }
   // items: one per chunk of nc children; backward (reverse breadth-first),
   // then forward (breadth-first); partial slots for families of several chunks
   std::vector<int> items, pbase(T.nl, 0);
@@ -848,10 +865,10 @@ int autotune(Problem& P, hipStream_t st) {
   HIP_TRY(hipEventCreate(&e1));
   const Tree& T = *P.tree;
   std::vector<std::pair<int, int>> cands = {{8, T.N}, {16, T.N}, {32, T.N}, {64, T.N}, {kTeamWG, T.N}};
-  // dataflow form: register budget (4 or 5 wavefronts per SIMD) and LDS
+  // dataflow form: register budget (4 to 7 wavefronts per SIMD) and LDS
   // budget (children per chunk against workgroups per CU); the cut field
   // carries occ * 1000 + LDS budget in KiB
-  for (int code : {4024, 5024, 4032, 5032, 4040, 5040, 5046})
+  for (int code : {4024, 5024, 6024, 7024, 4032, 5032, 6032, 7032, 4040, 5040, 5046})
     if (ensure_flow<S>(P, code / 1000, (code % 1000) * 1024) == SPOCK_OK && P.flow.grid > 0)
       cands.push_back({kTeamFlow, code});
   int ncut = 0;

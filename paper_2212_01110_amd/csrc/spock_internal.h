@@ -86,7 +86,7 @@ struct FlowState {
   int nbwd = 0;                      // backward items (as many forward items follow)
   int nc = 1;                        // children per LDS chunk
   int grid = 0;                      // resident workgroups (0: form unavailable)
-  int occ = 5;                       // register budget: 4 or 5 wavefronts per SIMD
+  int occ = 5;                       // register budget: 4 to 7 wavefronts per SIMD
   int elem = 0;                      // element size the state was sized for
   int budget = 32 * 1024;            // LDS budget the chunk size was chosen for
   // cooperative launch (residency guaranteed by the runtime) or a plain
