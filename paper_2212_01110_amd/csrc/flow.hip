@@ -53,8 +53,8 @@ typedef __attribute__((address_space(3))) void lds_void;
 // whole number of 64-word rows so that a wavefront copy may overrun it).
 // The mat-vec partial sums of an output vector of n entries take
 // min(4, 256 / n) * n elements (at most kFoldMax partial sums per output):
-// rx for n_x outputs, ru for n_u outputs. Backward: At q (rx), P1 ubar (rx),
-// Bt q (ru), R~^{-1} ubar (ru); forward: child k (rx each), K x (ru).
+// rx for n_x outputs, ru for n_u outputs. Backward: P1 ubar + sum At q (rx),
+// R~^{-1} ubar + sum Bt q (ru); forward: child k (rx each), K x (ru).
 struct FlowLds {
   int esz;     // words per element
   int sA, sB;  // per-child strides of the At / Abar and Bt / B regions
@@ -78,8 +78,7 @@ struct FlowLds {
     oRed = oU + pad(nu * esz);
     rx = (kFW / nx < kFoldMax ? kFW / nx : kFoldMax) * nx;
     ru = (kFW / nu < kFoldMax ? kFW / nu : kFoldMax) * nu;
-    const int bwd = 2 * rx + 2 * ru, fwd = (nc > 2 ? nc : 2) * rx + ru;
-    words = oRed + pad((bwd > fwd ? bwd : fwd) * esz);
+    words = oRed + pad(((nc > 1 ? nc : 1) * rx + ru) * esz);
   }
   __host__ __device__ int bytes() const { return words * 4; }
 };
@@ -263,16 +262,17 @@ __device__ __forceinline__ void sum_partials(const unsigned long long* pp, int n
 // Alg. 2 backward step in one mat-vec phase: substituting
 // g = ubar - sum_c B^c' q^c into d = R~^{-1} g and q = M1 g - K' ubar - xbar
 // + sum_c Abar^c' q^c (M1 = (K' + W) R~^{-1}) gives
-//   d = R~^{-1} ubar - sum_c Bt^c q^c,   q = P1 ubar - xbar + sum_c At^c q^c
-// with Bt^c = R~^{-1} B^c', At^c = Abar^c' - M1 B^c', P1 = M1 - K' formed
+//   d = R~^{-1} ubar + sum_c Bt^c q^c,   q = P1 ubar - xbar + sum_c At^c q^c
+// with Bt^c = -R~^{-1} B^c', At^c = Abar^c' - M1 B^c', P1 = M1 - K' formed
 // offline in FP64 (equal to Alg. 2's step in exact arithmetic).
 // Chunk j of family i (children j nc, ...). Wavefront 3 polls the chunk's
 // children's q while the copies are in flight. A chunk that is not the
-// family's last publishes its two partial sums; the last chunk forms its
-// children's products with P1 ubar and R~^{-1} ubar in the same phase, adds
-// the earlier chunks' partial sums (chunk order) and publishes d and q.
+// family's last publishes its two partial sums; the last chunk accumulates
+// P1 ubar and R~^{-1} ubar with its children's products (same outputs, same
+// partial-sum slots), adds the earlier chunks' partial sums (chunk order)
+// and publishes d and q.
 template <typename S>
-__device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, int i, int j) {
+__device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds L, unsigned* lds, int i, int j) {
   const DevProb<S>& P = A.P;
   const int t = threadIdx.x, w = t >> 6;
   const int nx = P.nx, nu = P.nu, fc = P.fc[i], n = P.nch[i];
@@ -281,10 +281,8 @@ __device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, 
   const S* qv = reinterpret_cast<const S*>(lds + L.oQ);
   const S* xb = reinterpret_cast<const S*>(lds + L.oX);
   const S* ub = reinterpret_cast<const S*>(lds + L.oU);
-  S* redA = reinterpret_cast<S*>(lds + L.oRed);  // sum_c At q partials
-  S* redC = redA + L.rx;                          // P1 ubar
-  S* redB = redC + L.rx;                          // sum_c Bt q
-  S* redD = redB + L.ru;                          // R~^{-1} ubar
+  S* redA = reinterpret_cast<S*>(lds + L.oRed);  // (P1 ubar +) sum_c At q partials
+  S* redB = redA + L.rx;                          // (R~^{-1} ubar +) sum_c Bt q
   const bool leafkids = fc >= P.nl;
   const int k0 = j * L.nc, kc = min(L.nc, n - k0);
   const bool last = k0 + kc == n;
@@ -306,12 +304,12 @@ __device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, 
   wait_vm();
   __syncthreads();
   if (last) {
-    mv_part<S>(M + L.oK / es, ub, nu, nx, redC, false);
-    mv_part<S>(M + L.oR / es, ub, nu, nu, redD, false);
+    mv_part<S>(M + L.oK / es, ub, nu, nx, redA, false);
+    mv_part<S>(M + L.oR / es, ub, nu, nu, redB, false);
   }
   for (int k = 0; k < kc; ++k) {
-    mv_part<S>(M + L.oA / es + k * (L.sA / es), qv + k * nx, nx, nx, redA, k > 0);
-    mv_part<S>(M + L.oB / es + k * (L.sB / es), qv + k * nx, nx, nu, redB, k > 0);
+    mv_part<S>(M + L.oA / es + k * (L.sA / es), qv + k * nx, nx, nx, redA, last || k > 0);
+    mv_part<S>(M + L.oB / es + k * (L.sB / es), qv + k * nx, nx, nu, redB, last || k > 0);
   }
   __syncthreads();
   if (!last) {
@@ -327,14 +325,8 @@ __device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, 
   S sa = 0, sb = 0;
   if (nprev > 0 && (t < nx || t < nu))
     sum_partials<S>(pp, nprev, nx + nu, t < nx ? t : -1, t < nu ? nx + t : -1, A.tag, A.err, sa, sb);
-  if (t < nx) {
-    sa += mv_fold<S>(redA, nx, t);
-    put_tagged<S>(A.qt + ((size_t)i * nx + t) * kTW<S>, mv_fold<S>(redC, nx, t) - xb[t] + sa, A.tag);
-  }
-  if (t < nu) {
-    sb += mv_fold<S>(redB, nu, t);
-    put_tagged<S>(A.dt + ((size_t)i * nu + t) * kTW<S>, mv_fold<S>(redD, nu, t) - sb, A.tag);
-  }
+  if (t < nx) put_tagged<S>(A.qt + ((size_t)i * nx + t) * kTW<S>, sa + mv_fold<S>(redA, nx, t) - xb[t], A.tag);
+  if (t < nu) put_tagged<S>(A.dt + ((size_t)i * nu + t) * kTW<S>, sb + mv_fold<S>(redB, nu, t), A.tag);
   __syncthreads();  // LDS reuse by the next item
 }
 
@@ -343,7 +335,7 @@ __device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, 
 // x^0 = x0 at the root. Wavefront 0 polls d (the family's backward step) and
 // x (the parent's forward step) while the copies are in flight.
 template <typename S>
-__device__ void flow_fwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, int i, int j) {
+__device__ void flow_fwd(const FlowArgs<S>& A, const FlowLds L, unsigned* lds, int i, int j) {
   const DevProb<S>& P = A.P;
   const Off<S> O(P);
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
@@ -374,7 +366,7 @@ __device__ void flow_fwd(const FlowArgs<S>& A, const FlowLds& L, unsigned* lds, 
   }
   wait_vm();
   __syncthreads();
-  S* redK = red + (L.nc > 2 ? L.nc : 2) * L.rx;
+  S* redK = red + (L.nc > 1 ? L.nc : 1) * L.rx;
   if (j == 0) mv_part<S>(M + L.oK / es, vx, nx, nu, redK, false);
   for (int k = 0; k < kc; ++k) {
     mv_part<S>(M + L.oB / es + k * (L.sB / es), vd, nu, nx, red + k * L.rx, false);

@@ -296,7 +296,7 @@ int upload(Problem& P, const spock_problem_data& d, const std::vector<double>& A
   D.M1C = M1p.second;
   D.P1C = P1p.second;
   // per child c of family i: At^c = Abar^c' - M1 B^c' (element (out o, in k)
-  // at k nx + o), Bt^c = R~^{-1} B^c' (element (out o, in k) at k nu + o)
+  // at k nx + o), Bt^c = -R~^{-1} B^c' (element (out o, in k) at k nu + o)
   auto AtRp = take((size_t)nn * nx * nx, S{});
   auto BtRp = take((size_t)nn * nx * nu, S{});
   parallel_for(nn - 1, [&](int c1) {
@@ -314,7 +314,7 @@ int upload(Problem& P, const spock_problem_data& d, const std::vector<double>& A
       for (int o = 0; o < nu; ++o) {
         double acc = 0;
         for (int j = 0; j < nu; ++j) acc += Ri[(size_t)o * nu + j] * Bm[(size_t)k * nu + j];
-        BtRp.first[(size_t)c * nx * nu + (size_t)k * nu + o] = (S)acc;
+        BtRp.first[(size_t)c * nx * nu + (size_t)k * nu + o] = (S)(-acc);
       }
     }
   });
@@ -716,7 +716,7 @@ int ensure_flow(Problem& P, int occ = 0, int budget = 0) {
     hipFuncAttributes fa{};
     if (hipFuncGetAttributes(&fa, flow_kernel<S>(occ)) != hipSuccess) return SPOCK_EHIP;
     const int by_lds = (160 * 1024) / std::max(512, ((lds + (int)fa.sharedSizeBytes + 511) / 512) * 512);
-    const int bound = fa.localSizeBytes > 0 ? 0 : std::min(occ, by_lds);  // no scratch-using build
+    const int bound = std::min(occ, by_lds);
     if (std::getenv("SPOCK_FLOW_DEBUG"))
       std::fprintf(stderr, "[flow] occ %d nc %d lds %d: query %d per CU -> %d per CU\n", occ, nc, lds, nb,
                    std::min(nb, bound));

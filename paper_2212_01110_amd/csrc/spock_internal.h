@@ -49,9 +49,9 @@ struct DevProb {
   const S* WC;   // [nl][nu][nx]  W = sum_c Abar'P B, column-major (W d, backward)
   const S* M1C;  // [nl][nu][nx]  M1 = (K' + W) R~^{-1}, column-major (per-stage forms)
   // backward step of the dataflow form in one mat-vec phase (FP64-formed):
-  //   d = R~^{-1} ubar - sum_c Bt^c q^c,  q = P1 ubar - xbar + sum_c At^c q^c
+  //   d = R~^{-1} ubar + sum_c Bt^c q^c,  q = P1 ubar - xbar + sum_c At^c q^c
   const S* AtR;  // [nn][nx][nx]  At^c = Abar^c' - M1 B^c' (parent's M1), stored like AbR's role
-  const S* BtR;  // [nn][nx][nu]  Bt^c = R~^{-1} B^c' (parent's R~^{-1}), stored like BR's role
+  const S* BtR;  // [nn][nx][nu]  Bt^c = -R~^{-1} B^c' (parent's R~^{-1}), stored like BR's role
   const S* P1C;  // [nl][nu][nx]  P1 = M1 - K', stored like M1C
   S alpha;
 };
