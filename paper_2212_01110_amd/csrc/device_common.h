@@ -10,11 +10,12 @@ namespace spk {
 
 // ---------------------------------------------------------------- helpers
 __device__ __forceinline__ void wave_lds_sync() {
-  // Teams live inside one wavefront: LDS traffic between their lanes only
-  // needs ordering at wavefront scope.
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  // Teams live inside one wavefront and exchange values through LDS only:
+  // the ordering is at wavefront scope and for LDS alone, so global loads
+  // stay free to move across it.
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
 }
 
 template <int T>

@@ -200,6 +200,26 @@ def test_spock_matches_oracle_step_by_step(name):
     assert np.max(np.abs(host(v) - ref.v)) <= 1e-9 * max(1.0, np.max(np.abs(ref.v)))
 
 
+@pytest.mark.parametrize("m", [1, 2, 4])
+def test_spock_anderson_memory_matches_oracle(m):
+    # the Anderson ring on the device with memory 1, 2 and 4 (the default 3
+    # is covered above): 40 iterations, same decisions and iterate as the
+    # oracle, which checks slot reuse once the ring is full and the columns
+    # the direction takes
+    inst = CASES["config1"]
+    gp, op = build(inst)
+    ref = O.spock_solve(op, inst.x0, O.Settings(eps_abs=1e-12, eps_rel=1e-12, max_iters=40, m=m))
+    x0 = dev(inst.x0, torch.float64)
+    v = torch.zeros(gp.n_v, dtype=torch.float64, device="cuda")
+    info = gp.solve(x0, v, SP.default_settings(eps_abs=1e-12, eps_rel=1e-12, max_iters=40, m=m))
+    c = ref.counts
+    got = (info["iters"], info["n_k0"], info["n_k1"], info["n_k2"], info["n_km"], info["n_backtracks"])
+    want = (ref.iters, c["K0"], c["K1"], c["K2"], c["KM"], c["backtracks"])
+    assert got == want
+    assert abs(info["xi"] - ref.xi) <= 1e-8 * ref.xi
+    assert np.max(np.abs(host(v) - ref.v)) <= 1e-9 * max(1.0, np.max(np.abs(ref.v)))
+
+
 def test_cp_matches_oracle_iteration_count():
     # vanilla CP is deterministic up to rounding: same number of iterations
     inst = G.make_config(1)
