@@ -1200,8 +1200,9 @@ __global__ void __launch_bounds__(256) k_aa_dir(long long n, long long nv, const
 // Gram matrix of the kept ones has lambda_min / lambda_max >= 1e-12 (the
 // singular-value ratio 1e-6 of the residual differences; cyclic Jacobi until
 // the test is decided) and a Cholesky factor; gamma solves G gamma = rhs. gamma
-// is written for every column of the order (0 for dropped ones) and the
-// kept count to kept_out (as a double).
+// is written for every column of the order (0 for dropped ones), and the
+// device ring takes the new order (the kept columns) and the direction's
+// columns.
 // Fixed-size (N <= 4) helpers, fully unrolled so that the matrices stay in
 // registers.
 template <int N>
