@@ -45,21 +45,17 @@ namespace {
 
 constexpr int kFW = 256;                   // threads per workgroup (4 wavefronts)
 constexpr unsigned kSpinLimit = 1u << 21;  // polls of one bounded wait
-constexpr int kFoldMax = 4;                // partial sums per mat-vec output
 
 typedef __attribute__((address_space(3))) void lds_void;
 
 // Word offsets of the dynamic LDS regions (32-bit words; every region is a
 // whole number of 64-word rows so that a wavefront copy may overrun it).
-// The mat-vec partial sums of an output vector of n entries take
-// min(4, 256 / n) * n elements (at most kFoldMax partial sums per output):
-// rx for n_x outputs, ru for n_u outputs. Backward: P1 ubar + sum At q (rx),
-// R~^{-1} ubar + sum Bt q (ru); forward: child k (rx each), K x (ru).
+// The mat-vec partial sums take 64 elements per unit of work, at most
+// max(4, nc + 1) units per item.
 struct FlowLds {
   int esz;     // words per element
   int sA, sB;  // per-child strides of the At / Abar and Bt / B regions
   int oA, oB, oR, oK, oQ, oX, oU, oRed;  // oK: P1 (backward) or K (forward)
-  int rx, ru;  // elements of an n_x-output and an n_u-output partial-sum area
   int nc;      // children per chunk
   int words;
   __host__ __device__ static int pad(int w) { return (w + 63) & ~63; }
@@ -76,9 +72,7 @@ struct FlowLds {
     oX = oQ + pad(nc * nx * esz);  // xbar (backward) or x (forward)
     oU = oX + pad(nx * esz);       // ubar (backward) or d (forward)
     oRed = oU + pad(nu * esz);
-    rx = (kFW / nx < kFoldMax ? kFW / nx : kFoldMax) * nx;
-    ru = (kFW / nu < kFoldMax ? kFW / nu : kFoldMax) * nu;
-    words = oRed + pad(((nc > 1 ? nc : 1) * rx + ru) * esz);
+    words = oRed + pad((nc + 1 > 4 ? nc + 1 : 4) * 64 * esz);
   }
   __host__ __device__ int bytes() const { return words * 4; }
 };
@@ -121,38 +115,61 @@ __device__ __forceinline__ void wait_vm() {
 // products of the inputs k in [g * kb, (g + 1) * kb), kb a multiple of 4:
 // the vector is read four entries at a time, the matrix down one column
 // with a single running address, into red[t] (added to it when acc).
+// ---------------------------------------------------------------- mat-vec phase
+// An item's products form output blocks (backward: q and d; forward: each
+// child's x and, in chunk 0, u). Block b has n_b <= 64 outputs over an
+// input of l_b entries, the concatenation of a head segment and equal
+// segments (one matrix each, stored input-major: entry (k, o) at k n_b + o).
+// A block is cut into contiguous input ranges, the units of work; a unit
+// runs on one wavefront with lane o on output o, so that the lanes of a
+// wavefront never diverge. Unit u writes its partial sums to red[64 u + o].
+
+// a0 + a1 += sum over inputs k in [k0, k1) of M[k nout + o] v[k]
 template <typename S>
-__device__ __forceinline__ void mv_part(const S* M, const S* v, int nin, int nout, S* red, bool acc) {
-  const int G = min(kFW / nout, kFoldMax), t = threadIdx.x;
-  if (t < G * nout) {
-    const int g = t / nout, o = t - g * nout;
-    const int kb = (((nin + G - 1) / G) + 3) & ~3;
-    const int k0 = g * kb, k1 = min(nin, k0 + kb);
-    const S* mp = M + (size_t)k0 * nout + o;
-    S a0 = 0, a1 = 0;
-    int k = k0;
-    for (; k + 4 <= k1; k += 4, mp += 4 * nout) {
-      const S v0 = v[k], v1 = v[k + 1], v2 = v[k + 2], v3 = v[k + 3];
-      const S m0 = mp[0], m1 = mp[nout], m2 = mp[2 * nout], m3 = mp[3 * nout];
-      a0 += m0 * v0 + m2 * v2;
-      a1 += m1 * v1 + m3 * v3;
-    }
-    for (; k < k1; ++k, mp += nout) a0 += mp[0] * v[k];
-    const S s = a0 + a1;
-    red[t] = acc ? red[t] + s : s;
+__device__ __forceinline__ void dot_range(const S* M, const S* v, int nout, int o, int k0, int k1, S& a0, S& a1) {
+  const S* mp = M + k0 * nout + o;
+  int k = k0;
+  for (; k + 4 <= k1; k += 4, mp += 4 * nout) {
+    const S v0 = v[k], v1 = v[k + 1], v2 = v[k + 2], v3 = v[k + 3];
+    const S m0 = mp[0], m1 = mp[nout], m2 = mp[2 * nout], m3 = mp[3 * nout];
+    a0 += m0 * v0 + m2 * v2;
+    a1 += m1 * v1 + m3 * v3;
   }
+  for (; k < k1; ++k, mp += nout) a0 += mp[0] * v[k];
 }
 
+// Output o's sum over inputs [r0, r1) of the concatenation of a head
+// segment (nh inputs: matrix Mh, vector vh) and cnt segments of ns inputs
+// (segment k: matrix Ms + k ms, vector vs + k vk).
 template <typename S>
-__device__ __forceinline__ S mv_fold(const S* red, int nout, int o) {
-  const int G = min(kFW / nout, kFoldMax);
-  S s0 = 0, s1 = 0;
-  int g = 0;
-  for (; g + 1 < G; g += 2) {
-    s0 += red[g * nout + o];
-    s1 += red[(g + 1) * nout + o];
+__device__ __forceinline__ S dot_concat(const S* Mh, const S* vh, int nh, const S* Ms, int ms, const S* vs, int vk,
+                                        int ns, int cnt, int nout, int o, int r0, int r1) {
+  S a0 = 0, a1 = 0;
+  if (r0 < nh) dot_range<S>(Mh, vh, nout, o, r0, min(r1, nh), a0, a1);
+  r0 = max(r0 - nh, 0);
+  r1 -= nh;
+  for (int k = r0 / ns; k < cnt && k * ns < r1; ++k) {
+    const int b = k * ns;
+    dot_range<S>(Ms + k * ms, vs + k * vk, nout, o, max(r0 - b, 0), min(r1 - b, ns), a0, a1);
   }
-  if (g < G) s0 += red[g * nout + o];
+  return a0 + a1;
+}
+
+// Input range of part p of a block of len inputs cut into P parts: [r0, r1)
+// with ranges of a multiple of 4 inputs (the last one shorter, possibly empty).
+__device__ __forceinline__ int part_len(int len, int P) { return (((len + P - 1) / P) + 3) & ~3; }
+
+// Output o summed over the P units of a block, whose partial sums start at
+// red (unit order: even units, odd units, then the two added).
+template <typename S>
+__device__ __forceinline__ S fold_units(const S* red, int P, int o) {
+  S s0 = 0, s1 = 0;
+  int p = 0;
+  for (; p + 1 < P; p += 2) {
+    s0 += red[p * 64 + o];
+    s1 += red[(p + 1) * 64 + o];
+  }
+  if (p < P) s0 += red[p * 64 + o];
   return s0 + s1;
 }
 
@@ -274,15 +291,14 @@ __device__ __forceinline__ void sum_partials(const unsigned long long* pp, int n
 template <typename S>
 __device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds L, unsigned* lds, int i, int j) {
   const DevProb<S>& P = A.P;
-  const int t = threadIdx.x, w = t >> 6;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const int nx = P.nx, nu = P.nu, fc = P.fc[i], n = P.nch[i];
   const int es = L.esz;
   S* M = reinterpret_cast<S*>(lds);
   const S* qv = reinterpret_cast<const S*>(lds + L.oQ);
   const S* xb = reinterpret_cast<const S*>(lds + L.oX);
   const S* ub = reinterpret_cast<const S*>(lds + L.oU);
-  S* redA = reinterpret_cast<S*>(lds + L.oRed);  // (P1 ubar +) sum_c At q partials
-  S* redB = redA + L.rx;                          // (R~^{-1} ubar +) sum_c Bt q
+  S* red = reinterpret_cast<S*>(lds + L.oRed);  // units q0, q1, d0, d1
   const bool leafkids = fc >= P.nl;
   const int k0 = j * L.nc, kc = min(L.nc, n - k0);
   const bool last = k0 + kc == n;
@@ -303,19 +319,21 @@ __device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds L, unsigned* lds, i
     wait_tagged<S>(A.qt + (size_t)(fc + k0) * nx * kTW<S>, kc * nx, A.tag, reinterpret_cast<S*>(lds + L.oQ), A.err);
   wait_vm();
   __syncthreads();
-  if (last) {
-    mv_part<S>(M + L.oK / es, ub, nu, nx, redA, false);
-    mv_part<S>(M + L.oR / es, ub, nu, nu, redB, false);
-  }
-  for (int k = 0; k < kc; ++k) {
-    mv_part<S>(M + L.oA / es + k * (L.sA / es), qv + k * nx, nx, nx, redA, last || k > 0);
-    mv_part<S>(M + L.oB / es + k * (L.sB / es), qv + k * nx, nx, nu, redB, last || k > 0);
+  {
+    // q block [P1 | At^c ...] and d block [R~^{-1} | Bt^c ...] over
+    // [ubar; q^c ...] (ubar only in the family's last chunk), two units each
+    const int nh = last ? nu : 0, len = nh + kc * nx, kb = part_len(len, 2);
+    const bool dblk = w >= 2;
+    const int nout = dblk ? nu : nx, r0 = (w & 1) * kb;
+    if (lane < nout)
+      red[w * 64 + lane] = dot_concat<S>(M + (dblk ? L.oR : L.oK) / es, ub, nh, M + (dblk ? L.oB : L.oA) / es,
+                                         (dblk ? L.sB : L.sA) / es, qv, nx, nx, kc, nout, lane, r0, min(len, r0 + kb));
   }
   __syncthreads();
   if (!last) {
     unsigned long long* pp = A.pt + (size_t)(A.pbase[i] + j) * (nx + nu) * kTW<S>;
-    if (t < nx) put_tagged<S>(pp + (size_t)t * kTW<S>, mv_fold<S>(redA, nx, t), A.tag);
-    if (t < nu) put_tagged<S>(pp + (size_t)(nx + t) * kTW<S>, mv_fold<S>(redB, nu, t), A.tag);
+    if (t < nx) put_tagged<S>(pp + (size_t)t * kTW<S>, fold_units<S>(red, 2, t), A.tag);
+    if (t < nu) put_tagged<S>(pp + (size_t)(nx + t) * kTW<S>, fold_units<S>(red + 128, 2, t), A.tag);
     __syncthreads();  // LDS reuse by the next item
     return;
   }
@@ -325,8 +343,8 @@ __device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds L, unsigned* lds, i
   S sa = 0, sb = 0;
   if (nprev > 0 && (t < nx || t < nu))
     sum_partials<S>(pp, nprev, nx + nu, t < nx ? t : -1, t < nu ? nx + t : -1, A.tag, A.err, sa, sb);
-  if (t < nx) put_tagged<S>(A.qt + ((size_t)i * nx + t) * kTW<S>, sa + mv_fold<S>(redA, nx, t) - xb[t], A.tag);
-  if (t < nu) put_tagged<S>(A.dt + ((size_t)i * nu + t) * kTW<S>, sb + mv_fold<S>(redB, nu, t), A.tag);
+  if (t < nx) put_tagged<S>(A.qt + ((size_t)i * nx + t) * kTW<S>, sa + fold_units<S>(red, 2, t) - xb[t], A.tag);
+  if (t < nu) put_tagged<S>(A.dt + ((size_t)i * nu + t) * kTW<S>, sb + fold_units<S>(red + 128, 2, t), A.tag);
   __syncthreads();  // LDS reuse by the next item
 }
 
@@ -344,7 +362,7 @@ __device__ void flow_fwd(const FlowArgs<S>& A, const FlowLds L, unsigned* lds, i
   S* M = reinterpret_cast<S*>(lds);
   S* vx = reinterpret_cast<S*>(lds + L.oX);
   S* vd = reinterpret_cast<S*>(lds + L.oU);
-  S* red = reinterpret_cast<S*>(lds + L.oRed);  // [child k] partials (rx each); then K x (ru)
+  S* red = reinterpret_cast<S*>(lds + L.oRed);  // units: each child's, then u's
   const int k0 = j * L.nc, kc = min(L.nc, n - k0);
   int rot = 1;
   for (int k = 0; k < kc; ++k) {
@@ -366,17 +384,46 @@ __device__ void flow_fwd(const FlowArgs<S>& A, const FlowLds L, unsigned* lds, i
   }
   wait_vm();
   __syncthreads();
-  S* redK = red + (L.nc > 1 ? L.nc : 1) * L.rx;
-  if (j == 0) mv_part<S>(M + L.oK / es, vx, nx, nu, redK, false);
-  for (int k = 0; k < kc; ++k) {
-    mv_part<S>(M + L.oB / es + k * (L.sB / es), vd, nu, nx, red + k * L.rx, false);
-    mv_part<S>(M + L.oA / es + k * (L.sA / es), vx, nx, nx, red + k * L.rx, true);
+  // child k: [Abar^c | B^c] [x; d] in Pc units; u (chunk 0): K x in Pu units.
+  // Up to 4 blocks share the 4 wavefronts (the split with the shortest
+  // longest range); more blocks take one unit each, the wavefronts in turn.
+  const int lx = nx + nu;
+  int Pc = 1, Pu = j == 0 ? 1 : 0;
+  if (kc + Pu < 4) {
+    if (j != 0) {
+      Pc = 4 / kc;
+    } else if (kc == 2) {
+      Pu = 2;
+    } else {
+      int best = 1 << 30;
+      for (int pc = 1; pc <= 3; ++pc) {
+        const int m = max(part_len(lx, pc), part_len(nx, 4 - pc));
+        if (m < best) {
+          best = m;
+          Pc = pc;
+          Pu = 4 - pc;
+        }
+      }
+    }
+  }
+  const int kbx = part_len(lx, Pc), kbu = Pu > 0 ? part_len(nx, Pu) : 0, nux = kc * Pc;
+  for (int u = w; u < nux + Pu; u += 4) {
+    if (u < nux) {
+      const int k = u / Pc, r0 = (u - k * Pc) * kbx;
+      if (lane < nx)
+        red[u * 64 + lane] = dot_concat<S>(M + L.oA / es + k * (L.sA / es), vx, nx, M + L.oB / es + k * (L.sB / es),
+                                           0, vd, 0, nu, 1, nx, lane, r0, min(lx, r0 + kbx));
+    } else {
+      const int r0 = (u - nux) * kbu;
+      if (lane < nu)
+        red[u * 64 + lane] = dot_concat<S>(M + L.oK / es, vx, nx, M, 0, vx, 0, 1, 0, nu, lane, r0, min(nx, r0 + kbu));
+    }
   }
   __syncthreads();
-  if (j == 0 && t < nu) A.zout[O.u(i) + t] = mv_fold<S>(redK, nu, t) + vd[t];
+  if (j == 0 && t < nu) A.zout[O.u(i) + t] = fold_units<S>(red + nux * 64, Pu, t) + vd[t];
   for (int k = 0; k < kc; ++k)
     if (t < nx) {
-      const S xc = mv_fold<S>(red + k * L.rx, nx, t);
+      const S xc = fold_units<S>(red + k * Pc * 64, Pc, t);
       A.zout[O.x(fc + k0 + k) + t] = xc;
       if (fc + k0 + k < P.nl) put_tagged<S>(A.xt + ((size_t)(fc + k0 + k) * nx + t) * kTW<S>, xc, A.tag);
     }
