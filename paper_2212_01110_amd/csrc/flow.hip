@@ -160,18 +160,23 @@ __device__ __forceinline__ S dot_concat(const S* Mh, const S* vh, int nh, const 
 __device__ __forceinline__ int part_len(int len, int P) { return (((len + P - 1) / P) + 3) & ~3; }
 
 // Output o summed over the P units of a block, whose partial sums start at
-// red (unit order: even units, odd units, then the two added).
+// red, `stride` apart (unit order: even units, odd units, then the two added).
 template <typename S>
-__device__ __forceinline__ S fold_units(const S* red, int P, int o) {
+__device__ __forceinline__ S fold_units(const S* red, int P, int o, int stride = 64) {
   S s0 = 0, s1 = 0;
   int p = 0;
   for (; p + 1 < P; p += 2) {
-    s0 += red[p * 64 + o];
-    s1 += red[(p + 1) * 64 + o];
+    s0 += red[p * stride + o];
+    s1 += red[(p + 1) * stride + o];
   }
-  if (p < P) s0 += red[p * 64 + o];
+  if (p < P) s0 += red[p * stride + o];
   return s0 + s1;
 }
+
+// One child per chunk, narrow n_u: every range lies inside one segment, so
+// the ranges of the n_u-output block share one wavefront as lane groups of
+// n_u (same loop, per-lane base pointers). Half of n_x, rounded down to 4.
+__device__ __forceinline__ int half4(int n) { return (n / 2) & ~3; }
 
 __device__ __forceinline__ unsigned ld_flag(const unsigned* f) {
   return __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -319,7 +324,25 @@ __device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds L, unsigned* lds, i
     wait_tagged<S>(A.qt + (size_t)(fc + k0) * nx * kTW<S>, kc * nx, A.tag, reinterpret_cast<S*>(lds + L.oQ), A.err);
   wait_vm();
   __syncthreads();
-  {
+  const bool narrow = kc == 1 && 3 * nu <= 64;
+  if (narrow) {
+    // three ranges per block: the last chunk's ubar and the two halves of
+    // q^c, else the thirds of q^c; q block on wavefronts 0-2 (lane = output),
+    // d block on wavefront 3 (lane group g of n_u lanes = range g)
+    const int g = w < 3 ? w : lane / nu, o = w < 3 ? lane : lane - g * nu;
+    const bool dblk = w == 3;
+    const int h = half4(nx), k3 = part_len(nx, 3);
+    const bool head = last && g == 0;
+    const int ra = last ? (g == 2 ? h : 0) : g * k3;
+    const int rb = last ? (g == 0 ? nu : g == 1 ? h : nx) : min(nx, ra + k3);
+    const int nout = dblk ? nu : nx;
+    const S* Mp = M + (head ? (dblk ? L.oR : L.oK) : (dblk ? L.oB : L.oA)) / es;
+    if (o < nout && g < 3) {
+      S a0 = 0, a1 = 0;
+      dot_range<S>(Mp, head ? ub : qv, nout, o, ra, rb, a0, a1);
+      red[(dblk ? 192 + g * nu : g * 64) + o] = a0 + a1;
+    }
+  } else {
     // q block [P1 | At^c ...] and d block [R~^{-1} | Bt^c ...] over
     // [ubar; q^c ...] (ubar only in the family's last chunk), two units each
     const int nh = last ? nu : 0, len = nh + kc * nx, kb = part_len(len, 2);
@@ -330,10 +353,14 @@ __device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds L, unsigned* lds, i
                                          (dblk ? L.sB : L.sA) / es, qv, nx, nx, kc, nout, lane, r0, min(len, r0 + kb));
   }
   __syncthreads();
+  // q: units at red (stride 64); d: at red + 128 (stride 64) or red + 192 (stride n_u)
+  const int nun = narrow ? 3 : 2;
+  const S* redd = red + (narrow ? 192 : 128);
+  const int dstr = narrow ? nu : 64;
   if (!last) {
     unsigned long long* pp = A.pt + (size_t)(A.pbase[i] + j) * (nx + nu) * kTW<S>;
-    if (t < nx) put_tagged<S>(pp + (size_t)t * kTW<S>, fold_units<S>(red, 2, t), A.tag);
-    if (t < nu) put_tagged<S>(pp + (size_t)(nx + t) * kTW<S>, fold_units<S>(red + 128, 2, t), A.tag);
+    if (t < nx) put_tagged<S>(pp + (size_t)t * kTW<S>, fold_units<S>(red, nun, t), A.tag);
+    if (t < nu) put_tagged<S>(pp + (size_t)(nx + t) * kTW<S>, fold_units<S>(redd, nun, t, dstr), A.tag);
     __syncthreads();  // LDS reuse by the next item
     return;
   }
@@ -343,8 +370,8 @@ __device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds L, unsigned* lds, i
   S sa = 0, sb = 0;
   if (nprev > 0 && (t < nx || t < nu))
     sum_partials<S>(pp, nprev, nx + nu, t < nx ? t : -1, t < nu ? nx + t : -1, A.tag, A.err, sa, sb);
-  if (t < nx) put_tagged<S>(A.qt + ((size_t)i * nx + t) * kTW<S>, sa + fold_units<S>(red, 2, t) - xb[t], A.tag);
-  if (t < nu) put_tagged<S>(A.dt + ((size_t)i * nu + t) * kTW<S>, sb + fold_units<S>(red + 128, 2, t), A.tag);
+  if (t < nx) put_tagged<S>(A.qt + ((size_t)i * nx + t) * kTW<S>, sa + fold_units<S>(red, nun, t) - xb[t], A.tag);
+  if (t < nu) put_tagged<S>(A.dt + ((size_t)i * nu + t) * kTW<S>, sb + fold_units<S>(redd, nun, t, dstr), A.tag);
   __syncthreads();  // LDS reuse by the next item
 }
 
@@ -388,8 +415,26 @@ __device__ void flow_fwd(const FlowArgs<S>& A, const FlowLds L, unsigned* lds, i
   // Up to 4 blocks share the 4 wavefronts (the split with the shortest
   // longest range); more blocks take one unit each, the wavefronts in turn.
   const int lx = nx + nu;
+  const bool narrow = kc == 1 && j == 0 && 2 * nu <= 64;
   int Pc = 1, Pu = j == 0 ? 1 : 0;
-  if (kc + Pu < 4) {
+  if (narrow) {
+    // x: ranges Abar x (two halves) and B d on wavefronts 0-2 (lane =
+    // output); u: the two halves of K x on wavefront 3 (lane groups of n_u)
+    Pc = 3;
+    Pu = 0;
+    const int h = half4(nx);
+    const int g = w < 3 ? w : lane / nu, o = w < 3 ? lane : lane - g * nu;
+    const int nout = w < 3 ? nx : nu;
+    const bool bd = w < 3 && g == 2;  // the B d range
+    const S* Mp = M + (w == 3 ? L.oK : bd ? L.oB : L.oA) / es;
+    const int ra = bd ? 0 : (g == 1 ? h : 0);
+    const int rb = bd ? nu : (g == 0 ? h : nx);
+    if (o < nout && g < (w < 3 ? 3 : 2)) {
+      S a0 = 0, a1 = 0;
+      dot_range<S>(Mp, bd ? vd : vx, nout, o, ra, rb, a0, a1);
+      red[(w < 3 ? g * 64 : 192 + g * nu) + o] = a0 + a1;
+    }
+  } else if (kc + Pu < 4) {
     if (j != 0) {
       Pc = 4 / kc;
     } else if (kc == 2) {
@@ -407,7 +452,7 @@ __device__ void flow_fwd(const FlowArgs<S>& A, const FlowLds L, unsigned* lds, i
     }
   }
   const int kbx = part_len(lx, Pc), kbu = Pu > 0 ? part_len(nx, Pu) : 0, nux = kc * Pc;
-  for (int u = w; u < nux + Pu; u += 4) {
+  for (int u = narrow ? 4 : w; u < nux + Pu; u += 4) {
     if (u < nux) {
       const int k = u / Pc, r0 = (u - k * Pc) * kbx;
       if (lane < nx)
@@ -420,7 +465,8 @@ __device__ void flow_fwd(const FlowArgs<S>& A, const FlowLds L, unsigned* lds, i
     }
   }
   __syncthreads();
-  if (j == 0 && t < nu) A.zout[O.u(i) + t] = fold_units<S>(red + nux * 64, Pu, t) + vd[t];
+  if (j == 0 && t < nu)
+    A.zout[O.u(i) + t] = (narrow ? fold_units<S>(red + 192, 2, t, nu) : fold_units<S>(red + nux * 64, Pu, t)) + vd[t];
   for (int k = 0; k < kc; ++k)
     if (t < nx) {
       const S xc = fold_units<S>(red + k * Pc * 64, Pc, t);
