@@ -199,7 +199,15 @@ CONFIG_NAMES = {
 
 
 def make_config(k: int, seed: int = 0) -> Instance:
-    """Single-instance workloads 1, 2, 3 (and the shared tree of 5)."""
+    """Single-instance workloads:
+
+    1: 15-node tree, branching 2 for 3 stages, n_x 2, n_u 1;
+    2: 223-node tree, branching 2 for 5 stages then 1 (N 10), n_x 20, n_u 10;
+    3: 20 776-node tree, branching 3 for 7 stages then 1 (N 15, 2187
+       scenarios), n_x 50, n_u 20;
+    5: the 95-node tree shared by the 64-instance batch (branching 2 for 4
+       stages then 1, N 8), n_x 20, n_u 10.
+    """
     rng = np.random.default_rng(seed)
     if k == 1:
         anc = branching_anc([2, 2, 2])
