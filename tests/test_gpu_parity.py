@@ -28,6 +28,10 @@ def _cases():
         "b2x3-nx64": G.make_random_small(13, [2, 2, 2], 64, 64),
         "b5-wide": G.make_random_small(14, [5, 3], 6, 2),
         "b2-nx1": G.make_random_small(15, [2, 2, 1], 1, 1),
+        # n_u between 22 and 32: general mat-vec units backward, lane groups
+        # forward; n_x = 37: uneven halves and thirds of the input ranges
+        "b2-1-2-nu24": G.make_random_small(17, [2, 1, 2], 8, 24),
+        "b3-1-nx37": G.make_random_small(18, [3, 1], 37, 21),
     }
 
 
@@ -274,7 +278,7 @@ def test_solve_config5(prec):
 
 
 # ---------------------------------------------------------------- every lane mapping
-MAP_CASES = ["config2", "b3-1-2", "b2x3-nx64", "b5-wide", "config1"]
+MAP_CASES = ["config2", "b3-1-2", "b2x3-nx64", "b5-wide", "config1", "b2-1-2-nu24", "b3-1-nx37"]
 
 
 @pytest.mark.parametrize("prec", list(FP))
