@@ -11,13 +11,15 @@
 // A family with several chunks has them on different workgroups at the same
 // time: in the forward sweep each writes its own children's states; in the
 // backward sweep each but the last publishes its partial sums
-// sum_c Abar^c' q^c and sum_c B^c' q^c, which the last one adds, in chunk
-// order, to its own before the family's step.
+// sum_c At^c q^c and sum_c Bt^c q^c (the regrouped one-phase step below),
+// which the last one adds, in chunk order, to its own before the family's
+// step.
 // Workgroup b runs items b, b + G, b + 2G, ... (G = grid size = the
-// resident capacity from the occupancy of the kernel; a cooperative launch
-// guarantees residency, a plain one, the default, has it whenever the device
-// runs nothing else). An item waits only on items with a smaller index, so
-// the smallest unfinished item never waits and the launch drains.
+// resident capacity: the occupancy query bounded by the build's register
+// budget and by the LDS in 512-byte blocks; a cooperative launch guarantees
+// residency, a plain one, the default, has it whenever the device runs
+// nothing else). An item waits only on items with a smaller index, so the
+// smallest unfinished item never waits and the launch drains.
 //
 // Values crossing workgroups (q and d of the backward step, x of the
 // forward step) travel as tagged words: each 32-bit half of a value shares a
@@ -33,7 +35,8 @@
 // The matrices of an item, with its xbar/ubar rows (and the leaf seeds) from
 // the pre-pass, are copied into LDS by direct global-to-LDS loads issued
 // before the item's dependency wait: an item costs one HBM round trip, its
-// wait, and LDS mat-vecs.
+// wait, and one phase of LDS mat-vecs, cut into wavefront-uniform units
+// (one output block and one input range per wavefront, lane = output).
 #include "device_common.h"
 
 #include <math.h>
