@@ -109,6 +109,13 @@ int spock_problem_destroy(spock_problem* prob);
 /* sizes and step: n_z, n_eta, alpha and ||L|| (any pointer may be NULL) */
 int spock_problem_sizes(const spock_problem* prob, int64_t* n_z, int64_t* n_eta,
                         double* alpha, double* norm_L);
+/* The family-to-lane mapping the next evaluation of T will use (as
+ * spock_info.mapping), the workgroups of the dataflow launch (0 for the
+ * other mappings) and whether the dataflow form has been given up for this
+ * problem (1) after one of its bounded waits gave up. Any pointer may be
+ * NULL. Errors: SPOCK_EINVAL. */
+int spock_problem_mapping(const spock_problem* prob, int32_t* mapping, int32_t* flow_grid,
+                          int32_t* flow_failed);
 
 /* Solver settings (section 3 termination; Alg. 3 parameters). method CP runs
  * v <- T(v); method SPOCK runs Alg. 3 with Anderson memory m (1..4).
@@ -135,7 +142,11 @@ typedef struct {
   double V_s0;             /* s^0 of the returned point */
   double V_nested;         /* nested AV@R cost of its (x, u), if requested, else NaN */
   double seconds;          /* host wall time of the call */
-  int32_t mapping;         /* lanes per tree family used (8..64), or 256 for one workgroup per family */
+  int32_t mapping;         /* lanes per tree family used (8..64), 256 for one workgroup per family,
+                              512 for the one-launch dataflow sweeps */
+  int32_t flow_fallback;   /* 1 if a bounded wait of the dataflow sweeps gave up (workgroups not
+                              all resident): the call was redone from its start with the per-stage
+                              form, which the problem keeps from then on; else 0 */
 } spock_info;
 
 /* Solves one instance from x0_dev (FP64 [nx], device) and the warm start in
@@ -197,7 +208,10 @@ int spock_apply_L(spock_problem* prob, const void* z_dev, void* eta_dev, void* s
 /* z_dev[n_z] = L* eta_dev[n_eta], the adjoint of L */
 int spock_apply_Lt(spock_problem* prob, const void* eta_dev, void* z_dev, void* stream);
 /* zout_dev = prox_{alpha f}(zin_dev) (section 5.3): s^0 - alpha, projection on
- * S1 with root state x0_dev (Alg. 2), projection on S2 */
+ * S1 with root state x0_dev (Alg. 2), projection on S2. With the dataflow
+ * mapping (512) this call and spock_T synchronise the stream to read the
+ * sweeps' error word; if a bounded wait gave up they switch the problem to
+ * the per-stage form and evaluate again. */
 int spock_prox_f(spock_problem* prob, const void* zin_dev, const double* x0_dev,
                  void* zout_dev, void* stream);
 /* out_dev = prox_{alpha g*}(w_dev) = w - alpha proj_S3(w / alpha) (section 5.4) */

@@ -8,8 +8,10 @@ built library is missing.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -29,6 +31,7 @@ EXPORTED = [
     "spock_problem_destroy", "spock_problem_sizes", "spock_settings_default", "spock_solve",
     "spock_solve_batched", "spock_apply_L", "spock_apply_Lt", "spock_prox_f",
     "spock_prox_gstar", "spock_T", "spock_version", "spock_backward", "spock_profile_T",
+    "spock_problem_mapping",
 ]
 
 
@@ -64,7 +67,7 @@ class Info(ctypes.Structure):
                 ("n_backtracks", ctypes.c_int32), ("xi0", ctypes.c_double),
                 ("xi", ctypes.c_double), ("V_s0", ctypes.c_double),
                 ("V_nested", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("mapping", ctypes.c_int32)]
+                ("mapping", ctypes.c_int32), ("flow_fallback", ctypes.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -73,6 +76,26 @@ class Info(ctypes.Structure):
 
 
 _lib = None
+# live handles, destroyed in order (problems, then trees) by an exit hook that
+# runs before the interpreter and the HIP runtime shut down, so no handle is
+# freed from a finaliser at an unknown point of the shutdown
+_live_problems: "weakref.WeakSet" = None
+_live_trees: "weakref.WeakSet" = None
+
+
+def _track(obj, trees: bool):
+    global _live_problems, _live_trees
+    if _live_problems is None:
+        _live_problems, _live_trees = weakref.WeakSet(), weakref.WeakSet()
+        atexit.register(_destroy_all)
+    (_live_trees if trees else _live_problems).add(obj)
+
+
+def _destroy_all():
+    for p in list(_live_problems or ()):
+        p.close()
+    for t in list(_live_trees or ()):
+        t.close()
 
 
 def lib():
@@ -89,6 +112,7 @@ def lib():
         L.spock_problem_factor.argtypes = [vp, ctypes.POINTER(_ProblemData), ctypes.POINTER(vp)]
         L.spock_problem_destroy.argtypes = [vp]
         L.spock_problem_sizes.argtypes = [vp, vp, vp, vp, vp]
+        L.spock_problem_mapping.argtypes = [vp, vp, vp, vp]
         L.spock_settings_default.argtypes = [ctypes.POINTER(Settings)]
         L.spock_settings_default.restype = None
         L.spock_solve.argtypes = [vp, vp, ctypes.POINTER(Settings), vp, ctypes.POINTER(Info), vp]
@@ -147,11 +171,15 @@ class Tree:
         lib().spock_tree_shape(h, ctypes.byref(N), ctypes.byref(nl), ctypes.byref(nleaf))
         self.N, self.num_nonleaf, self.num_leaves = N.value, nl.value, nleaf.value
         self.num_nodes = len(self._anc)
+        _track(self, trees=True)
 
-    def __del__(self):
+    def close(self):
         if getattr(self, "handle", None) and _lib is not None:
             _lib.spock_tree_destroy(self.handle)
-            self.handle = None
+        self.handle = None
+
+    def __del__(self):
+        self.close()
 
 
 class Problem:
@@ -176,6 +204,7 @@ class Problem:
                                   ctypes.byref(nl))
         self.n_z, self.n_eta, self.alpha, self.norm_L = nz.value, ne.value, al.value, nl.value
         self.n_v = self.n_z + self.n_eta
+        _track(self, trees=False)
 
     @classmethod
     def from_instance(cls, inst, precision=FP64, alpha=0.0, tree=None):
@@ -183,15 +212,43 @@ class Problem:
         return cls(tree, inst.nx, inst.nu, inst.A, inst.B, inst.q, inst.r, inst.qN, inst.xmin,
                    inst.xmax, inst.umin, inst.umax, inst.a_risk, precision, alpha)
 
+    def mapping(self) -> dict:
+        """Mapping the next evaluation of T uses, the dataflow grid, and
+        whether the dataflow form was given up for this problem."""
+        m, g, f = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().spock_problem_mapping(self.handle, ctypes.byref(m), ctypes.byref(g), ctypes.byref(f)),
+               "spock_problem_mapping")
+        return {"mapping": m.value, "flow_grid": g.value, "flow_failed": bool(f.value)}
+
     @property
     def torch_dtype(self):
         import torch
         return torch.float64 if self.precision == FP64 else torch.float32
 
-    def __del__(self):
+    def close(self):
         if getattr(self, "handle", None) and _lib is not None:
             _lib.spock_problem_destroy(self.handle)
-            self.handle = None
+        self.handle = None
+
+    def __del__(self):
+        self.close()
+
+    def refactor(self, q=None, r=None, qN=None, x_box=None, precision=None, alpha=0.0) -> "Problem":
+        """A new problem on the same tree with some cost diagonals replaced
+        (Alg. 1 runs again)."""
+        k = dict(self._keep)
+        for name, val in (("q", q), ("r", r), ("qN", qN)):
+            if val is not None:
+                k[name] = np.asarray(val, dtype=np.float64)
+        if x_box is not None:
+            k["xmin"], k["xmax"] = (np.asarray(b, dtype=np.float64) for b in x_box)
+        return Problem(self.tree, self.nx, self.nu, k["A"], k["B"], k["q"], k["r"], k["qN"], k["xmin"],
+                       k["xmax"], k["umin"], k["umax"], k["a_risk"],
+                       self.precision if precision is None else precision, alpha)
+
+    @property
+    def q(self) -> np.ndarray:
+        return self._keep["q"]
 
     # ---- entry points
     def solve(self, x0, v, settings: Settings | None = None) -> dict:

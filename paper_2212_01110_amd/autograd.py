@@ -1,11 +1,15 @@
 """torch.autograd glue over spock_solve / spock_backward (marshalling only).
 
-SpockValue.apply(x0, q, problem, settings) returns (V*, u0) for the problem
-whose stage-cost diagonals equal q ([num_nodes][nx], FP64); backward calls
-spock_backward with the incoming cotangents and returns the gradients with
-respect to x0 and q."""
+SpockValue.apply(x0, q, problem, settings) returns (V*, u0) of the problem
+with stage-cost diagonals q ([num_nodes][nx], FP64) and root state x0. When q
+differs from the diagonals the problem was factored with, the forward pass
+factors a problem with this q on the same tree (Alg. 1 runs again), so V*
+and u0 are always functions of the q passed in. backward calls
+spock_backward at that problem's solution with the incoming cotangents and
+returns the gradients with respect to x0 and q."""
 from __future__ import annotations
 
+import numpy as np
 import torch
 
 from . import Problem, Settings, default_settings
@@ -16,6 +20,11 @@ class SpockValue(torch.autograd.Function):
     def forward(ctx, x0: torch.Tensor, q: torch.Tensor, problem: Problem,
                 settings: Settings | None = None):
         s = settings or default_settings(eps_abs=1e-10, eps_rel=1e-10, max_iters=400000)
+        qh = q.detach().to("cpu", torch.float64).numpy()
+        if qh.shape != problem.q.shape:
+            raise ValueError(f"q has shape {tuple(qh.shape)}, the problem {problem.q.shape}")
+        if not np.array_equal(qh[1:], problem.q[1:]):
+            problem = problem.refactor(q=qh)
         v = torch.zeros(problem.n_v, dtype=problem.torch_dtype, device=x0.device)
         x0c = x0.detach().to(torch.float64).contiguous()
         info = problem.solve(x0c, v, s)

@@ -26,7 +26,8 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
-    objs = []
+    from concurrent.futures import ThreadPoolExecutor
+    objs, cmds = [], []
     for src in SOURCES:
         obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
         cmd = [hipcc(), *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
@@ -34,8 +35,13 @@ def build(verbose: bool = False) -> str:
             cmd[1:1] = ["-x", "hip"]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        cmds.append(cmd)
         objs.append(obj)
+    # one compiler process per translation unit, at most 4 at a time
+    with ThreadPoolExecutor(max_workers=min(4, len(cmds))) as ex:
+        for res in list(ex.map(lambda c: subprocess.run(c), cmds)):
+            if res.returncode != 0:
+                raise subprocess.CalledProcessError(res.returncode, res.args)
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

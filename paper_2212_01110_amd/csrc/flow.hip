@@ -47,7 +47,6 @@ namespace spk {
 namespace {
 
 constexpr int kFW = 256;                   // threads per workgroup (4 wavefronts)
-constexpr unsigned kSpinLimit = 1u << 21;  // polls of one bounded wait
 
 typedef __attribute__((address_space(3))) void lds_void;
 
@@ -192,9 +191,9 @@ __device__ __forceinline__ unsigned ld_flag(const unsigned* f) {
 // (bounded), copying the values to dst (LDS).
 template <typename S>
 __device__ __forceinline__ void wait_tagged(const unsigned long long* src, int n, unsigned tag, S* dst,
-                                            unsigned* err) {
+                                            unsigned* err, unsigned spin) {
   const int lane = threadIdx.x & 63;
-  for (unsigned it = 0; it < kSpinLimit; ++it) {
+  for (unsigned it = 0; it < spin; ++it) {
     bool ok = true;
     for (int e = lane; e < n; e += 64) {
       S v;
@@ -212,9 +211,9 @@ __device__ __forceinline__ void wait_tagged(const unsigned long long* src, int n
 template <typename S>
 __device__ __forceinline__ void wait_tagged2(const unsigned long long* srcA, int nA, S* dstA,
                                              const unsigned long long* srcB, int nB, S* dstB, unsigned tag,
-                                             unsigned* err) {
+                                             unsigned* err, unsigned spin) {
   const int lane = threadIdx.x & 63;
-  for (unsigned it = 0; it < kSpinLimit; ++it) {
+  for (unsigned it = 0; it < spin; ++it) {
     bool ok = true;
     for (int e = lane; e < nA; e += 64) {
       S v;
@@ -249,6 +248,7 @@ struct FlowArgs {
   const int* pbase;          // [nl] first partial slot of a family with several chunks
   unsigned* err;             // [1]
   unsigned tag;
+  unsigned spin;             // polls of one bounded wait before it gives up
   int nc, nbwd, nitems;
 };
 
@@ -257,8 +257,8 @@ struct FlowArgs {
 // until every word carries tag (bounded).
 template <typename S>
 __device__ __forceinline__ void sum_partials(const unsigned long long* pp, int n, int rs, int ea, int eb,
-                                             unsigned tag, unsigned* err, S& sa, S& sb) {
-  for (unsigned it = 0; it < kSpinLimit; ++it) {
+                                             unsigned tag, unsigned* err, unsigned spin, S& sa, S& sb) {
+  for (unsigned it = 0; it < spin; ++it) {
     bool ok = true;
     S a = 0, b = 0;
     for (int q = 0; q < n; ++q) {
@@ -324,7 +324,7 @@ __device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds L, unsigned* lds, i
   if (leafkids)  // seeds -xbar of the leaf children, written by the pre-pass
     dma_words(A.seeds + (size_t)(fc + k0) * nx, lds, L.oQ, kc * nx * es, rot++);
   else if (w == 3)  // children's q from their backward items
-    wait_tagged<S>(A.qt + (size_t)(fc + k0) * nx * kTW<S>, kc * nx, A.tag, reinterpret_cast<S*>(lds + L.oQ), A.err);
+    wait_tagged<S>(A.qt + (size_t)(fc + k0) * nx * kTW<S>, kc * nx, A.tag, reinterpret_cast<S*>(lds + L.oQ), A.err, A.spin);
   wait_vm();
   __syncthreads();
   const bool narrow = kc == 1 && 3 * nu <= 64;
@@ -372,7 +372,7 @@ __device__ void flow_bwd(const FlowArgs<S>& A, const FlowLds L, unsigned* lds, i
   const unsigned long long* pp = nprev > 0 ? A.pt + (size_t)A.pbase[i] * (nx + nu) * kTW<S> : nullptr;
   S sa = 0, sb = 0;
   if (nprev > 0 && (t < nx || t < nu))
-    sum_partials<S>(pp, nprev, nx + nu, t < nx ? t : -1, t < nu ? nx + t : -1, A.tag, A.err, sa, sb);
+    sum_partials<S>(pp, nprev, nx + nu, t < nx ? t : -1, t < nu ? nx + t : -1, A.tag, A.err, A.spin, sa, sb);
   if (t < nx) put_tagged<S>(A.qt + ((size_t)i * nx + t) * kTW<S>, sa + fold_units<S>(red, nun, t) - xb[t], A.tag);
   if (t < nu) put_tagged<S>(A.dt + ((size_t)i * nu + t) * kTW<S>, sb + fold_units<S>(redd, nun, t, dstr), A.tag);
   __syncthreads();  // LDS reuse by the next item
@@ -402,9 +402,9 @@ __device__ void flow_fwd(const FlowArgs<S>& A, const FlowLds L, unsigned* lds, i
   if (j == 0) dma_words(P.KC + (size_t)i * nx * nu, lds, L.oK, nx * nu * es, rot++);
   if (w == 0) {
     if (i != 0) {  // d and x polled together
-      wait_tagged2<S>(A.dt + (size_t)i * nu * kTW<S>, nu, vd, A.xt + (size_t)i * nx * kTW<S>, nx, vx, A.tag, A.err);
+      wait_tagged2<S>(A.dt + (size_t)i * nu * kTW<S>, nu, vd, A.xt + (size_t)i * nx * kTW<S>, nx, vx, A.tag, A.err, A.spin);
     } else {
-      wait_tagged<S>(A.dt, nu, A.tag, vd, A.err);
+      wait_tagged<S>(A.dt, nu, A.tag, vd, A.err, A.spin);
       if (lane < nx) {
         const S xv = (S)A.x0[lane];
         if (j == 0) A.zout[1 + lane] = xv;
@@ -535,6 +535,7 @@ hipError_t launch_sweeps_flow(const Problem& P, const DevProb<S>& D, S* zout, co
   A.items = F.items;
   A.pbase = F.pbase;
   A.err = F.err;
+  A.spin = F.spin;
   if (++P.flow_epoch == 0u) P.flow_epoch = 1u;  // tag 0 is the cleared state
   A.tag = P.flow_epoch;
   A.nc = F.nc;

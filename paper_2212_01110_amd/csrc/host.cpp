@@ -624,6 +624,15 @@ extern "C" int spock_problem_sizes(const spock_problem* p, int64_t* nz, int64_t*
   return SPOCK_OK;
 }
 
+extern "C" int spock_problem_mapping(const spock_problem* p, int32_t* mapping, int32_t* flow_grid,
+                                     int32_t* flow_failed) {
+  if (!p) return SPOCK_EINVAL;
+  if (mapping) *mapping = p->p.team;
+  if (flow_grid) *flow_grid = p->p.team == kTeamFlow ? p->p.flow.grid : 0;
+  if (flow_failed) *flow_failed = p->p.flow_failed ? 1 : 0;
+  return SPOCK_OK;
+}
+
 extern "C" void spock_settings_default(spock_settings* s) {
   if (!s) return;
   s->eps_abs = 1e-4;
@@ -676,6 +685,21 @@ struct Work {
 // kernel at the register budget occ, and the flags (zeroed once; they are
 // epoch-tagged). The error word is cleared on every call (each API call
 // starts clean).
+// Test knobs of the dataflow form, read on every sizing call:
+// SPOCK_FLOW_GRID caps the grid (fewer workgroups, each running more items,
+// so small trees also take the multi-item drain), SPOCK_FLOW_SPIN sets the
+// polls of one bounded wait (0: every wait gives up at once, which forces the
+// error path with every kernel still ending normally).
+void flow_knobs(FlowState& F) {
+  F.grid = F.resident;
+  F.spin = 1u << 21;
+  if (const char* env = std::getenv("SPOCK_FLOW_GRID")) {
+    const int cap = std::atoi(env);
+    if (cap > 0 && F.grid > 0) F.grid = std::min(F.grid, cap);
+  }
+  if (const char* env = std::getenv("SPOCK_FLOW_SPIN")) F.spin = (unsigned)std::strtoul(env, nullptr, 10);
+}
+
 template <typename S>
 int ensure_flow(Problem& P, int occ = 0, int budget = 0) {
   FlowState& F = P.flow;
@@ -686,6 +710,7 @@ int ensure_flow(Problem& P, int occ = 0, int budget = 0) {
   if (const char* env = std::getenv("SPOCK_FLOW_LDS")) budget = std::max(4096, std::atoi(env));
   if (F.mem && F.elem == (int)sizeof(S) && F.occ == occ && F.budget == budget) {
     if (hipMemset(F.err, 0, sizeof(unsigned)) != hipSuccess) return SPOCK_EHIP;
+    flow_knobs(F);
     return SPOCK_OK;
   }
   if (F.mem) (void)hipFree(F.mem);
@@ -762,6 +787,8 @@ int ensure_flow(Problem& P, int occ = 0, int budget = 0) {
   if (const char* env = std::getenv("SPOCK_FLOW_COOP")) F.coop = std::atoi(env) != 0;
   F.elem = (int)sizeof(S);
   F.grid = (coop && fits) ? nb * ncu : 0;
+  F.resident = F.grid;
+  flow_knobs(F);
   return SPOCK_OK;
 }
 
@@ -839,6 +866,7 @@ int ensure_work(Problem& P, Work<S>& W) {
     P.mbox_dev = static_cast<Mailbox*>(dp);
     P.mbox_epoch = 0;
   }
+  if (P.team == kTeamFlow && P.flow_failed) set_mapping(P, kTeamWG, default_cut(*P.tree));
   if (P.team == kTeamFlow) {
     const int rc = ensure_flow<S>(P);
     if (rc) return rc;
@@ -869,7 +897,7 @@ int autotune(Problem& P, hipStream_t st) {
   // budget (children per chunk against workgroups per CU); the cut field
   // carries occ * 1000 + LDS budget in KiB
   for (int code : {4024, 5024, 6024, 7024, 4032, 5032, 6032, 7032, 4040, 5040, 5046})
-    if (ensure_flow<S>(P, code / 1000, (code % 1000) * 1024) == SPOCK_OK && P.flow.grid > 0)
+    if (!P.flow_failed && ensure_flow<S>(P, code / 1000, (code % 1000) * 1024) == SPOCK_OK && P.flow.grid > 0)
       cands.push_back({kTeamFlow, code});
   int ncut = 0;
   for (int t = std::max(0, T.N - 64); t < T.N && ncut < 3; ++t)
@@ -946,6 +974,33 @@ int autotune(Problem& P, hipStream_t st) {
   return SPOCK_OK;
 }
 
+// Internal status: a bounded wait of the dataflow sweeps gave up during the
+// call (its workgroups were not all resident), so the results it produced
+// are void. The entry points then switch the problem to the per-stage
+// workgroup form (flow_fallback) and redo the call; it never reaches the
+// caller.
+constexpr int kFlowGaveUp = 1000;
+
+// Reads the error word of the dataflow sweeps (synchronises the stream).
+int flow_gave_up(const Problem& P, hipStream_t st, bool& gave_up) {
+  gave_up = false;
+  if (P.team != kTeamFlow || !P.flow.err) return SPOCK_OK;
+  unsigned err = 0;
+  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipMemcpy(&err, P.flow.err, sizeof(unsigned), hipMemcpyDeviceToHost));
+  gave_up = err != 0u;
+  return SPOCK_OK;
+}
+
+// After a give-up: clear the word and run the per-stage workgroup form from
+// now on (the problem never returns to the dataflow form).
+int flow_fallback(Problem& P) {
+  if (P.flow.err) HIP_TRY(hipMemset(P.flow.err, 0, sizeof(unsigned)));
+  P.flow_failed = true;
+  set_mapping(P, kTeamWG, default_cut(*P.tree));
+  return SPOCK_OK;
+}
+
 struct Stats {
   double xip = 0, xid = 0, om2 = 0, rz2 = 0, re2 = 0, cross = 0;
   double xi() const { return std::max(xip, xid); }
@@ -995,6 +1050,12 @@ struct Solver {
     out.re2 = hbuf[4];
     out.cross = hbuf[5];
     ++t_evals;
+    if (!out.ok()) {  // NaN statistics: a dataflow wait that gave up, or the iterate itself
+      bool gave_up = false;
+      const int rc = flow_gave_up(P, st, gave_up);
+      if (rc) return rc;
+      if (gave_up) return kFlowGaveUp;
+    }
     return SPOCK_OK;
   }
   // Polls the mailbox for the epoch; every 4096 polls the stream is asked
@@ -1227,6 +1288,18 @@ extern "C" int spock_solve(spock_problem* ph, const double* x0_dev, const spock_
   int rc = (P.precision == SPOCK_FP64)
                ? solve_impl<double>(P, x0_dev, *s, static_cast<double*>(v_io), loc, st)
                : solve_impl<float>(P, x0_dev, *s, static_cast<float*>(v_io), loc, st);
+  if (rc == kFlowGaveUp) {
+    // v_io is written only at the end of a solve: redo it from the same
+    // start with the per-stage form
+    rc = flow_fallback(P);
+    if (rc) return rc;
+    loc = spock_info{};
+    loc.V_nested = std::numeric_limits<double>::quiet_NaN();
+    loc.mapping = P.team;
+    loc.flow_fallback = 1;
+    rc = (P.precision == SPOCK_FP64) ? solve_impl<double>(P, x0_dev, *s, static_cast<double*>(v_io), loc, st)
+                                     : solve_impl<float>(P, x0_dev, *s, static_cast<float*>(v_io), loc, st);
+  }
   if (rc) return rc;
   // s^0 and, on request, the nested cost of the returned trajectory
   const Tree& T = *P.tree;
@@ -1284,14 +1357,25 @@ extern "C" int spock_prox_gstar(spock_problem* ph, const void* w, void* out, voi
 }
 
 namespace {
+// With the dataflow form, the operator entry points synchronise to read
+// the sweeps' error word; after a give-up they switch the problem to the
+// per-stage form and evaluate again.
 template <typename S>
 int prox_f_impl(Problem& P, const S* zin, const double* x0, S* zout, hipStream_t st) {
-  Work<S> W;
-  int rc = ensure_work<S>(P, W);
-  if (rc) return rc;
-  HIP_TRY(launch_fill<S>(P.neta, W.eta_zero, 0.0, st));
-  HIP_TRY(launch_T<S>(P, zin, zout, x0, W.q, W.d, W.xbar, W.ubar, W.partials, W.stats, st, W.eta_zero, false));
-  return SPOCK_OK;
+  for (int attempt = 0;; ++attempt) {
+    Work<S> W;
+    int rc = ensure_work<S>(P, W);
+    if (rc) return rc;
+    HIP_TRY(launch_fill<S>(P.neta, W.eta_zero, 0.0, st));
+    HIP_TRY(launch_T<S>(P, zin, zout, x0, W.q, W.d, W.xbar, W.ubar, W.partials, W.stats, st, W.eta_zero, false));
+    bool gave_up = false;
+    rc = flow_gave_up(P, st, gave_up);
+    if (rc) return rc;
+    if (!gave_up) return SPOCK_OK;
+    if (attempt > 0) return SPOCK_EHIP;
+    rc = flow_fallback(P);
+    if (rc) return rc;
+  }
 }
 template <typename S>
 int T_impl(Problem& P, const S* v, const double* x0, S* Tv, double* stats, hipStream_t st) {
@@ -1299,6 +1383,14 @@ int T_impl(Problem& P, const S* v, const double* x0, S* Tv, double* stats, hipSt
   int rc = ensure_work<S>(P, W);
   if (rc) return rc;
   HIP_TRY(launch_T<S>(P, v, Tv, x0, W.q, W.d, W.xbar, W.ubar, W.partials, W.stats, st, W.eta_zero, true));
+  bool gave_up = false;
+  rc = flow_gave_up(P, st, gave_up);
+  if (rc) return rc;
+  if (gave_up) {
+    rc = flow_fallback(P);
+    if (rc) return rc;
+    return T_impl<S>(P, v, x0, Tv, stats, st);
+  }
   if (stats) {
     HIP_TRY(hipMemcpyAsync(stats, W.stats, 6 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -1372,6 +1464,11 @@ struct BatchCache {
   double* infos = nullptr;
   size_t infos_n = 0;
   std::vector<std::pair<std::vector<long long>, int>> tuned;  // key -> team
+  // the instantiated graph of the last launch, reused while its arguments
+  // (descriptor and info buffers, settings, team, grid) stay the same
+  hipGraphExec_t exec = nullptr;
+  std::vector<unsigned char> exec_key;
+  hipStream_t cap = nullptr;  // capture stream (created once)
 };
 BatchCache& batch_cache() {
   static BatchCache c;
@@ -1472,22 +1569,39 @@ int batched_impl(int B, spock_problem* const* probs, const double* const* x0, co
     if (team < 0) team = 64;
     C.tuned.push_back({key, team});
   }
-  // ---- the persistent launch, captured in a graph
-  hipStream_t cap;
-  HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-  hipGraph_t graph;
-  hipGraphExec_t exec;
-  HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-  (void)launch_solve_batched<S>(dev_desc, B, bs, team, VM, C.infos, grid, cap);
-  HIP_TRY(hipStreamEndCapture(cap, &graph));
-  HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-  HIP_TRY(hipGraphLaunch(exec, stream));
+  // ---- the persistent launch, captured in a graph (instantiated once per
+  // set of launch arguments and kept)
+  {
+    std::vector<unsigned char> key2(sizeof(BatchSettings) + 6 * sizeof(long long));
+    const long long parts[6] = {(long long)(uintptr_t)dev_desc, (long long)(uintptr_t)C.infos, B, team, VM,
+                                (long long)sizeof(S)};
+    std::memcpy(key2.data(), &bs, sizeof(BatchSettings));
+    std::memcpy(key2.data() + sizeof(BatchSettings), parts, sizeof(parts));
+    if (!C.exec || C.exec_key != key2) {
+      if (C.exec) (void)hipGraphExecDestroy(C.exec);
+      C.exec = nullptr;
+      C.exec_key.clear();
+      if (!C.cap) HIP_TRY(hipStreamCreateWithFlags(&C.cap, hipStreamNonBlocking));
+      hipGraph_t graph = nullptr;
+      HIP_TRY(hipStreamBeginCapture(C.cap, hipStreamCaptureModeThreadLocal));
+      const hipError_t le = launch_solve_batched<S>(dev_desc, B, bs, team, VM, C.infos, grid, C.cap);
+      const hipError_t ee = hipStreamEndCapture(C.cap, &graph);
+      if (le != hipSuccess || ee != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return SPOCK_EHIP;
+      }
+      hipGraphExec_t exec = nullptr;
+      const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ie != hipSuccess) return SPOCK_EHIP;
+      C.exec = exec;
+      C.exec_key = key2;
+    }
+  }
+  HIP_TRY(hipGraphLaunch(C.exec, stream));
   std::vector<double> hi((size_t)16 * B);
   HIP_TRY(hipMemcpyAsync(hi.data(), C.infos, sizeof(double) * 16 * B, hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
-  (void)hipGraphExecDestroy(exec);
-  (void)hipGraphDestroy(graph);
-  (void)hipStreamDestroy(cap);
   for (int b = 0; b < B; ++b) {
     const double* r = hi.data() + (size_t)16 * b;
     spock_info& I = infos[b];
@@ -1559,7 +1673,7 @@ extern "C" int spock_solve_batched(int32_t B, spock_problem* const* probs, const
 namespace {
 
 template <typename S>
-int backward_impl(Problem& P, const S* vstar, const double* x0, double gV, const double* gu0,
+int backward_once(Problem& P, const S* vstar, const double* x0, double gV, const double* gu0,
                   double* gx0, double* gq, double* gqN, const spock_settings& s, spock_info& info,
                   hipStream_t st) {
   Work<S> W;
@@ -1633,6 +1747,10 @@ int backward_impl(Problem& P, const S* vstar, const double* x0, double gV, const
       HIP_TRY(hipMemcpyAsync(hd.data(), W.dots, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
       HIP_TRY(hipStreamSynchronize(st));
       diff = hd[0];
+      bool gave_up = false;
+      rc = flow_gave_up(P, st, gave_up);
+      if (rc) return rc;
+      if (gave_up) return kFlowGaveUp;
       if (!std::isfinite(diff)) {
         info.status = SPOCK_NUMERICAL;
         break;
@@ -1649,6 +1767,12 @@ int backward_impl(Problem& P, const S* vstar, const double* x0, double gV, const
   // gradients from the converged adjoint
   rc = partial(w);
   if (rc) return rc;
+  {
+    bool gave_up = false;
+    rc = flow_gave_up(P, st, gave_up);
+    if (rc) return rc;
+    if (gave_up) return kFlowGaveUp;
+  }
   S* mu = W.q;
   HIP_TRY(launch_phiT<S>(P, cz, mu, st));
   {
@@ -1664,6 +1788,22 @@ int backward_impl(Problem& P, const S* vstar, const double* x0, double gV, const
   if (gq || gqN) HIP_TRY(launch_grad_q<S>(P, vstar, la, lb, gq, gqN, st));
   HIP_TRY(hipStreamSynchronize(st));
   return SPOCK_OK;
+}
+
+// The adjoint iteration; redone from its start with the per-stage form if a
+// bounded wait of the dataflow sweeps gave up during it.
+template <typename S>
+int backward_impl(Problem& P, const S* vstar, const double* x0, double gV, const double* gu0,
+                  double* gx0, double* gq, double* gqN, const spock_settings& s, spock_info& info,
+                  hipStream_t st) {
+  int rc = backward_once<S>(P, vstar, x0, gV, gu0, gx0, gq, gqN, s, info, st);
+  if (rc != kFlowGaveUp) return rc;
+  rc = flow_fallback(P);
+  if (rc) return rc;
+  info.flow_fallback = 1;
+  info.mapping = P.team;
+  rc = backward_once<S>(P, vstar, x0, gV, gu0, gx0, gq, gqN, s, info, st);
+  return rc == kFlowGaveUp ? SPOCK_EHIP : rc;
 }
 
 }  // namespace

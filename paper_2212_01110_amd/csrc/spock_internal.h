@@ -85,7 +85,9 @@ struct FlowState {
   int* pbase = nullptr;              // [nl] first partial slot of a family with several chunks
   int nbwd = 0;                      // backward items (as many forward items follow)
   int nc = 1;                        // children per LDS chunk
-  int grid = 0;                      // resident workgroups (0: form unavailable)
+  int grid = 0;                      // workgroups launched (0: form unavailable)
+  int resident = 0;                  // resident capacity the grid is bounded by
+  unsigned spin = 1u << 21;          // polls of one bounded wait before it gives up
   int occ = 5;                       // register budget: 4 to 7 wavefronts per SIMD
   int elem = 0;                      // element size the state was sized for
   int budget = 32 * 1024;            // LDS budget the chunk size was chosen for
@@ -136,6 +138,9 @@ struct Problem {
   int cut = 0;
   int team_pp = 64;  // lanes per family of the parallel pre/post passes
   bool tuned = false;
+  // set once a bounded wait of the dataflow sweeps gave up: the problem then
+  // runs the per-stage workgroup form for good
+  bool flow_failed = false;
   FlowState flow;
   mutable unsigned flow_epoch = 0;  // tag of the last dataflow launch (never 0 once launched)
   // when set, launch_T records prof[0..4] before the pre-pass, after it,

@@ -19,7 +19,17 @@ import numpy as np  # noqa: E402
 import oracle as O  # noqa: E402
 import spock_gen as G  # noqa: E402
 
-OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_refs.json")
+OUT = os.environ.get("SPOCK_GOLDEN_OUT",
+                     os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_refs.json"))
+
+
+def _entry(res, method, eps, op, dt, **extra):
+    out = {"method": method, "eps": eps, "status": res.status, "iters": res.iters,
+           "t_evals": res.t_evals, "V_s0": res.V_s0, "V_nested": res.V_nested,
+           "u0": res.u0.tolist(), "alpha": op.alpha, "norm_L": op.normL,
+           "xi0": res.xi0, "xi": res.xi, "seconds": dt, "counts": res.counts}
+    out.update(extra)
+    return out
 
 
 def run(name, inst, method, eps, max_iters=200000):
@@ -30,10 +40,25 @@ def run(name, inst, method, eps, max_iters=200000):
     dt = time.time() - t
     print(f"{name}: {method} eps={eps} {res.status} iters={res.iters} t_evals={res.t_evals} "
           f"V={res.V_nested:.12g} {dt:.1f}s", flush=True)
-    return {"method": method, "eps": eps, "status": res.status, "iters": res.iters,
-            "t_evals": res.t_evals, "V_s0": res.V_s0, "V_nested": res.V_nested,
-            "u0": res.u0.tolist(), "alpha": op.alpha, "norm_L": op.normL,
-            "xi0": res.xi0, "xi": res.xi, "seconds": dt, "counts": res.counts}
+    return _entry(res, method, eps, op, dt)
+
+
+def run_chain(name, inst, levels, max_iters=400000):
+    """SPOCK to the first tolerance from v = 0, then continued from the
+    returned point to each tighter absolute tolerance in turn (a fresh
+    Anderson memory at each restart). Returns one entry per level."""
+    op = O.Problem(inst)
+    out, v0, t0 = {}, None, time.time()
+    for k, eps in enumerate(levels):
+        s = O.Settings(eps_abs=eps, eps_rel=eps if k == 0 else 0.0, max_iters=max_iters)
+        res = O.spock_solve(op, inst.x0, s, v0=v0)
+        dt = time.time() - t0
+        print(f"{name}: spock chain eps={eps} {res.status} iters={res.iters} V={res.V_nested:.12g} "
+              f"{dt:.1f}s", flush=True)
+        out[eps] = _entry(res, "spock", eps, op, dt, start="continued" if k else "v=0",
+                          chain=[float(e) for e in levels[: k + 1]])
+        v0 = res.v
+    return out
 
 
 JOBS = {
@@ -50,10 +75,25 @@ JOBS = {
 }
 
 
+# jobs that write several entries: name -> (function, {key: level})
+CHAINS = {
+    "config2_chain": (lambda: run_chain("config2", G.make_config(2), [1e-5, 1e-6, 1e-7]),
+                      {1e-6: "config2_spock_1e-6", 1e-7: "config2_spock_1e-7"}),
+    "config5_chain": (lambda: run_chain("config5", G.make_config(5), [1e-5, 1e-6, 1e-7, 1e-8]),
+                      {1e-7: "config5_spock_1e-7", 1e-8: "config5_spock_1e-8"}),
+}
+
+
 def main(names):
     refs = json.load(open(OUT)) if os.path.exists(OUT) else {}
     for n in names or JOBS:
-        refs[n] = JOBS[n]()
+        if n in CHAINS:
+            fn, keys = CHAINS[n]
+            res = fn()
+            for lvl, key in keys.items():
+                refs[key] = res[lvl]
+        else:
+            refs[n] = JOBS[n]()
         with open(OUT, "w") as f:
             json.dump(refs, f, indent=1, sort_keys=True)
 

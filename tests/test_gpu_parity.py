@@ -1,16 +1,21 @@
 """GPU parity: every entry point through the C-ABI against the FP64 oracle.
 
 Per-operator results on identical inputs must agree within 1e-12 relative in
-FP64 (1e-5 in FP32 storage). Converged solutions are compared only on what
-is unique: V* (as s^0 and as the nested cost of the returned policy) and u^0.
+FP64 (relative to max(1, max |reference|)); FP32 storage within FP32_TOL, a
+bound measured on these cases and derived in the design notes (a few hundred
+FP32 roundings through the sweeps). Converged solutions are compared only on
+what is unique: V* (as s^0 and as the nested cost of the returned policy) and
+u^0.
 """
+import re
+
 import numpy as np
 import pytest
 
 import oracle as O
 import paper_2212_01110_amd as SP
 import spock_gen as G
-from tests.gpu_util import build, dev, host, relerr
+from tests.gpu_util import build, check, dev, host, relerr, seeded
 
 pytestmark = pytest.mark.gpu
 
@@ -36,7 +41,15 @@ def _cases():
 
 
 CASES = {k: v for k, v in _cases().items() if v is not None}
-FP = {"fp64": (SP.FP64, 1e-12), "fp32": (SP.FP32, 2e-5)}
+FP64_TOL = 1e-12
+# FP32 storage: the largest error measured over every case and mapping here
+# is 1.1e-6 (19 FP32 unit roundoffs, prox_f of the n_u = 24 tree); the bound
+# leaves a factor of four
+FP32_TOL = 5e-6
+FP = {"fp64": (SP.FP64, FP64_TOL), "fp32": (SP.FP32, FP32_TOL)}
+# residual statistics of T are FP64 sums over the FP32-stored residual in
+# FP32 storage (largest measured 2.0e-7), relative to max(1, |value|)
+STAT_TOL = {"fp64": FP64_TOL, "fp32": 2e-6}
 
 
 @pytest.fixture(scope="module")
@@ -49,7 +62,19 @@ def probs():
 
 
 def _rng(name):
-    return np.random.default_rng(abs(hash(name)) % (2 ** 32))
+    return seeded(name)
+
+
+def _check_stats(tag, st, rs, r, op, srel):
+    rz, re = op.lay.split(r)
+    xp, xd = np.max(np.abs(rs["xi_p"])), np.max(np.abs(rs["xi_d"]))
+    check(tag + ":xi_p", abs(st["xi_p"] - xp) / max(1, xp), srel)
+    check(tag + ":xi_d", abs(st["xi_d"] - xd) / max(1, xd), srel)
+    check(tag + ":rz2", abs(st["rz2"] - rz @ rz) / max(1, rz @ rz), srel)
+    check(tag + ":re2", abs(st["re2"] - re @ re) / max(1, re @ re), srel)
+    check(tag + ":omega2", abs(st["omega2"] - rs["omega"] ** 2) / max(1, rz @ rz + re @ re), srel)
+    # omega^2 is the M-norm of r (section 3): <r, M r>
+    check(tag + ":omega2_Mr", abs(st["omega2"] - r @ O.M_apply(op, r)) / max(1, rz @ rz + re @ re), srel)
 
 
 @pytest.mark.parametrize("prec", list(FP))
@@ -67,8 +92,8 @@ def test_L_and_Lt(probs, name, prec):
     gp.apply_L(zt, eo)
     gp.apply_Lt(et, zo)
     z_in, e_in = host(zt), host(et)
-    assert relerr(host(eo), O.L_apply(op.lay, op.inst, z_in)) <= tol
-    assert relerr(host(zo), O.Lt_apply(op.lay, op.inst, e_in)) <= tol
+    check(f"L:{name}:{prec}", relerr(host(eo), O.L_apply(op.lay, op.inst, z_in)), tol)
+    check(f"Lt:{name}:{prec}", relerr(host(zo), O.Lt_apply(op.lay, op.inst, e_in)), tol)
 
 
 @pytest.mark.parametrize("prec", list(FP))
@@ -82,7 +107,7 @@ def test_prox_gstar(probs, name, prec):
     out = torch.zeros_like(wt)
     gp.prox_gstar(wt, out)
     ref = O.prox_gstar(op.lay, op.inst, host(wt), op.alpha)
-    assert relerr(host(out), ref) <= 4 * tol
+    check(f"prox_gstar:{name}:{prec}", relerr(host(out), ref), tol)
 
 
 @pytest.mark.parametrize("prec", list(FP))
@@ -98,7 +123,7 @@ def test_prox_f(probs, name, prec):
     out = torch.zeros_like(zt)
     gp.prox_f(zt, x0, out)
     ref = O.prox_f(op.lay, op.inst, op.fac, host(zt), op.alpha, op.inst.x0)
-    assert relerr(host(out), ref) <= 50 * tol
+    check(f"prox_f:{name}:{prec}", relerr(host(out), ref), tol)
 
 
 @pytest.mark.parametrize("prec", list(FP))
@@ -115,17 +140,9 @@ def test_T_and_residual_statistics(probs, name, prec):
     st = gp.T(vt, x0, Tv)
     vin = host(vt)
     ref = O.T_apply(op, vin, op.inst.x0)
-    assert relerr(host(Tv), ref) <= 50 * tol
-    rs = O.residual_stats(op, vin - ref)
+    check(f"T:{name}:{prec}", relerr(host(Tv), ref), tol)
     r = vin - ref
-    rz, re = op.lay.split(r)
-    srel = 50 * tol if prec == "fp64" else 1e-4
-    assert abs(st["xi_p"] - np.max(np.abs(rs["xi_p"]))) <= srel * max(1, np.max(np.abs(rs["xi_p"])))
-    assert abs(st["xi_d"] - np.max(np.abs(rs["xi_d"]))) <= srel * max(1, np.max(np.abs(rs["xi_d"])))
-    assert abs(st["rz2"] - rz @ rz) <= srel * max(1, rz @ rz)
-    assert abs(st["re2"] - re @ re) <= srel * max(1, re @ re)
-    om2 = rs["omega"] ** 2
-    assert abs(st["omega2"] - om2) <= srel * max(1, rz @ rz + re @ re)
+    _check_stats(f"stats:{name}:{prec}", st, O.residual_stats(op, r), r, op, STAT_TOL[prec])
 
 
 def test_norm_L_matches_oracle(probs):
@@ -246,81 +263,174 @@ def _golden(key):
     return refs[key]
 
 
+# Converged solutions against tight oracle references (tests/golden): the
+# FP64 path is solved to the reference's own tolerance; FP32 storage is
+# solved to 1e-5 (above its residual floor). V* and u^0 are compared at the
+# stated 1e-4 relative tolerance (relative to max(1, |value|)).
+SOLVE_CASES = {"config2": ("config2_spock_1e-7", 1e-7), "config5": ("config5_spock_1e-8", 1e-8)}
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_solve_config2(prec):
-    # reference: the oracle solved to 1e-5 (tests/golden/make_golden.py)
-    inst = G.make_config(2)
-    ref = _golden("config2_spock_1e-5")
-    gp, op = build(inst, FP[prec][0])
+@pytest.mark.parametrize("name", list(SOLVE_CASES))
+def test_solve_against_tight_reference(name, prec):
+    key, eps = SOLVE_CASES[name]
+    ref = _golden(key)
+    inst = CASES[name]
+    gp, op = build(inst, FP[prec][0], alpha=ref["alpha"])
     x0 = dev(inst.x0, torch.float64)
     v = torch.zeros(gp.n_v, dtype=gp.torch_dtype, device="cuda")
-    info = gp.solve(x0, v, SP.default_settings(compute_nested=1))
+    e = eps if prec == "fp64" else 1e-5
+    info = gp.solve(x0, v, SP.default_settings(eps_abs=e, eps_rel=e, max_iters=400000, compute_nested=1))
     assert info["status"] == "converged", info
-    tol = 1e-4
-    assert abs(info["V_nested"] - ref["V_nested"]) <= tol * abs(ref["V_nested"]), (info, ref)
-    assert abs(info["V_s0"] - ref["V_nested"]) <= tol * abs(ref["V_nested"]), (info, ref)
+    Vr = ref["V_nested"]
+    check(f"solve_V_nested:{name}:{prec}", abs(info["V_nested"] - Vr) / max(1, abs(Vr)), 1e-4)
+    check(f"solve_V_s0:{name}:{prec}", abs(info["V_s0"] - Vr) / max(1, abs(Vr)), 1e-4)
     out = host(v)
     u0 = out[op.lay.u_off[0]: op.lay.u_off[0] + op.lay.nu]
     u0r = np.array(ref["u0"])
-    assert np.max(np.abs(u0 - u0r)) <= 1e-2 * max(1, np.max(np.abs(u0r)))
-
-
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_solve_config5(prec):
-    inst = G.make_config(5)
-    ref = _golden("config5_spock_1e-5")
-    gp, op = build(inst, FP[prec][0])
-    x0 = dev(inst.x0, torch.float64)
-    v = torch.zeros(gp.n_v, dtype=gp.torch_dtype, device="cuda")
-    info = gp.solve(x0, v, SP.default_settings(eps_abs=1e-5, eps_rel=1e-5, compute_nested=1))
-    assert info["status"] == "converged", info
-    assert abs(info["V_nested"] - ref["V_nested"]) <= 1e-4 * abs(ref["V_nested"]), (info, ref)
+    check(f"solve_u0:{name}:{prec}", np.max(np.abs(u0 - u0r)) / max(1, np.max(np.abs(u0r))), 1e-4)
 
 
 # ---------------------------------------------------------------- every lane mapping
 MAP_CASES = ["config2", "b3-1-2", "b2x3-nx64", "b5-wide", "config1", "b2-1-2-nu24", "b3-1-nx37"]
 
 
-@pytest.mark.parametrize("prec", list(FP))
-@pytest.mark.parametrize("mapping", ["8", "16", "32", "64", "256", "256c0", "256c1", "256c2", "512", "512n1",
-                                     "512p16", "512p32"])
-@pytest.mark.parametrize("name", MAP_CASES)
-def test_T_every_mapping(name, mapping, prec, monkeypatch):
-    # team sizes 8..64, one workgroup per family with per-stage launches,
-    # subtree-owning workgroups below cut stage 0, 1 or 2, and the one-launch
-    # dataflow form (512; 512n1 with an LDS budget of one child per chunk, so
-    # families with several children take several chunks)
-    team, _, cut = mapping.partition("c")
-    if team.startswith("512"):
-        # p16 / p32: 16 or 32 lanes per family in the pre/post passes
-        team, _, pp = team.partition("p")
+MAPPINGS = ["8", "16", "32", "64", "256", "256c0", "256c1", "256c2", "512", "512n1", "512p16", "512p32",
+            "512g1", "512g3", "512n1g2"]
+
+
+def _set_mapping(mapping, monkeypatch):
+    """Environment for a mapping code: team size 8..64; 256 (one workgroup
+    per family, per-stage launches; cN: subtree-owning workgroups below cut
+    stage N); 512 the one-launch dataflow form, with n1: an LDS budget of one
+    child per chunk (families with several children take several chunks),
+    pK: K lanes per family in the pre/post passes, gG: a grid of G workgroups
+    (each drains many items, reusing its LDS, across dependency rounds).
+    Returns the mapping the problem must report."""
+    m = re.fullmatch(r"(\d+)(?:c(\d))?(n1)?(?:p(\d+))?(?:g(\d+))?", mapping)
+    team, cut, n1, pp, grid = m.groups()
+    if team == "512":
         if pp:
             monkeypatch.setenv("SPOCK_TEAM_PP", pp)
-        team, _, _ = team.partition("n")
-        monkeypatch.setenv("SPOCK_FLOW_LDS", "4096" if mapping.endswith("n1") else "40960")
+        monkeypatch.setenv("SPOCK_FLOW_LDS", "4096" if n1 else "40960")
+        if grid:
+            monkeypatch.setenv("SPOCK_FLOW_GRID", grid)
     monkeypatch.setenv("SPOCK_TEAM", team)
     monkeypatch.setenv("SPOCK_CUT", cut if cut else "1000")
+    return int(team)
+
+
+@pytest.mark.parametrize("prec", list(FP))
+@pytest.mark.parametrize("mapping", MAPPINGS)
+@pytest.mark.parametrize("name", MAP_CASES)
+def test_T_every_mapping(name, mapping, prec, monkeypatch):
+    want = _set_mapping(mapping, monkeypatch)
     inst = CASES[name]
     gp, op = build(inst, FP[prec][0])
     tol = FP[prec][1]
     dt = gp.torch_dtype
-    rng = np.random.default_rng(len(mapping))
+    rng = seeded(mapping)
     v = rng.standard_normal(op.lay.n_v)
     vt = dev(v, dt)
     x0 = dev(op.inst.x0, torch.float64)
     Tv = torch.zeros_like(vt)
     st = gp.T(vt, x0, Tv)
+    got = gp.mapping()
+    if want <= 64:
+        # a team mapping whose LDS (256 / team families of 5 vectors of
+        # max(nx, nu) rounded up to 4, plus the statistics) exceeds 64 KiB
+        # runs one workgroup per family instead
+        vm = (max(inst.nx, inst.nu) + 3) // 4 * 4
+        if (256 // want) * 5 * vm * (8 if prec == "fp64" else 4) + 5 * 256 * 8 > 64 * 1024:
+            want = 256
+    assert got["mapping"] == want and not got["flow_failed"], got
+    if mapping.startswith("512") and "g" in mapping:
+        assert got["flow_grid"] == int(mapping.rsplit("g", 1)[1]), got
     vin = host(vt)
     ref = O.T_apply(op, vin, op.inst.x0)
-    assert relerr(host(Tv), ref) <= 50 * tol
-    rs = O.residual_stats(op, vin - ref)
-    srel = 50 * tol if prec == "fp64" else 1e-4
-    assert abs(st["xi_p"] - np.max(np.abs(rs["xi_p"]))) <= srel * max(1, np.max(np.abs(rs["xi_p"])))
-    assert abs(st["xi_d"] - np.max(np.abs(rs["xi_d"]))) <= srel * max(1, np.max(np.abs(rs["xi_d"])))
+    tag = f"{name}:{mapping}:{prec}"
+    check("T_map:" + tag, relerr(host(Tv), ref), tol)
+    r = vin - ref
+    _check_stats("stats_map:" + tag, st, O.residual_stats(op, r), r, op, STAT_TOL[prec])
     zo = torch.zeros(op.lay.n_z, dtype=dt, device="cuda")
     gp.prox_f(vt[: op.lay.n_z].contiguous(), x0, zo)
     reff = O.prox_f(op.lay, op.inst, op.fac, vin[: op.lay.n_z], op.alpha, op.inst.x0)
-    assert relerr(host(zo), reff) <= 50 * tol
+    check("prox_f_map:" + tag, relerr(host(zo), reff), tol)
+
+
+# ---------------------------------------------------------------- the 20 776-node tree
+@pytest.fixture(scope="module")
+def tree20776():
+    """n_x = 50, n_u = 20, N = 15 (branching 3 for 7 stages): the oracle's
+    Alg. 1 factors and one seeded iterate; alpha = 0.3 is passed to both sides
+    (alpha ||L|| < 1 holds: ||L||^2 <= 1 + 3 max q = 4 on this tree)."""
+    from oracle.layout import Layout
+
+    class _P:
+        pass
+    inst = G.make_config(3)
+    op = _P()
+    op.inst, op.lay, op.alpha = inst, Layout(inst), 0.3
+    op.fac = O.factor_s1(op.lay, inst)
+    v = seeded("tree20776").standard_normal(op.lay.n_v)
+    return inst, op, v
+
+
+@pytest.mark.parametrize("prec", list(FP))
+def test_T_and_prox_f_on_20776_node_tree(tree20776, prec, monkeypatch):
+    # the dataflow sweeps at the size the benchmark times: about 20 items per
+    # workgroup, LDS reused across items and cross-round waits, element by
+    # element against the oracle
+    monkeypatch.setenv("SPOCK_TEAM", "512")
+    inst, op, v = tree20776
+    gp = SP.Problem.from_instance(inst, precision=FP[prec][0], alpha=op.alpha)
+    dt = gp.torch_dtype
+    vt = dev(v, dt)
+    x0 = dev(inst.x0, torch.float64)
+    Tv = torch.zeros_like(vt)
+    st = gp.T(vt, x0, Tv)
+    got = gp.mapping()
+    assert got["mapping"] == 512 and got["flow_grid"] > 0 and not got["flow_failed"], got
+    vin = host(vt)
+    ref = O.T_apply(op, vin, inst.x0)
+    check(f"T:tree20776:{prec}", relerr(host(Tv), ref), FP[prec][1])
+    r = vin - ref
+    _check_stats(f"stats:tree20776:{prec}", st, O.residual_stats(op, r), r, op, STAT_TOL[prec])
+    zo = torch.zeros(op.lay.n_z, dtype=dt, device="cuda")
+    gp.prox_f(vt[: op.lay.n_z].contiguous(), x0, zo)
+    reff = O.prox_f(op.lay, inst, op.fac, vin[: op.lay.n_z], op.alpha, inst.x0)
+    check(f"prox_f:tree20776:{prec}", relerr(host(zo), reff), FP[prec][1])
+
+
+# ---------------------------------------------------------------- a dataflow wait that gives up
+@pytest.mark.parametrize("prec", list(FP))
+def test_flow_give_up_falls_back_to_per_stage_form(prec, monkeypatch):
+    # SPOCK_FLOW_SPIN=0: every bounded wait of the dataflow sweeps gives up at
+    # once (every kernel still ends normally). The operator entry points and
+    # the solver must detect it, switch the problem to the per-stage form and
+    # return exact results, never NaN statistics or a line-search backtrack.
+    monkeypatch.setenv("SPOCK_TEAM", "512")
+    monkeypatch.setenv("SPOCK_FLOW_SPIN", "0")
+    inst = CASES["b3-1-2"]
+    gp, op = build(inst, FP[prec][0])
+    tol = FP[prec][1]
+    vt = dev(seeded("giveup").standard_normal(op.lay.n_v), gp.torch_dtype)
+    x0 = dev(inst.x0, torch.float64)
+    Tv = torch.zeros_like(vt)
+    st = gp.T(vt, x0, Tv)
+    got = gp.mapping()
+    assert got["flow_failed"] and got["mapping"] == 256, got
+    assert np.isfinite(st["omega2"])
+    check(f"T_giveup:{prec}", relerr(host(Tv), O.T_apply(op, host(vt), inst.x0)), tol)
+    # a solve on a fresh problem: the first evaluation gives up, the solve is
+    # redone from the same start with the per-stage form
+    gp2 = SP.Problem.from_instance(inst, precision=FP[prec][0], alpha=op.alpha)
+    v = torch.zeros(gp2.n_v, dtype=gp2.torch_dtype, device="cuda")
+    info = gp2.solve(x0, v, SP.default_settings(eps_abs=1e-6, eps_rel=1e-6))
+    assert info["flow_fallback"] == 1 and info["mapping"] == 256, info
+    assert info["status"] == "converged", info
+    ref = O.spock_solve(op, inst.x0, O.Settings(eps_abs=1e-10, eps_rel=1e-10))
+    check(f"solve_giveup:{prec}", abs(info["V_s0"] - ref.V_s0) / max(1, abs(ref.V_s0)), 1e-4)
 
 
 @pytest.mark.parametrize("coop", ["0", "1"])
@@ -343,12 +453,12 @@ def test_flow_form_repeated_launches(prec, coop, monkeypatch):
         Tv = torch.zeros_like(vt)
         st = gp.T(vt, x0, Tv)
         ref = O.T_apply(op, host(vt), op.inst.x0)
-        assert relerr(host(Tv), ref) <= 50 * tol, rep
+        check(f"T_repeat:{prec}:{coop}", relerr(host(Tv), ref), tol)
         assert np.isfinite(st["omega2"])
         zo = torch.zeros(op.lay.n_z, dtype=dt, device="cuda")
         gp.prox_f(vt[: op.lay.n_z].contiguous(), x0, zo)
         reff = O.prox_f(op.lay, op.inst, op.fac, host(vt)[: op.lay.n_z], op.alpha, op.inst.x0)
-        assert relerr(host(zo), reff) <= 50 * tol, rep
+        check(f"prox_f_repeat:{prec}:{coop}", relerr(host(zo), reff), tol)
 
 
 @pytest.mark.parametrize("method", ["cp", "spock"])
