@@ -52,7 +52,8 @@ enum {
   SPOCK_EFACTOR = -5,     /* Alg. 1 hit a non-SPD R~ or a non-finite value */
   SPOCK_EHIP = -6,        /* a HIP runtime call failed */
   SPOCK_ENOMEM = -7,      /* host or device allocation failed */
-  SPOCK_EUNSUPPORTED = -8 /* nx or nu above 64, or an unsupported mode */
+  SPOCK_EUNSUPPORTED = -8, /* nx or nu above 64, or an unsupported mode */
+  SPOCK_ETOOBIG = -9       /* the problem needs more than the fixed scratch of spock_T_noalloc */
 };
 
 /* spock_info.status: outcome of an iteration, not an error. SPOCK_REJECTED is
@@ -222,6 +223,22 @@ int spock_prox_gstar(spock_problem* prob, const void* w_dev, void* out_dev, void
  * synchronises. */
 int spock_T(spock_problem* prob, const void* v_dev, const double* x0_dev, void* Tv_dev,
             double* stats_host, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): spock_T
+ * without any allocation. The sweep buffers and the statistic partials live
+ * in a fixed device array of 64 MiB per GPU, held until the process ends;
+ * the evaluation always uses the per-stage sweeps (the dataflow form needs
+ * buffers of its own). The call allocates nothing: no hipMalloc, hipFree or
+ * allocating routine (the caller passes v_dev, x0_dev and Tv_dev). Every
+ * call on one GPU shares that GPU's array, so calls that overlap on one GPU
+ * (several streams or threads) race; calls ordered on one stream do not.
+ * Nothing in the array needs to start cleared. stats_host as in spock_T (the
+ * call then synchronises). Errors: SPOCK_EINVAL, SPOCK_ETOOBIG (the problem's
+ * buffers exceed the 64 MiB), SPOCK_EUNSUPPORTED (device index 64 or above),
+ * SPOCK_EHIP. */
+int spock_T_noalloc(spock_problem* prob, const void* v_dev, const double* x0_dev, void* Tv_dev,
+                    double* stats_host, void* stream);
 
 /* Timing aid for the CP operator (results as spock_T, statistics not
  * returned): evaluates T(v_dev) reps times on `stream` with HIP events

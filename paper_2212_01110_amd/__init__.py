@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(HERE, "libspock.so")
 
 SPOCK_OK = 0
 ERRORS = {-1: "SPOCK_EINVAL", -2: "SPOCK_ETREE", -3: "SPOCK_EPROB", -4: "SPOCK_EBOX",
-          -5: "SPOCK_EFACTOR", -6: "SPOCK_EHIP", -7: "SPOCK_ENOMEM", -8: "SPOCK_EUNSUPPORTED"}
+          -5: "SPOCK_EFACTOR", -6: "SPOCK_EHIP", -7: "SPOCK_ENOMEM", -8: "SPOCK_EUNSUPPORTED",
+          -9: "SPOCK_ETOOBIG"}
 STATUS = {0: "converged", 1: "maxiter", 2: "numerical", 3: "rejected"}
 FP64, FP32 = 0, 1
 METHOD_CP, METHOD_SPOCK = 0, 1
@@ -31,7 +32,7 @@ EXPORTED = [
     "spock_problem_destroy", "spock_problem_sizes", "spock_settings_default", "spock_solve",
     "spock_solve_batched", "spock_apply_L", "spock_apply_Lt", "spock_prox_f",
     "spock_prox_gstar", "spock_T", "spock_version", "spock_backward", "spock_profile_T",
-    "spock_problem_mapping",
+    "spock_problem_mapping", "spock_T_noalloc",
 ]
 
 
@@ -122,6 +123,7 @@ def lib():
         L.spock_prox_f.argtypes = [vp, vp, vp, vp, vp]
         L.spock_prox_gstar.argtypes = [vp, vp, vp, vp]
         L.spock_T.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.spock_T_noalloc.argtypes = [vp, vp, vp, vp, vp, vp]
         L.spock_profile_T.argtypes = [vp, vp, vp, vp, i32, vp, vp]
         L.spock_backward.argtypes = [vp, vp, vp, dbl, vp, vp, vp, vp, ctypes.POINTER(Settings),
                                      ctypes.POINTER(Info), vp]
@@ -296,6 +298,16 @@ class Problem:
         _check(lib().spock_profile_T(self.handle, _ptr(v), _ptr(x0), _ptr(Tv), int(reps),
                                      ctypes.c_void_p(us.ctypes.data), _stream()), "spock_profile_T")
         return dict(zip(("pre", "sweeps", "post", "reduce", "total"), us.tolist()))
+
+    def T_noalloc(self, v, x0, Tv, want_stats=True):
+        """spock_T_noalloc: T(v) with no device allocation (fixed scratch)."""
+        st = np.zeros(6) if want_stats else None
+        _check(lib().spock_T_noalloc(self.handle, _ptr(v), _ptr(x0), _ptr(Tv),
+                                     ctypes.c_void_p(st.ctypes.data) if want_stats else None, _stream()),
+               "spock_T_noalloc")
+        if st is None:
+            return None
+        return dict(xi_p=st[0], xi_d=st[1], omega2=st[2], rz2=st[3], re2=st[4], cross=st[5])
 
     def T(self, v, x0, Tv, want_stats=True):
         st = np.zeros(6) if want_stats else None

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -1416,6 +1417,85 @@ extern "C" int spock_T(spock_problem* ph, const void* v, const double* x0, void*
   return (P.precision == SPOCK_FP64)
              ? T_impl<double>(P, static_cast<const double*>(v), x0, static_cast<double*>(Tv), stats, st)
              : T_impl<float>(P, static_cast<const float*>(v), x0, static_cast<float*>(Tv), stats, st);
+}
+
+// ============================================================== allocation-free T
+// Fixed device scratch of the allocation-free entry point: the sweep
+// buffers (q, d, xbar, ubar) and the statistic partials of one evaluation of
+// T. Every GPU the library runs on holds its own copy until the process
+// ends. Host code never uses the array's name as an address: the device
+// address comes from hipGetSymbolAddress, once per device.
+namespace {
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kScratchDevices = 64;
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+
+int scratch_address(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kScratchDevices) return SPOCK_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return SPOCK_EHIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return SPOCK_OK;
+}
+
+template <typename S>
+int T_noalloc_impl(const Problem& P, const S* v, const double* x0, S* Tv, double* stats, hipStream_t st) {
+  const Tree& T = *P.tree;
+  size_t off = 0;
+  auto place = [&](size_t bytes) {
+    const size_t at = off;
+    off = (off + bytes + 255) & ~size_t(255);
+    return at;
+  };
+  const size_t oq = place(sizeof(S) * (size_t)T.nn * P.nx), od = place(sizeof(S) * (size_t)T.nn * P.nu);
+  const size_t oxb = place(sizeof(S) * (size_t)T.nn * P.nx), oub = place(sizeof(S) * (size_t)T.nn * P.nu);
+  const size_t opart = place(sizeof(double) * (size_t)(T.nl + 1) * kStats), ostat = place(sizeof(double) * 8);
+  if (off > kScratchBytes) return SPOCK_ETOOBIG;
+  void* base = nullptr;
+  int rc = scratch_address(&base);
+  if (rc) return rc;
+  char* b = static_cast<char*>(base);
+  // the per-stage sweeps (the dataflow form keeps exchange buffers of its own)
+  SweepMap map;
+  if (P.team == kTeamFlow) {
+    map.team = kTeamWG;
+    map.cut = std::max(default_cut(T), std::max(0, T.N - 64));
+  } else {
+    map.team = P.team;
+    map.cut = P.cut;
+  }
+  // every scratch word an evaluation reads it first writes: nothing needs clearing
+  HIP_TRY(launch_T<S>(P, v, Tv, x0, reinterpret_cast<S*>(b + oq), reinterpret_cast<S*>(b + od),
+                      reinterpret_cast<S*>(b + oxb), reinterpret_cast<S*>(b + oub),
+                      reinterpret_cast<double*>(b + opart), reinterpret_cast<double*>(b + ostat), st, nullptr,
+                      true, Publish{}, map));
+  if (stats) {
+    HIP_TRY(hipMemcpyAsync(stats, b + ostat, 6 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  return SPOCK_OK;
+}
+}  // namespace
+
+extern "C" int spock_T_noalloc(spock_problem* ph, const void* v, const double* x0, void* Tv, double* stats,
+                               void* stream) {
+  if (!ph || !v || !Tv || !x0) return SPOCK_EINVAL;
+  const Problem& P = ph->p;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  return (P.precision == SPOCK_FP64)
+             ? T_noalloc_impl<double>(P, static_cast<const double*>(v), x0, static_cast<double*>(Tv), stats, st)
+             : T_noalloc_impl<float>(P, static_cast<const float*>(v), x0, static_cast<float*>(Tv), stats, st);
 }
 
 extern "C" int spock_profile_T(spock_problem* ph, const void* v, const double* x0, void* Tv, int32_t reps,

@@ -498,9 +498,9 @@ static void launch_sweeps_team(const Problem& P, const DevProb<S>& D, S* zout, c
 
 template <typename S>
 static void launch_sweeps_wg(const Problem& P, const DevProb<S>& D, S* zout, const double* x0,
-                             const S* xbar, const S* ubar, S* q, S* d, hipStream_t st) {
+                             const S* xbar, const S* ubar, S* q, S* d, hipStream_t st, int cut) {
   const Tree& tr = *P.tree;
-  const int tc = P.cut;  // stages >= tc are walked by subtree-owning workgroups
+  const int tc = cut;  // stages >= tc are walked by subtree-owning workgroups
   if (tc < tr.N) {
     const int roots = tr.stage_off[tc + 1] - tr.stage_off[tc];
     hipLaunchKernelGGL(k_bwd_tail_wg<S>, dim3(roots), dim3(kWG), 0, st, D, xbar, ubar, q, d, tc,
@@ -549,8 +549,10 @@ int post_blocks(const Problem& P) {
 template <typename S>
 hipError_t launch_T(const Problem& P, const S* v, S* Tv, const double* x0, S* q, S* d, S* xbar,
                     S* ubar, double* partials, double* stats_dev, hipStream_t st,
-                    const S* eta_zero, bool dual, Publish pub) {
+                    const S* eta_zero, bool dual, Publish pub, SweepMap map) {
   const DevProb<S>& D = dev_of<S>(P);
+  const int team = map.team > 0 ? map.team : P.team;
+  const int cut = map.team > 0 ? map.cut : P.cut;
   const S* z = v;
   const S* eta = dual ? v + P.nz : eta_zero;
   S* zout = Tv;
@@ -566,7 +568,7 @@ hipError_t launch_T(const Problem& P, const S* v, S* Tv, const double* x0, S* q,
     default: launch_pre<S, 64>(P, D, z, eta, zout, xbar, ubar, q, st); break;
   }
   mark(1);
-  switch (P.team) {
+  switch (team) {
     case kTeamFlow: {
       const hipError_t e = launch_sweeps_flow<S>(P, D, zout, x0, xbar, ubar, q, d, st);
       if (e != hipSuccess) return e;
@@ -576,7 +578,7 @@ hipError_t launch_T(const Problem& P, const S* v, S* Tv, const double* x0, S* q,
     case 16: launch_sweeps_team<S, 16>(P, D, zout, x0, xbar, ubar, q, d, st); break;
     case 32: launch_sweeps_team<S, 32>(P, D, zout, x0, xbar, ubar, q, d, st); break;
     case 64: launch_sweeps_team<S, 64>(P, D, zout, x0, xbar, ubar, q, d, st); break;
-    default: launch_sweeps_wg<S>(P, D, zout, x0, xbar, ubar, q, d, st); break;
+    default: launch_sweeps_wg<S>(P, D, zout, x0, xbar, ubar, q, d, st, cut); break;
   }
   mark(2);
   if (dual) {
@@ -588,7 +590,7 @@ hipError_t launch_T(const Problem& P, const S* v, S* Tv, const double* x0, S* q,
     }
     mark(3);
     hipLaunchKernelGGL(k_reduce_stats, dim3(1), dim3(256), 0, st, partials, post_blocks(P),
-                       (double)D.alpha, stats_dev, P.team == kTeamFlow ? (const unsigned*)P.flow.err : nullptr,
+                       (double)D.alpha, stats_dev, team == kTeamFlow ? (const unsigned*)P.flow.err : nullptr,
                        pub);
   }
   mark(4);
@@ -596,10 +598,10 @@ hipError_t launch_T(const Problem& P, const S* v, S* Tv, const double* x0, S* q,
 }
 template hipError_t launch_T<double>(const Problem&, const double*, double*, const double*, double*,
                                      double*, double*, double*, double*, double*, hipStream_t,
-                                     const double*, bool, Publish);
+                                     const double*, bool, Publish, SweepMap);
 template hipError_t launch_T<float>(const Problem&, const float*, float*, const double*, float*,
                                     float*, float*, float*, double*, double*, hipStream_t, const float*,
-                                    bool, Publish);
+                                    bool, Publish, SweepMap);
 
 // ---------------------------------------------------------------- L and L*
 // One thread per family (test entry points; simple and exact).

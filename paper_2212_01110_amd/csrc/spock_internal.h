@@ -155,10 +155,15 @@ struct Problem {
 // (kernels.hip) All return hipError_t of the last launch.
 // T(v) (or prox_f of z when dual is false): parallel pre-pass, backward and
 // forward sweeps, parallel post-pass with the residual statistics.
+// Sweep mapping of one launch (team 0: the problem's own mapping and cut).
+struct SweepMap {
+  int team = 0;
+  int cut = 0;
+};
 template <typename S>
 hipError_t launch_T(const Problem& P, const S* v, S* Tv, const double* x0, S* q, S* d, S* xbar,
                     S* ubar, double* partials, double* stats_dev, hipStream_t st,
-                    const S* eta_zero, bool dual, Publish pub = Publish{});
+                    const S* eta_zero, bool dual, Publish pub = Publish{}, SweepMap map = SweepMap{});
 int post_blocks(const Problem& P);
 // Dataflow form of the sweeps (flow.hip): one persistent launch per T.
 template <typename S>
