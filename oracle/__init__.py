@@ -14,7 +14,8 @@ Modules, each citing the passage it follows:
   cp         the CP operator T, residual, xi, omega, vanilla CP (section 3)
   spock      Anderson directions and SPOCK (section 6, Alg. 3)
   risk       AV@R and the exact nested cost of a policy (section 4.2, eq. original-problem)
-  sensitivity envelope gradients of V* w.r.t. x0 and the cost weights (section 3)
+  sensitivity envelope gradients of V*, and implicit (fixed-point) tangents of V* and
+              u^0 w.r.t. x0 and the cost weights (section 3)
 
 Pins (tests/test_oracle_*.py) tie every function to the mathematics rather
 than to itself: L/L* by the adjoint identity and a feasible conic point built
@@ -32,11 +33,12 @@ from .cp import (Problem, T_apply, residual_stats, M_apply, cp_solve, Settings,
                  SolveResult)
 from .spock import spock_solve, AndersonBuffer
 from .risk import avar, nested_cost
-from .sensitivity import envelope_gradients
+from .sensitivity import envelope_gradients, fixed_point_tangent, implicit_gradients, T_jvp
 
 __all__ = [
     "Layout", "L_apply", "Lt_apply", "norm_L", "dense_L", "factor_s1", "proj_S1",
     "proj_S2_block", "proj_S2", "prox_f", "proj_S3", "prox_gstar", "proj_soc",
     "Problem", "T_apply", "residual_stats", "M_apply", "cp_solve", "Settings", "SolveResult",
     "spock_solve", "AndersonBuffer", "avar", "nested_cost", "envelope_gradients",
+    "fixed_point_tangent", "implicit_gradients", "T_jvp",
 ]

@@ -36,6 +36,9 @@ class Settings:
     max_ls: int = 20
     rank_tol: float = 1e-6
     direction: str = "anderson"      # "anderson" | "zero" (test switch)
+    # factor of <r~, v~ - v>_M in the K2 step: 1 for a firmly nonexpansive T
+    # (the reading taken); the printed 2 alpha only as a test switch
+    k2_factor: float = 1.0
 
 
 @dataclass

@@ -60,7 +60,10 @@ class AndersonBuffer:
 
 
 def spock_solve(prob: Problem, x0: np.ndarray, settings: Settings, v0=None,
-                keep_history: bool = False) -> SolveResult:
+                keep_history: bool = False, trace: list | None = None) -> SolveResult:
+    """Alg. 3. With a list in trace, every K2 step appends
+    (v, v~, T(v~), v_new): the iterate, the trial point, its image and the
+    step's result (test instrumentation only)."""
     lay = prob.lay
     s = settings
     v = np.zeros(lay.n_v) if v0 is None else np.array(v0, dtype=float)
@@ -118,9 +121,12 @@ def spock_solve(prob: Problem, x0: np.ndarray, settings: Settings, v0=None,
                 counts["K1"] += 1
                 accepted = True
                 break
-            rho = om_t ** 2 - tau * (rt @ Md)
+            rho = om_t ** 2 - s.k2_factor * tau * (rt @ Md)
             if rho >= s.sigma * om_t * omega:                              # K2
-                v = v - s.lam * rho / om_t ** 2 * rt
+                v_new = v - s.lam * rho / om_t ** 2 * rt
+                if trace is not None:
+                    trace.append((v, vt, Tvt, v_new))
+                v = v_new
                 counts["K2"] += 1
                 Tv = T_apply(prob, v, x0)
                 t_evals += 1

@@ -10,6 +10,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libspock.so")
 SOURCES = ["host.cpp", "kernels.hip", "flow.hip", "batched.hip", "backward.hip"]
+# host-only C++ (no HIP), built with the host compiler
+HOST_SOURCES = ["host_core.cpp"]
+HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-pthread"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed FP32 arithmetic disabled for every HIP translation unit
@@ -37,13 +40,17 @@ def build(verbose: bool = False) -> str:
             print(" ".join(cmd), flush=True)
         cmds.append(cmd)
         objs.append(obj)
+    for src in HOST_SOURCES:
+        obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
+        cmds.append(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
     # one compiler process per translation unit, at most 4 at a time
     with ThreadPoolExecutor(max_workers=min(4, len(cmds))) as ex:
         for res in list(ex.map(lambda c: subprocess.run(c), cmds)):
             if res.returncode != 0:
                 raise subprocess.CalledProcessError(res.returncode, res.args)
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -6,6 +6,7 @@
 #include <string>
 
 #include "../../include/spock.h"
+#include "host_core.h"
 
 namespace spk {
 
@@ -56,12 +57,6 @@ struct DevProb {
   S alpha;
 };
 
-struct Tree {
-  int nn = 0, nl = 0, N = 0;
-  std::vector<int> anc, fc, nch, stage;
-  std::vector<int> stage_off;  // [N+2]: nodes of stage t are [stage_off[t], stage_off[t+1])
-  std::vector<double> prob, pcond;
-};
 
 // Device arrays of one precision.
 struct DevArrays {

@@ -75,6 +75,44 @@ JOBS = {
 }
 
 
+def tangent_direction(kind, seed, inst):
+    """Seeded parameter direction: x0 [nx] or diag Q [nn, nx] (row 0 zero)."""
+    rng = np.random.default_rng(seed)
+    if kind == "x0":
+        return rng.standard_normal(inst.nx)
+    d = rng.standard_normal((inst.num_nodes, inst.nx))
+    d[0] = 0.0
+    return d
+
+
+def run_tangents(name, inst, eps, dirs):
+    """Tight oracle solve, then the fixed-point tangents of V* (= s^0) and
+    u^0 along seeded directions of x0 and diag Q (oracle.fixed_point_tangent,
+    GMRES on the derivative of T)."""
+    op = O.Problem(inst)
+    t = time.time()
+    res = O.spock_solve(op, inst.x0, O.Settings(eps_abs=eps, eps_rel=eps, max_iters=900000))
+    out = {"eps": eps, "alpha": op.alpha, "status": res.status, "xi": res.xi, "V_s0": res.V_s0,
+           "u0": res.u0.tolist(), "dirs": []}
+    lay = op.lay
+    for kind, seed in dirs:
+        d = tangent_direction(kind, seed, inst)
+        dv = O.fixed_point_tangent(op, res.v, inst.x0, **({"dx0": d} if kind == "x0" else {"dq": d}), tol=1e-11)
+        out["dirs"].append({"kind": kind, "seed": seed, "dV": float(dv[0]),
+                            "du0": dv[lay.u_off[0]: lay.u_off[0] + lay.nu].tolist()})
+        print(f"{name}: tangent {kind} seed {seed} dV={dv[0]:.10g} {time.time() - t:.1f}s", flush=True)
+    out["seconds"] = time.time() - t
+    return out
+
+
+JOBS["config5_tangents_1e-11"] = lambda: run_tangents(
+    "config5", G.make_config(5), 1e-11, [("x0", 501), ("x0", 502), ("q", 503), ("q", 504)])
+# two of the 64 instances of the batched form (same tree and data, own x0)
+JOBS["config5b0_tangents_1e-11"] = lambda: run_tangents(
+    "config5[0]", G.make_batch(5, count=1)[0], 1e-11, [("x0", 511), ("q", 512)])
+JOBS["config5b37_tangents_1e-11"] = lambda: run_tangents(
+    "config5[37]", G.make_batch(5, count=38)[37], 1e-11, [("x0", 513), ("q", 514)])
+
 # jobs that write several entries: name -> (function, {key: level})
 CHAINS = {
     "config2_chain": (lambda: run_chain("config2", G.make_config(2), [1e-5, 1e-6, 1e-7]),

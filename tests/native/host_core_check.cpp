@@ -1,0 +1,81 @@
+// CPU driver of the host-only library code (host_core.cpp) for the sanitizer
+// test: reads one case from a text file (argv[1]) and prints what the
+// library computes, one labelled array per line, for the test to compare
+// with the oracle. Input (whitespace-separated): nn nx nu; anc[nn];
+// prob[nn]; A B q r qN xmin xmax umin umax a_risk (the spock_problem_data
+// arrays); x[nn][nx] u[nl][nu] (a trajectory); nc (children per chunk).
+#include <cstdio>
+#include <fstream>
+#include <vector>
+
+#include "../../paper_2212_01110_amd/csrc/host_core.h"
+
+using spk::Tree;
+
+static void put(const char* name, const std::vector<double>& v) {
+  std::printf("%s", name);
+  for (double x : v) std::printf(" %.17g", x);
+  std::printf("\n");
+}
+
+int main(int argc, char** argv) {
+  if (argc < 2) return 2;
+  std::ifstream in(argv[1]);
+  int nn = 0, nx = 0, nu = 0;
+  in >> nn >> nx >> nu;
+  std::vector<int32_t> anc(nn);
+  std::vector<double> prob(nn);
+  for (auto& a : anc) in >> a;
+  for (auto& p : prob) in >> p;
+  auto read = [&](size_t n) {
+    std::vector<double> v(n);
+    for (auto& x : v) in >> x;
+    return v;
+  };
+  std::vector<double> A = read((size_t)nn * nx * nx), B = read((size_t)nn * nx * nu), q = read((size_t)nn * nx),
+                      r = read((size_t)nn * nu), qN = read((size_t)nn * nx), xmin = read((size_t)nn * nx),
+                      xmax = read((size_t)nn * nx), umin = read((size_t)nn * nu), umax = read((size_t)nn * nu),
+                      a = read(nn);
+  Tree T;
+  const int rt = spk::build_tree(nn, anc.data(), prob.data(), T);
+  std::printf("tree_rc %d\n", rt);
+  if (rt != SPOCK_OK) return 0;
+  std::printf("shape %d %d %d\n", T.N, T.nl, T.nn - T.nl);
+  std::vector<double> x = read((size_t)nn * nx), u = read((size_t)T.nl * nu);
+  int nc = 1;
+  in >> nc;
+  spock_problem_data d{};
+  d.nx = nx;
+  d.nu = nu;
+  d.A = A.data();
+  d.B = B.data();
+  d.q = q.data();
+  d.r = r.data();
+  d.qN = qN.data();
+  d.xmin = xmin.data();
+  d.xmax = xmax.data();
+  d.umin = umin.data();
+  d.umax = umax.data();
+  d.a_risk = a.data();
+  const int rd = spk::check_problem_data(T, d);
+  std::printf("data_rc %d\n", rd);
+  if (rd != SPOCK_OK) return 0;
+  spk::Factor F;
+  const int rf = spk::factor_alg1(T, d, F);
+  std::printf("factor_rc %d\n", rf);
+  if (rf != SPOCK_OK) return 0;
+  put("K", F.K);
+  put("Abar", F.Abar);
+  put("P", F.P);
+  put("Rinv", F.Rinv);
+  put("W", F.W);
+  std::printf("normL %.17g\n", spk::norm_L_blocks(T, d));
+  std::printf("nested %.17g\n", spk::nested_cost(T, nx, nu, q.data(), r.data(), qN.data(), a.data(), x, u));
+  std::vector<int> items, pbase;
+  int nslots = 0, nbwd = 0;
+  const int ri = spk::build_flow_items(T, nc, 64, items, pbase, nslots, nbwd);
+  std::printf("items_rc %d %d %d\n", ri, nbwd, nslots);
+  std::vector<double> it(items.begin(), items.end());
+  put("items", it);
+  return 0;
+}

@@ -166,21 +166,72 @@ def test_anderson_buffer_rules():
     assert len(bb.dR) == 1 and bb.dR[0] is not dR[0]
 
 
-def test_fejer_monotone_on_K2_steps():
-    inst = G.make_random_small(51, [2, 2], 2, 1)
+def _dense_M(P):
+    """M = [I, -alpha L*; -alpha L, I] (section 3) from the dense L."""
+    Ld = O.dense_L(P.lay, P.inst)
+    nz, ne = P.lay.n_z, P.lay.n_eta
+    M = np.eye(nz + ne)
+    M[:nz, nz:] = -P.alpha * Ld.T
+    M[nz:, :nz] = -P.alpha * Ld
+    return M
+
+
+def test_M_apply_and_omega_match_dense_definition():
+    # omega of the residual statistics is the M-norm of r: r'Mr with M built
+    # densely from its definition (the column-by-column L is pinned by the
+    # adjoint identity); a sign error in the cross term would show here
+    inst = G.make_random_small(52, [3, 1], 3, 2)
     P = O.Problem(inst)
-    ref = O.spock_solve(P, inst.x0, TIGHT)
-    vstar = ref.v
-    s = O.Settings(eps_abs=1e-6, eps_rel=1e-6, c0=0.0, c1=0.0, direction="zero", lam=1.0)
-    # K2 steps with d = 0 are KM steps: distance to v* in the M-norm never grows
-    v = np.zeros(P.lay.n_v)
-    prev = np.inf
-    for _ in range(200):
-        dist = (v - vstar) @ O.M_apply(P, v - vstar)
-        assert dist <= prev * (1 + 1e-12) + 1e-18
-        prev = dist
-        v = O.T_apply(P, v, inst.x0)
-    del s
+    M = _dense_M(P)
+    rng = np.random.default_rng(9)
+    for _ in range(10):
+        r = rng.standard_normal(P.lay.n_v)
+        assert np.max(np.abs(O.M_apply(P, r) - M @ r)) <= 1e-13 * max(1, np.max(np.abs(M @ r)))
+        om = O.residual_stats(P, r)["omega"]
+        assert abs(om ** 2 - r @ M @ r) <= 1e-12 * (r @ r)
+
+
+def _K2_trace(inst, k2_factor=1.0, iters=400):
+    P = O.Problem(inst)
+    trace = []
+    s = O.Settings(eps_abs=1e-12, eps_rel=1e-12, max_iters=iters, k2_factor=k2_factor)
+    O.spock_solve(P, inst.x0, s, trace=trace)
+    return P, trace
+
+
+def test_K2_steps_project_on_a_halfspace_containing_the_fixed_points():
+    # SPOCK's own K2 steps (Anderson directions, lambda = 1): for a firmly
+    # nonexpansive T the halfspace {w : <r~, v~ - w>_M >= ||r~||_M^2}
+    # contains Fix T, and the step lands on its boundary; hence Fejer
+    # monotonicity in the M-norm towards any fixed point. This decides the
+    # reading of the K2 factor (1, not the printed 2 alpha).
+    inst = G.make_config(1)
+    P, trace = _K2_trace(inst)
+    assert len(trace) >= 20
+    M = _dense_M(P)
+    vstar = O.spock_solve(P, inst.x0, TIGHT).v
+    for v, vt, Tvt, vn in trace:
+        rt = vt - Tvt
+        nr = rt @ M @ rt
+        assert abs(rt @ M @ (vt - vn) - nr) <= 1e-9 * nr
+        assert (vn - vstar) @ M @ (vn - vstar) <= (v - vstar) @ M @ (v - vstar) * (1 + 1e-12) + 1e-20
+        # Fix T lies in the halfspace
+        assert rt @ M @ (vt - vstar) >= nr * (1 - 1e-9) - 1e-14
+
+
+def test_K2_printed_factor_leaves_the_halfspace_boundary():
+    # the printed factor 2 alpha planted in the oracle: its K2 step does not
+    # land on the boundary of that halfspace (alpha != 1/2 here)
+    inst = G.make_config(1)
+    P, _ = _K2_trace(inst, iters=1)
+    assert abs(2 * P.alpha - 1.0) > 0.05
+    P, trace = _K2_trace(inst, k2_factor=2 * P.alpha)
+    assert trace
+    M = _dense_M(P)
+    v, vt, Tvt, vn = trace[0]
+    rt = vt - Tvt
+    nr = rt @ M @ rt
+    assert abs(rt @ M @ (vt - vn) - nr) > 1e-6 * nr
 
 
 def test_cp_and_spock_agree():
