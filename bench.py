@@ -1,21 +1,34 @@
 """Benchmark of the SPOCK hot path on one MI355X.
 
-Workload: the 20 776-node scenario tree (n_x = 50, n_u = 20, N = 15,
-branching 3 for 7 stages, 2187 scenarios), FP32 bulk iterations with FP64
-factorisation, Anderson solve and residual statistics. A step is one SPOCK
-iteration (Alg. 3): the evaluations of the CP operator T (pre-pass, both
-Alg. 2 sweeps, dual update, residual statistics), the Anderson
-Gram/direction kernels and the SuperMann line-search. K steps are timed as
+Headline workload: the 20 776-node scenario tree (n_x = 50, n_u = 20,
+N = 15, branching 3 for 7 stages, 2187 scenarios), FP32 bulk iterations with
+FP64 factorisation, Anderson solve and residual statistics. A step is one
+SPOCK iteration (Alg. 3): the evaluations of the CP operator T (pre-pass,
+both Alg. 2 sweeps, dual update, residual statistics), the Anderson
+Gram/direction kernels and the SuperMann line search. K steps are timed as
 one solve capped at K iterations from a cold start (v = 0); value = T
 evaluations per second (= CP iterations = calls of L, the paper's count).
 
 roofline: the dominant kernel (the sweeps of T, one launch per evaluation in
 the dataflow form) timed with HIP events recorded by the library on its own
-stream, against its algorithmic bytes. cpu_baseline: the FP64 oracle timed on
-a bounded number of T evaluations (with residual statistics) of the same
-workload. The same JSON line carries the time-to-residual results of the
-smaller workloads: 223-node tree FP64 vs FP32, and the 512-instance batch in
-FP32 from a warm start vs the plain FP64 path.
+stream, against the algorithmic bytes of the sweeps as the method states them
+(every factor matrix once per sweep that uses it, q and d written and read
+once); the whole T (those plus v read and T(v) written) beside it.
+cpu_baseline: the FP64 oracle, single-threaded, on a bounded number of T
+evaluations of the same workload.
+
+The same JSON line carries the other legs of the metric, each measured:
+  tree20776_fp64            the headline workload in FP64 bulk
+  tree20776_residual_budget ξ reached from a cold start within a stated
+                            iteration budget (FP32 and FP64), with ξ0
+  time_to_residual_223node  SPOCK to ξ <= max(1e-4, 1e-4 ξ0), FP64 and FP32
+  time_to_residual_512batch 512 uneven trees from perturbed warm starts:
+                            batched FP32 and FP64 launches against the plain
+                            FP64 path solving every instance one by one
+  datacentre_cp_vs_spock    the paper's section-6 comparison (N 7, n_x 5,
+                            eps 1e-5): T evaluations of CP and SPOCK on the GPU
+  datacentre_scaling        the paper's open-loop series (n_x = n_u = 50,
+                            N = 3..15, eps 1e-3), SPOCK in FP32 and FP64
 """
 from __future__ import annotations
 
@@ -36,6 +49,9 @@ NAMES = {1: "15-node binary tree nx2 nu1 N3 (AV@R a=0.5)",
          2: "223-node tree nx20 nu10 N10 (branching 2 for 5 stages)",
          3: "20776-node tree nx50 nu20 N15 (branching 3 for 7 stages, 2187 scenarios)",
          5: "95-node tree nx20 nu10 N8 (branching 2 for 4 stages)"}
+# the paper's own figures (sequential Julia, CPU and precision not stated), as context
+PAPER_SCALING_S = {3: 0.0299, 6: 0.285, 9: 2.43, 12: 22.9, 14: 78.3, 15: 151.5}
+PAPER_SCALING_ITERS = {3: 105, 6: 128, 9: 110, 12: 109, 15: 105}
 
 
 def log(msg):
@@ -50,31 +66,41 @@ def tree_counts(inst):
     return nn, nl, nn - nl
 
 
-def algorithmic_elems_sweeps(inst):
-    """Elements both Alg. 2 sweeps of one T must move, in the form the
-    sweeps kernel computes: every factor matrix once per sweep that uses it
-    (backward: At^c = Abar^c' - M1 B^c', Bt^c = R~^{-1} B^c' per child and
-    R~^{-1}, P1 = M1 - K' per family; forward: Abar^c, B^c per child and K
-    per family), xbar/ubar read, q and d written once and read once, x^i read
-    and u^i, x^c written in the forward sweep."""
-    nn, nl, _ = tree_counts(inst)
-    nx, nu = inst.nx, inst.nu
-    mats = 2 * (nn - 1) * (nx * nx + nx * nu) + nl * (2 * nx * nu + nu * nu)
-    bwd_vec = nl * (nx + nu) + nl * (nx + nu) + (nn - 1) * nx        # xbar,ubar; q,d out; children q in
-    fwd_vec = nl * (nu + nx) + nl * nu + (nn - 1) * nx               # d, x^i in; u, x^c out
-    return int(mats + bwd_vec + fwd_vec)
-
-
-def algorithmic_elems_T(inst):
-    """Elements one whole evaluation of T must move: the sweeps above, plus v
-    read once and T(v) written once, and the per-node data of L and the
-    boxes read once."""
+def sizes(inst):
     nn, nl, nleaf = tree_counts(inst)
     nx, nu = inst.nx, inst.nu
     n_z = 1 + nn * nx + nl * nu + 4 * (nn - 1) + nl
     n_eta = 2 * (nn - 1) + 2 * nl + nl * (nx + nu) + (nn - 1) * (nx + nu + 2) + nleaf * (2 * nx + 2)
-    node = (nn - 1) * (nx + nu) + nleaf * nx + nn * 2 * nx + nl * 2 * nu + 2 * nn
-    return algorithmic_elems_sweeps(inst) + 2 * (n_z + n_eta) + node
+    return n_z, n_eta
+
+
+def algorithmic_elems_sweeps(inst):
+    """Elements both Alg. 2 sweeps must move as the method states them: every
+    factor matrix once per sweep that uses it (Abar and B per child in both
+    sweeps, K per family in both, R~^{-1} and W per family in the backward
+    sweep), and q and d written once and read once."""
+    nn, nl, _ = tree_counts(inst)
+    nx, nu = inst.nx, inst.nu
+    mats = (nn - 1) * (2 * nx * nx + 2 * nx * nu) + nl * (2 * nu * nx + nu * nu + nx * nu)
+    return int(mats + 2 * (nn * nx + nl * nu))
+
+
+def algorithmic_elems_sweeps_regrouped(inst):
+    """The same for the regrouped backward step the sweeps kernel computes
+    (At, Bt per child and R~^{-1}, P1 per family backward; Abar, B per child
+    and K per family forward) with its vector traffic."""
+    nn, nl, _ = tree_counts(inst)
+    nx, nu = inst.nx, inst.nu
+    mats = 2 * (nn - 1) * (nx * nx + nx * nu) + nl * (2 * nx * nu + nu * nu)
+    bwd_vec = nl * (nx + nu) + nl * (nx + nu) + (nn - 1) * nx
+    fwd_vec = nl * (nu + nx) + nl * nu + (nn - 1) * nx
+    return int(mats + bwd_vec + fwd_vec)
+
+
+def algorithmic_elems_T(inst):
+    """One whole T: the sweeps plus v read once and T(v) written once."""
+    n_z, n_eta = sizes(inst)
+    return algorithmic_elems_sweeps(inst) + 2 * (n_z + n_eta)
 
 
 def measured_traffic():
@@ -100,36 +126,33 @@ def measured_traffic():
 
 def cpu_baseline(inst, alpha, budget_s):
     """FP64 oracle: T evaluations with residual statistics from v = 0 until
-    the time budget is spent (the step size is taken as given, so the
-    oracle's exact ||L|| is not part of the sample)."""
+    the time budget is spent, on one thread (the oracle walks the tree node
+    by node; BLAS is limited to one thread for its small products)."""
     import oracle as O
     from oracle.layout import Layout
+    from threadpoolctl import threadpool_limits
 
     class _P:
         pass
     p = _P()
     p.inst, p.lay = inst, Layout(inst)
-    p.fac = O.factor_s1(p.lay, inst)
-    p.alpha = alpha
-    v = np.zeros(p.lay.n_v)
-    n = 0
-    t0 = time.perf_counter()
-    while True:
-        Tv = O.T_apply(p, v, inst.x0)
-        O.residual_stats(p, v - Tv)
-        v = Tv
-        n += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or n >= 1000:
-            break
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except Exception:
-        cores = os.cpu_count()
-    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
-    return {"value": round(n / el, 4), "unit": "CP iters/s", "cores": min(cores, threads), "kind": "oracle",
-            "sample": f"{n} evaluations of T with residual statistics (FP64 numpy) on the same workload "
-                      f"from v=0, {el:.1f} s"}
+    with threadpool_limits(limits=1):
+        p.fac = O.factor_s1(p.lay, inst)
+        p.alpha = alpha
+        v = np.zeros(p.lay.n_v)
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            Tv = O.T_apply(p, v, inst.x0)
+            O.residual_stats(p, v - Tv)
+            v = Tv
+            n += 1
+            el = time.perf_counter() - t0
+            if el >= budget_s or n >= 1000:
+                break
+    return {"value": round(n / el, 4), "unit": "CP iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} evaluations of T with residual statistics (FP64 numpy, one thread) on the "
+                      f"same workload from v=0, {el:.1f} s"}
 
 
 def timed_solve(torch, gp, x0, v, settings):
@@ -138,6 +161,53 @@ def timed_solve(torch, gp, x0, v, settings):
     info = gp.solve(x0, v, settings)
     torch.cuda.synchronize()
     return time.perf_counter() - t0, info
+
+
+def roofline_of(prof, inst, itemsize):
+    e_sw = algorithmic_elems_sweeps(inst)
+    e_T = algorithmic_elems_T(inst)
+    ach = e_sw * itemsize / (prof["sweeps"] * 1e-6) / 1e9
+    ach_T = e_T * itemsize / (prof["total"] * 1e-6) / 1e9
+    return {"achieved": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4),
+            "bytes_per_launch": e_sw * itemsize, "us_per_launch": round(prof["sweeps"], 2),
+            "T_phases_us": {k: round(x, 2) for k, x in prof.items()},
+            "T_whole_algorithmic_bytes": e_T * itemsize,
+            "T_whole_GBps": round(ach_T, 1), "T_whole_frac": round(ach_T / HBM_PEAK_GBS, 4),
+            "regrouped_bytes_per_launch": algorithmic_elems_sweeps_regrouped(inst) * itemsize}
+
+
+def leg_fp64(torch, SP, inst, steps, reps):
+    """The headline workload in FP64 bulk: T evaluations/s over the same
+    capped solve and the phase timing."""
+    gp = SP.Problem.from_instance(inst, precision=SP.FP64)
+    x0 = torch.as_tensor(inst.x0, dtype=torch.float64, device="cuda")
+    v = torch.zeros(gp.n_v, dtype=torch.float64, device="cuda")
+    gp.solve(x0, v, SP.default_settings(max_iters=5))
+    v.zero_()
+    sec, info = timed_solve(torch, gp, x0, v, SP.default_settings(max_iters=steps))
+    prof = gp.profile_T(v, x0, torch.empty_like(v), reps=reps)
+    out = {"value": round(info["t_evals"] / sec, 2), "unit": "CP iters/s", "steps": info["iters"],
+           "t_evals": info["t_evals"], "seconds": round(sec, 4), "mapping": info["mapping"]}
+    out.update(roofline_of(prof, inst, 8))
+    log(f"20776-node FP64: {out['value']} T/s, sweeps {out['achieved']} GB/s")
+    return out, gp
+
+
+def leg_budget(torch, SP, inst, gps, iters):
+    """SPOCK from v = 0 for at most `iters` iterations, FP32 and FP64: the
+    residual reached against the target max(1e-4, 1e-4 xi0)."""
+    out = {"workload": NAMES[3], "iteration_budget": iters}
+    x0 = torch.as_tensor(inst.x0, dtype=torch.float64, device="cuda")
+    for name, gp in gps.items():
+        v = torch.zeros(gp.n_v, dtype=gp.torch_dtype, device="cuda")
+        sec, info = timed_solve(torch, gp, x0, v, SP.default_settings(max_iters=iters))
+        tgt = max(1e-4, 1e-4 * info["xi0"])
+        out[name] = {"seconds": round(sec, 3), "iters": info["iters"], "t_evals": info["t_evals"],
+                     "xi0": info["xi0"], "xi": info["xi"], "target": tgt,
+                     "reached": info["status"] == "converged", "V_s0": info["V_s0"],
+                     "counts": {k: info[k] for k in ("n_k0", "n_k1", "n_k2", "n_km", "n_backtracks")}}
+        log(f"20776-node {name} budget: xi {info['xi0']:.4g} -> {info['xi']:.4g} in {sec:.2f}s")
+    return out
 
 
 def ttr_single(torch, SP, G):
@@ -163,18 +233,17 @@ def ttr_single(torch, SP, G):
     return out
 
 
-def ttr_batched(torch, SP, G, n_plain):
+def ttr_batched(torch, SP, G):
     """512 uneven instances: warm start = FP64 solution + N(0, 0.05^2) on
-    every entry (seeded); batched FP32 (one persistent graph-captured launch)
-    vs the plain FP64 path, instance by instance, on a sample of n_plain
-    instances (the same warm starts), extrapolated to the batch."""
+    every entry (seeded); batched FP32 and FP64 (one persistent graph-captured
+    launch each) vs the plain FP64 path solving every instance one by one
+    from the same warm starts."""
     insts = G.make_batch(4, count=512)
     x0s = [torch.as_tensor(i.x0, dtype=torch.float64, device="cuda") for i in insts]
     p64 = [SP.Problem.from_instance(i, precision=SP.FP64) for i in insts]
     p32 = [SP.Problem.from_instance(i, precision=SP.FP32) for i in insts]
     v64 = [torch.zeros(p.n_v, dtype=torch.float64, device="cuda") for p in p64]
     log("512-batch problems factored")
-    # previous solutions: batched FP64 to 1e-5 (at most 5000 iterations)
     t0 = time.perf_counter()
     SP.solve_batched(p64, x0s, v64, SP.default_settings(eps_abs=1e-5, eps_rel=1e-5, max_iters=5000))
     torch.cuda.synchronize()
@@ -182,47 +251,88 @@ def ttr_batched(torch, SP, G, n_plain):
     rng = np.random.default_rng(2024)
     warm = [v + torch.as_tensor(rng.normal(0.0, 0.05, v.numel()), device="cuda") for v in v64]
     s = SP.default_settings(max_iters=200000)
-    # batched FP32 (autotune / graph capture outside the timing)
-    vb = [w.to(torch.float32) for w in warm]
-    SP.solve_batched(p32, x0s, [x.clone() for x in vb], SP.default_settings(max_iters=5))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos32 = SP.solve_batched(p32, x0s, vb, s)
-    torch.cuda.synchronize()
-    t_b32 = time.perf_counter() - t0
-    log(f"512-batch FP32 warm {t_b32:.3f}s")
-    # batched FP64 for context
-    vb64 = [w.clone() for w in warm]
-    SP.solve_batched(p64, x0s, [x.clone() for x in vb64], SP.default_settings(max_iters=5))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos64b = SP.solve_batched(p64, x0s, vb64, s)
-    torch.cuda.synchronize()
-    t_b64 = time.perf_counter() - t0
-    # plain FP64, one solve per instance, on a sample of the same warm starts
-    idx = np.linspace(0, 511, n_plain).astype(int)
-    t_plain = 0.0
-    iters_plain = []
-    for b in idx:
-        v = warm[b].clone()
-        p64[b].solve(x0s[b], v.clone(), SP.default_settings(max_iters=3))
-        sec, info = timed_solve(torch, p64[b], x0s[b], v, s)
+    res = {}
+    for name, probs, dt in (("fp32", p32, torch.float32), ("fp64", p64, torch.float64)):
+        vb = [w.to(dt) for w in warm]
+        SP.solve_batched(probs, x0s, [x.clone() for x in vb], SP.default_settings(max_iters=5))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = SP.solve_batched(probs, x0s, vb, s)
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t0, infos)
+        log(f"512-batch {name} warm {res[name][0]:.3f}s")
+    # plain FP64, every instance one by one from the same warm starts
+    t_plain, iters_plain, infos_plain = 0.0, [], []
+    for b in range(512):
+        p64[b].solve(x0s[b], warm[b].clone(), SP.default_settings(max_iters=3))  # mapping tuned, untimed
+        sec, info = timed_solve(torch, p64[b], x0s[b], warm[b].clone(), s)
         t_plain += sec
         iters_plain.append(info["iters"])
-    log(f"plain FP64 sample {t_plain:.3f}s")
-    t_plain_all = t_plain * 512 / n_plain
-    conv32 = sum(i["status"] == "converged" for i in infos32)
-    verr = max(abs(a["V_s0"] - b["V_s0"]) / max(1.0, abs(b["V_s0"])) for a, b in zip(infos32, infos64b))
-    log(f"512-batch FP32 {t_b32:.3f}s, FP64 batched {t_b64:.3f}s, plain FP64 {t_plain_all:.2f}s (extrapolated)")
+        infos_plain.append(info)
+    log(f"plain FP64 all 512 {t_plain:.3f}s")
+    i32, i64 = res["fp32"][1], res["fp64"][1]
+    rel = lambda a, b: abs(a["V_s0"] - b["V_s0"]) / max(1.0, abs(b["V_s0"]))  # noqa: E731
     return {"workload": "512 uneven trees nx10 nu5 N 5..12 (warm start, sigma 0.05)",
-            "batched_fp32_seconds": round(t_b32, 4), "batched_fp32_converged": conv32,
-            "batched_fp32_max_iters": max(i["iters"] for i in infos32),
-            "batched_fp32_V_max_rel_err_vs_fp64": verr,
-            "batched_fp64_seconds": round(t_b64, 4),
-            "plain_fp64_seconds_extrapolated": round(t_plain_all, 3),
-            "plain_fp64_sample": f"{n_plain} of 512 instances timed one by one ({t_plain:.3f} s), scaled by 512/{n_plain}",
-            "plain_fp64_mean_iters": float(np.mean(iters_plain)),
-            "speedup_batched_fp32_vs_plain_fp64": round(t_plain_all / t_b32, 2)}
+            "batched_fp32_seconds": round(res["fp32"][0], 4),
+            "batched_fp32_converged": sum(i["status"] == "converged" for i in i32),
+            "batched_fp32_iters_median_max": [int(np.median([i["iters"] for i in i32])), max(i["iters"] for i in i32)],
+            "batched_fp64_seconds": round(res["fp64"][0], 4),
+            "batched_fp64_iters_median_max": [int(np.median([i["iters"] for i in i64])), max(i["iters"] for i in i64)],
+            "plain_fp64_seconds": round(t_plain, 3),
+            "plain_fp64_iters_median_max": [int(np.median(iters_plain)), max(iters_plain)],
+            "plain_fp64_converged": sum(i["status"] == "converged" for i in infos_plain),
+            "V_max_rel_diff_batched_fp32_vs_plain_fp64": max(rel(a, b) for a, b in zip(i32, infos_plain)),
+            "V_max_rel_diff_batched_fp64_vs_plain_fp64": max(rel(a, b) for a, b in zip(i64, infos_plain)),
+            "speedup_batched_fp32_vs_plain_fp64": round(t_plain / res["fp32"][0], 2),
+            "speedup_batched_fp64_vs_plain_fp64": round(t_plain / res["fp64"][0], 2)}
+
+
+def leg_datacentre(torch, SP, G):
+    """Section 6 first experiment: the data-centre model (N 7, n_x 5, binary
+    tree, a 0.95), CP and SPOCK in FP64 to eps_abs = eps_rel = 1e-5."""
+    inst = G.make_datacentre(7, 5)
+    gp = SP.Problem.from_instance(inst, precision=SP.FP64)
+    x0 = torch.as_tensor(inst.x0, dtype=torch.float64, device="cuda")
+    out = {"workload": "data-centre model N7 nx5 (255 nodes), eps 1e-5, FP64",
+           "paper_L_calls": {"cp": 3159, "spock": 571}}
+    for method in ("cp", "spock"):
+        v = torch.zeros(gp.n_v, dtype=torch.float64, device="cuda")
+        gp.solve(x0, v.clone(), SP.default_settings(max_iters=3, method=method))
+        sec, info = timed_solve(torch, gp, x0, v, SP.default_settings(eps_abs=1e-5, eps_rel=1e-5,
+                                                                      max_iters=200000, method=method))
+        out[method] = {"t_evals": info["t_evals"], "iters": info["iters"], "seconds": round(sec, 4),
+                       "status": info["status"], "V_s0": info["V_s0"]}
+    out["t_evals_ratio_cp_over_spock"] = round(out["cp"]["t_evals"] / out["spock"]["t_evals"], 3)
+    log(f"datacentre N7: CP {out['cp']['t_evals']} vs SPOCK {out['spock']['t_evals']} T evaluations")
+    return out
+
+
+def leg_scaling(torch, SP, G, horizons):
+    """Section 6 open-loop series: data-centre model with n_x = n_u = 50,
+    binary tree of horizon N, SPOCK to eps 1e-3 from v = 0, FP32 and FP64."""
+    out = {"workload": "data-centre model nx=nu=50, binary tree, N = " + ",".join(map(str, horizons)) +
+           ", SPOCK eps 1e-3 from v=0",
+           "paper_seconds_context": PAPER_SCALING_S, "paper_iters_context": PAPER_SCALING_ITERS,
+           "paper_hardware": "sequential Julia, CPU and precision not stated", "runs": []}
+    for N in horizons:
+        inst = G.make_datacentre(N, 50)
+        x0 = torch.as_tensor(inst.x0, dtype=torch.float64, device="cuda")
+        row = {"N": N, "nodes": int(inst.num_nodes)}
+        for name, prec in (("fp32", SP.FP32), ("fp64", SP.FP64)):
+            gp = SP.Problem.from_instance(inst, precision=prec)
+            v = torch.zeros(gp.n_v, dtype=gp.torch_dtype, device="cuda")
+            gp.solve(x0, v, SP.default_settings(max_iters=3))
+            v.zero_()
+            sec, info = timed_solve(torch, gp, x0, v, SP.default_settings(eps_abs=1e-3, eps_rel=1e-3,
+                                                                          max_iters=20000))
+            row[name] = {"seconds": round(sec, 4), "iters": info["iters"], "t_evals": info["t_evals"],
+                         "status": info["status"], "V_s0": info["V_s0"], "mapping": info["mapping"]}
+            del gp, v
+            torch.cuda.empty_cache()
+        log(f"datacentre N{N}: fp32 {row['fp32']['seconds']}s ({row['fp32']['iters']} it), "
+            f"fp64 {row['fp64']['seconds']}s ({row['fp64']['iters']} it)")
+        out["runs"].append(row)
+    return out
 
 
 def main():
@@ -235,9 +345,12 @@ def main():
     ap.add_argument("--method", default="spock", choices=["spock", "cp"])
     ap.add_argument("--t-reps", type=int, default=30)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--budget-iters", type=int, default=3000)
+    ap.add_argument("--horizons", default="3,6,9,12,15")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--plain-sample", type=int, default=16)
+    ap.add_argument("--legs", default="fp64,budget,223,512,datacentre,scaling",
+                    help="comma-separated extra legs to run (see the module docstring)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of 512 MiB (reference for the memory-traffic counters)")
     args = ap.parse_args()
@@ -288,25 +401,30 @@ def main():
     Tv = torch.empty_like(v)
     prof = gp.profile_T(v, x0, Tv, reps=args.t_reps)
     itemsize = 4 if prec == SP.FP32 else 8
-    e_sw = algorithmic_elems_sweeps(inst)
-    e_T = algorithmic_elems_T(inst)
-    us_sw = prof["sweeps"]
-    achieved = e_sw * itemsize / (us_sw * 1e-6) / 1e9
     kname = "k_T_flow (both Alg. 2 sweeps, one launch)" if info["mapping"] == 512 else \
         "per-stage backward/forward sweep launches"
     traffic = measured_traffic() if (args.config == 3 and prec == SP.FP32 and info["mapping"] == 512) else None
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": kname, "bytes_per_launch": e_sw * itemsize, "us_per_launch": round(us_sw, 2),
-            "T_phases_us": {k: round(x, 2) for k, x in prof.items()},
-            "T_whole_algorithmic_bytes": e_T * itemsize,
-            "T_whole_GBps": round(e_T * itemsize / (prof["total"] * 1e-6) / 1e9, 1)}
-    log(f"T phases (us): {prof}; sweeps {achieved:.0f} GB/s")
+    roof = {"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": traffic, "kernel": kname}
+    roof.update(roofline_of(prof, inst, itemsize))
+    log(f"T phases (us): {prof}; sweeps {roof['achieved']} GB/s ({roof['frac']}), whole T {roof['T_whole_frac']}")
 
     extras = {}
-    if not args.no_extras:
+    legs = set(args.legs.split(",")) if not args.no_extras else set()
+    if args.config == 3 and ({"fp64", "budget"} & legs):
+        gps = {args.precision: gp}
+        if "fp64" in legs and prec == SP.FP32:
+            extras["tree20776_fp64"], gps["fp64"] = leg_fp64(torch, SP, inst, args.steps, args.t_reps)
+        if "budget" in legs:
+            extras["tree20776_residual_budget"] = leg_budget(torch, SP, inst, gps, args.budget_iters)
+        gps.clear()
+    if "223" in legs:
         extras["time_to_residual_223node"] = ttr_single(torch, SP, G)
-        extras["time_to_residual_512batch"] = ttr_batched(torch, SP, G, args.plain_sample)
+    if "512" in legs:
+        extras["time_to_residual_512batch"] = ttr_batched(torch, SP, G)
+    if "datacentre" in legs:
+        extras["datacentre_cp_vs_spock"] = leg_datacentre(torch, SP, G)
+    if "scaling" in legs:
+        extras["datacentre_scaling"] = leg_scaling(torch, SP, G, [int(n) for n in args.horizons.split(",")])
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(inst, gp.alpha, args.cpu_budget)
