@@ -62,6 +62,12 @@ enum {
 enum { SPOCK_CONVERGED = 0, SPOCK_MAXITER = 1, SPOCK_NUMERICAL = 2, SPOCK_REJECTED = 3 };
 enum { SPOCK_FP64 = 0, SPOCK_FP32 = 1 };
 enum { SPOCK_METHOD_CP = 0, SPOCK_METHOD_SPOCK = 1 };
+/* How the Anderson least squares (section 6.2) is solved: AUTO takes the
+ * device Gram solve for m <= 4 and the QR-updated form above; GRAM: normal
+ * equations with an FP64 Cholesky on the device (m <= 4); QR: a thin QR
+ * factorisation updated at every push (Gram-Schmidt with reorthogonalisation
+ * for a new column, Givens rotations to drop the oldest; m <= 10). */
+enum { SPOCK_AA_AUTO = 0, SPOCK_AA_GRAM = 1, SPOCK_AA_QR = 2 };
 
 /* Scenario tree (section 4.1). anc[num_nodes] with anc[0] = -1 and
  * 0 <= anc[i] < i, nondecreasing in i (breadth-first, contiguous children);
@@ -119,7 +125,8 @@ int spock_problem_mapping(const spock_problem* prob, int32_t* mapping, int32_t* 
                           int32_t* flow_failed);
 
 /* Solver settings (section 3 termination; Alg. 3 parameters). method CP runs
- * v <- T(v); method SPOCK runs Alg. 3 with Anderson memory m (1..4).
+ * v <- T(v); method SPOCK runs Alg. 3 with Anderson memory m (1..10; 1..4
+ * with anderson = SPOCK_AA_GRAM and in spock_solve_batched).
  * Parameters follow Alg. 3: c0, c1, c2 in [0,1), beta, sigma in (0,1),
  * lambda in (0,2); max_ls caps the backtracking (then a plain KM step is
  * taken). compute_nested != 0 also evaluates the exact nested AV@R cost of the
@@ -129,10 +136,12 @@ typedef struct {
   int32_t max_iters, method, m, max_ls;
   double c0, c1, c2, beta, sigma, lambda;
   int32_t compute_nested;
+  int32_t anderson;        /* SPOCK_AA_AUTO, SPOCK_AA_GRAM or SPOCK_AA_QR */
 } spock_settings;
 
 /* Fills the defaults: eps 1e-4/1e-4, max_iters 20000, SPOCK, m = 3,
- * max_ls = 20, c0 = c1 = c2 = 0.99, beta = 0.5, sigma = 0.1, lambda = 1. */
+ * max_ls = 20, c0 = c1 = c2 = 0.99, beta = 0.5, sigma = 0.1, lambda = 1,
+ * anderson = SPOCK_AA_AUTO. */
 void spock_settings_default(spock_settings* s);
 
 typedef struct {

@@ -26,6 +26,7 @@ ERRORS = {-1: "SPOCK_EINVAL", -2: "SPOCK_ETREE", -3: "SPOCK_EPROB", -4: "SPOCK_E
 STATUS = {0: "converged", 1: "maxiter", 2: "numerical", 3: "rejected"}
 FP64, FP32 = 0, 1
 METHOD_CP, METHOD_SPOCK = 0, 1
+AA_AUTO, AA_GRAM, AA_QR = 0, 1, 2
 
 EXPORTED = [
     "spock_tree_create", "spock_tree_destroy", "spock_tree_shape", "spock_problem_factor",
@@ -58,7 +59,8 @@ class Settings(ctypes.Structure):
                 ("m", ctypes.c_int32), ("max_ls", ctypes.c_int32),
                 ("c0", ctypes.c_double), ("c1", ctypes.c_double), ("c2", ctypes.c_double),
                 ("beta", ctypes.c_double), ("sigma", ctypes.c_double),
-                ("lam", ctypes.c_double), ("compute_nested", ctypes.c_int32)]
+                ("lam", ctypes.c_double), ("compute_nested", ctypes.c_int32),
+                ("anderson", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -154,6 +156,8 @@ def default_settings(**kw) -> Settings:
             k = "lam"
         if k == "method" and isinstance(v, str):
             v = METHOD_CP if v.lower() == "cp" else METHOD_SPOCK
+        if k == "anderson" and isinstance(v, str):
+            v = {"auto": AA_AUTO, "gram": AA_GRAM, "qr": AA_QR}[v.lower()]
         setattr(s, k, v)
     return s
 

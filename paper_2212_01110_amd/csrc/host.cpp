@@ -406,6 +406,7 @@ extern "C" void spock_settings_default(spock_settings* s) {
   s->sigma = 0.1;
   s->lambda = 1.0;
   s->compute_nested = 0;
+  s->anderson = SPOCK_AA_AUTO;
 }
 
 extern "C" const char* spock_version(void) { return "spock-mi355x 0.1 (gfx950)"; }
@@ -413,7 +414,9 @@ extern "C" const char* spock_version(void) { return "spock-mi355x 0.1 (gfx950)";
 // ============================================================== workspace
 namespace {
 
-constexpr int kMaxMem = kAAMax;  // Anderson memory supported by the push kernel
+// Anderson memory: up to kAAMax with the device Gram solve, up to kMaxMem
+// with the QR-updated least squares
+constexpr int kMaxMem = 10;
 
 template <typename S>
 struct Work {
@@ -427,6 +430,7 @@ struct Work {
   double* gamma = nullptr;    // [8]
   double* aaG = nullptr;      // Anderson Gram matrix [16] (by slot)
   double* vpart = nullptr;    // vector-kernel partials [blocks][8]
+  double* qrdots = nullptr;   // dot products of the QR-updated Anderson step [64]
   S* eta_zero = nullptr;      // n_eta zeros
   double* x0_zero = nullptr;  // kMaxDim zeros (autotuning input)
   S* pool[10 + 2 * kMaxMem];  // n_v buffers
@@ -556,6 +560,7 @@ int ensure_work(Problem& P, Work<S>& W) {
   add(sizeof(double) * 8);
   add(sizeof(double) * 32);
   add(sizeof(double) * (size_t)nblk * 8);
+  add(sizeof(double) * 64);
   add(sizeof(unsigned) * 2 * kRedCounters);
   add(sizeof(unsigned long long) * kRedRecWords);
   add(sizeof(AARingDev));
@@ -587,6 +592,7 @@ int ensure_work(Problem& P, Work<S>& W) {
   W.gamma = reinterpret_cast<double*>(take(sizeof(double) * 8));
   W.aaG = reinterpret_cast<double*>(take(sizeof(double) * 32));
   W.vpart = reinterpret_cast<double*>(take(sizeof(double) * (size_t)nblk * 8));
+  W.qrdots = reinterpret_cast<double*>(take(sizeof(double) * 64));
   W.counters = reinterpret_cast<unsigned*>(take(sizeof(unsigned) * 2 * kRedCounters));
   W.rec = reinterpret_cast<unsigned long long*>(take(sizeof(unsigned long long) * kRedRecWords));
   W.ring = reinterpret_cast<AARingDev*>(take(sizeof(AARingDev)));
@@ -832,6 +838,261 @@ struct Solver {
 // (drop the oldest column while lambda_min/lambda_max(G) < 1e-12, i.e.
 // sigma_min/sigma_max(dR) < 1e-6). Returns the number of columns kept.
 
+// Singular values extremes of a k x k matrix (one-sided Jacobi on its
+// columns, FP64): smin and smax.
+void sv_extremes(int k, const double (*R)[kMaxMem], double& smin, double& smax) {
+  double A[kMaxMem][kMaxMem];
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) A[i][j] = R[i][j];
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < k; ++p)
+      for (int q = p + 1; q < k; ++q) {
+        double a = 0, b = 0, c = 0;
+        for (int i = 0; i < k; ++i) {
+          a += A[i][p] * A[i][p];
+          b += A[i][q] * A[i][q];
+          c += A[i][p] * A[i][q];
+        }
+        if (c == 0.0 || std::fabs(c) <= 1e-17 * std::sqrt(a * b)) continue;
+        off = std::max(off, std::fabs(c) / std::sqrt(a * b));
+        const double z = (b - a) / (2.0 * c);
+        const double t = (z >= 0 ? 1.0 : -1.0) / (std::fabs(z) + std::sqrt(1.0 + z * z));
+        const double cs = 1.0 / std::sqrt(1.0 + t * t), sn = cs * t;
+        for (int i = 0; i < k; ++i) {
+          const double x = A[i][p], y = A[i][q];
+          A[i][p] = cs * x - sn * y;
+          A[i][q] = sn * x + cs * y;
+        }
+      }
+    if (off <= 1e-15) break;
+  }
+  smin = std::numeric_limits<double>::infinity();
+  smax = 0.0;
+  for (int j = 0; j < k; ++j) {
+    double n2 = 0;
+    for (int i = 0; i < k; ++i) n2 += A[i][j] * A[i][j];
+    smin = std::min(smin, std::sqrt(n2));
+    smax = std::max(smax, std::sqrt(n2));
+  }
+}
+
+// Anderson step with the least squares min ||M^R gamma - r|| solved through
+// a thin QR factorisation M^R = Q R that is updated at every push (section
+// 6.2). A new column is orthogonalised against Q by classical Gram-Schmidt
+// with one reorthogonalisation; the oldest column is removed by Givens
+// rotations that bring R[:, 1:] back to triangular form, the same rotations
+// mixing the columns of Q; gamma solves R gamma = Q'r. The rank rule drops the
+// oldest column while sigma_min / sigma_max(R) < 1e-6 (those of M^R). The
+// vectors (Q, and E = dV - dR) stay on the device; R, the rotations and gamma
+// are FP64 on the host, which reads 2-3 small batches of dot products per push.
+template <typename S>
+struct QrAnderson {
+  int m = 0, k = 0;            // memory and active columns
+  long long nv = 0;
+  S* E[kMaxMem] = {};          // slots of E = dV - dR
+  S* Q[kMaxMem] = {};          // slots of the orthonormal columns
+  int ord[kMaxMem] = {};       // slot of active column j, oldest first
+  double R[kMaxMem][kMaxMem] = {};
+  double qr[kMaxMem] = {};     // Q'r for the current r
+  double gamma[kMaxMem] = {};
+  double* dots_dev = nullptr;
+  double* part = nullptr;
+  hipStream_t st = nullptr;
+
+  int free_slot() const {
+    for (int sl = 0; sl < m; ++sl) {
+      bool used = false;
+      for (int j = 0; j < k; ++j) used = used || ord[j] == sl;
+      if (!used) return sl;
+    }
+    return -1;
+  }
+  // pairs (xs[j], ys[j]) j < n into h[j] (n <= 24), one synchronisation
+  int dots(int n, const S* const* xs, const S* const* ys, double* h) {
+    for (int b = 0; b < n; b += 8) {
+      VecPtrs<S> X{}, Y{};
+      const int c = std::min(8, n - b);
+      for (int j = 0; j < c; ++j) {
+        X.p[j] = xs[b + j];
+        Y.p[j] = ys[b + j];
+      }
+      HIP_TRY(launch_dots<S>(nv, c, X, Y, part, dots_dev + b, st));
+    }
+    HIP_TRY(hipMemcpyAsync(h, dots_dev, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return SPOCK_OK;
+  }
+  // w <- w - sum_j h_j Q_j
+  int subtract(S* w, const double* h) {
+    if (k == 0) return SPOCK_OK;
+    ColMix<S> M;
+    M.nin = k + 1;
+    M.nout = 1;
+    M.in[0] = w;
+    M.c[0][0] = 1.0;
+    for (int j = 0; j < k; ++j) {
+      M.in[1 + j] = Q[ord[j]];
+      M.c[0][1 + j] = -h[j];
+    }
+    M.out[0] = w;
+    HIP_TRY(launch_colmix<S>(nv, M, st));
+    return SPOCK_OK;
+  }
+  // removes the oldest column: Givens rotations on R[:, 1:], the same
+  // rotations on the columns of Q and on Q'r
+  int drop_oldest() {
+    if (k == 0) return SPOCK_OK;
+    double H[kMaxMem][kMaxMem] = {}, Wm[kMaxMem][kMaxMem] = {};
+    for (int i = 0; i < k; ++i) {
+      Wm[i][i] = 1.0;
+      for (int j = 0; j + 1 < k; ++j) H[i][j] = R[i][j + 1];
+    }
+    for (int j = 0; j + 1 < k; ++j) {
+      const double a = H[j][j], b = H[j + 1][j], r = std::hypot(a, b);
+      const double c = r > 0.0 ? a / r : 1.0, sn = r > 0.0 ? b / r : 0.0;
+      for (int l = 0; l < k - 1; ++l) {
+        const double x = H[j][l], y = H[j + 1][l];
+        H[j][l] = c * x + sn * y;
+        H[j + 1][l] = -sn * x + c * y;
+      }
+      for (int i = 0; i < k; ++i) {  // W <- W G_j', columns j, j + 1
+        const double x = Wm[i][j], y = Wm[i][j + 1];
+        Wm[i][j] = c * x + sn * y;
+        Wm[i][j + 1] = -sn * x + c * y;
+      }
+      const double x = qr[j], y = qr[j + 1];
+      qr[j] = c * x + sn * y;
+      qr[j + 1] = -sn * x + c * y;
+    }
+    if (k > 1) {
+      ColMix<S> M;
+      M.nin = k;
+      M.nout = k - 1;
+      for (int i = 0; i < k; ++i) M.in[i] = Q[ord[i]];
+      // the new columns go to the slots of columns 1..k-1 (inputs are read first)
+      for (int j = 0; j + 1 < k; ++j) {
+        M.out[j] = Q[ord[j + 1]];
+        for (int i = 0; i < k; ++i) M.c[j][i] = Wm[i][j];
+      }
+      HIP_TRY(launch_colmix<S>(nv, M, st));
+    }
+    for (int j = 0; j + 1 < k; ++j) ord[j] = ord[j + 1];
+    for (int i = 0; i < kMaxMem; ++i)
+      for (int j = 0; j < kMaxMem; ++j) R[i][j] = (i < k - 1 && j < k - 1) ? H[i][j] : 0.0;
+    for (int j = k - 1; j < kMaxMem; ++j) qr[j] = 0.0;
+    --k;
+    return SPOCK_OK;
+  }
+  // push of the newest difference pair and solve; r = v - Tv, then d and
+  // step = v + d
+  int push_and_direction(const S* v, const S* vprev, const S* Tv, const S* rprev, S* r, S* d, S* step) {
+    if (k == m) {
+      const int rc = drop_oldest();
+      if (rc) return rc;
+    }
+    const int sl = free_slot();
+    if (sl < 0) return SPOCK_EINVAL;
+    S* w = Q[sl];
+    {  // r = v - Tv, dR = r - rprev (into the new Q slot), E = dV - dR = Tv + rprev - vprev
+      ColMix<S> M;
+      M.nin = 4;
+      M.nout = 3;
+      M.in[0] = v;
+      M.in[1] = Tv;
+      M.in[2] = rprev;
+      M.in[3] = vprev;
+      M.out[0] = r;
+      M.out[1] = w;
+      M.out[2] = E[sl];
+      const double cr[4] = {1, -1, 0, 0}, cw[4] = {1, -1, -1, 0}, ce[4] = {0, 1, 1, -1};
+      for (int j = 0; j < 4; ++j) {
+        M.c[0][j] = cr[j];
+        M.c[1][j] = cw[j];
+        M.c[2][j] = ce[j];
+      }
+      HIP_TRY(launch_colmix<S>(nv, M, st));
+    }
+    const S* xs[24];
+    const S* ys[24];
+    double h[24], h1[kMaxMem] = {}, h2[kMaxMem] = {};
+    // Q'w and Q'r
+    for (int j = 0; j < k; ++j) {
+      xs[j] = Q[ord[j]];
+      ys[j] = w;
+      xs[k + j] = Q[ord[j]];
+      ys[k + j] = r;
+    }
+    int rc = k ? dots(2 * k, xs, ys, h) : SPOCK_OK;
+    if (rc) return rc;
+    for (int j = 0; j < k; ++j) {
+      h1[j] = h[j];
+      qr[j] = h[k + j];
+    }
+    if ((rc = subtract(w, h1))) return rc;
+    // reorthogonalisation
+    if (k) {
+      for (int j = 0; j < k; ++j) {
+        xs[j] = Q[ord[j]];
+        ys[j] = w;
+      }
+      if ((rc = dots(k, xs, ys, h2))) return rc;
+      if ((rc = subtract(w, h2))) return rc;
+    }
+    xs[0] = w;
+    ys[0] = w;
+    xs[1] = w;
+    ys[1] = r;
+    if ((rc = dots(2, xs, ys, h))) return rc;
+    const double rho = std::sqrt(std::max(h[0], 0.0));
+    {
+      ColMix<S> M;  // normalise
+      M.nin = 1;
+      M.nout = 1;
+      M.in[0] = w;
+      M.out[0] = w;
+      M.c[0][0] = rho > 0.0 ? 1.0 / rho : 0.0;
+      HIP_TRY(launch_colmix<S>(nv, M, st));
+    }
+    for (int j = 0; j < k; ++j) R[j][k] = h1[j] + h2[j];
+    for (int j = 0; j <= k; ++j) R[k][j] = 0.0;
+    R[k][k] = rho;
+    qr[k] = rho > 0.0 ? h[1] / rho : 0.0;
+    ord[k] = sl;
+    ++k;
+    // rank rule: drop the oldest column while sigma_min / sigma_max < 1e-6
+    while (k > 0) {
+      double smin = 0, smax = 0;
+      sv_extremes(k, R, smin, smax);
+      if (smax > 0.0 && smin / smax >= 1e-6) break;
+      if ((rc = drop_oldest())) return rc;
+    }
+    // gamma = R^{-1} Q'r
+    for (int i = k - 1; i >= 0; --i) {
+      double acc = qr[i];
+      for (int j = i + 1; j < k; ++j) acc -= R[i][j] * gamma[j];
+      gamma[i] = acc / R[i][i];
+    }
+    ColMix<S> M;  // d = -r - sum_j gamma_j E_j, step = v + d
+    M.nin = k + 2;
+    M.nout = 2;
+    M.in[0] = r;
+    M.in[1] = v;
+    M.c[0][0] = -1.0;
+    M.c[1][0] = -1.0;
+    M.c[1][1] = 1.0;
+    for (int j = 0; j < k; ++j) {
+      M.in[2 + j] = E[ord[j]];
+      M.c[0][2 + j] = -gamma[j];
+      M.c[1][2 + j] = -gamma[j];
+    }
+    M.out[0] = d;
+    M.out[1] = step;
+    HIP_TRY(launch_colmix<S>(nv, M, st));
+    return SPOCK_OK;
+  }
+};
+
 template <typename S>
 int solve_impl(Problem& P, const double* x0, const spock_settings& s, S* vio, spock_info& info,
                hipStream_t st) {
@@ -908,9 +1169,24 @@ int solve_impl(Problem& P, const double* x0, const spock_settings& s, S* vio, sp
     HIP_TRY(hipMemcpyAsync(W.ring, &r0, sizeof(r0), hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
   }
+  // QR-updated least squares (memory up to kMaxMem), else the device Gram solve
+  const bool use_qr = s.anderson == SPOCK_AA_QR || (s.anderson == SPOCK_AA_AUTO && s.m > kAAMax);
+  QrAnderson<S> qa;
+  if (use_qr) {
+    qa.m = s.m;
+    qa.nv = nv;
+    qa.dots_dev = W.qrdots;
+    qa.part = W.vpart;
+    qa.st = st;
+    for (int j = 0; j < s.m; ++j) {
+      qa.E[j] = dV[j];
+      qa.Q[j] = dR[j];
+    }
+  }
   // r = v - Tv, the Anderson push and Gram solve, d, and spare = v + d for
   // the current iterate (stream-ordered after its T)
   auto prepare = [&]() -> int {
+    if (have_prev && use_qr) return qa.push_and_direction(v, vprev, Tv, rprev, rcur, dir, spare);
     if (have_prev) {
       HIP_TRY(launch_aa_push<S>(nv, v, vprev, Tv, rprev, rcur, dV[0], dR[0], sstride, W.rec, W.counters,
                                 W.next_tag(), W.aaG, W.ring, W.gamma, st));
@@ -922,12 +1198,15 @@ int solve_impl(Problem& P, const double* x0, const spock_settings& s, S* vio, sp
     }
     return SPOCK_OK;
   };
-  // T of the new iterate, its preparation queued behind it, then its statistics
+  // T of the new iterate, its preparation queued behind it, then its
+  // statistics (the QR step reads dot products, so it follows the wait)
   auto eval_next = [&]() -> int {
     unsigned long long ep = 0;
     int r = SV.launch(v, Tv, ep);
-    if (!r) r = prepare();
-    return r ? r : SV.wait(ep, Sc);
+    if (!r && !use_qr) r = prepare();
+    if (!r) r = SV.wait(ep, Sc);
+    if (!r && use_qr) r = prepare();
+    return r;
   };
   auto accept_prev = [&]() {
     std::swap(vprev, v);      // vprev <- old v
@@ -1013,6 +1292,9 @@ extern "C" int spock_solve(spock_problem* ph, const double* x0_dev, const spock_
   if (!ph || !x0_dev || !s || !v_io || !info) return SPOCK_EINVAL;
   if (s->method != SPOCK_METHOD_CP && s->method != SPOCK_METHOD_SPOCK) return SPOCK_EINVAL;
   if (s->method == SPOCK_METHOD_SPOCK && (s->m < 1 || s->m > kMaxMem)) return SPOCK_EINVAL;
+  if (s->anderson != SPOCK_AA_AUTO && s->anderson != SPOCK_AA_GRAM && s->anderson != SPOCK_AA_QR)
+    return SPOCK_EINVAL;
+  if (s->method == SPOCK_METHOD_SPOCK && s->anderson == SPOCK_AA_GRAM && s->m > kAAMax) return SPOCK_EINVAL;
   if (!(s->eps_abs >= 0 && s->eps_rel >= 0) || s->max_iters < 0 || s->max_ls < 1) return SPOCK_EINVAL;
   if (!(s->beta > 0 && s->beta < 1 && s->sigma > 0 && s->sigma < 1 && s->lambda > 0 && s->lambda < 2))
     return SPOCK_EINVAL;
@@ -1456,7 +1738,9 @@ extern "C" int spock_solve_batched(int32_t B, spock_problem* const* probs, const
                                    void* stream) {
   if (B < 1 || !probs || !x0 || !s || !v_io || !infos) return SPOCK_EINVAL;
   if (s->method != SPOCK_METHOD_CP && s->method != SPOCK_METHOD_SPOCK) return SPOCK_EINVAL;
-  if (s->method == SPOCK_METHOD_SPOCK && (s->m < 1 || s->m > kMaxMem)) return SPOCK_EINVAL;
+  // the batched engine keeps the Gram solve in the workgroup: memory up to kAAMax
+  if (s->method == SPOCK_METHOD_SPOCK && (s->m < 1 || s->m > kAAMax || s->anderson == SPOCK_AA_QR))
+    return SPOCK_EINVAL;
   if (!(s->eps_abs >= 0 && s->eps_rel >= 0) || s->max_iters < 0 || s->max_ls < 1) return SPOCK_EINVAL;
   if (!(s->beta > 0 && s->beta < 1 && s->sigma > 0 && s->sigma < 1 && s->lambda > 0 && s->lambda < 2))
     return SPOCK_EINVAL;

@@ -1509,6 +1509,32 @@ hipError_t launch_aa_dir(long long n, const S* r, const S* eb, long long stride,
   return hipGetLastError();
 }
 
+// Column mix for the QR-updated Anderson step: out_i = sum_j C[i][j] in_j
+// over the elements (i < nout, j < nin, both <= kMixMax). Every thread reads
+// all inputs of its elements before it writes, so outputs may alias inputs.
+template <typename S>
+__global__ void __launch_bounds__(256) k_colmix(long long n, ColMix<S> M) {
+  SPK_GRID_LOOP(e, 0, n) {
+    double x[kMixMax];
+#pragma unroll
+    for (int j = 0; j < kMixMax; ++j) x[j] = j < M.nin ? (double)M.in[j][e] : 0.0;
+#pragma unroll
+    for (int i = 0; i < kMixMax; ++i) {
+      if (i >= M.nout) break;
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 0; j < kMixMax; ++j) acc += j < M.nin ? M.c[i][j] * x[j] : 0.0;
+      M.out[i][e] = (S)acc;
+    }
+  }
+}
+template <typename S>
+hipError_t launch_colmix(long long n, const ColMix<S>& M, hipStream_t st) {
+  if (M.nin < 1 || M.nin > kMixMax || M.nout < 1 || M.nout > kMixMax) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_colmix<S>, dim3(dots_blocks(n)), dim3(256), 0, st, n, M);
+  return hipGetLastError();
+}
+
 #define SPK_INST(S)                                                                                \
   template hipError_t launch_lincomb<S>(long long, S*, double, const S*, double, const S*,         \
                                         hipStream_t);                                              \
@@ -1524,7 +1550,8 @@ hipError_t launch_aa_dir(long long n, const S* r, const S* eb, long long stride,
                                         S*, long long, unsigned long long*, unsigned*, unsigned,    \
                                         double*, AARingDev*, double*, hipStream_t);                 \
   template hipError_t launch_aa_dir<S>(long long, const S*, const S*, long long, const AARingDev*,  \
-                                       const double*, S*, const S*, S*, hipStream_t);
+                                       const double*, S*, const S*, S*, hipStream_t);              \
+  template hipError_t launch_colmix<S>(long long, const ColMix<S>&, hipStream_t);
 SPK_INST(double)
 SPK_INST(float)
 

@@ -235,6 +235,18 @@ hipError_t launch_aa_dir(long long n, const S* r, const S* eb, long long stride,
                          const double* gamma_dev, S* d, const S* base, S* step, hipStream_t st);
 template <typename S>
 hipError_t launch_fill(long long n, S* out, double val, hipStream_t st);
+// out_i = sum_j c[i][j] in_j, elementwise over n (outputs may alias inputs);
+// the vector operations of the QR-updated Anderson step
+constexpr int kMixMax = 12;
+template <typename S>
+struct ColMix {
+  int nin = 0, nout = 0;
+  const S* in[kMixMax] = {};
+  S* out[kMixMax] = {};
+  double c[kMixMax][kMixMax] = {};
+};
+template <typename S>
+hipError_t launch_colmix(long long n, const ColMix<S>& M, hipStream_t st);
 // <v - Tv, w> to *out_dev (fixed-order sum in the last workgroup to finish,
 // counted on *counter, over tagged records as for the push), then the
 // statistics stats[0..8) published to pub.

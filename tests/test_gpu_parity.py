@@ -473,3 +473,48 @@ def test_flow_form_solve_config1(method, monkeypatch):
     info = gp.solve(x0, v, SP.default_settings(eps_abs=1e-9, eps_rel=1e-9, method=method))
     assert info["status"] == "converged" and info["mapping"] == 512
     assert abs(info["V_s0"] - ref.V_s0) <= 1e-6 * max(1, abs(ref.V_s0))
+
+
+# ---------------------------------------------------------------- QR-updated Anderson step
+@pytest.mark.parametrize("m", [2, 3, 5, 10])
+@pytest.mark.parametrize("name", ["config1", "b3-1-2"])
+def test_spock_qr_anderson_matches_oracle_step_by_step(name, m):
+    # the least squares of the Anderson step through a QR factorisation
+    # updated at every push (memory up to 10): the same decisions, backtracks
+    # and iterate as the oracle (SVD least squares) over 60 iterations
+    inst = CASES[name]
+    gp, op = build(inst)
+    ref = O.spock_solve(op, inst.x0, O.Settings(eps_abs=1e-12, eps_rel=1e-12, max_iters=60, m=m))
+    x0 = dev(inst.x0, torch.float64)
+    v = torch.zeros(gp.n_v, dtype=torch.float64, device="cuda")
+    info = gp.solve(x0, v, SP.default_settings(eps_abs=1e-12, eps_rel=1e-12, max_iters=60, m=m, anderson="qr"))
+    c = ref.counts
+    got = (info["iters"], info["n_k0"], info["n_k1"], info["n_k2"], info["n_km"], info["n_backtracks"])
+    want = (ref.iters, c["K0"], c["K1"], c["K2"], c["KM"], c["backtracks"])
+    assert got == want
+    assert abs(info["xi"] - ref.xi) <= 1e-8 * ref.xi
+    check(f"qr_aa_iterate:{name}:{m}", np.max(np.abs(host(v) - ref.v)) / max(1.0, np.max(np.abs(ref.v))), 1e-9)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_spock_qr_anderson_memory_10_converges_to_reference(prec):
+    inst = CASES["config5"]
+    ref = _golden("config5_spock_1e-8")
+    gp, op = build(inst, FP[prec][0], alpha=ref["alpha"])
+    x0 = dev(inst.x0, torch.float64)
+    v = torch.zeros(gp.n_v, dtype=gp.torch_dtype, device="cuda")
+    e = 1e-8 if prec == "fp64" else 1e-5
+    info = gp.solve(x0, v, SP.default_settings(eps_abs=e, eps_rel=e, max_iters=400000, m=10, compute_nested=1))
+    assert info["status"] == "converged", info
+    check(f"qr_aa_m10_V:{prec}", abs(info["V_nested"] - ref["V_nested"]) / max(1, abs(ref["V_nested"])), 1e-4)
+
+
+def test_anderson_settings_rejected():
+    inst = CASES["config1"]
+    gp, _ = build(inst)
+    x0 = dev(inst.x0, torch.float64)
+    v = torch.zeros(gp.n_v, dtype=torch.float64, device="cuda")
+    for kw in ({"m": 11}, {"m": 5, "anderson": "gram"}, {"anderson": 7}):
+        with pytest.raises(SP.SpockError) as e:
+            gp.solve(x0, v, SP.default_settings(**kw))
+        assert e.value.code == -1
