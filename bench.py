@@ -25,10 +25,15 @@ The same JSON line carries the other legs of the metric, each measured:
   time_to_residual_512batch 512 uneven trees from perturbed warm starts:
                             batched FP32 and FP64 launches against the plain
                             FP64 path solving every instance one by one
+  fp32_error_vs_oracle      FP32 bulk against stored oracle solutions (V*, u^0)
+                            and its residual floor
   datacentre_cp_vs_spock    the paper's section-6 comparison (N 7, n_x 5,
                             eps 1e-5): T evaluations of CP and SPOCK on the GPU
   datacentre_scaling        the paper's open-loop series (n_x = n_u = 50,
                             N = 3..15, eps 1e-3), SPOCK in FP32 and FP64
+  datacentre_closed_loop_mpc the paper's closed-loop simulation (N 10,
+                            n_x = n_u = 20, 20 steps, 15 realisations), warm
+                            against cold starts
 """
 from __future__ import annotations
 
@@ -253,7 +258,7 @@ def ttr_batched(torch, SP, G):
     s = SP.default_settings(max_iters=200000)
     res = {}
     for name, probs, dt in (("fp32", p32, torch.float32), ("fp64", p64, torch.float64)):
-        vb = [w.to(dt) for w in warm]
+        vb = [w.to(dt, copy=True) for w in warm]  # the solves overwrite their starts
         SP.solve_batched(probs, x0s, [x.clone() for x in vb], SP.default_settings(max_iters=5))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -270,6 +275,9 @@ def ttr_batched(torch, SP, G):
         iters_plain.append(info["iters"])
         infos_plain.append(info)
     log(f"plain FP64 all 512 {t_plain:.3f}s")
+    # reference values: batched FP64 solved to 1e-8 from the same warm starts
+    vt = [w.clone() for w in warm]
+    tight = SP.solve_batched(p64, x0s, vt, SP.default_settings(eps_abs=1e-8, eps_rel=1e-8, max_iters=200000))
     i32, i64 = res["fp32"][1], res["fp64"][1]
     rel = lambda a, b: abs(a["V_s0"] - b["V_s0"]) / max(1.0, abs(b["V_s0"]))  # noqa: E731
     return {"workload": "512 uneven trees nx10 nu5 N 5..12 (warm start, sigma 0.05)",
@@ -281,10 +289,72 @@ def ttr_batched(torch, SP, G):
             "plain_fp64_seconds": round(t_plain, 3),
             "plain_fp64_iters_median_max": [int(np.median(iters_plain)), max(iters_plain)],
             "plain_fp64_converged": sum(i["status"] == "converged" for i in infos_plain),
-            "V_max_rel_diff_batched_fp32_vs_plain_fp64": max(rel(a, b) for a, b in zip(i32, infos_plain)),
-            "V_max_rel_diff_batched_fp64_vs_plain_fp64": max(rel(a, b) for a, b in zip(i64, infos_plain)),
+            "V_max_rel_err_batched_fp32_vs_fp64_1e-8": max(rel(a, b) for a, b in zip(i32, tight)),
+            "V_max_rel_err_batched_fp64_vs_fp64_1e-8": max(rel(a, b) for a, b in zip(i64, tight)),
+            "V_max_rel_err_plain_fp64_vs_fp64_1e-8": max(rel(a, b) for a, b in zip(infos_plain, tight)),
             "speedup_batched_fp32_vs_plain_fp64": round(t_plain / res["fp32"][0], 2),
             "speedup_batched_fp64_vs_plain_fp64": round(t_plain / res["fp64"][0], 2)}
+
+
+def _golden():
+    path = os.path.join(ROOT, "tests", "golden", "oracle_refs.json")
+    return json.load(open(path)) if os.path.exists(path) else {}
+
+
+def leg_fp32_error(torch, SP, G):
+    """FP32 bulk against the FP64 oracle per result (stored oracle solutions,
+    tests/golden): V* and u^0 of the 223-node tree and of three of the 512
+    trees, each solved in FP32 to 1e-5; and the FP32 residual floor: the
+    smallest xi an FP32 solve reaches when asked for 1e-9 (223-node tree;
+    the 512 trees in one batched launch)."""
+    refs = _golden()
+    out = {}
+    rel = lambda a, b: abs(a - b) / max(1.0, abs(b))  # noqa: E731
+
+    def u0_of(v, inst):
+        h = v.detach().double().cpu().numpy()
+        off = 1 + inst.num_nodes * inst.nx
+        return h[off: off + inst.nu]
+    key2 = "config2_spock_1e-7" if "config2_spock_1e-7" in refs else "config2_spock_1e-5"
+    inst = G.make_config(2)
+    x0 = torch.as_tensor(inst.x0, dtype=torch.float64, device="cuda")
+    gp = SP.Problem.from_instance(inst, precision=SP.FP32, alpha=refs[key2]["alpha"])
+    v = torch.zeros(gp.n_v, dtype=torch.float32, device="cuda")
+    info = gp.solve(x0, v, SP.default_settings(eps_abs=1e-5, eps_rel=1e-5, max_iters=400000, compute_nested=1))
+    u0r = np.array(refs[key2]["u0"])
+    out["tree223"] = {"reference": key2, "status": info["status"],
+                      "V_rel_err": rel(info["V_nested"], refs[key2]["V_nested"]),
+                      "u0_rel_err": float(np.max(np.abs(u0_of(v, inst) - u0r)) / max(1.0, np.max(np.abs(u0r))))}
+    v.zero_()
+    info = gp.solve(x0, v, SP.default_settings(eps_abs=1e-9, eps_rel=1e-9, max_iters=40000))
+    out["tree223"]["fp32_floor_xi"] = info["xi"]
+    out["tree223"]["fp32_floor_iters"] = info["iters"]
+    insts = G.make_batch(4, count=8)
+    rows = {}
+    for b in (2, 5, 7):
+        key = f"config4_b{b}_spock_1e-6"
+        if key not in refs:
+            continue
+        gpb = SP.Problem.from_instance(insts[b], precision=SP.FP32, alpha=refs[key]["alpha"])
+        xb = torch.as_tensor(insts[b].x0, dtype=torch.float64, device="cuda")
+        vb = torch.zeros(gpb.n_v, dtype=torch.float32, device="cuda")
+        ib = gpb.solve(xb, vb, SP.default_settings(eps_abs=1e-5, eps_rel=1e-5, max_iters=400000,
+                                                   compute_nested=1))
+        u0r = np.array(refs[key]["u0"])
+        rows[b] = {"V_rel_err": rel(ib["V_nested"], refs[key]["V_nested"]),
+                   "u0_rel_err": float(np.max(np.abs(u0_of(vb, insts[b]) - u0r)) / max(1.0, np.max(np.abs(u0r))))}
+    out["trees512_sample"] = rows
+    # floor of the batch: FP32 batched launch asked for 1e-9 from v = 0
+    insts = G.make_batch(4, count=512)
+    p32 = [SP.Problem.from_instance(i, precision=SP.FP32) for i in insts]
+    x0s = [torch.as_tensor(i.x0, dtype=torch.float64, device="cuda") for i in insts]
+    vs = [torch.zeros(p.n_v, dtype=torch.float32, device="cuda") for p in p32]
+    infos = SP.solve_batched(p32, x0s, vs, SP.default_settings(eps_abs=1e-9, eps_rel=1e-9, max_iters=4000))
+    xs = np.array([i["xi"] for i in infos])
+    out["trees512_fp32_floor_xi"] = {"median": float(np.median(xs)), "p90": float(np.percentile(xs, 90)),
+                                     "max": float(xs.max()), "iteration_cap": 4000}
+    log(f"FP32 errors: {out}")
+    return out
 
 
 def leg_datacentre(torch, SP, G):
@@ -303,6 +373,15 @@ def leg_datacentre(torch, SP, G):
         out[method] = {"t_evals": info["t_evals"], "iters": info["iters"], "seconds": round(sec, 4),
                        "status": info["status"], "V_s0": info["V_s0"]}
     out["t_evals_ratio_cp_over_spock"] = round(out["cp"]["t_evals"] / out["spock"]["t_evals"], 3)
+    # Anderson memory within the paper's range (3 to 10; QR-updated above 4)
+    out["spock_by_memory"] = {}
+    for m in (1, 3, 5, 10):
+        v = torch.zeros(gp.n_v, dtype=torch.float64, device="cuda")
+        sec, info = timed_solve(torch, gp, x0, v, SP.default_settings(eps_abs=1e-5, eps_rel=1e-5,
+                                                                      max_iters=200000, m=m))
+        out["spock_by_memory"][m] = {"t_evals": info["t_evals"], "iters": info["iters"],
+                                     "k2_share": round(info["n_k2"] / max(1, info["iters"]), 3),
+                                     "seconds": round(sec, 4), "status": info["status"]}
     log(f"datacentre N7: CP {out['cp']['t_evals']} vs SPOCK {out['spock']['t_evals']} T evaluations")
     return out
 
@@ -335,6 +414,29 @@ def leg_scaling(torch, SP, G, horizons):
     return out
 
 
+def leg_mpc(torch, SP, G, steps=20, realisations=15):
+    """Section 6 closed-loop simulation: data-centre model N 10,
+    n_x = n_u = 20 (2047 nodes), x0 = 0.1 * 1, eps 1e-3, 20 steps for 15
+    seeded realisations of the disturbance (branch w = 2 with probability
+    0.7), all realisations in one batched launch per step; warm starts from
+    the previous step's solution against cold starts."""
+    from paper_2212_01110_amd.mpc import closed_loop
+    inst = G.make_datacentre(10, 20)
+    out = {"workload": "data-centre model N10 nx=nu=20 (2047 nodes), eps 1e-3, "
+                       f"{steps} steps x {realisations} realisations, FP64, batched per step"}
+    gp = SP.Problem.from_instance(inst, precision=SP.FP64)
+    branches = (np.random.default_rng(2023).random((realisations, steps)) < 0.7).astype(int)
+    s = SP.default_settings(eps_abs=1e-3, eps_rel=1e-3, max_iters=200000)
+    for name, warm in (("warm", True), ("cold", False)):
+        res = closed_loop(gp, inst.A[1:3], inst.B[1:3], inst.x0, branches, s, warm=warm)
+        out[name] = {"seconds_per_step": [round(x, 4) for x in res["step_seconds"]],
+                     "mean_t_evals_per_step": [round(float(x), 1) for x in res["t_evals"].mean(axis=0)],
+                     "total_seconds": round(float(res["step_seconds"].sum()), 3),
+                     "all_converged": all(st == "converged" for row in res["status"] for st in row)}
+        log(f"mpc {name}: {out[name]['total_seconds']}s, T evals per step {out[name]['mean_t_evals_per_step'][:4]}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -349,7 +451,7 @@ def main():
     ap.add_argument("--horizons", default="3,6,9,12,15")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--legs", default="fp64,budget,223,512,datacentre,scaling",
+    ap.add_argument("--legs", default="fp64,budget,223,512,fp32err,datacentre,scaling,mpc",
                     help="comma-separated extra legs to run (see the module docstring)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of 512 MiB (reference for the memory-traffic counters)")
@@ -421,8 +523,12 @@ def main():
         extras["time_to_residual_223node"] = ttr_single(torch, SP, G)
     if "512" in legs:
         extras["time_to_residual_512batch"] = ttr_batched(torch, SP, G)
+    if "fp32err" in legs:
+        extras["fp32_error_vs_oracle"] = leg_fp32_error(torch, SP, G)
     if "datacentre" in legs:
         extras["datacentre_cp_vs_spock"] = leg_datacentre(torch, SP, G)
+    if "mpc" in legs:
+        extras["datacentre_closed_loop_mpc"] = leg_mpc(torch, SP, G)
     if "scaling" in legs:
         extras["datacentre_scaling"] = leg_scaling(torch, SP, G, [int(n) for n in args.horizons.split(",")])
     cpu = None
