@@ -274,10 +274,17 @@ def ttr_batched(torch, SP, G):
         t_plain += sec
         iters_plain.append(info["iters"])
         infos_plain.append(info)
+        if b % 128 == 127:
+            log(f"plain FP64: {b + 1} of 512 instances, {t_plain:.2f}s")
     log(f"plain FP64 all 512 {t_plain:.3f}s")
-    # reference values: batched FP64 solved to 1e-8 from the same warm starts
-    vt = [w.clone() for w in warm]
-    tight = SP.solve_batched(p64, x0s, vt, SP.default_settings(eps_abs=1e-8, eps_rel=1e-8, max_iters=200000))
+    # reference values on a sample of 32 instances: plain FP64 solved to 1e-8
+    sample = np.linspace(0, 511, 32).astype(int)
+    tight = {}
+    for k, b in enumerate(sample):
+        tight[b] = p64[b].solve(x0s[b], warm[b].clone(), SP.default_settings(eps_abs=1e-8, eps_rel=1e-8,
+                                                                             max_iters=200000))
+        if k % 8 == 7:
+            log(f"512-batch FP64 references to 1e-8: {k + 1} of 32")
     i32, i64 = res["fp32"][1], res["fp64"][1]
     rel = lambda a, b: abs(a["V_s0"] - b["V_s0"]) / max(1.0, abs(b["V_s0"]))  # noqa: E731
     return {"workload": "512 uneven trees nx10 nu5 N 5..12 (warm start, sigma 0.05)",
@@ -289,9 +296,10 @@ def ttr_batched(torch, SP, G):
             "plain_fp64_seconds": round(t_plain, 3),
             "plain_fp64_iters_median_max": [int(np.median(iters_plain)), max(iters_plain)],
             "plain_fp64_converged": sum(i["status"] == "converged" for i in infos_plain),
-            "V_max_rel_err_batched_fp32_vs_fp64_1e-8": max(rel(a, b) for a, b in zip(i32, tight)),
-            "V_max_rel_err_batched_fp64_vs_fp64_1e-8": max(rel(a, b) for a, b in zip(i64, tight)),
-            "V_max_rel_err_plain_fp64_vs_fp64_1e-8": max(rel(a, b) for a, b in zip(infos_plain, tight)),
+            "V_rel_err_reference": "32 of the 512 instances (evenly spaced) solved by the plain FP64 path to 1e-8",
+            "V_max_rel_err_batched_fp32": max(rel(i32[b], tight[b]) for b in sample),
+            "V_max_rel_err_batched_fp64": max(rel(i64[b], tight[b]) for b in sample),
+            "V_max_rel_err_plain_fp64": max(rel(infos_plain[b], tight[b]) for b in sample),
             "speedup_batched_fp32_vs_plain_fp64": round(t_plain / res["fp32"][0], 2),
             "speedup_batched_fp64_vs_plain_fp64": round(t_plain / res["fp64"][0], 2)}
 
@@ -428,7 +436,8 @@ def leg_mpc(torch, SP, G, steps=20, realisations=15):
     branches = (np.random.default_rng(2023).random((realisations, steps)) < 0.7).astype(int)
     s = SP.default_settings(eps_abs=1e-3, eps_rel=1e-3, max_iters=200000)
     for name, warm in (("warm", True), ("cold", False)):
-        res = closed_loop(gp, inst.A[1:3], inst.B[1:3], inst.x0, branches, s, warm=warm)
+        res = closed_loop(gp, inst.A[1:3], inst.B[1:3], inst.x0, branches, s, warm=warm,
+                          progress=lambda t, sec: log(f"mpc {name} step {t}: {sec:.3f}s"))
         out[name] = {"seconds_per_step": [round(x, 4) for x in res["step_seconds"]],
                      "mean_t_evals_per_step": [round(float(x), 1) for x in res["t_evals"].mean(axis=0)],
                      "total_seconds": round(float(res["step_seconds"].sum()), 3),

@@ -1,5 +1,15 @@
 """Canonical ordering of the primal vector z and the dual vector eta.
 
+General problems (section 4.3 conic risk, section 4.1 constraints): when the
+instance carries `risk` (per nonleaf node i: E^i [ny, n_i], F^i [ny, nnu],
+b^i [ny] and kpos^i, the number of leading rows of the cone K = R^kpos_+ x
+{0}) the block y^i has ny^i entries; when it carries `cons` (Gamma_x
+[nn, nc, nx], Gamma_u [nn, nc, nu], bounds cmin, cmax [nn, nc] at nonleaf
+nodes and Gamma_N [nn, ncN, nx], cNmin, cNmax at leaves) the constraint rows
+of eta are Gamma_x x + Gamma_u u and Gamma_N x. Without them: AV@R_a
+(ny = 2 n + 1, E = [a I, -I, 1]', b = (p, 0, 1), kpos = 2 n) and boxes
+(Gamma = identity).
+
 Follows section 5.2 ("Operator splitting"):
   z   = (s^0, z_1, z_2), z_1 = ((x^i) over all nodes, (u^i) over nonleaf nodes),
         z_2 = (y^i, tau^{[i]}, s^{[i]}) per nonleaf node i, where tau^{[i]} and
@@ -41,6 +51,13 @@ class Layout:
                 raise ValueError("every leaf must sit at the last stage")
         self.stage_nodes = [[i for i in range(nn) if self.stage[i] == t]
                             for t in range(self.N + 1)]
+        self.risk = getattr(inst, "risk", None)
+        self.cons = getattr(inst, "cons", None)
+        self.ny = np.zeros(nn, dtype=np.int64)
+        for i in self.nonleaf:
+            self.ny[i] = (len(self.risk.b[i]) if self.risk is not None else 2 * len(self.children[i]) + 1)
+        self.nc = self.cons.Gx.shape[1] if self.cons is not None else nx + nu
+        self.ncN = self.cons.GN.shape[1] if self.cons is not None else nx
         prob = np.asarray(inst.prob, dtype=float)
         # conditional probability of a child given its ancestor (the pi used
         # by the risk measure of the ancestor's node, section 4.4)
@@ -64,9 +81,8 @@ class Layout:
         self.y_off = np.full(nn, -1, dtype=np.int64)
         self.tau_off = np.full(nn, -1, dtype=np.int64)
         for i in self.nonleaf:
-            n = len(self.children[i])
             self.y_off[i] = off
-            off += 2 * n + 1
+            off += self.ny[i]
             for c in self.children[i]:
                 self.tau_off[c] = off
                 off += 1
@@ -79,18 +95,17 @@ class Layout:
         off = 0
         self.e1y = np.full(nn, -1, dtype=np.int64)
         self.e1s = np.full(nn, -1, dtype=np.int64)
-        self.e1x = np.full(nn, -1, dtype=np.int64)
-        self.e1u = np.full(nn, -1, dtype=np.int64)
+        self.e1c = np.full(nn, -1, dtype=np.int64)
         for i in self.nonleaf:
-            n = len(self.children[i])
             self.e1y[i] = off
-            off += 2 * n + 1
+            off += self.ny[i]
             self.e1s[i] = off
             off += 1
-            self.e1x[i] = off
-            off += nx
-            self.e1u[i] = off
-            off += nu
+            self.e1c[i] = off
+            off += self.nc
+        # with boxes the constraint rows are (x^i, u^i)
+        self.e1x = self.e1c
+        self.e1u = np.where(self.e1c >= 0, self.e1c + nx, -1)
         self.e2x = np.full(nn, -1, dtype=np.int64)
         self.e2u = np.full(nn, -1, dtype=np.int64)
         self.e2a = np.full(nn, -1, dtype=np.int64)
@@ -109,8 +124,8 @@ class Layout:
         self.e3a = np.full(nn, -1, dtype=np.int64)
         self.e3b = np.full(nn, -1, dtype=np.int64)
         for j in self.leaves:
-            self.e3x[j] = off
-            off += nx
+            self.e3x[j] = off              # constraint rows (x^j itself with boxes)
+            off += self.ncN
             self.e3q[j] = off
             off += nx
             self.e3a[j] = off
@@ -120,13 +135,52 @@ class Layout:
         self.n_eta = off
         self.n_v = self.n_z + self.n_eta
 
-    # ---- small helpers ----
+    # ---- the conic risk of each nonleaf node (section 4.3)
     def b_vector(self, i):
-        """b^i = (pi, 0_n, 1) of the AV@R conic form (section 4.3), with pi the
-        conditional probabilities of the children of i."""
+        """b^i; for AV@R (pi, 0_n, 1), pi the conditional probabilities of
+        the children of i."""
+        if self.risk is not None:
+            return np.asarray(self.risk.b[i], float)
         ch = self.children[i]
         n = len(ch)
         return np.concatenate([self.p[ch], np.zeros(n), [1.0]])
+
+    def E_matrix(self, i, a_risk=None):
+        """E^i [ny, n_i]; for AV@R_a [a I; -I; 1']."""
+        if self.risk is not None:
+            return np.asarray(self.risk.E[i], float)
+        n = len(self.children[i])
+        return np.vstack([a_risk * np.eye(n), -np.eye(n), np.ones((1, n))])
+
+    def F_matrix(self, i):
+        """F^i [ny, nnu]; empty for AV@R."""
+        if self.risk is not None:
+            return np.asarray(self.risk.F[i], float).reshape(self.ny[i], -1)
+        return np.zeros((self.ny[i], 0))
+
+    def kpos(self, i):
+        """rows of y^i in the nonnegative part of K* (the rest are free)."""
+        if self.risk is not None:
+            return int(self.risk.kpos[i])
+        return 2 * len(self.children[i])
+
+    # ---- constraint rows (section 4.1)
+    def gamma(self, inst, i):
+        """(Gamma_x, Gamma_u, cmin, cmax) of nonleaf i."""
+        if self.cons is not None:
+            c = self.cons
+            return c.Gx[i], c.Gu[i], c.cmin[i], c.cmax[i]
+        nx, nu = self.nx, self.nu
+        Gx = np.vstack([np.eye(nx), np.zeros((nu, nx))])
+        Gu = np.vstack([np.zeros((nx, nu)), np.eye(nu)])
+        return Gx, Gu, np.concatenate([inst.xmin[i], inst.umin[i]]), np.concatenate([inst.xmax[i], inst.umax[i]])
+
+    def gamma_N(self, inst, j):
+        """(Gamma_N, cmin, cmax) of leaf j."""
+        if self.cons is not None:
+            c = self.cons
+            return c.GN[j], c.cNmin[j], c.cNmax[j]
+        return np.eye(self.nx), inst.xmin[j], inst.xmax[j]
 
     def split(self, v):
         return v[: self.n_z], v[self.n_z:]

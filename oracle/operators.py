@@ -16,12 +16,13 @@ def L_apply(lay: Layout, inst, z: np.ndarray) -> np.ndarray:
     nx, nu = lay.nx, lay.nu
     eta = np.zeros(lay.n_eta)
     for i in lay.nonleaf:
-        n = len(lay.children[i])
-        y = z[lay.y_off[i]: lay.y_off[i] + 2 * n + 1]
-        eta[lay.e1y[i]: lay.e1y[i] + 2 * n + 1] = y
+        ny = lay.ny[i]
+        y = z[lay.y_off[i]: lay.y_off[i] + ny]
+        eta[lay.e1y[i]: lay.e1y[i] + ny] = y
         eta[lay.e1s[i]] = z[lay.s_off[i]] - lay.b_vector(i) @ y
-        eta[lay.e1x[i]: lay.e1x[i] + nx] = z[lay.x_off[i]: lay.x_off[i] + nx]
-        eta[lay.e1u[i]: lay.e1u[i] + nu] = z[lay.u_off[i]: lay.u_off[i] + nu]
+        Gx, Gu, _, _ = lay.gamma(inst, i)
+        eta[lay.e1c[i]: lay.e1c[i] + lay.nc] = (Gx @ z[lay.x_off[i]: lay.x_off[i] + nx]
+                                                + Gu @ z[lay.u_off[i]: lay.u_off[i] + nu])
     for c in range(1, lay.num_nodes):
         i = lay.anc[c]
         eta[lay.e2x[c]: lay.e2x[c] + nx] = np.sqrt(inst.q[c]) * z[lay.x_off[i]: lay.x_off[i] + nx]
@@ -30,7 +31,7 @@ def L_apply(lay: Layout, inst, z: np.ndarray) -> np.ndarray:
         eta[lay.e2b[c]] = 0.5 * z[lay.tau_off[c]]
     for j in lay.leaves:
         xj = z[lay.x_off[j]: lay.x_off[j] + nx]
-        eta[lay.e3x[j]: lay.e3x[j] + nx] = xj
+        eta[lay.e3x[j]: lay.e3x[j] + lay.ncN] = lay.gamma_N(inst, j)[0] @ xj
         eta[lay.e3q[j]: lay.e3q[j] + nx] = np.sqrt(inst.qN[j]) * xj
         eta[lay.e3a[j]] = 0.5 * z[lay.s_off[j]]
         eta[lay.e3b[j]] = 0.5 * z[lay.s_off[j]]
@@ -41,20 +42,22 @@ def Lt_apply(lay: Layout, inst, eta: np.ndarray) -> np.ndarray:
     nx, nu = lay.nx, lay.nu
     z = np.zeros(lay.n_z)
     for i in lay.nonleaf:
-        n = len(lay.children[i])
-        e_y = eta[lay.e1y[i]: lay.e1y[i] + 2 * n + 1]
+        ny = lay.ny[i]
+        e_y = eta[lay.e1y[i]: lay.e1y[i] + ny]
         e_s = eta[lay.e1s[i]]
-        z[lay.y_off[i]: lay.y_off[i] + 2 * n + 1] += e_y - lay.b_vector(i) * e_s
+        z[lay.y_off[i]: lay.y_off[i] + ny] += e_y - lay.b_vector(i) * e_s
         z[lay.s_off[i]] += e_s
-        z[lay.x_off[i]: lay.x_off[i] + nx] += eta[lay.e1x[i]: lay.e1x[i] + nx]
-        z[lay.u_off[i]: lay.u_off[i] + nu] += eta[lay.e1u[i]: lay.e1u[i] + nu]
+        Gx, Gu, _, _ = lay.gamma(inst, i)
+        e_c = eta[lay.e1c[i]: lay.e1c[i] + lay.nc]
+        z[lay.x_off[i]: lay.x_off[i] + nx] += Gx.T @ e_c
+        z[lay.u_off[i]: lay.u_off[i] + nu] += Gu.T @ e_c
     for c in range(1, lay.num_nodes):
         i = lay.anc[c]
         z[lay.x_off[i]: lay.x_off[i] + nx] += np.sqrt(inst.q[c]) * eta[lay.e2x[c]: lay.e2x[c] + nx]
         z[lay.u_off[i]: lay.u_off[i] + nu] += np.sqrt(inst.r[c]) * eta[lay.e2u[c]: lay.e2u[c] + nu]
         z[lay.tau_off[c]] += 0.5 * (eta[lay.e2a[c]] + eta[lay.e2b[c]])
     for j in lay.leaves:
-        z[lay.x_off[j]: lay.x_off[j] + nx] += (eta[lay.e3x[j]: lay.e3x[j] + nx]
+        z[lay.x_off[j]: lay.x_off[j] + nx] += (lay.gamma_N(inst, j)[0].T @ eta[lay.e3x[j]: lay.e3x[j] + lay.ncN]
                                              + np.sqrt(inst.qN[j]) * eta[lay.e3q[j]: lay.e3q[j] + nx])
         z[lay.s_off[j]] += 0.5 * (eta[lay.e3a[j]] + eta[lay.e3b[j]])
     return z
@@ -80,7 +83,7 @@ def _block_columns(lay: Layout):
         n = len(lay.children[i])
         groups.append(list(range(lay.x_off[i], lay.x_off[i] + nx))
                       + list(range(lay.u_off[i], lay.u_off[i] + nu)))
-        groups.append(list(range(lay.y_off[i], lay.y_off[i] + 2 * n + 1)) + [lay.s_off[i]])
+        groups.append(list(range(lay.y_off[i], lay.y_off[i] + lay.ny[i])) + [lay.s_off[i]])
         for c in lay.children[i]:
             groups.append([lay.tau_off[c]])
     for j in lay.leaves:

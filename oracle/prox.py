@@ -70,17 +70,21 @@ def proj_S1(lay: Layout, inst, fac, xbar: np.ndarray, ubar: np.ndarray, x0: np.n
 
 # ---------------------------------------------------------------- S2
 def s2_matrix(lay: Layout, inst, i):
-    """[E' -I -I] of S2^i (section 5.2; F is empty for AV@R, section 4.3):
-    E' y = a y_1 - y_2 + y_3 1, acting on (y, tau^{[i]}, s^{[i]})."""
+    """[E' -I -I; F' 0 0] of S2^i (section 5.2), acting on (y, tau^{[i]},
+    s^{[i]}); for AV@R F is empty and E' y = a y_1 - y_2 + y_3 1."""
     n = len(lay.children[i])
-    a = inst.a_risk[i]
-    Et = np.hstack([a * np.eye(n), -np.eye(n), np.ones((n, 1))])
-    return np.hstack([Et, -np.eye(n), -np.eye(n)])
+    E = lay.E_matrix(i, inst.a_risk[i])
+    F = lay.F_matrix(i)
+    top = np.hstack([E.T, -np.eye(n), -np.eye(n)])
+    if F.shape[1] == 0:
+        return top
+    return np.vstack([top, np.hstack([F.T, np.zeros((F.shape[1], 2 * n))])])
 
 
 def proj_S2_block(G: np.ndarray, w: np.ndarray) -> np.ndarray:
-    """Projection of w on ker G: w - G' (G G')^{-1} G w."""
-    return w - G.T @ np.linalg.solve(G @ G.T, G @ w)
+    """Projection of w on ker G: w - G' (G G')^+ G w (least squares, so that
+    dependent rows of G are allowed)."""
+    return w - G.T @ np.linalg.lstsq(G @ G.T, G @ w, rcond=None)[0]
 
 
 def proj_S2(lay: Layout, inst, z: np.ndarray) -> np.ndarray:
@@ -93,9 +97,8 @@ def proj_S2(lay: Layout, inst, z: np.ndarray) -> np.ndarray:
 
 
 def s2_indices(lay: Layout, i):
-    n = len(lay.children[i])
     ch = lay.children[i]
-    return np.concatenate([np.arange(lay.y_off[i], lay.y_off[i] + 2 * n + 1),
+    return np.concatenate([np.arange(lay.y_off[i], lay.y_off[i] + lay.ny[i]),
                            lay.tau_off[ch], lay.s_off[ch]]).astype(np.int64)
 
 
@@ -139,26 +142,27 @@ def _proj_translated_soc(v: np.ndarray) -> np.ndarray:
 
 
 def proj_S3(lay: Layout, inst, w: np.ndarray) -> np.ndarray:
-    """Projection on S3 (eq. S3-def), with K* = R^{2n}_+ x R (the dual of
-    R^{2n}_+ x {0}), C^i the state/input box and C^j the terminal state box."""
-    nx, nu = lay.nx, lay.nu
+    """Projection on S3 (eq. S3-def): y^i on K* = R^kpos_+ x R^{ny - kpos}
+    (the dual of R^kpos_+ x {0}; for AV@R kpos = 2n), s^i - b'y^i on R_+, the
+    constraint rows on C^i = [cmin, cmax] (the state/input box when Gamma is
+    the identity), the SOC blocks, and the leaves' rows on C_N^j."""
     p = np.zeros_like(w)
     for i in lay.nonleaf:
-        n = len(lay.children[i])
-        y = w[lay.e1y[i]: lay.e1y[i] + 2 * n + 1]
-        p[lay.e1y[i]: lay.e1y[i] + 2 * n] = np.maximum(y[:2 * n], 0.0)
-        p[lay.e1y[i] + 2 * n] = y[2 * n]
+        ny, kp = lay.ny[i], lay.kpos(i)
+        y = w[lay.e1y[i]: lay.e1y[i] + ny]
+        p[lay.e1y[i]: lay.e1y[i] + kp] = np.maximum(y[:kp], 0.0)
+        p[lay.e1y[i] + kp: lay.e1y[i] + ny] = y[kp:]
         p[lay.e1s[i]] = max(w[lay.e1s[i]], 0.0)
-        sl = slice(lay.e1x[i], lay.e1x[i] + nx)
-        p[sl] = np.clip(w[sl], inst.xmin[i], inst.xmax[i])
-        sl = slice(lay.e1u[i], lay.e1u[i] + nu)
-        p[sl] = np.clip(w[sl], inst.umin[i], inst.umax[i])
+        _, _, cmin, cmax = lay.gamma(inst, i)
+        sl = slice(lay.e1c[i], lay.e1c[i] + lay.nc)
+        p[sl] = np.clip(w[sl], cmin, cmax)
     for c in range(1, lay.num_nodes):
         sl = slice(lay.e2x[c], lay.e2b[c] + 1)
         p[sl] = _proj_translated_soc(w[sl])
     for j in lay.leaves:
-        sl = slice(lay.e3x[j], lay.e3x[j] + nx)
-        p[sl] = np.clip(w[sl], inst.xmin[j], inst.xmax[j])
+        _, cmin, cmax = lay.gamma_N(inst, j)
+        sl = slice(lay.e3x[j], lay.e3x[j] + lay.ncN)
+        p[sl] = np.clip(w[sl], cmin, cmax)
         sl = slice(lay.e3q[j], lay.e3b[j] + 1)
         p[sl] = _proj_translated_soc(w[sl])
     return p

@@ -1,5 +1,5 @@
-"""AV@R and the exact nested risk-averse cost of a policy (section 4.2 and
-eq. original-problem).
+"""AV@R, general conic risk measures and the nested risk-averse cost of a
+policy (sections 4.2, 4.3 and eq. original-problem).
 
 AV@R_a[Z] = min_t { t + (1/a) E^p[Z - t]_+ } for a > 0 (t is a scalar) and
 max Z for a = 0. The objective is convex and piecewise linear in t with
@@ -20,10 +20,41 @@ def avar(Z: np.ndarray, p: np.ndarray, a: float) -> float:
     return float(min(vals))
 
 
+def conic_risk(E, F, b, kpos, Z) -> float:
+    """rho(Z) = max { mu'Z : E mu + F nu <=_K b } (section 4.3), K the first
+    kpos rows nonnegative (<=), the rest zero (=); a linear program in
+    (mu, nu), solved by scipy's HiGHS."""
+    from scipy.optimize import linprog
+    E = np.asarray(E, float)
+    F = np.asarray(F, float).reshape(E.shape[0], -1)
+    b = np.asarray(b, float)
+    n, nnu = E.shape[1], F.shape[1]
+    A = np.hstack([E, F])
+    c = -np.concatenate([np.asarray(Z, float), np.zeros(nnu)])
+    kw = {}
+    if kpos > 0:
+        kw.update(A_ub=A[:kpos], b_ub=b[:kpos])
+    if kpos < A.shape[0]:
+        kw.update(A_eq=A[kpos:], b_eq=b[kpos:])
+    res = linprog(c, bounds=[(None, None)] * (n + nnu), method="highs",
+                  options={"primal_feasibility_tolerance": 1e-10, "dual_feasibility_tolerance": 1e-10}, **kw)
+    if res.status != 0:
+        raise RuntimeError(f"risk LP failed: {res.message}")
+    return float(-res.fun)
+
+
+def node_risk(lay, inst, i, Z) -> float:
+    """The risk measure of nonleaf node i applied to its children's values."""
+    if lay.risk is None:
+        return avar(Z, lay.p[lay.children[i]], inst.a_risk[i])
+    return conic_risk(lay.E_matrix(i), lay.F_matrix(i), lay.b_vector(i), lay.kpos(i), Z)
+
+
 def nested_cost(lay, inst, x: np.ndarray, u: np.ndarray) -> float:
-    """Nested AV@R cost of the trajectory (x, u) on the tree: leaves carry
-    x'Q_N x; each nonleaf i carries AV@R_{a_i} over its children c of
-    (x^i'Q^c x^i + u^i'R^c u^i + V^c) with conditional probabilities."""
+    """Nested risk-averse cost of the trajectory (x, u) on the tree: leaves
+    carry x'Q_N x; each nonleaf i carries its risk measure (AV@R_{a_i} with
+    conditional probabilities, or the conic risk of section 4.3) over its
+    children c of (x^i'Q^c x^i + u^i'R^c u^i + V^c)."""
     V = np.zeros(lay.num_nodes)
     for j in lay.leaves:
         V[j] = x[j] @ (inst.qN[j] * x[j])
@@ -32,5 +63,5 @@ def nested_cost(lay, inst, x: np.ndarray, u: np.ndarray) -> float:
             ch = lay.children[i]
             Z = np.array([x[i] @ (inst.q[c] * x[i]) + u[i] @ (inst.r[c] * u[i]) + V[c]
                           for c in ch])
-            V[i] = avar(Z, lay.p[ch], inst.a_risk[i])
+            V[i] = node_risk(lay, inst, i, Z)
     return float(V[0])

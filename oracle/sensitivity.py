@@ -94,26 +94,26 @@ def _soc_jacobian(v: np.ndarray) -> np.ndarray:
 
 def _S3_jvp(lay, inst, p: np.ndarray, dp: np.ndarray) -> np.ndarray:
     """Derivative of proj_S3 at p applied to dp (blocks as in proj_S3)."""
-    nx, nu = lay.nx, lay.nu
     out = np.zeros_like(dp)
     for i in lay.nonleaf:
-        n = len(lay.children[i])
-        sl = slice(lay.e1y[i], lay.e1y[i] + 2 * n)
+        kp, ny = lay.kpos(i), lay.ny[i]
+        sl = slice(lay.e1y[i], lay.e1y[i] + kp)
         out[sl] = (p[sl] > 0.0) * dp[sl]
-        out[lay.e1y[i] + 2 * n] = dp[lay.e1y[i] + 2 * n]
+        sl = slice(lay.e1y[i] + kp, lay.e1y[i] + ny)
+        out[sl] = dp[sl]
         out[lay.e1s[i]] = (p[lay.e1s[i]] > 0.0) * dp[lay.e1s[i]]
-        sl = slice(lay.e1x[i], lay.e1x[i] + nx)
-        out[sl] = ((p[sl] > inst.xmin[i]) & (p[sl] < inst.xmax[i])) * dp[sl]
-        sl = slice(lay.e1u[i], lay.e1u[i] + nu)
-        out[sl] = ((p[sl] > inst.umin[i]) & (p[sl] < inst.umax[i])) * dp[sl]
+        _, _, cmin, cmax = lay.gamma(inst, i)
+        sl = slice(lay.e1c[i], lay.e1c[i] + lay.nc)
+        out[sl] = ((p[sl] > cmin) & (p[sl] < cmax)) * dp[sl]
     shift_of = lambda m: np.concatenate([np.zeros(m - 2), [0.5, -0.5]])  # noqa: E731
     for c in range(1, lay.num_nodes):
         sl = slice(lay.e2x[c], lay.e2b[c] + 1)
         m = sl.stop - sl.start
         out[sl] = _soc_jacobian(p[sl] - shift_of(m)) @ dp[sl]
     for j in lay.leaves:
-        sl = slice(lay.e3x[j], lay.e3x[j] + nx)
-        out[sl] = ((p[sl] > inst.xmin[j]) & (p[sl] < inst.xmax[j])) * dp[sl]
+        _, cmin, cmax = lay.gamma_N(inst, j)
+        sl = slice(lay.e3x[j], lay.e3x[j] + lay.ncN)
+        out[sl] = ((p[sl] > cmin) & (p[sl] < cmax)) * dp[sl]
         sl = slice(lay.e3q[j], lay.e3b[j] + 1)
         m = sl.stop - sl.start
         out[sl] = _soc_jacobian(p[sl] - shift_of(m)) @ dp[sl]

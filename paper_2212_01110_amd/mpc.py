@@ -20,7 +20,7 @@ from . import Problem, default_settings, solve_batched
 
 
 def closed_loop(problem: Problem, A_w: np.ndarray, B_w: np.ndarray, x0: np.ndarray, branches: np.ndarray,
-                settings=None, warm: bool = True, batched: bool = True) -> dict:
+                settings=None, warm: bool = True, batched: bool = True, progress=None) -> dict:
     """Runs the loop for R realisations over S steps.
 
     A_w [d, nx, nx], B_w [d, nx, nu]: the plant for each disturbance value
@@ -29,7 +29,8 @@ def closed_loop(problem: Problem, A_w: np.ndarray, B_w: np.ndarray, x0: np.ndarr
     realisation and step; warm: start each solve from the previous solution
     (else from v = 0). Returns states [R, S+1, nx], inputs [R, S, nu],
     iterations and T evaluations [R, S], the status of every solve and the
-    wall time of every step [S]."""
+    wall time of every step [S]. progress(t, seconds) is called after each
+    step when given."""
     import torch
     s = settings or default_settings(eps_abs=1e-3, eps_rel=1e-3, max_iters=200000)
     branches = np.asarray(branches, dtype=np.int64)
@@ -64,5 +65,7 @@ def closed_loop(problem: Problem, A_w: np.ndarray, B_w: np.ndarray, x0: np.ndarr
             iters[r, t], tev[r, t], status[r][t] = infos[r]["iters"], infos[r]["t_evals"], infos[r]["status"]
             w = branches[r, t]
             xs[r, t + 1] = A_w[w] @ xs[r, t] + B_w[w] @ u0
+        if progress:
+            progress(t, step_s[t])
     return {"states": xs, "inputs": us, "iters": iters, "t_evals": tev, "status": status,
             "step_seconds": step_s}

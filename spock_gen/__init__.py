@@ -65,6 +65,10 @@ class Instance:
     x0: np.ndarray
     name: str = ""
     meta: dict = field(default_factory=dict)
+    # general conic risk (RiskData) and polyhedral constraints
+    # (ConstraintData); None: AV@R_a per node and the boxes
+    risk: object = None
+    cons: object = None
 
     @property
     def num_nodes(self) -> int:
@@ -317,4 +321,115 @@ def make_random_small(seed: int, branching: Sequence[int], nx: int, nu: int,
                      prob_kind=prob_kind, x0_kind="N", name=f"random{seed}")
     inst.r = rng.uniform(0.1, 1.0, size=inst.r.shape)
     inst.qN = rng.uniform(0.5, 2.0, size=inst.qN.shape)
+    return inst
+
+
+# ---------------------------------------------------------------- general conic risk and constraints
+@dataclass
+class RiskData:
+    """Conic risk of every nonleaf node (section 4.3): E[i] [ny, n_i], F[i]
+    [ny, nnu], b[i] [ny], kpos[i] leading rows of K in the nonnegative
+    orthant (the rest in {0}); None at leaves."""
+    E: list
+    F: list
+    b: list
+    kpos: np.ndarray
+
+
+@dataclass
+class ConstraintData:
+    """Polyhedral constraints Gamma_x x + Gamma_u u in [cmin, cmax] at
+    nonleaf nodes and Gamma_N x in [cNmin, cNmax] at leaves (section 4.1)."""
+    Gx: np.ndarray     # [nn, nc, nx]
+    Gu: np.ndarray     # [nn, nc, nu]
+    cmin: np.ndarray   # [nn, nc]
+    cmax: np.ndarray
+    GN: np.ndarray     # [nn, ncN, nx]
+    cNmin: np.ndarray  # [nn, ncN]
+    cNmax: np.ndarray
+
+
+def _children_lists(anc):
+    nn = len(anc)
+    ch = [[] for _ in range(nn)]
+    for i in range(1, nn):
+        ch[int(anc[i])].append(i)
+    return ch
+
+
+def avar_as_conic(inst: Instance) -> RiskData:
+    """AV@R_a of every nonleaf node written as a general conic risk:
+    E = [a I; -I; 1'], F empty, b = (p, 0, 1), K = R^{2n}_+ x {0}."""
+    ch = _children_lists(inst.anc)
+    E, F, b = [None] * inst.num_nodes, [None] * inst.num_nodes, [None] * inst.num_nodes
+    kpos = np.zeros(inst.num_nodes, dtype=np.int64)
+    for i, c in enumerate(ch):
+        if not c:
+            continue
+        n = len(c)
+        p = inst.prob[c] / inst.prob[i]
+        E[i] = np.vstack([inst.a_risk[i] * np.eye(n), -np.eye(n), np.ones((1, n))])
+        F[i] = np.zeros((2 * n + 1, 0))
+        b[i] = np.concatenate([p, np.zeros(n), [1.0]])
+        kpos[i] = 2 * n
+    return RiskData(E, F, b, kpos)
+
+
+def mixture_risk(inst: Instance, kappa: float) -> RiskData:
+    """rho(Z) = (1 - kappa) E^p[Z] + kappa max Z, the ambiguity set
+    {mu = (1 - kappa) p + kappa nu, nu >= 0, 1'nu = 1} in the conic form
+    E mu + F nu <=_K b with nu != 0: rows -nu <= 0 (nonnegative cone),
+    mu - kappa nu = (1 - kappa) p and 1'nu = 1 (zero cone)."""
+    ch = _children_lists(inst.anc)
+    E, F, b = [None] * inst.num_nodes, [None] * inst.num_nodes, [None] * inst.num_nodes
+    kpos = np.zeros(inst.num_nodes, dtype=np.int64)
+    for i, c in enumerate(ch):
+        if not c:
+            continue
+        n = len(c)
+        p = inst.prob[c] / inst.prob[i]
+        E[i] = np.vstack([np.zeros((n, n)), np.eye(n), np.zeros((1, n))])
+        F[i] = np.vstack([-np.eye(n), -kappa * np.eye(n), np.ones((1, n))])
+        b[i] = np.concatenate([np.zeros(n), (1.0 - kappa) * p, [1.0]])
+        kpos[i] = n
+    return RiskData(E, F, b, kpos)
+
+
+def boxes_as_constraints(inst: Instance) -> ConstraintData:
+    """The state/input boxes written as polyhedral constraints (Gamma = I)."""
+    nn, nx, nu = inst.num_nodes, inst.nx, inst.nu
+    Gx = np.zeros((nn, nx + nu, nx))
+    Gu = np.zeros((nn, nx + nu, nu))
+    Gx[:, :nx, :] = np.eye(nx)
+    Gu[:, nx:, :] = np.eye(nu)
+    return ConstraintData(Gx, Gu, np.concatenate([inst.xmin, inst.umin], axis=1),
+                          np.concatenate([inst.xmax, inst.umax], axis=1),
+                          np.tile(np.eye(nx), (nn, 1, 1)), inst.xmin.copy(), inst.xmax.copy())
+
+
+def random_constraints(rng: np.random.Generator, inst: Instance, nc: int, ncN: int, bound: float) -> ConstraintData:
+    """|Gamma_x x + Gamma_u u| <= bound row-wise (rows with unit norm, random
+    directions) at nonleaf nodes and |Gamma_N x| <= bound at leaves."""
+    nn, nx, nu = inst.num_nodes, inst.nx, inst.nu
+    G = rng.standard_normal((nn, nc, nx + nu))
+    G /= np.linalg.norm(G, axis=2, keepdims=True)
+    GN = rng.standard_normal((nn, ncN, nx))
+    GN /= np.linalg.norm(GN, axis=2, keepdims=True)
+    return ConstraintData(G[:, :, :nx].copy(), G[:, :, nx:].copy(), np.full((nn, nc), -bound),
+                          np.full((nn, nc), bound), GN, np.full((nn, ncN), -bound), np.full((nn, ncN), bound))
+
+
+def make_general_small(seed: int, branching: Sequence[int], nx: int, nu: int, kappa: float = 0.4,
+                       nc: int | None = None, ncN: int | None = None, bound: float = 2.0,
+                       x0_scale: float = 0.5) -> Instance:
+    """Small instance with the mixture risk (a conic risk with nu != 0) and
+    random polyhedral constraints (nc rows at nonleaf nodes, ncN at leaves;
+    None keeps the boxes)."""
+    inst = make_random_small(seed, branching, nx, nu)
+    rng = np.random.default_rng([seed, 77])
+    inst.x0 = x0_scale * inst.x0 / max(1.0, np.max(np.abs(inst.x0)))
+    inst.risk = mixture_risk(inst, kappa)
+    if nc is not None:
+        inst.cons = random_constraints(rng, inst, nc, ncN if ncN is not None else nx, bound)
+    inst.name = f"general{seed}"
     return inst

@@ -26,9 +26,13 @@ def _avar(Z, p, a):
 
 
 class NestedDP:
-    def __init__(self, inst, xatol=1e-11):
+    """risk(i, Z): the risk measure of node i applied to its children's
+    values (AV@R_a of the node, from its definition, when not given)."""
+
+    def __init__(self, inst, xatol=1e-11, risk=None):
         assert inst.nu == 1
         self.inst = inst
+        self.risk = risk
         self.ch, self.stage = tree_lists(inst.anc)
         self.xatol = xatol
         self.max_abs_x = 0.0
@@ -46,7 +50,7 @@ class NestedDP:
                 ell = float(x @ (inst.q[c] * x) + inst.r[c][0] * uu * uu)
                 xc = inst.A[c] @ x + inst.B[c][:, 0] * uu
                 Z.append(ell + self.value(c, xc))
-            return _avar(Z, p, inst.a_risk[i])
+            return self.risk(i, Z) if self.risk is not None else _avar(Z, p, inst.a_risk[i])
 
         res = minimize_scalar(obj, bounds=(inst.umin[i][0], inst.umax[i][0]),
                               method="bounded", options={"xatol": self.xatol, "maxiter": 500})

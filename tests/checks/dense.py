@@ -133,3 +133,35 @@ def feasible_conic_point(lay, inst, x, u):
                 z[lay.s_off[c]] = V[c]
     z[0] = V[0]
     return z, V
+
+
+def cut_through(inst, x_star, u_star, rows_per_node=1):
+    """Bounds of the polyhedral constraint rows placed between the value a
+    solution gives them and the value of the zero-input trajectory (x from
+    the dynamics with u = 0), so that the given solution becomes infeasible
+    while the zero-input point stays strictly feasible (the first
+    rows_per_node rows of every nonleaf node; the others keep their bounds).
+    Returns a modified copy."""
+    out = inst.copy()
+    c = out.cons
+    ch, _ = tree_lists(inst.anc)
+    x0t = np.zeros((inst.num_nodes, inst.nx))
+    x0t[0] = inst.x0
+    for cc in range(1, inst.num_nodes):
+        x0t[cc] = inst.A[cc] @ x0t[inst.anc[cc]]
+    cmin, cmax = c.cmin.copy(), c.cmax.copy()
+    for i in range(inst.num_nodes):
+        if not ch[i]:
+            continue
+        r_star = c.Gx[i] @ x_star[i] + c.Gu[i] @ u_star[i]
+        r_zero = c.Gx[i] @ x0t[i]
+        for k in range(min(rows_per_node, r_star.shape[0])):
+            mid = 0.5 * (r_star[k] + r_zero[k])
+            if abs(r_star[k] - r_zero[k]) < 1e-6:
+                continue
+            if r_star[k] > r_zero[k]:
+                cmax[i, k] = mid
+            else:
+                cmin[i, k] = mid
+    out.cons = type(c)(c.Gx, c.Gu, cmin, cmax, c.GN, c.cNmin, c.cNmax)
+    return out

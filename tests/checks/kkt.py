@@ -2,15 +2,16 @@
 eq. min-s0-v1), written from the program's statement, not from the oracle.
 
 Variables (own indexing): x^i for every node, u^i for nonleaf nodes, per
-nonleaf node i the AV@R conic dual y^i = (y1 in R^n_i, y2 in R^n_i, y3 in R)
-(section 4.3: E = [a I, -I, 1]', b = (p, 0, 1), K* = R^{2n}_+ x R), the
+nonleaf node i the conic dual y^i of its risk measure, the
 stage-cost bound tau^c of every non-root node and the cost-to-go bound s^i of
 every node; s^0 is the objective. Constraints:
   x^0 = x0,  x^c = A^c x^i + B^c u^i                       (dynamics)
-  a_i y1_k - y2_k + y3 = tau^c + s^c   for the k-th child c    (E'y = tau + s)
-  y1 >= 0, y2 >= 0,  p'y1 + y3 <= s^i                          (y in K*, b'y <= s)
-  y3 >= -1                                                     (keeps the optimum; see below)
-  xmin <= x^i <= xmax,  umin <= u^i <= umax                    (boxes)
+  E^i'y = tau + s (one row per child), F^i'y = 0              (section 4.3)
+  y in K* (its first kpos entries >= 0), b^i'y <= s^i
+  AV@R_a (default): E = [a I; -I; 1'], F empty, b = (p, 0, 1), kpos = 2 n_i,
+  with y3 >= -1 added (keeps the optimum; see below)
+  cmin <= Gamma_x x^i + Gamma_u u^i <= cmax, cNmin <= Gamma_N x^j <= cNmax
+  (the state/input boxes when the instance carries no constraint data)
   x^i'Q^c x^i + u^i'R^c u^i <= tau^c,  x^j'Q_N x^j <= s^j      (cost epigraphs)
 
 Solved by the logarithmic barrier method with equality-constrained Newton
@@ -47,15 +48,29 @@ class EpigraphIPM:
         for i in self.nonleaf:
             self.iu[i] = np.arange(n, n + nu)
             n += nu
-        self.iy1, self.iy2, self.iy3 = {}, {}, {}
+        # the conic risk of every nonleaf node (section 4.3): AV@R_a unless the
+        # instance carries a general one
+        self.risk = getattr(inst, "risk", None)
+        self.cons = getattr(inst, "cons", None)
+        self.E, self.Fr, self.b, self.kpos = {}, {}, {}, {}
         for i in self.nonleaf:
             k = len(self.ch[i])
-            self.iy1[i] = np.arange(n, n + k)
-            n += k
-            self.iy2[i] = np.arange(n, n + k)
-            n += k
-            self.iy3[i] = n
-            n += 1
+            p = inst.prob[self.ch[i]] / inst.prob[i]
+            if self.risk is None:
+                self.E[i] = np.vstack([inst.a_risk[i] * np.eye(k), -np.eye(k), np.ones((1, k))])
+                self.Fr[i] = np.zeros((2 * k + 1, 0))
+                self.b[i] = np.concatenate([p, np.zeros(k), [1.0]])
+                self.kpos[i] = 2 * k
+            else:
+                self.E[i] = np.asarray(self.risk.E[i], float)
+                self.b[i] = np.asarray(self.risk.b[i], float)
+                self.Fr[i] = np.asarray(self.risk.F[i], float).reshape(len(self.b[i]), -1)
+                self.kpos[i] = int(self.risk.kpos[i])
+        self.iy = {}
+        for i in self.nonleaf:
+            ny = len(self.b[i])
+            self.iy[i] = np.arange(n, n + ny)
+            n += ny
         self.itau = {}
         for c in range(1, nn):
             self.itau[c] = n
@@ -86,15 +101,17 @@ class EpigraphIPM:
                 row[self.iu[i]] -= inst.B[c][k]
                 F.append(row)
                 h.append(0.0)
-        for i in self.nonleaf:                                # E'y = tau + s
-            a = inst.a_risk[i]
+        for i in self.nonleaf:                                # E'y = tau + s, F'y = 0
             for k, c in enumerate(self.ch[i]):
                 row = np.zeros(n)
-                row[self.iy1[i][k]] = a
-                row[self.iy2[i][k]] = -1.0
-                row[self.iy3[i]] = 1.0
+                row[self.iy[i]] = self.E[i][:, k]
                 row[self.itau[c]] = -1.0
                 row[self.isv[c]] = -1.0
+                F.append(row)
+                h.append(0.0)
+            for col in self.Fr[i].T:
+                row = np.zeros(n)
+                row[self.iy[i]] = col
                 F.append(row)
                 h.append(0.0)
         self.F, self.h = np.array(F), np.array(h)
@@ -108,30 +125,43 @@ class EpigraphIPM:
             G.append(row)
             g.append(rhs)
         for i in self.nonleaf:
-            p = inst.prob[self.ch[i]] / inst.prob[i]
-            for k in range(len(self.ch[i])):
-                add(self.iy1[i][k], -1.0, 0.0)
-                add(self.iy2[i][k], -1.0, 0.0)
-            row = np.zeros(n)
-            row[self.iy1[i]] = p
-            row[self.iy3[i]] = 1.0
+            for k in range(self.kpos[i]):                       # y in K*
+                add(self.iy[i][k], -1.0, 0.0)
+            row = np.zeros(n)                                   # b'y <= s
+            row[self.iy[i]] = self.b[i]
             row[self.isv[i]] = -1.0
             G.append(row)
             g.append(0.0)
-            # y3 >= -1: the AV@R minimiser t = y3 is one of the (nonnegative)
-            # child values, or for a = 1 any t <= min of them, so the optimum
-            # stays feasible; without it the direction (y1 + d 1, y3 - d)
-            # leaves every constraint and s^0 unchanged when a = 1 and the
-            # barrier problem has no minimiser
-            add(self.iy3[i], -1.0, 1.0)
+            if self.risk is None:
+                # y3 >= -1: the AV@R minimiser t = y3 is one of the
+                # (nonnegative) child values, or for a = 1 any t <= min of
+                # them, so the optimum stays feasible; without it the
+                # direction (y1 + d 1, y3 - d) leaves every constraint and s^0
+                # unchanged when a = 1 and the barrier problem has no minimiser
+                add(self.iy[i][-1], -1.0, 1.0)
+
+        def rows(idx_x, Gx, idx_u, Gu, lo, hi):                 # lo <= Gx x + Gu u <= hi
+            for r in range(Gx.shape[0]):
+                row = np.zeros(n)
+                row[idx_x] = Gx[r]
+                if idx_u is not None:
+                    row[idx_u] = Gu[r]
+                G.append(row)
+                g.append(hi[r])
+                G.append(-row)
+                g.append(-lo[r])
+        c = self.cons
         for i in range(self.nn):
-            for k in range(nx):
-                add(self.ix[i][k], 1.0, inst.xmax[i][k])
-                add(self.ix[i][k], -1.0, -inst.xmin[i][k])
-        for i in self.nonleaf:
-            for k in range(nu):
-                add(self.iu[i][k], 1.0, inst.umax[i][k])
-                add(self.iu[i][k], -1.0, -inst.umin[i][k])
+            if i in self.iu:                                    # nonleaf
+                if c is None:
+                    rows(self.ix[i], np.eye(nx), None, None, inst.xmin[i], inst.xmax[i])
+                    rows(self.iu[i], np.eye(nu), None, None, inst.umin[i], inst.umax[i])
+                else:
+                    rows(self.ix[i], c.Gx[i], self.iu[i], c.Gu[i], c.cmin[i], c.cmax[i])
+            elif c is None:
+                rows(self.ix[i], np.eye(nx), None, None, inst.xmin[i], inst.xmax[i])
+            else:
+                rows(self.ix[i], c.GN[i], None, None, c.cNmin[i], c.cNmax[i])
         self.G, self.g = np.array(G), np.array(g)
         # quadratic inequalities sum_k w_k z_{idx_k}^2 - z_j <= 0
         self.quads = []
@@ -144,9 +174,29 @@ class EpigraphIPM:
         self.m = len(self.g) + len(self.quads)
 
     # ------------------------------------------------------------------ start
+    def _strict_y(self, i, Z):
+        """A y with E'y = Z, F'y = 0 and its cone rows at least a positive
+        margin (a small linear program: maximise the margin, at most 1)."""
+        from scipy.optimize import linprog
+        E, F, kp = self.E[i], self.Fr[i], self.kpos[i]
+        ny = E.shape[0]
+        A_eq = np.hstack([np.vstack([E.T, F.T]), np.zeros((E.shape[1] + F.shape[1], 1))])
+        b_eq = np.concatenate([Z, np.zeros(F.shape[1])])
+        A_ub = np.zeros((kp, ny + 1))
+        for k in range(kp):
+            A_ub[k, k] = -1.0                                   # t - y_k <= 0
+            A_ub[k, -1] = 1.0
+        c = np.zeros(ny + 1)
+        c[-1] = -1.0
+        res = linprog(c, A_ub=A_ub if kp else None, b_ub=np.zeros(kp) if kp else None, A_eq=A_eq, b_eq=b_eq,
+                      bounds=[(None, None)] * ny + [(None, 1.0)], method="highs")
+        if res.status != 0 or res.x[-1] <= 0.0:
+            raise ValueError("no strictly feasible conic dual point for the start")
+        return res.x[:ny]
+
     def feasible_start(self):
-        """u = 0, x from the dynamics, tau and s with a margin, y1 = 1,
-        y3 above every child's tau + s (so y2 > 0), s^i above b'y."""
+        """u = 0, x from the dynamics, tau and s with a margin, y strictly
+        inside its cone with E'y = tau + s and F'y = 0, s^i above b'y."""
         inst, z = self.inst, np.zeros(self.n)
         x = np.zeros((self.nn, self.nx))
         x[0] = self.x0
@@ -165,12 +215,14 @@ class EpigraphIPM:
                     continue
                 ch = self.ch[i]
                 Z = np.array([z[self.itau[c]] + z[self.isv[c]] for c in ch])
-                y1 = np.ones(len(ch))
-                y3 = max(Z.max(), 0.0) + 1.0
-                y2 = inst.a_risk[i] * y1 + y3 - Z
-                z[self.iy1[i]], z[self.iy2[i]], z[self.iy3[i]] = y1, y2, y3
-                p = inst.prob[ch] / inst.prob[i]
-                z[self.isv[i]] = p @ y1 + y3 + 1.0
+                if self.risk is None:                           # y1 = 1, y3 above every Z (y2 > 0)
+                    k = len(ch)
+                    y3 = max(Z.max(), 0.0) + 1.0
+                    y = np.concatenate([np.ones(k), inst.a_risk[i] + y3 - Z, [y3]])
+                else:
+                    y = self._strict_y(i, Z)
+                z[self.iy[i]] = y
+                z[self.isv[i]] = self.b[i] @ y + 1.0
         if np.min(self.slacks(z)) <= 0.0:
             raise ValueError("hand-built start is not strictly feasible (box too tight for u = 0)")
         return z
