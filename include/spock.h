@@ -95,6 +95,34 @@ int spock_tree_shape(const spock_tree* tree, int32_t* N, int32_t* num_nonleaf,
  *   precision: SPOCK_FP64 or SPOCK_FP32 storage of the iteration data
  *   alpha: CP step size; <= 0 selects 0.99 / ||L||; otherwise must satisfy
  *          0 < alpha ||L|| < 1 (section 3). */
+/* General coherent risk measures in the conic form of section 4.3: at
+ * nonleaf node i, rho(Z) = max { mu'Z : E^i mu + F^i nu <=_K b^i } with
+ * K = R^{kpos_i}_+ x {0}^{ny_i - kpos_i} (the first kpos_i rows are
+ * inequalities, the rest equalities); the problem then carries the conic
+ * dual y^i (ny_i entries) in place of AV@R's 2 n_i + 1, and S2 becomes the
+ * kernel of [E' -I -I; F' 0 0]. Per nonleaf node i in breadth-first order,
+ * concatenated (leaves have none):
+ *   ny[num_nodes], nnu[num_nodes], kpos[num_nodes] (0 at leaves; ny_i >= 1,
+ *   0 <= kpos_i <= ny_i, nnu_i >= 0)
+ *   E: [ny_i][n_i] row-major, F: [ny_i][nnu_i] (NULL if every nnu_i is 0),
+ *   b: [ny_i]. */
+typedef struct {
+  const int32_t *ny, *nnu, *kpos;
+  const double *E, *F, *b;
+} spock_risk_data;
+
+/* General polyhedral constraints (section 4.1, eq. constraints): at nonleaf
+ * node i, cmin <= Gamma_x x^i + Gamma_u u^i <= cmax (nc rows); at leaf j,
+ * cNmin <= Gamma_N x^j <= cNmax (ncN rows). Row-major per node:
+ * Gx [num_nodes][nc][nx], Gu [num_nodes][nc][nu], cmin, cmax [num_nodes][nc]
+ * (read at nonleaf nodes); GN [num_nodes][ncN][nx], cNmin, cNmax
+ * [num_nodes][ncN] (read at leaves). Bounds may be +-infinity, nc, ncN >= 1. */
+typedef struct {
+  int32_t nc, ncN;
+  const double *Gx, *Gu, *cmin, *cmax;
+  const double *GN, *cNmin, *cNmax;
+} spock_constraint_data;
+
 typedef struct {
   int32_t nx, nu;
   const double *A, *B;
@@ -103,13 +131,25 @@ typedef struct {
   const double* a_risk;
   int32_t precision;
   double alpha;
+  /* NULL: AV@R_a of a_risk at every nonleaf node. Otherwise the general
+   * conic risk above (a_risk is not read). */
+  const spock_risk_data* risk;
+  /* NULL: the boxes xmin..umax. Otherwise the polyhedral constraints above
+   * (the boxes are not read, and x0 is not checked against a root box). */
+  const spock_constraint_data* cons;
 } spock_problem_data;
 
 /* Runs Alg. 1 (offline S1 factorisation) in FP64 on the host, computes ||L||
  * from its block-diagonal structure (remark after the definition of L) and
  * uploads the stage-ordered device layout. Synchronises. The tree must
- * outlive the problem. Errors: SPOCK_EINVAL, SPOCK_EBOX, SPOCK_EFACTOR,
- * SPOCK_EUNSUPPORTED, SPOCK_EHIP, SPOCK_ENOMEM. */
+ * outlive the problem. With general risk or constraint data the vector
+ * layout follows it (y^i of ny_i entries; nc constraint rows in place of
+ * (x^i, u^i) in group 1 of eta, ncN in place of x^j in group 3), and the
+ * problem runs in spock_solve, the operator entry points and
+ * spock_T_noalloc; spock_solve_batched and spock_backward reject it with
+ * SPOCK_EUNSUPPORTED, and spock_info.V_nested is NaN for it. Errors:
+ * SPOCK_EINVAL, SPOCK_EBOX, SPOCK_EFACTOR, SPOCK_EUNSUPPORTED, SPOCK_EHIP,
+ * SPOCK_ENOMEM. */
 int spock_problem_factor(const spock_tree* tree, const spock_problem_data* data,
                          spock_problem** out);
 int spock_problem_destroy(spock_problem* prob);

@@ -43,6 +43,18 @@ class SpockError(RuntimeError):
         self.code = code
 
 
+class _RiskData(ctypes.Structure):
+    _fields_ = [("ny", ctypes.c_void_p), ("nnu", ctypes.c_void_p), ("kpos", ctypes.c_void_p),
+                ("E", ctypes.c_void_p), ("F", ctypes.c_void_p), ("b", ctypes.c_void_p)]
+
+
+class _ConstraintData(ctypes.Structure):
+    _fields_ = [("nc", ctypes.c_int32), ("ncN", ctypes.c_int32),
+                ("Gx", ctypes.c_void_p), ("Gu", ctypes.c_void_p), ("cmin", ctypes.c_void_p),
+                ("cmax", ctypes.c_void_p), ("GN", ctypes.c_void_p), ("cNmin", ctypes.c_void_p),
+                ("cNmax", ctypes.c_void_p)]
+
+
 class _ProblemData(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("nu", ctypes.c_int32),
                 ("A", ctypes.c_void_p), ("B", ctypes.c_void_p),
@@ -50,7 +62,40 @@ class _ProblemData(ctypes.Structure):
                 ("xmin", ctypes.c_void_p), ("xmax", ctypes.c_void_p),
                 ("umin", ctypes.c_void_p), ("umax", ctypes.c_void_p),
                 ("a_risk", ctypes.c_void_p), ("precision", ctypes.c_int32),
-                ("alpha", ctypes.c_double)]
+                ("alpha", ctypes.c_double),
+                ("risk", ctypes.POINTER(_RiskData)), ("cons", ctypes.POINTER(_ConstraintData))]
+
+
+def _risk_struct(risk, anc, keep):
+    """Flattens per-node E, F, b (nonleaf nodes in breadth-first order) into
+    the C layout; arrays are kept alive in `keep`."""
+    nn = len(anc)
+    nonleaf = sorted(set(int(a) for a in anc[1:]))
+    ny = np.zeros(nn, dtype=np.int32)
+    nnu = np.zeros(nn, dtype=np.int32)
+    kpos = np.zeros(nn, dtype=np.int32)
+    E, F, b = [], [], []
+    for i in nonleaf:
+        Ei = np.asarray(risk.E[i], dtype=np.float64)
+        bi = np.asarray(risk.b[i], dtype=np.float64)
+        Fi = np.asarray(risk.F[i], dtype=np.float64).reshape(len(bi), -1)
+        ny[i], nnu[i], kpos[i] = len(bi), Fi.shape[1], int(risk.kpos[i])
+        E.append(Ei.ravel())
+        F.append(Fi.ravel())
+        b.append(bi)
+    arr = {"ny": ny, "nnu": nnu, "kpos": kpos, "E": np.ascontiguousarray(np.concatenate(E)),
+           "F": np.ascontiguousarray(np.concatenate(F)) if sum(f.size for f in F) else np.zeros(1),
+           "b": np.ascontiguousarray(np.concatenate(b))}
+    keep.update({"risk_" + k: v for k, v in arr.items()})
+    return _RiskData(**{k: v.ctypes.data for k, v in arr.items()})
+
+
+def _cons_struct(cons, keep):
+    arr = {k: np.ascontiguousarray(getattr(cons, k), dtype=np.float64)
+           for k in ("Gx", "Gu", "cmin", "cmax", "GN", "cNmin", "cNmax")}
+    keep.update({"cons_" + k: v for k, v in arr.items()})
+    return _ConstraintData(nc=arr["Gx"].shape[1], ncN=arr["GN"].shape[1],
+                           **{k: v.ctypes.data for k, v in arr.items()})
 
 
 class Settings(ctypes.Structure):
@@ -192,13 +237,22 @@ class Problem:
     """Factored problem on the device (Alg. 1 in FP64, storage in `precision`)."""
 
     def __init__(self, tree: Tree, nx, nu, A, B, q, r, qN, xmin, xmax, umin, umax, a_risk,
-                 precision=FP64, alpha=0.0):
+                 precision=FP64, alpha=0.0, risk=None, cons=None):
         self.tree = tree
         arrs = {k: np.ascontiguousarray(v, dtype=np.float64) for k, v in
                 dict(A=A, B=B, q=q, r=r, qN=qN, xmin=xmin, xmax=xmax, umin=umin,
                      umax=umax, a_risk=a_risk).items()}
         self._keep = arrs
+        self._risk, self._cons = risk, cons
+        extra = {}
+        if risk is not None:
+            self._risk_c = _risk_struct(risk, tree._anc, extra)
+        if cons is not None:
+            self._cons_c = _cons_struct(cons, extra)
+        self._keep_general = extra
         d = _ProblemData(nx=nx, nu=nu, precision=precision, alpha=alpha,
+                         risk=ctypes.pointer(self._risk_c) if risk is not None else None,
+                         cons=ctypes.pointer(self._cons_c) if cons is not None else None,
                          **{k: v.ctypes.data for k, v in arrs.items()})
         h = ctypes.c_void_p()
         _check(lib().spock_problem_factor(tree.handle, ctypes.byref(d), ctypes.byref(h)),
@@ -216,7 +270,8 @@ class Problem:
     def from_instance(cls, inst, precision=FP64, alpha=0.0, tree=None):
         tree = tree or Tree(inst.anc, inst.prob)
         return cls(tree, inst.nx, inst.nu, inst.A, inst.B, inst.q, inst.r, inst.qN, inst.xmin,
-                   inst.xmax, inst.umin, inst.umax, inst.a_risk, precision, alpha)
+                   inst.xmax, inst.umin, inst.umax, inst.a_risk, precision, alpha,
+                   getattr(inst, "risk", None), getattr(inst, "cons", None))
 
     def mapping(self) -> dict:
         """Mapping the next evaluation of T uses, the dataflow grid, and
@@ -250,7 +305,7 @@ class Problem:
             k["xmin"], k["xmax"] = (np.asarray(b, dtype=np.float64) for b in x_box)
         return Problem(self.tree, self.nx, self.nu, k["A"], k["B"], k["q"], k["r"], k["qN"], k["xmin"],
                        k["xmax"], k["umin"], k["umax"], k["a_risk"],
-                       self.precision if precision is None else precision, alpha)
+                       self.precision if precision is None else precision, alpha, self._risk, self._cons)
 
     @property
     def q(self) -> np.ndarray:

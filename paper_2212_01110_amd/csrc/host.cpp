@@ -95,7 +95,7 @@ int upload(Problem& P, const spock_problem_data& d, const std::vector<double>& A
   auto ap = take(nn, S{});
   for (int i = 0; i < nn; ++i) {
     pp.first[i] = (S)T.pcond[i];
-    ap.first[i] = (S)d.a_risk[i];
+    ap.first[i] = d.a_risk ? (S)d.a_risk[i] : S(0);
   }
   D.p = pp.second; D.a = ap.second;
   auto sqp = take((size_t)nn * nx, S{});
@@ -105,16 +105,18 @@ int upload(Problem& P, const spock_problem_data& d, const std::vector<double>& A
   auto srp = take((size_t)nn * nu, S{});
   auto ulop = take((size_t)nn * nu, S{});
   auto uhip = take((size_t)nn * nu, S{});
+  // (general problems carry their constraints elsewhere; their boxes may be absent)
+  const S inf = std::numeric_limits<S>::infinity();
   for (size_t e = 0; e < (size_t)nn * nx; ++e) {
     sqp.first[e] = (S)std::sqrt(d.q[e]);
     sqNp.first[e] = (S)std::sqrt(d.qN[e]);
-    xlop.first[e] = (S)d.xmin[e];
-    xhip.first[e] = (S)d.xmax[e];
+    xlop.first[e] = d.xmin ? (S)d.xmin[e] : -inf;
+    xhip.first[e] = d.xmax ? (S)d.xmax[e] : inf;
   }
   for (size_t e = 0; e < (size_t)nn * nu; ++e) {
     srp.first[e] = (S)std::sqrt(d.r[e]);
-    ulop.first[e] = (S)d.umin[e];
-    uhip.first[e] = (S)d.umax[e];
+    ulop.first[e] = d.umin ? (S)d.umin[e] : -inf;
+    uhip.first[e] = d.umax ? (S)d.umax[e] : inf;
   }
   D.sq = sqp.second; D.sqN = sqNp.second; D.xlo = xlop.second; D.xhi = xhip.second;
   D.sr = srp.second; D.ulo = ulop.second; D.uhi = uhip.second;
@@ -233,6 +235,126 @@ int upload(Problem& P, const spock_problem_data& d, const std::vector<double>& A
   return SPOCK_OK;
 }
 
+// Device data of a general problem (layout G from build_general): offsets,
+// E, b, the S2 projectors and the constraint rows (the identity rows and
+// bounds of the boxes when d has no constraint data).
+template <typename S>
+int upload_general(Problem& P, const spock_problem_data& d, const GeneralLayout& GL) {
+  const Tree& T = *P.tree;
+  const int nn = T.nn, nl = T.nl, nx = P.nx, nu = P.nu, nc = GL.nc, ncN = GL.ncN, nleaf = nn - nl;
+  // constraint rows as arrays (boxes: Gamma = identity)
+  std::vector<double> Gx((size_t)nl * nc * nx, 0.0), Gu((size_t)nl * nc * nu, 0.0), cmin((size_t)nl * nc),
+      cmax((size_t)nl * nc), GN((size_t)nleaf * ncN * nx, 0.0), cNmin((size_t)nleaf * ncN), cNmax((size_t)nleaf * ncN);
+  const spock_constraint_data* C = d.cons;
+  for (int i = 0; i < nl; ++i) {
+    if (C) {
+      std::copy(C->Gx + (size_t)i * nc * nx, C->Gx + (size_t)(i + 1) * nc * nx, Gx.begin() + (size_t)i * nc * nx);
+      std::copy(C->Gu + (size_t)i * nc * nu, C->Gu + (size_t)(i + 1) * nc * nu, Gu.begin() + (size_t)i * nc * nu);
+      std::copy(C->cmin + (size_t)i * nc, C->cmin + (size_t)(i + 1) * nc, cmin.begin() + (size_t)i * nc);
+      std::copy(C->cmax + (size_t)i * nc, C->cmax + (size_t)(i + 1) * nc, cmax.begin() + (size_t)i * nc);
+    } else {
+      for (int o = 0; o < nx; ++o) {
+        Gx[((size_t)i * nc + o) * nx + o] = 1.0;
+        cmin[(size_t)i * nc + o] = d.xmin[(size_t)i * nx + o];
+        cmax[(size_t)i * nc + o] = d.xmax[(size_t)i * nx + o];
+      }
+      for (int o = 0; o < nu; ++o) {
+        Gu[((size_t)i * nc + nx + o) * nu + o] = 1.0;
+        cmin[(size_t)i * nc + nx + o] = d.umin[(size_t)i * nu + o];
+        cmax[(size_t)i * nc + nx + o] = d.umax[(size_t)i * nu + o];
+      }
+    }
+  }
+  for (int j = nl; j < nn; ++j) {
+    const size_t l = (size_t)(j - nl);
+    if (C) {
+      std::copy(C->GN + (size_t)j * ncN * nx, C->GN + (size_t)(j + 1) * ncN * nx, GN.begin() + l * ncN * nx);
+      std::copy(C->cNmin + (size_t)j * ncN, C->cNmin + (size_t)(j + 1) * ncN, cNmin.begin() + l * ncN);
+      std::copy(C->cNmax + (size_t)j * ncN, C->cNmax + (size_t)(j + 1) * ncN, cNmax.begin() + l * ncN);
+    } else {
+      for (int o = 0; o < nx; ++o) {
+        GN[(l * ncN + o) * nx + o] = 1.0;
+        cNmin[l * ncN + o] = d.xmin[(size_t)j * nx + o];
+        cNmax[l * ncN + o] = d.xmax[(size_t)j * nx + o];
+      }
+    }
+  }
+  // one block: 64-bit offsets, 32-bit counts, then the S arrays
+  std::vector<char> host;
+  size_t off = 0;
+  std::vector<std::pair<size_t, size_t>> parts;  // (offset, bytes)
+  auto place = [&](size_t bytes) {
+    off = (off + 255) & ~size_t(255);
+    parts.push_back({off, bytes});
+    off += bytes;
+    return parts.size() - 1;
+  };
+  const size_t i_z2 = place(8 * nl), i_e1 = place(8 * nl), i_Eo = place(8 * nl), i_yo = place(8 * nl),
+               i_Po = place(8 * nl), i_ny = place(4 * nl), i_kp = place(4 * nl),
+               i_E = place(sizeof(S) * GL.E.size()), i_b = place(sizeof(S) * GL.b.size()),
+               i_P = place(sizeof(S) * GL.PS2.size()), i_Gx = place(sizeof(S) * Gx.size()),
+               i_Gu = place(sizeof(S) * Gu.size()), i_cmin = place(sizeof(S) * cmin.size()),
+               i_cmax = place(sizeof(S) * cmax.size()), i_GN = place(sizeof(S) * GN.size()),
+               i_cNmin = place(sizeof(S) * cNmin.size()), i_cNmax = place(sizeof(S) * cNmax.size());
+  host.assign(off + 256, 0);
+  auto put64 = [&](size_t k, const std::vector<long long>& v) { std::memcpy(host.data() + parts[k].first, v.data(), 8 * v.size()); };
+  auto put32 = [&](size_t k, const std::vector<int>& v) { std::memcpy(host.data() + parts[k].first, v.data(), 4 * v.size()); };
+  auto putS = [&](size_t k, const std::vector<double>& v) {
+    S* dst = reinterpret_cast<S*>(host.data() + parts[k].first);
+    for (size_t e = 0; e < v.size(); ++e) dst[e] = (S)v[e];
+  };
+  put64(i_z2, GL.z2off);
+  put64(i_e1, GL.e1off);
+  put64(i_Eo, GL.Eoff);
+  put64(i_yo, GL.yoff);
+  put64(i_Po, GL.Poff);
+  put32(i_ny, GL.ny);
+  put32(i_kp, GL.kpos);
+  putS(i_E, GL.E);
+  putS(i_b, GL.b);
+  putS(i_P, GL.PS2);
+  putS(i_Gx, Gx);
+  putS(i_Gu, Gu);
+  putS(i_cmin, cmin);
+  putS(i_cmax, cmax);
+  putS(i_GN, GN);
+  putS(i_cNmin, cNmin);
+  putS(i_cNmax, cNmax);
+  void* mem = nullptr;
+  if (hipMalloc(&mem, host.size()) != hipSuccess) return SPOCK_ENOMEM;
+  if (hipMemcpy(mem, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(mem);
+    return SPOCK_EHIP;
+  }
+  char* base = static_cast<char*>(mem);
+  GenDev<S> G;
+  G.nc = nc;
+  G.ncN = ncN;
+  G.eE2 = GL.eE2;
+  G.eE3 = GL.eE3;
+  G.z2off = reinterpret_cast<const long long*>(base + parts[i_z2].first);
+  G.e1off = reinterpret_cast<const long long*>(base + parts[i_e1].first);
+  G.Eoff = reinterpret_cast<const long long*>(base + parts[i_Eo].first);
+  G.yoff = reinterpret_cast<const long long*>(base + parts[i_yo].first);
+  G.Poff = reinterpret_cast<const long long*>(base + parts[i_Po].first);
+  G.ny = reinterpret_cast<const int*>(base + parts[i_ny].first);
+  G.kpos = reinterpret_cast<const int*>(base + parts[i_kp].first);
+  G.E = reinterpret_cast<const S*>(base + parts[i_E].first);
+  G.b = reinterpret_cast<const S*>(base + parts[i_b].first);
+  G.PS2 = reinterpret_cast<const S*>(base + parts[i_P].first);
+  G.Gx = reinterpret_cast<const S*>(base + parts[i_Gx].first);
+  G.Gu = reinterpret_cast<const S*>(base + parts[i_Gu].first);
+  G.cmin = reinterpret_cast<const S*>(base + parts[i_cmin].first);
+  G.cmax = reinterpret_cast<const S*>(base + parts[i_cmax].first);
+  G.GN = reinterpret_cast<const S*>(base + parts[i_GN].first);
+  G.cNmin = reinterpret_cast<const S*>(base + parts[i_cNmin].first);
+  G.cNmax = reinterpret_cast<const S*>(base + parts[i_cNmax].first);
+  P.gmem = mem;
+  P.general = true;
+  if constexpr (sizeof(S) == 8) P.gd64 = G; else P.gd32 = G;
+  return SPOCK_OK;
+}
+
 // Family-to-lane mapping: team size (or kTeamWG), the first stage walked by
 // subtree-owning workgroups (kTeamWG only; N = none), and the offsets of the
 // forward-sweep statistic records of every launch.
@@ -296,11 +418,16 @@ extern "C" int spock_problem_factor(const spock_tree* th, const spock_problem_da
   if (nx < 1 || nu < 1) return SPOCK_EINVAL;
   if (nx > kMaxDim || nu > kMaxDim) return SPOCK_EUNSUPPORTED;
   if (d->precision != SPOCK_FP64 && d->precision != SPOCK_FP32) return SPOCK_EINVAL;
-  if (!d->A || !d->B || !d->q || !d->r || !d->qN || !d->xmin || !d->xmax || !d->umin || !d->umax ||
-      !d->a_risk)
-    return SPOCK_EINVAL;
+  if (!d->A || !d->B || !d->q || !d->r || !d->qN) return SPOCK_EINVAL;
   {
     const int rc = check_problem_data(T, *d);
+    if (rc) return rc;
+  }
+  // general conic risk or polyhedral constraints: their layout and S2 projectors
+  const bool general = d->risk || d->cons;
+  GeneralLayout GL;
+  if (general) {
+    const int rc = build_general(T, *d, kGenMaxBlock, GL);
     if (rc) return rc;
   }
   // ---- Alg. 1, FP64
@@ -311,7 +438,7 @@ extern "C" int spock_problem_factor(const spock_tree* th, const spock_problem_da
   const std::vector<double>& Rinv = fac.Rinv;
   const std::vector<double>& W = fac.W;
   // ---- ||L||: block-diagonal after a column permutation; closed forms per block
-  const double normL = norm_L_blocks(T, *d);
+  const double normL = general ? norm_L_general(T, *d, GL) : norm_L_blocks(T, *d);
   double alpha = d->alpha;
   if (alpha <= 0.0) alpha = 0.99 / normL;
   else if (!(alpha * normL < 1.0)) return SPOCK_EINVAL;
@@ -326,14 +453,20 @@ extern "C" int spock_problem_factor(const spock_tree* th, const spock_problem_da
   P.nz = 1 + (long long)nn * nx + (long long)nl * nu + 4LL * (nn - 1) + nl;
   P.neta = 2LL * (nn - 1) + 2LL * nl + (long long)nl * (nx + nu) + (long long)(nn - 1) * (nx + nu + 2) +
            (long long)(nn - nl) * (2 * nx + 2);
+  if (general) {
+    P.nz = GL.nz;
+    P.neta = GL.neta;
+  }
   P.alpha = alpha;
   P.normL = normL;
-  P.xlo0.assign(d->xmin, d->xmin + nx);
-  P.xhi0.assign(d->xmax, d->xmax + nx);
+  if (!d->cons) {  // the root box that x0 must lie in
+    P.xlo0.assign(d->xmin, d->xmin + nx);
+    P.xhi0.assign(d->xmax, d->xmax + nx);
+  }
   P.q.assign(d->q, d->q + (size_t)nn * nx);
   P.r.assign(d->r, d->r + (size_t)nn * nu);
   P.qN.assign(d->qN, d->qN + (size_t)nn * nx);
-  P.a_risk.assign(d->a_risk, d->a_risk + nn);
+  if (d->a_risk) P.a_risk.assign(d->a_risk, d->a_risk + nn);
   int team = std::max(nx, nu) >= 24 ? kTeamWG : next_pow2_team(std::max(nx, nu));
   const size_t elem = d->precision == SPOCK_FP64 ? 8 : 4;
   if (mapping_lds(P, team, elem) > 64 * 1024) team = kTeamWG;
@@ -352,9 +485,13 @@ extern "C" int spock_problem_factor(const spock_tree* th, const spock_problem_da
     const int v = std::atoi(env);
     if ((v == 8 || v == 16 || v == 32 || v == 64) && v * 4 >= P.team_pp) P.team_pp = v;
   }
-  const int rc = (d->precision == SPOCK_FP64) ? upload<double>(P, *d, Abar, K, Rinv, W)
-                                              : upload<float>(P, *d, Abar, K, Rinv, W);
+  int rc = (d->precision == SPOCK_FP64) ? upload<double>(P, *d, Abar, K, Rinv, W)
+                                        : upload<float>(P, *d, Abar, K, Rinv, W);
+  if (rc == SPOCK_OK && general)
+    rc = (d->precision == SPOCK_FP64) ? upload_general<double>(P, *d, GL) : upload_general<float>(P, *d, GL);
   if (rc != SPOCK_OK) {
+    if (P.dmem) (void)hipFree(P.dmem);
+    if (P.gmem) (void)hipFree(P.gmem);
     delete h;
     return rc;
   }
@@ -365,6 +502,7 @@ extern "C" int spock_problem_factor(const spock_tree* th, const spock_problem_da
 extern "C" int spock_problem_destroy(spock_problem* p) {
   if (!p) return SPOCK_EINVAL;
   if (p->p.dmem) (void)hipFree(p->p.dmem);
+  if (p->p.gmem) (void)hipFree(p->p.gmem);
   if (p->p.work) (void)hipFree(p->p.work);
   if (p->p.flow.mem) (void)hipFree(p->p.flow.mem);
   if (p->p.mbox) (void)hipHostFree(p->p.mbox);
@@ -1305,7 +1443,7 @@ extern "C" int spock_solve(spock_problem* ph, const double* x0_dev, const spock_
   std::vector<double> hx(P.nx);
   HIP_TRY(hipMemcpyAsync(hx.data(), x0_dev, P.nx * sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  for (int k = 0; k < P.nx; ++k)
+  for (int k = 0; k < (int)P.xlo0.size(); ++k)
     if (!(hx[k] >= P.xlo0[k] && hx[k] <= P.xhi0[k])) return SPOCK_EBOX;
   spock_info loc{};
   loc.V_nested = std::numeric_limits<double>::quiet_NaN();
@@ -1344,7 +1482,7 @@ extern "C" int spock_solve(spock_problem* ph, const double* x0_dev, const spock_
     for (size_t e = 0; e < hf.size(); ++e) hv[e] = hf[e];
   }
   loc.V_s0 = hv[0];
-  if (s->compute_nested) {
+  if (s->compute_nested && !P.general) {
     std::vector<double> x(hv.begin() + 1, hv.begin() + 1 + (size_t)T.nn * P.nx);
     std::vector<double> u(hv.begin() + 1 + (size_t)T.nn * P.nx, hv.end());
     loc.V_nested = nested_cost(T, P.nx, P.nu, P.q.data(), P.r.data(), P.qN.data(), P.a_risk.data(), x, u);
@@ -1749,6 +1887,7 @@ extern "C" int spock_solve_batched(int32_t B, spock_problem* const* probs, const
     const Problem& P = probs[b]->p;
     if (P.precision != probs[0]->p.precision || P.nx != probs[0]->p.nx || P.nu != probs[0]->p.nu)
       return SPOCK_EINVAL;
+    if (P.general) return SPOCK_EUNSUPPORTED;
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
   const auto t0 = std::chrono::steady_clock::now();
@@ -1923,6 +2062,7 @@ extern "C" int spock_backward(spock_problem* ph, const void* v_star, const doubl
                               const spock_settings* s, spock_info* info, void* stream) {
   if (!ph || !v_star || !x0 || !grad_x0 || !s || !info || s->max_iters < 1) return SPOCK_EINVAL;
   Problem& P = ph->p;
+  if (P.general) return SPOCK_EUNSUPPORTED;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const auto t0 = std::chrono::steady_clock::now();
   spock_info loc{};

@@ -166,20 +166,284 @@ int check_problem_data(const Tree& T, const spock_problem_data& dd) {
   }
   for (int j = nl; j < nn; ++j)
     for (int k = 0; k < nx; ++k) if (!(d->qN[(size_t)j * nx + k] >= 0.0) || !is_finite(d->qN[(size_t)j * nx + k])) return SPOCK_EINVAL;
-  for (int i = 0; i < nn; ++i)
-    for (int k = 0; k < nx; ++k) {
-      const double lo = d->xmin[(size_t)i * nx + k], hi = d->xmax[(size_t)i * nx + k];
-      if (std::isnan(lo) || std::isnan(hi) || lo > hi) return SPOCK_EBOX;
-    }
-  for (int i = 0; i < nl; ++i) {
-    for (int k = 0; k < nu; ++k) {
-      const double lo = d->umin[(size_t)i * nu + k], hi = d->umax[(size_t)i * nu + k];
-      if (std::isnan(lo) || std::isnan(hi) || lo > hi) return SPOCK_EBOX;
-    }
-    if (!(d->a_risk[i] >= 0.0 && d->a_risk[i] <= 1.0)) return SPOCK_EINVAL;
+  // the boxes (unless general constraints replace them) and AV@R's a
+  // (unless a general risk replaces it)
+  if (!d->cons) {
+    if (!d->xmin || !d->xmax || !d->umin || !d->umax) return SPOCK_EINVAL;
+    for (int i = 0; i < nn; ++i)
+      for (int k = 0; k < nx; ++k) {
+        const double lo = d->xmin[(size_t)i * nx + k], hi = d->xmax[(size_t)i * nx + k];
+        if (std::isnan(lo) || std::isnan(hi) || lo > hi) return SPOCK_EBOX;
+      }
+    for (int i = 0; i < nl; ++i)
+      for (int k = 0; k < nu; ++k) {
+        const double lo = d->umin[(size_t)i * nu + k], hi = d->umax[(size_t)i * nu + k];
+        if (std::isnan(lo) || std::isnan(hi) || lo > hi) return SPOCK_EBOX;
+      }
   }
-
+  if (!d->risk) {
+    if (!d->a_risk) return SPOCK_EINVAL;
+    for (int i = 0; i < nl; ++i)
+      if (!(d->a_risk[i] >= 0.0 && d->a_risk[i] <= 1.0)) return SPOCK_EINVAL;
+  }
   return SPOCK_OK;
+}
+
+namespace {
+// Symmetric eigendecomposition by cyclic Jacobi (row-major k x k; A is
+// overwritten by its eigenvalues on the diagonal, V receives the vectors as
+// columns).
+void sym_jacobi(int k, std::vector<double>& A, std::vector<double>& V) {
+  V.assign((size_t)k * k, 0.0);
+  for (int i = 0; i < k; ++i) V[(size_t)i * k + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int p = 0; p < k; ++p) {
+      dia += A[(size_t)p * k + p] * A[(size_t)p * k + p];
+      for (int q = p + 1; q < k; ++q) off += A[(size_t)p * k + q] * A[(size_t)p * k + q];
+    }
+    if (off <= 1e-32 * std::max(dia, 1e-300)) break;
+    for (int p = 0; p < k; ++p)
+      for (int q = p + 1; q < k; ++q) {
+        const double apq = A[(size_t)p * k + q];
+        if (apq == 0.0) continue;
+        const double th = 0.5 * (A[(size_t)q * k + q] - A[(size_t)p * k + p]) / apq;
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int r = 0; r < k; ++r) {
+          const double arp = A[(size_t)r * k + p], arq = A[(size_t)r * k + q];
+          A[(size_t)r * k + p] = c * arp - sn * arq;
+          A[(size_t)r * k + q] = sn * arp + c * arq;
+        }
+        for (int r = 0; r < k; ++r) {
+          const double apr = A[(size_t)p * k + r], aqr = A[(size_t)q * k + r];
+          A[(size_t)p * k + r] = c * apr - sn * aqr;
+          A[(size_t)q * k + r] = sn * apr + c * aqr;
+        }
+        for (int r = 0; r < k; ++r) {
+          const double vrp = V[(size_t)r * k + p], vrq = V[(size_t)r * k + q];
+          V[(size_t)r * k + p] = c * vrp - sn * vrq;
+          V[(size_t)r * k + q] = sn * vrp + c * vrq;
+        }
+      }
+  }
+}
+}  // namespace
+
+double sym_max_eig(int k, std::vector<double> A) {
+  std::vector<double> V;
+  sym_jacobi(k, A, V);
+  double m = -std::numeric_limits<double>::infinity();
+  for (int i = 0; i < k; ++i) m = std::max(m, A[(size_t)i * k + i]);
+  return m;
+}
+
+int build_general(const Tree& T, const spock_problem_data& d, int max_block, GeneralLayout& G) {
+  const int nn = T.nn, nl = T.nl, nx = d.nx, nu = d.nu;
+  G = GeneralLayout{};
+  G.ny.assign(nl, 0);
+  G.nnu.assign(nl, 0);
+  G.kpos.assign(nl, 0);
+  const spock_risk_data* R = d.risk;
+  const spock_constraint_data* C = d.cons;
+  if (R && (!R->ny || !R->nnu || !R->kpos || !R->E || !R->b)) return SPOCK_EINVAL;
+  long long ne = 0, nb = 0, nf = 0;
+  for (int i = 0; i < nl; ++i) {
+    const int n = T.nch[i];
+    if (R) {
+      G.ny[i] = R->ny[i];
+      G.nnu[i] = R->nnu[i];
+      G.kpos[i] = R->kpos[i];
+      if (G.ny[i] < 1 || G.nnu[i] < 0 || G.kpos[i] < 0 || G.kpos[i] > G.ny[i]) return SPOCK_EINVAL;
+    } else {
+      G.ny[i] = 2 * n + 1;
+      G.kpos[i] = 2 * n;
+    }
+    if (G.ny[i] + 2 * n > max_block) return SPOCK_EUNSUPPORTED;
+    ne += (long long)G.ny[i] * n;
+    nb += G.ny[i];
+    nf += (long long)G.ny[i] * G.nnu[i];
+  }
+  if (R && nf > 0 && !R->F) return SPOCK_EINVAL;
+  // E, b (AV@R: E = [a I; -I; 1'], b = (p, 0, 1))
+  G.E.assign(ne, 0.0);
+  G.b.assign(nb, 0.0);
+  G.Eoff.assign(nl, 0);
+  G.yoff.assign(nl, 0);
+  std::vector<long long> Foff(nl, 0);
+  {
+    long long oe = 0, ob = 0, of = 0;
+    for (int i = 0; i < nl; ++i) {
+      const int n = T.nch[i], ny = G.ny[i];
+      G.Eoff[i] = oe;
+      G.yoff[i] = ob;
+      Foff[i] = of;
+      if (R) {
+        for (long long e = 0; e < (long long)ny * n; ++e) G.E[oe + e] = R->E[oe + e];
+        for (int k = 0; k < ny; ++k) G.b[ob + k] = R->b[ob + k];
+      } else {
+        const double a = d.a_risk[i];
+        for (int k = 0; k < n; ++k) {
+          G.E[oe + (size_t)k * n + k] = a;
+          G.E[oe + (size_t)(n + k) * n + k] = -1.0;
+          G.E[oe + (size_t)(2 * n) * n + k] = 1.0;
+          G.b[ob + k] = T.pcond[T.fc[i] + k];
+        }
+        G.b[ob + 2 * n] = 1.0;
+      }
+      oe += (long long)ny * n;
+      ob += ny;
+      of += (long long)ny * G.nnu[i];
+    }
+  }
+  for (double v : G.E) if (!is_finite(v)) return SPOCK_EINVAL;
+  for (double v : G.b) if (!is_finite(v)) return SPOCK_EINVAL;
+  if (R && nf > 0)
+    for (long long e = 0; e < nf; ++e) if (!is_finite(R->F[e])) return SPOCK_EINVAL;
+  // constraints
+  if (C) {
+    if (C->nc < 1 || C->ncN < 1 || !C->Gx || !C->Gu || !C->cmin || !C->cmax || !C->GN || !C->cNmin || !C->cNmax)
+      return SPOCK_EINVAL;
+    G.nc = C->nc;
+    G.ncN = C->ncN;
+    for (int i = 0; i < nl; ++i) {
+      for (int e = 0; e < G.nc * nx; ++e) if (!is_finite(C->Gx[(size_t)i * G.nc * nx + e])) return SPOCK_EINVAL;
+      for (int e = 0; e < G.nc * nu; ++e) if (!is_finite(C->Gu[(size_t)i * G.nc * nu + e])) return SPOCK_EINVAL;
+      for (int r = 0; r < G.nc; ++r) {
+        const double lo = C->cmin[(size_t)i * G.nc + r], hi = C->cmax[(size_t)i * G.nc + r];
+        if (std::isnan(lo) || std::isnan(hi) || lo > hi) return SPOCK_EBOX;
+      }
+    }
+    for (int j = nl; j < nn; ++j) {
+      for (int e = 0; e < G.ncN * nx; ++e) if (!is_finite(C->GN[(size_t)j * G.ncN * nx + e])) return SPOCK_EINVAL;
+      for (int r = 0; r < G.ncN; ++r) {
+        const double lo = C->cNmin[(size_t)j * G.ncN + r], hi = C->cNmax[(size_t)j * G.ncN + r];
+        if (std::isnan(lo) || std::isnan(hi) || lo > hi) return SPOCK_EBOX;
+      }
+    }
+  } else {
+    G.nc = nx + nu;
+    G.ncN = nx;
+  }
+  // offsets and sizes
+  G.z2off.assign(nl, 0);
+  G.e1off.assign(nl, 0);
+  long long oz = 1 + (long long)nn * nx + (long long)nl * nu, oe1 = 0;
+  for (int i = 0; i < nl; ++i) {
+    G.z2off[i] = oz;
+    oz += G.ny[i] + 2LL * T.nch[i];
+    G.e1off[i] = oe1;
+    oe1 += G.ny[i] + 1 + G.nc;
+  }
+  G.nz = oz;
+  G.eE2 = oe1;
+  G.eE3 = G.eE2 + (long long)(nn - 1) * (nx + nu + 2);
+  G.neta = G.eE3 + (long long)(nn - nl) * (G.ncN + nx + 2);
+  // S2 projectors: I - G'(GG')^+ G with G = [E' -I -I; F' 0 0]
+  G.Poff.assign(nl, 0);
+  long long op = 0;
+  for (int i = 0; i < nl; ++i) {
+    G.Poff[i] = op;
+    op += (long long)(G.ny[i] + 2 * T.nch[i]) * (G.ny[i] + 2 * T.nch[i]);
+  }
+  G.PS2.assign(op, 0.0);
+  std::vector<char> good(nl, 1);
+  parallel_for(nl, [&](int i) {
+    const int n = T.nch[i], ny = G.ny[i], nnu = G.nnu[i], m = ny + 2 * n, rows = n + nnu;
+    std::vector<double> Gm((size_t)rows * m, 0.0);
+    const double* E = G.E.data() + G.Eoff[i];
+    for (int c = 0; c < n; ++c) {
+      for (int k = 0; k < ny; ++k) Gm[(size_t)c * m + k] = E[(size_t)k * n + c];
+      Gm[(size_t)c * m + ny + c] = -1.0;
+      Gm[(size_t)c * m + ny + n + c] = -1.0;
+    }
+    if (R)
+      for (int f = 0; f < nnu; ++f)
+        for (int k = 0; k < ny; ++k) Gm[(size_t)(n + f) * m + k] = R->F[Foff[i] + (size_t)k * nnu + f];
+    std::vector<double> GG((size_t)rows * rows, 0.0), V;
+    for (int a = 0; a < rows; ++a)
+      for (int b = 0; b < rows; ++b) {
+        double acc = 0;
+        for (int k = 0; k < m; ++k) acc += Gm[(size_t)a * m + k] * Gm[(size_t)b * m + k];
+        GG[(size_t)a * rows + b] = acc;
+      }
+    sym_jacobi(rows, GG, V);
+    double lmax = 0;
+    for (int a = 0; a < rows; ++a) lmax = std::max(lmax, GG[(size_t)a * rows + a]);
+    // pseudo-inverse of GG' on its range
+    std::vector<double> Pinv((size_t)rows * rows, 0.0);
+    for (int e = 0; e < rows; ++e) {
+      const double lam = GG[(size_t)e * rows + e];
+      if (!(lam > 1e-12 * lmax)) continue;
+      for (int a = 0; a < rows; ++a)
+        for (int b = 0; b < rows; ++b) Pinv[(size_t)a * rows + b] += V[(size_t)a * rows + e] * V[(size_t)b * rows + e] / lam;
+    }
+    // P = I - G' Pinv G
+    std::vector<double> PG((size_t)rows * m, 0.0);
+    for (int a = 0; a < rows; ++a)
+      for (int k = 0; k < m; ++k) {
+        double acc = 0;
+        for (int b = 0; b < rows; ++b) acc += Pinv[(size_t)a * rows + b] * Gm[(size_t)b * m + k];
+        PG[(size_t)a * m + k] = acc;
+      }
+    double* Pm = G.PS2.data() + G.Poff[i];
+    for (int r = 0; r < m; ++r)
+      for (int k = 0; k < m; ++k) {
+        double acc = (r == k) ? 1.0 : 0.0;
+        for (int a = 0; a < rows; ++a) acc -= Gm[(size_t)a * m + r] * PG[(size_t)a * m + k];
+        Pm[(size_t)r * m + k] = acc;
+        if (!is_finite(acc)) good[i] = 0;
+      }
+  });
+  for (char g : good)
+    if (!g) return SPOCK_EINVAL;
+  return SPOCK_OK;
+}
+
+double norm_L_general(const Tree& T, const spock_problem_data& d, const GeneralLayout& G) {
+  const int nn = T.nn, nl = T.nl, nx = d.nx, nu = d.nu, k = nx + nu;
+  const spock_constraint_data* C = d.cons;
+  std::vector<double> best(std::max(nl, 1), 0.5);
+  parallel_for(nl, [&](int i) {
+    double b2 = 0;
+    for (int e = 0; e < G.ny[i]; ++e) b2 += G.b[G.yoff[i] + e] * G.b[G.yoff[i] + e];
+    double v = 1.0 + 0.5 * b2 + std::sqrt(b2) * std::sqrt(1.0 + 0.25 * b2);
+    // (x^i, u^i) block: Gamma'Gamma + sum_c diag(q^c, r^c)
+    std::vector<double> M((size_t)k * k, 0.0);
+    if (C) {
+      for (int r = 0; r < G.nc; ++r) {
+        std::vector<double> row(k);
+        for (int o = 0; o < nx; ++o) row[o] = C->Gx[((size_t)i * G.nc + r) * nx + o];
+        for (int o = 0; o < nu; ++o) row[nx + o] = C->Gu[((size_t)i * G.nc + r) * nu + o];
+        for (int a = 0; a < k; ++a)
+          for (int b = 0; b < k; ++b) M[(size_t)a * k + b] += row[a] * row[b];
+      }
+    } else {
+      for (int a = 0; a < k; ++a) M[(size_t)a * k + a] = 1.0;
+    }
+    for (int c = T.fc[i]; c < T.fc[i] + T.nch[i]; ++c) {
+      for (int o = 0; o < nx; ++o) M[(size_t)o * k + o] += d.q[(size_t)c * nx + o];
+      for (int o = 0; o < nu; ++o) M[(size_t)(nx + o) * k + nx + o] += d.r[(size_t)c * nu + o];
+    }
+    v = std::max(v, sym_max_eig(k, M));
+    best[i] = std::max(best[i], v);
+  });
+  double b2max = 0.5;
+  for (double v : best) b2max = std::max(b2max, v);
+  for (int j = nl; j < nn; ++j) {
+    std::vector<double> M((size_t)nx * nx, 0.0);
+    if (C) {
+      for (int r = 0; r < G.ncN; ++r)
+        for (int a = 0; a < nx; ++a)
+          for (int b = 0; b < nx; ++b)
+            M[(size_t)a * nx + b] += C->GN[((size_t)j * G.ncN + r) * nx + a] * C->GN[((size_t)j * G.ncN + r) * nx + b];
+    } else {
+      for (int a = 0; a < nx; ++a) M[(size_t)a * nx + a] = 1.0;
+    }
+    for (int o = 0; o < nx; ++o) M[(size_t)o * nx + o] += d.qN[(size_t)j * nx + o];
+    b2max = std::max(b2max, sym_max_eig(nx, M));
+  }
+  return std::sqrt(b2max);
 }
 
 int factor_alg1(const Tree& T, const spock_problem_data& dd, Factor& F) {

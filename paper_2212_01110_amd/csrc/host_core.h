@@ -59,6 +59,32 @@ double nested_cost(const Tree& T, int nx, int nu, const double* q, const double*
 int build_flow_items(const Tree& T, int nc, int chunk_codes, std::vector<int>& items, std::vector<int>& pbase,
                      int& nslots, int& nbwd);
 
+// General problems (conic risk of section 4.3, polyhedral constraints of
+// section 4.1): the vector layout, and per nonleaf node the projector of
+// its (y, tau, s) block on S2 = ker [E' -I -I; F' 0 0] (FP64, row-major
+// m x m, m = ny + 2 n_i), I - G'(G G')^+ G from an eigendecomposition of
+// G G'. Offsets: z2off[i] of the (y, tau, s) block in z, e1off[i] of group
+// 1 (y, s-row, nc constraint rows) in eta, Eoff / yoff / Poff of node i's
+// E, b and projector in their concatenations.
+struct GeneralLayout {
+  int nc = 0, ncN = 0;
+  long long nz = 0, neta = 0, eE2 = 0, eE3 = 0;
+  std::vector<int> ny, nnu, kpos;                      // [nl]
+  std::vector<long long> z2off, e1off, Eoff, yoff, Poff;  // [nl]
+  std::vector<double> E, b, PS2;
+};
+// Validates the risk and constraint data of d (either may be NULL: AV@R
+// from a_risk, or the boxes) and builds the layout. max_block bounds
+// ny + 2 n_i. Returns SPOCK_OK, SPOCK_EINVAL, SPOCK_EBOX or
+// SPOCK_EUNSUPPORTED.
+int build_general(const Tree& T, const spock_problem_data& d, int max_block, GeneralLayout& G);
+// ||L|| of a general problem: the largest spectral norm of its blocks
+// ((x^i, u^i): Gamma' Gamma + sum_c diag(q^c, r^c); (y^i, s^i): closed form in
+// ||b^i||; tau^c and leaf s^j: 1/2; leaf x^j: Gamma_N' Gamma_N + diag(q_N)).
+double norm_L_general(const Tree& T, const spock_problem_data& d, const GeneralLayout& G);
+// Largest eigenvalue of a symmetric k x k matrix (row-major; cyclic Jacobi).
+double sym_max_eig(int k, std::vector<double> A);
+
 // Parallel loop over [0, n) on up to 16 host threads.
 template <typename F>
 void parallel_for(int n, F&& f) {

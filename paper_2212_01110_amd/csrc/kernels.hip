@@ -542,6 +542,7 @@ static void launch_post(const Problem& P, const DevProb<S>& D, const S* z, const
 
 // Number of statistic records written by the post-pass.
 int post_blocks(const Problem& P) {
+  if (P.general) return gen_post_blocks(P);
   const int tpb = 256 / P.team_pp;
   return (P.tree->nl + tpb - 1) / tpb;
 }
@@ -561,11 +562,16 @@ hipError_t launch_T(const Problem& P, const S* v, S* Tv, const double* x0, S* q,
     if (P.prof) (void)hipEventRecord(P.prof[k], st);
   };
   mark(0);
-  switch (P.team_pp) {
-    case 8: launch_pre<S, 8>(P, D, z, eta, zout, xbar, ubar, q, st); break;
-    case 16: launch_pre<S, 16>(P, D, z, eta, zout, xbar, ubar, q, st); break;
-    case 32: launch_pre<S, 32>(P, D, z, eta, zout, xbar, ubar, q, st); break;
-    default: launch_pre<S, 64>(P, D, z, eta, zout, xbar, ubar, q, st); break;
+  if (P.general) {
+    const hipError_t e = launch_gen_pre<S>(P, z, eta, zout, xbar, ubar, q, st);
+    if (e != hipSuccess) return e;
+  } else {
+    switch (P.team_pp) {
+      case 8: launch_pre<S, 8>(P, D, z, eta, zout, xbar, ubar, q, st); break;
+      case 16: launch_pre<S, 16>(P, D, z, eta, zout, xbar, ubar, q, st); break;
+      case 32: launch_pre<S, 32>(P, D, z, eta, zout, xbar, ubar, q, st); break;
+      default: launch_pre<S, 64>(P, D, z, eta, zout, xbar, ubar, q, st); break;
+    }
   }
   mark(1);
   switch (team) {
@@ -582,11 +588,16 @@ hipError_t launch_T(const Problem& P, const S* v, S* Tv, const double* x0, S* q,
   }
   mark(2);
   if (dual) {
-    switch (P.team_pp) {
-      case 8: launch_post<S, 8>(P, D, z, eta, zout, eout, partials, st); break;
-      case 16: launch_post<S, 16>(P, D, z, eta, zout, eout, partials, st); break;
-      case 32: launch_post<S, 32>(P, D, z, eta, zout, eout, partials, st); break;
-      default: launch_post<S, 64>(P, D, z, eta, zout, eout, partials, st); break;
+    if (P.general) {
+      const hipError_t e = launch_gen_post<S>(P, z, eta, zout, eout, partials, st);
+      if (e != hipSuccess) return e;
+    } else {
+      switch (P.team_pp) {
+        case 8: launch_post<S, 8>(P, D, z, eta, zout, eout, partials, st); break;
+        case 16: launch_post<S, 16>(P, D, z, eta, zout, eout, partials, st); break;
+        case 32: launch_post<S, 32>(P, D, z, eta, zout, eout, partials, st); break;
+        default: launch_post<S, 64>(P, D, z, eta, zout, eout, partials, st); break;
+      }
     }
     mark(3);
     hipLaunchKernelGGL(k_reduce_stats, dim3(1), dim3(256), 0, st, partials, post_blocks(P),
@@ -767,6 +778,7 @@ __global__ void __launch_bounds__(256) k_apply_M(DevProb<S> P, const S* __restri
 
 template <typename S>
 hipError_t launch_M(const Problem& P, const S* d, S* Md, hipStream_t st) {
+  if (P.general) return launch_gen_M<S>(P, d, Md, st);
   const DevProb<S>& D = dev_of<S>(P);
   const int T = P.team_pp, tpb = 256 / T;
   const dim3 grid((P.tree->nl + tpb - 1) / tpb);
@@ -836,18 +848,21 @@ __global__ void k_prox_gstar(DevProb<S> P, const S* __restrict__ w, S* __restric
 
 template <typename S>
 hipError_t launch_L(const Problem& P, const S* z, S* eta, hipStream_t st) {
+  if (P.general) return launch_gen_L<S>(P, z, eta, st);
   const int nl = P.tree->nl;
   hipLaunchKernelGGL(k_apply_L<S>, dim3((nl + 127) / 128), dim3(128), 0, st, dev_of<S>(P), z, eta);
   return hipGetLastError();
 }
 template <typename S>
 hipError_t launch_Lt(const Problem& P, const S* eta, S* z, hipStream_t st) {
+  if (P.general) return launch_gen_Lt<S>(P, eta, z, st);
   const int nl = P.tree->nl;
   hipLaunchKernelGGL(k_apply_Lt<S>, dim3((nl + 127) / 128), dim3(128), 0, st, dev_of<S>(P), eta, z);
   return hipGetLastError();
 }
 template <typename S>
 hipError_t launch_prox_gstar(const Problem& P, const S* w, S* out, hipStream_t st) {
+  if (P.general) return launch_gen_prox_gstar<S>(P, w, out, st);
   const int nl = P.tree->nl;
   hipLaunchKernelGGL(k_prox_gstar<S>, dim3((nl + 127) / 128), dim3(128), 0, st, dev_of<S>(P), w, out);
   return hipGetLastError();

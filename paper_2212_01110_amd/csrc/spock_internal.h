@@ -58,6 +58,39 @@ struct DevProb {
 };
 
 
+// Device view of the general parts of a problem (conic risk of section 4.3,
+// polyhedral constraints of section 4.1), precision S. Per nonleaf node i:
+// z2off[i] the offset in z of its block (y^i, tau of its children, s of its
+// children); e1off[i] the offset in eta of its group 1 (y^i, s^i - b'y^i,
+// the nc constraint rows); ny, kpos; E^i [ny][n_i] row-major at E + Eoff[i];
+// b^i at b + yoff[i]; the S2 projector of its (y, tau, s) block (m x m,
+// m = ny + 2 n_i, row-major) at PS2 + Poff[i]; Gx [nl][nc][nx],
+// Gu [nl][nc][nu], cmin, cmax [nl][nc]. Per leaf j (index j - nl):
+// GN [nleaf][ncN][nx], cNmin, cNmax [nleaf][ncN]. Group 2 of non-root c at
+// eE2 + (c - 1)(nx + nu + 2); group 3 of leaf j at eE3 + (j - nl)(ncN + nx + 2).
+template <typename S>
+struct GenDev {
+  int nc = 0, ncN = 0;
+  long long eE2 = 0, eE3 = 0;
+  const long long* z2off = nullptr;
+  const long long* e1off = nullptr;
+  const int* ny = nullptr;
+  const int* kpos = nullptr;
+  const long long* Eoff = nullptr;
+  const long long* yoff = nullptr;
+  const long long* Poff = nullptr;
+  const S* E = nullptr;
+  const S* b = nullptr;
+  const S* PS2 = nullptr;
+  const S* Gx = nullptr;
+  const S* Gu = nullptr;
+  const S* cmin = nullptr;
+  const S* cmax = nullptr;
+  const S* GN = nullptr;
+  const S* cNmin = nullptr;
+  const S* cNmax = nullptr;
+};
+
 // Device arrays of one precision.
 struct DevArrays {
   void* base = nullptr;  // one allocation holding everything below
@@ -133,6 +166,12 @@ struct Problem {
   int cut = 0;
   int team_pp = 64;  // lanes per family of the parallel pre/post passes
   bool tuned = false;
+  // general conic risk / polyhedral constraints (general kernels for the
+  // pre- and post-passes, L, L*, prox of g* and M; device block gmem)
+  bool general = false;
+  void* gmem = nullptr;
+  GenDev<double> gd64{};
+  GenDev<float> gd32{};
   // set once a bounded wait of the dataflow sweeps gave up: the problem then
   // runs the per-stage workgroup form for good
   bool flow_failed = false;
@@ -160,6 +199,25 @@ hipError_t launch_T(const Problem& P, const S* v, S* Tv, const double* x0, S* q,
                     S* ubar, double* partials, double* stats_dev, hipStream_t st,
                     const S* eta_zero, bool dual, Publish pub = Publish{}, SweepMap map = SweepMap{});
 int post_blocks(const Problem& P);
+// General problems (general.hip): pre-pass, post-pass with statistics
+// (post_blocks records), L, L*, prox of g* and M, one thread per family.
+// kGenMaxBlock bounds ny + 2 n_i of a family (its (y, tau, s) block).
+constexpr int kGenMaxBlock = 96;
+int gen_post_blocks(const Problem& P);
+template <typename S>
+hipError_t launch_gen_pre(const Problem& P, const S* z, const S* eta, S* zout, S* xbar, S* ubar, S* qbuf,
+                          hipStream_t st);
+template <typename S>
+hipError_t launch_gen_post(const Problem& P, const S* z, const S* eta, const S* zout, S* eout, double* partials,
+                           hipStream_t st);
+template <typename S>
+hipError_t launch_gen_L(const Problem& P, const S* z, S* eta, hipStream_t st);
+template <typename S>
+hipError_t launch_gen_Lt(const Problem& P, const S* eta, S* z, hipStream_t st);
+template <typename S>
+hipError_t launch_gen_prox_gstar(const Problem& P, const S* w, S* out, hipStream_t st);
+template <typename S>
+hipError_t launch_gen_M(const Problem& P, const S* d, S* Md, hipStream_t st);
 // Dataflow form of the sweeps (flow.hip): one persistent launch per T.
 template <typename S>
 hipError_t launch_sweeps_flow(const Problem& P, const DevProb<S>& D, S* zout, const double* x0, const S* xbar,
