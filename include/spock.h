@@ -229,17 +229,19 @@ int spock_solve_batched(int32_t B, spock_problem* const* probs,
 /* Gradients of the optimal risk-averse cost V* = s^0 and of the first input
  * u^0 with respect to x0 and the diagonal cost weights, by implicit
  * differentiation at the fixed point v* = T(v*) (section 3): the adjoint
- * w = J_T(v*)' w + g is iterated with the transposed CP operator (projection
+ * w = J_T(v*)' w + g, applied with the transposed CP operator (projection
  * Jacobians at the stored pre-prox point, Alg. 2 sweeps with zero root state
- * for the S1 projection), then the parameter Jacobian of T is applied.
+ * for the S1 projection), is solved as (I - J_T(v*)') w = g by restarted
+ * GMRES (30 Krylov vectors; the environment variable SPOCK_ADJ_RESTART sets
+ * 2 to 120), then the parameter Jacobian of T is applied.
  *   v_star_dev: [n_v] of the problem precision, the output of spock_solve
  *   x0_dev: FP64 [nx]; gV: cotangent of V*; gu0_dev: FP64 [nu] cotangent of u^0 or NULL
  *   grad_x0_dev: FP64 [nx] out; grad_q_dev: FP64 [num_nodes][nx] out or NULL
  *     (row c = d/d diag(Q^c), row 0 zero); grad_qN_dev: FP64 [num_nodes][nx]
  *     out or NULL (leaf rows = d/d diag(Q_N^j), other rows zero)
  *   s->eps_abs: tolerance on ||w_{k+1} - w_k||_inf relative to max(1, ||w||_inf);
- *   s->max_iters: adjoint iteration cap. info->iters, info->xi report the
- *   adjoint iterations and last increment; info->status is SPOCK_CONVERGED or
+ *   s->max_iters: cap on applications of J_T'. info->iters, info->xi report
+ *   those applications and the last residual |w - J_T' w - g|_inf; info->status is SPOCK_CONVERGED or
  *   SPOCK_MAXITER. Synchronises the stream. The gradient is that of the
  *   fixed point reached; where the solution is not unique (degenerate active
  *   sets) the adjoint may not converge and info->status says so.

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libspock.so")
-SOURCES = ["host.cpp", "kernels.hip", "flow.hip", "batched.hip", "backward.hip", "general.hip"]
+SOURCES = ["host.cpp", "kernels.hip", "flow.hip", "batched.hip", "backward.hip", "general.hip", "shared.hip"]
 # host-only C++ (no HIP), built with the host compiler
 HOST_SOURCES = ["host_core.cpp"]
 HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-pthread"]

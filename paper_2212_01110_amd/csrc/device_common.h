@@ -691,6 +691,94 @@ __device__ __forceinline__ void fam_post_team(const DevProb<S>& P, const S* __re
   wave_lds_sync();
 }
 
+// M d = (d_z - alpha L* d_eta, d_eta - alpha L d_z), the metric of the
+// SuperMann line search (Alg. 3): one team of T lanes per family writes the
+// family's columns of L* (y^i, s^i, x^i, u^i, tau^c, and x^c, s^c of leaf
+// children) and its rows of L (groups 1, 2 of its children, 3 of its leaf
+// children), so every entry of M d is written once.
+template <typename S, int T>
+__device__ __forceinline__ void fam_apply_M(const DevProb<S>& P, const S* __restrict__ d, S* __restrict__ Md, int i,
+                                            int lane) {
+  const Off<S> O(P);
+  const int nx = P.nx, nu = P.nu, fc = P.fc[i], n = P.nch[i];
+  const S al = P.alpha;
+  const S* dz = d;
+  const S* de = d + P.nz;
+  S* mz = Md;
+  S* me = Md + P.nz;
+  const long long zb = O.z2(i), e1 = O.e1(i);
+  const S es = de[O.e1s(i)];
+  // columns y^i and s^i of L*; rows y and s - b'y of group 1
+  double by = 0;
+  for (int k = lane; k < 2 * n + 1; k += T) {
+    const S bk = (k < n) ? P.p[fc + k] : ((k == 2 * n) ? S(1) : S(0));
+    const S yk = dz[zb + k];
+    mz[zb + k] = yk - al * (de[e1 + k] - bk * es);
+    me[e1 + k] = de[e1 + k] - al * yk;
+    by += (double)(bk * yk);
+  }
+  const S bys = (S)team_sum<T>(by);
+  if (lane == 0) {
+    mz[O.s(i)] = dz[O.s(i)] - al * es;
+    me[O.e1s(i)] = es - al * (dz[O.s(i)] - bys);
+  }
+  // columns x^i, u^i; rows x, u of group 1 and of the children's group 2
+  for (int o = lane; o < nx; o += T) {
+    const S xo = dz[O.x(i) + o];
+    S acc = de[O.e1x(i) + o];
+    for (int k = 0; k < n; ++k) {
+      const int c = fc + k;
+      const S sq = P.sq[(size_t)c * nx + o];
+      const long long e2 = O.e2(c) + o;
+      acc += sq * de[e2];
+      me[e2] = de[e2] - al * sq * xo;
+    }
+    mz[O.x(i) + o] = xo - al * acc;
+    me[O.e1x(i) + o] = de[O.e1x(i) + o] - al * xo;
+  }
+  for (int o = lane; o < nu; o += T) {
+    const S uo = dz[O.u(i) + o];
+    S acc = de[O.e1u(i) + o];
+    for (int k = 0; k < n; ++k) {
+      const int c = fc + k;
+      const S sr = P.sr[(size_t)c * nu + o];
+      const long long e2 = O.e2(c) + nx + o;
+      acc += sr * de[e2];
+      me[e2] = de[e2] - al * sr * uo;
+    }
+    mz[O.u(i) + o] = uo - al * acc;
+    me[O.e1u(i) + o] = de[O.e1u(i) + o] - al * uo;
+  }
+  // tau^c and the two scalars of group 2
+  for (int k = lane; k < n; k += T) {
+    const int c = fc + k;
+    const long long e2 = O.e2(c) + nx + nu;
+    const S tc = dz[O.tau(c)];
+    mz[O.tau(c)] = tc - al * S(0.5) * (de[e2] + de[e2 + 1]);
+    me[e2] = de[e2] - al * S(0.5) * tc;
+    me[e2 + 1] = de[e2 + 1] - al * S(0.5) * tc;
+  }
+  if (fc < P.nl) return;
+  // leaf children: columns x^c, s^c; rows of group 3
+  for (int k = 0; k < n; ++k) {
+    const int c = fc + k;
+    const long long e3 = O.e3(c);
+    for (int o = lane; o < nx; o += T) {
+      const S xc = dz[O.x(c) + o];
+      const S sqn = P.sqN[(size_t)c * nx + o];
+      mz[O.x(c) + o] = xc - al * (de[e3 + o] + sqn * de[e3 + nx + o]);
+      me[e3 + o] = de[e3 + o] - al * xc;
+      me[e3 + nx + o] = de[e3 + nx + o] - al * sqn * xc;
+    }
+    if (lane == 0) {
+      const S sc = dz[O.s(c)];
+      mz[O.s(c)] = sc - al * S(0.5) * (de[e3 + 2 * nx] + de[e3 + 2 * nx + 1]);
+      me[e3 + 2 * nx] = de[e3 + 2 * nx] - al * S(0.5) * sc;
+      me[e3 + 2 * nx + 1] = de[e3 + 2 * nx + 1] - al * S(0.5) * sc;
+    }
+  }
+}
+
 // Tagged words: element e of a vector occupies kTW<S> 64-bit words, each
 // holding (epoch << 32) | one 32-bit half of the value.
 template <typename S>

@@ -564,4 +564,19 @@ int build_flow_items(const Tree& T, int nc, int chunk_codes, std::vector<int>& i
   return SPOCK_OK;
 }
 
+int build_post_blocks(const Tree& T, int cap, std::vector<int>& bfam) {
+  bfam.clear();
+  int count = 0;
+  for (int f = 0; f < T.nl; ++f) {
+    if (f == 0 || (count > 0 && count + T.nch[f] > cap)) {
+      bfam.push_back(f);
+      count = 0;
+    }
+    count += T.nch[f];
+  }
+  const int nb = (int)bfam.size();
+  bfam.push_back(T.nl);
+  return nb;
+}
+
 }  // namespace spk

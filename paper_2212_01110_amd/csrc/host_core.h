@@ -59,6 +59,13 @@ double nested_cost(const Tree& T, int nx, int nu, const double* q, const double*
 int build_flow_items(const Tree& T, int nc, int chunk_codes, std::vector<int>& items, std::vector<int>& pbase,
                      int& nslots, int& nbwd);
 
+// Blocks of the node-parallel post-pass: families packed in breadth-first
+// order, block b owning families [bfam[b], bfam[b + 1]) whose children (one
+// contiguous run) number at most cap (a family with more children than cap
+// gets a block of its own; cap must be at least the largest family for the
+// kernel, which the caller checks). Returns the number of blocks.
+int build_post_blocks(const Tree& T, int cap, std::vector<int>& bfam);
+
 // General problems (conic risk of section 4.3, polyhedral constraints of
 // section 4.1): the vector layout, and per nonleaf node the projector of
 // its (y, tau, s) block on S2 = ker [E' -I -I; F' 0 0] (FP64, row-major

@@ -66,6 +66,91 @@ __global__ void __launch_bounds__(256) k_post(DevProb<S> P, const S* __restrict_
   block_stats(st, partials);
 }
 
+// node-parallel post-pass: the same update and statistics as k_post, with
+// the children of a family on separate teams. Block b owns the families
+// [bfam[b], bfam[b + 1]) and their children (one contiguous run of at most
+// cap nodes). Phase A: a team per child does the rows of group 2 (and group
+// 3 at a leaf) and leaves that child's part of L* r_eta on the columns x^i,
+// u^i of its parent in LDS. Phase B: a team per family adds those parts in
+// child order (the order the family-serial kernel uses) and does group 1
+// and the columns x^i, u^i. No family chain: every child is independent.
+template <typename S, int T>
+__global__ void __launch_bounds__(256) k_post_nodes(DevProb<S> P, const int* __restrict__ bfam,
+                                                    const S* __restrict__ z, const S* __restrict__ eta,
+                                                    const S* __restrict__ zout, S* __restrict__ eout, int VM,
+                                                    double* __restrict__ partials) {
+  extern __shared__ unsigned char smem_raw[];
+  constexpr int TPB = 256 / T;
+  constexpr int C = (kMaxDim + T - 1) / T;
+  S* smem = reinterpret_cast<S*>(smem_raw);
+  const int lane = threadIdx.x % T;
+  const int team = threadIdx.x / T;
+  const int nx = P.nx, nu = P.nu, GW = nx + nu;
+  S* mine = smem + (size_t)team * 3 * VM;  // u+ of the parent (VM), scratch (2 VM)
+  S* G = smem + (size_t)TPB * 3 * VM;      // [children of the block][nx + nu]
+  const Off<S> O(P);
+  const int f0 = bfam[blockIdx.x], f1 = bfam[blockIdx.x + 1];
+  const int c0 = P.fc[f0];
+  const int c1 = P.fc[f1 - 1] + P.nch[f1 - 1];
+  StatAcc st;
+  for (int ch = c0 + team; ch < c1; ch += TPB) {
+    const int i = P.anc[ch];
+    const long long ui = O.u(i);
+    S xp[C], xo[C], xc[C], gx[C], gu[C];
+    wave_lds_sync();
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int o = lane + c * T;
+      xp[c] = xo[c] = xc[c] = gx[c] = gu[c] = 0;
+      if (o < nx) {
+        xp[c] = zout[O.x(i) + o];
+        xo[c] = z[O.x(i) + o];
+        if (ch >= P.nl) xc[c] = zout[O.x(ch) + o];
+      }
+      if (o < nu) mine[o] = zout[ui + o];
+    }
+    wave_lds_sync();
+    fam_dual_child<S, T>(P, O, z, eta, zout, eout, i, ch, lane, xp, xo, mine, xc, mine + VM, gx, gu, st);
+    S* g = G + (size_t)(ch - c0) * GW;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int o = lane + c * T;
+      if (o < nx) g[o] = gx[c];
+      if (o < nu) g[nx + o] = gu[c];
+    }
+  }
+  __syncthreads();
+  for (int f = f0 + team; f < f1; f += TPB) {
+    const long long ui = O.u(f);
+    const int fc = P.fc[f], n = P.nch[f];
+    S xp[C], xo[C], up[C], uo[C], gx[C], gu[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int o = lane + c * T;
+      xp[c] = xo[c] = up[c] = uo[c] = gx[c] = gu[c] = 0;
+      if (o < nx) {
+        xp[c] = zout[O.x(f) + o];
+        xo[c] = z[O.x(f) + o];
+      }
+      if (o < nu) {
+        up[c] = zout[ui + o];
+        uo[c] = z[ui + o];
+      }
+    }
+    for (int k = 0; k < n; ++k) {
+      const S* g = G + (size_t)(fc + k - c0) * GW;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const int o = lane + c * T;
+        if (o < nx) gx[c] += g[o];
+        if (o < nu) gu[c] += g[nx + o];
+      }
+    }
+    fam_dual_node<S, T>(P, O, z, eta, zout, eout, f, lane, xp, xo, up, uo, gx, gu, st);
+  }
+  block_stats(st, partials);
+}
+
 // ---------------------------------------------------------------- team sweeps
 // One team of T lanes per family; one launch per stage.
 template <typename S, int T>
@@ -531,11 +616,20 @@ static void launch_pre(const Problem& P, const DevProb<S>& D, const S* z, const 
                      zout, xbar, ubar, q);
 }
 
+static int pp_index(int T) { return T == 8 ? 0 : T == 16 ? 1 : T == 32 ? 2 : 3; }
+
 template <typename S, int T>
 static void launch_post(const Problem& P, const DevProb<S>& D, const S* z, const S* eta,
                         const S* zout, S* eout, double* partials, hipStream_t st) {
   const int tpb = 256 / T;
   const int VM = (std::max(P.nx, P.nu) + 3) & ~3;
+  const int k = pp_index(T);
+  if (P.pblk_n[k] > 0) {
+    const size_t lds = ((size_t)tpb * 3 * VM + (size_t)P.pblk_cap[k] * (P.nx + P.nu)) * sizeof(S);
+    hipLaunchKernelGGL((k_post_nodes<S, T>), dim3(P.pblk_n[k]), dim3(256), lds, st, D, P.d_pblk[k], z, eta, zout,
+                       eout, VM, partials);
+    return;
+  }
   hipLaunchKernelGGL((k_post<S, T>), dim3((P.tree->nl + tpb - 1) / tpb), dim3(256),
                      (size_t)tpb * 3 * VM * sizeof(S), st, D, z, eta, zout, eout, VM, partials);
 }
@@ -543,6 +637,8 @@ static void launch_post(const Problem& P, const DevProb<S>& D, const S* z, const
 // Number of statistic records written by the post-pass.
 int post_blocks(const Problem& P) {
   if (P.general) return gen_post_blocks(P);
+  const int k = pp_index(P.team_pp);
+  if (P.pblk_n[k] > 0) return P.pblk_n[k];
   const int tpb = 256 / P.team_pp;
   return (P.tree->nl + tpb - 1) / tpb;
 }
@@ -686,94 +782,13 @@ __global__ void k_apply_Lt(DevProb<S> P, const S* __restrict__ eta, S* __restric
   }
 }
 
-// M d = (d_z - alpha L* d_eta, d_eta - alpha L d_z), the metric of the
-// SuperMann line search (Alg. 3): one team of T lanes per family writes the
-// family's columns of L* (y^i, s^i, x^i, u^i, tau^c, and x^c, s^c of leaf
-// children) and its rows of L (groups 1, 2 of its children, 3 of its leaf
-// children), so every entry of M d is written once.
+// M d of one problem: one team of T lanes per family.
 template <typename S, int T>
 __global__ void __launch_bounds__(256) k_apply_M(DevProb<S> P, const S* __restrict__ d, S* __restrict__ Md) {
   const int lane = threadIdx.x % T;
   const int i = blockIdx.x * (blockDim.x / T) + threadIdx.x / T;
   if (i >= P.nl) return;
-  const Off<S> O(P);
-  const int nx = P.nx, nu = P.nu, fc = P.fc[i], n = P.nch[i];
-  const S al = P.alpha;
-  const S* dz = d;
-  const S* de = d + P.nz;
-  S* mz = Md;
-  S* me = Md + P.nz;
-  const long long zb = O.z2(i), e1 = O.e1(i);
-  const S es = de[O.e1s(i)];
-  // columns y^i and s^i of L*; rows y and s - b'y of group 1
-  double by = 0;
-  for (int k = lane; k < 2 * n + 1; k += T) {
-    const S bk = (k < n) ? P.p[fc + k] : ((k == 2 * n) ? S(1) : S(0));
-    const S yk = dz[zb + k];
-    mz[zb + k] = yk - al * (de[e1 + k] - bk * es);
-    me[e1 + k] = de[e1 + k] - al * yk;
-    by += (double)(bk * yk);
-  }
-  const S bys = (S)team_sum<T>(by);
-  if (lane == 0) {
-    mz[O.s(i)] = dz[O.s(i)] - al * es;
-    me[O.e1s(i)] = es - al * (dz[O.s(i)] - bys);
-  }
-  // columns x^i, u^i; rows x, u of group 1 and of the children's group 2
-  for (int o = lane; o < nx; o += T) {
-    const S xo = dz[O.x(i) + o];
-    S acc = de[O.e1x(i) + o];
-    for (int k = 0; k < n; ++k) {
-      const int c = fc + k;
-      const S sq = P.sq[(size_t)c * nx + o];
-      const long long e2 = O.e2(c) + o;
-      acc += sq * de[e2];
-      me[e2] = de[e2] - al * sq * xo;
-    }
-    mz[O.x(i) + o] = xo - al * acc;
-    me[O.e1x(i) + o] = de[O.e1x(i) + o] - al * xo;
-  }
-  for (int o = lane; o < nu; o += T) {
-    const S uo = dz[O.u(i) + o];
-    S acc = de[O.e1u(i) + o];
-    for (int k = 0; k < n; ++k) {
-      const int c = fc + k;
-      const S sr = P.sr[(size_t)c * nu + o];
-      const long long e2 = O.e2(c) + nx + o;
-      acc += sr * de[e2];
-      me[e2] = de[e2] - al * sr * uo;
-    }
-    mz[O.u(i) + o] = uo - al * acc;
-    me[O.e1u(i) + o] = de[O.e1u(i) + o] - al * uo;
-  }
-  // tau^c and the two scalars of group 2
-  for (int k = lane; k < n; k += T) {
-    const int c = fc + k;
-    const long long e2 = O.e2(c) + nx + nu;
-    const S tc = dz[O.tau(c)];
-    mz[O.tau(c)] = tc - al * S(0.5) * (de[e2] + de[e2 + 1]);
-    me[e2] = de[e2] - al * S(0.5) * tc;
-    me[e2 + 1] = de[e2 + 1] - al * S(0.5) * tc;
-  }
-  if (fc < P.nl) return;
-  // leaf children: columns x^c, s^c; rows of group 3
-  for (int k = 0; k < n; ++k) {
-    const int c = fc + k;
-    const long long e3 = O.e3(c);
-    for (int o = lane; o < nx; o += T) {
-      const S xc = dz[O.x(c) + o];
-      const S sqn = P.sqN[(size_t)c * nx + o];
-      mz[O.x(c) + o] = xc - al * (de[e3 + o] + sqn * de[e3 + nx + o]);
-      me[e3 + o] = de[e3 + o] - al * xc;
-      me[e3 + nx + o] = de[e3 + nx + o] - al * sqn * xc;
-    }
-    if (lane == 0) {
-      const S sc = dz[O.s(c)];
-      mz[O.s(c)] = sc - al * S(0.5) * (de[e3 + 2 * nx] + de[e3 + 2 * nx + 1]);
-      me[e3 + 2 * nx] = de[e3 + 2 * nx] - al * S(0.5) * sc;
-      me[e3 + 2 * nx + 1] = de[e3 + 2 * nx + 1] - al * S(0.5) * sc;
-    }
-  }
+  fam_apply_M<S, T>(P, d, Md, i, lane);
 }
 
 template <typename S>

@@ -19,6 +19,8 @@ constexpr int kStats = 5;
 constexpr int kTeamWG = 256;
 // Mapping code of the one-launch dataflow form of T (flow.hip).
 constexpr int kTeamFlow = 512;
+// Mapping code reported by the shared-tree batched form (shared.hip).
+constexpr int kTeamShared = 1024;
 
 // Device view of one problem's iteration data in precision S. Node-indexed
 // arrays follow breadth-first order; matrices are stored as the transpose of
@@ -165,6 +167,12 @@ struct Problem {
   // N means every stage has its own launch
   int cut = 0;
   int team_pp = 64;  // lanes per family of the parallel pre/post passes
+  // node-parallel post-pass, per team size 8, 16, 32, 64 (index log2(T) - 3):
+  // the device block table (pblk_n[k] + 1 family indices) and the child
+  // capacity of a block; pblk_n[k] = 0 selects the family-serial kernel
+  const int* d_pblk[4] = {};
+  int pblk_n[4] = {};
+  int pblk_cap[4] = {};
   bool tuned = false;
   // general conic risk / polyhedral constraints (general kernels for the
   // pre- and post-passes, L, L*, prox of g* and M; device block gmem)
@@ -352,5 +360,13 @@ hipError_t launch_maxdiff(long long n, const S* a, const S* b, double* partials,
                           hipStream_t st);
 template <typename S>
 hipError_t launch_copy_elem(S* dst, const S* src, hipStream_t st);
+
+// Shared-tree batched form (shared.hip): B instances of one problem that
+// differ in x0 and iterate, in lockstep rounds of one evaluation of T for all
+// (MFMA sweeps); results and errors as spock_solve_batched. Keeps a device
+// workspace between calls (not thread safe).
+template <typename S>
+int shared_solve(Problem& P, int B, const double* const* x0, const spock_settings& s, void* const* vio,
+                 spock_info* infos, hipStream_t st);
 
 }  // namespace spk

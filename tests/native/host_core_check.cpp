@@ -6,6 +6,8 @@
 // arrays); x[nn][nx] u[nl][nu] (a trajectory); nc (children per chunk).
 #include <cstdio>
 #include <fstream>
+#include <string>
+#include <algorithm>
 #include <vector>
 
 #include "../../paper_2212_01110_amd/csrc/host_core.h"
@@ -77,5 +79,17 @@ int main(int argc, char** argv) {
   std::printf("items_rc %d %d %d\n", ri, nbwd, nslots);
   std::vector<double> it(items.begin(), items.end());
   put("items", it);
+  // post-pass blocks at the capacities the library uses (teams per block
+  // 32, 16, 8, 4, raised to the largest family)
+  int maxnch = 1;
+  for (int i = 0; i < T.nl; ++i) maxnch = std::max(maxnch, T.nch[i]);
+  for (int tpb : {32, 16, 8, 4}) {
+    std::vector<int> bf;
+    const int cap = std::max(tpb, maxnch);
+    const int nb = spk::build_post_blocks(T, cap, bf);
+    std::printf("pblk%d %d %d\n", tpb, nb, cap);
+    std::vector<double> b(bf.begin(), bf.end());
+    put(("pblk" + std::to_string(tpb) + "_f").c_str(), b);
+  }
   return 0;
 }

@@ -358,6 +358,37 @@ def test_T_every_mapping(name, mapping, prec, monkeypatch):
     check("prox_f_map:" + tag, relerr(host(zo), reff), tol)
 
 
+# b5-wide: a family of 5 children, more than the 4 teams of a block at 64
+# lanes; b2x3-nx64 in FP64 at 8 lanes: LDS above 64 KiB, family kernel
+POST_CASES = ["config2", "b5-wide", "b2x3-nx64", "b2-nx1", "b3-1-nx37", "b1-chain"]
+
+
+@pytest.mark.parametrize("prec", list(FP))
+@pytest.mark.parametrize("form", ["nodes", "family"])
+@pytest.mark.parametrize("tpp", ["8", "16", "32", "64"])
+@pytest.mark.parametrize("name", POST_CASES)
+def test_post_pass_forms(name, tpp, form, prec, monkeypatch):
+    # both post-pass kernels (children on teams of their own in blocks that
+    # own whole families; one team per family walking its children) at every
+    # team size: T and its statistics against the oracle
+    monkeypatch.setenv("SPOCK_TEAM", "512")
+    monkeypatch.setenv("SPOCK_TEAM_PP", tpp)
+    if form == "family":
+        monkeypatch.setenv("SPOCK_POST", "family")
+    inst = CASES[name]
+    gp, op = build(inst, FP[prec][0])
+    vt = dev(seeded(f"post:{name}:{tpp}").standard_normal(op.lay.n_v), gp.torch_dtype)
+    x0 = dev(op.inst.x0, torch.float64)
+    Tv = torch.zeros_like(vt)
+    st = gp.T(vt, x0, Tv)
+    vin = host(vt)
+    ref = O.T_apply(op, vin, op.inst.x0)
+    tag = f"{name}:{tpp}:{form}:{prec}"
+    check("T_post:" + tag, relerr(host(Tv), ref), FP[prec][1])
+    r = vin - ref
+    _check_stats("stats_post:" + tag, st, O.residual_stats(op, r), r, op, STAT_TOL[prec])
+
+
 # ---------------------------------------------------------------- the 20 776-node tree
 @pytest.fixture(scope="module")
 def tree20776():

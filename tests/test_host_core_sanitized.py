@@ -103,6 +103,16 @@ def test_host_core_matches_oracle_under_sanitizers(driver, tmp_path, name, mk, n
         i = lay.anc[c]
         assert pos_b[c] < pos_b[i] and pos_f[i] < pos_f[c]
     assert sorted(set(fam[:nbwd])) == list(lay.nonleaf)
+    # post-pass blocks: consecutive runs of families covering all of them,
+    # each with at most cap children (the children of a run are contiguous)
+    nch = np.bincount(np.asarray(lay.anc[1:]), minlength=inst.num_nodes)
+    for tpb in (32, 16, 8, 4):
+        nb, cap = out[f"pblk{tpb}"].astype(int)
+        bf = out[f"pblk{tpb}_f"].astype(int)
+        assert len(bf) == nb + 1 and bf[0] == 0 and bf[-1] == len(lay.nonleaf)
+        assert np.all(np.diff(bf) >= 1)
+        for k in range(nb):
+            assert nch[bf[k]:bf[k + 1]].sum() <= cap
 
 
 def test_malformed_trees_and_data_under_sanitizers(driver, tmp_path):
