@@ -34,6 +34,11 @@ The same JSON line carries the other legs of the metric, each measured:
   datacentre_closed_loop_mpc the paper's closed-loop simulation (N 10,
                             n_x = n_u = 20, 20 steps, 15 realisations), warm
                             against cold starts
+  differentiation_64_instances 64 instances of the 95-node tree sharing its
+                            data: forward by the shared-tree (MFMA) form, the
+                            block engine and one by one; adjoint gradients
+  shared_forward_64_instances (only when asked: --legs shared64) one FP32
+                            forward of that workload by the shared-tree form
 """
 from __future__ import annotations
 
@@ -446,6 +451,91 @@ def leg_mpc(torch, SP, G, steps=20, realisations=15):
     return out
 
 
+def leg_diff64(torch, SP, G):
+    """The differentiation workload: 64 instances of the 95-node tree (n_x 20,
+    n_u 10, N 8, branching 2 for 4 stages; shared tree and data, own x0).
+    Forward in FP32 to eps 1e-5 three ways: the shared-tree form (one call,
+    instances in lockstep, Alg. 2 sweeps as 16-instance MFMA tiles), the
+    per-instance block engine (SPOCK_SHARED=0) and spock_solve instance by
+    instance; FP64 forward to 1e-10 by the first two. Then the adjoint
+    gradients d(V*, u^0)/d(x0, diag Q) of all 64 instances in FP32 (to 1e-6)
+    and of 8 of them in FP64 (to 1e-10)."""
+    insts = G.make_batch(5)
+    out = {"workload": "64 instances of the 95-node tree nx20 nu10 N8 (shared tree and data, own x0)"}
+    gu = np.random.default_rng(7).standard_normal(insts[0].nu)
+    for pname, prec, eps, beps, nadj in (("fp32", SP.FP32, 1e-5, 1e-6, 64), ("fp64", SP.FP64, 1e-10, 1e-10, 8)):
+        gp = SP.Problem.from_instance(insts[0], precision=prec)
+        dt = gp.torch_dtype
+        x0s = [torch.as_tensor(i.x0, dtype=torch.float64, device="cuda") for i in insts]
+        s = SP.default_settings(eps_abs=eps, eps_rel=eps, max_iters=400000)
+        res = {}
+        forms = [("shared_mfma", "1"), ("block_engine", "0")]
+        for form, env in forms:
+            os.environ["SPOCK_SHARED"] = env
+            vs = [torch.zeros(gp.n_v, dtype=dt, device="cuda") for _ in insts]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            infos = SP.solve_batched([gp] * len(insts), x0s, vs, s)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            res[form] = {"seconds": round(el, 4), "all_converged": all(i["status"] == "converged" for i in infos),
+                         "t_evals_total": int(sum(i["t_evals"] for i in infos)),
+                         "max_iters": int(max(i["iters"] for i in infos)), "mapping": infos[0]["mapping"]}
+            if form == "shared_mfma":
+                res[form]["rounds"] = int(max(i["t_evals"] for i in infos))
+                res[form]["ms_per_round"] = round(el / res[form]["rounds"] * 1e3, 4)
+                sol = vs
+            log(f"diff64 {pname} forward {form}: {el:.3f}s {res[form]}")
+        os.environ.pop("SPOCK_SHARED", None)
+        if pname == "fp32":
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ok = True
+            for b in range(len(insts)):
+                v1 = torch.zeros(gp.n_v, dtype=dt, device="cuda")
+                ok = gp.solve(x0s[b], v1, s)["status"] == "converged" and ok
+            torch.cuda.synchronize()
+            res["per_instance_spock_solve"] = {"seconds": round(time.perf_counter() - t0, 4), "all_converged": ok}
+            log(f"diff64 {pname} forward one by one: {res['per_instance_spock_solve']}")
+        gut = torch.as_tensor(gu, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its, ok = [], True
+        for b in range(nadj):
+            _, _, _, bi = gp.backward(sol[b], x0s[b], gV=1.0, gu0=gut,
+                                      settings=SP.default_settings(eps_abs=beps, max_iters=200000))
+            its.append(bi["iters"])
+            ok = ok and bi["status"] == "converged"
+        torch.cuda.synchronize()
+        res["adjoint"] = {"instances": nadj, "eps": beps, "seconds": round(time.perf_counter() - t0, 4),
+                          "all_converged": ok, "J_T_applications_mean": round(float(np.mean(its)), 1),
+                          "J_T_applications_max": int(np.max(its))}
+        log(f"diff64 {pname} adjoint: {res['adjoint']}")
+        out[pname] = res
+        gp.close()
+    return out
+
+
+def leg_shared64(torch, SP, G):
+    """One FP32 forward of the 64-instance workload by the shared-tree form
+    alone (eps 1e-5), for kernel profiles of that form."""
+    insts = G.make_batch(5)
+    gp = SP.Problem.from_instance(insts[0], precision=SP.FP32)
+    x0s = [torch.as_tensor(i.x0, dtype=torch.float64, device="cuda") for i in insts]
+    vs = [torch.zeros(gp.n_v, dtype=torch.float32, device="cuda") for _ in insts]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = SP.solve_batched([gp] * len(insts), x0s, vs, SP.default_settings(eps_abs=1e-5, eps_rel=1e-5))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    rounds = int(max(i["t_evals"] for i in infos))
+    out = {"seconds": round(el, 4), "rounds": rounds, "ms_per_round": round(el / rounds * 1e3, 4),
+           "all_converged": all(i["status"] == "converged" for i in infos), "mapping": infos[0]["mapping"]}
+    log(f"shared64: {out}")
+    gp.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -460,7 +550,7 @@ def main():
     ap.add_argument("--horizons", default="3,6,9,12,15")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--legs", default="fp64,budget,223,512,fp32err,datacentre,scaling,mpc",
+    ap.add_argument("--legs", default="fp64,budget,223,512,fp32err,datacentre,scaling,mpc,diff64",
                     help="comma-separated extra legs to run (see the module docstring)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of 512 MiB (reference for the memory-traffic counters)")
@@ -538,6 +628,10 @@ def main():
         extras["datacentre_cp_vs_spock"] = leg_datacentre(torch, SP, G)
     if "mpc" in legs:
         extras["datacentre_closed_loop_mpc"] = leg_mpc(torch, SP, G)
+    if "diff64" in legs:
+        extras["differentiation_64_instances"] = leg_diff64(torch, SP, G)
+    if "shared64" in legs:
+        extras["shared_forward_64_instances"] = leg_shared64(torch, SP, G)
     if "scaling" in legs:
         extras["datacentre_scaling"] = leg_scaling(torch, SP, G, [int(n) for n in args.horizons.split(",")])
     cpu = None

@@ -49,21 +49,31 @@ struct Mfma<double> {
 };
 
 constexpr int kShCols = 16;   // instances per MFMA tile
-constexpr int kShWaves = 8;   // wavefronts per workgroup of the sweeps
+constexpr int kShWaves = 16;  // wavefronts per workgroup of the sweeps
+constexpr int kShRed = 1024;  // threads of the per-instance reductions
 
 // acc += A[m0 .. m0 + 16)[0 .. nin) X, A input-major (element (out o, in k)
-// at k nout + o), X column j (instance) at x + j * xs, element k at +k.
+// at k nout + o), X column j (instance) at x + j * xs, element k at +k;
+// nin <= 64. The operands of 8 steps (32 inputs) are loaded before their
+// MFMAs, so a chain waits for one round of loads per 32 inputs.
 template <typename S>
 __device__ __forceinline__ void tile_mma(typename Mfma<S>::acc_t& acc, const S* __restrict__ A, int nout, int nin,
                                          int m0, const S* __restrict__ x, long long xs, int lane) {
   const int r = lane & 15, kk = lane >> 4;
   const int m = m0 + r;
   const S* xj = x + (size_t)r * xs;
-  for (int k0 = 0; k0 < nin; k0 += 4) {
-    const int k = k0 + kk;
-    const S a = (m < nout && k < nin) ? A[(size_t)k * nout + m] : S(0);
-    const S b = (k < nin) ? xj[k] : S(0);
-    acc = Mfma<S>::step(a, b, acc);
+  for (int k0 = 0; k0 < nin; k0 += 32) {
+    S a[8], b[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int k = k0 + 4 * t + kk;
+      const bool in = k < nin;
+      a[t] = (in && m < nout) ? A[(size_t)k * nout + m] : S(0);
+      b[t] = in ? xj[k] : S(0);
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+      if (k0 + 4 * t < nin) acc = Mfma<S>::step(a[t], b[t], acc);
   }
 }
 
@@ -89,20 +99,26 @@ __global__ void __launch_bounds__(256) k_sh_pre(DevProb<S> P, const S* __restric
   fam_pre_team<S, T>(P, z, z + P.nz, Tv + b * vs, xbar + b * wx, ubar + b * wu, q + b * wx, f, lane);
 }
 
-// Both sweeps of Alg. 2 for 16 instances per workgroup; a wavefront per node
-// of a stage, workgroup barriers between stages. Backward (one mat-vec
+// Both sweeps of Alg. 2 for 16 instances per workgroup, workgroup barriers
+// between stages. The work of a stage is split into (node, 16-row tile)
+// items spread over the wavefronts: backward, the tiles of d^i and of q^i
+// (independent given the children's q); forward, the tiles of u^i and of
+// every child's x^c (independent given x^i and d^i). Backward (one mat-vec
 // phase): d^i = R~^{-1} ubar^i + sum_c Bt^c q^c, q^i = P1 ubar^i - xbar^i +
 // sum_c At^c q^c. Forward: u^i = K x^i + d^i, x^c = Abar^c x^i + B^c d^i.
+// maxch: the largest number of children of a node.
 template <typename S>
 __global__ void __launch_bounds__(64 * kShWaves) k_sh_sweeps(DevProb<S> P, const int* __restrict__ stage_off,
                                                               S* __restrict__ Tv, const double* __restrict__ x0s,
                                                               S* __restrict__ xbar, S* __restrict__ ubar,
-                                                              S* __restrict__ q, S* __restrict__ d, long long vs) {
+                                                              S* __restrict__ q, S* __restrict__ d, long long vs,
+                                                              int maxch) {
   using acc_t = typename Mfma<S>::acc_t;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, kk = lane >> 4;
   const size_t b0 = (size_t)blockIdx.x * kShCols;
   const int nx = P.nx, nu = P.nu;
+  const int tu = (nu + 15) / 16, tx = (nx + 15) / 16;
   const long long wx = (long long)P.nn * nx, wu = (long long)P.nn * nu;
   const Off<S> O(P);
   S* q0 = q + b0 * wx;
@@ -111,10 +127,14 @@ __global__ void __launch_bounds__(64 * kShWaves) k_sh_sweeps(DevProb<S> P, const
   const S* ub0 = ubar + b0 * wu;
   S* z0 = Tv + b0 * vs;
   for (int t = P.N - 1; t >= 0; --t) {
-    for (int i = stage_off[t] + wave; i < stage_off[t + 1]; i += kShWaves) {
+    const int a = stage_off[t];
+    const int items = (stage_off[t + 1] - a) * (tu + tx);
+    for (int it = wave; it < items; it += kShWaves) {
+      const int i = a + it / (tu + tx), sub = it % (tu + tx);
       const int fc = P.fc[i], n = P.nch[i];
-      for (int m0 = 0; m0 < nu; m0 += 16) {
-        acc_t acc = zero_acc<S>();
+      acc_t acc = zero_acc<S>();
+      if (sub < tu) {  // d^i, rows 16 sub ..
+        const int m0 = 16 * sub;
         tile_mma<S>(acc, P.Rinv + (size_t)i * nu * nu, nu, nu, m0, ub0 + (size_t)i * nu, wu, lane);
         for (int k = 0; k < n; ++k)
           tile_mma<S>(acc, P.BtR + (size_t)(fc + k) * nx * nu, nu, nx, m0, q0 + (size_t)(fc + k) * nx, wx, lane);
@@ -123,9 +143,8 @@ __global__ void __launch_bounds__(64 * kShWaves) k_sh_sweeps(DevProb<S> P, const
           const int m = m0 + Mfma<S>::row(kk, r);
           if (m < nu) d0[(size_t)col * wu + (size_t)i * nu + m] = acc[r];
         }
-      }
-      for (int m0 = 0; m0 < nx; m0 += 16) {
-        acc_t acc = zero_acc<S>();
+      } else {  // q^i
+        const int m0 = 16 * (sub - tu);
         tile_mma<S>(acc, P.P1C + (size_t)i * nu * nx, nx, nu, m0, ub0 + (size_t)i * nu, wu, lane);
         for (int k = 0; k < n; ++k)
           tile_mma<S>(acc, P.AtR + (size_t)(fc + k) * nx * nx, nx, nx, m0, q0 + (size_t)(fc + k) * nx, wx, lane);
@@ -147,31 +166,34 @@ __global__ void __launch_bounds__(64 * kShWaves) k_sh_sweeps(DevProb<S> P, const
     z0[(size_t)j * vs + O.x(0) + o] = (S)x0s[(b0 + j) * nx + o];
   }
   __syncthreads();
+  const int per = tu + maxch * tx;
   for (int t = 0; t < P.N; ++t) {
-    for (int i = stage_off[t] + wave; i < stage_off[t + 1]; i += kShWaves) {
+    const int a = stage_off[t];
+    const int items = (stage_off[t + 1] - a) * per;
+    for (int it = wave; it < items; it += kShWaves) {
+      const int i = a + it / per, sub = it % per;
       const int fc = P.fc[i], n = P.nch[i];
       const S* xi = z0 + O.x(i);
       const S* di = d0 + (size_t)i * nu;
-      for (int m0 = 0; m0 < nu; m0 += 16) {
-        acc_t acc = zero_acc<S>();
+      acc_t acc = zero_acc<S>();
+      if (sub < tu) {  // u^i
+        const int m0 = 16 * sub;
         tile_mma<S>(acc, P.KC + (size_t)i * nx * nu, nu, nx, m0, xi, vs, lane);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int m = m0 + Mfma<S>::row(kk, r);
           if (m < nu) z0[(size_t)col * vs + O.u(i) + m] = acc[r] + di[(size_t)col * wu + m];
         }
-      }
-      for (int k = 0; k < n; ++k) {
+      } else {  // x^c of child k
+        const int k = (sub - tu) / tx, m0 = 16 * ((sub - tu) % tx);
+        if (k >= n) continue;
         const int c = fc + k;
-        for (int m0 = 0; m0 < nx; m0 += 16) {
-          acc_t acc = zero_acc<S>();
-          tile_mma<S>(acc, P.AbC + (size_t)c * nx * nx, nx, nx, m0, xi, vs, lane);
-          tile_mma<S>(acc, P.BC + (size_t)c * nu * nx, nx, nu, m0, di, wu, lane);
+        tile_mma<S>(acc, P.AbC + (size_t)c * nx * nx, nx, nx, m0, xi, vs, lane);
+        tile_mma<S>(acc, P.BC + (size_t)c * nu * nx, nx, nu, m0, di, wu, lane);
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int m = m0 + Mfma<S>::row(kk, r);
-            if (m < nx) z0[(size_t)col * vs + O.x(c) + m] = acc[r];
-          }
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + Mfma<S>::row(kk, r);
+          if (m < nx) z0[(size_t)col * vs + O.x(c) + m] = acc[r];
         }
       }
     }
@@ -239,16 +261,23 @@ __global__ void __launch_bounds__(256) k_sh_stats(const double* __restrict__ par
   }
 }
 
-// Fixed-order sum of K per-thread values over the block; the result in red[j][0].
+// Fixed-order sum of K per-thread values over the workgroup (wavefront
+// butterflies, then the wavefront sums in order); the result in red[j][0].
 template <int K>
-__device__ __forceinline__ void sh_block_sums(const double (&acc)[K], double (*red)[256]) {
-  for (int j = 0; j < K; ++j) red[j][threadIdx.x] = acc[j];
+__device__ __forceinline__ void sh_block_sums(double (&acc)[K], double (*red)[kShRed / 64]) {
+#pragma unroll
+  for (int j = 0; j < K; ++j)
+    for (int o = 32; o >= 1; o >>= 1) acc[j] += __shfl_xor(acc[j], o, 64);
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int j = 0; j < K; ++j) red[j][w] = acc[j];
   __syncthreads();
-  for (int s = blockDim.x / 2; s >= 1; s >>= 1) {
-    if ((int)threadIdx.x < s)
-      for (int j = 0; j < K; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + s];
-    __syncthreads();
+  if ((int)threadIdx.x < K) {
+    double s = 0;
+    for (int k = 0; k < nw; ++k) s += red[threadIdx.x][k];
+    red[threadIdx.x][0] = s;
   }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------- vector steps
@@ -314,9 +343,9 @@ __global__ void __launch_bounds__(256) k_sh_commit(ShVec<S> V, const int* __rest
 // dot products dots[b][s] = <dR_s, dR>, dots[b][kAAMax + s] = <dR_s, r> for
 // s < m (the new slot's own column included). One workgroup per instance.
 template <typename S>
-__global__ void __launch_bounds__(256) k_sh_push(ShVec<S> V, const int* __restrict__ mode, const int* __restrict__ ns,
-                                                 int m, double* __restrict__ dots) {
-  __shared__ double red[2 * kAAMax][256];
+__global__ void __launch_bounds__(kShRed) k_sh_push(ShVec<S> V, const int* __restrict__ mode, const int* __restrict__ ns,
+                                                    int m, double* __restrict__ dots) {
+  __shared__ double red[2 * kAAMax][kShRed / 64];
   const size_t b = blockIdx.x;
   const int md = mode[b];
   if (md == 0) return;
@@ -380,8 +409,8 @@ __global__ void __launch_bounds__(256) k_sh_M(DevProb<S> P, ShVec<S> V, const in
 
 // out[b] = <vt - tvt, md> (mask[b]), one workgroup per instance
 template <typename S>
-__global__ void __launch_bounds__(256) k_sh_rdot(ShVec<S> V, const int* __restrict__ mask, double* __restrict__ out) {
-  __shared__ double red[1][256];
+__global__ void __launch_bounds__(kShRed) k_sh_rdot(ShVec<S> V, const int* __restrict__ mask, double* __restrict__ out) {
+  __shared__ double red[1][kShRed / 64];
   const size_t b = blockIdx.x;
   if (!mask[b]) return;
   const size_t o = b * V.vs;
@@ -735,6 +764,8 @@ int shared_solve(Problem& P, int B, const double* const* x0, const spock_setting
   const Par hp_dir = par_at(par_h, kParDir), dp_dir = par_at(par_d, kParDir);
   const Par dp_cand = par_at(par_d, kParCand);
   const int sweep_grid = Bp / kShCols;
+  int maxch = 1;
+  for (int i = 0; i < Tr.nl; ++i) maxch = std::max(maxch, Tr.nch[i]);
   std::vector<char> prep(Bp), head(Bp);
   while (any_active()) {
     // ---- one evaluation of T at vt for every instance
@@ -745,7 +776,7 @@ int shared_solve(Problem& P, int B, const double* const* x0, const spock_setting
       default: sh_launch_pre<S, 64>(P, D, V, xbar, ubar, q, Bp, st); break;
     }
     hipLaunchKernelGGL(k_sh_sweeps<S>, dim3(sweep_grid), dim3(64 * kShWaves), 0, st, D, P.d_stage_off, V.tvt, x0s,
-                       xbar, ubar, q, d, vs);
+                       xbar, ubar, q, d, vs, maxch);
     switch (T) {
       case 8: sh_launch_post<S, 8>(P, D, V, partials, Bp, st); break;
       case 16: sh_launch_post<S, 16>(P, D, V, partials, Bp, st); break;
@@ -760,7 +791,7 @@ int shared_solve(Problem& P, int B, const double* const* x0, const spock_setting
       if (I[b].active && I[b].phase == kShLS) any_ls = hp_rdot.mask[b] = 1;
     if (any_ls) {
       if (int rc = upload(kParRdot)) return rc;
-      hipLaunchKernelGGL(k_sh_rdot<S>, dim3(Bp), dim3(256), 0, st, V, dp_rdot.mask, rdot_d);
+      hipLaunchKernelGGL(k_sh_rdot<S>, dim3(Bp), dim3(kShRed), 0, st, V, dp_rdot.mask, rdot_d);
     }
     SH_TRY(hipGetLastError());
     SH_TRY(hipMemcpyAsync(hres, res, sizeof(double) * (size_t)Bp * 9, hipMemcpyDeviceToHost, st));
@@ -887,7 +918,7 @@ int shared_solve(Problem& P, int B, const double* const* x0, const spock_setting
     }
     if (any_prep) {
       if (int rc = upload(kParPush)) return rc;
-      hipLaunchKernelGGL(k_sh_push<S>, dim3(Bp), dim3(256), 0, st, V, dp_push.mode, dp_push.slot, s.m, dots_d);
+      hipLaunchKernelGGL(k_sh_push<S>, dim3(Bp), dim3(kShRed), 0, st, V, dp_push.mode, dp_push.slot, s.m, dots_d);
       if (any_push) {
         SH_TRY(hipMemcpyAsync(hdots, dots_d, sizeof(double) * (size_t)Bp * 2 * kAAMax, hipMemcpyDeviceToHost, st));
         SH_TRY(hipStreamSynchronize(st));
