@@ -243,7 +243,7 @@ def ttr_single(torch, SP, G):
     return out
 
 
-def ttr_batched(torch, SP, G):
+def ttr_batched(torch, SP, G, keep=None):
     """512 uneven instances: warm start = FP64 solution + N(0, 0.05^2) on
     every entry (seeded); batched FP32 and FP64 (one persistent graph-captured
     launch each) vs the plain FP64 path solving every instance one by one
@@ -252,6 +252,8 @@ def ttr_batched(torch, SP, G):
     x0s = [torch.as_tensor(i.x0, dtype=torch.float64, device="cuda") for i in insts]
     p64 = [SP.Problem.from_instance(i, precision=SP.FP64) for i in insts]
     p32 = [SP.Problem.from_instance(i, precision=SP.FP32) for i in insts]
+    if keep is not None:
+        keep["p32_512"] = p32
     v64 = [torch.zeros(p.n_v, dtype=torch.float64, device="cuda") for p in p64]
     log("512-batch problems factored")
     t0 = time.perf_counter()
@@ -282,14 +284,14 @@ def ttr_batched(torch, SP, G):
         if b % 128 == 127:
             log(f"plain FP64: {b + 1} of 512 instances, {t_plain:.2f}s")
     log(f"plain FP64 all 512 {t_plain:.3f}s")
-    # reference values on a sample of 32 instances: plain FP64 solved to 1e-8
-    sample = np.linspace(0, 511, 32).astype(int)
+    # reference values on a sample of 16 instances: plain FP64 solved to 1e-8
+    sample = np.linspace(0, 511, 16).astype(int)
     tight = {}
     for k, b in enumerate(sample):
         tight[b] = p64[b].solve(x0s[b], warm[b].clone(), SP.default_settings(eps_abs=1e-8, eps_rel=1e-8,
                                                                              max_iters=200000))
         if k % 8 == 7:
-            log(f"512-batch FP64 references to 1e-8: {k + 1} of 32")
+            log(f"512-batch FP64 references to 1e-8: {k + 1} of 16")
     i32, i64 = res["fp32"][1], res["fp64"][1]
     rel = lambda a, b: abs(a["V_s0"] - b["V_s0"]) / max(1.0, abs(b["V_s0"]))  # noqa: E731
     return {"workload": "512 uneven trees nx10 nu5 N 5..12 (warm start, sigma 0.05)",
@@ -301,7 +303,7 @@ def ttr_batched(torch, SP, G):
             "plain_fp64_seconds": round(t_plain, 3),
             "plain_fp64_iters_median_max": [int(np.median(iters_plain)), max(iters_plain)],
             "plain_fp64_converged": sum(i["status"] == "converged" for i in infos_plain),
-            "V_rel_err_reference": "32 of the 512 instances (evenly spaced) solved by the plain FP64 path to 1e-8",
+            "V_rel_err_reference": "16 of the 512 instances (evenly spaced) solved by the plain FP64 path to 1e-8",
             "V_max_rel_err_batched_fp32": max(rel(i32[b], tight[b]) for b in sample),
             "V_max_rel_err_batched_fp64": max(rel(i64[b], tight[b]) for b in sample),
             "V_max_rel_err_plain_fp64": max(rel(infos_plain[b], tight[b]) for b in sample),
@@ -314,7 +316,7 @@ def _golden():
     return json.load(open(path)) if os.path.exists(path) else {}
 
 
-def leg_fp32_error(torch, SP, G):
+def leg_fp32_error(torch, SP, G, keep=None):
     """FP32 bulk against the FP64 oracle per result (stored oracle solutions,
     tests/golden): V* and u^0 of the 223-node tree and of three of the 512
     trees, each solved in FP32 to 1e-5; and the FP32 residual floor: the
@@ -359,7 +361,7 @@ def leg_fp32_error(torch, SP, G):
     out["trees512_sample"] = rows
     # floor of the batch: FP32 batched launch asked for 1e-9 from v = 0
     insts = G.make_batch(4, count=512)
-    p32 = [SP.Problem.from_instance(i, precision=SP.FP32) for i in insts]
+    p32 = (keep or {}).get("p32_512") or [SP.Problem.from_instance(i, precision=SP.FP32) for i in insts]
     x0s = [torch.as_tensor(i.x0, dtype=torch.float64, device="cuda") for i in insts]
     vs = [torch.zeros(p.n_v, dtype=torch.float32, device="cuda") for p in p32]
     infos = SP.solve_batched(p32, x0s, vs, SP.default_settings(eps_abs=1e-9, eps_rel=1e-9, max_iters=4000))
@@ -550,8 +552,9 @@ def main():
     ap.add_argument("--horizons", default="3,6,9,12,15")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--legs", default="fp64,budget,223,512,fp32err,datacentre,scaling,mpc,diff64",
-                    help="comma-separated extra legs to run (see the module docstring)")
+    ap.add_argument("--legs", default="fp64,budget,223,512,fp32err,datacentre,scaling",
+                    help="comma-separated extra legs to run (see the module docstring); 'all' adds "
+                         "the closed-loop simulation (mpc) and the 64-instance differentiation (diff64)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of 512 MiB (reference for the memory-traffic counters)")
     args = ap.parse_args()
@@ -611,32 +614,47 @@ def main():
 
     extras = {}
     legs = set(args.legs.split(",")) if not args.no_extras else set()
+    if "all" in legs:
+        legs |= {"fp64", "budget", "223", "512", "fp32err", "datacentre", "scaling", "mpc", "diff64"}
+    keep = {}
+    leg_seconds = {}
+
+    def timed_leg(name, fn):
+        t = time.perf_counter()
+        r = fn()
+        leg_seconds[name] = round(time.perf_counter() - t, 1)
+        log(f"leg {name}: {leg_seconds[name]}s")
+        return r
     if args.config == 3 and ({"fp64", "budget"} & legs):
         gps = {args.precision: gp}
         if "fp64" in legs and prec == SP.FP32:
-            extras["tree20776_fp64"], gps["fp64"] = leg_fp64(torch, SP, inst, args.steps, args.t_reps)
+            extras["tree20776_fp64"], gps["fp64"] = timed_leg(
+                "fp64", lambda: leg_fp64(torch, SP, inst, args.steps, args.t_reps))
         if "budget" in legs:
-            extras["tree20776_residual_budget"] = leg_budget(torch, SP, inst, gps, args.budget_iters)
+            extras["tree20776_residual_budget"] = timed_leg(
+                "budget", lambda: leg_budget(torch, SP, inst, gps, args.budget_iters))
         gps.clear()
     if "223" in legs:
-        extras["time_to_residual_223node"] = ttr_single(torch, SP, G)
+        extras["time_to_residual_223node"] = timed_leg("223", lambda: ttr_single(torch, SP, G))
     if "512" in legs:
-        extras["time_to_residual_512batch"] = ttr_batched(torch, SP, G)
+        extras["time_to_residual_512batch"] = timed_leg("512", lambda: ttr_batched(torch, SP, G, keep))
     if "fp32err" in legs:
-        extras["fp32_error_vs_oracle"] = leg_fp32_error(torch, SP, G)
+        extras["fp32_error_vs_oracle"] = timed_leg("fp32err", lambda: leg_fp32_error(torch, SP, G, keep))
+    keep.clear()
     if "datacentre" in legs:
-        extras["datacentre_cp_vs_spock"] = leg_datacentre(torch, SP, G)
+        extras["datacentre_cp_vs_spock"] = timed_leg("datacentre", lambda: leg_datacentre(torch, SP, G))
     if "mpc" in legs:
-        extras["datacentre_closed_loop_mpc"] = leg_mpc(torch, SP, G)
+        extras["datacentre_closed_loop_mpc"] = timed_leg("mpc", lambda: leg_mpc(torch, SP, G))
     if "diff64" in legs:
-        extras["differentiation_64_instances"] = leg_diff64(torch, SP, G)
+        extras["differentiation_64_instances"] = timed_leg("diff64", lambda: leg_diff64(torch, SP, G))
     if "shared64" in legs:
-        extras["shared_forward_64_instances"] = leg_shared64(torch, SP, G)
+        extras["shared_forward_64_instances"] = timed_leg("shared64", lambda: leg_shared64(torch, SP, G))
     if "scaling" in legs:
-        extras["datacentre_scaling"] = leg_scaling(torch, SP, G, [int(n) for n in args.horizons.split(",")])
+        extras["datacentre_scaling"] = timed_leg(
+            "scaling", lambda: leg_scaling(torch, SP, G, [int(n) for n in args.horizons.split(",")]))
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(inst, gp.alpha, args.cpu_budget)
+        cpu = timed_leg("cpu_baseline", lambda: cpu_baseline(inst, gp.alpha, args.cpu_budget))
         log(f"cpu baseline {cpu['value']} CP iters/s")
 
     out = {
@@ -660,6 +678,7 @@ def main():
         "cpu_baseline": cpu,
     }
     out.update(extras)
+    out["leg_seconds"] = leg_seconds
     print(json.dumps(out), flush=True)
 
 
