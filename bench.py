@@ -217,6 +217,18 @@ def leg_budget(torch, SP, inst, gps, iters):
                      "reached": info["status"] == "converged", "V_s0": info["V_s0"],
                      "counts": {k: info[k] for k in ("n_k0", "n_k1", "n_k2", "n_km", "n_backtracks")}}
         log(f"20776-node {name} budget: xi {info['xi0']:.4g} -> {info['xi']:.4g} in {sec:.2f}s")
+    # Anderson memory within the paper's range (section 6.2: 3 to 10), FP32
+    gp = gps.get("fp32")
+    if gp is not None:
+        out["fp32_by_memory"] = {}
+        for m in (5, 10):
+            v = torch.zeros(gp.n_v, dtype=gp.torch_dtype, device="cuda")
+            sec, info = timed_solve(torch, gp, x0, v, SP.default_settings(max_iters=iters, m=m))
+            its = max(1, info["iters"])
+            out["fp32_by_memory"][m] = {"seconds": round(sec, 3), "iters": info["iters"],
+                                        "t_evals": info["t_evals"], "xi": info["xi"],
+                                        "k2_share": round(info["n_k2"] / its, 3)}
+            log(f"20776-node fp32 budget m={m}: xi -> {info['xi']:.4g} in {sec:.2f}s")
     return out
 
 
@@ -240,6 +252,16 @@ def ttr_single(torch, SP, G):
                      "V_rel_err_vs_fp64": abs(info["V_s0"] - ref_V) / max(1.0, abs(ref_V)),
                      "mapping": info["mapping"]}
         log(f"223-node {name}: {info['status']} {info['iters']} iters {sec:.3f}s")
+        if name == "fp64":  # Anderson memory within the paper's range (section 6.2)
+            out["fp64_by_memory"] = {}
+            for m in (5, 10):
+                v.zero_()
+                sec, info = timed_solve(torch, gp, x0, v, SP.default_settings(max_iters=200000, m=m))
+                its = max(1, info["iters"])
+                out["fp64_by_memory"][m] = {"seconds": round(sec, 4), "iters": info["iters"],
+                                            "t_evals": info["t_evals"], "status": info["status"],
+                                            "k2_share": round(info["n_k2"] / its, 3)}
+                log(f"223-node fp64 m={m}: {info['status']} {info['iters']} iters {sec:.3f}s")
     return out
 
 
