@@ -53,6 +53,8 @@ class Layout:
                             for t in range(self.N + 1)]
         self.risk = getattr(inst, "risk", None)
         self.cons = getattr(inst, "cons", None)
+        # dense cost matrices (section 4.1 allows any Q, Q_N >= 0, R > 0)
+        self.dense_costs = any(getattr(inst, k, None) is not None for k in ("Qm", "Rm", "QNm"))
         self.ny = np.zeros(nn, dtype=np.int64)
         for i in self.nonleaf:
             self.ny[i] = (len(self.risk.b[i]) if self.risk is not None else 2 * len(self.children[i]) + 1)
@@ -165,6 +167,26 @@ class Layout:
         return 2 * len(self.children[i])
 
     # ---- constraint rows (section 4.1)
+    def cost_matrices(self, inst, c):
+        """(Q^c, R^c, Q_N^c) as matrices: the dense ones when the instance
+        carries them, else the diagonals."""
+        Q = inst.Qm[c] if getattr(inst, "Qm", None) is not None else np.diag(inst.q[c])
+        R = inst.Rm[c] if getattr(inst, "Rm", None) is not None else np.diag(inst.r[c])
+        QN = inst.QNm[c] if getattr(inst, "QNm", None) is not None else np.diag(inst.qN[c])
+        return Q, R, QN
+
+    def cost_roots(self, inst, c):
+        """Symmetric positive semidefinite square roots of (Q^c, R^c, Q_N^c),
+        the blocks that multiply x and u in the cost rows of eta (section
+        5.2): V diag(sqrt(lambda)) V' from the eigendecomposition."""
+        def root(M):
+            lam, V = np.linalg.eigh(0.5 * (M + M.T))
+            return (V * np.sqrt(np.maximum(lam, 0.0))) @ V.T
+        cache = self.__dict__.setdefault("_roots", {})
+        if c not in cache:
+            cache[c] = tuple(root(M) for M in self.cost_matrices(inst, c))
+        return cache[c]
+
     def gamma(self, inst, i):
         """(Gamma_x, Gamma_u, cmin, cmax) of nonleaf i."""
         if self.cons is not None:

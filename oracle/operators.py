@@ -25,14 +25,23 @@ def L_apply(lay: Layout, inst, z: np.ndarray) -> np.ndarray:
                                                 + Gu @ z[lay.u_off[i]: lay.u_off[i] + nu])
     for c in range(1, lay.num_nodes):
         i = lay.anc[c]
-        eta[lay.e2x[c]: lay.e2x[c] + nx] = np.sqrt(inst.q[c]) * z[lay.x_off[i]: lay.x_off[i] + nx]
-        eta[lay.e2u[c]: lay.e2u[c] + nu] = np.sqrt(inst.r[c]) * z[lay.u_off[i]: lay.u_off[i] + nu]
+        xi, ui = z[lay.x_off[i]: lay.x_off[i] + nx], z[lay.u_off[i]: lay.u_off[i] + nu]
+        if lay.dense_costs:
+            Qh, Rh, _ = lay.cost_roots(inst, c)
+            eta[lay.e2x[c]: lay.e2x[c] + nx] = Qh @ xi
+            eta[lay.e2u[c]: lay.e2u[c] + nu] = Rh @ ui
+        else:
+            eta[lay.e2x[c]: lay.e2x[c] + nx] = np.sqrt(inst.q[c]) * xi
+            eta[lay.e2u[c]: lay.e2u[c] + nu] = np.sqrt(inst.r[c]) * ui
         eta[lay.e2a[c]] = 0.5 * z[lay.tau_off[c]]
         eta[lay.e2b[c]] = 0.5 * z[lay.tau_off[c]]
     for j in lay.leaves:
         xj = z[lay.x_off[j]: lay.x_off[j] + nx]
         eta[lay.e3x[j]: lay.e3x[j] + lay.ncN] = lay.gamma_N(inst, j)[0] @ xj
-        eta[lay.e3q[j]: lay.e3q[j] + nx] = np.sqrt(inst.qN[j]) * xj
+        if lay.dense_costs:
+            eta[lay.e3q[j]: lay.e3q[j] + nx] = lay.cost_roots(inst, j)[2] @ xj
+        else:
+            eta[lay.e3q[j]: lay.e3q[j] + nx] = np.sqrt(inst.qN[j]) * xj
         eta[lay.e3a[j]] = 0.5 * z[lay.s_off[j]]
         eta[lay.e3b[j]] = 0.5 * z[lay.s_off[j]]
     return eta
@@ -53,12 +62,19 @@ def Lt_apply(lay: Layout, inst, eta: np.ndarray) -> np.ndarray:
         z[lay.u_off[i]: lay.u_off[i] + nu] += Gu.T @ e_c
     for c in range(1, lay.num_nodes):
         i = lay.anc[c]
-        z[lay.x_off[i]: lay.x_off[i] + nx] += np.sqrt(inst.q[c]) * eta[lay.e2x[c]: lay.e2x[c] + nx]
-        z[lay.u_off[i]: lay.u_off[i] + nu] += np.sqrt(inst.r[c]) * eta[lay.e2u[c]: lay.e2u[c] + nu]
+        ex, eu = eta[lay.e2x[c]: lay.e2x[c] + nx], eta[lay.e2u[c]: lay.e2u[c] + nu]
+        if lay.dense_costs:
+            Qh, Rh, _ = lay.cost_roots(inst, c)
+            z[lay.x_off[i]: lay.x_off[i] + nx] += Qh.T @ ex
+            z[lay.u_off[i]: lay.u_off[i] + nu] += Rh.T @ eu
+        else:
+            z[lay.x_off[i]: lay.x_off[i] + nx] += np.sqrt(inst.q[c]) * ex
+            z[lay.u_off[i]: lay.u_off[i] + nu] += np.sqrt(inst.r[c]) * eu
         z[lay.tau_off[c]] += 0.5 * (eta[lay.e2a[c]] + eta[lay.e2b[c]])
     for j in lay.leaves:
-        z[lay.x_off[j]: lay.x_off[j] + nx] += (lay.gamma_N(inst, j)[0].T @ eta[lay.e3x[j]: lay.e3x[j] + lay.ncN]
-                                             + np.sqrt(inst.qN[j]) * eta[lay.e3q[j]: lay.e3q[j] + nx])
+        eq = eta[lay.e3q[j]: lay.e3q[j] + nx]
+        qn = lay.cost_roots(inst, j)[2].T @ eq if lay.dense_costs else np.sqrt(inst.qN[j]) * eq
+        z[lay.x_off[j]: lay.x_off[j] + nx] += lay.gamma_N(inst, j)[0].T @ eta[lay.e3x[j]: lay.e3x[j] + lay.ncN] + qn
         z[lay.s_off[j]] += 0.5 * (eta[lay.e3a[j]] + eta[lay.e3b[j]])
     return z
 

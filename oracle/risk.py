@@ -57,11 +57,11 @@ def nested_cost(lay, inst, x: np.ndarray, u: np.ndarray) -> float:
     children c of (x^i'Q^c x^i + u^i'R^c u^i + V^c)."""
     V = np.zeros(lay.num_nodes)
     for j in lay.leaves:
-        V[j] = x[j] @ (inst.qN[j] * x[j])
+        V[j] = x[j] @ lay.cost_matrices(inst, j)[2] @ x[j]
     for t in range(lay.N - 1, -1, -1):
         for i in lay.stage_nodes[t]:
             ch = lay.children[i]
-            Z = np.array([x[i] @ (inst.q[c] * x[i]) + u[i] @ (inst.r[c] * u[i]) + V[c]
-                          for c in ch])
+            Z = np.array([x[i] @ lay.cost_matrices(inst, c)[0] @ x[i] + u[i] @ lay.cost_matrices(inst, c)[1] @ u[i]
+                          + V[c] for c in ch])
             V[i] = node_risk(lay, inst, i, Z)
     return float(V[0])

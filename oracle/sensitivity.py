@@ -23,6 +23,8 @@ from .operators import Lt_apply
 
 def envelope_gradients(prob, v):
     lay, inst = prob.lay, prob.inst
+    if lay.dense_costs:
+        raise NotImplementedError("gradients with respect to diagonal cost weights need diagonal costs")
     nx, nu = lay.nx, lay.nu
     z, eta = lay.split(v)
     # ---- diag Q (non-root c) and diag Q_N (leaves)
@@ -158,6 +160,8 @@ def T_jvp(prob, v, x0, dv, dx0=None, dq=None, dqN=None, point=None):
     """Derivative of T at (v, theta) along (dv, dtheta); dq and dqN are
     perturbations of the weight diagonals [num_nodes][nx]; point is
     T_point(prob, v, x0) if already at hand."""
+    if prob.lay.dense_costs:
+        raise NotImplementedError("gradients with respect to diagonal cost weights need diagonal costs")
     from .operators import L_apply, Lt_apply
     from .prox import proj_S1, proj_S2
     lay, inst, a = prob.lay, prob.inst, prob.alpha

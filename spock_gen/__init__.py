@@ -43,6 +43,8 @@ __all__ = [
     "make_datacentre",
     "make_random_small",
     "CONFIG_NAMES",
+    "dense_costs",
+    "rotate_states_inputs",
 ]
 
 
@@ -69,6 +71,11 @@ class Instance:
     # (ConstraintData); None: AV@R_a per node and the boxes
     risk: object = None
     cons: object = None
+    # dense cost matrices [num_nodes][nx][nx], [num_nodes][nu][nu] and
+    # [num_nodes][nx][nx] (section 4.1); None: the diagonals q, r, qN
+    Qm: object = None
+    Rm: object = None
+    QNm: object = None
 
     @property
     def num_nodes(self) -> int:
@@ -433,3 +440,50 @@ def make_general_small(seed: int, branching: Sequence[int], nx: int, nu: int, ka
         inst.cons = random_constraints(rng, inst, nc, ncN if ncN is not None else nx, bound)
     inst.name = f"general{seed}"
     return inst
+
+
+def _random_spd(rng: np.random.Generator, n: int, lo: float, hi: float) -> np.ndarray:
+    """U diag(lam) U' with U Haar-orthogonal and lam ~ U[lo, hi]."""
+    g = rng.standard_normal((n, n))
+    qm, rr = np.linalg.qr(g)
+    qm = qm * np.sign(np.diag(rr))
+    return (qm * rng.uniform(lo, hi, size=n)) @ qm.T
+
+
+def dense_costs(inst: Instance, seed: int) -> Instance:
+    """A copy of inst with dense symmetric positive definite Q^c, R^c, Q_N^j
+    (eigenvalues in [0.5, 2], [0.1, 1], [0.5, 2]) in place of the diagonals."""
+    out = inst.copy()
+    rng = np.random.default_rng([seed, 91])
+    nn, nx, nu = inst.num_nodes, inst.nx, inst.nu
+    out.Qm = np.stack([_random_spd(rng, nx, 0.5, 2.0) for _ in range(nn)])
+    out.Rm = np.stack([_random_spd(rng, nu, 0.1, 1.0) for _ in range(nn)])
+    out.QNm = np.stack([_random_spd(rng, nx, 0.5, 2.0) for _ in range(nn)])
+    out.name = inst.name + "+dense"
+    return out
+
+
+def rotate_states_inputs(inst: Instance, U: np.ndarray, W: np.ndarray) -> Instance:
+    """The same problem in the coordinates x' = U x, u' = W u (U, W
+    orthogonal): A' = U A U', B' = U B W', Q' = U Q U', R' = W R W',
+    Q_N' = U Q_N U' (dense), x0' = U x0. The boxes are not invariant under
+    the rotation and are widened to +-1e6 (callers keep them inactive)."""
+    out = inst.copy()
+    nn = inst.num_nodes
+    out.A = np.stack([U @ inst.A[c] @ U.T for c in range(nn)])
+    out.B = np.stack([U @ inst.B[c] @ W.T for c in range(nn)])
+    Q = inst.Qm if inst.Qm is not None else np.stack([np.diag(q) for q in inst.q])
+    R = inst.Rm if inst.Rm is not None else np.stack([np.diag(r) for r in inst.r])
+    QN = inst.QNm if inst.QNm is not None else np.stack([np.diag(q) for q in inst.qN])
+    out.Qm = np.stack([U @ Q[c] @ U.T for c in range(nn)])
+    out.Rm = np.stack([W @ R[c] @ W.T for c in range(nn)])
+    out.QNm = np.stack([U @ QN[c] @ U.T for c in range(nn)])
+    out.x0 = U @ inst.x0
+    big = 1e6
+    out.xmin = np.full_like(inst.xmin, -big)
+    out.xmax = np.full_like(inst.xmax, big)
+    out.umin = np.full_like(inst.umin, -big)
+    out.umax = np.full_like(inst.umax, big)
+    out.name = inst.name + "+rotated"
+    return out
+

@@ -41,13 +41,17 @@ class NestedDP:
         inst = self.inst
         self.max_abs_x = max(self.max_abs_x, float(np.max(np.abs(x))))
         if not self.ch[i]:
+            if getattr(inst, "QNm", None) is not None:
+                return float(x @ inst.QNm[i] @ x)
             return float(x @ (inst.qN[i] * x))
         p = [inst.prob[c] / inst.prob[i] for c in self.ch[i]]
 
         def obj(uu):
             Z = []
             for c in self.ch[i]:
-                ell = float(x @ (inst.q[c] * x) + inst.r[c][0] * uu * uu)
+                qx = inst.Qm[c] @ x if getattr(inst, "Qm", None) is not None else inst.q[c] * x
+                rr = inst.Rm[c][0, 0] if getattr(inst, "Rm", None) is not None else inst.r[c][0]
+                ell = float(x @ qx + rr * uu * uu)
                 xc = inst.A[c] @ x + inst.B[c][:, 0] * uu
                 Z.append(ell + self.value(c, xc))
             return self.risk(i, Z) if self.risk is not None else _avar(Z, p, inst.a_risk[i])

@@ -71,6 +71,7 @@ def nullspace_projection(G, w):
 
 def tree_lqr(inst, x0):
     """Risk-neutral tree LQR (a = 1, boxes inactive): returns V* and u^0."""
+    assert getattr(inst, "Qm", None) is None, "diagonal costs only"
     anc = inst.anc
     nn = len(anc)
     ch, stage = tree_lists(anc)

@@ -30,6 +30,7 @@ from .dense import tree_lists
 
 class EpigraphIPM:
     def __init__(self, inst, x0=None):
+        assert getattr(inst, "Qm", None) is None and getattr(inst, "Rm", None) is None, "diagonal costs only"
         self.inst = inst
         self.x0 = np.asarray(inst.x0 if x0 is None else x0, float)
         anc = np.asarray(inst.anc)
