@@ -85,7 +85,8 @@ int spock_tree_shape(const spock_tree* tree, int32_t* N, int32_t* num_nonleaf,
 /* Problem data (section 4.1, "Dynamics", "Constraints", "Quadratic costs";
  * section 4.2 for AV@R). Host arrays, row-major, indexed by node; row 0 of
  * per-edge data (A, B, q, r) is unused. Q, R and Q_N are diagonal and given by
- * their diagonals; the constraint sets are boxes (Gamma = identity).
+ * their diagonals unless the dense matrices below are given; the constraint
+ * sets are boxes (Gamma = identity) unless polyhedral rows are given.
  *   A  [num_nodes][nx][nx], B [num_nodes][nx][nu]: x^c = A^c x^{anc c} + B^c u^{anc c}
  *   q  [num_nodes][nx] > 0, r [num_nodes][nu] > 0: stage cost x'Q^c x + u'R^c u charged at c
  *   qN [num_nodes][nx] >= 0: terminal cost x'Q_N x, read at leaves
@@ -137,6 +138,16 @@ typedef struct {
   /* NULL: the boxes xmin..umax. Otherwise the polyhedral constraints above
    * (the boxes are not read, and x0 is not checked against a root box). */
   const spock_constraint_data* cons;
+  /* NULL: the diagonals q, r, qN. Otherwise dense symmetric cost matrices
+   * (section 4.1), all three: Qm [num_nodes][nx][nx] (row c: Q^c, positive
+   * semidefinite), Rm [num_nodes][nu][nu] (positive definite) and QNm
+   * [num_nodes][nx][nx] (positive semidefinite, read at leaves); q, r, qN are
+   * then not read (may be NULL). The cost rows of L carry their symmetric
+   * square roots. A problem with dense costs runs the general kernels.
+   * Errors: SPOCK_EINVAL when only some are given, or a matrix is not finite,
+   * not symmetric (1e-12 relative) or not (semi)definite as stated; the
+   * batched engines and spock_backward return SPOCK_EUNSUPPORTED for it. */
+  const double *Qm, *Rm, *QNm;
 } spock_problem_data;
 
 /* Runs Alg. 1 (offline S1 factorisation) in FP64 on the host, computes ||L||

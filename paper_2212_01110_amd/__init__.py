@@ -63,7 +63,8 @@ class _ProblemData(ctypes.Structure):
                 ("umin", ctypes.c_void_p), ("umax", ctypes.c_void_p),
                 ("a_risk", ctypes.c_void_p), ("precision", ctypes.c_int32),
                 ("alpha", ctypes.c_double),
-                ("risk", ctypes.POINTER(_RiskData)), ("cons", ctypes.POINTER(_ConstraintData))]
+                ("risk", ctypes.POINTER(_RiskData)), ("cons", ctypes.POINTER(_ConstraintData)),
+                ("Qm", ctypes.c_void_p), ("Rm", ctypes.c_void_p), ("QNm", ctypes.c_void_p)]
 
 
 def _risk_struct(risk, anc, keep):
@@ -237,11 +238,13 @@ class Problem:
     """Factored problem on the device (Alg. 1 in FP64, storage in `precision`)."""
 
     def __init__(self, tree: Tree, nx, nu, A, B, q, r, qN, xmin, xmax, umin, umax, a_risk,
-                 precision=FP64, alpha=0.0, risk=None, cons=None):
+                 precision=FP64, alpha=0.0, risk=None, cons=None, Qm=None, Rm=None, QNm=None):
+        """Dense costs: Qm, Rm, QNm (num_nodes x n x n each, all three or
+        none) replace the diagonals q, r, qN, which may then be None."""
         self.tree = tree
         arrs = {k: np.ascontiguousarray(v, dtype=np.float64) for k, v in
                 dict(A=A, B=B, q=q, r=r, qN=qN, xmin=xmin, xmax=xmax, umin=umin,
-                     umax=umax, a_risk=a_risk).items()}
+                     umax=umax, a_risk=a_risk, Qm=Qm, Rm=Rm, QNm=QNm).items() if v is not None}
         self._keep = arrs
         self._risk, self._cons = risk, cons
         extra = {}
@@ -271,7 +274,8 @@ class Problem:
         tree = tree or Tree(inst.anc, inst.prob)
         return cls(tree, inst.nx, inst.nu, inst.A, inst.B, inst.q, inst.r, inst.qN, inst.xmin,
                    inst.xmax, inst.umin, inst.umax, inst.a_risk, precision, alpha,
-                   getattr(inst, "risk", None), getattr(inst, "cons", None))
+                   getattr(inst, "risk", None), getattr(inst, "cons", None),
+                   getattr(inst, "Qm", None), getattr(inst, "Rm", None), getattr(inst, "QNm", None))
 
     def mapping(self) -> dict:
         """Mapping the next evaluation of T uses, the dataflow grid, and
@@ -303,13 +307,14 @@ class Problem:
                 k[name] = np.asarray(val, dtype=np.float64)
         if x_box is not None:
             k["xmin"], k["xmax"] = (np.asarray(b, dtype=np.float64) for b in x_box)
-        return Problem(self.tree, self.nx, self.nu, k["A"], k["B"], k["q"], k["r"], k["qN"], k["xmin"],
-                       k["xmax"], k["umin"], k["umax"], k["a_risk"],
-                       self.precision if precision is None else precision, alpha, self._risk, self._cons)
+        return Problem(self.tree, self.nx, self.nu, k["A"], k["B"], k.get("q"), k.get("r"), k.get("qN"),
+                       k["xmin"], k["xmax"], k["umin"], k["umax"], k["a_risk"],
+                       self.precision if precision is None else precision, alpha, self._risk, self._cons,
+                       k.get("Qm"), k.get("Rm"), k.get("QNm"))
 
     @property
     def q(self) -> np.ndarray:
-        return self._keep["q"]
+        return self._keep.get("q")
 
     # ---- entry points
     def solve(self, x0, v, settings: Settings | None = None) -> dict:

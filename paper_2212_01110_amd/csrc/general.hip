@@ -48,6 +48,23 @@ struct GOff {
   __device__ const S* Gx(int i) const { return G.Gx + (size_t)i * G.nc * P.nx; }
   __device__ const S* Gu(int i) const { return G.Gu + (size_t)i * G.nc * P.nu; }
   __device__ const S* GN(int j) const { return G.GN + (size_t)(j - P.nl) * G.ncN * P.nx; }
+  // Row o of a cost root applied to the vector f(base + k), k < n: kind 0
+  // Q^c (on x), 1 R^c (on u), 2 Q_N^c (on x). Dense symmetric roots when the
+  // problem has dense costs, else the roots of the diagonals. The roots are
+  // symmetric, so the same rows give the L* columns.
+  template <typename F>
+  __device__ S croot(int kind, int c, int o, long long base, F&& f) const {
+    const int n = kind == 1 ? P.nu : P.nx;
+    const S* M = kind == 0 ? G.Qh : (kind == 1 ? G.Rh : G.QNh);
+    if (M) {
+      const S* row = M + ((size_t)c * n + o) * n;
+      S acc = 0;
+      for (int k = 0; k < n; ++k) acc += row[k] * f(base + k);
+      return acc;
+    }
+    const S* dg = kind == 0 ? P.sq : (kind == 1 ? P.sr : P.sqN);
+    return dg[(size_t)c * n + o] * f(base + o);
+  }
 };
 
 // (L* eta) on column x^i of nonleaf i, component o: Gamma_x' eta_c plus the
@@ -60,7 +77,8 @@ __device__ S lt_x(const GOff<S>& O, const S* eta, int i, int o) {
   const long long ec = O.e1c(i);
   S acc = 0;
   for (int r = 0; r < nc; ++r) acc += gx[(size_t)r * nx + o] * eta[ec + r];
-  for (int c = P.fc[i]; c < P.fc[i] + P.nch[i]; ++c) acc += P.sq[(size_t)c * nx + o] * eta[O.e2(c) + o];
+  auto ev = [&](long long e) { return eta[e]; };
+  for (int c = P.fc[i]; c < P.fc[i] + P.nch[i]; ++c) acc += O.croot(0, c, o, O.e2(c), ev);
   return acc;
 }
 template <typename S>
@@ -71,7 +89,8 @@ __device__ S lt_u(const GOff<S>& O, const S* eta, int i, int o) {
   const long long ec = O.e1c(i);
   S acc = 0;
   for (int r = 0; r < nc; ++r) acc += gu[(size_t)r * nu + o] * eta[ec + r];
-  for (int c = P.fc[i]; c < P.fc[i] + P.nch[i]; ++c) acc += P.sr[(size_t)c * nu + o] * eta[O.e2(c) + nx + o];
+  auto ev = [&](long long e) { return eta[e]; };
+  for (int c = P.fc[i]; c < P.fc[i] + P.nch[i]; ++c) acc += O.croot(1, c, o, O.e2(c) + nx, ev);
   return acc;
 }
 // column x^j of leaf j: Gamma_N' eta_cN + Q_N^{1/2} eta_q
@@ -81,7 +100,7 @@ __device__ S lt_xleaf(const GOff<S>& O, const S* eta, int j, int o) {
   const int nx = P.nx, ncN = O.G.ncN;
   const S* gn = O.GN(j);
   const long long e3 = O.e3(j);
-  S acc = P.sqN[(size_t)j * nx + o] * eta[O.e3q(j) + o];
+  S acc = O.croot(2, j, o, O.e3q(j), [&](long long e) { return eta[e]; });
   for (int r = 0; r < ncN; ++r) acc += gn[(size_t)r * nx + o] * eta[e3 + r];
   return acc;
 }
@@ -204,8 +223,9 @@ __device__ void fam_gen_L(const GOff<S>& O, const S* z, S* eta, int i, const S* 
   for (int r = 0; r < G.nc; ++r) put(O.e1c(i) + r, l_c<S>(O, z, i, r));
   for (int c = P.fc[i]; c < P.fc[i] + P.nch[i]; ++c) {
     const long long e2 = O.e2(c);
-    for (int o = 0; o < nx; ++o) put(e2 + o, P.sq[(size_t)c * nx + o] * z[O.x(i) + o]);
-    for (int o = 0; o < nu; ++o) put(e2 + nx + o, P.sr[(size_t)c * nu + o] * z[O.u(i) + o]);
+    auto zv = [&](long long e) { return z[e]; };
+    for (int o = 0; o < nx; ++o) put(e2 + o, O.croot(0, c, o, O.x(i), zv));
+    for (int o = 0; o < nu; ++o) put(e2 + nx + o, O.croot(1, c, o, O.u(i), zv));
     const S th = S(0.5) * z[O.tau(c)];
     put(e2 + nx + nu, th);
     put(e2 + nx + nu + 1, th);
@@ -213,7 +233,7 @@ __device__ void fam_gen_L(const GOff<S>& O, const S* z, S* eta, int i, const S* 
       const long long e3 = O.e3(c);
       for (int r = 0; r < G.ncN; ++r) put(e3 + r, l_cN<S>(O, z, c, r));
       const long long e3q = O.e3q(c);
-      for (int o = 0; o < nx; ++o) put(e3q + o, P.sqN[(size_t)c * nx + o] * z[O.x(c) + o]);
+      for (int o = 0; o < nx; ++o) put(e3q + o, O.croot(2, c, o, O.x(c), zv));
       const S sh = S(0.5) * z[O.s(c)];
       put(e3q + nx, sh);
       put(e3q + nx + 1, sh);
@@ -325,9 +345,8 @@ __global__ void __launch_bounds__(kGenThreads) k_gen_post(DevProb<S> P, GenDev<S
     }
     for (int c = fc; c < fc + n; ++c) {
       const long long e2 = O.e2(c);
-      for (int o = 0; o < nx; ++o) eout[e2 + o] = eta[e2 + o] + al * P.sq[(size_t)c * nx + o] * zz(O.x(i) + o);
-      for (int o = 0; o < nu; ++o)
-        eout[e2 + nx + o] = eta[e2 + nx + o] + al * P.sr[(size_t)c * nu + o] * zz(O.u(i) + o);
+      for (int o = 0; o < nx; ++o) eout[e2 + o] = eta[e2 + o] + al * O.croot(0, c, o, O.x(i), zz);
+      for (int o = 0; o < nu; ++o) eout[e2 + nx + o] = eta[e2 + nx + o] + al * O.croot(1, c, o, O.u(i), zz);
       const S th = S(0.5) * zz(O.tau(c));
       eout[e2 + nx + nu] = eta[e2 + nx + nu] + al * th;
       eout[e2 + nx + nu + 1] = eta[e2 + nx + nu + 1] + al * th;
@@ -339,7 +358,7 @@ __global__ void __launch_bounds__(kGenThreads) k_gen_post(DevProb<S> P, GenDev<S
           for (int o = 0; o < nx; ++o) acc += gn[o] * zz(O.x(c) + o);
           eout[e3 + r] = eta[e3 + r] + al * acc;
         }
-        for (int o = 0; o < nx; ++o) eout[e3q + o] = eta[e3q + o] + al * P.sqN[(size_t)c * nx + o] * zz(O.x(c) + o);
+        for (int o = 0; o < nx; ++o) eout[e3q + o] = eta[e3q + o] + al * O.croot(2, c, o, O.x(c), zz);
         const S sh = S(0.5) * zz(O.s(c));
         eout[e3q + nx] = eta[e3q + nx] + al * sh;
         eout[e3q + nx + 1] = eta[e3q + nx + 1] + al * sh;
@@ -365,8 +384,8 @@ __global__ void __launch_bounds__(kGenThreads) k_gen_post(DevProb<S> P, GenDev<S
     }
     for (int c = fc; c < fc + n; ++c) {
       const long long e2 = O.e2(c);
-      for (int o = 0; o < nx; ++o) row(e2 + o, P.sq[(size_t)c * nx + o] * rz(O.x(i) + o));
-      for (int o = 0; o < nu; ++o) row(e2 + nx + o, P.sr[(size_t)c * nu + o] * rz(O.u(i) + o));
+      for (int o = 0; o < nx; ++o) row(e2 + o, O.croot(0, c, o, O.x(i), rz));
+      for (int o = 0; o < nu; ++o) row(e2 + nx + o, O.croot(1, c, o, O.u(i), rz));
       row(e2 + nx + nu, S(0.5) * rz(O.tau(c)));
       row(e2 + nx + nu + 1, S(0.5) * rz(O.tau(c)));
       if (c >= P.nl) {
@@ -377,7 +396,7 @@ __global__ void __launch_bounds__(kGenThreads) k_gen_post(DevProb<S> P, GenDev<S
           for (int o = 0; o < nx; ++o) acc += gn[o] * rz(O.x(c) + o);
           row(e3 + r, acc);
         }
-        for (int o = 0; o < nx; ++o) row(e3q + o, P.sqN[(size_t)c * nx + o] * rz(O.x(c) + o));
+        for (int o = 0; o < nx; ++o) row(e3q + o, O.croot(2, c, o, O.x(c), rz));
         row(e3q + nx, S(0.5) * rz(O.s(c)));
         row(e3q + nx + 1, S(0.5) * rz(O.s(c)));
       }
@@ -396,14 +415,14 @@ __global__ void __launch_bounds__(kGenThreads) k_gen_post(DevProb<S> P, GenDev<S
       const S* gx = O.Gx(i);
       S acc = 0;
       for (int r = 0; r < G.nc; ++r) acc += gx[(size_t)r * nx + o] * re(O.e1c(i) + r);
-      for (int c = fc; c < fc + n; ++c) acc += P.sq[(size_t)c * nx + o] * re(O.e2(c) + o);
+      for (int c = fc; c < fc + n; ++c) acc += O.croot(0, c, o, O.e2(c), re);
       col(O.x(i) + o, acc);
     }
     for (int o = 0; o < nu; ++o) {
       const S* gu = O.Gu(i);
       S acc = 0;
       for (int r = 0; r < G.nc; ++r) acc += gu[(size_t)r * nu + o] * re(O.e1c(i) + r);
-      for (int c = fc; c < fc + n; ++c) acc += P.sr[(size_t)c * nu + o] * re(O.e2(c) + nx + o);
+      for (int c = fc; c < fc + n; ++c) acc += O.croot(1, c, o, O.e2(c) + nx, re);
       col(O.u(i) + o, acc);
     }
     for (int c = fc; c < fc + n; ++c) {
@@ -413,7 +432,7 @@ __global__ void __launch_bounds__(kGenThreads) k_gen_post(DevProb<S> P, GenDev<S
         const long long e3 = O.e3(c), e3q = O.e3q(c);
         for (int o = 0; o < nx; ++o) {
           const S* gn = O.GN(c);
-          S acc = P.sqN[(size_t)c * nx + o] * re(e3q + o);
+          S acc = O.croot(2, c, o, e3q, re);
           for (int r = 0; r < G.ncN; ++r) acc += gn[(size_t)r * nx + o] * re(e3 + r);
           col(O.x(c) + o, acc);
         }

@@ -316,6 +316,10 @@ int upload_general(Problem& P, const spock_problem_data& d, const GeneralLayout&
     off += bytes;
     return parts.size() - 1;
   };
+  std::vector<double> Qh, Rh, QNh;
+  if (d.Qm) dense_cost_roots(T, d, Qh, Rh, QNh);
+  const size_t i_Qh = place(sizeof(S) * Qh.size()), i_Rh = place(sizeof(S) * Rh.size()),
+               i_QNh = place(sizeof(S) * QNh.size());
   const size_t i_z2 = place(8 * nl), i_e1 = place(8 * nl), i_Eo = place(8 * nl), i_yo = place(8 * nl),
                i_Po = place(8 * nl), i_ny = place(4 * nl), i_kp = place(4 * nl),
                i_E = place(sizeof(S) * GL.E.size()), i_b = place(sizeof(S) * GL.b.size()),
@@ -347,6 +351,9 @@ int upload_general(Problem& P, const spock_problem_data& d, const GeneralLayout&
   putS(i_GN, GN);
   putS(i_cNmin, cNmin);
   putS(i_cNmax, cNmax);
+  putS(i_Qh, Qh);
+  putS(i_Rh, Rh);
+  putS(i_QNh, QNh);
   void* mem = nullptr;
   if (hipMalloc(&mem, host.size()) != hipSuccess) return SPOCK_ENOMEM;
   if (hipMemcpy(mem, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) {
@@ -376,6 +383,11 @@ int upload_general(Problem& P, const spock_problem_data& d, const GeneralLayout&
   G.GN = reinterpret_cast<const S*>(base + parts[i_GN].first);
   G.cNmin = reinterpret_cast<const S*>(base + parts[i_cNmin].first);
   G.cNmax = reinterpret_cast<const S*>(base + parts[i_cNmax].first);
+  if (d.Qm) {
+    G.Qh = reinterpret_cast<const S*>(base + parts[i_Qh].first);
+    G.Rh = reinterpret_cast<const S*>(base + parts[i_Rh].first);
+    G.QNh = reinterpret_cast<const S*>(base + parts[i_QNh].first);
+  }
   P.gmem = mem;
   P.general = true;
   if constexpr (sizeof(S) == 8) P.gd64 = G; else P.gd32 = G;
@@ -445,13 +457,35 @@ extern "C" int spock_problem_factor(const spock_tree* th, const spock_problem_da
   if (nx < 1 || nu < 1) return SPOCK_EINVAL;
   if (nx > kMaxDim || nu > kMaxDim) return SPOCK_EUNSUPPORTED;
   if (d->precision != SPOCK_FP64 && d->precision != SPOCK_FP32) return SPOCK_EINVAL;
-  if (!d->A || !d->B || !d->q || !d->r || !d->qN) return SPOCK_EINVAL;
+  const bool dense = d->Qm || d->Rm || d->QNm;
+  if (!d->A || !d->B || (!dense && (!d->q || !d->r || !d->qN))) return SPOCK_EINVAL;
   {
     const int rc = check_problem_data(T, *d);
     if (rc) return rc;
   }
-  // general conic risk or polyhedral constraints: their layout and S2 projectors
-  const bool general = d->risk || d->cons;
+  // dense costs: their diagonals stand in where a diagonal is stored (the
+  // special-form arrays, which the general kernels do not read)
+  spock_problem_data dd = *d;
+  std::vector<double> qdiag, rdiag, qNdiag;
+  if (dense) {
+    qdiag.assign((size_t)nn * nx, 0.0);
+    rdiag.assign((size_t)nn * nu, 0.0);
+    qNdiag.assign((size_t)nn * nx, 0.0);
+    for (int c = 0; c < nn; ++c) {
+      for (int o = 0; o < nx; ++o) {
+        qdiag[(size_t)c * nx + o] = std::max(0.0, d->Qm[((size_t)c * nx + o) * nx + o]);
+        qNdiag[(size_t)c * nx + o] = std::max(0.0, d->QNm[((size_t)c * nx + o) * nx + o]);
+      }
+      for (int o = 0; o < nu; ++o) rdiag[(size_t)c * nu + o] = std::max(0.0, d->Rm[((size_t)c * nu + o) * nu + o]);
+    }
+    dd.q = qdiag.data();
+    dd.r = rdiag.data();
+    dd.qN = qNdiag.data();
+  }
+  d = &dd;
+  // general conic risk, polyhedral constraints or dense costs: the general
+  // layout, S2 projectors and kernels
+  const bool general = d->risk || d->cons || dense;
   GeneralLayout GL;
   if (general) {
     const int rc = build_general(T, *d, kGenMaxBlock, GL);

@@ -158,14 +158,21 @@ int check_problem_data(const Tree& T, const spock_problem_data& dd) {
   const spock_problem_data* d = &dd;
   const int nn = T.nn, nl = T.nl, nx = d->nx, nu = d->nu;
   // data checks
+  const bool dense = d->Qm || d->Rm || d->QNm;
   for (int c = 1; c < nn; ++c) {
     for (int e = 0; e < nx * nx; ++e) if (!is_finite(d->A[(size_t)c * nx * nx + e])) return SPOCK_EINVAL;
     for (int e = 0; e < nx * nu; ++e) if (!is_finite(d->B[(size_t)c * nx * nu + e])) return SPOCK_EINVAL;
+    if (dense) continue;
     for (int k = 0; k < nx; ++k) if (!(d->q[(size_t)c * nx + k] > 0.0) || !is_finite(d->q[(size_t)c * nx + k])) return SPOCK_EINVAL;
     for (int k = 0; k < nu; ++k) if (!(d->r[(size_t)c * nu + k] > 0.0) || !is_finite(d->r[(size_t)c * nu + k])) return SPOCK_EINVAL;
   }
-  for (int j = nl; j < nn; ++j)
-    for (int k = 0; k < nx; ++k) if (!(d->qN[(size_t)j * nx + k] >= 0.0) || !is_finite(d->qN[(size_t)j * nx + k])) return SPOCK_EINVAL;
+  if (dense) {
+    const int rc = check_dense_costs(T, *d);
+    if (rc) return rc;
+  } else {
+    for (int j = nl; j < nn; ++j)
+      for (int k = 0; k < nx; ++k) if (!(d->qN[(size_t)j * nx + k] >= 0.0) || !is_finite(d->qN[(size_t)j * nx + k])) return SPOCK_EINVAL;
+  }
   // the boxes (unless general constraints replace them) and AV@R's a
   // (unless a general risk replaces it)
   if (!d->cons) {
@@ -422,6 +429,13 @@ double norm_L_general(const Tree& T, const spock_problem_data& d, const GeneralL
       for (int a = 0; a < k; ++a) M[(size_t)a * k + a] = 1.0;
     }
     for (int c = T.fc[i]; c < T.fc[i] + T.nch[i]; ++c) {
+      if (d.Qm) {  // (Q^{1/2})'Q^{1/2} = Q
+        for (int a = 0; a < nx; ++a)
+          for (int b = 0; b < nx; ++b) M[(size_t)a * k + b] += d.Qm[((size_t)c * nx + a) * nx + b];
+        for (int a = 0; a < nu; ++a)
+          for (int b = 0; b < nu; ++b) M[(size_t)(nx + a) * k + nx + b] += d.Rm[((size_t)c * nu + a) * nu + b];
+        continue;
+      }
       for (int o = 0; o < nx; ++o) M[(size_t)o * k + o] += d.q[(size_t)c * nx + o];
       for (int o = 0; o < nu; ++o) M[(size_t)(nx + o) * k + nx + o] += d.r[(size_t)c * nu + o];
     }
@@ -440,7 +454,12 @@ double norm_L_general(const Tree& T, const spock_problem_data& d, const GeneralL
     } else {
       for (int a = 0; a < nx; ++a) M[(size_t)a * nx + a] = 1.0;
     }
-    for (int o = 0; o < nx; ++o) M[(size_t)o * nx + o] += d.qN[(size_t)j * nx + o];
+    if (d.QNm) {
+      for (int a = 0; a < nx; ++a)
+        for (int b = 0; b < nx; ++b) M[(size_t)a * nx + b] += d.QNm[((size_t)j * nx + a) * nx + b];
+    } else {
+      for (int o = 0; o < nx; ++o) M[(size_t)o * nx + o] += d.qN[(size_t)j * nx + o];
+    }
     b2max = std::max(b2max, sym_max_eig(nx, M));
   }
   return std::sqrt(b2max);
@@ -579,4 +598,75 @@ int build_post_blocks(const Tree& T, int cap, std::vector<int>& bfam) {
   return nb;
 }
 
+namespace {
+// eigenvalues (ascending order not needed) and vectors of a symmetric n x n block
+void sym_eig(int n, const double* M, std::vector<double>& lam, std::vector<double>& V) {
+  std::vector<double> A(M, M + (size_t)n * n);
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < a; ++b) A[(size_t)a * n + b] = A[(size_t)b * n + a] = 0.5 * (A[(size_t)a * n + b] + A[(size_t)b * n + a]);
+  sym_jacobi(n, A, V);
+  lam.resize(n);
+  for (int a = 0; a < n; ++a) lam[a] = A[(size_t)a * n + a];
+}
+
+int check_block(int n, const double* M, bool definite) {
+  double mx = 0;
+  for (int e = 0; e < n * n; ++e) {
+    if (!is_finite(M[e])) return SPOCK_EINVAL;
+    mx = std::max(mx, std::fabs(M[e]));
+  }
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < a; ++b)
+      if (std::fabs(M[(size_t)a * n + b] - M[(size_t)b * n + a]) > 1e-12 * std::max(1.0, mx)) return SPOCK_EINVAL;
+  std::vector<double> lam, V;
+  sym_eig(n, M, lam, V);
+  double lmin = lam[0], lmax = lam[0];
+  for (double l : lam) {
+    lmin = std::min(lmin, l);
+    lmax = std::max(lmax, l);
+  }
+  if (definite ? !(lmin > 0.0) : (lmin < -1e-12 * std::max(1.0, lmax))) return SPOCK_EINVAL;
+  return SPOCK_OK;
+}
+
+void root_block(int n, const double* M, double* out) {
+  std::vector<double> lam, V;
+  sym_eig(n, M, lam, V);
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) {
+      double s = 0;
+      for (int k = 0; k < n; ++k) s += V[(size_t)a * n + k] * std::sqrt(std::max(lam[k], 0.0)) * V[(size_t)b * n + k];
+      out[(size_t)a * n + b] = s;
+    }
+}
+}  // namespace
+
+int check_dense_costs(const Tree& T, const spock_problem_data& d) {
+  if (!d.Qm || !d.Rm || !d.QNm) return SPOCK_EINVAL;
+  const int nx = d.nx, nu = d.nu;
+  for (int c = 1; c < T.nn; ++c) {
+    if (check_block(nx, d.Qm + (size_t)c * nx * nx, false)) return SPOCK_EINVAL;
+    if (check_block(nu, d.Rm + (size_t)c * nu * nu, true)) return SPOCK_EINVAL;
+  }
+  for (int j = T.nl; j < T.nn; ++j)
+    if (check_block(nx, d.QNm + (size_t)j * nx * nx, false)) return SPOCK_EINVAL;
+  return SPOCK_OK;
+}
+
+void dense_cost_roots(const Tree& T, const spock_problem_data& d, std::vector<double>& Qh, std::vector<double>& Rh,
+                      std::vector<double>& QNh) {
+  const int nn = T.nn, nx = d.nx, nu = d.nu;
+  Qh.assign((size_t)nn * nx * nx, 0.0);
+  Rh.assign((size_t)nn * nu * nu, 0.0);
+  QNh.assign((size_t)nn * nx * nx, 0.0);
+  parallel_for(nn, [&](int c) {
+    if (c >= 1) {
+      root_block(nx, d.Qm + (size_t)c * nx * nx, Qh.data() + (size_t)c * nx * nx);
+      root_block(nu, d.Rm + (size_t)c * nu * nu, Rh.data() + (size_t)c * nu * nu);
+    }
+    if (c >= T.nl) root_block(nx, d.QNm + (size_t)c * nx * nx, QNh.data() + (size_t)c * nx * nx);
+  });
+}
+
 }  // namespace spk
+

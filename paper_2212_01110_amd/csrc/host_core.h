@@ -59,6 +59,15 @@ double nested_cost(const Tree& T, int nx, int nu, const double* q, const double*
 int build_flow_items(const Tree& T, int nc, int chunk_codes, std::vector<int>& items, std::vector<int>& pbase,
                      int& nslots, int& nbwd);
 
+// Dense costs (spock_problem_data Qm, Rm, QNm): finite and symmetric, Q and
+// Q_N positive semidefinite, R positive definite (cyclic Jacobi
+// eigenvalues). Returns SPOCK_OK or SPOCK_EINVAL.
+int check_dense_costs(const Tree& T, const spock_problem_data& d);
+// Their symmetric square roots V diag(sqrt(lambda)) V', row-major per node:
+// Qh, QNh [nn][nx][nx], Rh [nn][nu][nu].
+void dense_cost_roots(const Tree& T, const spock_problem_data& d, std::vector<double>& Qh, std::vector<double>& Rh,
+                      std::vector<double>& QNh);
+
 // Blocks of the node-parallel post-pass: families packed in breadth-first
 // order, block b owning families [bfam[b], bfam[b + 1]) whose children (one
 // contiguous run) number at most cap (a family with more children than cap

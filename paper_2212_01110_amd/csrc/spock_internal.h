@@ -91,6 +91,12 @@ struct GenDev {
   const S* GN = nullptr;
   const S* cNmin = nullptr;
   const S* cNmax = nullptr;
+  // dense costs: symmetric square roots of Q^c, R^c, Q_N^j, row-major per
+  // node ([nn][nx][nx], [nn][nu][nu], [nn][nx][nx]); nullptr: the diagonal
+  // roots sq, sr, sqN of the problem
+  const S* Qh = nullptr;
+  const S* Rh = nullptr;
+  const S* QNh = nullptr;
 };
 
 // Device arrays of one precision.

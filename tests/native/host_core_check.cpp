@@ -3,8 +3,12 @@
 // library computes, one labelled array per line, for the test to compare
 // with the oracle. Input (whitespace-separated): nn nx nu; anc[nn];
 // prob[nn]; A B q r qN xmin xmax umin umax a_risk (the spock_problem_data
-// arrays); x[nn][nx] u[nl][nu] (a trajectory); nc (children per chunk).
+// arrays); x[nn][nx] u[nl][nu] (a trajectory); nc (children per chunk);
+// dense (0 or 1), then, if 1, Qm[nn][nx][nx] Rm[nn][nu][nu] QNm[nn][nx][nx]
+// (dense costs: their check, their symmetric roots and ||L|| of the general
+// layout are printed in place of the diagonal figures).
 #include <cstdio>
+#include <cstdlib>
 #include <fstream>
 #include <string>
 #include <algorithm>
@@ -29,9 +33,14 @@ int main(int argc, char** argv) {
   std::vector<double> prob(nn);
   for (auto& a : anc) in >> a;
   for (auto& p : prob) in >> p;
+  // tokens through strtod, which also reads inf and nan
   auto read = [&](size_t n) {
     std::vector<double> v(n);
-    for (auto& x : v) in >> x;
+    std::string tok;
+    for (auto& x : v) {
+      in >> tok;
+      x = std::strtod(tok.c_str(), nullptr);
+    }
     return v;
   };
   std::vector<double> A = read((size_t)nn * nx * nx), B = read((size_t)nn * nx * nu), q = read((size_t)nn * nx),
@@ -44,8 +53,14 @@ int main(int argc, char** argv) {
   if (rt != SPOCK_OK) return 0;
   std::printf("shape %d %d %d\n", T.N, T.nl, T.nn - T.nl);
   std::vector<double> x = read((size_t)nn * nx), u = read((size_t)T.nl * nu);
-  int nc = 1;
-  in >> nc;
+  int nc = 1, dense = 0;
+  in >> nc >> dense;
+  std::vector<double> Qm, Rm, QNm;
+  if (dense) {
+    Qm = read((size_t)nn * nx * nx);
+    Rm = read((size_t)nn * nu * nu);
+    QNm = read((size_t)nn * nx * nx);
+  }
   spock_problem_data d{};
   d.nx = nx;
   d.nu = nu;
@@ -59,9 +74,26 @@ int main(int argc, char** argv) {
   d.umin = umin.data();
   d.umax = umax.data();
   d.a_risk = a.data();
+  if (dense) {
+    d.Qm = Qm.data();
+    d.Rm = Rm.data();
+    d.QNm = QNm.data();
+  }
   const int rd = spk::check_problem_data(T, d);
   std::printf("data_rc %d\n", rd);
   if (rd != SPOCK_OK) return 0;
+  if (dense) {
+    std::vector<double> Qh, Rh, QNh;
+    spk::dense_cost_roots(T, d, Qh, Rh, QNh);
+    put("Qh", Qh);
+    put("Rh", Rh);
+    put("QNh", QNh);
+    spk::GeneralLayout GL;
+    const int rg = spk::build_general(T, d, 96, GL);  // the library's block bound
+    std::printf("general_rc %d\n", rg);
+    if (rg == SPOCK_OK) std::printf("normL %.17g\n", spk::norm_L_general(T, d, GL));
+    return 0;
+  }
   spk::Factor F;
   const int rf = spk::factor_alg1(T, d, F);
   std::printf("factor_rc %d\n", rf);

@@ -1,7 +1,7 @@
 """GPU parity of general problems: conic risk measures (E, F, b, K) with
-nu != 0 (section 4.3) and polyhedral constraints (section 4.1), through the
-C ABI against the oracle: every operator on identical inputs, ||L||, and
-converged solutions."""
+nu != 0 (section 4.3), polyhedral constraints and dense cost matrices
+(section 4.1), through the C ABI against the oracle: every operator on
+identical inputs, ||L||, and converged solutions."""
 import numpy as np
 import pytest
 
@@ -38,6 +38,11 @@ CASES = {
     "mixture-poly-deep": lambda: _active(84, [2, 2, 1], 2, 2, 5),
     "avar-as-general": _avar_written_generally,
     "mixture-nx20": lambda: G.make_general_small(86, [2, 2, 1, 1], 20, 10, nc=12, ncN=6, bound=3.0),
+    # dense Q, R, Q_N (AV@R and boxes otherwise; with general risk and
+    # polyhedral rows; n_x = 20 so the roots span several lanes' rows)
+    "dense-avar": lambda: G.dense_costs(G.make_random_small(11, [3, 1, 2], 4, 3), seed=21),
+    "dense-mixture-poly": lambda: G.dense_costs(_active(82, [3, 1], 3, 2, 4), seed=22),
+    "dense-nx20": lambda: G.dense_costs(G.make_random_small(18, [2, 2, 1], 20, 10), seed=23),
 }
 _INST = {}
 _REF = {}
@@ -114,7 +119,8 @@ def test_general_T_every_sweep_mapping(name, mapping, monkeypatch):
 
 
 @pytest.mark.parametrize("prec", list(FP))
-@pytest.mark.parametrize("name", ["mixture-box", "mixture-poly", "mixture-poly-deep"])
+@pytest.mark.parametrize("name", ["mixture-box", "mixture-poly", "mixture-poly-deep", "dense-avar",
+                                  "dense-mixture-poly"])
 def test_general_solve_matches_oracle(name, prec):
     inst = _inst(name)
     gp, op = _build(inst, prec)
@@ -134,6 +140,42 @@ def test_general_solve_matches_oracle(name, prec):
     out = host(v)
     u0 = out[op.lay.u_off[0]: op.lay.u_off[0] + op.lay.nu]
     check(f"gen_solve_u0:{name}:{prec}", np.max(np.abs(u0 - ref.u0)) / max(1, np.max(np.abs(ref.u0))), tol)
+
+
+def test_dense_costs_rotation_invariance():
+    # x' = U x, u' = W u with U, W orthogonal maps a problem with diagonal
+    # costs onto one with dense costs and the same optimal value, u0' = W u0
+    # (inactive boxes: they are not invariant); the diagonal problem runs
+    # the special-form kernels, the rotated one the general kernels
+    base = G.make_random_small(17, [3, 2], 5, 3)
+    big = 1e6
+    base.xmin[:], base.xmax[:], base.umin[:], base.umax[:] = -big, big, -big, big
+    rng = np.random.default_rng(5)
+    U = np.linalg.qr(rng.standard_normal((base.nx, base.nx)))[0]
+    W = np.linalg.qr(rng.standard_normal((base.nu, base.nu)))[0]
+    rot = G.rotate_states_inputs(base, U, W)
+    st = SP.default_settings(eps_abs=1e-10, eps_rel=1e-10, max_iters=900000)
+    out = {}
+    for name, inst in (("diag", base), ("rot", rot)):
+        gp = SP.Problem.from_instance(inst, precision=SP.FP64)
+        v = torch.zeros(gp.n_v, dtype=torch.float64, device="cuda")
+        info = gp.solve(dev(inst.x0, torch.float64), v, st)
+        assert info["status"] == "converged", (name, info)
+        lay = O.Problem(inst).lay
+        out[name] = (info["V_s0"], host(v)[lay.u_off[0]: lay.u_off[0] + lay.nu])
+    (Vd, ud), (Vr, ur) = out["diag"], out["rot"]
+    check("dense_rot_V", abs(Vr - Vd) / max(1, abs(Vd)), 1e-7)
+    check("dense_rot_u0", np.max(np.abs(ur - W @ ud)) / max(1, np.max(np.abs(ud))), 1e-5)
+
+
+def test_dense_costs_rejected_by_factor():
+    inst = G.dense_costs(G.make_random_small(11, [3, 1, 2], 4, 3), seed=21)
+    bad = inst.copy()
+    bad.Qm = inst.Qm.copy()
+    bad.Qm[2] -= 3.0 * np.eye(inst.nx)              # indefinite
+    with pytest.raises(SP.SpockError) as e:
+        SP.Problem.from_instance(bad)
+    assert e.value.code == -1
 
 
 def test_general_problems_rejected_where_unsupported():

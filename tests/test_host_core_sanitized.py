@@ -29,7 +29,7 @@ def driver(tmp_path_factory):
     return exe
 
 
-def _run(driver, tmp_path, inst, x=None, u=None, nc=1, anc=None, prob=None):
+def _run(driver, tmp_path, inst, x=None, u=None, nc=1, anc=None, prob=None, dense=None):
     nn, nx, nu = inst.num_nodes, inst.nx, inst.nu
     anc = inst.anc if anc is None else anc
     prob = inst.prob if prob is None else prob
@@ -39,7 +39,9 @@ def _run(driver, tmp_path, inst, x=None, u=None, nc=1, anc=None, prob=None):
     parts = [np.array([nn, nx, nu]), np.asarray(anc), np.asarray(prob)]
     parts += [np.asarray(getattr(inst, k), float).ravel() for k in
               ("A", "B", "q", "r", "qN", "xmin", "xmax", "umin", "umax", "a_risk")]
-    parts += [x.ravel(), u.ravel(), np.array([nc])]
+    parts += [x.ravel(), u.ravel(), np.array([nc]), np.array([0 if dense is None else 1])]
+    if dense is not None:
+        parts += [np.asarray(m, float).ravel() for m in dense]
     path = tmp_path / "case.txt"
     with open(path, "w") as f:
         for p in parts:
@@ -132,3 +134,56 @@ def test_malformed_trees_and_data_under_sanitizers(driver, tmp_path):
     bad = inst.copy()
     bad.A[5, 0, 0] = np.nan                             # non-finite dynamics
     assert _run(driver, tmp_path, bad)["data_rc"][0] == -1
+
+
+def _sym_root_ok(M, H):
+    # H symmetric, positive semidefinite, H @ H == M
+    assert np.max(np.abs(H - np.swapaxes(H, -1, -2))) <= 1e-13 * max(1.0, np.max(np.abs(H)))
+    assert np.min(np.linalg.eigvalsh(H)) >= -1e-12
+    assert np.max(np.abs(H @ H - M)) <= 1e-12 * max(1.0, np.max(np.abs(M)))
+
+
+@pytest.mark.parametrize("name,mk", [("config1", lambda: G.make_config(1)),
+                                      ("b5-wide", lambda: G.make_random_small(14, [5, 3], 6, 2))])
+def test_dense_costs_under_sanitizers(driver, tmp_path, name, mk):
+    # dense costs (section 4.1: Q, Q_N positive semidefinite, R positive
+    # definite): their symmetric roots and ||L|| of the general layout
+    # against the oracle's L, which uses the same roots
+    inst = G.dense_costs(mk(), seed=7)
+    nn, nx, nu = inst.num_nodes, inst.nx, inst.nu
+    Q = inst.Qm.copy()
+    Q[3] = Q[3] - (np.min(np.linalg.eigvalsh(Q[3]))) * np.eye(nx)  # singular: allowed
+    inst.Qm = Q
+    out = _run(driver, tmp_path, inst, dense=(inst.Qm, inst.Rm, inst.QNm))
+    assert out["data_rc"][0] == 0 and out["general_rc"][0] == 0
+    lay = O.Problem(inst).lay
+    for key, M, n, nodes in (("Qh", inst.Qm, nx, range(1, nn)), ("Rh", inst.Rm, nu, range(1, nn)),
+                             ("QNh", inst.QNm, nx, lay.leaves)):
+        H = out[key].reshape(nn, n, n)
+        for c in nodes:
+            _sym_root_ok(M[c], H[c])
+    ref = O.Problem(inst).normL
+    assert abs(out["normL"][0] - ref) <= 1e-12 * ref
+
+
+def test_dense_costs_rejected_under_sanitizers(driver, tmp_path):
+    inst = G.dense_costs(G.make_config(1), seed=8)
+    nx, nu = inst.nx, inst.nu
+
+    def rc(Qm=None, Rm=None, QNm=None):
+        m = (inst.Qm if Qm is None else Qm, inst.Rm if Rm is None else Rm, inst.QNm if QNm is None else QNm)
+        return _run(driver, tmp_path, inst, dense=m)["data_rc"][0]
+
+    assert rc() == 0
+    Q = inst.Qm.copy()
+    Q[2, 0, 1] += 1e-3                                  # not symmetric
+    assert rc(Qm=Q) == -1
+    Q = inst.Qm.copy()
+    Q[4] -= 3.0 * np.eye(nx)                            # indefinite
+    assert rc(Qm=Q) == -1
+    R = inst.Rm.copy()
+    R[1] = np.zeros((nu, nu))                           # R must be definite
+    assert rc(Rm=R) == -1
+    QN = inst.QNm.copy()
+    QN[-1, 0, 0] = np.inf                               # non-finite
+    assert rc(QNm=QN) == -1
