@@ -58,7 +58,7 @@ int upload(Problem& P, const spock_problem_data& d, const std::vector<double>& A
   const size_t nvec = (size_t)nn * (4 * nx + 3 * nu) + 2 * (size_t)nn + 64;
   const size_t nmat = (size_t)nn * (3 * nx * nx + 3 * nx * nu) + (size_t)nl * (2 * nu * nx + nu * nu + 3 * nx * nu);
   const size_t bytes = (nvec + nmat) * sizeof(S) + (3 * (size_t)nn + T.N + 2 + 4 * ((size_t)nl + 2)) * sizeof(int) +
-                       72 * 256;
+                       (size_t)nn * sizeof(long long) + 72 * 256;
   std::vector<char> host(bytes, 0);
   void* dmem = nullptr;
   if (hipMalloc(&dmem, bytes) != hipSuccess) return SPOCK_ENOMEM;
@@ -93,6 +93,27 @@ int upload(Problem& P, const spock_problem_data& d, const std::vector<double>& A
     ancp.first[i] = T.anc[i];
   }
   D.fc = fcp.second; D.nch = nchp.second; D.anc = ancp.second;
+  // slot of s^c in its ancestor's z2 block (y 2n+1, tau n, s n), for the
+  // flat post-pass
+  {
+    auto sp = take(nn, 0LL);
+    sp.first[0] = 0;
+    for (int c = 1; c < nn; ++c) {
+      const int a = T.anc[c];
+      const long long z2a = D.zZ2 + 4LL * (T.fc[a] - 1) + a;
+      sp.first[c] = z2a + 3LL * T.nch[a] + 1 + (c - T.fc[a]);
+    }
+    P.d_spos = sp.second;
+  }
+  {
+    const char* pm = std::getenv("SPOCK_POST");
+    P.post_flat = pm && std::string(pm) == "flat";
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+      P.ncu = ncu;
+    P.flat_bpc = flat_post_occupancy<S>();
+  }
   // block tables of the node-parallel post-pass (one per team size); a
   // table is dropped when its LDS (per team 3 VM, per child slot nx + nu)
   // would exceed 64 KiB, and all are dropped under SPOCK_POST=family
@@ -919,6 +940,22 @@ int autotune(Problem& P, hipStream_t st) {
       }
     }
     P.team_pp = pick;
+    // the flat post-pass against the team forms at that team size (the
+    // pre-pass keeps its team size either way); SPOCK_POST fixes the form
+    if (!std::getenv("SPOCK_POST")) {
+      P.post_flat = true;
+      HIP_TRY(launch_T<S>(P, W.pool[0], W.pool[1], W.x0_zero, W.q, W.d, W.xbar, W.ubar, W.partials, W.stats, st,
+                          W.eta_zero, true));
+      HIP_TRY(hipEventRecord(e0, st));
+      for (int r = 0; r < 3; ++r)
+        HIP_TRY(launch_T<S>(P, W.pool[0], W.pool[1], W.x0_zero, W.q, W.d, W.xbar, W.ubar, W.partials, W.stats,
+                            st, W.eta_zero, true));
+      HIP_TRY(hipEventRecord(e1, st));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      P.post_flat = ms < best_pp;
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

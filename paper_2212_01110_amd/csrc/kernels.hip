@@ -151,6 +151,248 @@ __global__ void __launch_bounds__(256) k_post_nodes(DevProb<S> P, const int* __r
   block_stats(st, partials);
 }
 
+// Flat post-pass: one wavefront per unit, a unit being a nonleaf family
+// (group 1 of i and group 2 of each child c) or a leaf (group 3). The rows
+// and columns a unit touches are exactly those of the family-serial form,
+// so no unit waits on another. A family's columns x^i and u^i share one
+// index k < nx + nu with the first rows of each child's group 2, so every
+// lane holds the same two components of all of them. Offsets are
+// arithmetic in i once fc[i] and nch[i] are read, and the slot of s^i in
+// its ancestor's block comes from spos[i]: one level of scalar loads, then
+// every data load of the unit at once. Statistics: wavefront shuffles,
+// then the block's four wavefronts in order, one record per block.
+template <typename S>
+__device__ __forceinline__ void flat_family(const DevProb<S>& P, const Off<S>& O, const long long* __restrict__ spos,
+                                            const S* __restrict__ z, const S* __restrict__ eta,
+                                            const S* __restrict__ zout, S* __restrict__ eout, int i, int lane,
+                                            StatAcc& st) {
+  const int nx = P.nx, nu = P.nu, K = nx + nu;
+  const int fc = P.fc[i], n = P.nch[i];
+  const S al = P.alpha;
+  const S ia = S(1) / al;
+  const long long e1 = O.e1(i), e1x = e1 + 2LL * n + 2, zb = O.z2(i);
+  const long long xi = O.x(i), ui = O.u(i);
+  const long long sp = spos[i];
+  // One batch of loads, with clamped indices and no branches, so that
+  // every load of the unit is in flight at once: columns x^i, u^i (slot s:
+  // k = lane + 64 s), the y block (one entry per lane when 2n + 1 <= 64)
+  // and the scalars.
+  bool on[2];
+  S zp[2], zo[2], lo[2], hi[2], eb[2], gc[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int k = lane + 64 * s;
+    on[s] = k < K;
+    const int kk = on[s] ? k : 0;
+    const bool isx = kk < nx;
+    const long long zi = isx ? xi + kk : ui + (kk - nx);
+    const size_t bi = isx ? (size_t)i * nx + kk : (size_t)i * nu + (kk - nx);
+    zp[s] = zout[zi];
+    zo[s] = z[zi];
+    lo[s] = (isx ? P.xlo : P.ulo)[bi];
+    hi[s] = (isx ? P.xhi : P.uhi)[bi];
+    eb[s] = eta[e1x + kk];
+    gc[s] = 0;
+  }
+  const int ny = 2 * n + 1;
+  const int ky = lane < ny ? lane : 0;
+  const S yv = z[zb + ky], ypv = zout[zb + ky], eyv = eta[e1 + ky];
+  const S pk = P.p[fc + (lane < n ? lane : 0)];
+  const S si = z[sp], sip = zout[sp];
+  const S y3 = z[zb + 2 * n], y3p = zout[zb + 2 * n];
+  const S es = eta[e1 + 2 * n + 1];
+  // group 2 of every child: (Q^{1/2} x^i, R^{1/2} u^i, tau/2, tau/2)
+  for (int c = fc; c < fc + n; ++c) {
+    const long long e2 = O.e2(c);
+    const long long tp = zb + 2LL * n + 1 + (c - fc);
+    S sc[2], ev[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int kk = on[s] ? lane + 64 * s : 0;
+      sc[s] = kk < nx ? P.sq[(size_t)c * nx + kk] : P.sr[(size_t)c * nu + (kk - nx)];
+      ev[s] = eta[e2 + kk];
+    }
+    const S tau = z[tp], taup = zout[tp];
+    const S ea = eta[e2 + K], ebb = eta[e2 + K + 1];
+    S wv[2], ov[2], lz[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      wv[s] = on[s] ? ev[s] + al * sc[s] * (S(2) * zp[s] - zo[s]) : S(0);
+      lz[s] = sc[s] * (zo[s] - zp[s]);
+      ov[s] = 0;
+    }
+    const S wa = ea + al * S(0.5) * (S(2) * taup - tau);
+    const S wb = ebb + al * S(0.5) * (S(2) * taup - tau);
+    S oa, ob;
+    soc_prox<S, 64, 64>(wv, ov, K, wa, wb, oa, ob, al, lane);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      if (on[s]) {
+        eout[e2 + lane + 64 * s] = ov[s];
+        const S re = ev[s] - ov[s];
+        st.row((double)re, (double)lz[s], (double)ia);
+        gc[s] += sc[s] * re;
+      }
+    }
+    if (lane == 0) {
+      const S rtau = tau - taup;
+      const S rea = ea - oa, reb = ebb - ob;
+      eout[e2 + K] = oa;
+      eout[e2 + K + 1] = ob;
+      st.row((double)rea, 0.5 * (double)rtau, (double)ia);
+      st.row((double)reb, 0.5 * (double)rtau, (double)ia);
+      st.col((double)rtau, 0.5 * ((double)rea + (double)reb), (double)ia);
+    }
+  }
+  // group 1: the boxes on (x^i, u^i) and the columns x^i, u^i
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    if (on[s]) {
+      const S w = eb[s] + al * (S(2) * zp[s] - zo[s]);
+      const S ep = w - al * clampv(w * ia, lo[s], hi[s]);
+      eout[e1x + lane + 64 * s] = ep;
+      const S re = eb[s] - ep;
+      const S rz = zo[s] - zp[s];
+      st.row((double)re, (double)rz, (double)ia);
+      st.col((double)rz, (double)(re + gc[s]), (double)ia);
+    }
+  }
+  // group 1: y in K* = R^{2n}_+ x R and the row s^i - b'y
+  double bw = lane < n ? (double)(pk * (S(2) * ypv - yv)) : 0.0;
+  double bry = lane < n ? (double)(pk * (yv - ypv)) : 0.0;
+  for (int k = lane + 64; k < n; k += 64) {  // more than 64 children
+    const S pq = P.p[fc + k];
+    const S y1 = z[zb + k], y1p = zout[zb + k];
+    bw += (double)(pq * (S(2) * y1p - y1));
+    bry += (double)(pq * (y1 - y1p));
+  }
+  const S bW = (S)team_sum<64>(bw) + (S(2) * y3p - y3);
+  const S bR = (S)team_sum<64>(bry) + (y3 - y3p);
+  const S ws = es + al * ((S(2) * sip - si) - bW);
+  const S es_new = ws < S(0) ? ws : S(0);
+  const S res_ = es - es_new;
+  auto yrow = [&](int k, S y, S yp, S e, S pq) {
+    const S w = e + al * (S(2) * yp - y);
+    const S ep = (k < 2 * n) ? (w < S(0) ? w : S(0)) : S(0);
+    eout[e1 + k] = ep;
+    const S re = e - ep;
+    const S ry = y - yp;
+    st.row((double)re, (double)ry, (double)ia);
+    const S bk = (k < n) ? pq : ((k == 2 * n) ? S(1) : S(0));
+    st.col((double)ry, (double)(re - bk * res_), (double)ia);
+  };
+  if (lane < ny) yrow(lane, yv, ypv, eyv, pk);
+  for (int k = lane + 64; k < ny; k += 64) yrow(k, z[zb + k], zout[zb + k], eta[e1 + k], k < n ? P.p[fc + k] : S(0));
+  if (lane == 0) {
+    eout[e1 + 2 * n + 1] = es_new;
+    const S rsi = si - sip;
+    st.row((double)res_, (double)(rsi - bR), (double)ia);
+    st.col((double)rsi, (double)res_, (double)ia);
+  }
+}
+
+// Leaf j: group 3 (box on x^j, (Q_N^{1/2} x^j, s/2, s/2) in the SOC) and
+// the columns x^j, s^j; one batch of loads as in flat_family.
+template <typename S>
+__device__ __forceinline__ void flat_leaf(const DevProb<S>& P, const Off<S>& O, const long long* __restrict__ spos,
+                                          const S* __restrict__ z, const S* __restrict__ eta,
+                                          const S* __restrict__ zout, S* __restrict__ eout, int j, int lane,
+                                          StatAcc& st) {
+  const int nx = P.nx;
+  const S al = P.alpha;
+  const S ia = S(1) / al;
+  const long long e3 = O.e3(j), xj = O.x(j);
+  const long long sp = spos[j];
+  const bool on = lane < nx;
+  const int kk = on ? lane : 0;
+  const S xc = zout[xj + kk], xin = z[xj + kk];
+  const S ebx = eta[e3 + kk], eq = eta[e3 + nx + kk];
+  const S lo = P.xlo[(size_t)j * nx + kk], hi = P.xhi[(size_t)j * nx + kk];
+  const S sqn = P.sqN[(size_t)j * nx + kk];
+  const S sv = z[sp], svp = zout[sp];
+  const S ea = eta[e3 + 2 * nx], ebb = eta[e3 + 2 * nx + 1];
+  const S w = ebx + al * (S(2) * xc - xin);
+  const S pb = w - al * clampv(w * ia, lo, hi);
+  const S rex = ebx - pb;
+  S wq[2] = {on ? eq + al * sqn * (S(2) * xc - xin) : S(0), S(0)}, oq[2] = {S(0), S(0)};
+  const S wsa = ea + al * S(0.5) * (S(2) * svp - sv);
+  const S wsb = ebb + al * S(0.5) * (S(2) * svp - sv);
+  S osa, osb;
+  soc_prox<S, 64, 64>(wq, oq, nx, wsa, wsb, osa, osb, al, lane);
+  if (on) {
+    eout[e3 + lane] = pb;
+    st.row((double)rex, (double)(xin - xc), (double)ia);
+    eout[e3 + nx + lane] = oq[0];
+    const S req = eq - oq[0];
+    st.row((double)req, (double)(sqn * (xin - xc)), (double)ia);
+    st.col((double)(xin - xc), (double)(rex + sqn * req), (double)ia);
+  }
+  if (lane == 0) {
+    const S rs = sv - svp;
+    eout[e3 + 2 * nx] = osa;
+    eout[e3 + 2 * nx + 1] = osb;
+    const S rea = ea - osa, reb = ebb - osb;
+    st.row((double)rea, 0.5 * (double)rs, (double)ia);
+    st.row((double)reb, 0.5 * (double)rs, (double)ia);
+    st.col((double)rs, 0.5 * ((double)rea + (double)reb), (double)ia);
+  }
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256) k_post_flat(DevProb<S> P, const long long* __restrict__ spos,
+                                                   const S* __restrict__ z, const S* __restrict__ eta,
+                                                   const S* __restrict__ zout, S* __restrict__ eout,
+                                                   double* __restrict__ partials) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const Off<S> O(P);
+  StatAcc st;
+  const int stride = gridDim.x * 4;
+  for (int u = blockIdx.x * 4 + wave; u < P.nn; u += stride) {
+    if (u < P.nl) flat_family<S>(P, O, spos, z, eta, zout, eout, u, lane, st);
+    else flat_leaf<S>(P, O, spos, z, eta, zout, eout, u, lane, st);
+  }
+  // wavefront, then the four wavefronts in order
+  double v[kStats] = {st.rz2, st.re2, st.cross, st.xip, st.xid};
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    v[0] += __shfl_xor(v[0], m, 64);
+    v[1] += __shfl_xor(v[1], m, 64);
+    v[2] += __shfl_xor(v[2], m, 64);
+    v[3] = fmax(v[3], __shfl_xor(v[3], m, 64));
+    v[4] = fmax(v[4], __shfl_xor(v[4], m, 64));
+  }
+  __shared__ double red[4][kStats];
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < kStats; ++k) red[wave][k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < kStats) {
+    const int k = threadIdx.x;
+    double a = red[0][k];
+    for (int w = 1; w < 4; ++w) a = (k < 3) ? a + red[w][k] : fmax(a, red[w][k]);
+    partials[(size_t)blockIdx.x * kStats + k] = a;
+  }
+}
+
+// Blocks of the flat post-pass: the resident blocks per compute unit (one
+// wavefront per SIMD each; as many as the registers allow) times the
+// compute units, each wavefront looping over units; at most one statistics
+// record per nonleaf node plus one (the partials' size).
+int flat_post_blocks(const Problem& P) {
+  const int units = (P.tree->nn + 3) / 4;
+  return std::max(1, std::min({units, P.tree->nl + 1, P.flat_bpc * P.ncu}));
+}
+template <typename S>
+int flat_post_occupancy() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_post_flat<S>, 256, 0) != hipSuccess || nb < 1) nb = 1;
+  return nb;
+}
+template int flat_post_occupancy<double>();
+template int flat_post_occupancy<float>();
+
 // ---------------------------------------------------------------- team sweeps
 // One team of T lanes per family; one launch per stage.
 template <typename S, int T>
@@ -621,6 +863,11 @@ static int pp_index(int T) { return T == 8 ? 0 : T == 16 ? 1 : T == 32 ? 2 : 3; 
 template <typename S, int T>
 static void launch_post(const Problem& P, const DevProb<S>& D, const S* z, const S* eta,
                         const S* zout, S* eout, double* partials, hipStream_t st) {
+  if (P.post_flat) {
+    hipLaunchKernelGGL(k_post_flat<S>, dim3(flat_post_blocks(P)), dim3(256), 0, st, D, P.d_spos, z, eta, zout,
+                       eout, partials);
+    return;
+  }
   const int tpb = 256 / T;
   const int VM = (std::max(P.nx, P.nu) + 3) & ~3;
   const int k = pp_index(T);
@@ -637,6 +884,7 @@ static void launch_post(const Problem& P, const DevProb<S>& D, const S* z, const
 // Number of statistic records written by the post-pass.
 int post_blocks(const Problem& P) {
   if (P.general) return gen_post_blocks(P);
+  if (P.post_flat) return flat_post_blocks(P);
   const int k = pp_index(P.team_pp);
   if (P.pblk_n[k] > 0) return P.pblk_n[k];
   const int tpb = 256 / P.team_pp;

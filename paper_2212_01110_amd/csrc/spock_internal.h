@@ -179,6 +179,13 @@ struct Problem {
   const int* d_pblk[4] = {};
   int pblk_n[4] = {};
   int pblk_cap[4] = {};
+  // flat post-pass (one wavefront per family or leaf) in place of the team
+  // forms; d_spos [nn]: offset in z of s^c in its ancestor's block (0 at
+  // the root)
+  bool post_flat = false;
+  const long long* d_spos = nullptr;
+  int ncu = 256;    // compute units of the device (grid of the flat post-pass)
+  int flat_bpc = 1;  // resident blocks of the flat post-pass per compute unit
   bool tuned = false;
   // general conic risk / polyhedral constraints (general kernels for the
   // pre- and post-passes, L, L*, prox of g* and M; device block gmem)
@@ -213,6 +220,9 @@ hipError_t launch_T(const Problem& P, const S* v, S* Tv, const double* x0, S* q,
                     S* ubar, double* partials, double* stats_dev, hipStream_t st,
                     const S* eta_zero, bool dual, Publish pub = Publish{}, SweepMap map = SweepMap{});
 int post_blocks(const Problem& P);
+int flat_post_blocks(const Problem& P);
+template <typename S>
+int flat_post_occupancy();
 // General problems (general.hip): pre-pass, post-pass with statistics
 // (post_blocks records), L, L*, prox of g* and M, one thread per family.
 // kGenMaxBlock bounds ny + 2 n_i of a family (its (y, tau, s) block).

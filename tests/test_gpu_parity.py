@@ -389,6 +389,27 @@ def test_post_pass_forms(name, tpp, form, prec, monkeypatch):
     _check_stats("stats_post:" + tag, st, O.residual_stats(op, r), r, op, STAT_TOL[prec])
 
 
+@pytest.mark.parametrize("prec", list(FP))
+@pytest.mark.parametrize("name", POST_CASES + ["b3-1-2", "config1", "b2-1-2-nu24"])
+def test_post_pass_flat(name, prec, monkeypatch):
+    # the flat post-pass (one wavefront per family or leaf, n_x + n_u up to
+    # 128 on two slots per lane): T and its statistics against the oracle
+    monkeypatch.setenv("SPOCK_TEAM", "512")
+    monkeypatch.setenv("SPOCK_POST", "flat")
+    inst = CASES[name]
+    gp, op = build(inst, FP[prec][0])
+    vt = dev(seeded(f"postflat:{name}").standard_normal(op.lay.n_v), gp.torch_dtype)
+    x0 = dev(op.inst.x0, torch.float64)
+    Tv = torch.zeros_like(vt)
+    st = gp.T(vt, x0, Tv)
+    vin = host(vt)
+    ref = O.T_apply(op, vin, op.inst.x0)
+    tag = f"{name}:flat:{prec}"
+    check("T_post:" + tag, relerr(host(Tv), ref), FP[prec][1])
+    r = vin - ref
+    _check_stats("stats_post:" + tag, st, O.residual_stats(op, r), r, op, STAT_TOL[prec])
+
+
 # ---------------------------------------------------------------- the 20 776-node tree
 @pytest.fixture(scope="module")
 def tree20776():
@@ -407,12 +428,16 @@ def tree20776():
     return inst, op, v
 
 
+@pytest.mark.parametrize("post", ["team", "flat"])
 @pytest.mark.parametrize("prec", list(FP))
-def test_T_and_prox_f_on_20776_node_tree(tree20776, prec, monkeypatch):
+def test_T_and_prox_f_on_20776_node_tree(tree20776, prec, post, monkeypatch):
     # the dataflow sweeps at the size the benchmark times: about 20 items per
     # workgroup, LDS reused across items and cross-round waits, element by
-    # element against the oracle
+    # element against the oracle; both post-pass forms (the flat one runs
+    # several units per wavefront here)
     monkeypatch.setenv("SPOCK_TEAM", "512")
+    if post == "flat":
+        monkeypatch.setenv("SPOCK_POST", "flat")
     inst, op, v = tree20776
     gp = SP.Problem.from_instance(inst, precision=FP[prec][0], alpha=op.alpha)
     dt = gp.torch_dtype
@@ -424,9 +449,9 @@ def test_T_and_prox_f_on_20776_node_tree(tree20776, prec, monkeypatch):
     assert got["mapping"] == 512 and got["flow_grid"] > 0 and not got["flow_failed"], got
     vin = host(vt)
     ref = O.T_apply(op, vin, inst.x0)
-    check(f"T:tree20776:{prec}", relerr(host(Tv), ref), FP[prec][1])
+    check(f"T:tree20776:{prec}:{post}", relerr(host(Tv), ref), FP[prec][1])
     r = vin - ref
-    _check_stats(f"stats:tree20776:{prec}", st, O.residual_stats(op, r), r, op, STAT_TOL[prec])
+    _check_stats(f"stats:tree20776:{prec}:{post}", st, O.residual_stats(op, r), r, op, STAT_TOL[prec])
     zo = torch.zeros(op.lay.n_z, dtype=dt, device="cuda")
     gp.prox_f(vt[: op.lay.n_z].contiguous(), x0, zo)
     reff = O.prox_f(op.lay, inst, op.fac, vin[: op.lay.n_z], op.alpha, inst.x0)
