@@ -37,6 +37,9 @@ def _cases():
         # forward; n_x = 37: uneven halves and thirds of the input ranges
         "b2-1-2-nu24": G.make_random_small(17, [2, 1, 2], 8, 24),
         "b3-1-nx37": G.make_random_small(18, [3, 1], 37, 21),
+        # a family of 70 children: more than one wavefront's lanes in the
+        # y block of the flat post-pass
+        "b70-2": G.make_random_small(19, [70, 2], 3, 2),
     }
 
 
@@ -390,10 +393,11 @@ def test_post_pass_forms(name, tpp, form, prec, monkeypatch):
 
 
 @pytest.mark.parametrize("prec", list(FP))
-@pytest.mark.parametrize("name", POST_CASES + ["b3-1-2", "config1", "b2-1-2-nu24"])
+@pytest.mark.parametrize("name", POST_CASES + ["b3-1-2", "config1", "b2-1-2-nu24", "b70-2"])
 def test_post_pass_flat(name, prec, monkeypatch):
     # the flat post-pass (one wavefront per family or leaf, n_x + n_u up to
-    # 128 on two slots per lane): T and its statistics against the oracle
+    # 128 on two slots per lane, more than 64 children in the y block): T
+    # and its statistics against the oracle
     monkeypatch.setenv("SPOCK_TEAM", "512")
     monkeypatch.setenv("SPOCK_POST", "flat")
     inst = CASES[name]
