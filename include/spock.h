@@ -243,7 +243,8 @@ int spock_solve_batched(int32_t B, spock_problem* const* probs,
  * w = J_T(v*)' w + g, applied with the transposed CP operator (projection
  * Jacobians at the stored pre-prox point, Alg. 2 sweeps with zero root state
  * for the S1 projection), is solved as (I - J_T(v*)') w = g by restarted
- * GMRES (60 Krylov vectors; the environment variable SPOCK_ADJ_RESTART sets
+ * GMRES (120 Krylov vectors, 30 when 121 basis vectors would exceed 256 MiB;
+ * the environment variable SPOCK_ADJ_RESTART sets
  * 2 to 120), then the parameter Jacobian of T is applied.
  *   v_star_dev: [n_v] of the problem precision, the output of spock_solve
  *   x0_dev: FP64 [nx]; gV: cotangent of V*; gu0_dev: FP64 [nu] cotangent of u^0 or NULL

@@ -2100,23 +2100,32 @@ int backward_once(Problem& P, const S* vstar, const double* x0, double gV, const
     return SPOCK_OK;
   };
   // The fixed point of the affine map solves (I - J_T') w = g: restarted
-  // GMRES (kAdjRestart Krylov vectors, 60 unless SPOCK_ADJ_RESTART gives 2 to
-  // 120; about 3x fewer evaluations of A than the plain iteration on the
-  // 95-node tree at 1e-12; on eight instances of that tree 60 takes 25% fewer
-  // evaluations than 30 and 12% less time in FP32, while 120 saves
-  // evaluations but not time; classical Gram-Schmidt with one
+  // GMRES (kAdjRestart Krylov vectors, 120 or 30 as below unless
+  // SPOCK_ADJ_RESTART gives 2 to 120; about 3x fewer evaluations of A than the plain iteration on the
+  // 95-node tree at 1e-12; on eight instances of that tree 120 takes 35%
+  // fewer evaluations than 30, and with the Gram-Schmidt passes as single
+  // launches over the whole basis an evaluation costs the same at either
+  // length; classical Gram-Schmidt with one
   // reorthogonalisation, FP64 dot products and Hessenberg least squares on
   // the host), M v = v - A(v) + g. Convergence is judged on the true
   // residual |w - A(w)|_inf <= eps max(1, |w|_inf) at every restart; k counts
   // the evaluations of A.
   constexpr int kAdjMax = 120;
-  int kAdjRestart = 60;
+  // Small problems are launch-bound, and the passes cost little at any
+  // length; on large ones the passes stream the basis (about 4 reads of it
+  // per step), so the length stays at 30 once the basis would pass 256 MiB.
+  int kAdjRestart = sizeof(S) * (size_t)(kAdjMax + 1) * (size_t)nv <= (size_t(256) << 20) ? kAdjMax : 30;
   if (const char* env = std::getenv("SPOCK_ADJ_RESTART")) kAdjRestart = std::max(2, std::min(kAdjMax, std::atoi(env)));
   S* Aw = wn;
-  // Krylov vectors and the dot products of one Gram-Schmidt pass
+  static_assert(kAdjMax + 1 <= kBasisMax, "basis kernels hold every Krylov vector");
+  // Krylov vectors, the dot products of one Gram-Schmidt pass and their
+  // per-chunk partial sums
   const size_t basis_bytes = (sizeof(S) * (size_t)(kAdjRestart + 1) * (size_t)nv + 255) & ~size_t(255);
+  const size_t dots_bytes = sizeof(double) * (kAdjMax + 2);
   void* kmem = nullptr;
-  if (hipMalloc(&kmem, basis_bytes + sizeof(double) * (kAdjMax + 1)) != hipSuccess) return SPOCK_ENOMEM;
+  if (hipMalloc(&kmem, basis_bytes + dots_bytes + sizeof(double) * (size_t)(kAdjMax + 2) * kBasisChunks) !=
+      hipSuccess)
+    return SPOCK_ENOMEM;
   struct KrylovGuard {
     void* p;
     ~KrylovGuard() { (void)hipFree(p); }
@@ -2124,42 +2133,20 @@ int backward_once(Problem& P, const S* vstar, const double* x0, double gV, const
   S* basis = static_cast<S*>(kmem);
   auto V = [&](int j) { return basis + (size_t)j * (size_t)nv; };
   double* dots_dev = reinterpret_cast<double*>(static_cast<char*>(kmem) + basis_bytes);
-  // h[i] = <V_i, x> for i < n (n <= kAdjRestart + 1), one synchronisation
-  auto dots_with = [&](int n, const S* x, double* h) -> int {
-    for (int b = 0; b < n; b += 8) {
-      VecPtrs<S> X{}, Y{};
-      const int c = std::min(8, n - b);
-      for (int j = 0; j < c; ++j) {
-        X.p[j] = V(b + j);
-        Y.p[j] = x;
-      }
-      HIP_TRY(launch_dots<S>(nv, c, X, Y, W.vpart, dots_dev + b, st));
-    }
-    HIP_TRY(hipMemcpyAsync(h, dots_dev, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+  double* dots_part = reinterpret_cast<double*>(static_cast<char*>(kmem) + basis_bytes + dots_bytes);
+  // h[i] = <V_i, x> for i < n, and h[n] = <x, x> when xx: one pair of
+  // launches and one synchronisation
+  auto dots_with = [&](int n, const S* x, double* h, bool xx) -> int {
+    HIP_TRY(launch_basis_dots<S>(nv, n, basis, nv, x, xx, dots_part, dots_dev, st));
+    HIP_TRY(hipMemcpyAsync(h, dots_dev, sizeof(double) * (n + (xx ? 1 : 0)), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     return SPOCK_OK;
   };
-  // out = a x + sum_{i < n} c_i V_i (out may be x)
+  // out = a x + sum_{i < n} c_i V_i (out may be x), one launch
   auto mix = [&](S* out, double a, const S* x, int n, const double* c) -> int {
-    const S* cur = x;
-    double ca = a;
-    for (int b = 0; b < n || b == 0; b += kMixMax - 1) {
-      ColMix<S> M;
-      const int cnt = std::min(kMixMax - 1, n - b);
-      M.nin = 1 + std::max(cnt, 0);
-      M.nout = 1;
-      M.in[0] = cur;
-      M.c[0][0] = ca;
-      for (int j = 0; j < cnt; ++j) {
-        M.in[1 + j] = V(b + j);
-        M.c[0][1 + j] = c[b + j];
-      }
-      M.out[0] = out;
-      HIP_TRY(launch_colmix<S>(nv, M, st));
-      cur = out;
-      ca = 1.0;
-      if (n == 0) break;
-    }
+    BasisCoef C{};
+    for (int j = 0; j < n; ++j) C.c[j] = c[j];
+    HIP_TRY(launch_basis_mix<S>(nv, n, basis, nv, C, a, x, out, st));
     return SPOCK_OK;
   };
   auto norm_inf_check = [&](const S* x, const S* Ax, double& res, double& xn) -> int {
@@ -2193,7 +2180,7 @@ int backward_once(Problem& P, const S* vstar, const double* x0, double gV, const
     // r = A(w) - w = g - M w; V_0 = r / |r|
     HIP_TRY(launch_lincomb<S>(nv, V(0), 1.0, Aw, -1.0, w, st));
     double beta = 0;
-    if (int r = dots_with(1, V(0), &beta)) return r;
+    if (int r = dots_with(0, V(0), &beta, true)) return r;
     beta = std::sqrt(beta);
     if (!(beta > 0.0) || !std::isfinite(beta)) {
       info.status = std::isfinite(beta) ? SPOCK_CONVERGED : SPOCK_NUMERICAL;
@@ -2210,25 +2197,20 @@ int backward_once(Problem& P, const S* vstar, const double* x0, double gV, const
       if (int r = apply_A(V(j), Aw)) return r;
       ++k;
       HIP_TRY(launch_lincomb3<S>(nv, V(j + 1), 1.0, V(j), -1.0, Aw, 1.0, g, st));
-      double h[kAdjMax + 1], h2[kAdjMax + 1], neg[kAdjMax + 1];
-      if (int r = dots_with(j + 1, V(j + 1), h)) return r;
+      double h[kAdjMax + 2], h2[kAdjMax + 2], neg[kAdjMax + 1];
+      if (int r = dots_with(j + 1, V(j + 1), h, false)) return r;
       for (int i = 0; i <= j; ++i) neg[i] = -h[i];
       if (int r = mix(V(j + 1), 1.0, V(j + 1), j + 1, neg)) return r;
-      if (int r = dots_with(j + 1, V(j + 1), h2)) return r;
+      // second pass, with <v, v>: after it |v'|^2 = <v, v> - sum h2_i^2
+      // (the V_i orthonormal; h2 is a small correction, so no cancellation)
+      if (int r = dots_with(j + 1, V(j + 1), h2, true)) return r;
+      double hn = h2[j + 1];
       for (int i = 0; i <= j; ++i) {
         neg[i] = -h2[i];
         h[i] += h2[i];
+        hn -= h2[i] * h2[i];
       }
       if (int r = mix(V(j + 1), 1.0, V(j + 1), j + 1, neg)) return r;
-      double hn = 0;
-      {
-        VecPtrs<S> X{}, Y{};
-        X.p[0] = V(j + 1);
-        Y.p[0] = V(j + 1);
-        HIP_TRY(launch_dots<S>(nv, 1, X, Y, W.vpart, dots_dev, st));
-        HIP_TRY(hipMemcpyAsync(&hn, dots_dev, sizeof(double), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-      }
       hn = std::sqrt(std::max(hn, 0.0));
       for (int i = 0; i <= j; ++i) H(i, j) = h[i];
       H(j + 1, j) = hn;
@@ -2314,6 +2296,10 @@ extern "C" int spock_backward(spock_problem* ph, const void* v_star, const doubl
   const auto t0 = std::chrono::steady_clock::now();
   spock_info loc{};
   loc.V_nested = std::numeric_limits<double>::quiet_NaN();
+  {  // the sweep mapping and pass forms, as for a solve (once per problem)
+    const int rt = (P.precision == SPOCK_FP64) ? autotune<double>(P, st) : autotune<float>(P, st);
+    if (rt) return rt;
+  }
   loc.mapping = P.team;
   const int rc = (P.precision == SPOCK_FP64)
                      ? backward_impl<double>(P, static_cast<const double*>(v_star), x0, gV, gu0, grad_x0,

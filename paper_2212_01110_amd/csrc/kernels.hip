@@ -1787,6 +1787,69 @@ hipError_t launch_aa_dir(long long n, const S* r, const S* eb, long long stride,
   return hipGetLastError();
 }
 
+// Krylov basis kernels of the adjoint GMRES. The basis vectors are
+// V_j = basis + j * stride. k_basis_dots: block (c, j) sums chunk c of
+// <V_j, x> (j < n; <x, x> for j = n when the grid has n + 1 rows) in FP64
+// into part[j * gridDim.x + c]; k_basis_final adds the chunks in order.
+template <typename S>
+__global__ void __launch_bounds__(256) k_basis_dots(long long nv, int n, const S* __restrict__ basis,
+                                                    long long stride, const S* __restrict__ x,
+                                                    double* __restrict__ part) {
+  const int j = blockIdx.y;
+  const S* v = j < n ? basis + (size_t)j * (size_t)stride : x;
+  const long long chunk = (nv + gridDim.x - 1) / gridDim.x;
+  const long long e0 = (long long)blockIdx.x * chunk;
+  const long long e1 = e0 + chunk < nv ? e0 + chunk : nv;
+  double acc = 0;
+  for (long long e = e0 + threadIdx.x; e < e1; e += 256) acc += (double)v[e] * (double)x[e];
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(size_t)j * gridDim.x + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+__global__ void __launch_bounds__(256) k_basis_final(const double* __restrict__ part, int cb, int m,
+                                                     double* __restrict__ out) {
+  for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    double acc = 0;
+    for (int c = 0; c < cb; ++c) acc += part[(size_t)j * cb + c];
+    out[j] = acc;
+  }
+}
+// chunks per basis vector: about 8192 elements each, at most kBasisChunks
+static int basis_chunks(long long nv) {
+  const long long c = (nv + 8191) / 8192;
+  return (int)(c < 1 ? 1 : (c > kBasisChunks ? kBasisChunks : c));
+}
+template <typename S>
+hipError_t launch_basis_dots(long long nv, int n, const S* basis, long long stride, const S* x, bool xx,
+                             double* part, double* out_dev, hipStream_t st) {
+  if (n < 0 || n + (xx ? 1 : 0) > kBasisMax + 1 || n + (xx ? 1 : 0) < 1) return hipErrorInvalidValue;
+  const int cb = basis_chunks(nv), m = n + (xx ? 1 : 0);
+  hipLaunchKernelGGL(k_basis_dots<S>, dim3(cb, m), dim3(256), 0, st, nv, n, basis, stride, x, part);
+  hipLaunchKernelGGL(k_basis_final, dim3(1), dim3(256), 0, st, part, cb, m, out_dev);
+  return hipGetLastError();
+}
+// out = a x + sum_{j < n} C.c[j] V_j (out may be x: each element is read
+// before it is written, by the same thread)
+template <typename S>
+__global__ void __launch_bounds__(256) k_basis_mix(long long nv, int n, const S* __restrict__ basis,
+                                                   long long stride, BasisCoef C, double a, const S* x, S* out) {
+  SPK_GRID_LOOP(e, 0, nv) {
+    double acc = a * (double)x[e];
+    for (int j = 0; j < n; ++j) acc += C.c[j] * (double)basis[(size_t)j * (size_t)stride + e];
+    out[e] = (S)acc;
+  }
+}
+template <typename S>
+hipError_t launch_basis_mix(long long nv, int n, const S* basis, long long stride, const BasisCoef& C, double a,
+                            const S* x, S* out, hipStream_t st) {
+  if (n < 0 || n > kBasisMax) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_basis_mix<S>, dim3(dots_blocks(nv)), dim3(256), 0, st, nv, n, basis, stride, C, a, x, out);
+  return hipGetLastError();
+}
+
 // Column mix for the QR-updated Anderson step: out_i = sum_j C[i][j] in_j
 // over the elements (i < nout, j < nin, both <= kMixMax). Every thread reads
 // all inputs of its elements before it writes, so outputs may alias inputs.
@@ -1829,7 +1892,11 @@ hipError_t launch_colmix(long long n, const ColMix<S>& M, hipStream_t st) {
                                         double*, AARingDev*, double*, hipStream_t);                 \
   template hipError_t launch_aa_dir<S>(long long, const S*, const S*, long long, const AARingDev*,  \
                                        const double*, S*, const S*, S*, hipStream_t);              \
-  template hipError_t launch_colmix<S>(long long, const ColMix<S>&, hipStream_t);
+  template hipError_t launch_colmix<S>(long long, const ColMix<S>&, hipStream_t);                  \
+  template hipError_t launch_basis_dots<S>(long long, int, const S*, long long, const S*, bool, double*, \
+                                           double*, hipStream_t);                                       \
+  template hipError_t launch_basis_mix<S>(long long, int, const S*, long long, const BasisCoef&, double,   \
+                                          const S*, S*, hipStream_t);
 SPK_INST(double)
 SPK_INST(float)
 

@@ -329,6 +329,22 @@ struct ColMix {
 };
 template <typename S>
 hipError_t launch_colmix(long long n, const ColMix<S>& M, hipStream_t st);
+
+// Krylov basis of the adjoint GMRES: V_j = basis + j * stride, j < n <=
+// kBasisMax. Dots: out_dev[j] = <V_j, x> (FP64), and out_dev[n] = <x, x>
+// when xx; part holds (n + 1) * kBasisChunks doubles. Mix: out = a x +
+// sum_j C.c[j] V_j (out may be x).
+constexpr int kBasisMax = 128;
+constexpr int kBasisChunks = 64;
+struct BasisCoef {
+  double c[kBasisMax];
+};
+template <typename S>
+hipError_t launch_basis_dots(long long nv, int n, const S* basis, long long stride, const S* x, bool xx,
+                             double* part, double* out_dev, hipStream_t st);
+template <typename S>
+hipError_t launch_basis_mix(long long nv, int n, const S* basis, long long stride, const BasisCoef& C, double a,
+                            const S* x, S* out, hipStream_t st);
 // <v - Tv, w> to *out_dev (fixed-order sum in the last workgroup to finish,
 // counted on *counter, over tagged records as for the push), then the
 // statistics stats[0..8) published to pub.
