@@ -7,83 +7,113 @@
 
 namespace spk {
 
-// J_G d on a translated SOC block: vector part dv[0..len) (the last one of
-// which is the first trailing scalar), scalar dt; bv, bt the block of b*.
+// J_G d on a translated SOC block by one wavefront: vector part of len <=
+// 128 entries (lane o holds entries o and o + 64), then the two trailing
+// scalars a (entry len) and b (entry len + 1); b_ is the block of b*.
 template <typename S>
-__device__ void soc_jg(const S* b, const S* din, S* dout, int len, S al) {
-  // len = number of entries of the SOC vector part before the two scalars
+__device__ void soc_jg_wave(const S* __restrict__ b_, const S* __restrict__ din, S* __restrict__ dout, int len,
+                            S al, int lane) {
   const S ia = S(1) / al;
-  double r2 = 0;
-  for (int o = 0; o < len; ++o) r2 += (double)(b[o] * ia) * (double)(b[o] * ia);
-  const S va = b[len] * ia - S(0.5);
-  const S t = b[len + 1] * ia + S(0.5);
-  r2 += (double)va * (double)va;
+  S bv[2], dv[2];
+  double r2p = 0;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int o = lane + 64 * s;
+    const int oo = o < len ? o : 0;
+    bv[s] = o < len ? b_[oo] : S(0);
+    dv[s] = o < len ? din[oo] : S(0);
+    r2p += (double)(bv[s] * ia) * (double)(bv[s] * ia);
+  }
+  const S va = b_[len] * ia - S(0.5);
+  const S t = b_[len + 1] * ia + S(0.5);
+  const double r2 = team_sum<64>(r2p) + (double)va * (double)va;
   const S r = (S)sqrt(r2);
+  const S da = din[len], dt = din[len + 1];
   if (r <= t) {  // inside the cone: proj Jacobian = I, J_G = 0
-    for (int o = 0; o < len + 2; ++o) dout[o] = S(0);
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+      if (lane + 64 * s < len) dout[lane + 64 * s] = S(0);
+    if (lane == 0) {
+      dout[len] = S(0);
+      dout[len + 1] = S(0);
+    }
     return;
   }
   if (r <= -t) {  // polar cone: proj Jacobian = 0, J_G = I
-    for (int o = 0; o < len + 2; ++o) dout[o] = din[o];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+      if (lane + 64 * s < len) dout[lane + 64 * s] = dv[s];
+    if (lane == 0) {
+      dout[len] = da;
+      dout[len + 1] = dt;
+    }
     return;
   }
   // J_proj (x, t) -> 1/2 [ (1 + t/r) dx - (t/r) xh (xh.dx) + xh dt ; xh.dx + dt ],
   // xh = x / r, x = (b_vec / alpha, b_a / alpha - 1/2)
   const S ir = S(1) / r;
-  double xd = 0;
-  for (int o = 0; o < len; ++o) xd += (double)(b[o] * ia * ir) * (double)din[o];
-  xd += (double)(va * ir) * (double)din[len];
-  const S dt = din[len + 1];
+  double xdp = 0;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) xdp += (double)(bv[s] * ia * ir) * (double)dv[s];
+  const double xd = team_sum<64>(xdp) + (double)(va * ir) * (double)da;
   const S tr = t * ir;
-  for (int o = 0; o < len; ++o) {
-    const S xh = b[o] * ia * ir;
-    const S jp = S(0.5) * ((S(1) + tr) * din[o] - tr * xh * (S)xd + xh * dt);
-    dout[o] = din[o] - jp;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    if (lane + 64 * s < len) {
+      const S xh = bv[s] * ia * ir;
+      const S jp = S(0.5) * ((S(1) + tr) * dv[s] - tr * xh * (S)xd + xh * dt);
+      dout[lane + 64 * s] = dv[s] - jp;
+    }
   }
-  {
+  if (lane == 0) {
     const S xh = va * ir;
-    const S jp = S(0.5) * ((S(1) + tr) * din[len] - tr * xh * (S)xd + xh * dt);
-    dout[len] = din[len] - jp;
+    const S jp = S(0.5) * ((S(1) + tr) * da - tr * xh * (S)xd + xh * dt);
+    dout[len] = da - jp;
+    dout[len + 1] = dt - S(0.5) * ((S)xd + dt);
   }
-  dout[len + 1] = dt - S(0.5) * ((S)xd + dt);
 }
 
-// out = J_G(b*) w on every block of S3 (one thread per family).
+// out = J_G(b*) w on every block of S3: one wavefront per family (group 1
+// of i, group 2 of each child, group 3 of leaf children), grid-stride.
 template <typename S>
-__global__ void k_jg(DevProb<S> P, const S* __restrict__ b, const S* __restrict__ w, S* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= P.nl) return;
+__global__ void __launch_bounds__(256) k_jg(DevProb<S> P, const S* __restrict__ b, const S* __restrict__ w,
+                                            S* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
   const Off<S> O(P);
-  const int nx = P.nx, nu = P.nu, fc = P.fc[i], n = P.nch[i];
+  const int nx = P.nx, nu = P.nu;
   const S al = P.alpha, ia = S(1) / al;
-  const long long e1 = O.e1(i);
-  for (int k = 0; k < 2 * n; ++k) out[e1 + k] = (b[e1 + k] <= S(0)) ? w[e1 + k] : S(0);  // K*: max(.,0)
-  out[e1 + 2 * n] = S(0);                                                              // free entry
-  out[e1 + 2 * n + 1] = (b[e1 + 2 * n + 1] <= S(0)) ? w[e1 + 2 * n + 1] : S(0);          // R_+
-  for (int o = 0; o < nx; ++o) {
-    const long long e = O.e1x(i) + o;
-    const S v = b[e] * ia;
-    const bool in = v > P.xlo[(size_t)i * nx + o] && v < P.xhi[(size_t)i * nx + o];
-    out[e] = in ? S(0) : w[e];
-  }
-  for (int o = 0; o < nu; ++o) {
-    const long long e = O.e1u(i) + o;
-    const S v = b[e] * ia;
-    const bool in = v > P.ulo[(size_t)i * nu + o] && v < P.uhi[(size_t)i * nu + o];
-    out[e] = in ? S(0) : w[e];
-  }
-  for (int k = 0; k < n; ++k) {
-    const int c = fc + k;
-    const long long e2 = O.e2(c);
-    soc_jg<S>(b + e2, w + e2, out + e2, nx + nu, al);
-    if (c >= P.nl) {
-      const long long e3 = O.e3(c);
-      for (int o = 0; o < nx; ++o) {
-        const S v = b[e3 + o] * ia;
-        const bool in = v > P.xlo[(size_t)c * nx + o] && v < P.xhi[(size_t)c * nx + o];
-        out[e3 + o] = in ? S(0) : w[e3 + o];
+  for (int i = blockIdx.x * 4 + (int)(threadIdx.x >> 6); i < P.nl; i += gridDim.x * 4) {
+    const int fc = P.fc[i], n = P.nch[i];
+    const long long e1 = O.e1(i);
+    for (int k = lane; k < 2 * n; k += 64) out[e1 + k] = (b[e1 + k] <= S(0)) ? w[e1 + k] : S(0);  // K*: max(.,0)
+    if (lane == 0) {
+      out[e1 + 2 * n] = S(0);                                                       // free entry
+      out[e1 + 2 * n + 1] = (b[e1 + 2 * n + 1] <= S(0)) ? w[e1 + 2 * n + 1] : S(0);  // R_+
+    }
+    for (int o = lane; o < nx; o += 64) {
+      const long long e = O.e1x(i) + o;
+      const S v = b[e] * ia;
+      const bool in = v > P.xlo[(size_t)i * nx + o] && v < P.xhi[(size_t)i * nx + o];
+      out[e] = in ? S(0) : w[e];
+    }
+    for (int o = lane; o < nu; o += 64) {
+      const long long e = O.e1u(i) + o;
+      const S v = b[e] * ia;
+      const bool in = v > P.ulo[(size_t)i * nu + o] && v < P.uhi[(size_t)i * nu + o];
+      out[e] = in ? S(0) : w[e];
+    }
+    for (int c = fc; c < fc + n; ++c) {
+      const long long e2 = O.e2(c);
+      soc_jg_wave<S>(b + e2, w + e2, out + e2, nx + nu, al, lane);
+      if (c >= P.nl) {
+        const long long e3 = O.e3(c);
+        for (int o = lane; o < nx; o += 64) {
+          const S v = b[e3 + o] * ia;
+          const bool in = v > P.xlo[(size_t)c * nx + o] && v < P.xhi[(size_t)c * nx + o];
+          out[e3 + o] = in ? S(0) : w[e3 + o];
+        }
+        soc_jg_wave<S>(b + e3 + nx, w + e3 + nx, out + e3 + nx, nx, al, lane);
       }
-      soc_jg<S>(b + e3 + nx, w + e3 + nx, out + e3 + nx, nx, al);
     }
   }
 }
@@ -185,7 +215,7 @@ template <typename S>
 hipError_t launch_jg(const Problem& P, const S* b, const S* w, S* out, hipStream_t st) {
   const DevProb<S>& D = (sizeof(S) == 8) ? *reinterpret_cast<const DevProb<S>*>(&P.dp64)
                                          : *reinterpret_cast<const DevProb<S>*>(&P.dp32);
-  hipLaunchKernelGGL(k_jg<S>, dim3((P.tree->nl + 127) / 128), dim3(128), 0, st, D, b, w, out);
+  hipLaunchKernelGGL(k_jg<S>, dim3(family_wave_blocks(P.tree->nl)), dim3(256), 0, st, D, b, w, out);
   return hipGetLastError();
 }
 template <typename S>

@@ -2121,7 +2121,7 @@ int backward_once(Problem& P, const S* vstar, const double* x0, double gV, const
   // Krylov vectors, the dot products of one Gram-Schmidt pass and their
   // per-chunk partial sums
   const size_t basis_bytes = (sizeof(S) * (size_t)(kAdjRestart + 1) * (size_t)nv + 255) & ~size_t(255);
-  const size_t dots_bytes = sizeof(double) * (kAdjMax + 2);
+  const size_t dots_bytes = sizeof(double) * 2 * (kAdjMax + 2);  // the two passes' coefficients
   void* kmem = nullptr;
   if (hipMalloc(&kmem, basis_bytes + dots_bytes + sizeof(double) * (size_t)(kAdjMax + 2) * kBasisChunks) !=
       hipSuccess)
@@ -2149,6 +2149,30 @@ int backward_once(Problem& P, const S* vstar, const double* x0, double gV, const
     HIP_TRY(launch_basis_mix<S>(nv, n, basis, nv, C, a, x, out, st));
     return SPOCK_OK;
   };
+  // Arnoldi steps are pipelined: the passes take their coefficients from
+  // device memory, the reduction kernels also write them to mapped pinned
+  // host memory, and the host reduces column j of the Hessenberg matrix
+  // while step j + 1 runs (two slots, alternating).
+  double* d1 = dots_dev;
+  double* d2 = dots_dev + (kAdjMax + 2);
+  double* hp = nullptr;
+  if (hipHostMalloc(reinterpret_cast<void**>(&hp), sizeof(double) * 4 * (kAdjMax + 2),
+                    hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess)
+    return SPOCK_ENOMEM;
+  hipEvent_t evs[2] = {nullptr, nullptr};
+  struct PipeGuard {
+    double* hp;
+    hipEvent_t* ev;
+    ~PipeGuard() {
+      for (int e = 0; e < 2; ++e)
+        if (ev[e]) (void)hipEventDestroy(ev[e]);
+      (void)hipHostFree(hp);
+    }
+  } pguard{hp, evs};
+  for (int e = 0; e < 2; ++e)
+    if (hipEventCreateWithFlags(&evs[e], hipEventDisableTiming) != hipSuccess) return SPOCK_EHIP;
+  double* hp_dev = nullptr;  // the kernels write the slots through this view
+  if (hipHostGetDevicePointer(reinterpret_cast<void**>(&hp_dev), hp, 0) != hipSuccess) return SPOCK_EHIP;
   auto norm_inf_check = [&](const S* x, const S* Ax, double& res, double& xn) -> int {
     HIP_TRY(launch_maxdiff<S>(nv, x, Ax, W.vpart, W.dots, st));
     HIP_TRY(launch_maxdiff<S>(nv, x, zeros, W.vpart, W.dots + 1, st));
@@ -2192,27 +2216,19 @@ int backward_once(Problem& P, const S* vstar, const double* x0, double gV, const
     double cs[kAdjMax] = {}, sn[kAdjMax] = {}, gv[kAdjMax + 1] = {};
     gv[0] = beta;
     int jn = 0;
-    for (int j = 0; j < kAdjRestart && k < s.max_iters; ++j) {
-      // V_{j+1} <- M V_j = V_j - A(V_j) + g
-      if (int r = apply_A(V(j), Aw)) return r;
-      ++k;
-      HIP_TRY(launch_lincomb3<S>(nv, V(j + 1), 1.0, V(j), -1.0, Aw, 1.0, g, st));
-      double h[kAdjMax + 2], h2[kAdjMax + 2], neg[kAdjMax + 1];
-      if (int r = dots_with(j + 1, V(j + 1), h, false)) return r;
-      for (int i = 0; i <= j; ++i) neg[i] = -h[i];
-      if (int r = mix(V(j + 1), 1.0, V(j + 1), j + 1, neg)) return r;
-      // second pass, with <v, v>: after it |v'|^2 = <v, v> - sum h2_i^2
-      // (the V_i orthonormal; h2 is a small correction, so no cancellation)
-      if (int r = dots_with(j + 1, V(j + 1), h2, true)) return r;
+    // column j of H from slot j & 1 (the two passes' dots, <v, v> before
+    // the second); true when the Krylov space is done (small residual or a
+    // breakdown): the step launched after it is then discarded
+    auto column = [&](int j) -> int {
+      HIP_TRY(hipEventSynchronize(evs[j & 1]));
+      const double* h1 = hp + (size_t)(j & 1) * 2 * (kAdjMax + 2);
+      const double* h2 = h1 + (kAdjMax + 2);
       double hn = h2[j + 1];
       for (int i = 0; i <= j; ++i) {
-        neg[i] = -h2[i];
-        h[i] += h2[i];
+        H(i, j) = h1[i] + h2[i];
         hn -= h2[i] * h2[i];
       }
-      if (int r = mix(V(j + 1), 1.0, V(j + 1), j + 1, neg)) return r;
       hn = std::sqrt(std::max(hn, 0.0));
-      for (int i = 0; i <= j; ++i) H(i, j) = h[i];
       H(j + 1, j) = hn;
       for (int i = 0; i < j; ++i) {  // earlier rotations on column j
         const double x = H(i, j), y = H(i + 1, j);
@@ -2227,9 +2243,36 @@ int backward_once(Problem& P, const S* vstar, const double* x0, double gV, const
       gv[j + 1] = -sn[j] * gv[j];
       gv[j] = cs[j] * gv[j];
       jn = j + 1;
-      if (!std::isfinite(gv[j + 1])) break;
-      if (std::fabs(gv[j + 1]) <= 0.5 * thr || !(hn > 0.0)) break;
-      HIP_TRY(launch_lincomb<S>(nv, V(j + 1), 1.0 / hn, V(j + 1), 0.0, nullptr, st));
+      if (!std::isfinite(gv[j + 1])) return 1;
+      if (std::fabs(gv[j + 1]) <= 0.5 * thr || !(hn > 0.0)) return 1;
+      return 0;
+    };
+    int j = 0;
+    bool done = false;
+    for (; j < kAdjRestart && k < s.max_iters; ++j) {
+      // V_{j+1} <- M V_j = V_j - A(V_j) + g, then two Gram-Schmidt passes
+      // and the normalisation, all on the device
+      if (int r = apply_A(V(j), Aw)) return r;
+      ++k;
+      HIP_TRY(launch_lincomb3<S>(nv, V(j + 1), 1.0, V(j), -1.0, Aw, 1.0, g, st));
+      double* slot = hp_dev + (size_t)(j & 1) * 2 * (kAdjMax + 2);
+      HIP_TRY(launch_basis_dots<S>(nv, j + 1, basis, nv, V(j + 1), false, dots_part, d1, st, slot));
+      HIP_TRY(launch_basis_orth<S>(nv, j + 1, basis, nv, d1, false, V(j + 1), st));
+      HIP_TRY(launch_basis_dots<S>(nv, j + 1, basis, nv, V(j + 1), true, dots_part, d2, st, slot + (kAdjMax + 2)));
+      HIP_TRY(launch_basis_orth<S>(nv, j + 1, basis, nv, d2, true, V(j + 1), st));
+      HIP_TRY(hipEventRecord(evs[j & 1], st));
+      if (j > 0) {
+        const int r = column(j - 1);
+        if (r < 0) return r;
+        if (r > 0) {
+          done = true;
+          break;
+        }
+      }
+    }
+    if (!done && j > 0) {
+      const int r = column(j - 1);
+      if (r < 0) return r;
     }
     // w += V y, H y = g (upper triangular)
     double y[kAdjMax] = {};

@@ -959,76 +959,96 @@ template hipError_t launch_T<float>(const Problem&, const float*, float*, const 
                                     bool, Publish, SweepMap);
 
 // ---------------------------------------------------------------- L and L*
-// One thread per family (test entry points; simple and exact).
+// One wavefront per family (grid-stride over families, four per block):
+// the family's rows of L (group 1 of i, group 2 of each child, group 3 of
+// leaf children) and its columns of L* (y^i, s^i, x^i, u^i, tau^c, and x^c,
+// s^c of leaf children), lanes over components. Every entry is written by
+// exactly one family; sums over children run in child order.
 template <typename S>
-__global__ void k_apply_L(DevProb<S> P, const S* __restrict__ z, S* __restrict__ eta) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= P.nl) return;
+__global__ void __launch_bounds__(256) k_apply_L(DevProb<S> P, const S* __restrict__ z, S* __restrict__ eta) {
+  const int lane = threadIdx.x & 63;
   const Off<S> O(P);
-  const int nx = P.nx, nu = P.nu, fc = P.fc[i], n = P.nch[i];
-  const long long zb = O.z2(i), e1 = O.e1(i);
-  S by = z[zb + 2 * n];
-  for (int k = 0; k < 2 * n + 1; ++k) eta[e1 + k] = z[zb + k];
-  for (int k = 0; k < n; ++k) by += P.p[fc + k] * z[zb + k];
-  eta[e1 + 2 * n + 1] = z[O.s(i)] - by;
-  for (int o = 0; o < nx; ++o) eta[O.e1x(i) + o] = z[O.x(i) + o];
-  for (int o = 0; o < nu; ++o) eta[O.e1u(i) + o] = z[O.u(i) + o];
-  for (int k = 0; k < n; ++k) {
-    const int c = fc + k;
-    const long long e2 = O.e2(c);
-    for (int o = 0; o < nx; ++o) eta[e2 + o] = P.sq[(size_t)c * nx + o] * z[O.x(i) + o];
-    for (int o = 0; o < nu; ++o) eta[e2 + nx + o] = P.sr[(size_t)c * nu + o] * z[O.u(i) + o];
-    const S th = S(0.5) * z[O.tau(c)];
-    eta[e2 + nx + nu] = th;
-    eta[e2 + nx + nu + 1] = th;
-    if (c >= P.nl) {
-      const long long e3 = O.e3(c);
-      for (int o = 0; o < nx; ++o) {
-        eta[e3 + o] = z[O.x(c) + o];
-        eta[e3 + nx + o] = P.sqN[(size_t)c * nx + o] * z[O.x(c) + o];
+  const int nx = P.nx, nu = P.nu, K = nx + nu;
+  for (int i = blockIdx.x * 4 + (int)(threadIdx.x >> 6); i < P.nl; i += gridDim.x * 4) {
+    const int fc = P.fc[i], n = P.nch[i];
+    const long long zb = O.z2(i), e1 = O.e1(i), e1x = e1 + 2LL * n + 2;
+    double by = 0;
+    for (int k = lane; k < 2 * n + 1; k += 64) {
+      const S y = z[zb + k];
+      eta[e1 + k] = y;
+      if (k < n) by += (double)(P.p[fc + k] * y);
+    }
+    by = team_sum<64>(by) + (double)z[zb + 2 * n];
+    if (lane == 0) eta[e1 + 2 * n + 1] = z[O.s(i)] - (S)by;
+    for (int k = lane; k < K; k += 64) eta[e1x + k] = k < nx ? z[O.x(i) + k] : z[O.u(i) + (k - nx)];
+    for (int c = fc; c < fc + n; ++c) {
+      const long long e2 = O.e2(c);
+      for (int k = lane; k < K; k += 64)
+        eta[e2 + k] = k < nx ? P.sq[(size_t)c * nx + k] * z[O.x(i) + k]
+                             : P.sr[(size_t)c * nu + (k - nx)] * z[O.u(i) + (k - nx)];
+      if (lane == 0) {
+        const S th = S(0.5) * z[zb + 2LL * n + 1 + (c - fc)];
+        eta[e2 + K] = th;
+        eta[e2 + K + 1] = th;
       }
-      const S sh = S(0.5) * z[O.s(c)];
-      eta[e3 + 2 * nx] = sh;
-      eta[e3 + 2 * nx + 1] = sh;
+      if (c >= P.nl) {
+        const long long e3 = O.e3(c);
+        for (int o = lane; o < nx; o += 64) {
+          const S xc = z[O.x(c) + o];
+          eta[e3 + o] = xc;
+          eta[e3 + nx + o] = P.sqN[(size_t)c * nx + o] * xc;
+        }
+        if (lane == 0) {
+          const S sh = S(0.5) * z[zb + 3LL * n + 1 + (c - fc)];
+          eta[e3 + 2 * nx] = sh;
+          eta[e3 + 2 * nx + 1] = sh;
+        }
+      }
     }
   }
 }
 
 template <typename S>
-__global__ void k_apply_Lt(DevProb<S> P, const S* __restrict__ eta, S* __restrict__ z) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= P.nl) return;
+__global__ void __launch_bounds__(256) k_apply_Lt(DevProb<S> P, const S* __restrict__ eta, S* __restrict__ z) {
+  const int lane = threadIdx.x & 63;
   const Off<S> O(P);
-  const int nx = P.nx, nu = P.nu, fc = P.fc[i], n = P.nch[i];
-  const long long zb = O.z2(i), e1 = O.e1(i);
-  const S es = eta[O.e1s(i)];
-  for (int k = 0; k < 2 * n + 1; ++k) {
-    const S bk = (k < n) ? P.p[fc + k] : ((k == 2 * n) ? S(1) : S(0));
-    z[zb + k] = eta[e1 + k] - bk * es;
-  }
-  z[O.s(i)] = es;
-  for (int o = 0; o < nx; ++o) {
-    S acc = eta[O.e1x(i) + o];
-    for (int k = 0; k < n; ++k) acc += P.sq[(size_t)(fc + k) * nx + o] * eta[O.e2(fc + k) + o];
-    z[O.x(i) + o] = acc;
-  }
-  for (int o = 0; o < nu; ++o) {
-    S acc = eta[O.e1u(i) + o];
-    for (int k = 0; k < n; ++k) acc += P.sr[(size_t)(fc + k) * nu + o] * eta[O.e2(fc + k) + nx + o];
-    z[O.u(i) + o] = acc;
-  }
-  for (int k = 0; k < n; ++k) {
-    const int c = fc + k;
-    const long long e2 = O.e2(c);
-    z[O.tau(c)] = S(0.5) * (eta[e2 + nx + nu] + eta[e2 + nx + nu + 1]);
-    if (c >= P.nl) {
-      const long long e3 = O.e3(c);
-      for (int o = 0; o < nx; ++o)
-        z[O.x(c) + o] = eta[e3 + o] + P.sqN[(size_t)c * nx + o] * eta[e3 + nx + o];
-      z[O.s(c)] = S(0.5) * (eta[e3 + 2 * nx] + eta[e3 + 2 * nx + 1]);
+  const int nx = P.nx, nu = P.nu, K = nx + nu;
+  for (int i = blockIdx.x * 4 + (int)(threadIdx.x >> 6); i < P.nl; i += gridDim.x * 4) {
+    const int fc = P.fc[i], n = P.nch[i];
+    const long long zb = O.z2(i), e1 = O.e1(i), e1x = e1 + 2LL * n + 2;
+    const S es = eta[e1 + 2 * n + 1];
+    for (int k = lane; k < 2 * n + 1; k += 64) {
+      const S bk = (k < n) ? P.p[fc + k] : ((k == 2 * n) ? S(1) : S(0));
+      z[zb + k] = eta[e1 + k] - bk * es;
+    }
+    if (lane == 0) z[O.s(i)] = es;
+    for (int k = lane; k < K; k += 64) {
+      S acc = eta[e1x + k];
+      if (k < nx) {
+        for (int c = fc; c < fc + n; ++c) acc += P.sq[(size_t)c * nx + k] * eta[O.e2(c) + k];
+        z[O.x(i) + k] = acc;
+      } else {
+        const int o = k - nx;
+        for (int c = fc; c < fc + n; ++c) acc += P.sr[(size_t)c * nu + o] * eta[O.e2(c) + k];
+        z[O.u(i) + o] = acc;
+      }
+    }
+    for (int c = fc; c < fc + n; ++c) {
+      const long long e2 = O.e2(c);
+      if (lane == 0) z[zb + 2LL * n + 1 + (c - fc)] = S(0.5) * (eta[e2 + K] + eta[e2 + K + 1]);
+      if (c >= P.nl) {
+        const long long e3 = O.e3(c);
+        for (int o = lane; o < nx; o += 64)
+          z[O.x(c) + o] = eta[e3 + o] + P.sqN[(size_t)c * nx + o] * eta[e3 + nx + o];
+        if (lane == 0) z[zb + 3LL * n + 1 + (c - fc)] = S(0.5) * (eta[e3 + 2 * nx] + eta[e3 + 2 * nx + 1]);
+      }
     }
   }
 }
+
+// Blocks of the wavefront-per-family kernels: every family its wavefront,
+// up to 8192 blocks (then grid-stride).
+int family_wave_blocks(int nl) { return std::max(1, std::min((nl + 3) / 4, 8192)); }
 
 // M d of one problem: one team of T lanes per family.
 template <typename S, int T>
@@ -1112,15 +1132,13 @@ __global__ void k_prox_gstar(DevProb<S> P, const S* __restrict__ w, S* __restric
 template <typename S>
 hipError_t launch_L(const Problem& P, const S* z, S* eta, hipStream_t st) {
   if (P.general) return launch_gen_L<S>(P, z, eta, st);
-  const int nl = P.tree->nl;
-  hipLaunchKernelGGL(k_apply_L<S>, dim3((nl + 127) / 128), dim3(128), 0, st, dev_of<S>(P), z, eta);
+  hipLaunchKernelGGL(k_apply_L<S>, dim3(family_wave_blocks(P.tree->nl)), dim3(256), 0, st, dev_of<S>(P), z, eta);
   return hipGetLastError();
 }
 template <typename S>
 hipError_t launch_Lt(const Problem& P, const S* eta, S* z, hipStream_t st) {
   if (P.general) return launch_gen_Lt<S>(P, eta, z, st);
-  const int nl = P.tree->nl;
-  hipLaunchKernelGGL(k_apply_Lt<S>, dim3((nl + 127) / 128), dim3(128), 0, st, dev_of<S>(P), eta, z);
+  hipLaunchKernelGGL(k_apply_Lt<S>, dim3(family_wave_blocks(P.tree->nl)), dim3(256), 0, st, dev_of<S>(P), eta, z);
   return hipGetLastError();
 }
 template <typename S>
@@ -1810,11 +1828,12 @@ __global__ void __launch_bounds__(256) k_basis_dots(long long nv, int n, const S
   if (threadIdx.x == 0) part[(size_t)j * gridDim.x + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 __global__ void __launch_bounds__(256) k_basis_final(const double* __restrict__ part, int cb, int m,
-                                                     double* __restrict__ out) {
+                                                     double* __restrict__ out, double* __restrict__ host_out) {
   for (int j = threadIdx.x; j < m; j += blockDim.x) {
     double acc = 0;
     for (int c = 0; c < cb; ++c) acc += part[(size_t)j * cb + c];
     out[j] = acc;
+    if (host_out) host_out[j] = acc;  // mapped pinned memory, visible once the kernel completes
   }
 }
 // chunks per basis vector: about 8192 elements each, at most kBasisChunks
@@ -1824,11 +1843,11 @@ static int basis_chunks(long long nv) {
 }
 template <typename S>
 hipError_t launch_basis_dots(long long nv, int n, const S* basis, long long stride, const S* x, bool xx,
-                             double* part, double* out_dev, hipStream_t st) {
+                             double* part, double* out_dev, hipStream_t st, double* host_out) {
   if (n < 0 || n + (xx ? 1 : 0) > kBasisMax + 1 || n + (xx ? 1 : 0) < 1) return hipErrorInvalidValue;
   const int cb = basis_chunks(nv), m = n + (xx ? 1 : 0);
   hipLaunchKernelGGL(k_basis_dots<S>, dim3(cb, m), dim3(256), 0, st, nv, n, basis, stride, x, part);
-  hipLaunchKernelGGL(k_basis_final, dim3(1), dim3(256), 0, st, part, cb, m, out_dev);
+  hipLaunchKernelGGL(k_basis_final, dim3(1), dim3(256), 0, st, part, cb, m, out_dev, host_out);
   return hipGetLastError();
 }
 // out = a x + sum_{j < n} C.c[j] V_j (out may be x: each element is read
@@ -1847,6 +1866,35 @@ hipError_t launch_basis_mix(long long nv, int n, const S* basis, long long strid
                             const S* x, S* out, hipStream_t st) {
   if (n < 0 || n > kBasisMax) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_basis_mix<S>, dim3(dots_blocks(nv)), dim3(256), 0, st, nv, n, basis, stride, C, a, x, out);
+  return hipGetLastError();
+}
+
+// In-place Gram-Schmidt pass with device-resident coefficients: x -= sum_{j
+// < n} c[j] V_j; when norm, the result is also scaled by 1 / sqrt(c[n] -
+// sum_j c[j]^2) (c[n] = <x, x> before the pass; 0 when that is not
+// positive), so no coefficient has to travel to the host first.
+template <typename S>
+__global__ void __launch_bounds__(256) k_basis_orth(long long nv, int n, const S* __restrict__ basis,
+                                                    long long stride, const double* __restrict__ c, int norm,
+                                                    S* x) {
+  double scale = 1.0;
+  if (norm) {
+    double h2 = c[n];
+    for (int j = 0; j < n; ++j) h2 -= c[j] * c[j];
+    scale = h2 > 0.0 ? 1.0 / sqrt(h2) : 0.0;
+  }
+  SPK_GRID_LOOP(e, 0, nv) {
+    double acc = (double)x[e];
+    for (int j = 0; j < n; ++j) acc -= c[j] * (double)basis[(size_t)j * (size_t)stride + e];
+    x[e] = (S)(acc * scale);
+  }
+}
+template <typename S>
+hipError_t launch_basis_orth(long long nv, int n, const S* basis, long long stride, const double* c_dev, bool norm,
+                             S* x, hipStream_t st) {
+  if (n < 0 || n > kBasisMax) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_basis_orth<S>, dim3(dots_blocks(nv)), dim3(256), 0, st, nv, n, basis, stride, c_dev,
+                     norm ? 1 : 0, x);
   return hipGetLastError();
 }
 
@@ -1894,9 +1942,11 @@ hipError_t launch_colmix(long long n, const ColMix<S>& M, hipStream_t st) {
                                        const double*, S*, const S*, S*, hipStream_t);              \
   template hipError_t launch_colmix<S>(long long, const ColMix<S>&, hipStream_t);                  \
   template hipError_t launch_basis_dots<S>(long long, int, const S*, long long, const S*, bool, double*, \
-                                           double*, hipStream_t);                                       \
+                                           double*, hipStream_t, double*);                              \
   template hipError_t launch_basis_mix<S>(long long, int, const S*, long long, const BasisCoef&, double,   \
-                                          const S*, S*, hipStream_t);
+                                          const S*, S*, hipStream_t);                                     \
+  template hipError_t launch_basis_orth<S>(long long, int, const S*, long long, const double*, bool, S*,  \
+                                           hipStream_t);
 SPK_INST(double)
 SPK_INST(float)
 

@@ -221,6 +221,7 @@ hipError_t launch_T(const Problem& P, const S* v, S* Tv, const double* x0, S* q,
                     const S* eta_zero, bool dual, Publish pub = Publish{}, SweepMap map = SweepMap{});
 int post_blocks(const Problem& P);
 int flat_post_blocks(const Problem& P);
+int family_wave_blocks(int nl);
 template <typename S>
 int flat_post_occupancy();
 // General problems (general.hip): pre-pass, post-pass with statistics
@@ -332,7 +333,8 @@ hipError_t launch_colmix(long long n, const ColMix<S>& M, hipStream_t st);
 
 // Krylov basis of the adjoint GMRES: V_j = basis + j * stride, j < n <=
 // kBasisMax. Dots: out_dev[j] = <V_j, x> (FP64), and out_dev[n] = <x, x>
-// when xx; part holds (n + 1) * kBasisChunks doubles. Mix: out = a x +
+// when xx, also written to host_out (device view of mapped pinned memory)
+// when given; part holds (n + 1) * kBasisChunks doubles. Mix: out = a x +
 // sum_j C.c[j] V_j (out may be x).
 constexpr int kBasisMax = 128;
 constexpr int kBasisChunks = 64;
@@ -341,10 +343,15 @@ struct BasisCoef {
 };
 template <typename S>
 hipError_t launch_basis_dots(long long nv, int n, const S* basis, long long stride, const S* x, bool xx,
-                             double* part, double* out_dev, hipStream_t st);
+                             double* part, double* out_dev, hipStream_t st, double* host_out = nullptr);
 template <typename S>
 hipError_t launch_basis_mix(long long nv, int n, const S* basis, long long stride, const BasisCoef& C, double a,
                             const S* x, S* out, hipStream_t st);
+// x -= sum_{j < n} c_dev[j] V_j in place; with norm, then x /= sqrt(c_dev[n]
+// - sum_j c_dev[j]^2) (0 if that is not positive)
+template <typename S>
+hipError_t launch_basis_orth(long long nv, int n, const S* basis, long long stride, const double* c_dev, bool norm,
+                             S* x, hipStream_t st);
 // <v - Tv, w> to *out_dev (fixed-order sum in the last workgroup to finish,
 // counted on *counter, over tagged records as for the push), then the
 // statistics stats[0..8) published to pub.
