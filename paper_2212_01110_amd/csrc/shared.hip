@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -99,26 +100,117 @@ __global__ void __launch_bounds__(256) k_sh_pre(DevProb<S> P, const S* __restric
   fam_pre_team<S, T>(P, z, z + P.nz, Tv + b * vs, xbar + b * wx, ubar + b * wu, q + b * wx, f, lane);
 }
 
-// Both sweeps of Alg. 2 for 16 instances per workgroup, workgroup barriers
+// The sweeps of Alg. 2 for 16 instances per workgroup, workgroup barriers
 // between stages. The work of a stage is split into (node, 16-row tile)
 // items spread over the wavefronts: backward, the tiles of d^i and of q^i
 // (independent given the children's q); forward, the tiles of u^i and of
 // every child's x^c (independent given x^i and d^i). Backward (one mat-vec
 // phase): d^i = R~^{-1} ubar^i + sum_c Bt^c q^c, q^i = P1 ubar^i - xbar^i +
 // sum_c At^c q^c. Forward: u^i = K x^i + d^i, x^c = Abar^c x^i + B^c d^i.
-// maxch: the largest number of children of a node.
+//
+// Phases (one launch each): kShWhole walks every stage, one workgroup per
+// 16-instance tile group. With a cut stage tc, the subtrees rooted at stage
+// tc are independent: kShBwdSub runs one workgroup per (tile group,
+// subtree) over the subtree's stages bottom-up, kShBwdTop the stages above
+// tc, kShFwdTop the root state and the stages above tc, kShFwdSub the
+// subtrees top-down; so more compute units share the wide stages.
+constexpr int kShWhole = 0, kShBwdSub = 1, kShBwdTop = 2, kShFwdTop = 3, kShFwdSub = 4;
+constexpr int kShMaxLevels = 128;  // subtree levels a workgroup keeps in LDS
+
+struct ShSweepArgs {
+  int maxch, phase, tc, nsub;  // nsub: subtrees (nodes of stage tc) per tile group
+};
+
+template <typename S>
+__device__ __forceinline__ void sh_bwd_nodes(const DevProb<S>& P, int i0, int i1, S* q0, S* d0, const S* xb0,
+                                             const S* ub0, long long wx, long long wu, int lane, int wave) {
+  using acc_t = typename Mfma<S>::acc_t;
+  const int col = lane & 15, kk = lane >> 4;
+  const int nx = P.nx, nu = P.nu;
+  const int tu = (nu + 15) / 16, tx = (nx + 15) / 16;
+  const int items = (i1 - i0) * (tu + tx);
+  for (int it = wave; it < items; it += kShWaves) {
+    const int i = i0 + it / (tu + tx), sub = it % (tu + tx);
+    const int fc = P.fc[i], n = P.nch[i];
+    acc_t acc = zero_acc<S>();
+    if (sub < tu) {  // d^i, rows 16 sub ..
+      const int m0 = 16 * sub;
+      tile_mma<S>(acc, P.Rinv + (size_t)i * nu * nu, nu, nu, m0, ub0 + (size_t)i * nu, wu, lane);
+      for (int k = 0; k < n; ++k)
+        tile_mma<S>(acc, P.BtR + (size_t)(fc + k) * nx * nu, nu, nx, m0, q0 + (size_t)(fc + k) * nx, wx, lane);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + Mfma<S>::row(kk, r);
+        if (m < nu) d0[(size_t)col * wu + (size_t)i * nu + m] = acc[r];
+      }
+    } else {  // q^i
+      const int m0 = 16 * (sub - tu);
+      tile_mma<S>(acc, P.P1C + (size_t)i * nu * nx, nx, nu, m0, ub0 + (size_t)i * nu, wu, lane);
+      for (int k = 0; k < n; ++k)
+        tile_mma<S>(acc, P.AtR + (size_t)(fc + k) * nx * nx, nx, nx, m0, q0 + (size_t)(fc + k) * nx, wx, lane);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + Mfma<S>::row(kk, r);
+        if (m < nx) {
+          const size_t e = (size_t)col * wx + (size_t)i * nx + m;
+          q0[e] = acc[r] - xb0[e];
+        }
+      }
+    }
+  }
+}
+
+template <typename S>
+__device__ __forceinline__ void sh_fwd_nodes(const DevProb<S>& P, int i0, int i1, S* z0, const S* d0, long long vs,
+                                             long long wu, int maxch, int lane, int wave) {
+  using acc_t = typename Mfma<S>::acc_t;
+  const int col = lane & 15, kk = lane >> 4;
+  const int nx = P.nx, nu = P.nu;
+  const int tu = (nu + 15) / 16, tx = (nx + 15) / 16;
+  const Off<S> O(P);
+  const int per = tu + maxch * tx;
+  const int items = (i1 - i0) * per;
+  for (int it = wave; it < items; it += kShWaves) {
+    const int i = i0 + it / per, sub = it % per;
+    const int fc = P.fc[i], n = P.nch[i];
+    const S* xi = z0 + O.x(i);
+    const S* di = d0 + (size_t)i * nu;
+    acc_t acc = zero_acc<S>();
+    if (sub < tu) {  // u^i
+      const int m0 = 16 * sub;
+      tile_mma<S>(acc, P.KC + (size_t)i * nx * nu, nu, nx, m0, xi, vs, lane);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + Mfma<S>::row(kk, r);
+        if (m < nu) z0[(size_t)col * vs + O.u(i) + m] = acc[r] + di[(size_t)col * wu + m];
+      }
+    } else {  // x^c of child k
+      const int k = (sub - tu) / tx, m0 = 16 * ((sub - tu) % tx);
+      if (k >= n) continue;
+      const int c = fc + k;
+      tile_mma<S>(acc, P.AbC + (size_t)c * nx * nx, nx, nx, m0, xi, vs, lane);
+      tile_mma<S>(acc, P.BC + (size_t)c * nu * nx, nx, nu, m0, di, wu, lane);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + Mfma<S>::row(kk, r);
+        if (m < nx) z0[(size_t)col * vs + O.x(c) + m] = acc[r];
+      }
+    }
+  }
+}
+
 template <typename S>
 __global__ void __launch_bounds__(64 * kShWaves) k_sh_sweeps(DevProb<S> P, const int* __restrict__ stage_off,
                                                               S* __restrict__ Tv, const double* __restrict__ x0s,
                                                               S* __restrict__ xbar, S* __restrict__ ubar,
                                                               S* __restrict__ q, S* __restrict__ d, long long vs,
-                                                              int maxch) {
-  using acc_t = typename Mfma<S>::acc_t;
+                                                              ShSweepArgs A) {
+  __shared__ int lo[kShMaxLevels], hi[kShMaxLevels];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int col = lane & 15, kk = lane >> 4;
-  const size_t b0 = (size_t)blockIdx.x * kShCols;
+  const bool sub = A.phase == kShBwdSub || A.phase == kShFwdSub;
+  const int g = sub ? blockIdx.x / A.nsub : blockIdx.x;  // tile group
+  const size_t b0 = (size_t)g * kShCols;
   const int nx = P.nx, nu = P.nu;
-  const int tu = (nu + 15) / 16, tx = (nx + 15) / 16;
   const long long wx = (long long)P.nn * nx, wu = (long long)P.nn * nu;
   const Off<S> O(P);
   S* q0 = q + b0 * wx;
@@ -126,78 +218,51 @@ __global__ void __launch_bounds__(64 * kShWaves) k_sh_sweeps(DevProb<S> P, const
   const S* xb0 = xbar + b0 * wx;
   const S* ub0 = ubar + b0 * wu;
   S* z0 = Tv + b0 * vs;
-  for (int t = P.N - 1; t >= 0; --t) {
-    const int a = stage_off[t];
-    const int items = (stage_off[t + 1] - a) * (tu + tx);
-    for (int it = wave; it < items; it += kShWaves) {
-      const int i = a + it / (tu + tx), sub = it % (tu + tx);
-      const int fc = P.fc[i], n = P.nch[i];
-      acc_t acc = zero_acc<S>();
-      if (sub < tu) {  // d^i, rows 16 sub ..
-        const int m0 = 16 * sub;
-        tile_mma<S>(acc, P.Rinv + (size_t)i * nu * nu, nu, nu, m0, ub0 + (size_t)i * nu, wu, lane);
-        for (int k = 0; k < n; ++k)
-          tile_mma<S>(acc, P.BtR + (size_t)(fc + k) * nx * nu, nu, nx, m0, q0 + (size_t)(fc + k) * nx, wx, lane);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int m = m0 + Mfma<S>::row(kk, r);
-          if (m < nu) d0[(size_t)col * wu + (size_t)i * nu + m] = acc[r];
-        }
-      } else {  // q^i
-        const int m0 = 16 * (sub - tu);
-        tile_mma<S>(acc, P.P1C + (size_t)i * nu * nx, nx, nu, m0, ub0 + (size_t)i * nu, wu, lane);
-        for (int k = 0; k < n; ++k)
-          tile_mma<S>(acc, P.AtR + (size_t)(fc + k) * nx * nx, nx, nx, m0, q0 + (size_t)(fc + k) * nx, wx, lane);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int m = m0 + Mfma<S>::row(kk, r);
-          if (m < nx) {
-            const size_t e = (size_t)col * wx + (size_t)i * nx + m;
-            q0[e] = acc[r] - xb0[e];
-          }
-        }
+  if (sub) {
+    // node ranges of the subtree rooted at node stage_off[tc] + r, one per
+    // nonleaf stage tc .. N-1
+    const int r = blockIdx.x % A.nsub;
+    const int levels = P.N - A.tc;
+    if (threadIdx.x == 0) {
+      lo[0] = stage_off[A.tc] + r;
+      hi[0] = lo[0] + 1;
+      for (int l = 1; l < levels; ++l) {
+        lo[l] = P.fc[lo[l - 1]];
+        hi[l] = P.fc[hi[l - 1] - 1] + P.nch[hi[l - 1] - 1];
       }
     }
     __syncthreads();
-  }
-  // root state of every instance
-  for (int e = threadIdx.x; e < kShCols * nx; e += blockDim.x) {
-    const int j = e / nx, o = e % nx;
-    z0[(size_t)j * vs + O.x(0) + o] = (S)x0s[(b0 + j) * nx + o];
-  }
-  __syncthreads();
-  const int per = tu + maxch * tx;
-  for (int t = 0; t < P.N; ++t) {
-    const int a = stage_off[t];
-    const int items = (stage_off[t + 1] - a) * per;
-    for (int it = wave; it < items; it += kShWaves) {
-      const int i = a + it / per, sub = it % per;
-      const int fc = P.fc[i], n = P.nch[i];
-      const S* xi = z0 + O.x(i);
-      const S* di = d0 + (size_t)i * nu;
-      acc_t acc = zero_acc<S>();
-      if (sub < tu) {  // u^i
-        const int m0 = 16 * sub;
-        tile_mma<S>(acc, P.KC + (size_t)i * nx * nu, nu, nx, m0, xi, vs, lane);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int m = m0 + Mfma<S>::row(kk, r);
-          if (m < nu) z0[(size_t)col * vs + O.u(i) + m] = acc[r] + di[(size_t)col * wu + m];
-        }
-      } else {  // x^c of child k
-        const int k = (sub - tu) / tx, m0 = 16 * ((sub - tu) % tx);
-        if (k >= n) continue;
-        const int c = fc + k;
-        tile_mma<S>(acc, P.AbC + (size_t)c * nx * nx, nx, nx, m0, xi, vs, lane);
-        tile_mma<S>(acc, P.BC + (size_t)c * nu * nx, nx, nu, m0, di, wu, lane);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int m = m0 + Mfma<S>::row(kk, r);
-          if (m < nx) z0[(size_t)col * vs + O.x(c) + m] = acc[r];
-        }
+    if (A.phase == kShBwdSub) {
+      for (int l = levels - 1; l >= 0; --l) {
+        sh_bwd_nodes<S>(P, lo[l], hi[l], q0, d0, xb0, ub0, wx, wu, lane, wave);
+        __syncthreads();
+      }
+    } else {
+      for (int l = 0; l < levels; ++l) {
+        sh_fwd_nodes<S>(P, lo[l], hi[l], z0, d0, vs, wu, A.maxch, lane, wave);
+        __syncthreads();
       }
     }
+    return;
+  }
+  const int tb = A.phase == kShWhole ? P.N : A.tc;  // stages [0, tb) here
+  if (A.phase == kShWhole || A.phase == kShBwdTop) {
+    for (int t = tb - 1; t >= 0; --t) {
+      sh_bwd_nodes<S>(P, stage_off[t], stage_off[t + 1], q0, d0, xb0, ub0, wx, wu, lane, wave);
+      __syncthreads();
+    }
+  }
+  if (A.phase == kShWhole || A.phase == kShFwdTop) {
+    // root state of every instance
+    for (int e = threadIdx.x; e < kShCols * nx; e += blockDim.x) {
+      const int j = e / nx, o = e % nx;
+      z0[(size_t)j * vs + O.x(0) + o] = (S)x0s[(b0 + j) * nx + o];
+    }
     __syncthreads();
+    for (int t = 0; t < tb; ++t) {
+      sh_fwd_nodes<S>(P, stage_off[t], stage_off[t + 1], z0, d0, vs, wu, A.maxch, lane, wave);
+      __syncthreads();
+    }
   }
 }
 
@@ -766,6 +831,17 @@ int shared_solve(Problem& P, int B, const double* const* x0, const spock_setting
   const int sweep_grid = Bp / kShCols;
   int maxch = 1;
   for (int i = 0; i < Tr.nl; ++i) maxch = std::max(maxch, Tr.nch[i]);
+  // cut stage of the sweeps: the first stage with at least 8 nodes, if it
+  // has nonleaf stages below it (at most kShMaxLevels) and is not the root
+  // stage; SPOCK_SH_CUT overrides (0: one launch over the whole tree)
+  int sh_cut = 0;
+  for (int t = 1; t < Tr.N; ++t)
+    if (Tr.stage_off[t + 1] - Tr.stage_off[t] >= 8) {
+      sh_cut = t;
+      break;
+    }
+  if (const char* env = std::getenv("SPOCK_SH_CUT")) sh_cut = std::atoi(env);
+  if (sh_cut < 1 || sh_cut >= Tr.N || Tr.N - sh_cut > kShMaxLevels) sh_cut = 0;
   std::vector<char> prep(Bp), head(Bp);
   while (any_active()) {
     // ---- one evaluation of T at vt for every instance
@@ -775,8 +851,19 @@ int shared_solve(Problem& P, int B, const double* const* x0, const spock_setting
       case 32: sh_launch_pre<S, 32>(P, D, V, xbar, ubar, q, Bp, st); break;
       default: sh_launch_pre<S, 64>(P, D, V, xbar, ubar, q, Bp, st); break;
     }
-    hipLaunchKernelGGL(k_sh_sweeps<S>, dim3(sweep_grid), dim3(64 * kShWaves), 0, st, D, P.d_stage_off, V.tvt, x0s,
-                       xbar, ubar, q, d, vs, maxch);
+    if (sh_cut > 0) {
+      const int nsub = Tr.stage_off[sh_cut + 1] - Tr.stage_off[sh_cut];
+      for (int ph : {kShBwdSub, kShBwdTop, kShFwdTop, kShFwdSub}) {
+        const ShSweepArgs A{maxch, ph, sh_cut, nsub};
+        const bool subph = ph == kShBwdSub || ph == kShFwdSub;
+        hipLaunchKernelGGL(k_sh_sweeps<S>, dim3(subph ? sweep_grid * nsub : sweep_grid), dim3(64 * kShWaves), 0, st,
+                           D, P.d_stage_off, V.tvt, x0s, xbar, ubar, q, d, vs, A);
+      }
+    } else {
+      const ShSweepArgs A{maxch, kShWhole, 0, 1};
+      hipLaunchKernelGGL(k_sh_sweeps<S>, dim3(sweep_grid), dim3(64 * kShWaves), 0, st, D, P.d_stage_off, V.tvt, x0s,
+                         xbar, ubar, q, d, vs, A);
+    }
     switch (T) {
       case 8: sh_launch_post<S, 8>(P, D, V, partials, Bp, st); break;
       case 16: sh_launch_post<S, 16>(P, D, V, partials, Bp, st); break;

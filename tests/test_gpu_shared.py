@@ -52,11 +52,16 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("cut", ["auto", "0", "1"])
 @pytest.mark.parametrize("prec", list(FP))
 @pytest.mark.parametrize("name", list(CASES))
-def test_shared_T_matches_oracle(name, prec):
+def test_shared_T_matches_oracle(name, prec, cut, monkeypatch):
     # max_iters = 0: the call evaluates T once at the given point of every
-    # instance and returns it (status maxiter), with xi0 of that point
+    # instance and returns it (status maxiter), with xi0 of that point. The
+    # sweeps in one launch (cut 0), or split at stage 1 (subtree workgroups
+    # below it) or at the automatic cut
+    if cut != "auto":
+        monkeypatch.setenv("SPOCK_SH_CUT", cut)
     insts = CASES[name]()
     op = O.Problem(insts[0])
     gp = SP.Problem.from_instance(insts[0], precision=FP[prec][0], alpha=op.alpha)
@@ -77,8 +82,8 @@ def test_shared_T_matches_oracle(name, prec):
         rs = O.residual_stats(op, vin_used[b] - ref)
         xi = max(np.max(np.abs(rs["xi_p"])), np.max(np.abs(rs["xi_d"])))
         worst_xi = max(worst_xi, abs(infos[b]["xi0"] - xi) / max(1.0, xi))
-    check(f"shared_T:{name}:{prec}", worst, FP[prec][1])
-    check(f"shared_xi0:{name}:{prec}", worst_xi, STAT[prec])
+    check(f"shared_T:{name}:{prec}:{cut}", worst, FP[prec][1])
+    check(f"shared_xi0:{name}:{prec}:{cut}", worst_xi, STAT[prec])
 
 
 @pytest.mark.parametrize("method", ["spock", "cp"])
