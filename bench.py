@@ -581,8 +581,8 @@ def main():
                     help="also run one plain device copy of 512 MiB (reference for the memory-traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only (--gpus 1); the multi-GPU sharding of the tree "
-              "is described in the design notes, not implemented", file=sys.stderr)
+        print("bench.py: the solver runs on one GPU only (--gpus 1); sharding the tree over several GPUs "
+              "is a design, not implemented", file=sys.stderr)
         raise SystemExit(2)
 
     import torch
