@@ -21,6 +21,8 @@ class SpockValue(torch.autograd.Function):
                 settings: Settings | None = None):
         s = settings or default_settings(eps_abs=1e-10, eps_rel=1e-10, max_iters=400000)
         qh = q.detach().to("cpu", torch.float64).numpy()
+        if problem.q is None:
+            raise ValueError("the problem has dense cost matrices: no diagonal q to differentiate")
         if qh.shape != problem.q.shape:
             raise ValueError(f"q has shape {tuple(qh.shape)}, the problem {problem.q.shape}")
         if not np.array_equal(qh[1:], problem.q[1:]):
