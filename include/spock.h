@@ -263,6 +263,28 @@ int spock_backward(spock_problem* prob, const void* v_star_dev, const double* x0
                    double* grad_qN_dev, const spock_settings* s, spock_info* info_host,
                    void* stream);
 
+/* The gradients of spock_backward (section 3, implicit differentiation at
+ * the fixed point) for B instances of one problem that differ in x0 and in
+ * their solution, at once. The transposed S1 projection of every instance
+ * runs as one set of Alg. 2 sweeps over 16-instance matrix-core tiles (the
+ * shared-tree form of spock_solve_batched), and the instances' GMRES solves
+ * advance in lockstep Arnoldi steps (each its own basis, restart and
+ * convergence test, as in spock_backward).
+ *   B >= 1; v_star_dev[b], x0_dev[b], grad_x0_dev[b] as in spock_backward
+ *   for instance b; gu0_dev: NULL (no u^0 cotangent) or B pointers, each
+ *   NULL or FP64 [nu]; grad_q_dev, grad_qN_dev: NULL or B pointers, each
+ *   NULL or FP64 [num_nodes][nx]; gV: the same cotangent of V* for all.
+ *   info_host[B]: per instance as in spock_backward (info.mapping = 1024).
+ * Allocates its workspace (about 121 vectors of n_v per instance, 30 when
+ * that would pass 2 GiB) for the call. Synchronises the stream.
+ * Errors: SPOCK_EINVAL, SPOCK_EUNSUPPORTED (general risk, polyhedral rows or
+ * dense costs), SPOCK_EHIP, SPOCK_ENOMEM; on error no gradient is written. */
+int spock_backward_batched(spock_problem* prob, int32_t B, const void* const* v_star_dev,
+                           const double* const* x0_dev, double gV, const double* const* gu0_dev,
+                           double* const* grad_x0_dev, double* const* grad_q_dev,
+                           double* const* grad_qN_dev, const spock_settings* s, spock_info* info_host,
+                           void* stream);
+
 /* ---------------------------------------------------------------------------
  * Per-operator entry points (same kernels as the solver; used for operator
  * parity). All vectors are device arrays of the problem precision.

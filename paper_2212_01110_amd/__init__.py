@@ -33,7 +33,7 @@ EXPORTED = [
     "spock_problem_destroy", "spock_problem_sizes", "spock_settings_default", "spock_solve",
     "spock_solve_batched", "spock_apply_L", "spock_apply_Lt", "spock_prox_f",
     "spock_prox_gstar", "spock_T", "spock_version", "spock_backward", "spock_profile_T",
-    "spock_problem_mapping", "spock_T_noalloc",
+    "spock_problem_mapping", "spock_T_noalloc", "spock_backward_batched",
 ]
 
 
@@ -175,6 +175,8 @@ def lib():
         L.spock_profile_T.argtypes = [vp, vp, vp, vp, i32, vp, vp]
         L.spock_backward.argtypes = [vp, vp, vp, dbl, vp, vp, vp, vp, ctypes.POINTER(Settings),
                                      ctypes.POINTER(Info), vp]
+        L.spock_backward_batched.argtypes = [vp, i32, vp, vp, dbl, vp, vp, vp, vp, ctypes.POINTER(Settings),
+                                             vp, vp]
         L.spock_version.restype = ctypes.c_char_p
         _lib = L
     return _lib
@@ -393,6 +395,27 @@ def solve_batched(problems, x0s, vs, settings: Settings | None = None):
     _check(lib().spock_solve_batched(B, ph, xp, ctypes.byref(s), vp, infos, _stream()),
            "spock_solve_batched")
     return [i.as_dict() for i in infos]
+
+
+def backward_batched(problem, v_stars, x0s, gV=1.0, gu0s=None, want_q=True, settings: Settings | None = None):
+    """spock_backward_batched: the gradients of spock_backward for the
+    instances (v_stars[b], x0s[b]) of one problem at once; returns a list of
+    (grad_x0, grad_q, grad_qN, info) per instance (FP64 device tensors)."""
+    import torch
+    s = settings or default_settings(eps_abs=1e-12, max_iters=200000)
+    B = len(v_stars)
+    dev = x0s[0].device
+    gx = [torch.zeros(problem.nx, dtype=torch.float64, device=dev) for _ in range(B)]
+    shape = (problem.tree.num_nodes, problem.nx)
+    gq = [torch.zeros(shape, dtype=torch.float64, device=dev) for _ in range(B)] if want_q else None
+    gqN = [torch.zeros(shape, dtype=torch.float64, device=dev) for _ in range(B)] if want_q else None
+    arr = lambda ts: (ctypes.c_void_p * B)(*[t.data_ptr() if t is not None else None for t in ts])
+    infos = (Info * B)()
+    _check(lib().spock_backward_batched(problem.handle, B, arr(v_stars), arr(x0s), float(gV),
+                                        arr(gu0s) if gu0s is not None else None, arr(gx),
+                                        arr(gq) if want_q else None, arr(gqN) if want_q else None,
+                                        ctypes.byref(s), infos, _stream()), "spock_backward_batched")
+    return [(gx[b], gq[b] if want_q else None, gqN[b] if want_q else None, infos[b].as_dict()) for b in range(B)]
 
 
 def version() -> str:

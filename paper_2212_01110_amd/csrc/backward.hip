@@ -77,7 +77,10 @@ __device__ void soc_jg_wave(const S* __restrict__ b_, const S* __restrict__ din,
 // of i, group 2 of each child, group 3 of leaf children), grid-stride.
 template <typename S>
 __global__ void __launch_bounds__(256) k_jg(DevProb<S> P, const S* __restrict__ b, const S* __restrict__ w,
-                                            S* __restrict__ out) {
+                                            S* __restrict__ out, long long is) {
+  b += (size_t)blockIdx.y * is;  // instance blockIdx.y of a batch (stride is)
+  w += (size_t)blockIdx.y * is;
+  out += (size_t)blockIdx.y * is;
   const int lane = threadIdx.x & 63;
   const Off<S> O(P);
   const int nx = P.nx, nu = P.nu;
@@ -215,7 +218,14 @@ template <typename S>
 hipError_t launch_jg(const Problem& P, const S* b, const S* w, S* out, hipStream_t st) {
   const DevProb<S>& D = (sizeof(S) == 8) ? *reinterpret_cast<const DevProb<S>*>(&P.dp64)
                                          : *reinterpret_cast<const DevProb<S>*>(&P.dp32);
-  hipLaunchKernelGGL(k_jg<S>, dim3(family_wave_blocks(P.tree->nl)), dim3(256), 0, st, D, b, w, out);
+  hipLaunchKernelGGL(k_jg<S>, dim3(family_wave_blocks(P.tree->nl)), dim3(256), 0, st, D, b, w, out, 0LL);
+  return hipGetLastError();
+}
+template <typename S>
+hipError_t launch_jg_batch(const Problem& P, const S* b, const S* w, S* out, long long is, int B, hipStream_t st) {
+  const DevProb<S>& D = (sizeof(S) == 8) ? *reinterpret_cast<const DevProb<S>*>(&P.dp64)
+                                         : *reinterpret_cast<const DevProb<S>*>(&P.dp32);
+  hipLaunchKernelGGL(k_jg<S>, dim3(family_wave_blocks(P.tree->nl), B), dim3(256), 0, st, D, b, w, out, is);
   return hipGetLastError();
 }
 template <typename S>
@@ -248,6 +258,7 @@ hipError_t launch_maxdiff(long long n, const S* a, const S* b, double* partials,
 #define SPK_BINST(S)                                                                                  \
   template hipError_t launch_copy_elem<S>(S*, const S*, hipStream_t);                                 \
   template hipError_t launch_jg<S>(const Problem&, const S*, const S*, S*, hipStream_t);              \
+  template hipError_t launch_jg_batch<S>(const Problem&, const S*, const S*, S*, long long, int, hipStream_t); \
   template hipError_t launch_phiT<S>(const Problem&, const S*, S*, hipStream_t);                      \
   template hipError_t launch_grad_q<S>(const Problem&, const S*, const S*, const S*, double*, double*, \
                                        hipStream_t);                                                  \

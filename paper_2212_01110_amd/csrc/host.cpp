@@ -2329,6 +2329,30 @@ int backward_impl(Problem& P, const S* vstar, const double* x0, double gV, const
 
 }  // namespace
 
+extern "C" int spock_backward_batched(spock_problem* ph, int32_t B, const void* const* v_star,
+                                      const double* const* x0, double gV, const double* const* gu0,
+                                      double* const* grad_x0, double* const* grad_q, double* const* grad_qN,
+                                      const spock_settings* s, spock_info* infos, void* stream) {
+  if (!ph || B < 1 || !v_star || !x0 || !grad_x0 || !s || !infos || s->max_iters < 1) return SPOCK_EINVAL;
+  for (int b = 0; b < B; ++b)
+    if (!v_star[b] || !x0[b] || !grad_x0[b]) return SPOCK_EINVAL;
+  Problem& P = ph->p;
+  if (P.general) return SPOCK_EUNSUPPORTED;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const auto t0 = std::chrono::steady_clock::now();
+  std::vector<spock_info> loc(B);
+  const int rc = (P.precision == SPOCK_FP64)
+                     ? shared_backward<double>(P, B, v_star, x0, gV, gu0, grad_x0, grad_q, grad_qN, *s, loc.data(), st)
+                     : shared_backward<float>(P, B, v_star, x0, gV, gu0, grad_x0, grad_q, grad_qN, *s, loc.data(), st);
+  if (rc) return rc;
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  for (int b = 0; b < B; ++b) {
+    loc[b].seconds = secs;
+    infos[b] = loc[b];
+  }
+  return SPOCK_OK;
+}
+
 extern "C" int spock_backward(spock_problem* ph, const void* v_star, const double* x0, double gV,
                               const double* gu0, double* grad_x0, double* grad_q, double* grad_qN,
                               const spock_settings* s, spock_info* info, void* stream) {

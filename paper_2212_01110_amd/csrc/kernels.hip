@@ -965,7 +965,10 @@ template hipError_t launch_T<float>(const Problem&, const float*, float*, const 
 // s^c of leaf children), lanes over components. Every entry is written by
 // exactly one family; sums over children run in child order.
 template <typename S>
-__global__ void __launch_bounds__(256) k_apply_L(DevProb<S> P, const S* __restrict__ z, S* __restrict__ eta) {
+__global__ void __launch_bounds__(256) k_apply_L(DevProb<S> P, const S* __restrict__ z, S* __restrict__ eta,
+                                                 long long is) {
+  z += (size_t)blockIdx.y * is;  // instance blockIdx.y of a batch (stride is)
+  eta += (size_t)blockIdx.y * is;
   const int lane = threadIdx.x & 63;
   const Off<S> O(P);
   const int nx = P.nx, nu = P.nu, K = nx + nu;
@@ -1009,7 +1012,10 @@ __global__ void __launch_bounds__(256) k_apply_L(DevProb<S> P, const S* __restri
 }
 
 template <typename S>
-__global__ void __launch_bounds__(256) k_apply_Lt(DevProb<S> P, const S* __restrict__ eta, S* __restrict__ z) {
+__global__ void __launch_bounds__(256) k_apply_Lt(DevProb<S> P, const S* __restrict__ eta, S* __restrict__ z,
+                                                  long long is) {
+  eta += (size_t)blockIdx.y * is;  // instance blockIdx.y of a batch (stride is)
+  z += (size_t)blockIdx.y * is;
   const int lane = threadIdx.x & 63;
   const Off<S> O(P);
   const int nx = P.nx, nu = P.nu, K = nx + nu;
@@ -1132,13 +1138,29 @@ __global__ void k_prox_gstar(DevProb<S> P, const S* __restrict__ w, S* __restric
 template <typename S>
 hipError_t launch_L(const Problem& P, const S* z, S* eta, hipStream_t st) {
   if (P.general) return launch_gen_L<S>(P, z, eta, st);
-  hipLaunchKernelGGL(k_apply_L<S>, dim3(family_wave_blocks(P.tree->nl)), dim3(256), 0, st, dev_of<S>(P), z, eta);
+  hipLaunchKernelGGL(k_apply_L<S>, dim3(family_wave_blocks(P.tree->nl)), dim3(256), 0, st, dev_of<S>(P), z, eta,
+                     0LL);
+  return hipGetLastError();
+}
+template <typename S>
+hipError_t launch_L_batch(const Problem& P, const S* z, S* eta, long long is, int B, hipStream_t st) {
+  if (P.general) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_apply_L<S>, dim3(family_wave_blocks(P.tree->nl), B), dim3(256), 0, st, dev_of<S>(P), z, eta,
+                     is);
+  return hipGetLastError();
+}
+template <typename S>
+hipError_t launch_Lt_batch(const Problem& P, const S* eta, S* z, long long is, int B, hipStream_t st) {
+  if (P.general) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_apply_Lt<S>, dim3(family_wave_blocks(P.tree->nl), B), dim3(256), 0, st, dev_of<S>(P), eta, z,
+                     is);
   return hipGetLastError();
 }
 template <typename S>
 hipError_t launch_Lt(const Problem& P, const S* eta, S* z, hipStream_t st) {
   if (P.general) return launch_gen_Lt<S>(P, eta, z, st);
-  hipLaunchKernelGGL(k_apply_Lt<S>, dim3(family_wave_blocks(P.tree->nl)), dim3(256), 0, st, dev_of<S>(P), eta, z);
+  hipLaunchKernelGGL(k_apply_Lt<S>, dim3(family_wave_blocks(P.tree->nl)), dim3(256), 0, st, dev_of<S>(P), eta, z,
+                     0LL);
   return hipGetLastError();
 }
 template <typename S>
@@ -1148,6 +1170,10 @@ hipError_t launch_prox_gstar(const Problem& P, const S* w, S* out, hipStream_t s
   hipLaunchKernelGGL(k_prox_gstar<S>, dim3((nl + 127) / 128), dim3(128), 0, st, dev_of<S>(P), w, out);
   return hipGetLastError();
 }
+template hipError_t launch_L_batch<double>(const Problem&, const double*, double*, long long, int, hipStream_t);
+template hipError_t launch_L_batch<float>(const Problem&, const float*, float*, long long, int, hipStream_t);
+template hipError_t launch_Lt_batch<double>(const Problem&, const double*, double*, long long, int, hipStream_t);
+template hipError_t launch_Lt_batch<float>(const Problem&, const float*, float*, long long, int, hipStream_t);
 template hipError_t launch_L<double>(const Problem&, const double*, double*, hipStream_t);
 template hipError_t launch_L<float>(const Problem&, const float*, float*, hipStream_t);
 template hipError_t launch_Lt<double>(const Problem&, const double*, double*, hipStream_t);

@@ -24,6 +24,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <vector>
 
 namespace spk {
@@ -1076,6 +1077,453 @@ int shared_solve(Problem& P, int B, const double* const* x0, const spock_setting
   SH_TRY(hipStreamSynchronize(st));
   return SPOCK_OK;
 }
+
+// ================================================================ batched adjoint
+// The adjoint fixed point of section 3 (see spock_backward) for B instances
+// of one problem at once: every vector holds the instances `vs` elements
+// apart, the S1 part of J_T' runs the shared-tree sweeps above (zero root
+// state, zero dual), J_G, L and L* run with an instance grid dimension, and
+// every instance runs its own restarted GMRES; the Arnoldi steps advance in
+// lockstep, an instance leaving its cycle (small residual or breakdown) keeps
+// computing but its columns are not used.
+namespace {
+
+// out[o_i] = a x[x_i] + c y[y_i] + e w[w_i] on entries [0, len) of every
+// instance b (operand p at p.ptr + b * p.is + p.off); y, w may be null.
+template <typename S>
+struct BOp {
+  S* p;
+  long long is, off;
+};
+template <typename S>
+__global__ void __launch_bounds__(256) k_blin3(long long len, BOp<S> out, double a, BOp<S> x, double c, BOp<S> y,
+                                               double e, BOp<S> w) {
+  const size_t b = blockIdx.y;
+  S* o = out.p + b * out.is + out.off;
+  const S* xp = x.p + b * x.is + x.off;
+  const S* yp = y.p ? y.p + b * y.is + y.off : nullptr;
+  const S* wp = w.p ? w.p + b * w.is + w.off : nullptr;
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < len; k += (long long)gridDim.x * blockDim.x) {
+    double acc = a * (double)xp[k];
+    if (yp) acc += c * (double)yp[k];
+    if (wp) acc += e * (double)wp[k];
+    o[k] = (S)acc;
+  }
+}
+
+// Per instance b: out[2 b] = max_k |x_k - y_k|, out[2 b + 1] = max_k |x_k|
+// over its first n entries (one block of 1024 threads per instance).
+template <typename S>
+__global__ void __launch_bounds__(1024) k_bmaxdiff(long long n, const S* __restrict__ x, const S* __restrict__ y,
+                                                   long long is, double* __restrict__ out) {
+  const size_t b = blockIdx.x;
+  const S* xb = x + b * is;
+  const S* yb = y + b * is;
+  double m0 = 0, m1 = 0;
+  for (long long k = threadIdx.x; k < n; k += blockDim.x) {
+    m0 = fmax(m0, fabs((double)xb[k] - (double)yb[k]));
+    m1 = fmax(m1, fabs((double)xb[k]));
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    m0 = fmax(m0, __shfl_xor(m0, m, 64));
+    m1 = fmax(m1, __shfl_xor(m1, m, 64));
+  }
+  __shared__ double r0[16], r1[16];
+  if ((threadIdx.x & 63) == 0) {
+    r0[threadIdx.x >> 6] = m0;
+    r1[threadIdx.x >> 6] = m1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a0 = 0, a1 = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      a0 = fmax(a0, r0[w]);
+      a1 = fmax(a1, r1[w]);
+    }
+    out[2 * b] = a0;
+    out[2 * b + 1] = a1;
+  }
+}
+
+// Krylov basis of instance b at basis + b * bs (vector j at + j * vs), its
+// vector x at x + b * xs. k_bdots: block (c, j, b) sums chunk c of <V_j, x>
+// (j < n; <x, x> for j = n) into part[(b * m + j) * cb + c], m = gridDim.y;
+// k_bdots_final (block b) adds the chunks in order into out[b * ldo + j].
+template <typename S>
+__global__ void __launch_bounds__(256) k_bdots(long long nv, int n, const S* __restrict__ basis, long long bs,
+                                               long long vs, const S* __restrict__ x, long long xs,
+                                               double* __restrict__ part) {
+  const int j = blockIdx.y, m = gridDim.y;
+  const size_t b = blockIdx.z;
+  const S* xb = x + b * xs;
+  const S* v = j < n ? basis + b * bs + (size_t)j * vs : xb;
+  const long long chunk = (nv + gridDim.x - 1) / gridDim.x;
+  const long long e0 = (long long)blockIdx.x * chunk;
+  const long long e1 = e0 + chunk < nv ? e0 + chunk : nv;
+  double acc = 0;
+  for (long long e = e0 + threadIdx.x; e < e1; e += 256) acc += (double)v[e] * (double)xb[e];
+#pragma unroll
+  for (int k = 32; k >= 1; k >>= 1) acc += __shfl_xor(acc, k, 64);
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    part[((size_t)b * m + j) * gridDim.x + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+__global__ void __launch_bounds__(256) k_bdots_final(const double* __restrict__ part, int cb, int m,
+                                                     double* __restrict__ out, int ldo) {
+  const size_t b = blockIdx.x;
+  for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    double acc = 0;
+    for (int c = 0; c < cb; ++c) acc += part[((size_t)b * m + j) * cb + c];
+    out[b * ldo + j] = acc;
+  }
+}
+// x_b += sgn sum_{j < n} c_b[j] V_j (c_b = c + b * ldc, device); with norm,
+// then scaled by 1 / sqrt(c_b[n] - sum_j c_b[j]^2) (0 if not positive)
+template <typename S>
+__global__ void __launch_bounds__(256) k_bcomb(long long nv, int n, const S* __restrict__ basis, long long bs,
+                                               long long vs, const double* __restrict__ c, int ldc, double sgn,
+                                               int norm, S* x, long long xs) {
+  const size_t b = blockIdx.y;
+  const double* cb = c + b * ldc;
+  const S* Vb = basis + b * bs;
+  S* xb = x + b * xs;
+  double scale = 1.0;
+  if (norm) {
+    double h2 = cb[n];
+    for (int j = 0; j < n; ++j) h2 -= cb[j] * cb[j];
+    scale = h2 > 0.0 ? 1.0 / sqrt(h2) : 0.0;
+  }
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nv; e += (long long)gridDim.x * blockDim.x) {
+    double acc = (double)xb[e];
+    for (int j = 0; j < n; ++j) acc += sgn * cb[j] * (double)Vb[(size_t)j * vs + e];
+    xb[e] = (S)(acc * scale);
+  }
+}
+
+}  // namespace
+
+template <typename S>
+int shared_backward(Problem& P, int B, const void* const* vstar, const double* const* x0, double gV,
+                    const double* const* gu0, double* const* gx0, double* const* gq, double* const* gqN,
+                    const spock_settings& s, spock_info* infos, hipStream_t st) {
+  const Tree& Tr = *P.tree;
+  const DevProb<S>& D = sh_dev<S>(P);
+  const int nx = P.nx, nu = P.nu, T = P.team_pp;
+  const long long nz = P.nz, ne = P.neta, nv = nz + ne;
+  const long long vs = (nv + 63) & ~63LL;
+  const int Bp = (B + kShCols - 1) / kShCols * kShCols;
+  const double al = P.alpha;
+  constexpr int kMax = 120;  // Krylov vectors per cycle at most
+  int R = sizeof(S) * (size_t)(kMax + 1) * (size_t)vs * (size_t)Bp <= (size_t(2) << 30) ? kMax : 30;
+  if (const char* env = std::getenv("SPOCK_ADJ_RESTART")) R = std::max(2, std::min(kMax, std::atoi(env)));
+  const long long bs = (long long)(R + 1) * vs;  // basis stride between instances
+  const int cb = std::max(1, std::min(64, (int)((nv + 8191) / 8192)));
+  const int ldc = kMax + 2;
+  // ---- device memory: 14 batch vectors, the bases, sweep buffers, x0s,
+  // coefficients and partial sums
+  enum { kV, kTv, kDz, kLdz, kB, kG, kW, kAw, kLb, kCz, kLa, kTz, kTe, kIn, kNVec };
+  const size_t nvec = (size_t)Bp * vs;
+  size_t off = 0;
+  auto reserve = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~size_t(255);
+    return o;
+  };
+  const size_t o_vec = reserve(sizeof(S) * nvec * kNVec);
+  const size_t o_bas = reserve(sizeof(S) * (size_t)Bp * bs);
+  const size_t o_qx = reserve(sizeof(S) * (size_t)Bp * Tr.nn * nx * 2);
+  const size_t o_du = reserve(sizeof(S) * (size_t)Bp * Tr.nn * nu * 2);
+  const size_t o_x0 = reserve(sizeof(double) * (size_t)Bp * nx * 2);
+  const size_t o_c = reserve(sizeof(double) * (size_t)Bp * ldc * 3);
+  const size_t o_part = reserve(sizeof(double) * (size_t)Bp * (kMax + 2) * cb);
+  const size_t o_md = reserve(sizeof(double) * (size_t)Bp * 2);
+  const size_t o_mu = reserve(sizeof(S) * (size_t)Tr.nn * nx);
+  void* mem = nullptr;
+  if (hipMalloc(&mem, off) != hipSuccess) return SPOCK_ENOMEM;
+  struct Guard {
+    void* m;
+    ~Guard() { (void)hipFree(m); }
+  } guard{mem};
+  char* base = static_cast<char*>(mem);
+  SH_TRY(hipMemsetAsync(base, 0, off, st));  // padding instances stay at zero
+  S* vec[kNVec];
+  for (int r = 0; r < kNVec; ++r) vec[r] = reinterpret_cast<S*>(base + o_vec) + (size_t)r * nvec;
+  S* basis = reinterpret_cast<S*>(base + o_bas);
+  S* q = reinterpret_cast<S*>(base + o_qx);
+  S* xbar = q + (size_t)Bp * Tr.nn * nx;
+  S* d = reinterpret_cast<S*>(base + o_du);
+  S* ubar = d + (size_t)Bp * Tr.nn * nu;
+  double* x0s = reinterpret_cast<double*>(base + o_x0);
+  double* x0zero = x0s + (size_t)Bp * nx;
+  double* cdev = reinterpret_cast<double*>(base + o_c);  // [Bp][ldc] x 3: pass 1, pass 2, mix
+  double* c1 = cdev;
+  double* c2 = cdev + (size_t)Bp * ldc;
+  double* cm = cdev + 2 * (size_t)Bp * ldc;
+  double* part = reinterpret_cast<double*>(base + o_part);
+  double* md = reinterpret_cast<double*>(base + o_md);
+  S* mu = reinterpret_cast<S*>(base + o_mu);
+  const int vb = (int)std::min<long long>((nv + 255) / 256, 64);
+  auto op = [&](int r, long long o = 0) { return BOp<S>{vec[r], vs, o}; };
+  const BOp<S> none{nullptr, 0, 0};
+  auto lin3 = [&](long long len, BOp<S> o, double a, BOp<S> x, double c = 0, BOp<S> y = BOp<S>{nullptr, 0, 0},
+                  double e = 0, BOp<S> w = BOp<S>{nullptr, 0, 0}) -> int {
+    hipLaunchKernelGGL(k_blin3<S>, dim3(vb, Bp), dim3(256), 0, st, len, o, a, x, c, y, e, w);
+    SH_TRY(hipGetLastError());
+    return SPOCK_OK;
+  };
+  (void)none;
+  // ---- inputs: v* and x0 of every instance, the cotangents
+  for (int b = 0; b < B; ++b) {
+    SH_TRY(hipMemcpyAsync(vec[kV] + (size_t)b * vs, vstar[b], sizeof(S) * nv, hipMemcpyDeviceToDevice, st));
+    SH_TRY(hipMemcpyAsync(x0s + (size_t)b * nx, x0[b], sizeof(double) * nx, hipMemcpyDeviceToDevice, st));
+  }
+  {
+    const size_t head = 1 + (size_t)Tr.nn * nx + nu;
+    std::vector<S> hg((size_t)B * head, S(0));
+    std::vector<double> hu(nu);
+    for (int b = 0; b < B; ++b) {
+      hg[(size_t)b * head] = (S)gV;
+      if (gu0 && gu0[b]) {
+        SH_TRY(hipMemcpy(hu.data(), gu0[b], sizeof(double) * nu, hipMemcpyDeviceToHost));
+        for (int k = 0; k < nu; ++k) hg[(size_t)b * head + 1 + (size_t)Tr.nn * nx + k] = (S)hu[k];
+      }
+    }
+    for (int b = 0; b < B; ++b)
+      SH_TRY(hipMemcpyAsync(vec[kG] + (size_t)b * vs, hg.data() + (size_t)b * head, sizeof(S) * head,
+                            hipMemcpyHostToDevice, st));
+    SH_TRY(hipStreamSynchronize(st));  // hg is a local buffer
+  }
+  // T of the instances without (with) the dual part: pre-pass, then the
+  // sweeps in the phases of the shared-tree form
+  int maxch = 1;
+  for (int i = 0; i < Tr.nl; ++i) maxch = std::max(maxch, Tr.nch[i]);
+  int sh_cut = 0;
+  for (int t = 1; t < Tr.N; ++t)
+    if (Tr.stage_off[t + 1] - Tr.stage_off[t] >= 8) {
+      sh_cut = t;
+      break;
+    }
+  if (const char* env = std::getenv("SPOCK_SH_CUT")) sh_cut = std::atoi(env);
+  if (sh_cut < 1 || sh_cut >= Tr.N || Tr.N - sh_cut > kShMaxLevels) sh_cut = 0;
+  const int sweep_grid = Bp / kShCols;
+  auto prox = [&](S* in, S* out, const double* xs0) -> int {
+    const int tpb = 256 / T;
+    const dim3 grid((Tr.nl + tpb - 1) / tpb, Bp);
+    switch (T) {
+      case 8: hipLaunchKernelGGL((k_sh_pre<S, 8>), grid, dim3(256), 0, st, D, in, out, xbar, ubar, q, vs); break;
+      case 16: hipLaunchKernelGGL((k_sh_pre<S, 16>), grid, dim3(256), 0, st, D, in, out, xbar, ubar, q, vs); break;
+      case 32: hipLaunchKernelGGL((k_sh_pre<S, 32>), grid, dim3(256), 0, st, D, in, out, xbar, ubar, q, vs); break;
+      default: hipLaunchKernelGGL((k_sh_pre<S, 64>), grid, dim3(256), 0, st, D, in, out, xbar, ubar, q, vs); break;
+    }
+    if (sh_cut > 0) {
+      const int nsub = Tr.stage_off[sh_cut + 1] - Tr.stage_off[sh_cut];
+      for (int ph : {kShBwdSub, kShBwdTop, kShFwdTop, kShFwdSub}) {
+        const ShSweepArgs A{maxch, ph, sh_cut, nsub};
+        const bool subph = ph == kShBwdSub || ph == kShFwdSub;
+        hipLaunchKernelGGL(k_sh_sweeps<S>, dim3(subph ? sweep_grid * nsub : sweep_grid), dim3(64 * kShWaves), 0, st,
+                           D, P.d_stage_off, out, xs0, xbar, ubar, q, d, vs, A);
+      }
+    } else {
+      const ShSweepArgs A{maxch, kShWhole, 0, 1};
+      hipLaunchKernelGGL(k_sh_sweeps<S>, dim3(sweep_grid), dim3(64 * kShWaves), 0, st, D, P.d_stage_off, out, xs0,
+                         xbar, ubar, q, d, vs, A);
+    }
+    SH_TRY(hipGetLastError());
+    return SPOCK_OK;
+  };
+  // pre-prox point of the dual update at v*: b* = eta* + alpha L (2 z+ - z*)
+  if (int r = prox(vec[kV], vec[kTv], x0s)) return r;
+  if (int r = lin3(nz, op(kDz), 2.0, op(kTv), -1.0, op(kV))) return r;
+  SH_TRY(launch_L_batch<S>(P, vec[kDz], vec[kLdz], vs, Bp, st));
+  if (int r = lin3(ne, op(kB), 1.0, op(kV, nz), al, op(kLdz))) return r;
+  // one application of the transposed operator to vec[kIn]: lb, tz, cz, la
+  auto partial = [&](int in) -> int {
+    SH_TRY(launch_jg_batch<S>(P, vec[kB], vec[in] + nz, vec[kLb], vs, Bp, st));  // lambda_b = J_G w_eta
+    SH_TRY(launch_Lt_batch<S>(P, vec[kLb], vec[kTz], vs, Bp, st));              // L* lambda_b
+    if (int r = lin3(nz, op(kCz), 1.0, op(in), 2.0 * al, op(kTz))) return r;    // w_z + 2 alpha L* lambda_b
+    if (int r = prox(vec[kCz], vec[kLa], x0zero)) return r;                      // J_f c (zero dual part)
+    if (int r = lin3(1, op(kLa), 1.0, op(kCz))) return r;                        // identity on s^0
+    return SPOCK_OK;
+  };
+  // A(w) = J_T(v*)' w + g into vec[kAw]
+  auto apply_A = [&](int in) -> int {
+    if (int r = partial(in)) return r;
+    SH_TRY(launch_L_batch<S>(P, vec[kLa], vec[kTe], vs, Bp, st));
+    if (int r = lin3(nz, op(kAw), 1.0, op(kLa), -al, op(kTz), 1.0, op(kG))) return r;
+    if (int r = lin3(ne, op(kAw, nz), 1.0, op(kLb), -al, op(kTe), 1.0, op(kG, nz))) return r;
+    return SPOCK_OK;
+  };
+  auto bdots = [&](int n, const S* x, long long xs, bool xx, double* out) -> int {
+    const int m = n + (xx ? 1 : 0);
+    hipLaunchKernelGGL(k_bdots<S>, dim3(cb, m, Bp), dim3(256), 0, st, nv, n, basis, bs, vs, x, xs, part);
+    hipLaunchKernelGGL(k_bdots_final, dim3(Bp), dim3(256), 0, st, part, cb, m, out, ldc);
+    SH_TRY(hipGetLastError());
+    return SPOCK_OK;
+  };
+  auto bcomb = [&](int n, const double* c, double sgn, bool norm, S* x, long long xs) -> int {
+    hipLaunchKernelGGL(k_bcomb<S>, dim3(vb, Bp), dim3(256), 0, st, nv, n, basis, bs, vs, c, ldc, sgn, norm ? 1 : 0, x,
+                       xs);
+    SH_TRY(hipGetLastError());
+    return SPOCK_OK;
+  };
+  auto V = [&](int j) { return basis + (size_t)j * vs; };  // vector j of instance 0 (instances bs apart)
+  // ---- restarted GMRES per instance, Arnoldi steps in lockstep
+  SH_TRY(hipMemcpyAsync(vec[kW], vec[kG], sizeof(S) * nvec, hipMemcpyDeviceToDevice, st));
+  const double tol = std::max(s.eps_abs, 1e-15);
+  std::vector<int> kk(B, 0), state(B, 0);  // state: 0 running, 1 converged, 2 numerical, 3 max_iters
+  std::vector<double> diff(B, 0.0);
+  std::vector<double> hmd((size_t)Bp * 2), hc1((size_t)Bp * ldc), hc2((size_t)Bp * ldc), hcm((size_t)Bp * ldc);
+  std::vector<double> Hm((size_t)B * (kMax + 1) * kMax), cs((size_t)B * kMax), sn((size_t)B * kMax),
+      gvv((size_t)B * (kMax + 1));
+  std::vector<int> jn(B), incyc(B);
+  auto running = [&]() {
+    for (int b = 0; b < B; ++b)
+      if (state[b] == 0) return true;
+    return false;
+  };
+  while (running()) {
+    // true residual of every instance at w
+    SH_TRY(hipMemcpyAsync(vec[kIn], vec[kW], sizeof(S) * nvec, hipMemcpyDeviceToDevice, st));
+    if (int r = apply_A(kIn)) return r;
+    hipLaunchKernelGGL(k_bmaxdiff<S>, dim3(Bp), dim3(1024), 0, st, nv, vec[kW], vec[kAw], vs, md);
+    SH_TRY(hipGetLastError());
+    SH_TRY(hipMemcpyAsync(hmd.data(), md, sizeof(double) * 2 * Bp, hipMemcpyDeviceToHost, st));
+    SH_TRY(hipStreamSynchronize(st));
+    for (int b = 0; b < B; ++b) {
+      if (state[b] != 0) continue;
+      ++kk[b];
+      diff[b] = hmd[2 * b];
+      if (!std::isfinite(diff[b])) state[b] = 2;
+      else if (diff[b] <= tol * std::max(1.0, hmd[2 * b + 1])) state[b] = 1;
+      else if (kk[b] >= s.max_iters) state[b] = 3;
+    }
+    if (!running()) break;
+    // V_0 = (A(w) - w) / |.| for every instance
+    if (int r = lin3(nv, BOp<S>{basis, bs, 0}, 1.0, op(kAw), -1.0, op(kW))) return r;
+    if (int r = bdots(0, V(0), bs, true, c1)) return r;
+    SH_TRY(hipMemcpyAsync(hc1.data(), c1, sizeof(double) * Bp * ldc, hipMemcpyDeviceToHost, st));
+    SH_TRY(hipStreamSynchronize(st));
+    if (int r = bcomb(0, c1, 1.0, true, V(0), bs)) return r;
+    std::fill(Hm.begin(), Hm.end(), 0.0);
+    for (int b = 0; b < B; ++b) {
+      const double beta = std::sqrt(std::max(hc1[(size_t)b * ldc], 0.0));
+      gvv[(size_t)b * (kMax + 1)] = beta;
+      jn[b] = 0;
+      incyc[b] = state[b] == 0 && beta > 0.0 && std::isfinite(beta);
+      if (state[b] == 0 && !(beta > 0.0)) state[b] = std::isfinite(beta) ? 1 : 2;
+    }
+    auto any_in = [&]() {
+      for (int b = 0; b < B; ++b)
+        if (incyc[b]) return true;
+      return false;
+    };
+    for (int j = 0; j < R && any_in(); ++j) {
+      SH_TRY(hipMemcpy2DAsync(vec[kIn], sizeof(S) * vs, V(j), sizeof(S) * bs, sizeof(S) * nv, Bp,
+                              hipMemcpyDeviceToDevice, st));
+      if (int r = apply_A(kIn)) return r;
+      // V_{j+1} = V_j - A(V_j) + g, two Gram-Schmidt passes, normalisation
+      if (int r = lin3(nv, BOp<S>{V(j + 1), bs, 0}, 1.0, op(kIn), -1.0, op(kAw), 1.0, op(kG))) return r;
+      if (int r = bdots(j + 1, V(j + 1), bs, false, c1)) return r;
+      if (int r = bcomb(j + 1, c1, -1.0, false, V(j + 1), bs)) return r;
+      if (int r = bdots(j + 1, V(j + 1), bs, true, c2)) return r;
+      if (int r = bcomb(j + 1, c2, -1.0, true, V(j + 1), bs)) return r;
+      SH_TRY(hipMemcpyAsync(hc1.data(), c1, sizeof(double) * Bp * ldc, hipMemcpyDeviceToHost, st));
+      SH_TRY(hipMemcpyAsync(hc2.data(), c2, sizeof(double) * Bp * ldc, hipMemcpyDeviceToHost, st));
+      SH_TRY(hipStreamSynchronize(st));
+      for (int b = 0; b < B; ++b) {
+        if (!incyc[b]) continue;
+        ++kk[b];
+        double* Hb = Hm.data() + (size_t)b * (kMax + 1) * kMax;
+        auto H = [&](int i, int jj) -> double& { return Hb[(size_t)i * kMax + jj]; };
+        double* csb = cs.data() + (size_t)b * kMax;
+        double* snb = sn.data() + (size_t)b * kMax;
+        double* gv = gvv.data() + (size_t)b * (kMax + 1);
+        const double* h1 = hc1.data() + (size_t)b * ldc;
+        const double* h2 = hc2.data() + (size_t)b * ldc;
+        double hn = h2[j + 1];
+        for (int i = 0; i <= j; ++i) {
+          H(i, j) = h1[i] + h2[i];
+          hn -= h2[i] * h2[i];
+        }
+        hn = std::sqrt(std::max(hn, 0.0));
+        H(j + 1, j) = hn;
+        for (int i = 0; i < j; ++i) {
+          const double xv = H(i, j), yv = H(i + 1, j);
+          H(i, j) = csb[i] * xv + snb[i] * yv;
+          H(i + 1, j) = -snb[i] * xv + csb[i] * yv;
+        }
+        const double rr = std::hypot(H(j, j), H(j + 1, j));
+        csb[j] = rr > 0.0 ? H(j, j) / rr : 1.0;
+        snb[j] = rr > 0.0 ? H(j + 1, j) / rr : 0.0;
+        H(j, j) = rr;
+        H(j + 1, j) = 0.0;
+        gv[j + 1] = -snb[j] * gv[j];
+        gv[j] = csb[j] * gv[j];
+        jn[b] = j + 1;
+        const double thr = tol * std::max(1.0, hmd[2 * b + 1]);
+        if (!std::isfinite(gv[j + 1]) || std::fabs(gv[j + 1]) <= 0.5 * thr || !(hn > 0.0) || kk[b] >= s.max_iters)
+          incyc[b] = 0;
+      }
+    }
+    // w += V y per instance (H y = g, upper triangular; zero for the others)
+    std::fill(hcm.begin(), hcm.end(), 0.0);
+    int nmax = 0;
+    for (int b = 0; b < B; ++b) {
+      if (state[b] != 0 || jn[b] == 0) continue;
+      const double* Hb = Hm.data() + (size_t)b * (kMax + 1) * kMax;
+      const double* gv = gvv.data() + (size_t)b * (kMax + 1);
+      double* y = hcm.data() + (size_t)b * ldc;
+      for (int i = jn[b] - 1; i >= 0; --i) {
+        double t = gv[i];
+        for (int l = i + 1; l < jn[b]; ++l) t -= Hb[(size_t)i * kMax + l] * y[l];
+        y[i] = Hb[(size_t)i * kMax + i] != 0.0 ? t / Hb[(size_t)i * kMax + i] : 0.0;
+      }
+      nmax = std::max(nmax, jn[b]);
+    }
+    SH_TRY(hipMemcpyAsync(cm, hcm.data(), sizeof(double) * Bp * ldc, hipMemcpyHostToDevice, st));
+    if (int r = bcomb(nmax, cm, 1.0, false, vec[kW], vs)) return r;
+    SH_TRY(hipStreamSynchronize(st));  // hcm is reused
+  }
+  // gradients from the converged adjoints
+  SH_TRY(hipMemcpyAsync(vec[kIn], vec[kW], sizeof(S) * nvec, hipMemcpyDeviceToDevice, st));
+  if (int r = partial(kIn)) return r;
+  for (int b = 0; b < B; ++b) {
+    SH_TRY(launch_phiT<S>(P, vec[kCz] + (size_t)b * vs, mu, st));
+    std::vector<S> hm(nx);
+    SH_TRY(hipMemcpyAsync(hm.data(), mu, nx * sizeof(S), hipMemcpyDeviceToHost, st));
+    SH_TRY(hipStreamSynchronize(st));
+    std::vector<double> outv(nx);
+    for (int k = 0; k < nx; ++k) outv[k] = hm[k];
+    SH_TRY(hipMemcpy(gx0[b], outv.data(), nx * sizeof(double), hipMemcpyHostToDevice));
+    double* gqb = gq ? gq[b] : nullptr;
+    double* gqNb = gqN ? gqN[b] : nullptr;
+    if (gqb) SH_TRY(hipMemsetAsync(gqb, 0, sizeof(double) * (size_t)Tr.nn * nx, st));
+    if (gqNb) SH_TRY(hipMemsetAsync(gqNb, 0, sizeof(double) * (size_t)Tr.nn * nx, st));
+    if (gqb || gqNb)
+      SH_TRY(launch_grad_q<S>(P, vec[kV] + (size_t)b * vs, vec[kLa] + (size_t)b * vs, vec[kLb] + (size_t)b * vs, gqb,
+                              gqNb, st));
+    spock_info loc{};
+    loc.V_nested = std::numeric_limits<double>::quiet_NaN();
+    loc.status = state[b] == 1 ? SPOCK_CONVERGED : (state[b] == 2 ? SPOCK_NUMERICAL : SPOCK_MAXITER);
+    loc.iters = kk[b];
+    loc.t_evals = kk[b];
+    loc.xi = diff[b];
+    loc.mapping = kTeamShared;
+    infos[b] = loc;
+  }
+  SH_TRY(hipStreamSynchronize(st));
+  return SPOCK_OK;
+}
+
+template int shared_backward<double>(Problem&, int, const void* const*, const double* const*, double,
+                                     const double* const*, double* const*, double* const*, double* const*,
+                                     const spock_settings&, spock_info*, hipStream_t);
+template int shared_backward<float>(Problem&, int, const void* const*, const double* const*, double,
+                                    const double* const*, double* const*, double* const*, double* const*,
+                                    const spock_settings&, spock_info*, hipStream_t);
 
 template int shared_solve<double>(Problem&, int, const double* const*, const spock_settings&, void* const*,
                                   spock_info*, hipStream_t);

@@ -254,6 +254,11 @@ template <typename S>
 hipError_t launch_L(const Problem& P, const S* z, S* eta, hipStream_t st);
 template <typename S>
 hipError_t launch_Lt(const Problem& P, const S* eta, S* z, hipStream_t st);
+// L and L* of B instances whose vectors are `is` elements apart (special form)
+template <typename S>
+hipError_t launch_L_batch(const Problem& P, const S* z, S* eta, long long is, int B, hipStream_t st);
+template <typename S>
+hipError_t launch_Lt_batch(const Problem& P, const S* eta, S* z, long long is, int B, hipStream_t st);
 template <typename S>
 hipError_t launch_prox_gstar(const Problem& P, const S* w, S* out, hipStream_t st);
 // M d = (d_z - alpha L* d_eta, d_eta - alpha L d_z), team of team_pp lanes per family
@@ -390,6 +395,8 @@ size_t batched_pool_vectors();
 template <typename S>
 hipError_t launch_jg(const Problem& P, const S* b, const S* w, S* out, hipStream_t st);
 template <typename S>
+hipError_t launch_jg_batch(const Problem& P, const S* b, const S* w, S* out, long long is, int B, hipStream_t st);
+template <typename S>
 hipError_t launch_phiT(const Problem& P, const S* cz, S* mu, hipStream_t st);
 template <typename S>
 hipError_t launch_grad_q(const Problem& P, const S* vstar, const S* la, const S* lb, double* gq,
@@ -407,5 +414,12 @@ hipError_t launch_copy_elem(S* dst, const S* src, hipStream_t st);
 template <typename S>
 int shared_solve(Problem& P, int B, const double* const* x0, const spock_settings& s, void* const* vio,
                  spock_info* infos, hipStream_t st);
+// Adjoint gradients of B instances of one problem at once (the shared-tree
+// sweeps for J_f', lockstep GMRES per instance); arguments as spock_backward,
+// one per instance.
+template <typename S>
+int shared_backward(Problem& P, int B, const void* const* vstar, const double* const* x0, double gV,
+                    const double* const* gu0, double* const* gx0, double* const* gq, double* const* gqN,
+                    const spock_settings& s, spock_info* infos, hipStream_t st);
 
 }  // namespace spk

@@ -174,6 +174,45 @@ def test_64_instances_batched_forward_and_adjoints(prec):
                 check(f"bwd64:{b}:{d['kind']}:{prec}", abs(got - want) / max(1.0, abs(want)), tol)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_64_instances_batched_adjoint(prec):
+    # spock_backward_batched: all 64 adjoints of the differentiation workload
+    # at once (shared-tree sweeps, lockstep GMRES); instances 0 and 37 against
+    # the oracle's stored tangents, every instance converged and finite, and
+    # eight of them against spock_backward one by one (both converge to the
+    # same adjoint: agreement within the adjoint tolerance)
+    pr, eps, beps, tol = PREC[prec]
+    insts = G.make_batch(5)
+    refs = {0: _golden("config5b0_tangents_1e-11"), 37: _golden("config5b37_tangents_1e-11")}
+    gp = SP.Problem.from_instance(insts[0], precision=pr, alpha=refs[0]["alpha"])
+    x0s = [dev(i.x0, torch.float64) for i in insts]
+    vs = [torch.zeros(gp.n_v, dtype=gp.torch_dtype, device="cuda") for _ in insts]
+    infos = SP.solve_batched([gp] * len(insts), x0s, vs,
+                             SP.default_settings(eps_abs=eps, eps_rel=eps, max_iters=400000))
+    assert all(i["status"] == "converged" for i in infos)
+    gu = np.random.default_rng(7).standard_normal(insts[0].nu)
+    gut = dev(gu, torch.float64)
+    st = SP.default_settings(eps_abs=beps, max_iters=400000)
+    out = SP.backward_batched(gp, vs, x0s, gV=1.0, gu0s=[gut] * len(insts), settings=st)
+    for b, (gx, gq, gqN, bi) in enumerate(out):
+        assert bi["status"] == "converged" and bi["mapping"] == 1024, (b, bi)
+        assert np.all(np.isfinite(host(gx))) and np.all(np.isfinite(host(gq))) and np.all(np.isfinite(host(gqN)))
+    for b, r in refs.items():
+        gx, gq = host(out[b][0]), host(out[b][1])
+        for d in r["dirs"]:
+            dirv = _direction(d["kind"], d["seed"], insts[b])
+            want = d["dV"] + gu @ np.array(d["du0"])
+            got = gx @ dirv if d["kind"] == "x0" else float(np.sum(gq[1:] * dirv[1:]))
+            check(f"bwdb64:{b}:{d['kind']}:{prec}", abs(got - want) / max(1.0, abs(want)), tol)
+    for b in (0, 5, 13, 21, 37, 44, 52, 63):
+        gx1, gq1, _, bi = gp.backward(vs[b], x0s[b], gV=1.0, gu0=gut, settings=st)
+        assert bi["status"] == "converged"
+        scale = max(1.0, float(np.max(np.abs(host(gx1)))))
+        check(f"bwdb64_vs_single_x0:{b}:{prec}", float(np.max(np.abs(host(out[b][0]) - host(gx1)))) / scale, tol)
+        scale = max(1.0, float(np.max(np.abs(host(gq1)))))
+        check(f"bwdb64_vs_single_q:{b}:{prec}", float(np.max(np.abs(host(out[b][1]) - host(gq1)))) / scale, tol)
+
+
 def test_adjoint_falls_back_when_a_dataflow_wait_gives_up(monkeypatch):
     # every bounded wait of the dataflow sweeps gives up at once: the adjoint
     # is redone with the per-stage form and the gradients stay exact
