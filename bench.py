@@ -482,8 +482,9 @@ def leg_diff64(torch, SP, G):
     instances in lockstep, Alg. 2 sweeps as 16-instance MFMA tiles), the
     per-instance block engine (SPOCK_SHARED=0) and spock_solve instance by
     instance; FP64 forward to 1e-10 by the first two. Then the adjoint
-    gradients d(V*, u^0)/d(x0, diag Q) of all 64 instances in FP32 (to 1e-6)
-    and of 8 of them in FP64 (to 1e-10)."""
+    gradients d(V*, u^0)/d(x0, diag Q) one instance at a time (all 64 in
+    FP32 to 1e-6, 8 in FP64 to 1e-10), and of all 64 in one batched call in
+    both precisions."""
     insts = G.make_batch(5)
     out = {"workload": "64 instances of the 95-node tree nx20 nu10 N8 (shared tree and data, own x0)"}
     gu = np.random.default_rng(7).standard_normal(insts[0].nu)
@@ -535,6 +536,19 @@ def leg_diff64(torch, SP, G):
                           "all_converged": ok, "J_T_applications_mean": round(float(np.mean(its)), 1),
                           "J_T_applications_max": int(np.max(its))}
         log(f"diff64 {pname} adjoint: {res['adjoint']}")
+        # all 64 adjoints in one spock_backward_batched call
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outb = SP.backward_batched(gp, sol, x0s, gV=1.0, gu0s=[gut] * len(insts),
+                                   settings=SP.default_settings(eps_abs=beps, max_iters=400000))
+        torch.cuda.synchronize()
+        itb = [o[3]["iters"] for o in outb]
+        res["adjoint_batched"] = {"instances": len(insts), "eps": beps,
+                                  "seconds": round(time.perf_counter() - t0, 4),
+                                  "all_converged": all(o[3]["status"] == "converged" for o in outb),
+                                  "J_T_applications_mean": round(float(np.mean(itb)), 1),
+                                  "J_T_applications_max": int(np.max(itb))}
+        log(f"diff64 {pname} adjoint batched: {res['adjoint_batched']}")
         out[pname] = res
         gp.close()
     return out
