@@ -35,8 +35,11 @@ The same JSON line carries the other legs of the metric, each measured:
                             n_x = n_u = 20, 20 steps, 15 realisations), warm
                             against cold starts
   differentiation_64_instances 64 instances of the 95-node tree sharing its
-                            data: forward by the shared-tree (MFMA) form, the
-                            block engine and one by one; adjoint gradients
+                            data: forward by the shared-tree (MFMA) form and
+                            all 64 adjoint gradients in one batched call (by
+                            default); with --legs diff64 (or all) also the
+                            block engine, the forward one by one and the
+                            adjoints one by one
   shared_forward_64_instances (only when asked: --legs shared64) one FP32
                             forward of that workload by the shared-tree form
 """
@@ -475,7 +478,7 @@ def leg_mpc(torch, SP, G, steps=20, realisations=15):
     return out
 
 
-def leg_diff64(torch, SP, G):
+def leg_diff64(torch, SP, G, full=True):
     """The differentiation workload: 64 instances of the 95-node tree (n_x 20,
     n_u 10, N 8, branching 2 for 4 stages; shared tree and data, own x0).
     Forward in FP32 to eps 1e-5 three ways: the shared-tree form (one call,
@@ -484,7 +487,8 @@ def leg_diff64(torch, SP, G):
     instance; FP64 forward to 1e-10 by the first two. Then the adjoint
     gradients d(V*, u^0)/d(x0, diag Q) one instance at a time (all 64 in
     FP32 to 1e-6, 8 in FP64 to 1e-10), and of all 64 in one batched call in
-    both precisions."""
+    both precisions. full=False (the default leg diff64b): the shared-tree
+    forward and the batched adjoints only."""
     insts = G.make_batch(5)
     out = {"workload": "64 instances of the 95-node tree nx20 nu10 N8 (shared tree and data, own x0)"}
     gu = np.random.default_rng(7).standard_normal(insts[0].nu)
@@ -494,7 +498,7 @@ def leg_diff64(torch, SP, G):
         x0s = [torch.as_tensor(i.x0, dtype=torch.float64, device="cuda") for i in insts]
         s = SP.default_settings(eps_abs=eps, eps_rel=eps, max_iters=400000)
         res = {}
-        forms = [("shared_mfma", "1"), ("block_engine", "0")]
+        forms = [("shared_mfma", "1"), ("block_engine", "0")] if full else [("shared_mfma", "1")]
         for form, env in forms:
             os.environ["SPOCK_SHARED"] = env
             vs = [torch.zeros(gp.n_v, dtype=dt, device="cuda") for _ in insts]
@@ -512,7 +516,7 @@ def leg_diff64(torch, SP, G):
                 sol = vs
             log(f"diff64 {pname} forward {form}: {el:.3f}s {res[form]}")
         os.environ.pop("SPOCK_SHARED", None)
-        if pname == "fp32":
+        if pname == "fp32" and full:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             ok = True
@@ -526,16 +530,17 @@ def leg_diff64(torch, SP, G):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         its, ok = [], True
-        for b in range(nadj):
+        for b in range(nadj if full else 0):
             _, _, _, bi = gp.backward(sol[b], x0s[b], gV=1.0, gu0=gut,
                                       settings=SP.default_settings(eps_abs=beps, max_iters=200000))
             its.append(bi["iters"])
             ok = ok and bi["status"] == "converged"
         torch.cuda.synchronize()
-        res["adjoint"] = {"instances": nadj, "eps": beps, "seconds": round(time.perf_counter() - t0, 4),
-                          "all_converged": ok, "J_T_applications_mean": round(float(np.mean(its)), 1),
-                          "J_T_applications_max": int(np.max(its))}
-        log(f"diff64 {pname} adjoint: {res['adjoint']}")
+        if full:
+            res["adjoint"] = {"instances": nadj, "eps": beps, "seconds": round(time.perf_counter() - t0, 4),
+                              "all_converged": ok, "J_T_applications_mean": round(float(np.mean(its)), 1),
+                              "J_T_applications_max": int(np.max(its))}
+            log(f"diff64 {pname} adjoint: {res['adjoint']}")
         # all 64 adjoints in one spock_backward_batched call
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -588,7 +593,7 @@ def main():
     ap.add_argument("--horizons", default="3,6,9,12,15")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--legs", default="fp64,budget,223,512,fp32err,datacentre,scaling",
+    ap.add_argument("--legs", default="fp64,budget,223,512,fp32err,datacentre,scaling,diff64b",
                     help="comma-separated extra legs to run (see the module docstring); 'all' adds "
                          "the closed-loop simulation (mpc) and the 64-instance differentiation (diff64)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -681,6 +686,8 @@ def main():
         extras["datacentre_cp_vs_spock"] = timed_leg("datacentre", lambda: leg_datacentre(torch, SP, G))
     if "mpc" in legs:
         extras["datacentre_closed_loop_mpc"] = timed_leg("mpc", lambda: leg_mpc(torch, SP, G))
+    if "diff64b" in legs and "diff64" not in legs:
+        extras["differentiation_64_instances"] = timed_leg("diff64b", lambda: leg_diff64(torch, SP, G, full=False))
     if "diff64" in legs:
         extras["differentiation_64_instances"] = timed_leg("diff64", lambda: leg_diff64(torch, SP, G))
     if "shared64" in legs:
