@@ -271,8 +271,9 @@ def ttr_single(torch, SP, G):
 def ttr_batched(torch, SP, G, keep=None):
     """512 uneven instances: warm start = FP64 solution + N(0, 0.05^2) on
     every entry (seeded); batched FP32 and FP64 (one persistent graph-captured
-    launch each) vs the plain FP64 path solving every instance one by one
-    from the same warm starts."""
+    launch each), and mixed (FP32 to 1e-3, then FP64 from there), vs the
+    plain FP64 path solving every instance one by one from the same warm
+    starts."""
     insts = G.make_batch(4, count=512)
     x0s = [torch.as_tensor(i.x0, dtype=torch.float64, device="cuda") for i in insts]
     p64 = [SP.Problem.from_instance(i, precision=SP.FP64) for i in insts]
@@ -298,6 +299,18 @@ def ttr_batched(torch, SP, G, keep=None):
         torch.cuda.synchronize()
         res[name] = (time.perf_counter() - t0, infos)
         log(f"512-batch {name} warm {res[name][0]:.3f}s")
+    # mixed precision: the FP32 batch to a loose 1e-3 (at most 3000
+    # iterations, above the FP32 residual floor of most trees), then the
+    # FP64 batch from those points to the target
+    vb = [w.to(torch.float32, copy=True) for w in warm]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    i_lo = SP.solve_batched(p32, x0s, vb, SP.default_settings(eps_abs=1e-3, eps_rel=1e-3, max_iters=3000))
+    vb = [x.to(torch.float64) for x in vb]
+    i_mix = SP.solve_batched(p64, x0s, vb, s)
+    torch.cuda.synchronize()
+    t_mix = time.perf_counter() - t0
+    log(f"512-batch mixed FP32 -> FP64 {t_mix:.3f}s")
     # plain FP64, every instance one by one from the same warm starts
     t_plain, iters_plain, infos_plain = 0.0, [], []
     for b in range(512):
@@ -332,8 +345,16 @@ def ttr_batched(torch, SP, G, keep=None):
             "V_max_rel_err_batched_fp32": max(rel(i32[b], tight[b]) for b in sample),
             "V_max_rel_err_batched_fp64": max(rel(i64[b], tight[b]) for b in sample),
             "V_max_rel_err_plain_fp64": max(rel(infos_plain[b], tight[b]) for b in sample),
+            "batched_mixed_seconds": round(t_mix, 4),
+            "batched_mixed_fp32_iters_median_max": [int(np.median([i["iters"] for i in i_lo])),
+                                                    max(i["iters"] for i in i_lo)],
+            "batched_mixed_fp64_iters_median_max": [int(np.median([i["iters"] for i in i_mix])),
+                                                    max(i["iters"] for i in i_mix)],
+            "batched_mixed_converged": sum(i["status"] == "converged" for i in i_mix),
+            "V_max_rel_err_batched_mixed": max(rel(i_mix[b], tight[b]) for b in sample),
             "speedup_batched_fp32_vs_plain_fp64": round(t_plain / res["fp32"][0], 2),
-            "speedup_batched_fp64_vs_plain_fp64": round(t_plain / res["fp64"][0], 2)}
+            "speedup_batched_fp64_vs_plain_fp64": round(t_plain / res["fp64"][0], 2),
+            "speedup_batched_mixed_vs_plain_fp64": round(t_plain / t_mix, 2)}
 
 
 def _golden():
