@@ -177,8 +177,20 @@ __device__ __forceinline__ void flat_family(const DevProb<S>& P, const Off<S>& O
   // every load of the unit is in flight at once: columns x^i, u^i (slot s:
   // k = lane + 64 s), the y block (one entry per lane when 2n + 1 <= 64)
   // and the scalars.
+  // FP64 loads the box rows' and the y block's operands after the cone
+  // blocks (fewer live registers across them)
+  constexpr bool kLateBox = sizeof(S) == 8;
   bool on[2];
   S zp[2], zo[2], lo[2], hi[2], eb[2], gc[2];
+  auto load_box = [&](int s) {
+    const int k = lane + 64 * s;
+    const int kk = on[s] ? k : 0;
+    const bool isx = kk < nx;
+    const size_t bi = isx ? (size_t)i * nx + kk : (size_t)i * nu + (kk - nx);
+    lo[s] = (isx ? P.xlo : P.ulo)[bi];
+    hi[s] = (isx ? P.xhi : P.uhi)[bi];
+    eb[s] = eta[e1x + kk];
+  };
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     const int k = lane + 64 * s;
@@ -186,21 +198,26 @@ __device__ __forceinline__ void flat_family(const DevProb<S>& P, const Off<S>& O
     const int kk = on[s] ? k : 0;
     const bool isx = kk < nx;
     const long long zi = isx ? xi + kk : ui + (kk - nx);
-    const size_t bi = isx ? (size_t)i * nx + kk : (size_t)i * nu + (kk - nx);
     zp[s] = zout[zi];
     zo[s] = z[zi];
-    lo[s] = (isx ? P.xlo : P.ulo)[bi];
-    hi[s] = (isx ? P.xhi : P.uhi)[bi];
-    eb[s] = eta[e1x + kk];
+    if (!kLateBox) load_box(s);
     gc[s] = 0;
   }
   const int ny = 2 * n + 1;
   const int ky = lane < ny ? lane : 0;
-  const S yv = z[zb + ky], ypv = zout[zb + ky], eyv = eta[e1 + ky];
-  const S pk = P.p[fc + (lane < n ? lane : 0)];
-  const S si = z[sp], sip = zout[sp];
-  const S y3 = z[zb + 2 * n], y3p = zout[zb + 2 * n];
-  const S es = eta[e1 + 2 * n + 1];
+  S yv, ypv, eyv, pk, si, sip, y3, y3p, es;
+  auto load_y = [&]() {
+    yv = z[zb + ky];
+    ypv = zout[zb + ky];
+    eyv = eta[e1 + ky];
+    pk = P.p[fc + (lane < n ? lane : 0)];
+    si = z[sp];
+    sip = zout[sp];
+    y3 = z[zb + 2 * n];
+    y3p = zout[zb + 2 * n];
+    es = eta[e1 + 2 * n + 1];
+  };
+  if (!kLateBox) load_y();
   // group 2 of every child: (Q^{1/2} x^i, R^{1/2} u^i, tau/2, tau/2)
   for (int c = fc; c < fc + n; ++c) {
     const long long e2 = O.e2(c);
@@ -245,6 +262,11 @@ __device__ __forceinline__ void flat_family(const DevProb<S>& P, const Off<S>& O
     }
   }
   // group 1: the boxes on (x^i, u^i) and the columns x^i, u^i
+  if (kLateBox) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s) load_box(s);
+    load_y();
+  }
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     if (on[s]) {
@@ -338,8 +360,11 @@ __device__ __forceinline__ void flat_leaf(const DevProb<S>& P, const Off<S>& O, 
   }
 }
 
+// Four wavefronts per SIMD: FP32 needs 122 VGPRs; FP64 (133 with the late
+// loads) is held to 128 at 12 bytes of scratch, measured faster than three.
 template <typename S>
-__global__ void __launch_bounds__(256) k_post_flat(DevProb<S> P, const long long* __restrict__ spos,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
+k_post_flat(DevProb<S> P, const long long* __restrict__ spos,
                                                    const S* __restrict__ z, const S* __restrict__ eta,
                                                    const S* __restrict__ zout, S* __restrict__ eout,
                                                    double* __restrict__ partials) {
