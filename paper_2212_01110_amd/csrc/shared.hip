@@ -1267,14 +1267,12 @@ int shared_backward(Problem& P, int B, const void* const* vstar, const double* c
   S* mu = reinterpret_cast<S*>(base + o_mu);
   const int vb = (int)std::min<long long>((nv + 255) / 256, 64);
   auto op = [&](int r, long long o = 0) { return BOp<S>{vec[r], vs, o}; };
-  const BOp<S> none{nullptr, 0, 0};
   auto lin3 = [&](long long len, BOp<S> o, double a, BOp<S> x, double c = 0, BOp<S> y = BOp<S>{nullptr, 0, 0},
                   double e = 0, BOp<S> w = BOp<S>{nullptr, 0, 0}) -> int {
     hipLaunchKernelGGL(k_blin3<S>, dim3(vb, Bp), dim3(256), 0, st, len, o, a, x, c, y, e, w);
     SH_TRY(hipGetLastError());
     return SPOCK_OK;
   };
-  (void)none;
   // ---- inputs: v* and x0 of every instance, the cotangents
   for (int b = 0; b < B; ++b) {
     SH_TRY(hipMemcpyAsync(vec[kV] + (size_t)b * vs, vstar[b], sizeof(S) * nv, hipMemcpyDeviceToDevice, st));
