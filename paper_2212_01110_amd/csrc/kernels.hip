@@ -773,42 +773,50 @@ __device__ void publish_stats(const double* vals, Publish pub) {
 // Sums the per-block statistics into {xi_p, xi_d, omega^2, rz2, re2, cross};
 // NaN when the error word of the dataflow sweeps is set (a bounded wait gave
 // up); then, when pub.mb is set, publishes out[0..8) to the host.
-__global__ void k_reduce_stats(const double* __restrict__ partials, int nblk, double alpha,
+__global__ void __launch_bounds__(256) k_reduce_stats(const double* __restrict__ partials, int nblk, double alpha,
                                double* __restrict__ out, const unsigned* __restrict__ err, Publish pub) {
-  __shared__ double red[kStats][256];
-  double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0;
+  // per thread over records t, t + 256, ...; then wavefront shuffles and
+  // the four wavefronts in order (one barrier)
+  double a[kStats] = {0, 0, 0, 0, 0};
   for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
     const double* p = partials + (size_t)b * kStats;
-    a0 += p[0];
-    a1 += p[1];
-    a2 += p[2];
-    a3 = fmax(a3, p[3]);
-    a4 = fmax(a4, p[4]);
+    a[0] += p[0];
+    a[1] += p[1];
+    a[2] += p[2];
+    a[3] = fmax(a[3], p[3]);
+    a[4] = fmax(a[4], p[4]);
   }
-  red[0][threadIdx.x] = a0;
-  red[1][threadIdx.x] = a1;
-  red[2][threadIdx.x] = a2;
-  red[3][threadIdx.x] = a3;
-  red[4][threadIdx.x] = a4;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    a[0] += __shfl_xor(a[0], m, 64);
+    a[1] += __shfl_xor(a[1], m, 64);
+    a[2] += __shfl_xor(a[2], m, 64);
+    a[3] = fmax(a[3], __shfl_xor(a[3], m, 64));
+    a[4] = fmax(a[4], __shfl_xor(a[4], m, 64));
+  }
+  __shared__ double red[4][kStats];
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < kStats; ++k) red[threadIdx.x >> 6][k] = a[k];
   __syncthreads();
-  for (int s = blockDim.x / 2; s >= 1; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      red[0][threadIdx.x] += red[0][threadIdx.x + s];
-      red[1][threadIdx.x] += red[1][threadIdx.x + s];
-      red[2][threadIdx.x] += red[2][threadIdx.x + s];
-      red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + s]);
-      red[4][threadIdx.x] = fmax(red[4][threadIdx.x], red[4][threadIdx.x + s]);
-    }
-    __syncthreads();
-  }
   if (threadIdx.x == 0) {
+    double t[kStats];
+#pragma unroll
+    for (int k = 0; k < kStats; ++k) t[k] = red[0][k];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+      t[0] += red[w][0];
+      t[1] += red[w][1];
+      t[2] += red[w][2];
+      t[3] = fmax(t[3], red[w][3]);
+      t[4] = fmax(t[4], red[w][4]);
+    }
     double r[8];
-    r[0] = red[3][0];
-    r[1] = red[4][0];
-    r[2] = red[0][0] + red[1][0] - 2.0 * alpha * red[2][0];
-    r[3] = red[0][0];
-    r[4] = red[1][0];
-    r[5] = red[2][0];
+    r[0] = t[3];
+    r[1] = t[4];
+    r[2] = t[0] + t[1] - 2.0 * alpha * t[2];
+    r[3] = t[0];
+    r[4] = t[1];
+    r[5] = t[2];
     if (err && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
       for (int k = 0; k < 6; ++k) r[k] = __builtin_nan("");
     for (int k = 0; k < 6; ++k) out[k] = r[k];
