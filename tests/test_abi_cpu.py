@@ -84,3 +84,33 @@ def test_uneven_and_chain_trees_accepted(lib):
         assert _create(inst.anc, inst.prob) == 0
     inst = G.make_config(3)
     assert _create(inst.anc, inst.prob) == 0
+
+
+def test_invalid_arguments_rejected_before_any_device_call(lib):
+    L = SP.lib()
+    s = SP.default_settings()
+    infos = (SP.Info * 2)()
+    arr = (ctypes.c_void_p * 2)()
+    # no problem handle / no instances
+    assert L.spock_backward_batched(None, 2, arr, arr, 1.0, None, arr, None, None, ctypes.byref(s), infos,
+                                    None) == -1
+    assert L.spock_backward(None, None, None, 1.0, None, None, None, None, ctypes.byref(s),
+                            ctypes.byref(SP.Info()), None) == -1
+
+
+def test_dense_costs_validated_by_factor(lib):
+    # dense Q, R, Q_N (section 4.1) pass through the library's own checks:
+    # an indefinite Q, a singular R and a non-symmetric Q_N are rejected with
+    # SPOCK_EINVAL when the problem is factored
+    inst = G.dense_costs(G.make_config(1), seed=3)
+    tree = SP.Tree(inst.anc, inst.prob)
+    for name, edit in (("Qm", lambda m: m.__setitem__(2, m[2] - 5.0 * np.eye(m.shape[1]))),
+                       ("Rm", lambda m: m.__setitem__(1, 0.0 * m[1])),
+                       ("QNm", lambda m: m.__setitem__((-1, 0, 1), m[-1, 0, 1] + 1e-3))):
+        bad = inst.copy()
+        m = getattr(inst, name).copy()
+        edit(m)
+        setattr(bad, name, m)
+        with pytest.raises(SP.SpockError) as e:
+            SP.Problem.from_instance(bad, tree=tree)
+        assert e.value.code == -1, name
