@@ -983,14 +983,8 @@ int shared_solve(Problem& P, int B, const double* const* x0, const spock_setting
           break;
       }
     }
-    // ---- accept the evaluated points (the K2 and KM candidates above read
-    // only rows of instances that commit nothing this round)
-    if (int rc = upload(kParCommit)) return rc;
-    hipLaunchKernelGGL(k_sh_commit<S>, vgrid, dim3(256), 0, st, V, dp_com.mode);
-    for (int b = 0; b < B; ++b)  // ended numerically: T of the point reached
-      if (I[b].active && I[b].phase == kShDone)
-        if (int rc = finish(b, I[b].info.status)) return rc;
-    // ---- residual, Anderson push, Gram solve and direction
+    // ---- the push parameters (host state only), then commit and push
+    // parameters in one upload (adjacent slots)
     bool any_prep = false, any_push = false;
     for (int b = 0; b < B; ++b) {
       if (!prep[b]) continue;
@@ -1004,8 +998,17 @@ int shared_solve(Problem& P, int B, const double* const* x0, const spock_setting
       }
       hp_dir.mask[b] = 1;
     }
+    static_assert(kParPush == kParCommit + 1, "adjacent staging slots");
+    SH_TRY(hipMemcpyAsync(par_d + (size_t)kParCommit * par_bytes, par_h + (size_t)kParCommit * par_bytes,
+                          2 * par_bytes, hipMemcpyHostToDevice, st));
+    // ---- accept the evaluated points (the K2 and KM candidates above read
+    // only rows of instances that commit nothing this round)
+    hipLaunchKernelGGL(k_sh_commit<S>, vgrid, dim3(256), 0, st, V, dp_com.mode);
+    for (int b = 0; b < B; ++b)  // ended numerically: T of the point reached
+      if (I[b].active && I[b].phase == kShDone)
+        if (int rc = finish(b, I[b].info.status)) return rc;
+    // ---- residual, Anderson push, Gram solve and direction
     if (any_prep) {
-      if (int rc = upload(kParPush)) return rc;
       hipLaunchKernelGGL(k_sh_push<S>, dim3(Bp), dim3(kShRed), 0, st, V, dp_push.mode, dp_push.slot, s.m, dots_d);
       if (any_push) {
         SH_TRY(hipMemcpyAsync(hdots, dots_d, sizeof(double) * (size_t)Bp * 2 * kAAMax, hipMemcpyDeviceToHost, st));
