@@ -1019,8 +1019,6 @@ int shared_solve(Problem& P, int B, const double* const* x0, const spock_setting
         if (I[b].have_prev) I[b].ring.solve(hdots + (size_t)b * 2 * kAAMax, hp_dir.gamma + (size_t)b * kAAMax);
         head[b] = 1;
       }
-      if (int rc = upload(kParDir)) return rc;
-      hipLaunchKernelGGL(k_sh_dir<S>, vgrid, dim3(256), 0, st, V, dp_dir.gamma, dp_dir.mask);
     }
     // ---- top of the next iteration of Alg. 3
     bool any_m = false;
@@ -1055,7 +1053,13 @@ int shared_solve(Problem& P, int B, const double* const* x0, const spock_setting
       set_cand(b, {{cV, 1.0}, {cDIR, 1.0}});
       in.phase = kShLS;
     }
-    if (int rc = upload(kParCand)) return rc;
+    // direction and candidate parameters in one upload (adjacent slots);
+    // the direction kernel writes dir and spare, which the copies of the
+    // instances that finished above do not read
+    static_assert(kParCand == kParDir + 1, "adjacent staging slots");
+    SH_TRY(hipMemcpyAsync(par_d + (size_t)kParDir * par_bytes, par_h + (size_t)kParDir * par_bytes, 2 * par_bytes,
+                          hipMemcpyHostToDevice, st));
+    if (any_prep) hipLaunchKernelGGL(k_sh_dir<S>, vgrid, dim3(256), 0, st, V, dp_dir.gamma, dp_dir.mask);
     if (any_m) {
       switch (T) {
         case 8: sh_launch_M<S, 8>(P, D, V, dp_cand.slot, Bp, st); break;
